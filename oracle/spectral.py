@@ -1,0 +1,102 @@
+"""Snapshot space, local spectral problem and adaptive basis selection.
+
+Section 4.1 (eq. snapshot_eqn) and section 4.2 (eqs. spectral_1,
+spectral_eqn).  For an interior coarse face E_i shared by blocks K1 (on the
+-n_i side) and K2 (on the +n_i side), and each fine face e_l of E_i, the
+snapshot v_l solves on each K of omega_i = K1 u K2 the mixed problem
+    kappa^{-1} v + grad p = 0,  div v = alpha_K  in K,
+    v . n_i = delta_l on E_i,   v . n = 0 on the rest of dK,
+with alpha_K the outward flux of K divided by |K| (so +|e_l|/|K| in K1 and
+-|e_l|/|K| in K2; the paper's compatibility condition, read with the
+outward normal).  The spectral problem a(v,w) = lambda s(v,w) on
+span{v_l} uses
+    a(v,w) = int_{E_i} kappa^{-1} (v.n_i)(w.n_i),
+    s(v,w) = (1/H) ( int_omega kappa^{-1} v.w + int_omega div v div w ),
+where kappa^{-1} on E_i is the mean of the two adjacent cells' values and
+H = |K|^{1/2}.  The first l_i = max(1, #{lambda < tol}) eigenvectors
+(ascending lambda) span V_ms^i.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+from .discretization import Grid2D
+
+
+def block_rect(g: Grid2D, I: int, J: int, pad: int = 0):
+    """Cell rectangle of coarse block (I, J), enlarged by ``pad`` cells and clipped to D."""
+    i0 = max(I * g.bx - pad, 0)
+    i1 = min((I + 1) * g.bx + pad, g.nx)
+    j0 = max(J * g.by - pad, 0)
+    j1 = min((J + 1) * g.by + pad, g.ny)
+    return i0, i1, j0, j1
+
+
+def face_geometry(g: Grid2D, face):
+    """Blocks K1 (low side), K2 (high side) and the fine faces of coarse face E.
+
+    Returns (K1, K2, e_faces (full indices), e_len, left_cells, right_cells).
+    """
+    kind, I, J = face
+    if kind == "x":
+        K1, K2 = (I - 1, J), (I, J)
+        jj = J * g.by + np.arange(g.by)
+        i = I * g.bx
+        e = g.xf(i, jj)
+        left, right = g.cell(i - 1, jj), g.cell(i, jj)
+        return K1, K2, e, np.full(g.by, g.hy), left, right
+    K1, K2 = (I, J - 1), (I, J)
+    ii = I * g.bx + np.arange(g.bx)
+    j = J * g.by
+    e = g.yf(ii, j)
+    left, right = g.cell(ii, j - 1), g.cell(ii, j)
+    return K1, K2, e, np.full(g.bx, g.hx), left, right
+
+
+def snapshots(g: Grid2D, A, B, block_solver, face):
+    """Snapshot matrix Psi (faces of omega x J) for one coarse face (eq. snapshot_eqn).
+
+    ``block_solver(I, J)`` returns the factorised restricted saddle system of
+    block (I, J).  Rows of Psi follow ``omega_faces`` = faces inside K1, faces
+    inside K2, then the fine faces of E.
+    """
+    K1, K2, e, e_len, _, _ = face_geometry(g, face)
+    J_i = e.size
+    parts = []
+    for K, sign in ((K1, 1.0), (K2, -1.0)):
+        bs = block_solver(*K)
+        area_K = bs.cells.size * g.cell_area
+        alpha = sign * e_len / area_K                       # outward flux / |K|
+        rhs_f = -A[bs.faces][:, e].toarray()                # -A_{I,E} delta_l
+        rhs_c = alpha[None, :] * g.cell_area - B[bs.cells][:, e].toarray()
+        v, _ = bs.solve(rhs_f, rhs_c)
+        parts.append((bs.faces, v))
+    faces = np.concatenate([parts[0][0], parts[1][0], e])
+    Psi = np.vstack([parts[0][1], parts[1][1], np.eye(J_i)])
+    return faces, Psi
+
+
+def omega_cells(g: Grid2D, face):
+    K1, K2, *_ = face_geometry(g, face)
+    return np.concatenate([g.cells_in(*block_rect(g, *K1)), g.cells_in(*block_rect(g, *K2))])
+
+
+def pencil(g: Grid2D, A, B, kinv_cells, face, faces, Psi, s_scale: float | None = None):
+    """Diagonal of the a-form and the s-form matrix on span(Psi) (eq. spectral_eqn)."""
+    _, _, e, e_len, left, right = face_geometry(g, face)
+    kE = 0.5 * (kinv_cells[left] + kinv_cells[right])
+    Dg = e_len * kE                                           # int_E kappa^{-1} delta_l delta_m
+    cells = omega_cells(g, face)
+    M = A[faces][:, faces]
+    divs = B[cells][:, faces] @ Psi                           # int_c div v = (div v)|c| per cell
+    H = np.sqrt(g.bx * g.hx * g.by * g.hy) if s_scale is None else s_scale
+    S = (Psi.T @ (M @ Psi) + divs.T @ (divs / g.cell_area)) / H
+    return Dg, 0.5 * (S + S.T)
+
+
+def select(Dg, S, tol):
+    """Solve a(v,w) = lambda s(v,w); keep the first max(1, #{lambda < tol}) modes."""
+    lam, V = sla.eigh(np.diag(Dg), S)
+    count = max(1, int(np.count_nonzero(lam < tol)))
+    return lam, V, count

@@ -1,0 +1,139 @@
+"""Pins of the oracle's preprocessing, coarse correction, two-grid and PCG (CPU)."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle.discretization import Grid2D
+from oracle.solver import OracleSolver, exact_solve
+from workloads import fields
+
+pytestmark = pytest.mark.filterwarnings("ignore::scipy.sparse.SparseEfficiencyWarning")
+
+
+def _small(n=16, b=4, seed=11, var=4.0, tol=0.5, **kw):
+    rng = np.random.default_rng(seed)
+    kappa = np.exp(np.sqrt(var) * rng.standard_normal((n, n)))
+    g = Grid2D(n, n, b, b)
+    return g, kappa, OracleSolver(g, kappa, tol, **kw)
+
+
+def test_preprocessing_satisfies_discrete_divergence():
+    """Section 3: B vbar = F holds to round-off (also with nonzero boundary flux)."""
+    g, kappa, o = _small()
+    F = fields.random_source(g.nx, g.ny, 3).ravel()
+    vbar, _, Fp = o.preprocess(F)
+    assert np.abs(o.B @ vbar - F).max() <= 1e-13 * np.abs(F).max()
+    gf = np.zeros(g.nf)
+    rng = np.random.default_rng(1)
+    gf[g.boundary_idx] = rng.standard_normal(g.boundary_idx.size)
+    # make the source compatible with the boundary flux: sum F = outward boundary flux
+    out = (o.B @ gf).sum()
+    F2 = F + out / g.nc
+    vbar, gb, Fp = o.preprocess(F2, gf)
+    assert abs(Fp.sum()) < 1e-12
+    assert np.abs(o.B @ (vbar + gb) - F2).max() <= 1e-12
+
+
+def test_coarse_correction_invariances():
+    """P depends only on span(V_ms^i); P r lies in ker B; P annihilates B^T q."""
+    g, kappa, o = _small(tol=2.0)
+    rng = np.random.default_rng(2)
+    r = o.mask * rng.standard_normal(g.nf)
+    z = o.coarse(r)
+    assert np.abs(o.B @ z).max() < 1e-11 * np.abs(z).max()
+    q = rng.standard_normal(g.nc)
+    assert np.abs(o.coarse(o.mask * (o.B.T @ q))).max() < 1e-10 * np.abs(z).max()
+    # mix each face's basis by a random invertible matrix: same span, same P
+    import scipy.sparse as sp
+    blocks, off = [], 0
+    for c in o.counts:
+        blocks.append(rng.standard_normal((c, c)) + 3 * np.eye(c))
+    o.Phi = o.Phi @ sp.block_diag(blocks).tocsr()
+    AH = (o.Phi.T @ o.A @ o.Phi).toarray()
+    BH = (o.RQ @ o.B @ o.Phi).toarray()
+    from oracle.solver import bordered_dense_or_sparse
+    o.coarse_lu, o.nH, o.mH = bordered_dense_or_sparse(AH, BH)
+    assert np.abs(o.coarse(r) - z).max() < 1e-11 * np.abs(z).max()
+
+
+def _dense_on_kerB(o, op):
+    g = o.g
+    I = g.interior_idx
+    Z = sla.null_space(o.B[:, I].toarray())
+    cols = []
+    for k in range(Z.shape[1]):
+        x = np.zeros(g.nf)
+        x[I] = Z[:, k]
+        cols.append(op(x)[I])
+    return Z, np.array(cols).T
+
+
+def test_twogrid_symmetric_positive_and_bounded():
+    """B_TG is symmetric; on ker B the eigenvalues of B_TG A lie in (0, 1];
+    eta * sum of local projections has spectrum <= 4 eta (4 colours in 2D)."""
+    g, kappa, o = _small(n=16, b=4, tol=0.5)
+    rng = np.random.default_rng(4)
+    x, y = o.mask * rng.standard_normal(g.nf), o.mask * rng.standard_normal(g.nf)
+    assert abs(x @ o.twogrid(y) - y @ o.twogrid(x)) < 1e-12 * abs(x @ o.twogrid(y)) + 1e-14
+    Z, MA = _dense_on_kerB(o, lambda v: o.twogrid(o.apply_A(v)))
+    T = Z.T @ MA
+    ev = np.linalg.eigvals(T)
+    assert np.abs(ev.imag).max() < 1e-8
+    assert ev.real.min() > 0 and ev.real.max() <= 1 + 1e-10
+    Z, SA = _dense_on_kerB(o, lambda v: o.smooth(o.apply_A(v)))
+    evs = np.linalg.eigvals(Z.T @ SA).real
+    assert evs.max() <= 4 * o.eta + 1e-10 and evs.min() > 0
+
+
+def test_lanczos_condition_matches_dense():
+    g, kappa, o = _small(n=16, b=4, tol=0.5)
+    Z, MA = _dense_on_kerB(o, lambda v: o.twogrid(o.apply_A(v)))
+    ev = np.linalg.eigvals(Z.T @ MA).real
+    dense = ev.max() / ev.min()
+    F = fields.random_source(g.nx, g.ny, 9).ravel()
+    res = o.solve(F, rtol=1e-14, maxit=300)
+    assert abs(res["cond"] - dense) < 1e-3 * dense
+
+
+def test_pcg_reaches_exact_solution():
+    """At rtol 1e-13 the iterative solution equals the direct one to <= 1e-10."""
+    g, kappa, o = _small(n=24, b=6, tol=0.5)
+    F = fields.random_source(g.nx, g.ny, 4).ravel()
+    res = o.solve(F, rtol=1e-13, maxit=300)
+    u, p = exact_solve(g, kappa, F)
+    assert np.linalg.norm(res["u"] - u) <= 1e-10 * np.linalg.norm(u)
+    assert np.linalg.norm(res["p"] - p) <= 1e-10 * np.linalg.norm(p)
+    # with boundary data
+    gf = np.zeros(g.nf)
+    gf[g.boundary_idx] = np.random.default_rng(3).standard_normal(g.boundary_idx.size)
+    F2 = F + (o.B @ gf).sum() / g.nc
+    res = o.solve(F2, gf, rtol=1e-13, maxit=300)
+    u, p = exact_solve(g, kappa, F2, gf)
+    assert np.linalg.norm(res["u"] - u) <= 1e-10 * np.linalg.norm(u)
+    assert np.linalg.norm(res["p"] - p) <= 1e-10 * np.linalg.norm(p)
+
+
+def test_pressure_recovery_exact_for_exact_velocity():
+    g, kappa, o = _small(n=16, b=4)
+    F = fields.random_source(g.nx, g.ny, 5).ravel()
+    u, p = exact_solve(g, kappa, F)
+    assert np.abs(o.pressure(u) - p).max() <= 1e-12 * np.abs(p).max()
+
+
+@pytest.mark.slow
+def test_iterations_flat_over_contrast():
+    """Section 6 robustness protocol on a synthetic binary medium: background 1,
+    channels/inclusions at 10^-6 .. 10^6.  The GMsFEM iteration count stays
+    within a narrow band (the paper's spread is 2), while the MsFEM coarse
+    space (one basis per face) degrades at high contrast."""
+    n, b = 32, 8
+    g = Grid2D(n, n, b, b)
+    F = fields.corner_source(n, n).ravel()
+    its, its_ms = [], []
+    for e in (-6, -4, -2, 0, 2, 4, 6):
+        kappa = fields.field_binary(n, n, 7, 10.0 ** e)
+        its.append(OracleSolver(g, kappa, 0.5).solve(F, rtol=1e-8)["iters"])
+        if e >= 2:
+            its_ms.append(OracleSolver(g, kappa, 0.5, basis="msfem").solve(F, rtol=1e-8)["iters"])
+    assert max(its) - min(its) <= 4, its
+    assert max(its_ms) > max(its) + 4, (its, its_ms)

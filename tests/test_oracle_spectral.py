@@ -1,0 +1,153 @@
+"""Pins of the oracle's snapshot space and local spectral problem (CPU)."""
+import numpy as np
+import pytest
+
+from oracle.discretization import Grid2D, div_matrix, mass_matrix
+from oracle.local import BorderedSaddle
+from oracle.spectral import block_rect, face_geometry, omega_cells, pencil, select, snapshots
+
+pytestmark = pytest.mark.filterwarnings("ignore::scipy.sparse.SparseEfficiencyWarning")
+
+
+def _setup(n, b, kappa):
+    g = Grid2D(n, n, b, b)
+    kinv = (1.0 / kappa).ravel()
+    A, B = mass_matrix(g, kinv).tocsr(), div_matrix(g).tocsr()
+    cache = {}
+
+    def block(I, J):
+        if (I, J) not in cache:
+            r = block_rect(g, I, J)
+            cache[(I, J)] = BorderedSaddle(A, B, g.faces_in(*r), g.cells_in(*r))
+        return cache[(I, J)]
+    return g, kinv, A, B, block
+
+
+def test_lambda0_closed_form_and_dct_eigenvectors():
+    """kappa = c on a uniform grid, square blocks of side H.
+
+    The sum of all snapshots is the coarse RT0 function (normal velocity
+    1 - d/H), for which a = H/c, int kappa^{-1}|v|^2 = 2H^2/(3c) and
+    int div^2 = 2, so lambda_0 = H^2 / (2H^2/3 + 2c).  The problem separates
+    along E, so the eigenvectors are the DCT-II vectors cos(m pi (l+1/2)/J).
+    """
+    for c in (1.0, 7.0):
+        n, b = 24, 6
+        g, kinv, A, B, block = _setup(n, b, np.full((n, n), c))
+        H = b / n
+        for face in (("x", 1, 2), ("y", 3, 1)):
+            fa, Psi = snapshots(g, A, B, block, face)
+            Dg, S = pencil(g, A, B, kinv, face, fa, Psi)
+            lam, V, _ = select(Dg, S, 0.5)
+            assert abs(lam[0] - H * H / (2 * H * H / 3 + 2 * c)) < 1e-12 * lam[0] * 100
+            J = Dg.size
+            l = np.arange(J)
+            for m in range(J):
+                d = np.cos(m * np.pi * (l + 0.5) / J)
+                v = V[:, m]
+                cosang = abs(d @ v) / (np.linalg.norm(d) * np.linalg.norm(v))
+                assert cosang > 1 - 1e-10, (m, cosang)
+            assert np.all(np.diff(lam) > 0)
+            # zero-net-flux modes are scale-free: lambda_1 near (pi/2) tanh(pi) for large J
+            assert 1.3 < lam[1] < 1.8
+
+
+def test_one_basis_per_face_at_unit_kappa():
+    """kappa = 1 with tol between lambda_0 and lambda_1 keeps exactly one mode per face."""
+    n, b = 32, 8
+    g, kinv, A, B, block = _setup(n, b, np.ones((n, n)))
+    for face in g.coarse_faces():
+        fa, Psi = snapshots(g, A, B, block, face)
+        Dg, S = pencil(g, A, B, kinv, face, fa, Psi)
+        _, _, cnt = select(Dg, S, 0.5)
+        assert cnt == 1
+
+
+def test_snapshot_boundary_and_divergence_conditions():
+    """Each snapshot has v.n_i = delta_l on E, zero flux on d(omega), div = +-|e_l|/|K|."""
+    rng = np.random.default_rng(3)
+    n, b = 16, 4
+    kappa = np.exp(2 * rng.standard_normal((n, n)))
+    g, kinv, A, B, block = _setup(n, b, kappa)
+    face = ("y", 2, 2)
+    fa, Psi = snapshots(g, A, B, block, face)
+    K1, K2, e, e_len, _, _ = face_geometry(g, face)
+    full = np.zeros((g.nf, Psi.shape[1]))
+    full[fa] = Psi
+    assert np.allclose(full[e], np.eye(e.size))
+    div = B @ full / g.cell_area
+    for K, sgn in ((K1, 1.0), (K2, -1.0)):
+        cells = g.cells_in(*block_rect(g, *K))
+        area = cells.size * g.cell_area
+        assert np.allclose(div[cells], sgn * e_len[None, :] / area, atol=1e-12)
+    other = np.setdiff1d(np.arange(g.nc), omega_cells(g, face))
+    assert np.allclose(full[np.setdiff1d(np.arange(g.nf), fa)], 0.0)
+    assert np.allclose(div[other], 0.0)
+
+
+def test_snapshot_is_energy_minimiser_via_stream_function():
+    """Brute force: the local saddle solution equals the energy minimiser over
+    particular solution + curl of an interior-vertex stream function."""
+    rng = np.random.default_rng(5)
+    n, b = 12, 6
+    kappa = np.exp(1.5 * rng.standard_normal((n, n)))
+    g, kinv, A, B, block = _setup(n, b, kappa)
+    face = ("x", 1, 0)
+    fa, Psi = snapshots(g, A, B, block, face)
+    K1 = face_geometry(g, face)[0]
+    i0, i1, j0, j1 = block_rect(g, *K1)
+    bs = block(*K1)
+    full = np.zeros((g.nf, Psi.shape[1]))
+    full[fa] = Psi
+    # discrete curl of interior vertices of K1 (flux across each face)
+    verts = [(i, j) for j in range(j0 + 1, j1) for i in range(i0 + 1, i1)]
+    C = np.zeros((g.nf, len(verts)))
+    for k, (i, j) in enumerate(verts):
+        # flux across a face = psi at its +tangent end minus psi at its other end
+        C[g.xf(i, j - 1), k] += 1.0 / g.hy
+        C[g.xf(i, j), k] -= 1.0 / g.hy
+        C[g.yf(i - 1, j), k] -= 1.0 / g.hx
+        C[g.yf(i, j), k] += 1.0 / g.hx
+    assert np.allclose(B @ C, 0.0)
+    Ad = A.toarray()
+    for l in range(Psi.shape[1]):
+        v = full[:, l].copy()
+        v[np.setdiff1d(np.arange(g.nf), np.concatenate([bs.faces, face_geometry(g, face)[2]]))] = 0.0
+        # any admissible perturbation C psi must not lower the energy: C^T A v = 0
+        grad = C.T @ (Ad @ v)
+        assert np.abs(grad).max() < 1e-10 * np.abs(Ad @ v).max()
+
+
+def test_generalised_eigen_residual_and_positivity():
+    rng = np.random.default_rng(7)
+    n, b = 16, 8
+    kappa = np.exp(3 * rng.standard_normal((n, n)))
+    g, kinv, A, B, block = _setup(n, b, kappa)
+    for face in g.coarse_faces():
+        fa, Psi = snapshots(g, A, B, block, face)
+        Dg, S = pencil(g, A, B, kinv, face, fa, Psi)
+        assert np.allclose(S, S.T)
+        assert np.linalg.eigvalsh(S).min() > 0
+        lam, V, _ = select(Dg, S, 0.2)
+        R = np.diag(Dg) @ V - S @ V * lam[None, :]
+        assert np.abs(R).max() < 1e-10 * np.abs(np.diag(Dg) @ V).max()
+        assert np.all(lam > 0) and np.all(np.diff(lam) >= 0)
+
+
+def test_high_contrast_channels_add_small_eigenvalues():
+    """Each separate high-permeability channel crossing E makes int_E kappa^{-1}
+    small on its faces and contributes one eigenvalue far below the zero-flux
+    modes, so the adaptive count equals the number of crossings (section 4.2:
+    the basis captures the channels)."""
+    n, b = 16, 8
+    for cols, expect in (((3,), 1), ((2, 5), 2)):
+        kappa = np.ones((n, n))
+        for c in cols:
+            kappa[:, c] = 1e6       # vertical channel crossing the y-faces of E
+        g, kinv, A, B, block = _setup(n, b, kappa)
+        face = ("y", 0, 1)
+        fa, Psi = snapshots(g, A, B, block, face)
+        Dg, S = pencil(g, A, B, kinv, face, fa, Psi)
+        lam, V, cnt = select(Dg, S, 0.5)
+        assert cnt == expect
+        assert np.all(lam[:expect] < 1e-4) and lam[expect] > 1.0
