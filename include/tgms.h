@@ -1,0 +1,150 @@
+/*
+ * tgms: two-grid preconditioned solver with an adaptive GMsFEM coarse space
+ * for mixed (RT0 velocity, P0 pressure) Darcy flow on a uniform Cartesian
+ * grid of the unit square, on one AMD MI355X (gfx950).
+ *
+ * Problem (paper section 2, eq. orgional_equation): find v, p with
+ *     kappa^{-1} v + grad p = 0,   div v = f   in D = (0,1)^2,
+ *     v . n = g on dD  (g = 0 in the paper),
+ * discretised by RT0 x P0 (eqs. matrixform, fine_system).  Algorithm
+ * (section 5): preprocessing (section 3) gives vbar with B vbar = F; PCG on
+ * the divergence-free remainder with a two-grid preconditioner made of an
+ * overlapping-patch smoother (eq. smooth) and a coarse correction through
+ * the adaptive spectral space (section 4, eqs. snapshot_eqn, spectral_eqn;
+ * eq. coarsepre).
+ *
+ * Conventions shared by every entry point
+ *   cells      (i, j), 0 <= i < nx, 0 <= j < ny, index j*nx + i (x fastest);
+ *   faces      "full" numbering including the boundary of D:
+ *              x-faces (at x = i/nx, row j, 0 <= i <= nx): index j*(nx+1) + i,
+ *              y-faces (at y = j/ny, column i, 0 <= j <= ny): index
+ *              (nx+1)*ny + j*nx + i;  nfaces = (nx+1)*ny + nx*(ny+1);
+ *              a face value is the normal velocity along +x or +y;
+ *   sources    cell-integrated, F_c = int_c f;
+ *   pressure   physical sign (A v = B^T p, i.e. kappa^{-1} v = -grad p),
+ *              zero mean over the cells.
+ *
+ * Memory: every array argument documented "device" is a pointer to GPU
+ * memory owned by the caller (e.g. a PyTorch tensor); the library reads or
+ * writes it on the context's stream and keeps no reference after the call
+ * returns.  The context owns all of its own workspaces.
+ *
+ * Errors: every call returns a tgms_status; on failure tgms_last_error()
+ * returns a message (thread-local, valid until the next call on that thread).
+ * No call aborts the process.
+ */
+#ifndef TGMS_H
+#define TGMS_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tgms_ctx tgms_ctx;
+
+typedef enum {
+    TGMS_OK = 0,
+    TGMS_E_INVAL = -1,        /* bad argument: sizes, non-positive or non-finite permeability */
+    TGMS_E_INCOMPAT = -2,     /* sum of sources differs from the boundary outflow */
+    TGMS_E_NOTCONV = -3,      /* PCG reached maxit; the last iterate is returned */
+    TGMS_E_BREAKDOWN = -4,    /* PCG breakdown (p^T A p <= 0 or not finite) */
+    TGMS_E_DEVICE = -5,       /* HIP runtime error */
+    TGMS_E_NOMEM = -6,        /* device allocation failed */
+    TGMS_E_UNSUPPORTED = -7   /* a size the kernels do not handle (see tgms_setup) */
+} tgms_status;
+
+typedef struct {
+    int nx, ny;   /* fine cells per axis */
+    int bx, by;   /* coarse block size in fine cells; nx % bx == 0, ny % by == 0 */
+} tgms_grid;
+
+typedef struct {
+    double eta;        /* smoother weight, eq. smooth (paper: 0.2) */
+    int overlap;       /* K_i^+ = K_i enlarged by this many fine cells, clipped to D (paper: 2) */
+    int precision;     /* 0: FP64 preconditioner and PCG;
+                          1: FP32 preconditioner (smoother factors, coarse basis, coarse
+                             inverse, inner operator applies) inside a flexible FP64 PCG */
+    double s_scale;    /* H in the 1/H prefactor of the s-form (eq. spectral_eqn);
+                          <= 0 selects |K|^(1/2), the coarse block side */
+    void* stream;      /* hipStream_t to run on; NULL = the default stream */
+} tgms_options;
+
+typedef struct {
+    int n_coarse_faces;   /* N_e: interior coarse faces (one local spectral problem each) */
+    int n_blocks;         /* coarse blocks */
+    int dim;              /* paper's "Dim": sum of basis counts + n_blocks + 1 */
+    int n_coarse_spd;     /* unknowns of the SPD coarse system actually factorised */
+    double t_setup_ms;    /* device time of tgms_setup (all phases) */
+    double t_snap_ms, t_eig_ms, t_coarse_ms, t_smoother_ms;  /* setup phases */
+} tgms_info_t;
+
+/* Paper defaults: eta 0.2, overlap 2, FP64, s_scale = |K|^(1/2), default stream. */
+void tgms_default_options(tgms_options* opt);
+
+/*
+ * Setup (section 5, Step 2, and the source-independent part of Step 1):
+ * snapshot space and local spectral problems for every interior coarse face
+ * (section 4), adaptive selection l_i = max(1, #{lambda < eig_tol}), the
+ * coarse operator and its FP64 Cholesky factorisation, the smoother patch
+ * factorisations (K_i^+), and the coarse RT0 operator used by preprocessing.
+ *   kappa  device, nx*ny doubles, permeability per cell (> 0, finite).
+ * Returns TGMS_E_INVAL for bad sizes or permeability, TGMS_E_UNSUPPORTED
+ * if a block or patch is wider than 62 cells or bx, by < 2.
+ * On success *out owns all device workspaces until tgms_destroy.
+ */
+tgms_status tgms_setup(const tgms_grid* grid, const double* kappa, double eig_tol,
+                       const tgms_options* opt, tgms_ctx** out);
+
+/*
+ * Solve (section 5, Steps 1, 3, 4): preprocessing, PCG to
+ * ||z_k||_2 <= rtol ||z_0||_2 (z = preconditioned residual), v = vbar + vtilde,
+ * then the pressure by least squares from A v = B^T p (zero mean).
+ *   F      device, nx*ny doubles, cell-integrated source;
+ *   g_bnd  device, nfaces doubles (full face numbering), only the boundary
+ *          entries are read; NULL means no-flow (the paper's case);
+ *   u      device, nfaces doubles, output velocity (boundary entries = g);
+ *   p      device, nx*ny doubles, output pressure (may be NULL);
+ *   iters, relres  host, outputs (may be NULL).
+ * TGMS_E_INCOMPAT if |sum F - boundary outflow| > 1e-12 (sum |F| + sum |g| |e|);
+ * TGMS_E_NOTCONV returns the last iterate with *iters = maxit.
+ */
+tgms_status tgms_solve(tgms_ctx* ctx, const double* F, const double* g_bnd, double rtol,
+                       int maxit, double* u, double* p, int* iters, double* relres);
+
+/* Sizes and timings of the setup. */
+tgms_status tgms_info(const tgms_ctx* ctx, tgms_info_t* info);
+
+/* Basis counts l_i (host, n_coarse_faces ints) and all eigenvalues lambda of
+ * each local spectral problem, ascending (host, n_coarse_faces * jmax doubles,
+ * jmax = max(bx, by); rows of faces with fewer fine faces are padded with 0).
+ * Coarse faces are ordered: x-faces (block row J, I = 1..Nx-1), then y-faces
+ * (J = 1..Ny-1, block column I). */
+tgms_status tgms_get_counts(const tgms_ctx* ctx, int* counts);
+tgms_status tgms_get_eigs(const tgms_ctx* ctx, double* eigs);
+
+/* Condition-number estimate of the preconditioned operator from the last
+ * solve's PCG scalars (Lanczos tridiagonal), as the paper reports "Cond". */
+tgms_status tgms_last_cond(const tgms_ctx* ctx, double* cond);
+
+void tgms_destroy(tgms_ctx* ctx);
+const char* tgms_last_error(void);
+
+/* ---- operator probes (same definitions the solver uses; for testing) ----
+ * Vectors are device arrays in the full face numbering; boundary entries of
+ * inputs are ignored and of outputs set to 0.                              */
+
+/* y = A_h x restricted to the interior faces (eq. fine_system). */
+tgms_status tgms_apply_A(tgms_ctx* ctx, const double* x, double* y);
+
+/* vbar of the preprocessing step (section 3, eq. subproblem): B vbar = F - B_bnd g. */
+tgms_status tgms_preprocess(tgms_ctx* ctx, const double* F, const double* g_bnd, double* vbar);
+
+/* z = M r for the residual r of the reduced problem: which = 0 smoother
+ * (eq. smooth), 1 coarse correction (eq. coarsepre), 2 two-grid (section 5).
+ * Runs in the context's precision. */
+tgms_status tgms_apply_precond(tgms_ctx* ctx, int which, const double* r, double* z);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TGMS_H */

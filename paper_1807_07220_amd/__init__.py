@@ -1,0 +1,122 @@
+"""Two-grid GMsFEM-preconditioned mixed Darcy solver on AMD MI355X (gfx950).
+
+``Solver(kappa, bx, by, eig_tol)`` runs the setup (adaptive spectral coarse
+space, coarse Cholesky, smoother factors) on the GPU; ``Solver.solve(F, g)``
+returns velocity, pressure and the PCG iteration count.  All arrays are
+float64 torch tensors on the GPU; the work runs in the HIP library
+``libtgms.so`` through its C ABI (include/tgms.h).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from ._lib import Grid, Info, Options, TgmsError, check, load  # noqa: F401
+
+__all__ = ["Solver", "TgmsError", "nfaces"]
+
+
+def nfaces(nx: int, ny: int) -> int:
+    """Length of a full face array: (nx+1)*ny x-faces then nx*(ny+1) y-faces."""
+    return (nx + 1) * ny + nx * (ny + 1)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """Setup on construction; see include/tgms.h for the definitions."""
+
+    def __init__(self, kappa: torch.Tensor, bx: int, by: int, eig_tol: float, eta: float = 0.2, overlap: int = 2,
+                 precision: str = "fp64", s_scale: float = 0.0, stream: torch.cuda.Stream | None = None):
+        lib = load()
+        if kappa.dim() != 2:
+            raise ValueError("kappa must be (ny, nx)")
+        self.ny, self.nx = kappa.shape
+        self.bx, self.by = int(bx), int(by)
+        self.device = kappa.device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(kappa.device)
+        opt = Options()
+        lib.tgms_default_options(ctypes.byref(opt))
+        opt.eta, opt.overlap, opt.s_scale = float(eta), int(overlap), float(s_scale)
+        opt.precision = {"fp64": 0, "mixed": 1}[precision]
+        opt.stream = ctypes.c_void_p(self.stream.cuda_stream)
+        grid = Grid(self.nx, self.ny, self.bx, self.by)
+        handle = ctypes.c_void_p()
+        kappa = kappa.contiguous()
+        check(lib.tgms_setup(ctypes.byref(grid), _ptr(kappa), float(eig_tol), ctypes.byref(opt),
+                             ctypes.byref(handle)))
+        self._h = handle
+        self.precision = precision
+
+    # ---- results ----------------------------------------------------------
+    def solve(self, F: torch.Tensor, g: torch.Tensor | None = None, rtol: float = 1e-8, maxit: int = 1000,
+              pressure: bool = True):
+        lib = load()
+        F = F.contiguous().reshape(-1)
+        u = torch.empty(nfaces(self.nx, self.ny), dtype=torch.float64, device=self.device)
+        p = torch.empty(self.nx * self.ny, dtype=torch.float64, device=self.device) if pressure else None
+        it, rel = ctypes.c_int(0), ctypes.c_double(0.0)
+        code = lib.tgms_solve(self._h, _ptr(F), _ptr(g), float(rtol), int(maxit), _ptr(u), _ptr(p),
+                              ctypes.byref(it), ctypes.byref(rel))
+        converged = code == 0
+        if code not in (0, -3):
+            check(code)
+        return {"u": u, "p": p, "iters": it.value, "relres": rel.value, "converged": converged}
+
+    def info(self) -> dict:
+        inf = Info()
+        check(load().tgms_info(self._h, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in Info._fields_}
+
+    def counts(self):
+        import numpy as np
+        n = self.info()["n_coarse_faces"]
+        out = np.zeros(n, dtype=np.int32)
+        check(load().tgms_get_counts(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def eigs(self):
+        import numpy as np
+        n = self.info()["n_coarse_faces"]
+        out = np.zeros((n, max(self.bx, self.by)), dtype=np.float64)
+        check(load().tgms_get_eigs(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def cond(self) -> float:
+        c = ctypes.c_double(0.0)
+        check(load().tgms_last_cond(self._h, ctypes.byref(c)))
+        return c.value
+
+    # ---- probes -----------------------------------------------------------
+    def apply_A(self, x: torch.Tensor) -> torch.Tensor:
+        y = torch.empty_like(x)
+        check(load().tgms_apply_A(self._h, _ptr(x), _ptr(y)))
+        return y
+
+    def preprocess(self, F: torch.Tensor, g: torch.Tensor | None = None) -> torch.Tensor:
+        v = torch.empty(nfaces(self.nx, self.ny), dtype=torch.float64, device=self.device)
+        check(load().tgms_preprocess(self._h, _ptr(F.contiguous().reshape(-1)), _ptr(g), _ptr(v)))
+        return v
+
+    def apply_precond(self, which: str, r: torch.Tensor) -> torch.Tensor:
+        z = torch.empty_like(r)
+        check(load().tgms_apply_precond(self._h, {"smoother": 0, "coarse": 1, "twogrid": 2}[which], _ptr(r), _ptr(z)))
+        return z
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().tgms_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,80 @@
+"""ctypes binding of libtgms.so (argument marshalling only).
+
+Every computation happens in the HIP library; this module converts torch
+tensors to device pointers and status codes to exceptions.  It raises if the
+library has not been built: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtgms.so")
+
+c_int, c_double, c_void_p, c_char_p = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_char_p
+
+STATUS = {0: "OK", -1: "INVAL", -2: "INCOMPAT", -3: "NOTCONV", -4: "BREAKDOWN", -5: "DEVICE", -6: "NOMEM",
+          -7: "UNSUPPORTED"}
+
+
+class TgmsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"tgms {STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", c_int), ("ny", c_int), ("bx", c_int), ("by", c_int)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("eta", c_double), ("overlap", c_int), ("precision", c_int), ("s_scale", c_double),
+                ("stream", c_void_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n_coarse_faces", c_int), ("n_blocks", c_int), ("dim", c_int), ("n_coarse_spd", c_int),
+                ("t_setup_ms", c_double), ("t_snap_ms", c_double), ("t_eig_ms", c_double),
+                ("t_coarse_ms", c_double), ("t_smoother_ms", c_double)]
+
+
+_lib = None
+
+# name -> (restype, argtypes); the exported C ABI of include/tgms.h
+SIGNATURES = {
+    "tgms_default_options": (None, [ctypes.POINTER(Options)]),
+    "tgms_setup": (c_int, [ctypes.POINTER(Grid), c_void_p, c_double, ctypes.POINTER(Options), ctypes.POINTER(c_void_p)]),
+    "tgms_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int, c_void_p, c_void_p,
+                           ctypes.POINTER(c_int), ctypes.POINTER(c_double)]),
+    "tgms_info": (c_int, [c_void_p, ctypes.POINTER(Info)]),
+    "tgms_get_counts": (c_int, [c_void_p, c_void_p]),
+    "tgms_get_eigs": (c_int, [c_void_p, c_void_p]),
+    "tgms_last_cond": (c_int, [c_void_p, ctypes.POINTER(c_double)]),
+    "tgms_destroy": (None, [c_void_p]),
+    "tgms_last_error": (c_char_p, []),
+    "tgms_apply_A": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "tgms_preprocess": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "tgms_apply_precond": (c_int, [c_void_p, c_int, c_void_p, c_void_p]),
+}
+
+
+def load():
+    """Load libtgms.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1807_07220_amd.build.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def check(code):
+    if code != 0:
+        raise TgmsError(code, load().tgms_last_error().decode())

@@ -1,0 +1,649 @@
+// Host orchestration of the C ABI declared in include/tgms.h.
+//
+// Setup (paper section 5, Step 2): block factors -> snapshots (section 4.1)
+// -> block Gram matrices -> pencils, eigenproblems and selection (section
+// 4.2) -> divergence-free coarse basis, its SPD matrix, stream functions and
+// FP64 Cholesky -> smoother patch factors -> coarse RT0 operator of the
+// preprocessing.  Solve (Steps 1, 3, 4): preprocessing (section 3), PCG in
+// stream-function coordinates with the two-grid preconditioner (section 5),
+// v = vbar + C psi, pressure.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+#include "common.h"
+
+namespace tgms {
+void bnd_faces(tgms_ctx* c, const double* g, double* gb);
+}
+
+namespace {
+thread_local std::string g_last_error;
+
+struct Timer {
+    hipEvent_t a, b;
+    hipStream_t s;
+    explicit Timer(hipStream_t st) : s(st) {
+        HIP_OK(hipEventCreate(&a));
+        HIP_OK(hipEventCreate(&b));
+        HIP_OK(hipEventRecord(a, s));
+    }
+    double ms() {
+        HIP_OK(hipEventRecord(b, s));
+        HIP_OK(hipEventSynchronize(b));
+        float t = 0;
+        HIP_OK(hipEventElapsedTime(&t, a, b));
+        HIP_OK(hipEventDestroy(a));
+        HIP_OK(hipEventDestroy(b));
+        return t;
+    }
+};
+
+template <typename F>
+tgms_status guarded(F&& f) {
+    try {
+        f();
+        return TGMS_OK;
+    } catch (const TgmsError& e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return TGMS_E_DEVICE;
+    }
+}
+
+// Extreme eigenvalues of the symmetric tridiagonal Lanczos matrix by bisection (Sturm counts).
+double lanczos_cond(const std::vector<double>& al, const std::vector<double>& be) {
+    const int k = (int)al.size();
+    if (k == 0) return 1.0;
+    std::vector<double> d(k), e(k, 0.0);
+    for (int i = 0; i < k; ++i) {
+        d[i] = 1.0 / al[i] + (i > 0 ? be[i - 1] / al[i - 1] : 0.0);
+        if (i + 1 < k && i < (int)be.size()) e[i] = std::sqrt(std::fabs(be[i])) / al[i];
+    }
+    double lo = d[0], hi = d[0];
+    for (int i = 0; i < k; ++i) {
+        const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + std::fabs(e[i]);
+        lo = std::min(lo, d[i] - r);
+        hi = std::max(hi, d[i] + r);
+    }
+    auto count_below = [&](double x) {
+        int cnt = 0;
+        double q = d[0] - x;
+        if (q < 0) ++cnt;
+        for (int i = 1; i < k; ++i) {
+            if (q == 0) q = 1e-300;
+            q = d[i] - x - e[i - 1] * e[i - 1] / q;
+            if (q < 0) ++cnt;
+        }
+        return cnt;
+    };
+    auto kth = [&](int idx) {
+        double a = lo, b = hi;
+        for (int it = 0; it < 200; ++it) {
+            const double m = 0.5 * (a + b);
+            if (count_below(m) > idx)
+                b = m;
+            else
+                a = m;
+        }
+        return 0.5 * (a + b);
+    };
+    const double mn = kth(0), mx = kth(k - 1);
+    return mn > 0 ? mx / mn : INFINITY;
+}
+
+template <typename T>
+const T* cell_a(tgms_ctx* c) {
+    if constexpr (sizeof(T) == 8)
+        return c->a;
+    else
+        return c->a32;
+}
+
+// z = B_TG g : one pre-smoothing, coarse correction, one post-smoothing, residual recomputed after each.
+template <typename T>
+void twogrid(tgms_ctx* c, const T* g, T* z, T* t) {
+    tgms::smooth<T>(c, g, z, false);
+    tgms::residual_K<T>(c, g, z, t, cell_a<T>(c));
+    tgms::coarse_apply<T>(c, t, z, true);
+    tgms::residual_K<T>(c, g, z, t, cell_a<T>(c));
+    tgms::smooth<T>(c, t, z, true);
+}
+
+void precond(tgms_ctx* c, int which, const double* g, double* z) {
+    const long long nv = (long long)c->nx * c->ny;
+    if (c->precision == 0) {
+        if (which == 0)
+            tgms::smooth<double>(c, g, z, false);
+        else if (which == 1)
+            tgms::coarse_apply<double>(c, g, z, false);
+        else
+            twogrid<double>(c, g, z, c->vt);
+    } else {
+        tgms::cast_d2f(c, nv, g, c->fg);
+        if (which == 0)
+            tgms::smooth<float>(c, c->fg, c->fz, false);
+        else if (which == 1)
+            tgms::coarse_apply<float>(c, c->fg, c->fz, false);
+        else
+            twogrid<float>(c, c->fg, c->fz, c->ft);
+        tgms::cast_f2d(c, nv, c->fz, z);
+    }
+}
+
+void build_coarse_numbering(tgms_ctx* c, const std::vector<double>& Yh, const std::vector<double>& Qh,
+                            std::vector<double>& Tm, std::vector<int>& zc) {
+    const int Nx = c->Nx, Ny = c->Ny, jm = c->jmax, ncol = c->ncol;
+    const std::vector<int>& cnt = c->counts_h;
+    std::vector<int> zoff(c->ne + 1, 0);
+    for (int i = 0; i < c->ne; ++i) zoff[i + 1] = zoff[i] + cnt[i] - 1;
+    const int nz = zoff[c->ne];
+    c->nv = (Nx - 1) * (Ny - 1);
+    c->ncs = nz + c->nv;
+    auto vid = [&](int I, int J) { return (I <= 0 || I >= Nx || J <= 0 || J >= Ny) ? -1 : nz + (J - 1) * (Nx - 1) + I - 1; };
+    // YQ_i = Y_i Q_i (jmax x cnt): coefficients over the face's snapshots
+    auto YQ = [&](int f, int l, int k) {
+        double s = 0.0;
+        for (int k2 = 0; k2 < cnt[f]; ++k2) s += Yh[(size_t)f * jm * jm + l * jm + k2] * Qh[(size_t)f * jm * jm + k2 * jm + k];
+        return s;
+    };
+    struct Slot {
+        int id;
+        int corner;
+        std::vector<double> col;
+    };
+    std::vector<std::vector<Slot>> slots(c->nblk);
+    int mu = 1;
+    for (int J = 0; J < Ny; ++J)
+        for (int I = 0; I < Nx; ++I) {
+            const int blk = J * Nx + I;
+            int face[4] = {-1, -1, -1, -1};
+            if (I > 0) face[0] = J * (Nx - 1) + I - 1;
+            if (I + 1 < Nx) face[1] = J * (Nx - 1) + I;
+            if (J > 0) face[2] = c->nex + (J - 1) * Nx + I;
+            if (J + 1 < Ny) face[3] = c->nex + J * Nx + I;
+            std::map<int, Slot> m;
+            for (int s = 0; s < 4; ++s) {
+                const int f = face[s];
+                if (f < 0) continue;
+                const int nl = (s < 2) ? c->by : c->bx;
+                for (int k = 1; k < cnt[f]; ++k) {
+                    Slot sl{zoff[f] + k - 1, 0, std::vector<double>(ncol, 0.0)};
+                    for (int l = 0; l < nl; ++l) sl.col[s * jm + l] = YQ(f, l, k);
+                    m[sl.id] = sl;
+                }
+                // carrier of this face enters the coarse-curl combination of its two end vertices
+                int v0I, v0J, v1I, v1J;
+                double s0, s1;
+                if (s == 0) { v0I = I; v0J = J + 1; s0 = 1; v1I = I; v1J = J; s1 = -1; }
+                else if (s == 1) { v0I = I + 1; v0J = J + 1; s0 = 1; v1I = I + 1; v1J = J; s1 = -1; }
+                else if (s == 2) { v0I = I; v0J = J; s0 = 1; v1I = I + 1; v1J = J; s1 = -1; }
+                else { v0I = I; v0J = J + 1; s0 = 1; v1I = I + 1; v1J = J + 1; s1 = -1; }
+                const int vv[2] = {vid(v0I, v0J), vid(v1I, v1J)};
+                const double ss[2] = {s0, s1};
+                const int VI[2] = {v0I, v1I}, VJ[2] = {v0J, v1J};
+                for (int e = 0; e < 2; ++e) {
+                    if (vv[e] < 0) continue;
+                    auto it = m.find(vv[e]);
+                    if (it == m.end()) {
+                        const int ci = (VI[e] == I + 1) ? 0 : c->bx, cj = (VJ[e] == J + 1) ? 0 : c->by;
+                        Slot sl{vv[e], cj * (c->bx + 1) + ci, std::vector<double>(ncol, 0.0)};
+                        it = m.emplace(vv[e], sl).first;
+                    }
+                    for (int l = 0; l < nl; ++l) it->second.col[s * jm + l] += ss[e] * YQ(f, l, 0);
+                }
+            }
+            for (auto& kv : m) slots[blk].push_back(kv.second);
+            mu = std::max(mu, (int)slots[blk].size());
+        }
+    c->mu = mu;
+    Tm.assign((size_t)c->nblk * ncol * mu, 0.0);
+    zc.assign((size_t)c->nblk * mu, 0);
+    std::vector<int> unk((size_t)c->nblk * mu, 0), nu(c->nblk);
+    std::vector<std::vector<int>> ent(c->ncs);
+    for (int b = 0; b < c->nblk; ++b) {
+        nu[b] = (int)slots[b].size();
+        for (int u = 0; u < nu[b]; ++u) {
+            const Slot& sl = slots[b][u];
+            unk[(size_t)b * mu + u] = sl.id;
+            zc[(size_t)b * mu + u] = sl.corner;
+            for (int k = 0; k < ncol; ++k) Tm[((size_t)b * ncol + k) * mu + u] = sl.col[k];
+            ent[sl.id].push_back(b * mu + u);
+        }
+    }
+    std::vector<int> ptr(c->ncs + 1, 0), flat;
+    for (int u = 0; u < c->ncs; ++u) {
+        ptr[u + 1] = ptr[u] + (int)ent[u].size();
+        flat.insert(flat.end(), ent[u].begin(), ent[u].end());
+    }
+    c->blk_unk = c->alloc<int>((size_t)c->nblk * mu);
+    c->blk_nu = c->alloc<int>(c->nblk);
+    c->unk_ptr = c->alloc<int>(c->ncs + 1);
+    c->unk_ent = c->alloc<int>(std::max<size_t>(flat.size(), 1));
+    HIP_OK(hipMemcpyAsync(c->blk_unk, unk.data(), sizeof(int) * unk.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(c->blk_nu, nu.data(), sizeof(int) * nu.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(c->unk_ptr, ptr.data(), sizeof(int) * ptr.size(), hipMemcpyHostToDevice, c->stream));
+    if (!flat.empty())
+        HIP_OK(hipMemcpyAsync(c->unk_ent, flat.data(), sizeof(int) * flat.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+}
+
+// Coarse RT0 vertex stiffness K_H = C_H^T A_H0 C_H (dense, host-assembled from the per-block Grams).
+void build_rt0_stiffness(tgms_ctx* c) {
+    const int Nx = c->Nx, Ny = c->Ny, nv = c->nv;
+    std::vector<double> ah(6 * c->nblk);
+    HIP_OK(hipMemcpyAsync(ah.data(), c->AH0, sizeof(double) * 6 * c->nblk, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    std::vector<double> K((size_t)nv * nv, 0.0);
+    const double Hx = c->bx * c->hx, Hy = c->by * c->hy;
+    auto vid = [&](int I, int J) { return (I <= 0 || I >= Nx || J <= 0 || J >= Ny) ? -1 : (J - 1) * (Nx - 1) + I - 1; };
+    for (int J = 0; J < Ny; ++J)
+        for (int I = 0; I < Nx; ++I) {
+            const double* m = &ah[6 * (J * Nx + I)];
+            // face velocities as combinations of corner stream-function values
+            struct Term { int v; double w; };
+            const Term W[2] = {{vid(I, J + 1), 1 / Hy}, {vid(I, J), -1 / Hy}};
+            const Term E[2] = {{vid(I + 1, J + 1), 1 / Hy}, {vid(I + 1, J), -1 / Hy}};
+            const Term S[2] = {{vid(I + 1, J), -1 / Hx}, {vid(I, J), 1 / Hx}};
+            const Term N[2] = {{vid(I + 1, J + 1), -1 / Hx}, {vid(I, J + 1), 1 / Hx}};
+            auto pair = [&](const Term* a, const Term* b, double w) {
+                for (int p = 0; p < 2; ++p)
+                    for (int q = 0; q < 2; ++q)
+                        if (a[p].v >= 0 && b[q].v >= 0) K[(size_t)a[p].v * nv + b[q].v] += w * a[p].w * b[q].w;
+            };
+            pair(W, W, m[0]);
+            pair(W, E, m[1]);
+            pair(E, W, m[1]);
+            pair(E, E, m[2]);
+            pair(S, S, m[3]);
+            pair(S, N, m[4]);
+            pair(N, S, m[4]);
+            pair(N, N, m[5]);
+        }
+    c->KH = c->alloc<double>((size_t)nv * nv);
+    HIP_OK(hipMemcpyAsync(c->KH, K.data(), sizeof(double) * K.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    tgms::dense_spd_inverse(c, c->KH, nv);
+}
+
+void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, const tgms_options* opt,
+                tgms_ctx** out) {
+    if (!grid || !kappa || !out) throw TgmsError{TGMS_E_INVAL, "null argument"};
+    tgms_options o;
+    tgms_default_options(&o);
+    if (opt) o = *opt;
+    const int nx = grid->nx, ny = grid->ny, bx = grid->bx, by = grid->by;
+    if (nx <= 0 || ny <= 0 || bx <= 0 || by <= 0 || nx % bx || ny % by)
+        throw TgmsError{TGMS_E_INVAL, "grid sizes must be positive and divisible by the block size"};
+    if (!(eig_tol > 0) || !(o.eta > 0) || o.overlap < 0) throw TgmsError{TGMS_E_INVAL, "bad tolerance, eta or overlap"};
+    if (bx < 3 || by < 3 || nx / bx < 2 || ny / by < 2)
+        throw TgmsError{TGMS_E_UNSUPPORTED, "need blocks of at least 3x3 cells and at least 2x2 blocks"};
+    if (o.overlap >= std::min(bx, by)) throw TgmsError{TGMS_E_UNSUPPORTED, "overlap must be smaller than a block"};
+    if (std::max(bx, by) > 64) throw TgmsError{TGMS_E_UNSUPPORTED, "blocks wider than 64 cells"};
+    const int ex = std::min(bx + 2 * o.overlap, nx), ey = std::min(by + 2 * o.overlap, ny);
+    if (ex - 1 + 1 >= 64) throw TgmsError{TGMS_E_UNSUPPORTED, "patch band wider than a wavefront"};
+    (void)ey;
+    auto* c = new tgms_ctx();
+    try {
+        c->stream = (hipStream_t)o.stream;
+        c->nx = nx; c->ny = ny; c->bx = bx; c->by = by;
+        c->Nx = nx / bx; c->Ny = ny / by; c->nblk = c->Nx * c->Ny;
+        c->nex = (c->Nx - 1) * c->Ny;
+        c->ne = c->nex + c->Nx * (c->Ny - 1);
+        c->jmax = std::max(bx, by);
+        c->hx = 1.0 / nx; c->hy = 1.0 / ny;
+        c->sx = 1.0 / c->hy; c->sy = 1.0 / c->hx;
+        c->H = o.s_scale > 0 ? o.s_scale : std::sqrt(bx * c->hx * by * c->hy);
+        c->eta = o.eta; c->tol = eig_tol; c->overlap = o.overlap; c->precision = o.precision ? 1 : 0;
+        c->nfx = (nx + 1) * ny; c->nfy = nx * (ny + 1); c->nf = c->nfx + c->nfy;
+        c->nfk = by * (bx + 1) + (by + 1) * bx;
+        c->ncol = 4 * c->jmax;
+        const long long ncell = (long long)nx * ny;
+        Timer total(c->stream);
+        c->kinv = c->alloc<double>(ncell);
+        c->a = c->alloc<double>(ncell);
+        c->a32 = c->alloc<float>(ncell);
+        int* bad = c->alloc<int>(1);
+        tgms::cell_weights(c, kappa, bad);
+        int hbad = 0;
+        HIP_OK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIP_OK(hipStreamSynchronize(c->stream));
+        if (hbad) throw TgmsError{TGMS_E_INVAL, "permeability must be finite and positive"};
+        // block factors
+        c->blk_m = bx - 1;
+        c->blk_n = (bx - 1) * (by - 1);
+        c->blk_b = bx;
+        c->blkL = c->alloc<double>((size_t)c->nblk * c->blk_n * (c->blk_b + 1));
+        c->blkS = c->alloc<double>((size_t)c->nblk * c->blk_n);
+        {
+            Timer t(c->stream);
+            tgms::factor_blocks(c);
+            // snapshots + Gram
+            c->Psi = c->alloc<double>((size_t)c->nblk * c->ncol * c->nfk);
+            c->APsi = c->alloc<double>((size_t)c->nblk * c->ncol * c->nfk);
+            c->G = c->alloc<double>((size_t)c->nblk * c->ncol * c->ncol);
+            tgms::snapshots(c);
+            tgms::gram(c);
+            c->t_snap_ms = t.ms();
+        }
+        // pencils and eigenproblems
+        c->eigs = c->alloc<double>((size_t)c->ne * c->jmax);
+        c->counts = c->alloc<int>(c->ne);
+        c->Y = c->alloc<double>((size_t)c->ne * c->jmax * c->jmax);
+        double* Qd = c->alloc<double>((size_t)c->ne * c->jmax * c->jmax);
+        {
+            Timer t(c->stream);
+            tgms::pencil_eig_q(c, Qd);
+            c->t_eig_ms = t.ms();
+        }
+        {
+            Timer t(c->stream);
+            c->counts_h.resize(c->ne);
+            std::vector<double> Yh((size_t)c->ne * c->jmax * c->jmax), Qh(Yh.size());
+            HIP_OK(hipMemcpyAsync(c->counts_h.data(), c->counts, sizeof(int) * c->ne, hipMemcpyDeviceToHost, c->stream));
+            HIP_OK(hipMemcpyAsync(Yh.data(), c->Y, sizeof(double) * Yh.size(), hipMemcpyDeviceToHost, c->stream));
+            HIP_OK(hipMemcpyAsync(Qh.data(), Qd, sizeof(double) * Qh.size(), hipMemcpyDeviceToHost, c->stream));
+            HIP_OK(hipStreamSynchronize(c->stream));
+            std::vector<double> Tm;
+            std::vector<int> zc;
+            build_coarse_numbering(c, Yh, Qh, Tm, zc);
+            double* Td = c->alloc<double>(Tm.size());
+            int* zcd = c->alloc<int>(zc.size());
+            HIP_OK(hipMemcpyAsync(Td, Tm.data(), sizeof(double) * Tm.size(), hipMemcpyHostToDevice, c->stream));
+            HIP_OK(hipMemcpyAsync(zcd, zc.data(), sizeof(int) * zc.size(), hipMemcpyHostToDevice, c->stream));
+            c->W = c->alloc<double>((size_t)c->nblk * bx * by * c->mu);
+            if (c->precision) c->W32 = c->alloc<float>((size_t)c->nblk * bx * by * c->mu);
+            c->Ac = c->alloc<double>((size_t)c->ncs * c->ncs);
+            tgms::coarse_local_run(c, Td, zcd);
+            tgms::dense_spd_inverse(c, c->Ac, c->ncs);
+            if (c->precision) {
+                c->Ac32 = c->alloc<float>((size_t)c->ncs * c->ncs);
+                tgms::cast_d2f(c, (long long)c->ncs * c->ncs, c->Ac, c->Ac32);
+            }
+            c->cy = c->alloc<double>((size_t)c->nblk * c->mu);
+            c->cvec = c->alloc<double>(2 * (size_t)c->ncs + 1);
+            c->cvec2 = c->alloc<double>((size_t)c->ncs + 1);
+            c->cy32 = c->alloc<float>((size_t)c->nblk * c->mu);
+            c->cvec32 = c->alloc<float>(2 * (size_t)c->ncs + 1);
+            c->cvec2_32 = c->alloc<float>((size_t)c->ncs + 1);
+            // coarse RT0 for the preprocessing
+            c->AH0 = c->alloc<double>((size_t)c->nblk * 6);
+            tgms::coarse_rt0_blocks(c);
+            build_rt0_stiffness(c);
+            c->cflux = c->alloc<double>(2 * ((size_t)c->Ny * (c->Nx + 1) + (size_t)(c->Ny + 1) * c->Nx));
+            c->svec = c->alloc<double>((size_t)c->nv + 1);
+            c->svec2 = c->alloc<double>(2 * (size_t)c->nv + 1);
+            c->t_coarse_ms = t.ms();
+        }
+        // smoother patches
+        {
+            Timer t(c->stream);
+            c->patch_h.resize(c->nblk);
+            long long off = 0, voff = 0;
+            for (int J = 0; J < c->Ny; ++J)
+                for (int I = 0; I < c->Nx; ++I) {
+                    Rect& r = c->patch_h[J * c->Nx + I];
+                    r.i0 = std::max(I * bx - o.overlap, 0);
+                    r.i1 = std::min((I + 1) * bx + o.overlap, nx);
+                    r.j0 = std::max(J * by - o.overlap, 0);
+                    r.j1 = std::min((J + 1) * by + o.overlap, ny);
+                    const int m = r.i1 - r.i0 - 1, n = m * (r.j1 - r.j0 - 1);
+                    r.off = off;
+                    r.voff = voff;
+                    off += (long long)n * (m + 2);
+                    voff += n;
+                    c->pat_nmax = std::max(c->pat_nmax, n);
+                    c->pat_bmax = std::max(c->pat_bmax, m + 1);
+                }
+            c->pat_pool = off;
+            c->pat_vpool = voff;
+            c->patch = c->alloc<Rect>(c->nblk);
+            HIP_OK(hipMemcpyAsync(c->patch, c->patch_h.data(), sizeof(Rect) * c->nblk, hipMemcpyHostToDevice, c->stream));
+            c->patL = c->alloc<double>(off);
+            c->patS = c->alloc<double>(voff);
+            c->patW = c->alloc<double>(voff);
+            if (c->precision) {
+                c->patL32 = c->alloc<float>(off);
+                c->patS32 = c->alloc<float>(voff);
+                c->patW32 = c->alloc<float>(voff);
+            }
+            tgms::factor_patches(c);
+            c->t_smoother_ms = t.ms();
+        }
+        // snapshot storage is no longer needed
+        // pressure: orthonormal DCT-II matrices and the 1D Neumann eigenvalues
+        {
+            auto dct = [](int n, std::vector<double>& Q, std::vector<double>& lam) {
+                Q.assign((size_t)n * n, 0.0);
+                lam.assign(n, 0.0);
+                for (int i = 0; i < n; ++i)
+                    for (int k = 0; k < n; ++k)
+                        Q[(size_t)i * n + k] = (k == 0 ? std::sqrt(1.0 / n) : std::sqrt(2.0 / n)) *
+                                               std::cos(M_PI * k * (i + 0.5) / n);
+                for (int k = 0; k < n; ++k) lam[k] = 2.0 - 2.0 * std::cos(M_PI * k / n);
+            };
+            std::vector<double> Q, lam;
+            dct(nx, Q, lam);
+            c->Qx = c->alloc<double>(Q.size());
+            c->lamx = c->alloc<double>(nx);
+            HIP_OK(hipMemcpyAsync(c->Qx, Q.data(), sizeof(double) * Q.size(), hipMemcpyHostToDevice, c->stream));
+            HIP_OK(hipMemcpyAsync(c->lamx, lam.data(), sizeof(double) * nx, hipMemcpyHostToDevice, c->stream));
+            HIP_OK(hipStreamSynchronize(c->stream));
+            dct(ny, Q, lam);
+            c->Qy = c->alloc<double>(Q.size());
+            c->lamy = c->alloc<double>(ny);
+            HIP_OK(hipMemcpyAsync(c->Qy, Q.data(), sizeof(double) * Q.size(), hipMemcpyHostToDevice, c->stream));
+            HIP_OK(hipMemcpyAsync(c->lamy, lam.data(), sizeof(double) * ny, hipMemcpyHostToDevice, c->stream));
+            HIP_OK(hipStreamSynchronize(c->stream));
+        }
+        // solve workspaces
+        const long long nvtx = ncell;
+        c->vx = c->alloc<double>(nvtx); c->vg = c->alloc<double>(nvtx); c->vz = c->alloc<double>(nvtx);
+        c->vp = c->alloc<double>(nvtx); c->vq = c->alloc<double>(nvtx); c->vt = c->alloc<double>(nvtx);
+        c->vt2 = c->alloc<double>(nvtx); c->vgold = c->alloc<double>(nvtx);
+        c->fg = c->alloc<float>(nvtx); c->fz = c->alloc<float>(nvtx); c->ft = c->alloc<float>(nvtx);
+        c->ft2 = c->alloc<float>(nvtx);
+        c->fbar = c->alloc<double>(c->nf); c->fu = c->alloc<double>(c->nf); c->fF = c->alloc<double>(c->nf);
+        c->cellw = c->alloc<double>(ncell); c->cellw2 = c->alloc<double>(std::max<long long>(ncell, 2 * c->nblk));
+        c->red = c->alloc<double>(4 * 512 + 16);
+        c->blkbuf = c->alloc<double>(2 * (size_t)c->nblk);
+        HIP_OK(hipHostMalloc((void**)&c->red_h, 16 * sizeof(double), hipHostMallocDefault));
+        HIP_OK(hipStreamSynchronize(c->stream));
+        c->t_setup_ms = total.ms();
+        *out = c;
+    } catch (...) {
+        tgms_destroy(c);
+        throw;
+    }
+}
+
+void solve_impl(tgms_ctx* c, const double* F, const double* g_bnd, double rtol, int maxit, double* u, double* p,
+                int* iters, double* relres, tgms_status* st) {
+    if (!c || !F || !u) throw TgmsError{TGMS_E_INVAL, "null argument"};
+    if (!(rtol >= 0) || maxit < 0) throw TgmsError{TGMS_E_INVAL, "bad rtol or maxit"};
+    const long long nv = (long long)c->nx * c->ny;
+    // Step 1: preprocessing
+    tgms::preprocess(c, F, g_bnd, c->fbar, c->cellw2);
+    // u0 = vbar + g_bnd (boundary entries), g = -C^T A u0
+    tgms::bnd_faces(c, g_bnd, c->fF);
+    tgms::axpy(c, c->nf, 1.0, c->fbar, c->fF);
+    tgms::curlT_A_faces(c, c->fF, c->vg, -1.0);
+    // Step 3: PCG in stream-function coordinates
+    tgms::zero(c, c->vx, sizeof(double) * nv);
+    precond(c, 2, c->vg, c->vz);
+    double d[3];
+    tgms::dot3(c, c->vg, c->vz, nullptr, d);
+    double rho = d[0];
+    const double z0 = std::sqrt(d[2]);
+    const bool flexible = c->precision != 0;
+    c->alphas.clear();
+    c->betas.clear();
+    int it = 0;
+    double rel = 1.0;
+    *st = TGMS_OK;
+    if (z0 > 0) {
+        HIP_OK(hipMemcpyAsync(c->vp, c->vz, sizeof(double) * nv, hipMemcpyDeviceToDevice, c->stream));
+        while (true) {
+            if (it >= maxit) {
+                *st = TGMS_E_NOTCONV;
+                break;
+            }
+            tgms::apply_K<double>(c, c->vp, c->vq, c->a);
+            const double pq = tgms::dot(c, c->vp, c->vq, nv);
+            if (!(pq > 0) || !std::isfinite(pq)) {
+                *st = TGMS_E_BREAKDOWN;
+                break;
+            }
+            const double alpha = rho / pq;
+            tgms::axpy(c, nv, alpha, c->vp, c->vx);
+            if (flexible)
+                HIP_OK(hipMemcpyAsync(c->vgold, c->vg, sizeof(double) * nv, hipMemcpyDeviceToDevice, c->stream));
+            tgms::axpy(c, nv, -alpha, c->vq, c->vg);
+            precond(c, 2, c->vg, c->vz);
+            tgms::dot3(c, c->vg, c->vz, flexible ? c->vgold : nullptr, d);
+            ++it;
+            c->alphas.push_back(alpha);
+            rel = std::sqrt(d[2]) / z0;
+            if (rel <= rtol) break;
+            const double beta = flexible ? (d[0] - d[1]) / rho : d[0] / rho;
+            c->betas.push_back(beta);
+            tgms::xpay(c, nv, c->vz, beta, c->vp);
+            rho = d[0];
+        }
+    }
+    // Step 4: v = vbar + g + C psi
+    tgms::curl_add(c, c->vx, c->fF, u);
+    if (p) tgms::pressure(c, u, p);
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (iters) *iters = it;
+    if (relres) *relres = rel;
+    if (*st != TGMS_OK) {
+        g_last_error = (*st == TGMS_E_NOTCONV) ? "PCG did not converge within maxit" : "PCG breakdown";
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C ABI
+extern "C" {
+
+void tgms_default_options(tgms_options* opt) {
+    if (!opt) return;
+    opt->eta = 0.2;
+    opt->overlap = 2;
+    opt->precision = 0;
+    opt->s_scale = 0.0;
+    opt->stream = nullptr;
+}
+
+tgms_status tgms_setup(const tgms_grid* grid, const double* kappa, double eig_tol, const tgms_options* opt,
+                       tgms_ctx** out) {
+    if (out) *out = nullptr;
+    return guarded([&] { setup_impl(grid, kappa, eig_tol, opt, out); });
+}
+
+tgms_status tgms_solve(tgms_ctx* ctx, const double* F, const double* g_bnd, double rtol, int maxit, double* u,
+                       double* p, int* iters, double* relres) {
+    tgms_status st = TGMS_OK;
+    tgms_status r = guarded([&] { solve_impl(ctx, F, g_bnd, rtol, maxit, u, p, iters, relres, &st); });
+    return r != TGMS_OK ? r : st;
+}
+
+tgms_status tgms_info(const tgms_ctx* c, tgms_info_t* info) {
+    if (!c || !info) {
+        g_last_error = "null argument";
+        return TGMS_E_INVAL;
+    }
+    int sum = 0;
+    for (int v : c->counts_h) sum += v;
+    info->n_coarse_faces = c->ne;
+    info->n_blocks = c->nblk;
+    info->dim = sum + c->nblk + 1;
+    info->n_coarse_spd = c->ncs;
+    info->t_setup_ms = c->t_setup_ms;
+    info->t_snap_ms = c->t_snap_ms;
+    info->t_eig_ms = c->t_eig_ms;
+    info->t_coarse_ms = c->t_coarse_ms;
+    info->t_smoother_ms = c->t_smoother_ms;
+    return TGMS_OK;
+}
+
+tgms_status tgms_get_counts(const tgms_ctx* c, int* counts) {
+    if (!c || !counts) {
+        g_last_error = "null argument";
+        return TGMS_E_INVAL;
+    }
+    std::copy(c->counts_h.begin(), c->counts_h.end(), counts);
+    return TGMS_OK;
+}
+
+tgms_status tgms_get_eigs(const tgms_ctx* c, double* eigs) {
+    if (!c || !eigs) {
+        g_last_error = "null argument";
+        return TGMS_E_INVAL;
+    }
+    return guarded([&] {
+        HIP_OK(hipMemcpyAsync(eigs, c->eigs, sizeof(double) * c->ne * c->jmax, hipMemcpyDeviceToHost, c->stream));
+        HIP_OK(hipStreamSynchronize(c->stream));
+    });
+}
+
+tgms_status tgms_last_cond(const tgms_ctx* c, double* cond) {
+    if (!c || !cond) {
+        g_last_error = "null argument";
+        return TGMS_E_INVAL;
+    }
+    *cond = lanczos_cond(c->alphas, c->betas);
+    return TGMS_OK;
+}
+
+void tgms_destroy(tgms_ctx* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    for (auto& b : c->owned) (void)hipFree(b.p);
+    if (c->red_h) (void)hipHostFree(c->red_h);
+    delete c;
+}
+
+const char* tgms_last_error(void) { return g_last_error.c_str(); }
+
+tgms_status tgms_apply_A(tgms_ctx* c, const double* x, double* y) {
+    if (!c || !x || !y) {
+        g_last_error = "null argument";
+        return TGMS_E_INVAL;
+    }
+    return guarded([&] {
+        tgms::faces_A_probe(c, x, y);
+        HIP_OK(hipStreamSynchronize(c->stream));
+    });
+}
+
+tgms_status tgms_preprocess(tgms_ctx* c, const double* F, const double* g_bnd, double* vbar) {
+    if (!c || !F || !vbar) {
+        g_last_error = "null argument";
+        return TGMS_E_INVAL;
+    }
+    return guarded([&] {
+        tgms::preprocess(c, F, g_bnd, vbar, c->cellw2);
+        HIP_OK(hipStreamSynchronize(c->stream));
+    });
+}
+
+tgms_status tgms_apply_precond(tgms_ctx* c, int which, const double* r, double* z) {
+    if (!c || !r || !z || which < 0 || which > 2) {
+        g_last_error = "bad argument";
+        return TGMS_E_INVAL;
+    }
+    return guarded([&] {
+        tgms::curlT(c, r, c->vt2);
+        precond(c, which, c->vt2, c->vq);
+        tgms::curl_add(c, c->vq, nullptr, z);
+        HIP_OK(hipStreamSynchronize(c->stream));
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,225 @@
+// Internal definitions shared by the tgms HIP sources (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tgms.h"
+
+#define TGMS_WAVE 64
+
+// ---------------------------------------------------------------- errors
+void tgms_set_error(const std::string& msg);
+
+struct TgmsError {
+    tgms_status code;
+    std::string msg;
+};
+
+#define HIP_OK(expr)                                                                 \
+    do {                                                                             \
+        hipError_t e_ = (expr);                                                      \
+        if (e_ != hipSuccess)                                                        \
+            throw TgmsError{e_ == hipErrorOutOfMemory ? TGMS_E_NOMEM : TGMS_E_DEVICE, \
+                            std::string(#expr) + ": " + hipGetErrorString(e_)};      \
+    } while (0)
+
+#define LAUNCH_OK() HIP_OK(hipGetLastError())
+
+// ---------------------------------------------------------------- wave helpers
+__device__ inline double readlane(double v, int l) {
+    int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+__device__ inline float readlane(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, TGMS_WAVE);
+    return v;
+}
+
+// ---------------------------------------------------------------- geometry
+// Vertex (i, j) is the lower-left corner of cell (i, j); vertex arrays are
+// ny x nx with the i = 0 and j = 0 entries (boundary of D) held at zero.  The
+// discrete curl maps a vertex function psi to normal velocities
+//   x-face (i, j):  (psi(i, j+1) - psi(i, j)) * sx,   sx = 1/hy,
+//   y-face (i, j): -(psi(i+1, j) - psi(i, j)) * sy,   sy = 1/hx,
+// so every curl is divergence free with zero flux through dD.  The H(div)
+// operator on that space is K = C^T A C, a 9-point vertex stencil whose
+// coefficients come from the weights a_c = |c| kappa_c^{-1} of the four cells
+// around the vertex (A00 = SW, A10 = SE, A01 = NW, A11 = NE).
+struct Stencil9 {
+    double c, e, w, n, s, ne, nw, se, sw;
+};
+
+__host__ __device__ inline Stencil9 stencil9(double A00, double A10, double A01, double A11, double sx2,
+                                             double sy2) {
+    const double s = sx2 + sy2;
+    Stencil9 k;
+    k.c = s * (A00 + A10 + A01 + A11) * (1.0 / 3.0);
+    k.e = (A10 + A11) * (sx2 * (1.0 / 6.0) - sy2 * (1.0 / 3.0));
+    k.w = (A00 + A01) * (sx2 * (1.0 / 6.0) - sy2 * (1.0 / 3.0));
+    k.n = (A01 + A11) * (sy2 * (1.0 / 6.0) - sx2 * (1.0 / 3.0));
+    k.s = (A00 + A10) * (sy2 * (1.0 / 6.0) - sx2 * (1.0 / 3.0));
+    k.ne = -s * A11 * (1.0 / 6.0);
+    k.nw = -s * A01 * (1.0 / 6.0);
+    k.se = -s * A10 * (1.0 / 6.0);
+    k.sw = -s * A00 * (1.0 / 6.0);
+    return k;
+}
+
+// Rectangle of cells [i0, i1) x [j0, j1) with its band-factor location.
+struct Rect {
+    int i0, i1, j0, j1;
+    long long off;   // offset of the factor (column band) in the pool, in elements
+    long long voff;  // offset of the local vector (n entries) in a per-problem vector pool
+};
+
+// ---------------------------------------------------------------- context
+struct DeviceBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct tgms_ctx {
+    // grid
+    int nx, ny, bx, by, Nx, Ny, nblk, ne, nex, jmax;
+    double hx, hy, sx, sy, H, eta, tol;
+    int overlap, precision;
+    hipStream_t stream;
+    int nfx, nfy, nf;  // full-face counts
+    // cell data
+    double* kinv = nullptr;  // kappa^{-1}
+    double* a = nullptr;     // |c| kappa^{-1}
+    float* a32 = nullptr;
+    // block (K_i) stream-function factors
+    int blk_m, blk_n, blk_b;  // m = bx-1 columns, n = (bx-1)(by-1), b = bx
+    double* blkL = nullptr;   // nblk * n * (b+1)
+    double* blkS = nullptr;   // nblk * n
+    // smoother patches (K_i^+)
+    std::vector<Rect> patch_h;
+    Rect* patch = nullptr;
+    int pat_bmax = 0, pat_nmax = 0;
+    long long pat_pool = 0, pat_vpool = 0;
+    double* patL = nullptr;
+    double* patS = nullptr;
+    float* patL32 = nullptr;
+    float* patS32 = nullptr;
+    double* patW = nullptr;  // per-patch local solution (vpool)
+    float* patW32 = nullptr;
+    // snapshots and Gram
+    int nfk, ncol;            // faces per block (full, incl. block boundary), snapshot columns per block
+    double* Psi = nullptr;    // nblk * ncol * nfk  (column major per block)
+    double* APsi = nullptr;
+    double* G = nullptr;      // nblk * ncol * ncol
+    // spectral results per coarse face
+    double* eigs = nullptr;   // ne * jmax (ascending lambda)
+    int* counts = nullptr;    // ne
+    double* Y = nullptr;      // ne * jmax * jmax
+    std::vector<int> counts_h;
+    // coarse SPD system
+    int ncs = 0;              // unknowns
+    int mu = 0;               // max unknowns touching one block
+    int* blk_unk = nullptr;   // nblk * mu (ids, -1 pad)
+    int* blk_nu = nullptr;    // nblk
+    double* blk_T = nullptr;  // nblk * ncol * mu : snapshot-column coefficients of each unknown on K
+    double* W = nullptr;      // nblk * (bx*by) * mu  stream functions on owned vertices
+    float* W32 = nullptr;
+    int* unk_ptr = nullptr;   // ncs+1 CSR of (block, slot) touching each unknown
+    int* unk_ent = nullptr;
+    double* Ac = nullptr;     // ncs * ncs (dense, then its inverse)
+    float* Ac32 = nullptr;
+    double* cy = nullptr;     // nblk * mu restricted values
+    float* cy32 = nullptr;
+    double* cvec = nullptr;   // ncs
+    double* cvec2 = nullptr;
+    float* cvec32 = nullptr;
+    float* cvec2_32 = nullptr;
+    // coarse RT0 (preprocessing)
+    int nv = 0;               // interior coarse vertices
+    double* AH0 = nullptr;    // nblk * 6 : WW, WE, EE, SS, SN, NN
+    double* KH = nullptr;     // nv * nv inverse of the coarse vertex stiffness
+    double* cflux = nullptr;  // coarse velocities: x part Ny*(Nx+1), y part (Ny+1)*Nx
+    double* svec = nullptr;   // nv
+    double* svec2 = nullptr;
+    // pressure
+    double* Qx = nullptr;     // nx*nx DCT-II (orthonormal)
+    double* Qy = nullptr;
+    double* lamx = nullptr;
+    double* lamy = nullptr;
+    // solve workspaces (vertex arrays nx*ny, face arrays nf)
+    double *vx = nullptr, *vg = nullptr, *vz = nullptr, *vp = nullptr, *vq = nullptr, *vt = nullptr,
+           *vt2 = nullptr, *vgold = nullptr;
+    float *fg = nullptr, *fz = nullptr, *ft = nullptr, *ft2 = nullptr;
+    double *fbar = nullptr, *fu = nullptr, *fF = nullptr, *cellw = nullptr, *cellw2 = nullptr;
+    double* blkbuf = nullptr; // 2 * nblk
+    double* red = nullptr;    // reduction scratch
+    double* red_h = nullptr;  // pinned host
+    int red_blocks = 0;
+    // diagnostics
+    std::vector<double> alphas, betas;
+    double t_setup_ms = 0, t_snap_ms = 0, t_eig_ms = 0, t_coarse_ms = 0, t_smoother_ms = 0;
+    std::vector<DeviceBuf> owned;
+
+    template <typename T>
+    T* alloc(size_t n) {
+        DeviceBuf b;
+        b.bytes = n * sizeof(T) + 256;
+        HIP_OK(hipMalloc(&b.p, b.bytes));
+        HIP_OK(hipMemsetAsync(b.p, 0, b.bytes, stream));
+        owned.push_back(b);
+        return reinterpret_cast<T*>(b.p);
+    }
+};
+
+// ---------------------------------------------------------------- launchers
+namespace tgms {
+// grid / vector kernels (k_grid.hip)
+void cell_weights(tgms_ctx* c, const double* kappa, int* bad);
+template <typename T>
+void apply_K(tgms_ctx* c, const T* psi, T* out, const T* a);
+template <typename T>
+void residual_K(tgms_ctx* c, const T* g, const T* psi, T* out, const T* a);  // out = g - K psi
+void faces_A(tgms_ctx* c, const double* u, double* out);                    // A u on interior faces
+void faces_A_probe(tgms_ctx* c, const double* u, double* out);              // same, boundary inputs ignored
+void curlT_A_faces(tgms_ctx* c, const double* u, double* g, double scale);  // g = scale * C^T A u
+void curl_add(tgms_ctx* c, const double* psi, const double* base, double* u); // u = base + C psi
+void curlT(tgms_ctx* c, const double* u, double* g);
+double dot(tgms_ctx* c, const double* x, const double* y, long long n);
+void dot3(tgms_ctx* c, const double* g, const double* z, const double* gold, double out[3]);
+double curl_norm2(tgms_ctx* c, const double* psi);
+void axpy(tgms_ctx* c, long long n, double a, const double* x, double* y);        // y += a x
+void xpay(tgms_ctx* c, long long n, const double* x, double b, double* y);        // y = x + b y
+void cast_d2f(tgms_ctx* c, long long n, const double* x, float* y);
+void cast_f2d(tgms_ctx* c, long long n, const float* x, double* y);
+void zero(tgms_ctx* c, void* p, size_t bytes);
+// band factors and smoother (k_band.hip)
+void factor_blocks(tgms_ctx* c);
+void factor_patches(tgms_ctx* c);
+template <typename T>
+void smooth(tgms_ctx* c, const T* g, T* z, bool accumulate);  // z (+)= S g
+// setup (k_setup.hip)
+void snapshots(tgms_ctx* c);
+void gram(tgms_ctx* c);
+void pencil_eig_q(tgms_ctx* c, double* Q);
+void coarse_local_run(tgms_ctx* c, const double* Tm, const int* zc);
+void coarse_rt0_blocks(tgms_ctx* c);
+// coarse apply (k_setup.hip)
+template <typename T>
+void coarse_apply(tgms_ctx* c, const T* g, T* z, bool accumulate);
+// dense (k_dense.hip)
+void dense_spd_inverse(tgms_ctx* c, double* A, int n);
+template <typename T>
+void symv(tgms_ctx* c, const T* A, int n, const T* x, T* y);
+void gemm(tgms_ctx* c, int transA, int transB, int M, int N, int K, double alpha, const double* A, int lda,
+          const double* B, int ldb, double beta, double* C, int ldc);
+// preprocessing and pressure (k_pre.hip)
+void preprocess(tgms_ctx* c, const double* F, const double* g_bnd, double* vbar, double* Fp);
+void pressure(tgms_ctx* c, const double* u, double* p);
+}  // namespace tgms

@@ -1,0 +1,257 @@
+// Dense FP64 Cholesky of the coarse SPD operator and its application.
+//
+// The coarse problem (paper eq. coarsepre, L_H = R_H L R_H^T) is solved
+// exactly ("direct solver", section 5).  After restriction to its
+// divergence-free subspace it is SPD; it is factorised A = L L^T by a blocked
+// right-looking Cholesky, then X = L^{-1} is formed by block forward
+// substitution.  The factor is kept as one n x n array
+//     B = tril(X) + triu(X^T, 1),
+// so A^{-1} g = X^T (X g) costs two triangular matrix-vector products that
+// each stream one triangle of B row by row.
+#include "common.h"
+
+namespace {
+
+constexpr int TB = 64;   // output tile
+constexpr int TK = 16;   // k step
+constexpr int NT = 256;  // threads (16 x 16), 4 x 4 outputs each
+
+// C = alpha * op(A) * op(B) + beta * C ; row-major; op(A) is M x K, op(B) is K x N.
+// lower_only: skip output tiles strictly above the diagonal (tile row < tile col).
+__global__ void __launch_bounds__(NT) k_gemm(int transA, int transB, int M, int N, int K, double alpha,
+                                             const double* __restrict__ A, int lda, const double* __restrict__ B,
+                                             int ldb, double beta, double* C, int ldc, int lower_only) {
+    const int tm = blockIdx.y, tn = blockIdx.x;
+    if (lower_only && tm < tn) return;
+    __shared__ double As[TK][TB + 1];
+    __shared__ double Bs[TK][TB + 1];
+    const int tid = threadIdx.x;
+    const int ty = tid / 16, tx = tid % 16;
+    const int m0 = tm * TB, n0 = tn * TB;
+    double acc[4][4] = {};
+    for (int k0 = 0; k0 < K; k0 += TK) {
+        // load op(A)[m0..m0+64, k0..k0+16] and op(B)[k0..k0+16, n0..n0+64]
+        for (int e = tid; e < TB * TK; e += NT) {
+            int mm, kk;
+            if (transA) {  // A stored K x M: contiguous along m
+                kk = e / TB;
+                mm = e % TB;
+            } else {
+                mm = e / TK;
+                kk = e % TK;
+            }
+            const int gm = m0 + mm, gk = k0 + kk;
+            double v = 0.0;
+            if (gm < M && gk < K) v = transA ? A[(long long)gk * lda + gm] : A[(long long)gm * lda + gk];
+            As[kk][mm] = v;
+        }
+        for (int e = tid; e < TB * TK; e += NT) {
+            int nn, kk;
+            if (transB) {  // B stored N x K: contiguous along k
+                nn = e / TK;
+                kk = e % TK;
+            } else {
+                kk = e / TB;
+                nn = e % TB;
+            }
+            const int gn = n0 + nn, gk = k0 + kk;
+            double v = 0.0;
+            if (gn < N && gk < K) v = transB ? B[(long long)gn * ldb + gk] : B[(long long)gk * ldb + gn];
+            Bs[kk][nn] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < TK; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[r] = As[kk][ty + 16 * r];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) b[s] = Bs[kk][tx + 16 * s];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) acc[r][s] += a[r] * b[s];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + ty + 16 * r;
+        if (gm >= M) continue;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int gn = n0 + tx + 16 * s;
+            if (gn >= N) continue;
+            double* cp = C + (long long)gm * ldc + gn;
+            *cp = alpha * acc[r][s] + (beta == 0.0 ? 0.0 : beta * *cp);
+        }
+    }
+}
+
+// Cholesky of the kb x kb diagonal block at (k0, k0) in place, and its inverse into Dinv (kb x kb, ld 64).
+__global__ void __launch_bounds__(NT) k_potrf_diag(double* __restrict__ A, int lda, int k0, int kb,
+                                                   double* __restrict__ Dinv, int* __restrict__ fail) {
+    __shared__ double S[TB][TB + 1];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < kb * kb; e += NT) {
+        int i = e / kb, j = e % kb;
+        S[i][j] = (j <= i) ? A[(long long)(k0 + i) * lda + k0 + j] : 0.0;
+    }
+    __syncthreads();
+    for (int j = 0; j < kb; ++j) {
+        const double d = S[j][j];
+        if (!(d > 0.0)) {
+            if (tid == 0) atomicOr(fail, 1);
+            return;
+        }
+        const double l = sqrt(d);
+        __syncthreads();
+        if (tid == 0) S[j][j] = l;
+        for (int i = j + 1 + tid; i < kb; i += NT) S[i][j] /= l;
+        __syncthreads();
+        for (int e = tid; e < (kb - j - 1) * (kb - j - 1); e += NT) {
+            int i = j + 1 + e / (kb - j - 1), k = j + 1 + e % (kb - j - 1);
+            if (k <= i) S[i][k] -= S[i][j] * S[k][j];
+        }
+        __syncthreads();
+    }
+    // inverse of the lower-triangular block: column c of Dinv solves L x = e_c (each thread
+    // writes and re-reads only its own column)
+    if (tid < kb) {
+        const int cidx = tid;
+        for (int i = 0; i < kb; ++i) {
+            double s = (i == cidx) ? 1.0 : 0.0;
+            for (int k = cidx; k < i; ++k) s -= S[i][k] * Dinv[k * TB + cidx];
+            Dinv[i * TB + cidx] = (i < cidx) ? 0.0 : s / S[i][i];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < kb * kb; e += NT) {
+        int i = e / kb, j = e % kb;
+        if (j <= i) A[(long long)(k0 + i) * lda + k0 + j] = S[i][j];
+    }
+}
+
+// B[i][j] = X[i][j] (j <= i), B[i][j] = X[j][i] (j > i)
+__global__ void k_pack_inverse(const double* __restrict__ X, double* __restrict__ B, int n) {
+    long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= (long long)n * n) return;
+    int i = (int)(e / n), j = (int)(e % n);
+    B[e] = (j <= i) ? X[e] : X[(long long)j * n + i];
+}
+
+__global__ void k_copy_block(const double* __restrict__ src, int lds, double* __restrict__ dst, int ldd, int rows,
+                             int cols) {
+    long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= (long long)rows * cols) return;
+    int i = (int)(e / cols), j = (int)(e % cols);
+    dst[(long long)i * ldd + j] = src[(long long)i * lds + j];
+}
+
+// y = tril(B) x (part 0) or y = triu(B) x (part 1): one wavefront per row.
+template <typename T>
+__global__ void k_trimv(const T* __restrict__ B, int n, const T* __restrict__ x, T* __restrict__ y, int part) {
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    const T* br = B + (long long)row * n;
+    const int j0 = part ? row : 0, j1 = part ? n : row + 1;
+    T s = T(0);
+    for (int j = j0 + lane; j < j1; j += 64) s += br[j] * x[j];
+    s = wave_sum(s);
+    if (lane == 0) y[row] = s;
+}
+
+inline unsigned nb(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+namespace tgms {
+
+void gemm(tgms_ctx* c, int transA, int transB, int M, int N, int K, double alpha, const double* A, int lda,
+          const double* B, int ldb, double beta, double* C, int ldc) {
+    if (M <= 0 || N <= 0) return;
+    dim3 grid((N + TB - 1) / TB, (M + TB - 1) / TB);
+    hipLaunchKernelGGL(k_gemm, grid, dim3(NT), 0, c->stream, transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C,
+                       ldc, 0);
+    LAUNCH_OK();
+}
+
+// In place: A (n x n, row-major, symmetric positive definite) -> B = tril(L^{-1}) + triu(L^{-T}, 1).
+void dense_spd_inverse(tgms_ctx* c, double* A, int n) {
+    if (n <= 0) return;
+    const int nblk = (n + TB - 1) / TB;
+    double* Dinv = c->alloc<double>((size_t)nblk * TB * TB);
+    int* fail = c->alloc<int>(1);
+    // 1. blocked Cholesky (lower)
+    for (int kb0 = 0; kb0 < nblk; ++kb0) {
+        const int k0 = kb0 * TB, kb = std::min(TB, n - k0), k1 = k0 + kb;
+        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(NT), 0, c->stream, A, n, k0, kb, Dinv + (size_t)kb0 * TB * TB,
+                           fail);
+        LAUNCH_OK();
+        const int m = n - k1;
+        if (m <= 0) break;
+        // panel: A[k1:, k0:k1] = A[k1:, k0:k1] * Dinv^T (each output row tile reads only its own row tile)
+        {
+            dim3 grid(1, (m + TB - 1) / TB);
+            hipLaunchKernelGGL(k_gemm, grid, dim3(NT), 0, c->stream, 0, 1, m, kb, kb, 1.0,
+                               (const double*)(A + (size_t)k1 * n + k0), n,
+                               (const double*)(Dinv + (size_t)kb0 * TB * TB), TB, 0.0, A + (size_t)k1 * n + k0, n, 0);
+            LAUNCH_OK();
+        }
+        // trailing: A[k1:, k1:] -= P P^T (lower tiles only)
+        {
+            dim3 grid((m + TB - 1) / TB, (m + TB - 1) / TB);
+            hipLaunchKernelGGL(k_gemm, grid, dim3(NT), 0, c->stream, 0, 1, m, m, kb, -1.0,
+                               (const double*)(A + (size_t)k1 * n + k0), n, (const double*)(A + (size_t)k1 * n + k0),
+                               n, 1.0, A + (size_t)k1 * n + k1, n, 1);
+            LAUNCH_OK();
+        }
+    }
+    int h = 0;
+    HIP_OK(hipMemcpyAsync(&h, fail, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (h) throw TgmsError{TGMS_E_INVAL, "coarse operator is not positive definite"};
+    // 2. X = L^{-1} by block rows: X[r, r] = Dinv_r, X[r, 0:r] = -Dinv_r (L[r, 0:r] X[0:r, 0:r])
+    double* X = c->alloc<double>((size_t)n * n);
+    double* Tm = c->alloc<double>((size_t)TB * n);
+    for (int r = 0; r < nblk; ++r) {
+        const int r0 = r * TB, rb = std::min(TB, n - r0);
+        hipLaunchKernelGGL(k_copy_block, dim3(nb((long long)rb * rb)), dim3(256), 0, c->stream,
+                           (const double*)(Dinv + (size_t)r * TB * TB), TB, X + (size_t)r0 * n + r0, n, rb, rb);
+        LAUNCH_OK();
+        if (r0 == 0) continue;
+        // Tm (rb x r0) = L[r0:r0+rb, 0:r0] * X[0:r0, 0:r0]
+        gemm(c, 0, 0, rb, r0, r0, 1.0, A + (size_t)r0 * n, n, X, n, 0.0, Tm, n);
+        // X[r0:, 0:r0] = -Dinv_r * Tm
+        gemm(c, 0, 0, rb, r0, rb, -1.0, Dinv + (size_t)r * TB * TB, TB, Tm, n, 0.0, X + (size_t)r0 * n, n);
+    }
+    // 3. pack
+    hipLaunchKernelGGL(k_pack_inverse, dim3(nb((long long)n * n)), dim3(256), 0, c->stream, (const double*)X, A, n);
+    LAUNCH_OK();
+    HIP_OK(hipStreamSynchronize(c->stream));
+    // release the temporaries (they are the last allocations)
+    for (int k = 0; k < 4; ++k) {
+        HIP_OK(hipFree(c->owned.back().p));
+        c->owned.pop_back();
+    }
+}
+
+// y = A^{-1} x with A^{-1} held as B = tril(X) + triu(X^T, 1); tmp has n entries.
+template <typename T>
+void symv(tgms_ctx* c, const T* B, int n, const T* x, T* y) {
+    if (n <= 0) return;
+    T* tmp;
+    if constexpr (sizeof(T) == 8)
+        tmp = (T*)c->cvec2;
+    else
+        tmp = (T*)c->cvec2_32;
+    hipLaunchKernelGGL((k_trimv<T>), dim3((n + 3) / 4), dim3(256), 0, c->stream, B, n, x, tmp, 0);
+    LAUNCH_OK();
+    hipLaunchKernelGGL((k_trimv<T>), dim3((n + 3) / 4), dim3(256), 0, c->stream, B, n, (const T*)tmp, y, 1);
+    LAUNCH_OK();
+}
+template void symv<double>(tgms_ctx*, const double*, int, const double*, double*);
+template void symv<float>(tgms_ctx*, const float*, int, const float*, float*);
+
+}  // namespace tgms

@@ -1,0 +1,597 @@
+// Adaptive spectral coarse space (paper section 4) and the coarse correction
+// (eq. coarsepre).
+//
+// Snapshots (section 4.1, eq. snapshot_eqn) are computed per coarse block K:
+// for every interior side E of K and every fine face e_l of E, the local
+// mixed problem with v.n = delta_l on E, zero flux on the rest of dK and
+// constant divergence (outward flux / |K|) is solved as
+//     v = v_p + C_K psi,  (C_K^T A_K C_K) psi = -C_K^T A_K v_p,
+// where v_p is an explicit particular flux with the right boundary flux and
+// divergence, and psi lives on K's interior vertices (band factor of
+// k_band.hip).  The snapshot of face E_i on omega_i is the pair of K1 and K2
+// solutions sharing delta_l on E_i.
+//
+// The spectral pencil (section 4.2, eq. spectral_eqn) of E_i is assembled
+// from the block Gram matrices G_K = Psi_K^T A_K Psi_K of its two blocks plus
+// the divergence term sum_K |e_l||e_m|/|K|, scaled by 1/H; the a-form is
+// diagonal, D_ll = |e_l| (kappa_L^{-1} + kappa_R^{-1})/2.  T = D^{-1/2} S
+// D^{-1/2} is diagonalised by cyclic Jacobi; lambda = 1/mu ascending and the
+// first max(1, #{lambda < tol}) modes are kept.
+//
+// The coarse problem is restricted to its divergence-free subspace, spanned
+// by (i) the zero-net-flux combinations of each face's modes and (ii) for each
+// interior coarse vertex the coarse-curl combination of the unit-flux
+// "carriers" of the four faces meeting there.  Its SPD matrix is the
+// divergence-free part of L_H; the coarse correction is
+// P = W (Z^T A Z)^{-1} W^T in stream-function coordinates, W holding the
+// stream functions of those basis fields on each block's vertices.
+#include "common.h"
+#include "band.h"
+#include "block.h"
+
+namespace {
+
+struct BlockGeom {
+    int nx, ny, bx, by, Nx, Ny, jmax, nfk, ncol;
+    double hx, hy, sx, sy;
+};
+
+// Snapshots: one wavefront per block, columns (side s, fine face l) in turn.
+__global__ void k_snapshots(BlockGeom G, const double* __restrict__ a, const double* __restrict__ blkL,
+                            const double* __restrict__ blkS, double* __restrict__ Psi) {
+    extern __shared__ double sm[];
+    const int bxl = G.bx, byl = G.by;
+    const int nfx = byl * (bxl + 1), nfy = (byl + 1) * bxl, nloc = (bxl - 1) * (byl - 1);
+    double* Fw = sm;
+    double* Fe = Fw + byl;
+    double* Fs = Fe + byl;
+    double* Fn = Fs + bxl;
+    double* q = Fn + bxl;
+    double* vx = q + bxl * byl;
+    double* vy = vx + nfx;
+    double* ox = vy + nfy;
+    double* oy = ox + nfx;
+    double* g = oy + nfy;
+    double* tmp = g + nloc;
+    const int blk = blockIdx.x, I = blk % G.Nx, J = blk / G.Nx;
+    const int lane = threadIdx.x;
+    const double* aK = a + (long long)J * G.by * G.nx + (long long)I * G.bx;
+    const double areaK = G.bx * G.hx * G.by * G.hy;
+    const long long ld = bxl + 1;
+    const double* L = blkL + (long long)blk * nloc * ld;
+    const double* S = blkS + (long long)blk * nloc;
+    double* out = Psi + (long long)blk * G.ncol * G.nfk;
+    for (int s = 0; s < 4; ++s) {
+        const bool interior = (s == 0 && I > 0) || (s == 1 && I < G.Nx - 1) || (s == 2 && J > 0) ||
+                              (s == 3 && J < G.Ny - 1);
+        const int nl = (s < 2) ? byl : bxl;
+        for (int l = 0; l < G.jmax; ++l) {
+            double* col = out + (long long)(s * G.jmax + l) * G.nfk;
+            if (!interior || l >= nl) {
+                for (int e = lane; e < G.nfk; e += 64) col[e] = 0.0;
+                continue;
+            }
+            // boundary flux delta_l on side s (velocity 1 in the +axis direction)
+            for (int e = lane; e < 2 * byl + 2 * bxl; e += 64) Fw[e] = 0.0;
+            __syncthreads();
+            const double elen = (s < 2) ? G.hy : G.hx;
+            double outflow;
+            if (lane == 0) {
+                if (s == 0) Fw[l] = elen;
+                if (s == 1) Fe[l] = elen;
+                if (s == 2) Fs[l] = elen;
+                if (s == 3) Fn[l] = elen;
+            }
+            outflow = (s == 1 || s == 3) ? elen : -elen;
+            const double qc = outflow / (bxl * byl);  // alpha |c| = outward flux / |K| * |c|
+            for (int e = lane; e < bxl * byl; e += 64) q[e] = qc;
+            __syncthreads();
+            particular_flux(bxl, byl, Fw, Fe, Fs, Fn, q, vx, vy, tmp);
+            for (int e = lane; e < nfx; e += 64) vx[e] *= 1.0 / G.hy;
+            for (int e = lane; e < nfy; e += 64) vy[e] *= 1.0 / G.hx;
+            __syncthreads();
+            block_mass(bxl, byl, aK, G.nx, vx, vy, ox, oy);
+            block_curlT(bxl, byl, ox, oy, G.sx, G.sy, -1.0, g);
+            band_solve_wave<double>(L, S, nloc, bxl, g);
+            __syncthreads();
+            block_curl_add(bxl, byl, g, G.sx, G.sy, vx, vy);
+            for (int e = lane; e < nfx; e += 64) col[e] = vx[e];
+            for (int e = lane; e < nfy; e += 64) col[nfx + e] = vy[e];
+            __syncthreads();
+        }
+    }
+}
+
+// APsi = A_K Psi_K (block-local mass applied to every snapshot column); one wavefront per (block, column).
+__global__ void k_apply_AK_cols(BlockGeom G, const double* __restrict__ a, const double* __restrict__ Psi,
+                                double* __restrict__ APsi) {
+    const int blk = blockIdx.x, colid = blockIdx.y;
+    const int I = blk % G.Nx, J = blk / G.Nx;
+    const double* aK = a + (long long)J * G.by * G.nx + (long long)I * G.bx;
+    const int bxl = G.bx, byl = G.by, nfx = byl * (bxl + 1);
+    const double* v = Psi + ((long long)blk * G.ncol + colid) * G.nfk;
+    double* o = APsi + ((long long)blk * G.ncol + colid) * G.nfk;
+    const double c3 = 1.0 / 3.0, c6 = 1.0 / 6.0;
+    for (int e = threadIdx.x; e < G.nfk; e += blockDim.x) {
+        double s = 0.0;
+        if (e < nfx) {
+            const int b = e / (bxl + 1), aa = e % (bxl + 1);
+            if (aa > 0) s += aK[(long long)b * G.nx + aa - 1] * (v[e] * c3 + v[e - 1] * c6);
+            if (aa < bxl) s += aK[(long long)b * G.nx + aa] * (v[e] * c3 + v[e + 1] * c6);
+        } else {
+            const int f = e - nfx, b = f / bxl, aa = f % bxl;
+            if (b > 0) s += aK[(long long)(b - 1) * G.nx + aa] * (v[e] * c3 + v[e - bxl] * c6);
+            if (b < byl) s += aK[(long long)b * G.nx + aa] * (v[e] * c3 + v[e + bxl] * c6);
+        }
+        o[e] = s;
+    }
+}
+
+// G_K = Psi_K^T (A_K Psi_K): one workgroup of (ncol/4)^2 threads per block, 4 x 4 outputs per thread.
+__global__ void k_gram(BlockGeom G, const double* __restrict__ Psi, const double* __restrict__ APsi,
+                       double* __restrict__ Gout) {
+    constexpr int FC = 32;
+    extern __shared__ double sm[];
+    const int ncol = G.ncol, q4 = ncol / 4;
+    double* Ps = sm;                // [ncol][FC]
+    double* As = sm + ncol * FC;    // [ncol][FC]
+    const int blk = blockIdx.x;
+    const double* P = Psi + (long long)blk * ncol * G.nfk;
+    const double* AP = APsi + (long long)blk * ncol * G.nfk;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int r0 = (tid / q4) * 4, c0 = (tid % q4) * 4;
+    double acc[4][4] = {};
+    for (int f0 = 0; f0 < G.nfk; f0 += FC) {
+        for (int e = tid; e < ncol * FC; e += nth) {
+            const int cc = e / FC, ff = e % FC;
+            const bool ok = f0 + ff < G.nfk;
+            Ps[e] = ok ? P[(long long)cc * G.nfk + f0 + ff] : 0.0;
+            As[e] = ok ? AP[(long long)cc * G.nfk + f0 + ff] : 0.0;
+        }
+        __syncthreads();
+        for (int ff = 0; ff < FC; ++ff) {
+            double x[4], y[4];
+            for (int r = 0; r < 4; ++r) x[r] = Ps[(r0 + r) * FC + ff];
+            for (int s = 0; s < 4; ++s) y[s] = As[(c0 + s) * FC + ff];
+            for (int r = 0; r < 4; ++r)
+                for (int s = 0; s < 4; ++s) acc[r][s] += x[r] * y[s];
+        }
+        __syncthreads();
+    }
+    double* Gb = Gout + (long long)blk * ncol * ncol;
+    for (int r = 0; r < 4; ++r)
+        for (int s = 0; s < 4; ++s) Gb[(r0 + r) * ncol + c0 + s] = acc[r][s];
+}
+
+// Pencil, Jacobi eigensolve, selection and recombination: one wavefront per coarse face.
+__global__ void k_pencil_eig(BlockGeom G, const double* __restrict__ kinv, const double* __restrict__ Gm,
+                             double tol, double invH, double* __restrict__ eigs, int* __restrict__ counts,
+                             double* __restrict__ Yout, double* __restrict__ Qout) {
+    __shared__ double T[64][65];
+    __shared__ double V[64][65];
+    __shared__ double D[64];
+    __shared__ double cs[32][2];
+    __shared__ int order[64];
+    __shared__ int rot_flag;
+    const int fid = blockIdx.x, lane = threadIdx.x;
+    const int nex = (G.Nx - 1) * G.Ny;
+    int K1, K2, s1, s2, Jn;
+    double elen;
+    long long cellL, cellR, step;
+    if (fid < nex) {  // x-face (I, J), I = 1..Nx-1
+        const int J = fid / (G.Nx - 1), I = fid % (G.Nx - 1) + 1;
+        K1 = J * G.Nx + I - 1;
+        K2 = J * G.Nx + I;
+        s1 = 1;
+        s2 = 0;
+        Jn = G.by;
+        elen = G.hy;
+        cellL = (long long)(J * G.by) * G.nx + I * G.bx - 1;
+        cellR = cellL + 1;
+        step = G.nx;
+    } else {  // y-face (I, J), J = 1..Ny-1
+        const int f = fid - nex, J = f / G.Nx + 1, I = f % G.Nx;
+        K1 = (J - 1) * G.Nx + I;
+        K2 = J * G.Nx + I;
+        s1 = 3;
+        s2 = 2;
+        Jn = G.bx;
+        elen = G.hx;
+        cellL = (long long)(J * G.by - 1) * G.nx + I * G.bx;
+        cellR = cellL + G.nx;
+        step = 1;
+    }
+    const double areaK = G.bx * G.hx * G.by * G.hy;
+    const double* G1 = Gm + (long long)K1 * G.ncol * G.ncol;
+    const double* G2 = Gm + (long long)K2 * G.ncol * G.ncol;
+    for (int l = lane; l < Jn; l += 64) D[l] = elen * 0.5 * (kinv[cellL + l * step] + kinv[cellR + l * step]);
+    __syncthreads();
+    for (int e = lane; e < Jn * Jn; e += 64) {
+        const int l = e / Jn, mm = e % Jn;
+        const double s = (G1[(s1 * G.jmax + l) * G.ncol + s1 * G.jmax + mm] +
+                          G2[(s2 * G.jmax + l) * G.ncol + s2 * G.jmax + mm] + 2.0 * elen * elen / areaK) *
+                         invH;
+        T[l][mm] = s / sqrt(D[l] * D[mm]);
+        V[l][mm] = (l == mm) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    // symmetrise (the two Gram halves are symmetric up to round-off)
+    for (int e = lane; e < Jn * Jn; e += 64) {
+        const int l = e / Jn, mm = e % Jn;
+        if (l < mm) {
+            const double avg = 0.5 * (T[l][mm] + T[mm][l]);
+            T[l][mm] = avg;
+            T[mm][l] = avg;
+        }
+    }
+    __syncthreads();
+    // cyclic Jacobi, round-robin ordering over N (even) players
+    const int N = (Jn + 1) & ~1, half = N / 2;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        if (lane == 0) rot_flag = 0;
+        __syncthreads();
+        for (int rnd = 0; rnd < N - 1; ++rnd) {
+            if (lane < half) {
+                auto pos = [&](int x) { return x == 0 ? 0 : 1 + (x - 1 + rnd) % (N - 1); };
+                const int p = pos(lane), qq = pos(N - 1 - lane);
+                double c = 1.0, s = 0.0;
+                if (p < Jn && qq < Jn) {
+                    const double apq = T[p][qq], app = T[p][p], aqq = T[qq][qq];
+                    if (fabs(apq) > 1e-300 && fabs(apq) > 1e-17 * sqrt(fabs(app * aqq))) {
+                        const double th = (aqq - app) / (2.0 * apq);
+                        const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                        c = 1.0 / sqrt(t * t + 1.0);
+                        s = t * c;
+                        rot_flag = 1;
+                    }
+                }
+                cs[lane][0] = c;
+                cs[lane][1] = s;
+            }
+            __syncthreads();
+            // rows: T <- P^T T
+            for (int e = lane; e < half * Jn; e += 64) {
+                const int k = e / Jn, x = e % Jn;
+                auto pos = [&](int y) { return y == 0 ? 0 : 1 + (y - 1 + rnd) % (N - 1); };
+                const int p = pos(k), qq = pos(N - 1 - k);
+                if (p < Jn && qq < Jn) {
+                    const double c = cs[k][0], s = cs[k][1];
+                    const double tp = T[p][x], tq = T[qq][x];
+                    T[p][x] = c * tp - s * tq;
+                    T[qq][x] = s * tp + c * tq;
+                }
+            }
+            __syncthreads();
+            // columns: T <- T P, V <- V P
+            for (int e = lane; e < half * Jn; e += 64) {
+                const int k = e / Jn, x = e % Jn;
+                auto pos = [&](int y) { return y == 0 ? 0 : 1 + (y - 1 + rnd) % (N - 1); };
+                const int p = pos(k), qq = pos(N - 1 - k);
+                if (p < Jn && qq < Jn) {
+                    const double c = cs[k][0], s = cs[k][1];
+                    const double tp = T[x][p], tq = T[x][qq];
+                    T[x][p] = c * tp - s * tq;
+                    T[x][qq] = s * tp + c * tq;
+                    const double vp = V[x][p], vq = V[x][qq];
+                    V[x][p] = c * vp - s * vq;
+                    V[x][qq] = s * vp + c * vq;
+                }
+            }
+            __syncthreads();
+        }
+        if (!rot_flag) break;
+        __syncthreads();
+    }
+    // sort mu descending (lambda = 1/mu ascending)
+    if (lane < Jn) {
+        const double mu = T[lane][lane];
+        int rank = 0;
+        for (int k = 0; k < Jn; ++k) {
+            const double o = T[k][k];
+            rank += (o > mu) || (o == mu && k < lane);
+        }
+        order[rank] = lane;
+    }
+    __syncthreads();
+    double* ev = eigs + (long long)fid * G.jmax;
+    for (int k = lane; k < G.jmax; k += 64) ev[k] = (k < Jn) ? 1.0 / T[order[k]][order[k]] : 0.0;
+    __syncthreads();
+    int cnt = 0;
+    for (int k = 0; k < Jn; ++k) cnt += (1.0 / T[order[k]][order[k]] < tol);
+    cnt = cnt < 1 ? 1 : cnt;
+    if (lane == 0) counts[fid] = cnt;
+    // Y[:, k] = D^{-1/2} v_k for the kept modes; flux f_k = |e| sum_l Y[l][k]
+    double* Yf = Yout + (long long)fid * G.jmax * G.jmax;
+    for (int e = lane; e < G.jmax * G.jmax; e += 64) {
+        const int l = e / G.jmax, k = e % G.jmax;
+        Yf[e] = (l < Jn && k < cnt) ? V[l][order[k]] / sqrt(D[l]) : 0.0;
+    }
+    __syncthreads();
+    // recombination Q (cnt x cnt, stored jmax x jmax): column 0 = f/|f|^2 (unit-flux carrier),
+    // columns 1.. = an orthonormal basis of f^perp (Householder reflector mapping f/|f| to e_1).
+    if (lane == 0) {
+        double f[64], nrm2 = 0.0;
+        for (int k = 0; k < cnt; ++k) {
+            double s = 0.0;
+            for (int l = 0; l < Jn; ++l) s += Yf[l * G.jmax + k];
+            f[k] = elen * s;
+            nrm2 += f[k] * f[k];
+        }
+        double* Qf = Qout + (long long)fid * G.jmax * G.jmax;
+        for (int e = 0; e < G.jmax * G.jmax; ++e) Qf[e] = 0.0;
+        for (int k = 0; k < cnt; ++k) Qf[k * G.jmax] = f[k] / nrm2;
+        if (cnt > 1) {
+            const double nr = sqrt(nrm2);
+            double w[64], ww = 0.0;
+            for (int k = 0; k < cnt; ++k) w[k] = f[k] / nr;
+            w[0] += (w[0] >= 0 ? 1.0 : -1.0);
+            for (int k = 0; k < cnt; ++k) ww += w[k] * w[k];
+            for (int r = 0; r < cnt; ++r)
+                for (int cc = 1; cc < cnt; ++cc)
+                    Qf[r * G.jmax + cc] = ((r == cc) ? 1.0 : 0.0) - 2.0 * w[r] * w[cc] / ww;
+        }
+    }
+}
+
+// Per block: Ak = T_K^T G_K T_K scattered into the dense coarse matrix, and the
+// path integral of every snapshot column to vertex values (for the stream functions).
+__global__ void k_coarse_local(BlockGeom G, const double* __restrict__ Gm, const double* __restrict__ Tm, int mu,
+                               const int* __restrict__ unk, const int* __restrict__ nunk, double* __restrict__ Ac,
+                               int ncs, const double* __restrict__ Psi, double* __restrict__ PPsi) {
+    extern __shared__ double sm[];
+    const int blk = blockIdx.x, tid = threadIdx.x, nth = blockDim.x;
+    const int ncol = G.ncol, nu = nunk[blk];
+    const double* Gb = Gm + (long long)blk * ncol * ncol;
+    const double* Tb = Tm + (long long)blk * ncol * mu;
+    double* GT = sm;  // ncol x mu
+    for (int e = tid; e < ncol * nu; e += nth) {
+        const int r = e / nu, u = e % nu;
+        double s = 0.0;
+        for (int k = 0; k < ncol; ++k) s += Gb[r * ncol + k] * Tb[k * mu + u];
+        GT[r * mu + u] = s;
+    }
+    __syncthreads();
+    const int* ub = unk + (long long)blk * mu;
+    for (int e = tid; e < nu * nu; e += nth) {
+        const int u = e / nu, w = e % nu;
+        double s = 0.0;
+        for (int k = 0; k < ncol; ++k) s += Tb[k * mu + u] * GT[k * mu + w];
+        atomicAdd(&Ac[(long long)ub[u] * ncs + ub[w]], s);
+    }
+    // path integral: psi(0,0) = 0, along the bottom edge by the y-fluxes, then up each column by the x-fluxes
+    const int bxl = G.bx, byl = G.by, nfx = byl * (bxl + 1);
+    const int nvtx = (bxl + 1) * (byl + 1);
+    for (int col = tid; col < ncol; col += nth) {
+        const double* v = Psi + ((long long)blk * ncol + col) * G.nfk;
+        double* o = PPsi + (long long)blk * nvtx * ncol;
+        double acc = 0.0;
+        o[col] = 0.0;
+        for (int a = 0; a < bxl; ++a) {
+            acc -= G.hx * v[nfx + a];  // y-face (a, 0)
+            o[(long long)(a + 1) * ncol + col] = acc;
+        }
+        for (int a = 0; a <= bxl; ++a) {
+            double p = o[(long long)a * ncol + col];
+            for (int b = 0; b < byl; ++b) {
+                p += G.hy * v[b * (bxl + 1) + a];
+                o[(long long)((b + 1) * (bxl + 1) + a) * ncol + col] = p;
+            }
+        }
+    }
+}
+
+// W_K[v][u] = sum_col PPsi[v][col] T[col][u] - (same at the unknown's zero corner), owned vertices.
+__global__ void k_coarse_W(BlockGeom G, const double* __restrict__ PPsi, const double* __restrict__ Tm, int mu,
+                           const int* __restrict__ nunk, const int* __restrict__ zc, double* __restrict__ W,
+                           float* __restrict__ W32) {
+    const int blk = blockIdx.x, tid = threadIdx.x;
+    const int I = blk % G.Nx, J = blk / G.Nx;
+    const int bxl = G.bx, byl = G.by, ncol = G.ncol, nu = nunk[blk];
+    const int nvtx = (bxl + 1) * (byl + 1), nown = bxl * byl;
+    const double* Pb = PPsi + (long long)blk * nvtx * ncol;
+    const double* Tb = Tm + (long long)blk * ncol * mu;
+    for (int e = tid; e < nown * mu; e += blockDim.x) {
+        const int v = e / mu, u = e % mu;
+        const int a = v % bxl, b = v / bxl;
+        double val = 0.0;
+        if (u < nu && !((I == 0 && a == 0) || (J == 0 && b == 0))) {
+            const int corner = zc[(long long)blk * mu + u];
+            const int vv = b * (bxl + 1) + a;
+            for (int k = 0; k < ncol; ++k) val += (Pb[(long long)vv * ncol + k] - Pb[(long long)corner * ncol + k]) * Tb[k * mu + u];
+        }
+        W[(long long)blk * nown * mu + e] = val;
+        if (W32) W32[(long long)blk * nown * mu + e] = (float)val;
+    }
+}
+
+// Coarse RT0 Gram per block: linear coarse basis functions W, E (x) and S, N (y).
+__global__ void k_rt0_blocks(BlockGeom G, const double* __restrict__ a, double* __restrict__ AH0) {
+    const int blk = blockIdx.x, I = blk % G.Nx, J = blk / G.Nx;
+    const int lane = threadIdx.x;
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    for (int e = lane; e < G.bx * G.by; e += 64) {
+        const int aa = e % G.bx, bb = e / G.bx;
+        const double w = a[(long long)(J * G.by + bb) * G.nx + I * G.bx + aa];
+        {  // x: phi_W = 1 - x/H at local faces aa, aa+1; phi_E = x/H
+            const double eL = (double)aa / G.bx, eR = (double)(aa + 1) / G.bx;
+            const double wL = 1.0 - eL, wR = 1.0 - eR;
+            s[0] += w * (wL * wL / 3 + wR * wR / 3 + wL * wR / 3);
+            s[1] += w * (wL * eL / 3 + wR * eR / 3 + (wL * eR + wR * eL) / 6);
+            s[2] += w * (eL * eL / 3 + eR * eR / 3 + eL * eR / 3);
+        }
+        {
+            const double nB = (double)bb / G.by, nT = (double)(bb + 1) / G.by;
+            const double sB = 1.0 - nB, sT = 1.0 - nT;
+            s[3] += w * (sB * sB / 3 + sT * sT / 3 + sB * sT / 3);
+            s[4] += w * (sB * nB / 3 + sT * nT / 3 + (sB * nT + sT * nB) / 6);
+            s[5] += w * (nB * nB / 3 + nT * nT / 3 + nB * nT / 3);
+        }
+    }
+    for (int k = 0; k < 6; ++k) {
+        const double t = wave_sum(s[k]);
+        if (lane == 0) AH0[(long long)blk * 6 + k] = t;
+    }
+}
+
+// ---- coarse apply in stream-function coordinates ----
+template <typename T>
+__global__ void k_coarse_restrict(const T* __restrict__ W, int mu, const int* __restrict__ nunk,
+                                  const T* __restrict__ g, int nx, int bx, int by, int Nx, T* __restrict__ cy) {
+    __shared__ T part[4][64];
+    const int blk = blockIdx.x, I = blk % Nx, J = blk / Nx;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int nown = bx * by, nu = nunk[blk];
+    const T* Wb = W + (long long)blk * nown * mu;
+    for (int u = 0; u < nu; ++u) {
+        T s = T(0);
+        for (int v = tid; v < nown; v += 256) {
+            const int aa = v % bx, bb = v / bx;
+            s += Wb[(long long)v * mu + u] * g[(long long)(J * by + bb) * nx + I * bx + aa];
+        }
+        s = wave_sum(s);
+        if (lane == 0) part[wid][u & 63] = s;
+        __syncthreads();
+        if (tid == 0) cy[(long long)blk * mu + u] = part[0][u & 63] + part[1][u & 63] + part[2][u & 63] + part[3][u & 63];
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ void k_coarse_accum(const int* __restrict__ ptr, const int* __restrict__ ent, const T* __restrict__ cy,
+                               int ncs, T* __restrict__ c) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= ncs) return;
+    T s = T(0);
+    for (int k = ptr[u]; k < ptr[u + 1]; ++k) s += cy[ent[k]];
+    c[u] = s;
+}
+
+template <typename T>
+__global__ void k_coarse_prolong(const T* __restrict__ W, int mu, const int* __restrict__ unk,
+                                 const int* __restrict__ nunk, const T* __restrict__ c, int nx, int bx, int by,
+                                 int Nx, T* __restrict__ z, int accumulate) {
+    const int blk = blockIdx.x, I = blk % Nx, J = blk / Nx;
+    const int nown = bx * by, nu = nunk[blk];
+    const T* Wb = W + (long long)blk * nown * mu;
+    const int* ub = unk + (long long)blk * mu;
+    for (int v = threadIdx.x; v < nown; v += blockDim.x) {
+        const int aa = v % bx, bb = v / bx;
+        T s = T(0);
+        for (int u = 0; u < nu; ++u) s += Wb[(long long)v * mu + u] * c[ub[u]];
+        T* zp = z + (long long)(J * by + bb) * nx + I * bx + aa;
+        *zp = accumulate ? *zp + s : s;
+    }
+}
+
+BlockGeom geom(tgms_ctx* c) {
+    BlockGeom G;
+    G.nx = c->nx;
+    G.ny = c->ny;
+    G.bx = c->bx;
+    G.by = c->by;
+    G.Nx = c->Nx;
+    G.Ny = c->Ny;
+    G.jmax = c->jmax;
+    G.nfk = c->nfk;
+    G.ncol = c->ncol;
+    G.hx = c->hx;
+    G.hy = c->hy;
+    G.sx = c->sx;
+    G.sy = c->sy;
+    return G;
+}
+
+}  // namespace
+
+namespace tgms {
+
+void snapshots(tgms_ctx* c) {
+    BlockGeom G = geom(c);
+    const int nfx = c->by * (c->bx + 1), nfy = (c->by + 1) * c->bx, nloc = (c->bx - 1) * (c->by - 1);
+    size_t lds = sizeof(double) * (2 * c->by + 2 * c->bx + c->bx * c->by + 2 * (nfx + nfy) + nloc + c->by + 2);
+    if (lds > 65536) throw TgmsError{TGMS_E_UNSUPPORTED, "coarse block too large for the snapshot kernel"};
+    hipLaunchKernelGGL(k_snapshots, dim3(c->nblk), dim3(64), lds, c->stream, G, c->a, c->blkL, c->blkS, c->Psi);
+    LAUNCH_OK();
+}
+
+void gram(tgms_ctx* c) {
+    BlockGeom G = geom(c);
+    hipLaunchKernelGGL(k_apply_AK_cols, dim3(c->nblk, c->ncol), dim3(256), 0, c->stream, G, c->a, c->Psi, c->APsi);
+    LAUNCH_OK();
+    const int q4 = c->ncol / 4;
+    size_t lds = sizeof(double) * 2 * c->ncol * 32;
+    hipLaunchKernelGGL(k_gram, dim3(c->nblk), dim3(q4 * q4), lds, c->stream, G, c->Psi, c->APsi, c->G);
+    LAUNCH_OK();
+}
+
+}  // namespace tgms
+
+// Entry points used by the host orchestrator (api.hip) that need the kernels above.
+namespace tgms {
+
+void pencil_eig_q(tgms_ctx* c, double* Q) {
+    BlockGeom G = geom(c);
+    hipLaunchKernelGGL(k_pencil_eig, dim3(c->ne), dim3(64), 0, c->stream, G, c->kinv, c->G, c->tol, 1.0 / c->H,
+                       c->eigs, c->counts, c->Y, Q);
+    LAUNCH_OK();
+}
+
+void coarse_local_run(tgms_ctx* c, const double* Tm, const int* zc) {
+    BlockGeom G = geom(c);
+    size_t lds = sizeof(double) * c->ncol * c->mu;
+    hipLaunchKernelGGL(k_coarse_local, dim3(c->nblk), dim3(256), lds, c->stream, G, c->G, Tm, c->mu, c->blk_unk,
+                       c->blk_nu, c->Ac, c->ncs, c->Psi, c->APsi);
+    LAUNCH_OK();
+    hipLaunchKernelGGL(k_coarse_W, dim3(c->nblk), dim3(256), 0, c->stream, G, c->APsi, Tm, c->mu, c->blk_nu, zc, c->W,
+                       c->precision ? c->W32 : nullptr);
+    LAUNCH_OK();
+}
+
+void coarse_rt0_blocks(tgms_ctx* c) {
+    BlockGeom G = geom(c);
+    hipLaunchKernelGGL(k_rt0_blocks, dim3(c->nblk), dim3(64), 0, c->stream, G, c->a, c->AH0);
+    LAUNCH_OK();
+}
+
+template <typename T>
+void coarse_apply(tgms_ctx* c, const T* g, T* z, bool accumulate) {
+    const T* W;
+    const T* Ainv;
+    T* cy;
+    T* c1;
+    T* c2;
+    if constexpr (sizeof(T) == 8) {
+        W = (const T*)c->W;
+        Ainv = (const T*)c->Ac;
+        cy = (T*)c->cy;
+        c1 = (T*)c->cvec;
+        c2 = (T*)c->cvec;
+    } else {
+        W = (const T*)c->W32;
+        Ainv = (const T*)c->Ac32;
+        cy = (T*)c->cy32;
+        c1 = (T*)c->cvec32;
+        c2 = (T*)c->cvec32;
+    }
+    hipLaunchKernelGGL((k_coarse_restrict<T>), dim3(c->nblk), dim3(256), 0, c->stream, W, c->mu, c->blk_nu, g, c->nx,
+                       c->bx, c->by, c->Nx, cy);
+    LAUNCH_OK();
+    hipLaunchKernelGGL((k_coarse_accum<T>), dim3((c->ncs + 255) / 256), dim3(256), 0, c->stream, c->unk_ptr,
+                       c->unk_ent, (const T*)cy, c->ncs, c1);
+    LAUNCH_OK();
+    // c2 = A^{-1} c1 : symv uses cvec2 as its temporary, result written back into c1's storage
+    T* res;
+    if constexpr (sizeof(T) == 8)
+        res = (T*)c->cvec + c->ncs;
+    else
+        res = (T*)c->cvec32 + c->ncs;
+    symv<T>(c, Ainv, c->ncs, c1, res);
+    (void)c2;
+    hipLaunchKernelGGL((k_coarse_prolong<T>), dim3(c->nblk), dim3(256), 0, c->stream, W, c->mu, c->blk_unk,
+                       c->blk_nu, (const T*)res, c->nx, c->bx, c->by, c->Nx, z, accumulate ? 1 : 0);
+    LAUNCH_OK();
+}
+template void coarse_apply<double>(tgms_ctx*, const double*, double*, bool);
+template void coarse_apply<float>(tgms_ctx*, const float*, float*, bool);
+
+}  // namespace tgms

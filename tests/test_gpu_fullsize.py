@@ -1,0 +1,87 @@
+"""Full-size (1024 x 1024) checks in the configuration the benchmark times (needs an MI355X).
+
+The oracle cannot solve this size in test time, so it checks sampled
+outputs one by one (the local spectral problems of sampled coarse faces)
+and properties that hold at any size (B u = F, preconditioner symmetry,
+convergence)."""
+import numpy as np
+import pytest
+
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from gpu_util import dev, host  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def big():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1807_07220_amd as tg
+    w = configs.get("darcy2d_1024_b16")
+    kappa, F = w.make_inputs()
+    return w, kappa, F, tg.Solver(dev(kappa), w.bx, w.by, 3.0)
+
+
+def _oracle_face(w, kappa, face, tol):
+    import scipy.sparse  # noqa: F401
+    from oracle.discretization import Grid2D, div_matrix, mass_matrix
+    from oracle.local import BorderedSaddle
+    from oracle.spectral import block_rect, pencil, select, snapshots
+    g = Grid2D(w.nx, w.ny, w.bx, w.by)
+    kinv = (1.0 / kappa).ravel()
+    A, B = mass_matrix(g, kinv).tocsr(), div_matrix(g).tocsr()
+
+    def block(I, J):
+        r = block_rect(g, I, J)
+        return BorderedSaddle(A, B, g.faces_in(*r), g.cells_in(*r))
+    fa, Psi = snapshots(g, A, B, block, face)
+    Dg, S = pencil(g, A, B, kinv, face, fa, Psi)
+    return select(Dg, S, tol)
+
+
+def test_sampled_spectral_problems(big):
+    w, kappa, F, s = big
+    from oracle.discretization import Grid2D
+    faces = Grid2D(w.nx, w.ny, w.bx, w.by).coarse_faces()
+    counts, eigs = s.counts(), s.eigs()
+    rng = np.random.default_rng(0)
+    for k in rng.choice(len(faces), size=12, replace=False):
+        lam, _, cnt = _oracle_face(w, kappa, faces[k], 3.0)
+        if not np.any(np.abs(lam - 3.0) <= 1e-8 * 3.0):
+            assert counts[k] == cnt
+        sel = lam < 3.0
+        assert np.all(np.abs(eigs[k][sel] - lam[sel]) <= 1e-9 * lam[sel])
+
+
+def test_solution_properties(big):
+    w, kappa, F, s = big
+    res = s.solve(dev(F), rtol=1e-8)
+    assert res["converged"] and res["iters"] < 60
+    u = host(res["u"])
+    nx, ny = w.nx, w.ny
+    ux = u[: (nx + 1) * ny].reshape(ny, nx + 1)
+    uy = u[(nx + 1) * ny:].reshape(ny + 1, nx)
+    div = (ux[:, 1:] - ux[:, :-1]) / ny + (uy[1:, :] - uy[:-1, :]) / nx
+    assert np.abs(div - F).max() <= 1e-12 * np.abs(F).max()
+    assert np.all(ux[:, 0] == 0) and np.all(ux[:, -1] == 0) and np.all(uy[0] == 0) and np.all(uy[-1] == 0)
+    p = host(res["p"])
+    assert abs(p.mean()) < 1e-12 * np.abs(p).max()
+
+
+def test_preconditioner_symmetric(big):
+    w, kappa, F, s = big
+    nf = (w.nx + 1) * w.ny + w.nx * (w.ny + 1)
+    rng = np.random.default_rng(5)
+    x, y = rng.standard_normal(nf), rng.standard_normal(nf)
+    from paper_1807_07220_amd import nfaces
+    assert nfaces(w.nx, w.ny) == nf
+    zx = host(s.apply_precond("twogrid", dev(x)))
+    zy = host(s.apply_precond("twogrid", dev(y)))
+    # interior faces only: the probe ignores boundary entries
+    from oracle.discretization import Grid2D
+    m = Grid2D(w.nx, w.ny).interior
+    a, b = x[m] @ zy[m], y[m] @ zx[m]
+    assert abs(a - b) <= 1e-10 * abs(a)

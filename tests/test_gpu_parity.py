@@ -1,0 +1,174 @@
+"""Parity of the HIP path with the FP64 oracle (needs an MI355X).
+
+Every test compares the library's result with the oracle's on the same
+seeded inputs.  Sizes span several coarse blocks and patches, square and
+non-square blocks, boundary-clipped patches and nonzero boundary data.
+"""
+import numpy as np
+import pytest
+
+from workloads import configs, fields
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+from gpu_util import dev, host, oracle_for, register, rel  # noqa: E402
+
+# Probe tolerances follow the conditioning of the local and coarse problems:
+# two backward-stable solvers of the same system agree to about eps * cond.
+# At contrast <= 1e3 that is below 1e-11; at contrast 1e6 the coarse and
+# block problems reach cond ~ 1e6 after equilibration, hence 1e-8 there.
+# The final velocity and pressure are held to 1e-10 in every case.
+PROBE_TOL = {"cfg32": 1e-11, "rect36x24": 1e-11, "chan64": 1e-8}
+
+CASES = {
+    # name: (nx, ny, bx, by, kappa generator, tol)
+    "cfg32": (32, 32, 8, 8, lambda: configs.get("darcy2d_32_b8").make_inputs()[0], 0.5),
+    "rect36x24": (36, 24, 6, 4, lambda: np.exp(2.0 * np.random.default_rng(7).standard_normal((24, 36))), 0.5),
+    "chan64": (64, 64, 8, 8, lambda: fields.field_channelized(64, 64, 11, contrast=1e6), 2.0),
+}
+
+
+def case(name, precision="fp64"):
+    import paper_1807_07220_amd as tg
+    nx, ny, bx, by, gen, tol = CASES[name]
+    kappa = gen()
+    register(name, kappa)
+    s = tg.Solver(dev(kappa), bx, by, tol, precision=precision)
+    o = oracle_for(nx, ny, bx, by, name, tol)
+    return s, o, kappa
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_apply_A(name):
+    s, o, _ = case(name)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(o.g.nf) * o.mask
+    y = host(s.apply_A(dev(x)))
+    assert rel(y, o.apply_A(x)) < 1e-14
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_counts_and_eigenvalues(name):
+    s, o, _ = case(name)
+    counts = s.counts()
+    eigs = s.eigs()
+    tol = CASES[name][5]
+    near = np.array([np.any(np.abs(e - tol) <= 1e-8 * tol) for e in o.eigs])
+    assert np.array_equal(counts[~near], o.counts[~near])
+    for k, e in enumerate(o.eigs):
+        J = e.size
+        # T = D^{-1/2} S D^{-1/2} has eigenvalues mu = 1/lambda; both solvers resolve mu to
+        # about eps * mu_max, i.e. lambda_k to a relative eps * lambda_k / lambda_min.
+        bound = 1e-12 + 1e-13 * e / e.min()
+        assert np.all(np.abs(eigs[k, :J] - e) <= bound * e), (k, eigs[k, :J], e)
+        sel = e < tol
+        assert np.all(np.abs(eigs[k, :J][sel] - e[sel]) <= 1e-9 * e[sel])
+    info = s.info()
+    assert info["dim"] == o.dim
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_preprocessing(name):
+    s, o, _ = case(name)
+    F = fields.random_source(o.g.nx, o.g.ny, 5).ravel()
+    vb = host(s.preprocess(dev(F)))
+    vo, _, _ = o.preprocess(F)
+    assert rel(vb, vo) < PROBE_TOL[name]
+    assert np.abs(o.B @ vb - F).max() < 1e-12 * np.abs(F).max()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("which", ["smoother", "coarse", "twogrid"])
+def test_preconditioner(name, which):
+    s, o, _ = case(name)
+    rng = np.random.default_rng(2)
+    r = rng.standard_normal(o.g.nf) * o.mask
+    z = host(s.apply_precond(which, dev(r)))
+    ref = {"smoother": o.smooth, "coarse": o.coarse, "twogrid": o.twogrid}[which](r)
+    assert rel(z, ref) < PROBE_TOL[name]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_solve(name):
+    s, o, _ = case(name)
+    F = fields.corner_source(o.g.nx, o.g.ny).ravel()
+    res = s.solve(dev(F), rtol=1e-8)
+    ro = o.solve(F, rtol=1e-8)
+    assert res["converged"]
+    assert abs(res["iters"] - ro["iters"]) <= 1
+    assert rel(host(res["u"]), ro["u"]) < 1e-10 or np.linalg.norm(host(res["u"]) - ro["u"]) <= 1e-10 * np.linalg.norm(ro["u"])
+    assert np.linalg.norm(host(res["p"]) - ro["p"]) <= 1e-10 * np.linalg.norm(ro["p"])
+
+
+def test_solve_with_boundary_data():
+    s, o, _ = case("rect36x24")
+    g = o.g
+    rng = np.random.default_rng(3)
+    gf = np.zeros(g.nf)
+    gf[g.boundary_idx] = rng.standard_normal(g.boundary_idx.size)
+    F = fields.random_source(g.nx, g.ny, 4).ravel() + (o.B @ gf).sum() / g.nc
+    res = s.solve(dev(F), dev(gf), rtol=1e-10)
+    ro = o.solve(F, gf, rtol=1e-10)
+    assert abs(res["iters"] - ro["iters"]) <= 1
+    assert np.linalg.norm(host(res["u"]) - ro["u"]) <= 1e-10 * np.linalg.norm(ro["u"])
+    assert np.linalg.norm(host(res["p"]) - ro["p"]) <= 1e-10 * np.linalg.norm(ro["p"])
+
+
+@pytest.mark.parametrize("name", ["cfg32", "chan64"])
+def test_mixed_precision_error(name):
+    s, o, _ = case(name, precision="mixed")
+    F = fields.corner_source(o.g.nx, o.g.ny).ravel()
+    res = s.solve(dev(F), rtol=1e-10)
+    ro = o.solve(F, rtol=1e-10)
+    assert res["converged"]
+    assert np.linalg.norm(host(res["u"]) - ro["u"]) <= 1e-8 * np.linalg.norm(ro["u"])
+    assert np.linalg.norm(host(res["p"]) - ro["p"]) <= 1e-8 * np.linalg.norm(ro["p"])
+
+
+def test_error_paths():
+    import paper_1807_07220_amd as tg
+    kappa = np.ones((32, 32))
+    kappa[3, 4] = 0.0
+    with pytest.raises(tg.TgmsError) as e:
+        tg.Solver(dev(kappa), 8, 8, 0.5)
+    assert e.value.status == "INVAL"
+    with pytest.raises(tg.TgmsError) as e:
+        tg.Solver(dev(np.ones((30, 32))), 8, 8, 0.5)
+    assert e.value.status == "INVAL"
+    s = tg.Solver(dev(np.ones((32, 32))), 8, 8, 0.5)
+    F = np.zeros((32, 32))
+    F[0, 0] = 1.0
+    with pytest.raises(tg.TgmsError) as e:
+        s.solve(dev(F))
+    assert e.value.status == "INCOMPAT"
+    F[5, 7] = -1.0
+    res = s.solve(dev(F), maxit=1, rtol=1e-14)
+    assert not res["converged"] and res["iters"] == 1
+    res = s.solve(dev(np.zeros((32, 32))))
+    assert res["converged"] and res["iters"] == 0
+    assert float(res["u"].abs().max()) == 0.0
+
+
+def test_solve_256_full_oracle():
+    """The 256x256 / 16x16-block workload (tolerance 0.2, contrast 1e6): full solve vs oracle."""
+    import paper_1807_07220_amd as tg
+    from oracle import Grid2D, OracleSolver
+    w = configs.get("darcy2d_256_b16")
+    kappa, F = w.make_inputs()
+    s = tg.Solver(dev(kappa), w.bx, w.by, w.eig_tol)
+    res = s.solve(dev(F), rtol=w.rtol)
+    o = OracleSolver(Grid2D(w.nx, w.ny, w.bx, w.by), kappa, w.eig_tol)
+    assert np.array_equal(s.counts(), o.counts)
+    ro = o.solve(F.ravel(), rtol=w.rtol, maxit=1000)
+    assert res["converged"] and abs(res["iters"] - ro["iters"]) <= 1
+    assert np.linalg.norm(host(res["u"]) - ro["u"]) <= 1e-10 * np.linalg.norm(ro["u"])
+    assert np.linalg.norm(host(res["p"]) - ro["p"]) <= 1e-10 * np.linalg.norm(ro["p"])
