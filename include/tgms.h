@@ -76,6 +76,7 @@ typedef struct {
     int n_coarse_spd;     /* unknowns of the SPD coarse system actually factorised */
     double t_setup_ms;    /* device time of tgms_setup (all phases) */
     double t_snap_ms, t_eig_ms, t_coarse_ms, t_smoother_ms;  /* setup phases */
+    int lds_max;          /* LDS bytes per workgroup the device allows (picks the smoother kernel) */
 } tgms_info_t;
 
 /* Paper defaults: eta 0.2, overlap 2, FP64, s_scale = |K|^(1/2), default stream. */
@@ -125,6 +126,15 @@ tgms_status tgms_get_eigs(const tgms_ctx* ctx, double* eigs);
 /* Condition-number estimate of the preconditioned operator from the last
  * solve's PCG scalars (Lanczos tridiagonal), as the paper reports "Cond". */
 tgms_status tgms_last_cond(const tgms_ctx* ctx, double* cond);
+
+/* Per-kernel timing with HIP events on the context's stream (for roofline
+ * measurements).  tgms_profile(ctx, 1) starts recording every launch of the
+ * instrumented kernels (and clears earlier records); tgms_profile_get
+ * returns the number of launches and their summed duration in ms.
+ * kernel: 0 = smoother patch solve, 1 = stream-function operator apply
+ * (K psi = C^T A C psi), 2 = coarse restriction, 3 = coarse prolongation. */
+tgms_status tgms_profile(tgms_ctx* ctx, int enable);
+tgms_status tgms_profile_get(tgms_ctx* ctx, int kernel, int* launches, double* total_ms);
 
 void tgms_destroy(tgms_ctx* ctx);
 const char* tgms_last_error(void);

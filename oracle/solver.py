@@ -69,6 +69,23 @@ def block_aggregation(g: Grid2D) -> sp.csr_matrix:
     return sp.csr_matrix((np.ones(g.nc), (blk, np.arange(g.nc))), shape=(g.Nx * g.Ny, g.nc))
 
 
+def pinned_cell_laplacian(BI):
+    """Solver of the singular, consistent system (B_I B_I^T) q = b.
+
+    The null space is the constants; the last cell's value is pinned to zero
+    (its equation is implied by the others for a consistent right-hand side),
+    which keeps the factorisation sparse.
+    """
+    L = (BI @ BI.T).tocsc()
+    lu = spla.splu(L[:-1, :-1].tocsc())
+
+    def solve(b):
+        q = np.zeros(L.shape[0])
+        q[:-1] = lu.solve(np.asarray(b, dtype=np.float64)[:-1])
+        return q
+    return solve
+
+
 def bordered_dense_or_sparse(Ah, Bh):
     """Factorise [[Ah, Bh^T, 0], [Bh, 0, 1], [0, 1^T, 0]] (one mean-zero multiplier)."""
     n, m = Ah.shape[0], Bh.shape[0]
@@ -94,8 +111,7 @@ class OracleSolver:
         self.mask = g.interior.astype(np.float64)
         self._blocks = {}
         BI = self.B[:, g.interior_idx]
-        one = sp.csr_matrix(np.ones((g.nc, 1)))
-        self._cell_lap = spla.splu(sp.bmat([[(BI @ BI.T).tocsc(), one], [one.T, None]], format="csc"))
+        self._cell_lap = pinned_cell_laplacian(BI)
         self.faces = g.coarse_faces()
         # Step 2: adaptive coarse space (section 4)
         self.omega_faces, self.Psi, self.eigs, self.counts, self.Phi_local = [], [], [], [], []
@@ -147,7 +163,7 @@ class OracleSolver:
 
     def project(self, r):
         """Euclidean projection of a face vector onto ker B (interior faces)."""
-        q = self._cell_lap.solve(np.concatenate([self.B @ (self.mask * r), [0.0]]))[: self.g.nc]
+        q = self._cell_lap(self.B @ (self.mask * r))
         return self.mask * (r - self.B.T @ q)
 
     def smooth(self, r):
@@ -251,11 +267,8 @@ class OracleSolver:
         g = self.g
         BI = self.B[:, g.interior_idx]
         a = (self.A @ u_full)[g.interior_idx]
-        L = (BI @ BI.T).tocsc()
-        one = sp.csr_matrix(np.ones((g.nc, 1)))
-        K = sp.bmat([[L, one], [one.T, None]], format="csc")
-        sol = spla.spsolve(K, np.concatenate([BI @ a, [0.0]]))
-        return sol[: g.nc]
+        p = self._cell_lap(BI @ a)
+        return p - p.mean()
 
     # ---- Steps 1-4 --------------------------------------------------------
     def solve(self, F, g_full=None, rtol=1e-8, maxit=500, flexible=False):
@@ -279,10 +292,17 @@ def exact_solve(g: Grid2D, kappa, F, g_full=None):
     I = g.interior_idx
     gb = np.zeros(g.nf) if g_full is None else np.asarray(g_full, dtype=np.float64).copy()
     gb[I] = 0.0
-    bs = BorderedSaddle(A, B, I, np.arange(g.nc))
+    # The pressure is determined up to a constant: the last cell's pressure is pinned
+    # to zero and its (redundant, by compatibility) divergence equation dropped; the
+    # pressure is then shifted to zero mean.  Same solution as the mean-zero multiplier.
+    AII = A[I][:, I]
+    BI = B[:, I]
+    K = sp.bmat([[AII, BI[:-1].T], [BI[:-1], None]], format="csc")
     rhs_f = -(A @ gb)[I]
-    rhs_c = np.asarray(F, dtype=np.float64).ravel() - B @ gb
-    v, pprime = bs.solve(rhs_f, rhs_c)
+    rhs_c = (np.asarray(F, dtype=np.float64).ravel() - B @ gb)[:-1]
+    sol = spla.splu(K).solve(np.concatenate([rhs_f, rhs_c]))
     u = gb.copy()
-    u[I] = v
+    u[I] = sol[: I.size]
+    pprime = np.concatenate([sol[I.size:], [0.0]])
+    pprime -= pprime.mean()
     return u, -pprime

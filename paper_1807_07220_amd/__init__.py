@@ -94,6 +94,17 @@ class Solver:
         check(load().tgms_last_cond(self._h, ctypes.byref(c)))
         return c.value
 
+    # ---- per-kernel event timing ------------------------------------------
+    KERNELS = {"smoother": 0, "apply_K": 1, "coarse_restrict": 2, "coarse_prolong": 3}
+
+    def profile(self, enable: bool = True):
+        check(load().tgms_profile(self._h, 1 if enable else 0))
+
+    def profile_get(self, kernel: str):
+        n, t = ctypes.c_int(0), ctypes.c_double(0.0)
+        check(load().tgms_profile_get(self._h, self.KERNELS[kernel], ctypes.byref(n), ctypes.byref(t)))
+        return n.value, t.value
+
     # ---- probes -----------------------------------------------------------
     def apply_A(self, x: torch.Tensor) -> torch.Tensor:
         y = torch.empty_like(x)

@@ -37,7 +37,7 @@ class Options(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("n_coarse_faces", c_int), ("n_blocks", c_int), ("dim", c_int), ("n_coarse_spd", c_int),
                 ("t_setup_ms", c_double), ("t_snap_ms", c_double), ("t_eig_ms", c_double),
-                ("t_coarse_ms", c_double), ("t_smoother_ms", c_double)]
+                ("t_coarse_ms", c_double), ("t_smoother_ms", c_double), ("lds_max", c_int)]
 
 
 _lib = None
@@ -52,6 +52,8 @@ SIGNATURES = {
     "tgms_get_counts": (c_int, [c_void_p, c_void_p]),
     "tgms_get_eigs": (c_int, [c_void_p, c_void_p]),
     "tgms_last_cond": (c_int, [c_void_p, ctypes.POINTER(c_double)]),
+    "tgms_profile": (c_int, [c_void_p, c_int]),
+    "tgms_profile_get": (c_int, [c_void_p, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_double)]),
     "tgms_destroy": (None, [c_void_p]),
     "tgms_last_error": (c_char_p, []),
     "tgms_apply_A": (c_int, [c_void_p, c_void_p, c_void_p]),

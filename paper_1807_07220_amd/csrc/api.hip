@@ -13,10 +13,33 @@
 #include <map>
 
 #include "common.h"
+#include "band.h"
 
 namespace tgms {
 void bnd_faces(tgms_ctx* c, const double* g, double* gb);
+
+static hipEvent_t take_event(tgms_ctx* c) {
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e;
+        HIP_OK(hipEventCreate(&e));
+        c->ev_pool.push_back(e);
+    }
+    return c->ev_pool[c->ev_used++];
 }
+
+ProfScope::ProfScope(tgms_ctx* ctx, int kid) : c(ctx), id(kid) {
+    if (!c->prof) return;
+    e1 = take_event(c);
+    HIP_OK(hipEventRecord(e1, c->stream));
+}
+
+ProfScope::~ProfScope() {
+    if (!c->prof || !e1) return;
+    hipEvent_t e2 = take_event(c);
+    (void)hipEventRecord(e2, c->stream);
+    c->prof_rec.push_back({id, {e1, e2}});
+}
+}  // namespace tgms
 
 namespace {
 thread_local std::string g_last_error;
@@ -302,6 +325,12 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         c->nfk = by * (bx + 1) + (by + 1) * bx;
         c->ncol = 4 * c->jmax;
         const long long ncell = (long long)nx * ny;
+        {
+            int dev = 0, v = 0;
+            HIP_OK(hipGetDevice(&dev));
+            if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+                c->lds_max = v;
+        }
         Timer total(c->stream);
         c->kinv = c->alloc<double>(ncell);
         c->a = c->alloc<double>(ncell);
@@ -316,7 +345,7 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         c->blk_m = bx - 1;
         c->blk_n = (bx - 1) * (by - 1);
         c->blk_b = bx;
-        c->blkL = c->alloc<double>((size_t)c->nblk * c->blk_n * (c->blk_b + 1));
+        c->blkL = c->alloc<double>((size_t)c->nblk * btri_size(bx - 1, by - 1));
         c->blkS = c->alloc<double>((size_t)c->nblk * c->blk_n);
         {
             Timer t(c->stream);
@@ -393,7 +422,8 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                     const int m = r.i1 - r.i0 - 1, n = m * (r.j1 - r.j0 - 1);
                     r.off = off;
                     r.voff = voff;
-                    off += (long long)n * (m + 2);
+                    off += (btri_size(m, r.j1 - r.j0 - 1) + 3) & ~3LL;  // 16-byte aligned factors
+                    c->pat_fmax = std::max(c->pat_fmax, btri_size(m, r.j1 - r.j0 - 1));
                     voff += n;
                     c->pat_nmax = std::max(c->pat_nmax, n);
                     c->pat_bmax = std::max(c->pat_bmax, m + 1);
@@ -407,7 +437,6 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
             c->patW = c->alloc<double>(voff);
             if (c->precision) {
                 c->patL32 = c->alloc<float>(off);
-                c->patS32 = c->alloc<float>(voff);
                 c->patW32 = c->alloc<float>(voff);
             }
             tgms::factor_patches(c);
@@ -450,6 +479,7 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         c->cellw = c->alloc<double>(ncell); c->cellw2 = c->alloc<double>(std::max<long long>(ncell, 2 * c->nblk));
         c->red = c->alloc<double>(4 * 512 + 16);
         c->blkbuf = c->alloc<double>(2 * (size_t)c->nblk);
+        c->sc = c->alloc<double>(16);
         HIP_OK(hipHostMalloc((void**)&c->red_h, 16 * sizeof(double), hipHostMallocDefault));
         HIP_OK(hipStreamSynchronize(c->stream));
         c->t_setup_ms = total.ms();
@@ -471,47 +501,87 @@ void solve_impl(tgms_ctx* c, const double* F, const double* g_bnd, double rtol, 
     tgms::bnd_faces(c, g_bnd, c->fF);
     tgms::axpy(c, c->nf, 1.0, c->fbar, c->fF);
     tgms::curlT_A_faces(c, c->fF, c->vg, -1.0);
-    // Step 3: PCG in stream-function coordinates
+    // Step 3: PCG in stream-function coordinates, scalars kept on the device; one
+    // iteration is captured once as a HIP graph and replayed (launched directly when
+    // capture is unavailable).  The host reads only |z_k|/|z_0| and the breakdown flag.
+    const bool flexible = c->precision != 0;
+    if (c->hist_cap < maxit + 2) {
+        c->hist = c->alloc<double>(2 * (size_t)(maxit + 2));
+        c->hist_cap = maxit + 2;
+        if (c->iter_graph) {
+            (void)hipGraphExecDestroy(c->iter_graph);
+            c->iter_graph = nullptr;
+        }
+    }
     tgms::zero(c, c->vx, sizeof(double) * nv);
     precond(c, 2, c->vg, c->vz);
-    double d[3];
-    tgms::dot3(c, c->vg, c->vz, nullptr, d);
-    double rho = d[0];
-    const double z0 = std::sqrt(d[2]);
-    const bool flexible = c->precision != 0;
+    tgms::pcg_beta(c, c->vg, c->vz, nullptr, c->sc, c->hist, flexible, true);
+    tgms::copy(c, nv, c->vz, c->vp);
+    HIP_OK(hipMemcpyAsync(c->red_h, c->sc, 9 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    const double z0 = std::sqrt(c->red_h[6]);
+    auto iteration = [&]() {
+        tgms::apply_K<double>(c, c->vp, c->vq, c->a);
+        tgms::pcg_alpha(c, c->vp, c->vq, c->sc, c->hist);
+        tgms::pcg_update(c, c->sc, c->vp, c->vq, c->vx, c->vg, flexible ? c->vgold : nullptr);
+        precond(c, 2, c->vg, c->vz);
+        tgms::pcg_beta(c, c->vg, c->vz, flexible ? c->vgold : nullptr, c->sc, c->hist, flexible, false);
+        tgms::pcg_dir(c, c->sc, c->vz, c->vp);
+    };
+    if (!c->iter_graph && !c->graph_failed && !c->prof && z0 > 0) {
+        hipGraph_t graph = nullptr;
+        bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            try {
+                iteration();
+            } catch (...) {
+                ok = false;
+            }
+            ok = (hipStreamEndCapture(c->stream, &graph) == hipSuccess) && ok;
+        }
+        if (ok && graph && hipGraphInstantiate(&c->iter_graph, graph, nullptr, nullptr, 0) != hipSuccess) {
+            c->iter_graph = nullptr;
+            ok = false;
+        }
+        if (graph) (void)hipGraphDestroy(graph);
+        if (!ok) {
+            c->graph_failed = true;
+            (void)hipGetLastError();
+        }
+    }
     c->alphas.clear();
     c->betas.clear();
     int it = 0;
     double rel = 1.0;
     *st = TGMS_OK;
     if (z0 > 0) {
-        HIP_OK(hipMemcpyAsync(c->vp, c->vz, sizeof(double) * nv, hipMemcpyDeviceToDevice, c->stream));
         while (true) {
             if (it >= maxit) {
                 *st = TGMS_E_NOTCONV;
                 break;
             }
-            tgms::apply_K<double>(c, c->vp, c->vq, c->a);
-            const double pq = tgms::dot(c, c->vp, c->vq, nv);
-            if (!(pq > 0) || !std::isfinite(pq)) {
+            if (c->iter_graph && !c->prof)
+                HIP_OK(hipGraphLaunch(c->iter_graph, c->stream));
+            else
+                iteration();
+            HIP_OK(hipMemcpyAsync(c->red_h, c->sc, 9 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HIP_OK(hipStreamSynchronize(c->stream));
+            ++it;
+            if (c->red_h[7] != 0.0) {
                 *st = TGMS_E_BREAKDOWN;
                 break;
             }
-            const double alpha = rho / pq;
-            tgms::axpy(c, nv, alpha, c->vp, c->vx);
-            if (flexible)
-                HIP_OK(hipMemcpyAsync(c->vgold, c->vg, sizeof(double) * nv, hipMemcpyDeviceToDevice, c->stream));
-            tgms::axpy(c, nv, -alpha, c->vq, c->vg);
-            precond(c, 2, c->vg, c->vz);
-            tgms::dot3(c, c->vg, c->vz, flexible ? c->vgold : nullptr, d);
-            ++it;
-            c->alphas.push_back(alpha);
-            rel = std::sqrt(d[2]) / z0;
+            rel = std::sqrt(c->red_h[5]);
             if (rel <= rtol) break;
-            const double beta = flexible ? (d[0] - d[1]) / rho : d[0] / rho;
-            c->betas.push_back(beta);
-            tgms::xpay(c, nv, c->vz, beta, c->vp);
-            rho = d[0];
+        }
+        std::vector<double> h(2 * (size_t)it);
+        if (it > 0) {
+            HIP_OK(hipMemcpyAsync(h.data(), c->hist, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));
+            HIP_OK(hipStreamSynchronize(c->stream));
+        }
+        for (int k = 0; k < it; ++k) {
+            c->alphas.push_back(h[2 * k]);
+            if (k + 1 < it) c->betas.push_back(h[2 * k + 1]);
         }
     }
     // Step 4: v = vbar + g + C psi
@@ -568,6 +638,7 @@ tgms_status tgms_info(const tgms_ctx* c, tgms_info_t* info) {
     info->t_eig_ms = c->t_eig_ms;
     info->t_coarse_ms = c->t_coarse_ms;
     info->t_smoother_ms = c->t_smoother_ms;
+    info->lds_max = c->lds_max;
     return TGMS_OK;
 }
 
@@ -600,10 +671,46 @@ tgms_status tgms_last_cond(const tgms_ctx* c, double* cond) {
     return TGMS_OK;
 }
 
+tgms_status tgms_profile(tgms_ctx* c, int enable) {
+    if (!c) {
+        g_last_error = "null argument";
+        return TGMS_E_INVAL;
+    }
+    return guarded([&] {
+        HIP_OK(hipStreamSynchronize(c->stream));
+        c->prof = enable != 0;
+        c->prof_rec.clear();
+        c->ev_used = 0;
+    });
+}
+
+tgms_status tgms_profile_get(tgms_ctx* c, int kernel, int* launches, double* total_ms) {
+    if (!c || !launches || !total_ms || kernel < 0 || kernel >= tgms::PK_COUNT) {
+        g_last_error = "bad argument";
+        return TGMS_E_INVAL;
+    }
+    return guarded([&] {
+        HIP_OK(hipStreamSynchronize(c->stream));
+        int n = 0;
+        double t = 0.0;
+        for (auto& r : c->prof_rec) {
+            if (r.first != kernel) continue;
+            float ms = 0.f;
+            HIP_OK(hipEventElapsedTime(&ms, r.second.first, r.second.second));
+            t += ms;
+            ++n;
+        }
+        *launches = n;
+        *total_ms = t;
+    });
+}
+
 void tgms_destroy(tgms_ctx* c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->iter_graph) (void)hipGraphExecDestroy(c->iter_graph);
     for (auto& b : c->owned) (void)hipFree(b.p);
     if (c->red_h) (void)hipHostFree(c->red_h);
     delete c;

@@ -1,45 +1,185 @@
-// Wavefront band solver for an equilibrated band Cholesky factor.
+// Wavefront solver for the local stream-function systems (block-row form).
 //
-// Solves M w = g where S M S = L L^T, L lower triangular with bandwidth b < 64,
-// stored column band: L[c*(b+1) + t] = L(c+t, c) for t = 1..b and
-// L[c*(b+1)] = 1 / L(c, c).  vec (LDS, n entries) holds g on entry and w on
-// exit.  One wavefront executes the call; every lane must enter it.
+// A rectangle's interior vertices form mh rows of m vertices; in row-major
+// order the equilibrated matrix S M S is block tridiagonal with m x m blocks,
+// and its Cholesky factor L is block bidiagonal:
+//   L_jj     lower triangular (dense inside the band),
+//   L_{j+1,j} upper Hessenberg (row a is nonzero for columns >= a-1).
+// The factor is stored per block row j as
+//   [ D_j = L_jj^{-1}, lower triangular, packed by columns (column c holds rows c..m-1) ]
+//   [ E_j = L_{j+1,j}, packed by columns (column c holds rows 0..min(c+1, m-1)) ]
+// followed by the n = m*mh entries of the equilibration scale S.
+// Both pieces together hold the same number of words as the band factor.
 //
-// Forward sweep (L y = S g): lane p keeps the running value of the row r with
-// r = p (mod 64); after row r is final its value is broadcast and the b rows
-// below it are updated (column-oriented, no reduction); lane r%64 then loads
-// row r+64.  Backward sweep (L^T w = y): each row is a dot product of column
-// r of L with w_{r+1..r+b}, which the lanes hold in the same rotating layout.
+// Forward  L y = S g :  y_j = D_j (S g_j - E_{j-1} y_{j-1})
+// Backward L^T w = y :  w_j = D_j^T (y_j - E_j^T w_{j+1}),  result S w.
+// Lane a owns entry a of every block vector; the 2*mh block steps are the
+// only sequential chain, and every load of a step is issued together.
 #pragma once
 #include "common.h"
 
-template <typename T>
-__device__ inline void band_solve_wave(const T* __restrict__ L, const T* __restrict__ S, int n, int b, T* vec) {
+#define TGMS_MMAX 32  // largest supported m (vertices per row of a rectangle)
+
+// smallest register-array width (16, 24 or 32) that holds m
+inline int btri_width(int m) { return m <= 16 ? 16 : (m <= 24 ? 24 : 32); }
+
+__host__ __device__ inline int btri_tri(int m) { return m * (m + 1) / 2; }
+__host__ __device__ inline int btri_hes(int m) { return (m - 1) * (m + 2) / 2 + m; }
+__host__ __device__ inline long long btri_size(int m, int mh) {
+    return (long long)mh * (btri_tri(m) + btri_hes(m)) + (long long)m * mh;
+}
+__host__ __device__ inline int btri_offD(int c, int m) { return c * m - c * (c - 1) / 2; }
+__host__ __device__ inline int btri_offE(int c) { return c * (c + 3) / 2; }
+
+// vec (LDS, n = m*mh): g on entry, M^{-1} g on exit.  tb, xb: LDS scratch of m entries each.
+template <typename T, int MW = TGMS_MMAX>
+__device__ inline void btri_solve_wave(const T* __restrict__ F, int m, int mh, T* vec, T* tb, T* xb) {
     const int lane = threadIdx.x & 63;
-    const long long ld = b + 1;
-    T acc = (lane < n) ? vec[lane] * S[lane] : T(0);
-    for (int r = 0; r < n; ++r) {
-        const int lr = r & 63;
-        const T y = readlane(acc, lr) * L[(long long)r * ld];
-        const int t = (lane - r) & 63;
-        if (lane == lr) {
-            vec[r] = y;
-            if (r + 64 < n) acc = vec[r + 64] * S[r + 64];
-        } else if (t <= b && r + t < n) {
-            acc -= L[(long long)r * ld + t] * y;
+    const int tri = btri_tri(m);
+    const long long bs = tri + btri_hes(m);
+    const T* S = F + (long long)mh * bs;
+    const bool act = lane < m;
+    // forward sweep
+    for (int j = 0; j < mh; ++j) {
+        const T* D = F + (long long)j * bs;
+        T t = act ? vec[j * m + lane] * S[j * m + lane] : T(0);
+        if (j > 0) {
+            const T* E = F + (long long)(j - 1) * bs + tri;
+            T e[MW];
+#pragma unroll
+            for (int c = 0; c < MW; ++c)
+                e[c] = (c < m && act && c + 1 >= lane) ? E[btri_offE(c) + lane] : T(0);
+            T acc = T(0);
+#pragma unroll
+            for (int c = 0; c < MW; ++c)
+                if (c < m) acc += e[c] * xb[c];
+            t -= acc;
         }
+        T d[MW];
+#pragma unroll
+        for (int c = 0; c < MW; ++c) d[c] = (c < m && act && c <= lane) ? D[btri_offD(c, m) + lane - c] : T(0);
+        if (act) tb[lane] = t;
+        __syncthreads();
+        T y = T(0);
+#pragma unroll
+        for (int c = 0; c < MW; ++c)
+            if (c < m) y += d[c] * tb[c];
+        __syncthreads();
+        if (act) {
+            xb[lane] = y;
+            vec[j * m + lane] = y;
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    T wreg = T(0);
-    for (int r = n - 1; r >= 0; --r) {
-        const int lr = r & 63;
-        const int t = (lane - r) & 63;
-        T prod = (t >= 1 && t <= b && r + t < n) ? L[(long long)r * ld + t] * wreg : T(0);
-        const T s = wave_sum(prod);
-        if (lane == lr) {
-            const T w = (vec[r] - s) * L[(long long)r * ld];
-            wreg = w;
-            vec[r] = w * S[r];
+    // backward sweep (xb holds w_{j+1})
+    for (int j = mh - 1; j >= 0; --j) {
+        const T* D = F + (long long)j * bs;
+        T t = act ? vec[j * m + lane] : T(0);
+        if (j + 1 < mh) {
+            const T* E = F + (long long)j * bs + tri + btri_offE(lane < m ? lane : 0);
+            T e[MW];
+#pragma unroll
+            for (int r = 0; r < MW; ++r) e[r] = (r < m && act && r <= lane + 1) ? E[r] : T(0);
+            T acc = T(0);
+#pragma unroll
+            for (int r = 0; r < MW; ++r)
+                if (r < m) acc += e[r] * xb[r];
+            t -= acc;
         }
+        const T* Dc = D + btri_offD(lane < m ? lane : 0, m) - (lane < m ? lane : 0);  // Dc[r] = D(r, lane)
+        T d[MW];
+#pragma unroll
+        for (int r = 0; r < MW; ++r) d[r] = (r < m && act && r >= lane) ? Dc[r] : T(0);
+        if (act) tb[lane] = t;
+        __syncthreads();
+        T w = T(0);
+#pragma unroll
+        for (int r = 0; r < MW; ++r)
+            if (r < m) w += d[r] * tb[r];
+        __syncthreads();
+        if (act) {
+            xb[lane] = w;
+            vec[j * m + lane] = w * S[j * m + lane];
+        }
+        __syncthreads();
+    }
+}
+
+// Same solve with the factor F already in LDS: operands are read from LDS inside
+// the multiply-add loops (no register staging).
+template <typename T>
+__device__ inline void btri_solve_lds(const T* F, int m, int mh, T* vec, T* tb, T* xb) {
+    const int lane = threadIdx.x;  // every thread of the workgroup passes the barriers; lanes >= m idle
+    const int tri = btri_tri(m);
+    const int bs = tri + btri_hes(m);
+    const T* S = F + mh * bs;
+    const bool act = lane < m;
+    const int la = act ? lane : 0;
+    for (int j = 0; j < mh; ++j) {
+        const T* D = F + j * bs;
+        T t = act ? vec[j * m + lane] * S[j * m + lane] : T(0);
+        if (j > 0) {
+            const T* E = F + (j - 1) * bs + tri;
+            T a0 = T(0), a1 = T(0);
+            const int c0 = la > 0 ? la - 1 : 0;
+            int c = c0;
+#pragma unroll 4
+            for (; c + 1 < m; c += 2) {
+                a0 += E[btri_offE(c) + la] * xb[c];
+                a1 += E[btri_offE(c + 1) + la] * xb[c + 1];
+            }
+            if (c < m) a0 += E[btri_offE(c) + la] * xb[c];
+            if (act) t -= a0 + a1;
+        }
+        if (act) tb[lane] = t;
+        __syncthreads();
+        T y0 = T(0), y1 = T(0);
+        int c = 0;
+#pragma unroll 4
+        for (; c + 1 <= la; c += 2) {
+            y0 += D[btri_offD(c, m) + la - c] * tb[c];
+            y1 += D[btri_offD(c + 1, m) + la - c - 1] * tb[c + 1];
+        }
+        if (c <= la) y0 += D[btri_offD(c, m) + la - c] * tb[c];
+        __syncthreads();
+        if (act) {
+            xb[lane] = y0 + y1;
+            vec[j * m + lane] = y0 + y1;
+        }
+        __syncthreads();
+    }
+    for (int j = mh - 1; j >= 0; --j) {
+        const T* D = F + j * bs;
+        T t = act ? vec[j * m + lane] : T(0);
+        if (j + 1 < mh) {
+            const T* E = F + j * bs + tri + btri_offE(la);
+            const int rmax = la + 1 < m ? la + 1 : m - 1;
+            T a0 = T(0), a1 = T(0);
+            int r = 0;
+#pragma unroll 4
+            for (; r + 1 <= rmax; r += 2) {
+                a0 += E[r] * xb[r];
+                a1 += E[r + 1] * xb[r + 1];
+            }
+            if (r <= rmax) a0 += E[r] * xb[r];
+            if (act) t -= a0 + a1;
+        }
+        if (act) tb[lane] = t;
+        __syncthreads();
+        const T* Dc = D + btri_offD(la, m) - la;
+        T w0 = T(0), w1 = T(0);
+        int r = la;
+#pragma unroll 4
+        for (; r + 1 < m; r += 2) {
+            w0 += Dc[r] * tb[r];
+            w1 += Dc[r + 1] * tb[r + 1];
+        }
+        if (r < m) w0 += Dc[r] * tb[r];
+        __syncthreads();
+        if (act) {
+            xb[lane] = w0 + w1;
+            vec[j * m + lane] = (w0 + w1) * S[j * m + lane];
+        }
+        __syncthreads();
     }
 }

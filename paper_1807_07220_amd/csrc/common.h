@@ -106,6 +106,8 @@ struct tgms_ctx {
     std::vector<Rect> patch_h;
     Rect* patch = nullptr;
     int pat_bmax = 0, pat_nmax = 0;
+    long long pat_fmax = 0;   // largest patch factor (elements)
+    int lds_max = 65536;      // device limit on LDS per workgroup (bytes)
     long long pat_pool = 0, pat_vpool = 0;
     double* patL = nullptr;
     double* patS = nullptr;
@@ -161,7 +163,17 @@ struct tgms_ctx {
     double* blkbuf = nullptr; // 2 * nblk
     double* red = nullptr;    // reduction scratch
     double* red_h = nullptr;  // pinned host
+    double* sc = nullptr;     // device PCG scalars (see k_grid.hip)
+    double* hist = nullptr;   // device alpha/beta history
+    int hist_cap = 0;
+    hipGraphExec_t iter_graph = nullptr;  // one captured PCG iteration
+    bool graph_failed = false;
     int red_blocks = 0;
+    // per-kernel event timing (tgms_profile)
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_rec;
     // diagnostics
     std::vector<double> alphas, betas;
     double t_setup_ms = 0, t_snap_ms = 0, t_eig_ms = 0, t_coarse_ms = 0, t_smoother_ms = 0;
@@ -180,6 +192,15 @@ struct tgms_ctx {
 
 // ---------------------------------------------------------------- launchers
 namespace tgms {
+enum ProfKernel { PK_SMOOTH = 0, PK_APPLYK = 1, PK_RESTRICT = 2, PK_PROLONG = 3, PK_COUNT = 4 };
+// record an event pair around one launch when profiling is on
+struct ProfScope {
+    tgms_ctx* c;
+    int id;
+    hipEvent_t e1 = nullptr;
+    ProfScope(tgms_ctx* ctx, int kid);
+    ~ProfScope();
+};
 // grid / vector kernels (k_grid.hip)
 void cell_weights(tgms_ctx* c, const double* kappa, int* bad);
 template <typename T>
@@ -194,6 +215,12 @@ void curlT(tgms_ctx* c, const double* u, double* g);
 double dot(tgms_ctx* c, const double* x, const double* y, long long n);
 void dot3(tgms_ctx* c, const double* g, const double* z, const double* gold, double out[3]);
 double curl_norm2(tgms_ctx* c, const double* psi);
+void pcg_alpha(tgms_ctx* c, const double* p, const double* q, double* sc, double* hist);
+void pcg_beta(tgms_ctx* c, const double* g, const double* z, const double* gold, double* sc, double* hist,
+              bool flexible, bool first);
+void pcg_update(tgms_ctx* c, const double* sc, const double* p, const double* q, double* x, double* g, double* gold);
+void pcg_dir(tgms_ctx* c, const double* sc, const double* z, double* p);
+void copy(tgms_ctx* c, long long n, const double* x, double* y);
 void axpy(tgms_ctx* c, long long n, double a, const double* x, double* y);        // y += a x
 void xpay(tgms_ctx* c, long long n, const double* x, double b, double* y);        // y = x + b y
 void cast_d2f(tgms_ctx* c, long long n, const double* x, float* y);

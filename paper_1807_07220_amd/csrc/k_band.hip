@@ -8,7 +8,7 @@
 // vertices.  C^T A C is the global 9-point stencil restricted to those
 // vertices: SPD and banded with lower bandwidth b = (interior vertices per
 // row) + 1.  It is diagonally equilibrated, factorised by a band Cholesky in
-// FP64 and stored column-band ("LC[c][t] = L(c+t, c)", LC[c][0] = 1/L(c,c)).
+// FP64 and then regrouped by vertex rows (block-row form of band.h).
 #include "common.h"
 #include "band.h"
 
@@ -18,7 +18,7 @@ namespace {
 template <bool WRITE32>
 __global__ void k_band_factor(const Rect* __restrict__ rects, const double* __restrict__ a, int nx, double sx2,
                               double sy2, double* __restrict__ Lpool, double* __restrict__ Spool,
-                              float* __restrict__ L32, float* __restrict__ S32, int* __restrict__ fail) {
+                              float* __restrict__ L32, int* __restrict__ fail) {
     extern __shared__ double M[];
     const Rect R = rects[blockIdx.x];
     const int m = R.i1 - R.i0 - 1, mh = R.j1 - R.j0 - 1;
@@ -77,32 +77,100 @@ __global__ void k_band_factor(const Rect* __restrict__ rects, const double* __re
         if (lane == 0) col[0] = inv;
         __syncthreads();
     }
-    for (long long e = lane; e < (long long)n * ld; e += TGMS_WAVE) {
-        Lpool[R.off + e] = M[e];
-        if (WRITE32) L32[R.off + e] = (float)M[e];
+    // repack by vertex rows: D_j = L_jj^{-1} (lower, by columns), E_j = L_{j+1,j} (Hessenberg, by columns)
+    const int tri = btri_tri(m), bs = tri + btri_hes(m);
+    double* out = Lpool + R.off;
+    for (int j = 0; j < mh; ++j) {
+        double* D = out + (long long)j * bs;
+        if (lane < m) {
+            const int cc = lane;  // column of L_jj^{-1}: solve L_jj x = e_cc, rows cc..m-1
+            for (int r = cc; r < m; ++r) {
+                double acc = (r == cc) ? 1.0 : 0.0;
+                for (int k = cc; k < r; ++k)
+                    acc -= M[(long long)(j * m + k) * ld + (r - k)] * D[btri_offD(cc, m) + (k - cc)];
+                // diagonal of L stored as its reciprocal
+                D[btri_offD(cc, m) + (r - cc)] = acc * M[(long long)(j * m + r) * ld];
+            }
+        }
+        if (j + 1 < mh) {
+            double* E = D + tri;
+            for (int e = lane; e < btri_hes(m); e += TGMS_WAVE) {
+                int cc = 0;
+                while (btri_offE(cc + 1) <= e && cc + 1 < m) ++cc;
+                const int a = e - btri_offE(cc);  // row of E_j, a <= cc + 1
+                E[e] = M[(long long)(j * m + cc) * ld + (m + a - cc)];
+            }
+        }
     }
-    if (WRITE32)
-        for (int r = lane; r < n; r += TGMS_WAVE) S32[R.voff + r] = (float)Spool[R.voff + r];
+    double* Sout = out + (long long)mh * bs;
+    for (int r = lane; r < n; r += TGMS_WAVE) Sout[r] = Spool[R.voff + r];
+    __syncthreads();
+    if (WRITE32) {
+        const long long tot = btri_size(m, mh);
+        for (long long e = lane; e < tot; e += TGMS_WAVE) L32[R.off + e] = (float)out[e];
+    }
 }
 
 // Smoother, phase 1: per patch, w = (C^T A C)^{-1} g on its interior vertices.
-template <typename T>
-__global__ void k_smooth_patches(const Rect* __restrict__ rects, const T* __restrict__ L, const T* __restrict__ S,
-                                 const T* __restrict__ g, int nx, T* __restrict__ wout) {
+template <typename T, int MW>
+__global__ void __launch_bounds__(64) k_smooth_patches(const Rect* __restrict__ rects, const T* __restrict__ L, const T* __restrict__ g,
+                                 int nx, T* __restrict__ wout) {
     extern __shared__ unsigned char smem_raw[];
-    T* vec = reinterpret_cast<T*>(smem_raw);
+    T* tb = reinterpret_cast<T*>(smem_raw);
+    T* xb = tb + 64;
+    T* vec = xb + 64;
     const Rect R = rects[blockIdx.x];
     const int m = R.i1 - R.i0 - 1, mh = R.j1 - R.j0 - 1;
-    const int n = m * mh, b = m + 1;
+    const int n = m * mh;
     const int lane = threadIdx.x;
     for (int r = lane; r < n; r += TGMS_WAVE) {
         const int aa = r % m, bb = r / m;
         vec[r] = g[(long long)(R.j0 + 1 + bb) * nx + R.i0 + 1 + aa];
     }
     __syncthreads();
-    band_solve_wave<T>(L + R.off, S + R.voff, n, b, vec);
+    btri_solve_wave<T, MW>(L + R.off, m, mh, vec, tb, xb);
     __syncthreads();
     for (int r = lane; r < n; r += TGMS_WAVE) wout[R.voff + r] = vec[r];
+}
+
+// Smoother, phase 1 with the patch factor staged in LDS: the workgroup (4 waves) copies
+// the whole factor with 16-byte loads, all in flight together; the block sweeps then
+// read only LDS.  Factors start at 16-byte-aligned offsets (multiples of 4 words).
+template <typename T, int MW>
+__global__ void __launch_bounds__(256) k_smooth_patches_lds(const Rect* __restrict__ rects, const T* __restrict__ L,
+                                                            const T* __restrict__ g, int nx, T* __restrict__ wout) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* tb = reinterpret_cast<T*>(smem_raw);
+    T* xb = tb + 64;
+    const Rect R = rects[blockIdx.x];
+    const int m = R.i1 - R.i0 - 1, mh = R.j1 - R.j0 - 1;
+    const int n = m * mh;
+    T* vec = xb + 64;
+    T* F = vec + ((n + 3) & ~3);
+    const long long fs = btri_size(m, mh);
+    const int tid = threadIdx.x;
+    using V = float4;  // 16 bytes
+    constexpr int PER = 16 / sizeof(T);
+    const V* src = reinterpret_cast<const V*>(L + R.off);
+    V* dst = reinterpret_cast<V*>(F);
+    const int nvec = (int)((fs + PER - 1) / PER);
+    int e = tid;
+    for (; e + 3 * 256 < nvec; e += 4 * 256) {
+        const V v0 = src[e], v1 = src[e + 256], v2 = src[e + 512], v3 = src[e + 768];
+        dst[e] = v0;
+        dst[e + 256] = v1;
+        dst[e + 512] = v2;
+        dst[e + 768] = v3;
+    }
+    for (; e < nvec; e += 256) dst[e] = src[e];
+    for (int r = tid; r < n; r += 256) {
+        const int aa = r % m, bb = r / m;
+        vec[r] = g[(long long)(R.j0 + 1 + bb) * nx + R.i0 + 1 + aa];
+    }
+    __syncthreads();
+    btri_solve_lds<T>(F, m, mh, vec, tb, xb);
+    __syncthreads();
+    for (int r = tid; r < n; r += 256) wout[R.voff + r] = vec[r];
 }
 
 // Smoother, phase 2: z(v) = [z(v)] + eta * sum of the patch solutions covering v
@@ -137,17 +205,18 @@ __global__ void k_smooth_gather(const Rect* __restrict__ rects, const T* __restr
 
 namespace tgms {
 
-static void factor_rects(tgms_ctx* c, Rect* rects, int count, int max_n, int max_b, double* L, double* S, float* L32,
-                         float* S32) {
+static void factor_rects(tgms_ctx* c, Rect* rects, int count, int max_n, int max_b, double* L, double* S,
+                         float* L32) {
     size_t lds = (size_t)max_n * (max_b + 1) * sizeof(double);
     if (lds > 65536) throw TgmsError{TGMS_E_UNSUPPORTED, "local band factor exceeds 64 KiB of LDS"};
     int* fail = c->alloc<int>(1);
+    if (max_b - 1 > TGMS_MMAX) throw TgmsError{TGMS_E_UNSUPPORTED, "local rectangle wider than 33 cells"};
     if (L32)
         hipLaunchKernelGGL((k_band_factor<true>), dim3(count), dim3(TGMS_WAVE), lds, c->stream, rects, c->a, c->nx,
-                           c->sx * c->sx, c->sy * c->sy, L, S, L32, S32, fail);
+                           c->sx * c->sx, c->sy * c->sy, L, S, L32, fail);
     else
         hipLaunchKernelGGL((k_band_factor<false>), dim3(count), dim3(TGMS_WAVE), lds, c->stream, rects, c->a,
-                           c->nx, c->sx * c->sx, c->sy * c->sy, L, S, L32, S32, fail);
+                           c->nx, c->sx * c->sx, c->sy * c->sy, L, S, L32, fail);
     LAUNCH_OK();
     int h = 0;
     HIP_OK(hipMemcpyAsync(&h, fail, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -157,7 +226,6 @@ static void factor_rects(tgms_ctx* c, Rect* rects, int count, int max_n, int max
 
 void factor_blocks(tgms_ctx* c) {
     std::vector<Rect> r(c->nblk);
-    const int ld = c->blk_b + 1;
     for (int J = 0; J < c->Ny; ++J)
         for (int I = 0; I < c->Nx; ++I) {
             Rect& q = r[J * c->Nx + I];
@@ -165,37 +233,68 @@ void factor_blocks(tgms_ctx* c) {
             q.i1 = (I + 1) * c->bx;
             q.j0 = J * c->by;
             q.j1 = (J + 1) * c->by;
-            q.off = (long long)(J * c->Nx + I) * c->blk_n * ld;
+            q.off = (long long)(J * c->Nx + I) * btri_size(c->bx - 1, c->by - 1);
             q.voff = (long long)(J * c->Nx + I) * c->blk_n;
         }
     Rect* d = c->alloc<Rect>(c->nblk);
     HIP_OK(hipMemcpyAsync(d, r.data(), sizeof(Rect) * c->nblk, hipMemcpyHostToDevice, c->stream));
-    factor_rects(c, d, c->nblk, c->blk_n, c->blk_b, c->blkL, c->blkS, nullptr, nullptr);
+    factor_rects(c, d, c->nblk, c->blk_n, c->blk_b, c->blkL, c->blkS, nullptr);
+}
+
+void enable_large_lds(tgms_ctx* c) {
+    // allow the staged smoother kernels to use the device's full per-workgroup LDS
+    (void)hipFuncSetAttribute((const void*)k_smooth_patches_lds<double, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
+    (void)hipFuncSetAttribute((const void*)k_smooth_patches_lds<double, 24>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
+    (void)hipFuncSetAttribute((const void*)k_smooth_patches_lds<double, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
+    (void)hipFuncSetAttribute((const void*)k_smooth_patches_lds<float, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
+    (void)hipFuncSetAttribute((const void*)k_smooth_patches_lds<float, 24>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
+    (void)hipFuncSetAttribute((const void*)k_smooth_patches_lds<float, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
+    (void)hipGetLastError();
 }
 
 void factor_patches(tgms_ctx* c) {
-    factor_rects(c, c->patch, c->nblk, c->pat_nmax, c->pat_bmax, c->patL, c->patS,
-                 c->precision ? c->patL32 : nullptr, c->precision ? c->patS32 : nullptr);
+    enable_large_lds(c);
+    factor_rects(c, c->patch, c->nblk, c->pat_nmax, c->pat_bmax, c->patL, c->patS, c->precision ? c->patL32 : nullptr);
 }
 
 template <typename T>
 void smooth(tgms_ctx* c, const T* g, T* z, bool accumulate) {
     const T* L;
-    const T* S;
     T* w;
     if constexpr (sizeof(T) == 8) {
         L = (const T*)c->patL;
-        S = (const T*)c->patS;
         w = (T*)c->patW;
     } else {
         L = (const T*)c->patL32;
-        S = (const T*)c->patS32;
         w = (T*)c->patW32;
     }
-    size_t lds = (size_t)c->pat_nmax * sizeof(T);
-    hipLaunchKernelGGL((k_smooth_patches<T>), dim3(c->nblk), dim3(TGMS_WAVE), lds, c->stream, c->patch, L, S, g,
-                       c->nx, w);
-    LAUNCH_OK();
+    size_t lds = (size_t)(c->pat_nmax + 128) * sizeof(T);
+    const size_t lds_staged = (size_t)(((c->pat_nmax + 3) & ~3) + 128 + c->pat_fmax + 4) * sizeof(T);
+    const bool staged = lds_staged <= (size_t)c->lds_max;
+    {
+        ProfScope ps(c, PK_SMOOTH);
+        const int mw = btri_width(c->pat_bmax - 1);
+        if (staged) {
+            if (mw == 16)
+                hipLaunchKernelGGL((k_smooth_patches_lds<T, 16>), dim3(c->nblk), dim3(256), lds_staged, c->stream,
+                                   c->patch, L, g, c->nx, w);
+            else if (mw == 24)
+                hipLaunchKernelGGL((k_smooth_patches_lds<T, 24>), dim3(c->nblk), dim3(256), lds_staged, c->stream,
+                                   c->patch, L, g, c->nx, w);
+            else
+                hipLaunchKernelGGL((k_smooth_patches_lds<T, 32>), dim3(c->nblk), dim3(256), lds_staged, c->stream,
+                                   c->patch, L, g, c->nx, w);
+        } else if (mw == 16)
+            hipLaunchKernelGGL((k_smooth_patches<T, 16>), dim3(c->nblk), dim3(TGMS_WAVE), lds, c->stream, c->patch, L, g,
+                               c->nx, w);
+        else if (mw == 24)
+            hipLaunchKernelGGL((k_smooth_patches<T, 24>), dim3(c->nblk), dim3(TGMS_WAVE), lds, c->stream, c->patch, L, g,
+                               c->nx, w);
+        else
+            hipLaunchKernelGGL((k_smooth_patches<T, 32>), dim3(c->nblk), dim3(TGMS_WAVE), lds, c->stream, c->patch, L, g,
+                               c->nx, w);
+        LAUNCH_OK();
+    }
     dim3 grid((c->nx + 63) / 64, (c->ny + 3) / 4);
     hipLaunchKernelGGL((k_smooth_gather<T>), grid, dim3(64, 4), 0, c->stream, c->patch, (const T*)w, c->nx, c->ny,
                        c->bx, c->by, c->Nx, c->Ny, T(c->eta), z, accumulate ? 1 : 0);

@@ -18,6 +18,11 @@ constexpr int NT = 256;  // threads (16 x 16), 4 x 4 outputs each
 
 // C = alpha * op(A) * op(B) + beta * C ; row-major; op(A) is M x K, op(B) is K x N.
 // lower_only: skip output tiles strictly above the diagonal (tile row < tile col).
+// 64 x 64 output tile per workgroup; each of the 4 wavefronts owns a 32 x 32 quarter made
+// of 2 x 2 FP64 MFMA 16x16x4 blocks.  Operand layout of v_mfma_f64_16x16x4f64: lane l
+// holds A[l%16][l/16] and B[l/16][l%16]; result element r of lane l is D[4*r + l/16][l%16].
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
 __global__ void __launch_bounds__(NT) k_gemm(int transA, int transB, int M, int N, int K, double alpha,
                                              const double* __restrict__ A, int lda, const double* __restrict__ B,
                                              int ldb, double beta, double* C, int ldc, int lower_only) {
@@ -26,14 +31,17 @@ __global__ void __launch_bounds__(NT) k_gemm(int transA, int transB, int M, int 
     __shared__ double As[TK][TB + 1];
     __shared__ double Bs[TK][TB + 1];
     const int tid = threadIdx.x;
-    const int ty = tid / 16, tx = tid % 16;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     const int m0 = tm * TB, n0 = tn * TB;
-    double acc[4][4] = {};
+    d4_t acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
+    const int li = lane & 15, lk = lane >> 4;
     for (int k0 = 0; k0 < K; k0 += TK) {
-        // load op(A)[m0..m0+64, k0..k0+16] and op(B)[k0..k0+16, n0..n0+64]
         for (int e = tid; e < TB * TK; e += NT) {
             int mm, kk;
-            if (transA) {  // A stored K x M: contiguous along m
+            if (transA) {
                 kk = e / TB;
                 mm = e % TB;
             } else {
@@ -47,7 +55,7 @@ __global__ void __launch_bounds__(NT) k_gemm(int transA, int transB, int M, int 
         }
         for (int e = tid; e < TB * TK; e += NT) {
             int nn, kk;
-            if (transB) {  // B stored N x K: contiguous along k
+            if (transB) {
                 nn = e / TK;
                 kk = e % TK;
             } else {
@@ -61,42 +69,38 @@ __global__ void __launch_bounds__(NT) k_gemm(int transA, int transB, int M, int 
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < TK; ++kk) {
-            double a[4], b[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) a[r] = As[kk][ty + 16 * r];
-#pragma unroll
-            for (int s = 0; s < 4; ++s) b[s] = Bs[kk][tx + 16 * s];
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int s = 0; s < 4; ++s) acc[r][s] += a[r] * b[s];
+        for (int k4 = 0; k4 < TK; k4 += 4) {
+            const double a0 = As[k4 + lk][wm + li], a1 = As[k4 + lk][wm + 16 + li];
+            const double b0 = Bs[k4 + lk][wn + li], b1 = Bs[k4 + lk][wn + 16 + li];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
         }
         __syncthreads();
     }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + ty + 16 * r;
-        if (gm >= M) continue;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int gn = n0 + tx + 16 * s;
-            if (gn >= N) continue;
-            double* cp = C + (long long)gm * ldc + gn;
-            *cp = alpha * acc[r][s] + (beta == 0.0 ? 0.0 : beta * *cp);
-        }
-    }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int r = 0; r < 4; ++r) {
+                const int gm = m0 + wm + 16 * a + 4 * r + lk, gn = n0 + wn + 16 * b + li;
+                if (gm >= M || gn >= N) continue;
+                double* cp = C + (long long)gm * ldc + gn;
+                *cp = alpha * acc[a][b][r] + (beta == 0.0 ? 0.0 : beta * *cp);
+            }
 }
 
 // Cholesky of the kb x kb diagonal block at (k0, k0) in place, and its inverse into Dinv (kb x kb, ld 64).
+// Thread (ty, tx) owns rows ty + 16 r and columns tx + 16 s of the 64 x 64 tile.
 __global__ void __launch_bounds__(NT) k_potrf_diag(double* __restrict__ A, int lda, int k0, int kb,
                                                    double* __restrict__ Dinv, int* __restrict__ fail) {
     __shared__ double S[TB][TB + 1];
-    const int tid = threadIdx.x;
-    for (int e = tid; e < kb * kb; e += NT) {
-        int i = e / kb, j = e % kb;
-        S[i][j] = (j <= i) ? A[(long long)(k0 + i) * lda + k0 + j] : 0.0;
-    }
+    __shared__ double X[TB][TB + 1];
+    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+    for (int r = 0; r < 4; ++r)
+        for (int q = 0; q < 4; ++q) {
+            const int i = ty + 16 * r, j = tx + 16 * q;
+            S[i][j] = (i < kb && j < kb && j <= i) ? A[(long long)(k0 + i) * lda + k0 + j] : (i == j ? 1.0 : 0.0);
+        }
     __syncthreads();
     for (int j = 0; j < kb; ++j) {
         const double d = S[j][j];
@@ -104,32 +108,37 @@ __global__ void __launch_bounds__(NT) k_potrf_diag(double* __restrict__ A, int l
             if (tid == 0) atomicOr(fail, 1);
             return;
         }
-        const double l = sqrt(d);
+        const double inv = 1.0 / sqrt(d);
         __syncthreads();
-        if (tid == 0) S[j][j] = l;
-        for (int i = j + 1 + tid; i < kb; i += NT) S[i][j] /= l;
+        if (tid < TB && tid >= j) S[tid][j] = (tid == j) ? d * inv : S[tid][j] * inv;
         __syncthreads();
-        for (int e = tid; e < (kb - j - 1) * (kb - j - 1); e += NT) {
-            int i = j + 1 + e / (kb - j - 1), k = j + 1 + e % (kb - j - 1);
-            if (k <= i) S[i][k] -= S[i][j] * S[k][j];
+        for (int r = 0; r < 4; ++r) {
+            const int i = ty + 16 * r;
+            if (i <= j) continue;
+            const double lij = S[i][j];
+            for (int q = 0; q < 4; ++q) {
+                const int k = tx + 16 * q;
+                if (k > j && k <= i) S[i][k] -= lij * S[k][j];
+            }
         }
         __syncthreads();
     }
-    // inverse of the lower-triangular block: column c of Dinv solves L x = e_c (each thread
-    // writes and re-reads only its own column)
-    if (tid < kb) {
+    // X = L^{-1}: thread c < kb solves L x = e_c (rows c..kb-1) serially
+    if (tid < TB) {
         const int cidx = tid;
-        for (int i = 0; i < kb; ++i) {
+        for (int i = 0; i < TB; ++i) {
             double s = (i == cidx) ? 1.0 : 0.0;
-            for (int k = cidx; k < i; ++k) s -= S[i][k] * Dinv[k * TB + cidx];
-            Dinv[i * TB + cidx] = (i < cidx) ? 0.0 : s / S[i][i];
+            for (int k = cidx; k < i; ++k) s -= S[i][k] * X[k][cidx];
+            X[i][cidx] = (i < cidx) ? 0.0 : s / S[i][i];
         }
     }
     __syncthreads();
-    for (int e = tid; e < kb * kb; e += NT) {
-        int i = e / kb, j = e % kb;
-        if (j <= i) A[(long long)(k0 + i) * lda + k0 + j] = S[i][j];
-    }
+    for (int r = 0; r < 4; ++r)
+        for (int q = 0; q < 4; ++q) {
+            const int i = ty + 16 * r, j = tx + 16 * q;
+            if (i < kb && j < kb && j <= i) A[(long long)(k0 + i) * lda + k0 + j] = S[i][j];
+            Dinv[i * TB + j] = (i < kb && j < kb) ? X[i][j] : 0.0;
+        }
 }
 
 // B[i][j] = X[i][j] (j <= i), B[i][j] = X[j][i] (j > i)
@@ -212,20 +221,35 @@ void dense_spd_inverse(tgms_ctx* c, double* A, int n) {
     HIP_OK(hipMemcpyAsync(&h, fail, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
     if (h) throw TgmsError{TGMS_E_INVAL, "coarse operator is not positive definite"};
-    // 2. X = L^{-1} by block rows: X[r, r] = Dinv_r, X[r, 0:r] = -Dinv_r (L[r, 0:r] X[0:r, 0:r])
+    // 2. X = L^{-1} by recursive halving: [L11 0; L21 L22]^{-1} = [X11 0; -X22 L21 X11, X22],
+    //    whose products are large square GEMMs; the 64 x 64 leaves are the inverses from step 1.
     double* X = c->alloc<double>((size_t)n * n);
-    double* Tm = c->alloc<double>((size_t)TB * n);
-    for (int r = 0; r < nblk; ++r) {
-        const int r0 = r * TB, rb = std::min(TB, n - r0);
-        hipLaunchKernelGGL(k_copy_block, dim3(nb((long long)rb * rb)), dim3(256), 0, c->stream,
-                           (const double*)(Dinv + (size_t)r * TB * TB), TB, X + (size_t)r0 * n + r0, n, rb, rb);
-        LAUNCH_OK();
-        if (r0 == 0) continue;
-        // Tm (rb x r0) = L[r0:r0+rb, 0:r0] * X[0:r0, 0:r0]
-        gemm(c, 0, 0, rb, r0, r0, 1.0, A + (size_t)r0 * n, n, X, n, 0.0, Tm, n);
-        // X[r0:, 0:r0] = -Dinv_r * Tm
-        gemm(c, 0, 0, rb, r0, rb, -1.0, Dinv + (size_t)r * TB * TB, TB, Tm, n, 0.0, X + (size_t)r0 * n, n);
-    }
+    double* Tm = c->alloc<double>((size_t)n * (n / 2 + TB));
+    struct Rec {
+        tgms_ctx* c;
+        double* A;
+        double* X;
+        double* Tm;
+        double* Dinv;
+        int n;
+        void run(int o, int len) {  // block [o, o+len) of L, o and len multiples of 64 except the last
+            if (len <= TB) {
+                hipLaunchKernelGGL(k_copy_block, dim3(nb((long long)len * len)), dim3(256), 0, c->stream,
+                                   (const double*)(Dinv + (size_t)(o / TB) * TB * TB), TB, X + (size_t)o * n + o, n,
+                                   len, len);
+                LAUNCH_OK();
+                return;
+            }
+            const int n1 = ((len / TB + 1) / 2) * TB, n2 = len - n1;
+            run(o, n1);
+            run(o + n1, n2);
+            // Tm (n2 x n1) = L21 X11 ; X21 = -X22 Tm
+            gemm(c, 0, 0, n2, n1, n1, 1.0, A + (size_t)(o + n1) * n + o, n, X + (size_t)o * n + o, n, 0.0, Tm, n1);
+            gemm(c, 0, 0, n2, n1, n2, -1.0, X + (size_t)(o + n1) * n + o + n1, n, Tm, n1, 0.0,
+                 X + (size_t)(o + n1) * n + o, n);
+        }
+    } rec{c, A, X, Tm, Dinv, n};
+    rec.run(0, n);
     // 3. pack
     hipLaunchKernelGGL(k_pack_inverse, dim3(nb((long long)n * n)), dim3(256), 0, c->stream, (const double*)X, A, n);
     LAUNCH_OK();

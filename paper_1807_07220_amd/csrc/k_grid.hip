@@ -245,6 +245,92 @@ __global__ void k_fill0(long long n, double* __restrict__ y) {
     if (t < n) y[t] = 0.0;
 }
 
+// ---- PCG with its scalars on the device (no host round trip inside an iteration) ----
+// sc: [0] rho, [1] p^T q, [2] alpha, [3] beta, [4] |z|^2, [5] |z|^2/|z0|^2, [6] |z0|^2,
+//     [7] breakdown flag, [8] iteration counter; hist holds alpha_k, beta_k pairs.
+enum { SC_RHO = 0, SC_PQ, SC_ALPHA, SC_BETA, SC_ZN2, SC_REL2, SC_Z02, SC_FLAG, SC_IT };
+
+__device__ inline double block_total(const double* __restrict__ part, int k) {
+    __shared__ double sh[RED_THREADS / TGMS_WAVE];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < RED_BLOCKS; b += RED_THREADS) s += part[k * RED_BLOCKS + b];
+    s = wave_sum(s);
+    if (lane == 0) sh[wid] = s;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < RED_THREADS / TGMS_WAVE; ++w) t += sh[w];
+    __syncthreads();
+    return t;
+}
+
+// after the p^T q partials: alpha = rho / p^T q
+__global__ void k_pcg_alpha(const double* __restrict__ part, double* __restrict__ sc, double* __restrict__ hist) {
+    const double pq = block_total(part, 0);
+    if (threadIdx.x == 0) {
+        const int it = (int)sc[SC_IT];
+        sc[SC_PQ] = pq;
+        if (!(pq > 0.0) || !(pq < INFINITY)) sc[SC_FLAG] = 1.0;
+        const double a = sc[SC_RHO] / pq;
+        sc[SC_ALPHA] = a;
+        hist[2 * it] = a;
+    }
+}
+
+// after the (g.z, z.gold, |Cz|^2) partials: rho, beta, relative residual; counts the iteration
+__global__ void k_pcg_beta(const double* __restrict__ part, double* __restrict__ sc, double* __restrict__ hist,
+                           int flexible, int first) {
+    const double gz = block_total(part, 0);
+    const double zgold = block_total(part, 1);
+    const double zn2 = block_total(part, 2);
+    if (threadIdx.x == 0) {
+        if (first) {
+            sc[SC_RHO] = gz;
+            sc[SC_Z02] = zn2;
+            sc[SC_ZN2] = zn2;
+            sc[SC_REL2] = 1.0;
+            sc[SC_IT] = 0.0;
+            sc[SC_FLAG] = 0.0;
+            return;
+        }
+        const int it = (int)sc[SC_IT];
+        const double rho = sc[SC_RHO];
+        const double beta = flexible ? (gz - zgold) / rho : gz / rho;
+        sc[SC_BETA] = beta;
+        sc[SC_RHO] = gz;
+        sc[SC_ZN2] = zn2;
+        sc[SC_REL2] = zn2 / sc[SC_Z02];
+        hist[2 * it + 1] = beta;
+        sc[SC_IT] = it + 1;
+    }
+}
+
+// x += alpha p ; gold = g (flexible) ; g -= alpha q
+__global__ void k_pcg_update(long long n, const double* __restrict__ sc, const double* __restrict__ p,
+                             const double* __restrict__ q, double* __restrict__ x, double* __restrict__ g,
+                             double* __restrict__ gold) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const double a = sc[SC_ALPHA];
+    x[t] += a * p[t];
+    const double gv = g[t];
+    if (gold) gold[t] = gv;
+    g[t] = gv - a * q[t];
+}
+
+// p = z + beta p
+__global__ void k_pcg_dir(long long n, const double* __restrict__ sc, const double* __restrict__ z,
+                          double* __restrict__ p) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    p[t] = z[t] + sc[SC_BETA] * p[t];
+}
+
+__global__ void k_copy(long long n, const double* __restrict__ x, double* __restrict__ y) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t < n) y[t] = x[t];
+}
+
 inline unsigned nb(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 double finish_reduce(tgms_ctx* c, int nv, double* out) {
@@ -272,6 +358,7 @@ void cell_weights(tgms_ctx* c, const double* kappa, int* bad) {
 template <typename T>
 void apply_K(tgms_ctx* c, const T* psi, T* out, const T* a) {
     dim3 grid((c->nx + TX - 1) / TX, (c->ny + TY - 1) / TY);
+    ProfScope ps(c, PK_APPLYK);
     hipLaunchKernelGGL((k_apply_K<T, 0>), grid, dim3(TX, TY), 0, c->stream, psi, (const T*)nullptr, out, a, c->nx,
                        c->ny, T(c->sx * c->sx), T(c->sy * c->sy));
     LAUNCH_OK();
@@ -279,6 +366,7 @@ void apply_K(tgms_ctx* c, const T* psi, T* out, const T* a) {
 template <typename T>
 void residual_K(tgms_ctx* c, const T* g, const T* psi, T* out, const T* a) {
     dim3 grid((c->nx + TX - 1) / TX, (c->ny + TY - 1) / TY);
+    ProfScope ps(c, PK_APPLYK);
     hipLaunchKernelGGL((k_apply_K<T, 1>), grid, dim3(TX, TY), 0, c->stream, psi, g, out, a, c->nx, c->ny,
                        T(c->sx * c->sx), T(c->sy * c->sy));
     LAUNCH_OK();
@@ -342,6 +430,47 @@ double curl_norm2(tgms_ctx* c, const double* psi) {
     LAUNCH_OK();
     double out[1];
     return finish_reduce(c, 1, out);
+}
+
+// partial sums of p.q into red, then alpha on the device
+void pcg_alpha(tgms_ctx* c, const double* p, const double* q, double* sc, double* hist) {
+    const long long n = (long long)c->nx * c->ny;
+    hipLaunchKernelGGL((k_multidot<1>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->stream, p, q, nullptr, nullptr,
+                       nullptr, nullptr, n, c->red);
+    LAUNCH_OK();
+    hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(RED_THREADS), 0, c->stream, (const double*)c->red, sc, hist);
+    LAUNCH_OK();
+}
+
+void pcg_beta(tgms_ctx* c, const double* g, const double* z, const double* gold, double* sc, double* hist,
+              bool flexible, bool first) {
+    const long long n = (long long)c->nx * c->ny;
+    hipLaunchKernelGGL((k_multidot<2>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->stream, g, z, gold ? gold : g, z,
+                       nullptr, nullptr, n, c->red);
+    LAUNCH_OK();
+    hipLaunchKernelGGL(k_curl_norm2, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->stream, z, c->nx, c->ny, c->sx, c->sy,
+                       c->red + 2 * RED_BLOCKS);
+    LAUNCH_OK();
+    hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(RED_THREADS), 0, c->stream, (const double*)c->red, sc, hist,
+                       flexible ? 1 : 0, first ? 1 : 0);
+    LAUNCH_OK();
+}
+
+void pcg_update(tgms_ctx* c, const double* sc, const double* p, const double* q, double* x, double* g, double* gold) {
+    const long long n = (long long)c->nx * c->ny;
+    hipLaunchKernelGGL(k_pcg_update, dim3(nb(n)), dim3(256), 0, c->stream, n, sc, p, q, x, g, gold);
+    LAUNCH_OK();
+}
+
+void pcg_dir(tgms_ctx* c, const double* sc, const double* z, double* p) {
+    const long long n = (long long)c->nx * c->ny;
+    hipLaunchKernelGGL(k_pcg_dir, dim3(nb(n)), dim3(256), 0, c->stream, n, sc, z, p);
+    LAUNCH_OK();
+}
+
+void copy(tgms_ctx* c, long long n, const double* x, double* y) {
+    hipLaunchKernelGGL(k_copy, dim3(nb(n)), dim3(256), 0, c->stream, n, x, y);
+    LAUNCH_OK();
 }
 
 void axpy(tgms_ctx* c, long long n, double a, const double* x, double* y) {

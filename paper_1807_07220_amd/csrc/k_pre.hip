@@ -136,7 +136,8 @@ struct PreGeom {
 };
 
 // Block corrections (eq. subproblem), one wavefront per block; adds into vbar's block-interior faces.
-__global__ void k_block_correct(PreGeom G, const double* __restrict__ a, const double* __restrict__ blkL,
+template <int MW>
+__global__ void __launch_bounds__(64) k_block_correct(PreGeom G, const double* __restrict__ a, const double* __restrict__ blkL,
                                 const double* __restrict__ blkS, const double* __restrict__ q,
                                 const double* __restrict__ Av, double* __restrict__ vbar) {
     extern __shared__ double sm[];
@@ -153,6 +154,8 @@ __global__ void k_block_correct(PreGeom G, const double* __restrict__ a, const d
     double* oy = ox + nfx;
     double* g = oy + nfy;
     double* tmp = g + nloc;
+    double* tb = tmp + byl + 2;
+    double* xb = tb + 64;
     const int blk = blockIdx.x, I = blk % G.Nx, J = blk / G.Nx, lane = threadIdx.x;
     const long long cell0 = (long long)J * G.by * G.nx + (long long)I * G.bx;
     const double* aK = a + cell0;
@@ -180,8 +183,7 @@ __global__ void k_block_correct(PreGeom G, const double* __restrict__ a, const d
     }
     __syncthreads();
     block_curlT(bxl, byl, ox, oy, G.sx, G.sy, 1.0, g);
-    const long long ld = bxl + 1;
-    band_solve_wave<double>(blkL + (long long)blk * nloc * ld, blkS + (long long)blk * nloc, nloc, bxl, g);
+    btri_solve_wave<double, MW>(blkL + (long long)blk * btri_size(bxl - 1, byl - 1), bxl - 1, byl - 1, g, tb, xb);
     __syncthreads();
     block_curl_add(bxl, byl, g, G.sx, G.sy, vx, vy);
     for (int e = lane; e < nfx; e += 64) {
@@ -314,9 +316,17 @@ void preprocess(tgms_ctx* c, const double* F, const double* g_bnd, double* vbar,
     LAUNCH_OK();
     PreGeom G{c->nx, c->ny, c->bx, c->by, Nx, Ny, c->hx, c->hy, c->sx, c->sy};
     const int nfxl = c->by * (c->bx + 1), nfyl = (c->by + 1) * c->bx, nloc = (c->bx - 1) * (c->by - 1);
-    size_t lds = sizeof(double) * (2 * c->by + 2 * c->bx + c->bx * c->by + 2 * (nfxl + nfyl) + nloc + c->by + 2);
-    hipLaunchKernelGGL(k_block_correct, dim3(c->nblk), dim3(64), lds, c->stream, G, c->a, c->blkL, c->blkS,
-                       (const double*)c->cellw, (const double*)c->fu, vbar);
+    size_t lds = sizeof(double) * (2 * c->by + 2 * c->bx + c->bx * c->by + 2 * (nfxl + nfyl) + nloc + c->by + 2 + 128);
+    const int mw = btri_width(c->bx - 1);
+    if (mw == 16)
+        hipLaunchKernelGGL((k_block_correct<16>), dim3(c->nblk), dim3(64), lds, c->stream, G, c->a, c->blkL, c->blkS,
+                           (const double*)c->cellw, (const double*)c->fu, vbar);
+    else if (mw == 24)
+        hipLaunchKernelGGL((k_block_correct<24>), dim3(c->nblk), dim3(64), lds, c->stream, G, c->a, c->blkL, c->blkS,
+                           (const double*)c->cellw, (const double*)c->fu, vbar);
+    else
+        hipLaunchKernelGGL((k_block_correct<32>), dim3(c->nblk), dim3(64), lds, c->stream, G, c->a, c->blkL, c->blkS,
+                           (const double*)c->cellw, (const double*)c->fu, vbar);
     LAUNCH_OK();
 }
 

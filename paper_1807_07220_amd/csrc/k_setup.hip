@@ -37,7 +37,8 @@ struct BlockGeom {
 };
 
 // Snapshots: one wavefront per block, columns (side s, fine face l) in turn.
-__global__ void k_snapshots(BlockGeom G, const double* __restrict__ a, const double* __restrict__ blkL,
+template <int MW>
+__global__ void __launch_bounds__(64) k_snapshots(BlockGeom G, const double* __restrict__ a, const double* __restrict__ blkL,
                             const double* __restrict__ blkS, double* __restrict__ Psi) {
     extern __shared__ double sm[];
     const int bxl = G.bx, byl = G.by;
@@ -53,13 +54,13 @@ __global__ void k_snapshots(BlockGeom G, const double* __restrict__ a, const dou
     double* oy = ox + nfx;
     double* g = oy + nfy;
     double* tmp = g + nloc;
+    double* tb = tmp + byl + 2;
+    double* xb = tb + 64;
     const int blk = blockIdx.x, I = blk % G.Nx, J = blk / G.Nx;
     const int lane = threadIdx.x;
     const double* aK = a + (long long)J * G.by * G.nx + (long long)I * G.bx;
     const double areaK = G.bx * G.hx * G.by * G.hy;
-    const long long ld = bxl + 1;
-    const double* L = blkL + (long long)blk * nloc * ld;
-    const double* S = blkS + (long long)blk * nloc;
+    const double* L = blkL + (long long)blk * btri_size(bxl - 1, byl - 1);
     double* out = Psi + (long long)blk * G.ncol * G.nfk;
     for (int s = 0; s < 4; ++s) {
         const bool interior = (s == 0 && I > 0) || (s == 1 && I < G.Nx - 1) || (s == 2 && J > 0) ||
@@ -92,7 +93,7 @@ __global__ void k_snapshots(BlockGeom G, const double* __restrict__ a, const dou
             __syncthreads();
             block_mass(bxl, byl, aK, G.nx, vx, vy, ox, oy);
             block_curlT(bxl, byl, ox, oy, G.sx, G.sy, -1.0, g);
-            band_solve_wave<double>(L, S, nloc, bxl, g);
+            btri_solve_wave<double, MW>(L, bxl - 1, byl - 1, g, tb, xb);
             __syncthreads();
             block_curl_add(bxl, byl, g, G.sx, G.sy, vx, vy);
             for (int e = lane; e < nfx; e += 64) col[e] = vx[e];
@@ -335,11 +336,16 @@ __global__ void k_pencil_eig(BlockGeom G, const double* __restrict__ kinv, const
 
 // Per block: Ak = T_K^T G_K T_K scattered into the dense coarse matrix, and the
 // path integral of every snapshot column to vertex values (for the stream functions).
+// Launched once per colour (I%2, J%2): blocks of one colour share no coarse unknown, so
+// their contributions are added without atomics and the assembly is deterministic.
 __global__ void k_coarse_local(BlockGeom G, const double* __restrict__ Gm, const double* __restrict__ Tm, int mu,
                                const int* __restrict__ unk, const int* __restrict__ nunk, double* __restrict__ Ac,
-                               int ncs, const double* __restrict__ Psi, double* __restrict__ PPsi) {
+                               int ncs, const double* __restrict__ Psi, double* __restrict__ PPsi, int colour) {
     extern __shared__ double sm[];
-    const int blk = blockIdx.x, tid = threadIdx.x, nth = blockDim.x;
+    const int bxc = (G.Nx + 1 - (colour & 1)) / 2;
+    const int bI = 2 * (blockIdx.x % bxc) + (colour & 1), bJ = 2 * (blockIdx.x / bxc) + (colour >> 1);
+    if (bI >= G.Nx || bJ >= G.Ny) return;
+    const int blk = bJ * G.Nx + bI, tid = threadIdx.x, nth = blockDim.x;
     const int ncol = G.ncol, nu = nunk[blk];
     const double* Gb = Gm + (long long)blk * ncol * ncol;
     const double* Tb = Tm + (long long)blk * ncol * mu;
@@ -356,7 +362,7 @@ __global__ void k_coarse_local(BlockGeom G, const double* __restrict__ Gm, const
         const int u = e / nu, w = e % nu;
         double s = 0.0;
         for (int k = 0; k < ncol; ++k) s += Tb[k * mu + u] * GT[k * mu + w];
-        atomicAdd(&Ac[(long long)ub[u] * ncs + ub[w]], s);
+        Ac[(long long)ub[u] * ncs + ub[w]] += s;
     }
     // path integral: psi(0,0) = 0, along the bottom edge by the y-fluxes, then up each column by the x-fluxes
     const int bxl = G.bx, byl = G.by, nfx = byl * (bxl + 1);
@@ -508,9 +514,15 @@ namespace tgms {
 void snapshots(tgms_ctx* c) {
     BlockGeom G = geom(c);
     const int nfx = c->by * (c->bx + 1), nfy = (c->by + 1) * c->bx, nloc = (c->bx - 1) * (c->by - 1);
-    size_t lds = sizeof(double) * (2 * c->by + 2 * c->bx + c->bx * c->by + 2 * (nfx + nfy) + nloc + c->by + 2);
+    size_t lds = sizeof(double) * (2 * c->by + 2 * c->bx + c->bx * c->by + 2 * (nfx + nfy) + nloc + c->by + 2 + 128);
     if (lds > 65536) throw TgmsError{TGMS_E_UNSUPPORTED, "coarse block too large for the snapshot kernel"};
-    hipLaunchKernelGGL(k_snapshots, dim3(c->nblk), dim3(64), lds, c->stream, G, c->a, c->blkL, c->blkS, c->Psi);
+    const int mw = btri_width(c->bx - 1);
+    if (mw == 16)
+        hipLaunchKernelGGL((k_snapshots<16>), dim3(c->nblk), dim3(64), lds, c->stream, G, c->a, c->blkL, c->blkS, c->Psi);
+    else if (mw == 24)
+        hipLaunchKernelGGL((k_snapshots<24>), dim3(c->nblk), dim3(64), lds, c->stream, G, c->a, c->blkL, c->blkS, c->Psi);
+    else
+        hipLaunchKernelGGL((k_snapshots<32>), dim3(c->nblk), dim3(64), lds, c->stream, G, c->a, c->blkL, c->blkS, c->Psi);
     LAUNCH_OK();
 }
 
@@ -539,9 +551,13 @@ void pencil_eig_q(tgms_ctx* c, double* Q) {
 void coarse_local_run(tgms_ctx* c, const double* Tm, const int* zc) {
     BlockGeom G = geom(c);
     size_t lds = sizeof(double) * c->ncol * c->mu;
-    hipLaunchKernelGGL(k_coarse_local, dim3(c->nblk), dim3(256), lds, c->stream, G, c->G, Tm, c->mu, c->blk_unk,
-                       c->blk_nu, c->Ac, c->ncs, c->Psi, c->APsi);
-    LAUNCH_OK();
+    for (int colour = 0; colour < 4; ++colour) {
+        const int bxc = (c->Nx + 1 - (colour & 1)) / 2, byc = (c->Ny + 1 - (colour >> 1)) / 2;
+        if (bxc <= 0 || byc <= 0) continue;
+        hipLaunchKernelGGL(k_coarse_local, dim3(bxc * byc), dim3(256), lds, c->stream, G, c->G, Tm, c->mu, c->blk_unk,
+                           c->blk_nu, c->Ac, c->ncs, c->Psi, c->APsi, colour);
+        LAUNCH_OK();
+    }
     hipLaunchKernelGGL(k_coarse_W, dim3(c->nblk), dim3(256), 0, c->stream, G, c->APsi, Tm, c->mu, c->blk_nu, zc, c->W,
                        c->precision ? c->W32 : nullptr);
     LAUNCH_OK();
@@ -573,9 +589,12 @@ void coarse_apply(tgms_ctx* c, const T* g, T* z, bool accumulate) {
         c1 = (T*)c->cvec32;
         c2 = (T*)c->cvec32;
     }
+    {
+    ProfScope ps(c, PK_RESTRICT);
     hipLaunchKernelGGL((k_coarse_restrict<T>), dim3(c->nblk), dim3(256), 0, c->stream, W, c->mu, c->blk_nu, g, c->nx,
                        c->bx, c->by, c->Nx, cy);
     LAUNCH_OK();
+    }
     hipLaunchKernelGGL((k_coarse_accum<T>), dim3((c->ncs + 255) / 256), dim3(256), 0, c->stream, c->unk_ptr,
                        c->unk_ent, (const T*)cy, c->ncs, c1);
     LAUNCH_OK();
@@ -587,6 +606,7 @@ void coarse_apply(tgms_ctx* c, const T* g, T* z, bool accumulate) {
         res = (T*)c->cvec32 + c->ncs;
     symv<T>(c, Ainv, c->ncs, c1, res);
     (void)c2;
+    ProfScope ps(c, PK_PROLONG);
     hipLaunchKernelGGL((k_coarse_prolong<T>), dim3(c->nblk), dim3(256), 0, c->stream, W, c->mu, c->blk_unk,
                        c->blk_nu, (const T*)res, c->nx, c->bx, c->by, c->Nx, z, accumulate ? 1 : 0);
     LAUNCH_OK();
