@@ -136,7 +136,9 @@ __global__ void __launch_bounds__(64) k_smooth_patches(const Rect* __restrict__ 
 // Smoother, phase 1 with the patch factor staged in LDS: the workgroup (4 waves) copies
 // the whole factor with 16-byte loads, all in flight together; the block sweeps then
 // read only LDS.  Factors start at 16-byte-aligned offsets (multiples of 4 words).
-template <typename T, int MW>
+// Patches whose row width is M1 or M2 (the interior and the boundary-clipped widths)
+// use the barrier-free compile-time-width solve; any other width the generic one.
+template <typename T, int M1, int M2>
 __global__ void __launch_bounds__(256) k_smooth_patches_lds(const Rect* __restrict__ rects, const T* __restrict__ L,
                                                             const T* __restrict__ g, int nx, T* __restrict__ wout) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -163,12 +165,23 @@ __global__ void __launch_bounds__(256) k_smooth_patches_lds(const Rect* __restri
         dst[e + 768] = v3;
     }
     for (; e < nvec; e += 256) dst[e] = src[e];
+    const bool fixed = (m == M1 || m == M2);
     for (int r = tid; r < n; r += 256) {
         const int aa = r % m, bb = r / m;
-        vec[r] = g[(long long)(R.j0 + 1 + bb) * nx + R.i0 + 1 + aa];
+        const T gv = g[(long long)(R.j0 + 1 + bb) * nx + R.i0 + 1 + aa];
+        vec[r] = fixed ? gv * L[R.off + fs - n + r] : gv;  // the fixed-width solve expects S g
     }
     __syncthreads();
-    btri_solve_lds<T>(F, m, mh, vec, tb, xb);
+    if (fixed) {
+        if (tid < 64) {  // one wavefront solves; the others wait at the barrier below
+            if (m == M1)
+                btri_solve_rl<T, M1>(F, mh, vec);
+            else
+                btri_solve_rl<T, M2>(F, mh, vec);
+        }
+    } else {
+        btri_solve_lds<T>(F, m, mh, vec, tb, xb);
+    }
     __syncthreads();
     for (int r = tid; r < n; r += 256) wout[R.voff + r] = vec[r];
 }
@@ -243,12 +256,12 @@ void factor_blocks(tgms_ctx* c) {
 
 void enable_large_lds(tgms_ctx* c) {
     // allow the staged smoother kernels to use the device's full per-workgroup LDS
-    (void)hipFuncSetAttribute((const void*)k_smooth_patches_lds<double, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
-    (void)hipFuncSetAttribute((const void*)k_smooth_patches_lds<double, 24>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
-    (void)hipFuncSetAttribute((const void*)k_smooth_patches_lds<double, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
-    (void)hipFuncSetAttribute((const void*)k_smooth_patches_lds<float, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
-    (void)hipFuncSetAttribute((const void*)k_smooth_patches_lds<float, 24>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
-    (void)hipFuncSetAttribute((const void*)k_smooth_patches_lds<float, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
+    (void)hipFuncSetAttribute((const void*)k_smooth_patches_lds<double, 19, 17>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
+    (void)hipFuncSetAttribute((const void*)k_smooth_patches_lds<double, 11, 9>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
+    (void)hipFuncSetAttribute((const void*)k_smooth_patches_lds<double, 1, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
+    (void)hipFuncSetAttribute((const void*)k_smooth_patches_lds<float, 19, 17>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
+    (void)hipFuncSetAttribute((const void*)k_smooth_patches_lds<float, 11, 9>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
+    (void)hipFuncSetAttribute((const void*)k_smooth_patches_lds<float, 1, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
     (void)hipGetLastError();
 }
 
@@ -275,14 +288,15 @@ void smooth(tgms_ctx* c, const T* g, T* z, bool accumulate) {
         ProfScope ps(c, PK_SMOOTH);
         const int mw = btri_width(c->pat_bmax - 1);
         if (staged) {
-            if (mw == 16)
-                hipLaunchKernelGGL((k_smooth_patches_lds<T, 16>), dim3(c->nblk), dim3(256), lds_staged, c->stream,
+            const int mi = c->pat_bmax - 1;  // interior patch row width
+            if (mi == 19)
+                hipLaunchKernelGGL((k_smooth_patches_lds<T, 19, 17>), dim3(c->nblk), dim3(256), lds_staged, c->stream,
                                    c->patch, L, g, c->nx, w);
-            else if (mw == 24)
-                hipLaunchKernelGGL((k_smooth_patches_lds<T, 24>), dim3(c->nblk), dim3(256), lds_staged, c->stream,
+            else if (mi == 11)
+                hipLaunchKernelGGL((k_smooth_patches_lds<T, 11, 9>), dim3(c->nblk), dim3(256), lds_staged, c->stream,
                                    c->patch, L, g, c->nx, w);
             else
-                hipLaunchKernelGGL((k_smooth_patches_lds<T, 32>), dim3(c->nblk), dim3(256), lds_staged, c->stream,
+                hipLaunchKernelGGL((k_smooth_patches_lds<T, 1, 1>), dim3(c->nblk), dim3(256), lds_staged, c->stream,
                                    c->patch, L, g, c->nx, w);
         } else if (mw == 16)
             hipLaunchKernelGGL((k_smooth_patches<T, 16>), dim3(c->nblk), dim3(TGMS_WAVE), lds, c->stream, c->patch, L, g,
