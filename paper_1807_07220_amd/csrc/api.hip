@@ -14,6 +14,7 @@
 
 #include "common.h"
 #include "band.h"
+#include "patch.h"
 
 namespace tgms {
 void bnd_faces(tgms_ctx* c, const double* g, double* gb);
@@ -307,7 +308,7 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
     if (o.overlap >= std::min(bx, by)) throw TgmsError{TGMS_E_UNSUPPORTED, "overlap must be smaller than a block"};
     if (std::max(bx, by) > 64) throw TgmsError{TGMS_E_UNSUPPORTED, "blocks wider than 64 cells"};
     const int ex = std::min(bx + 2 * o.overlap, nx), ey = std::min(by + 2 * o.overlap, ny);
-    if (ex - 1 + 1 >= 64) throw TgmsError{TGMS_E_UNSUPPORTED, "patch band wider than a wavefront"};
+    if (ex > 33) throw TgmsError{TGMS_E_UNSUPPORTED, "smoother patches wider than 33 cells"};
     (void)ey;
     auto* c = new tgms_ctx();
     try {
@@ -422,8 +423,8 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                     const int m = r.i1 - r.i0 - 1, n = m * (r.j1 - r.j0 - 1);
                     r.off = off;
                     r.voff = voff;
-                    off += (btri_size(m, r.j1 - r.j0 - 1) + 3) & ~3LL;  // 16-byte aligned factors
-                    c->pat_fmax = std::max(c->pat_fmax, btri_size(m, r.j1 - r.j0 - 1));
+                    off += (tw_size(m, r.j1 - r.j0 - 1) + 3) & ~3LL;  // 16-byte aligned factors
+                    c->pat_fmax = std::max(c->pat_fmax, tw_size(m, r.j1 - r.j0 - 1));
                     voff += n;
                     c->pat_nmax = std::max(c->pat_nmax, n);
                     c->pat_bmax = std::max(c->pat_bmax, m + 1);
@@ -433,7 +434,6 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
             c->patch = c->alloc<Rect>(c->nblk);
             HIP_OK(hipMemcpyAsync(c->patch, c->patch_h.data(), sizeof(Rect) * c->nblk, hipMemcpyHostToDevice, c->stream));
             c->patL = c->alloc<double>(off);
-            c->patS = c->alloc<double>(voff);
             c->patW = c->alloc<double>(voff);
             if (c->precision) {
                 c->patL32 = c->alloc<float>(off);

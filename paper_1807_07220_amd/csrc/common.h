@@ -110,9 +110,7 @@ struct tgms_ctx {
     int lds_max = 65536;      // device limit on LDS per workgroup (bytes)
     long long pat_pool = 0, pat_vpool = 0;
     double* patL = nullptr;
-    double* patS = nullptr;
     float* patL32 = nullptr;
-    float* patS32 = nullptr;
     double* patW = nullptr;  // per-patch local solution (vpool)
     float* patW32 = nullptr;
     // snapshots and Gram

@@ -1,6 +1,5 @@
-// Local direct solvers on cell rectangles: coarse blocks K_i (preprocessing
-// and snapshots, paper sections 3 and 4.1) and oversampled blocks K_i^+ (the
-// smoother, eq. smooth).
+// Local direct solvers on the coarse blocks K_i (preprocessing and snapshots,
+// paper sections 3 and 4.1).
 //
 // On a rectangle with zero normal flux on its boundary the local saddle
 // problem R L R^T [v; p] = [r; 0] has the divergence-free solution
@@ -111,109 +110,6 @@ __global__ void k_band_factor(const Rect* __restrict__ rects, const double* __re
     }
 }
 
-// Smoother, phase 1: per patch, w = (C^T A C)^{-1} g on its interior vertices.
-template <typename T, int MW>
-__global__ void __launch_bounds__(64) k_smooth_patches(const Rect* __restrict__ rects, const T* __restrict__ L, const T* __restrict__ g,
-                                 int nx, T* __restrict__ wout) {
-    extern __shared__ unsigned char smem_raw[];
-    T* tb = reinterpret_cast<T*>(smem_raw);
-    T* xb = tb + 64;
-    T* vec = xb + 64;
-    const Rect R = rects[blockIdx.x];
-    const int m = R.i1 - R.i0 - 1, mh = R.j1 - R.j0 - 1;
-    const int n = m * mh;
-    const int lane = threadIdx.x;
-    for (int r = lane; r < n; r += TGMS_WAVE) {
-        const int aa = r % m, bb = r / m;
-        vec[r] = g[(long long)(R.j0 + 1 + bb) * nx + R.i0 + 1 + aa];
-    }
-    __syncthreads();
-    btri_solve_wave<T, MW>(L + R.off, m, mh, vec, tb, xb);
-    __syncthreads();
-    for (int r = lane; r < n; r += TGMS_WAVE) wout[R.voff + r] = vec[r];
-}
-
-// Smoother, phase 1 with the patch factor staged in LDS: the workgroup (4 waves) copies
-// the whole factor with 16-byte loads, all in flight together; the block sweeps then
-// read only LDS.  Factors start at 16-byte-aligned offsets (multiples of 4 words).
-// Patches whose row width is M1 or M2 (the interior and the boundary-clipped widths)
-// use the barrier-free compile-time-width solve; any other width the generic one.
-template <typename T, int M1, int M2>
-__global__ void __launch_bounds__(256) k_smooth_patches_lds(const Rect* __restrict__ rects, const T* __restrict__ L,
-                                                            const T* __restrict__ g, int nx, T* __restrict__ wout) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* tb = reinterpret_cast<T*>(smem_raw);
-    T* xb = tb + 64;
-    const Rect R = rects[blockIdx.x];
-    const int m = R.i1 - R.i0 - 1, mh = R.j1 - R.j0 - 1;
-    const int n = m * mh;
-    T* vec = xb + 64;
-    T* F = vec + ((n + 3) & ~3);
-    const long long fs = btri_size(m, mh);
-    const int tid = threadIdx.x;
-    using V = float4;  // 16 bytes
-    constexpr int PER = 16 / sizeof(T);
-    const V* src = reinterpret_cast<const V*>(L + R.off);
-    V* dst = reinterpret_cast<V*>(F);
-    const int nvec = (int)((fs + PER - 1) / PER);
-    int e = tid;
-    for (; e + 3 * 256 < nvec; e += 4 * 256) {
-        const V v0 = src[e], v1 = src[e + 256], v2 = src[e + 512], v3 = src[e + 768];
-        dst[e] = v0;
-        dst[e + 256] = v1;
-        dst[e + 512] = v2;
-        dst[e + 768] = v3;
-    }
-    for (; e < nvec; e += 256) dst[e] = src[e];
-    const bool fixed = (m == M1 || m == M2);
-    for (int r = tid; r < n; r += 256) {
-        const int aa = r % m, bb = r / m;
-        const T gv = g[(long long)(R.j0 + 1 + bb) * nx + R.i0 + 1 + aa];
-        vec[r] = fixed ? gv * L[R.off + fs - n + r] : gv;  // the fixed-width solve expects S g
-    }
-    __syncthreads();
-    if (fixed) {
-        if (tid < 64) {  // one wavefront solves; the others wait at the barrier below
-            if (m == M1)
-                btri_solve_rl<T, M1>(F, mh, vec);
-            else
-                btri_solve_rl<T, M2>(F, mh, vec);
-        }
-    } else {
-        btri_solve_lds<T>(F, m, mh, vec, tb, xb);
-    }
-    __syncthreads();
-    for (int r = tid; r < n; r += 256) wout[R.voff + r] = vec[r];
-}
-
-// Smoother, phase 2: z(v) = [z(v)] + eta * sum of the patch solutions covering v
-// (fixed patch order, so the sum is deterministic; no atomics).
-template <typename T>
-__global__ void k_smooth_gather(const Rect* __restrict__ rects, const T* __restrict__ w, int nx, int ny, int bx,
-                                int by, int Nx, int Ny, T eta, T* __restrict__ z, int accumulate) {
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    const int j = blockIdx.y * 4 + threadIdx.y;
-    if (i >= nx || j >= ny) return;
-    const long long v = (long long)j * nx + i;
-    T s = T(0);
-    if (i > 0 && j > 0) {
-        const int I0 = i / bx, J0 = j / by;
-        for (int J = J0 - 1; J <= J0 + 1; ++J) {
-            if (J < 0 || J >= Ny) continue;
-            for (int I = I0 - 1; I <= I0 + 1; ++I) {
-                if (I < 0 || I >= Nx) continue;
-                const Rect R = rects[J * Nx + I];
-                if (i > R.i0 && i < R.i1 && j > R.j0 && j < R.j1) {
-                    const int m = R.i1 - R.i0 - 1;
-                    s += w[R.voff + (long long)(j - R.j0 - 1) * m + (i - R.i0 - 1)];
-                }
-            }
-        }
-    }
-    s *= eta;
-    z[v] = accumulate ? z[v] + s : s;
-}
-
 }  // namespace
 
 namespace tgms {
@@ -254,67 +150,5 @@ void factor_blocks(tgms_ctx* c) {
     factor_rects(c, d, c->nblk, c->blk_n, c->blk_b, c->blkL, c->blkS, nullptr);
 }
 
-void enable_large_lds(tgms_ctx* c) {
-    // allow the staged smoother kernels to use the device's full per-workgroup LDS
-    (void)hipFuncSetAttribute((const void*)k_smooth_patches_lds<double, 19, 17>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
-    (void)hipFuncSetAttribute((const void*)k_smooth_patches_lds<double, 11, 9>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
-    (void)hipFuncSetAttribute((const void*)k_smooth_patches_lds<double, 1, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
-    (void)hipFuncSetAttribute((const void*)k_smooth_patches_lds<float, 19, 17>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
-    (void)hipFuncSetAttribute((const void*)k_smooth_patches_lds<float, 11, 9>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
-    (void)hipFuncSetAttribute((const void*)k_smooth_patches_lds<float, 1, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
-    (void)hipGetLastError();
-}
-
-void factor_patches(tgms_ctx* c) {
-    enable_large_lds(c);
-    factor_rects(c, c->patch, c->nblk, c->pat_nmax, c->pat_bmax, c->patL, c->patS, c->precision ? c->patL32 : nullptr);
-}
-
-template <typename T>
-void smooth(tgms_ctx* c, const T* g, T* z, bool accumulate) {
-    const T* L;
-    T* w;
-    if constexpr (sizeof(T) == 8) {
-        L = (const T*)c->patL;
-        w = (T*)c->patW;
-    } else {
-        L = (const T*)c->patL32;
-        w = (T*)c->patW32;
-    }
-    size_t lds = (size_t)(c->pat_nmax + 128) * sizeof(T);
-    const size_t lds_staged = (size_t)(((c->pat_nmax + 3) & ~3) + 128 + c->pat_fmax + 4) * sizeof(T);
-    const bool staged = lds_staged <= (size_t)c->lds_max;
-    {
-        ProfScope ps(c, PK_SMOOTH);
-        const int mw = btri_width(c->pat_bmax - 1);
-        if (staged) {
-            const int mi = c->pat_bmax - 1;  // interior patch row width
-            if (mi == 19)
-                hipLaunchKernelGGL((k_smooth_patches_lds<T, 19, 17>), dim3(c->nblk), dim3(256), lds_staged, c->stream,
-                                   c->patch, L, g, c->nx, w);
-            else if (mi == 11)
-                hipLaunchKernelGGL((k_smooth_patches_lds<T, 11, 9>), dim3(c->nblk), dim3(256), lds_staged, c->stream,
-                                   c->patch, L, g, c->nx, w);
-            else
-                hipLaunchKernelGGL((k_smooth_patches_lds<T, 1, 1>), dim3(c->nblk), dim3(256), lds_staged, c->stream,
-                                   c->patch, L, g, c->nx, w);
-        } else if (mw == 16)
-            hipLaunchKernelGGL((k_smooth_patches<T, 16>), dim3(c->nblk), dim3(TGMS_WAVE), lds, c->stream, c->patch, L, g,
-                               c->nx, w);
-        else if (mw == 24)
-            hipLaunchKernelGGL((k_smooth_patches<T, 24>), dim3(c->nblk), dim3(TGMS_WAVE), lds, c->stream, c->patch, L, g,
-                               c->nx, w);
-        else
-            hipLaunchKernelGGL((k_smooth_patches<T, 32>), dim3(c->nblk), dim3(TGMS_WAVE), lds, c->stream, c->patch, L, g,
-                               c->nx, w);
-        LAUNCH_OK();
-    }
-    dim3 grid((c->nx + 63) / 64, (c->ny + 3) / 4);
-    hipLaunchKernelGGL((k_smooth_gather<T>), grid, dim3(64, 4), 0, c->stream, c->patch, (const T*)w, c->nx, c->ny,
-                       c->bx, c->by, c->Nx, c->Ny, T(c->eta), z, accumulate ? 1 : 0);
-    LAUNCH_OK();
-}
-template void smooth<double>(tgms_ctx*, const double*, double*, bool);
-template void smooth<float>(tgms_ctx*, const float*, float*, bool);
 
 }  // namespace tgms
