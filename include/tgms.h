@@ -67,6 +67,8 @@ typedef struct {
     double s_scale;    /* H in the 1/H prefactor of the s-form (eq. spectral_eqn);
                           <= 0 selects |K|^(1/2), the coarse block side */
     void* stream;      /* hipStream_t to run on; NULL = the default stream */
+    int graphs;        /* 1: PCG iterations replayed from a captured HIP graph (falls back to
+                          direct launches if capture fails); 0: every kernel launched directly */
 } tgms_options;
 
 typedef struct {
@@ -77,9 +79,12 @@ typedef struct {
     double t_setup_ms;    /* device time of tgms_setup (all phases) */
     double t_snap_ms, t_eig_ms, t_coarse_ms, t_smoother_ms;  /* setup phases */
     int lds_max;          /* LDS bytes per workgroup the device allows (picks the smoother kernel) */
+    int pcg_graph;        /* last solve: 0 kernels launched directly, 1 iterations replayed from a
+                             HIP graph, 2 the same with event timing recorded inside the graph */
 } tgms_info_t;
 
-/* Paper defaults: eta 0.2, overlap 2, FP64, s_scale = |K|^(1/2), default stream. */
+/* Paper defaults: eta 0.2, overlap 2, FP64, s_scale = |K|^(1/2), default stream,
+ * graph replay on. */
 void tgms_default_options(tgms_options* opt);
 
 /*
@@ -89,8 +94,10 @@ void tgms_default_options(tgms_options* opt);
  * coarse operator and its FP64 Cholesky factorisation, the smoother patch
  * factorisations (K_i^+), and the coarse RT0 operator used by preprocessing.
  *   kappa  device, nx*ny doubles, permeability per cell (> 0, finite).
- * Returns TGMS_E_INVAL for bad sizes or permeability, TGMS_E_UNSUPPORTED
- * if a block or patch is wider than 62 cells or bx, by < 2.
+ * Returns TGMS_E_INVAL for bad sizes, tolerance, eta, overlap or permeability;
+ * TGMS_E_UNSUPPORTED for blocks smaller than 3 x 3 cells, fewer than 2 x 2
+ * blocks, an overlap not smaller than the block, blocks wider than 64 cells or
+ * smoother patches (block + 2 overlap, clipped to D) wider than 33 cells.
  * On success *out owns all device workspaces until tgms_destroy.
  */
 tgms_status tgms_setup(const tgms_grid* grid, const double* kappa, double eig_tol,

@@ -7,12 +7,32 @@ and to its cells.  With zero flux on the subdomain boundary the pressure is
 determined up to a constant; one Lagrange multiplier enforcing a zero cell
 sum removes that null space (the '+1' in the paper's DOF counts of section 6
 is this multiplier).  The bordered system is factorised once by SuperLU.
+
+The paper solves every subproblem with a direct solver.  SuperLU's pivoting on
+these saddle matrices (mass entries spanning the permeability contrast, zero
+pressure block) leaves relative errors up to ~1e-9 at contrast 1e6, so every
+solve here takes one step of iterative refinement with the same factors
+(x <- x + K^{-1}(b - K x)), which brings it to FP64 round-off.
 """
 from __future__ import annotations
 
 import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
+
+
+class RefinedLU:
+    """SuperLU factorisation of a sparse matrix K with one refinement step per solve."""
+
+    def __init__(self, K: sp.spmatrix):
+        self.K = sp.csr_matrix(K)
+        self.lu = spla.splu(sp.csc_matrix(K))
+        self.shape = K.shape
+
+    def solve(self, b: np.ndarray) -> np.ndarray:
+        b = np.asarray(b, dtype=np.float64)
+        x = self.lu.solve(b)
+        return x + self.lu.solve(b - self.K @ x)
 
 
 class BorderedSaddle:
@@ -27,7 +47,7 @@ class BorderedSaddle:
         one = sp.csr_matrix(np.ones((ncl, 1)))
         K = sp.bmat([[Aff, Bcf.T, None], [Bcf, None, one], [None, one.T, None]], format="csc")
         self.nfl, self.ncl = nfl, ncl
-        self.lu = spla.splu(K)
+        self.lu = RefinedLU(K)
 
     def solve(self, rhs_f: np.ndarray, rhs_c: np.ndarray):
         """Return (velocity on self.faces, pressure multiplier p' on self.cells)."""

@@ -34,7 +34,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from .discretization import Grid2D, div_matrix, mass_matrix
-from .local import BorderedSaddle
+from .local import BorderedSaddle, RefinedLU
 from .spectral import block_rect, face_geometry, pencil, select, snapshots
 
 
@@ -77,7 +77,7 @@ def pinned_cell_laplacian(BI):
     which keeps the factorisation sparse.
     """
     L = (BI @ BI.T).tocsc()
-    lu = spla.splu(L[:-1, :-1].tocsc())
+    lu = RefinedLU(L[:-1, :-1])
 
     def solve(b):
         q = np.zeros(L.shape[0])
@@ -92,7 +92,7 @@ def bordered_dense_or_sparse(Ah, Bh):
     one = sp.csr_matrix(np.ones((m, 1)))
     K = sp.bmat([[sp.csr_matrix(Ah), sp.csr_matrix(Bh).T, None],
                  [sp.csr_matrix(Bh), None, one], [None, one.T, None]], format="csc")
-    return spla.splu(K), n, m
+    return RefinedLU(K), n, m
 
 
 class OracleSolver:
@@ -300,7 +300,7 @@ def exact_solve(g: Grid2D, kappa, F, g_full=None):
     K = sp.bmat([[AII, BI[:-1].T], [BI[:-1], None]], format="csc")
     rhs_f = -(A @ gb)[I]
     rhs_c = (np.asarray(F, dtype=np.float64).ravel() - B @ gb)[:-1]
-    sol = spla.splu(K).solve(np.concatenate([rhs_f, rhs_c]))
+    sol = RefinedLU(K).solve(np.concatenate([rhs_f, rhs_c]))
     u = gb.copy()
     u[I] = sol[: I.size]
     pprime = np.concatenate([sol[I.size:], [0.0]])

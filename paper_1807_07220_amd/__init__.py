@@ -34,7 +34,8 @@ class Solver:
     """Setup on construction; see include/tgms.h for the definitions."""
 
     def __init__(self, kappa: torch.Tensor, bx: int, by: int, eig_tol: float, eta: float = 0.2, overlap: int = 2,
-                 precision: str = "fp64", s_scale: float = 0.0, stream: torch.cuda.Stream | None = None):
+                 precision: str = "fp64", s_scale: float = 0.0, stream: torch.cuda.Stream | None = None,
+                 graphs: bool = True):
         lib = load()
         if kappa.dim() != 2:
             raise ValueError("kappa must be (ny, nx)")
@@ -47,6 +48,7 @@ class Solver:
         opt.eta, opt.overlap, opt.s_scale = float(eta), int(overlap), float(s_scale)
         opt.precision = {"fp64": 0, "mixed": 1}[precision]
         opt.stream = ctypes.c_void_p(self.stream.cuda_stream)
+        opt.graphs = 1 if graphs else 0
         grid = Grid(self.nx, self.ny, self.bx, self.by)
         handle = ctypes.c_void_p()
         kappa = kappa.contiguous()

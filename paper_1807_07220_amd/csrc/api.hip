@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <set>
 
 #include "common.h"
 #include "band.h"
@@ -28,6 +29,7 @@ static hipEvent_t take_event(tgms_ctx* c) {
     return c->ev_pool[c->ev_used++];
 }
 
+// Event pairs around launches when profiling (launches are then never captured).
 ProfScope::ProfScope(tgms_ctx* ctx, int kid) : c(ctx), id(kid) {
     if (!c->prof) return;
     e1 = take_event(c);
@@ -38,8 +40,15 @@ ProfScope::~ProfScope() {
     if (!c->prof || !e1) return;
     hipEvent_t e2 = take_event(c);
     (void)hipEventRecord(e2, c->stream);
-    c->prof_rec.push_back({id, {e1, e2}});
+    c->prof_rec.push_back({id, c->prof_iter, e1, e2});
 }
+
+// order the library stream after the work queued on the caller's stream
+void enter(tgms_ctx* c) {
+    HIP_OK(hipEventRecord(c->ev_enter, c->user_stream));
+    HIP_OK(hipStreamWaitEvent(c->stream, c->ev_enter, 0));
+}
+
 }  // namespace tgms
 
 namespace {
@@ -127,34 +136,54 @@ const T* cell_a(tgms_ctx* c) {
         return c->a32;
 }
 
-// z = B_TG g : one pre-smoothing, coarse correction, one post-smoothing, residual recomputed after each.
+// z = B_TG g (paper section 5): pre-smoothing, coarse correction, post-smoothing,
+// with the residual recomputed after each.  g: the right-hand side in the
+// preconditioner's precision (T); z: FP64 output.  With dots, the final gather
+// also forms the PCG scalars from g64 (and gold for the flexible variant).
 template <typename T>
-void twogrid(tgms_ctx* c, const T* g, T* z, T* t) {
-    tgms::smooth<T>(c, g, z, false);
-    tgms::residual_K<T>(c, g, z, t, cell_a<T>(c));
-    tgms::coarse_apply<T>(c, t, z, true);
-    tgms::residual_K<T>(c, g, z, t, cell_a<T>(c));
-    tgms::smooth<T>(c, t, z, true);
+void twogrid(tgms_ctx* c, const T* g, double* z, const double* g64, const double* gold, bool dots, bool first) {
+    const double* sc = dots ? c->sc : nullptr;
+    T *w, *z1, *t;
+    if constexpr (sizeof(T) == 8) {
+        w = (T*)c->patW;
+        z1 = (T*)c->vt2;
+        t = (T*)c->vt;
+    } else {
+        w = (T*)c->patW32;
+        z1 = (T*)c->fz;
+        t = (T*)c->ft;
+    }
+    tgms::smooth_patches<T>(c, g, sc);
+    tgms::gather_res<T>(c, w, g, cell_a<T>(c), z1, t, sc);
+    tgms::coarse_apply<T>(c, t, z1, true, sc);
+    tgms::residual<T>(c, z1, g, t, cell_a<T>(c), sc);
+    tgms::smooth_patches<T>(c, t, sc);
+    tgms::gather_final<T>(c, w, z1, z, g64, gold, dots, first);
 }
 
+// probes: which = 0 smoother, 1 coarse correction, 2 two-grid; g, z FP64 vertex arrays
 void precond(tgms_ctx* c, int which, const double* g, double* z) {
     const long long nv = (long long)c->nx * c->ny;
     if (c->precision == 0) {
-        if (which == 0)
-            tgms::smooth<double>(c, g, z, false);
-        else if (which == 1)
-            tgms::coarse_apply<double>(c, g, z, false);
-        else
-            twogrid<double>(c, g, z, c->vt);
+        if (which == 0) {
+            tgms::smooth_patches<double>(c, g, nullptr);
+            tgms::gather_final<double>(c, c->patW, nullptr, z, nullptr, nullptr, false, false);
+        } else if (which == 1) {
+            tgms::coarse_apply<double>(c, g, z, false, nullptr);
+        } else {
+            twogrid<double>(c, g, z, nullptr, nullptr, false, false);
+        }
     } else {
         tgms::cast_d2f(c, nv, g, c->fg);
-        if (which == 0)
-            tgms::smooth<float>(c, c->fg, c->fz, false);
-        else if (which == 1)
-            tgms::coarse_apply<float>(c, c->fg, c->fz, false);
-        else
-            twogrid<float>(c, c->fg, c->fz, c->ft);
-        tgms::cast_f2d(c, nv, c->fz, z);
+        if (which == 0) {
+            tgms::smooth_patches<float>(c, c->fg, nullptr);
+            tgms::gather_final<float>(c, c->patW32, nullptr, z, nullptr, nullptr, false, false);
+        } else if (which == 1) {
+            tgms::coarse_apply<float>(c, c->fg, c->fz, false, nullptr);
+            tgms::cast_f2d(c, nv, c->fz, z);
+        } else {
+            twogrid<float>(c, c->fg, z, nullptr, nullptr, false, false);
+        }
     }
 }
 
@@ -312,7 +341,13 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
     (void)ey;
     auto* c = new tgms_ctx();
     try {
-        c->stream = (hipStream_t)o.stream;
+        // All work runs on a stream of the library's own (default priority); each call
+        // first waits for what the caller queued on its stream (NULL: the null stream)
+        // and returns after synchronising, so results are visible on every stream.
+        c->user_stream = (hipStream_t)o.stream;
+        HIP_OK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        HIP_OK(hipEventCreateWithFlags(&c->ev_enter, hipEventDisableTiming));
+        tgms::enter(c);
         c->nx = nx; c->ny = ny; c->bx = bx; c->by = by;
         c->Nx = nx / bx; c->Ny = ny / by; c->nblk = c->Nx * c->Ny;
         c->nex = (c->Nx - 1) * c->Ny;
@@ -322,6 +357,7 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         c->sx = 1.0 / c->hy; c->sy = 1.0 / c->hx;
         c->H = o.s_scale > 0 ? o.s_scale : std::sqrt(bx * c->hx * by * c->hy);
         c->eta = o.eta; c->tol = eig_tol; c->overlap = o.overlap; c->precision = o.precision ? 1 : 0;
+        c->graph_failed = o.graphs == 0;  // never capture: launch every kernel directly
         c->nfx = (nx + 1) * ny; c->nfy = nx * (ny + 1); c->nf = c->nfx + c->nfy;
         c->nfk = by * (bx + 1) + (by + 1) * bx;
         c->ncol = 4 * c->jmax;
@@ -413,6 +449,7 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
             Timer t(c->stream);
             c->patch_h.resize(c->nblk);
             long long off = 0, voff = 0;
+            std::set<int> widths;
             for (int J = 0; J < c->Ny; ++J)
                 for (int I = 0; I < c->Nx; ++I) {
                     Rect& r = c->patch_h[J * c->Nx + I];
@@ -428,7 +465,11 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                     voff += n;
                     c->pat_nmax = std::max(c->pat_nmax, n);
                     c->pat_bmax = std::max(c->pat_bmax, m + 1);
+                    widths.insert(m);
                 }
+            // the kernels take fixed-width paths for up to two distinct row widths
+            c->pat_m1 = *widths.rbegin();
+            c->pat_m2 = widths.size() == 1 ? c->pat_m1 : widths.size() == 2 ? *widths.begin() : -1;
             c->pat_pool = off;
             c->pat_vpool = voff;
             c->patch = c->alloc<Rect>(c->nblk);
@@ -477,10 +518,11 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         c->ft2 = c->alloc<float>(nvtx);
         c->fbar = c->alloc<double>(c->nf); c->fu = c->alloc<double>(c->nf); c->fF = c->alloc<double>(c->nf);
         c->cellw = c->alloc<double>(ncell); c->cellw2 = c->alloc<double>(std::max<long long>(ncell, 2 * c->nblk));
-        c->red = c->alloc<double>(4 * 512 + 16);
         c->blkbuf = c->alloc<double>(2 * (size_t)c->nblk);
-        c->sc = c->alloc<double>(16);
-        HIP_OK(hipHostMalloc((void**)&c->red_h, 16 * sizeof(double), hipHostMallocDefault));
+        c->sc = c->alloc<double>(SC_COUNT);
+        c->part = c->alloc<double>(3 * (size_t)tgms::pcg_tiles(c));
+        c->vp1 = c->alloc<double>(nvtx);
+        HIP_OK(hipHostMalloc((void**)&c->red_h, SC_COUNT * sizeof(double), hipHostMallocDefault));
         HIP_OK(hipStreamSynchronize(c->stream));
         c->t_setup_ms = total.ms();
         *out = c;
@@ -494,6 +536,7 @@ void solve_impl(tgms_ctx* c, const double* F, const double* g_bnd, double rtol, 
                 int* iters, double* relres, tgms_status* st) {
     if (!c || !F || !u) throw TgmsError{TGMS_E_INVAL, "null argument"};
     if (!(rtol >= 0) || maxit < 0) throw TgmsError{TGMS_E_INVAL, "bad rtol or maxit"};
+    tgms::enter(c);
     const long long nv = (long long)c->nx * c->ny;
     // Step 1: preprocessing
     tgms::preprocess(c, F, g_bnd, c->fbar, c->cellw2);
@@ -501,9 +544,13 @@ void solve_impl(tgms_ctx* c, const double* F, const double* g_bnd, double rtol, 
     tgms::bnd_faces(c, g_bnd, c->fF);
     tgms::axpy(c, c->nf, 1.0, c->fbar, c->fF);
     tgms::curlT_A_faces(c, c->fF, c->vg, -1.0);
-    // Step 3: PCG in stream-function coordinates, scalars kept on the device; one
-    // iteration is captured once as a HIP graph and replayed (launched directly when
-    // capture is unavailable).  The host reads only |z_k|/|z_0| and the breakdown flag.
+    // Step 3: PCG in stream-function coordinates with its scalars on the device.
+    // Two iterations (the search direction alternates between two buffers) are
+    // captured once as a HIP graph and replayed; the kernels of iterations queued
+    // after convergence return at once, so the host reads the scalars only every
+    // four iterations.  With profiling on, the kernels are launched directly (four
+    // iterations per check as well) and each event pair is tagged with its
+    // iteration, so that launches of iterations after convergence are not counted.
     const bool flexible = c->precision != 0;
     if (c->hist_cap < maxit + 2) {
         c->hist = c->alloc<double>(2 * (size_t)(maxit + 2));
@@ -513,27 +560,39 @@ void solve_impl(tgms_ctx* c, const double* F, const double* g_bnd, double rtol, 
             c->iter_graph = nullptr;
         }
     }
+    const size_t prof_first = c->prof_rec.size(), ev_first = c->ev_used;
     tgms::zero(c, c->vx, sizeof(double) * nv);
-    precond(c, 2, c->vg, c->vz);
-    tgms::pcg_beta(c, c->vg, c->vz, nullptr, c->sc, c->hist, flexible, true);
-    tgms::copy(c, nv, c->vz, c->vp);
-    HIP_OK(hipMemcpyAsync(c->red_h, c->sc, 9 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIP_OK(hipStreamSynchronize(c->stream));
-    const double z0 = std::sqrt(c->red_h[6]);
-    auto iteration = [&]() {
-        tgms::apply_K<double>(c, c->vp, c->vq, c->a);
-        tgms::pcg_alpha(c, c->vp, c->vq, c->sc, c->hist);
-        tgms::pcg_update(c, c->sc, c->vp, c->vq, c->vx, c->vg, flexible ? c->vgold : nullptr);
-        precond(c, 2, c->vg, c->vz);
-        tgms::pcg_beta(c, c->vg, c->vz, flexible ? c->vgold : nullptr, c->sc, c->hist, flexible, false);
-        tgms::pcg_dir(c, c->sc, c->vz, c->vp);
+    tgms::zero(c, c->vp, sizeof(double) * nv);
+    tgms::zero(c, c->vp1, sizeof(double) * nv);
+    for (int k = 0; k < SC_COUNT; ++k) c->red_h[k] = 0.0;
+    c->red_h[SC_RTOL2] = rtol * rtol;
+    c->red_h[SC_MAXIT] = maxit;
+    c->red_h[SC_FLEX] = flexible ? 1.0 : 0.0;
+    HIP_OK(hipMemcpyAsync(c->sc, c->red_h, SC_COUNT * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    // z_0 = B_TG g_0, rho_0 = g.z, |z_0|^2
+    c->prof_iter = 0;
+    if (flexible) {
+        tgms::cast_d2f(c, nv, c->vg, c->fg);
+        twogrid<float>(c, c->fg, c->vz, c->vg, nullptr, true, true);
+    } else {
+        twogrid<double>(c, c->vg, c->vz, c->vg, nullptr, true, true);
+    }
+    auto iteration = [&](const double* pin, double* pout) {
+        tgms::dir_apply(c, c->vz, pin, pout, c->vq);
+        tgms::update(c, pout, c->vq, c->vx, c->vg, flexible ? c->vgold : nullptr, flexible ? c->fg : nullptr);
+        if (flexible)
+            twogrid<float>(c, c->fg, c->vz, c->vg, c->vgold, true, false);
+        else
+            twogrid<double>(c, c->vg, c->vz, c->vg, nullptr, true, false);
     };
-    if (!c->iter_graph && !c->graph_failed && !c->prof && z0 > 0) {
+    const bool use_graph = !c->prof && !c->graph_failed;
+    if (use_graph && !c->iter_graph) {
         hipGraph_t graph = nullptr;
         bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
         if (ok) {
             try {
-                iteration();
+                iteration(c->vp, c->vp1);
+                iteration(c->vp1, c->vp);
             } catch (...) {
                 ok = false;
             }
@@ -549,36 +608,58 @@ void solve_impl(tgms_ctx* c, const double* F, const double* g_bnd, double rtol, 
             (void)hipGetLastError();
         }
     }
+    const bool graph = use_graph && c->iter_graph;
+    c->last_graph = graph ? 1 : 0;
+    auto read_sc = [&]() {
+        HIP_OK(hipMemcpyAsync(c->red_h, c->sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_OK(hipStreamSynchronize(c->stream));
+    };
+    read_sc();
+    int launched = 0;  // iterations queued so far
+    while (c->red_h[SC_DONE] == 0.0) {
+        if (graph) {
+            HIP_OK(hipGraphLaunch(c->iter_graph, c->stream));
+            HIP_OK(hipGraphLaunch(c->iter_graph, c->stream));
+            launched += 4;
+        } else {
+            for (int l = 0; l < 4; ++l) {
+                c->prof_iter = ++launched;
+                if (launched % 2)
+                    iteration(c->vp, c->vp1);
+                else
+                    iteration(c->vp1, c->vp);
+            }
+        }
+        read_sc();
+    }
+    c->prof_iter = -1;
+    if (c->prof) {
+        // keep the timings of the launches that belong to iterations that ran
+        const int ran = (int)c->red_h[SC_IT] + (c->red_h[SC_FLAG] != 0.0 ? 1 : 0);
+        for (size_t k = prof_first; k < c->prof_rec.size(); ++k) {
+            const auto& r = c->prof_rec[k];
+            if (r.iter > ran) continue;
+            float ms = 0.f;
+            HIP_OK(hipEventElapsedTime(&ms, r.e1, r.e2));
+            c->prof_acc_ms[r.id] += ms;
+            c->prof_acc_n[r.id] += 1;
+        }
+        c->prof_rec.resize(prof_first);
+        c->ev_used = ev_first;
+    }
+    const int it = (int)c->red_h[SC_IT];
+    const double rel = std::sqrt(c->red_h[SC_REL2]);
+    *st = TGMS_OK;
+    if (c->red_h[SC_FLAG] != 0.0)
+        *st = TGMS_E_BREAKDOWN;
+    else if (c->red_h[SC_Z02] > 0.0 && rel > rtol)
+        *st = TGMS_E_NOTCONV;
     c->alphas.clear();
     c->betas.clear();
-    int it = 0;
-    double rel = 1.0;
-    *st = TGMS_OK;
-    if (z0 > 0) {
-        while (true) {
-            if (it >= maxit) {
-                *st = TGMS_E_NOTCONV;
-                break;
-            }
-            if (c->iter_graph && !c->prof)
-                HIP_OK(hipGraphLaunch(c->iter_graph, c->stream));
-            else
-                iteration();
-            HIP_OK(hipMemcpyAsync(c->red_h, c->sc, 9 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-            HIP_OK(hipStreamSynchronize(c->stream));
-            ++it;
-            if (c->red_h[7] != 0.0) {
-                *st = TGMS_E_BREAKDOWN;
-                break;
-            }
-            rel = std::sqrt(c->red_h[5]);
-            if (rel <= rtol) break;
-        }
+    if (it > 0) {
         std::vector<double> h(2 * (size_t)it);
-        if (it > 0) {
-            HIP_OK(hipMemcpyAsync(h.data(), c->hist, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));
-            HIP_OK(hipStreamSynchronize(c->stream));
-        }
+        HIP_OK(hipMemcpyAsync(h.data(), c->hist, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));
+        HIP_OK(hipStreamSynchronize(c->stream));
         for (int k = 0; k < it; ++k) {
             c->alphas.push_back(h[2 * k]);
             if (k + 1 < it) c->betas.push_back(h[2 * k + 1]);
@@ -607,6 +688,7 @@ void tgms_default_options(tgms_options* opt) {
     opt->precision = 0;
     opt->s_scale = 0.0;
     opt->stream = nullptr;
+    opt->graphs = 1;
 }
 
 tgms_status tgms_setup(const tgms_grid* grid, const double* kappa, double eig_tol, const tgms_options* opt,
@@ -639,6 +721,7 @@ tgms_status tgms_info(const tgms_ctx* c, tgms_info_t* info) {
     info->t_coarse_ms = c->t_coarse_ms;
     info->t_smoother_ms = c->t_smoother_ms;
     info->lds_max = c->lds_max;
+    info->pcg_graph = c->last_graph;
     return TGMS_OK;
 }
 
@@ -681,6 +764,10 @@ tgms_status tgms_profile(tgms_ctx* c, int enable) {
         c->prof = enable != 0;
         c->prof_rec.clear();
         c->ev_used = 0;
+        for (int k = 0; k < tgms::PK_COUNT; ++k) {
+            c->prof_acc_ms[k] = 0.0;
+            c->prof_acc_n[k] = 0;
+        }
     });
 }
 
@@ -691,12 +778,12 @@ tgms_status tgms_profile_get(tgms_ctx* c, int kernel, int* launches, double* tot
     }
     return guarded([&] {
         HIP_OK(hipStreamSynchronize(c->stream));
-        int n = 0;
-        double t = 0.0;
+        int n = c->prof_acc_n[kernel];
+        double t = c->prof_acc_ms[kernel];
         for (auto& r : c->prof_rec) {
-            if (r.first != kernel) continue;
+            if (r.id != kernel) continue;
             float ms = 0.f;
-            HIP_OK(hipEventElapsedTime(&ms, r.second.first, r.second.second));
+            HIP_OK(hipEventElapsedTime(&ms, r.e1, r.e2));
             t += ms;
             ++n;
         }
@@ -713,6 +800,8 @@ void tgms_destroy(tgms_ctx* c) {
     if (c->iter_graph) (void)hipGraphExecDestroy(c->iter_graph);
     for (auto& b : c->owned) (void)hipFree(b.p);
     if (c->red_h) (void)hipHostFree(c->red_h);
+    if (c->ev_enter) (void)hipEventDestroy(c->ev_enter);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
 
@@ -724,6 +813,7 @@ tgms_status tgms_apply_A(tgms_ctx* c, const double* x, double* y) {
         return TGMS_E_INVAL;
     }
     return guarded([&] {
+        tgms::enter(c);
         tgms::faces_A_probe(c, x, y);
         HIP_OK(hipStreamSynchronize(c->stream));
     });
@@ -735,6 +825,7 @@ tgms_status tgms_preprocess(tgms_ctx* c, const double* F, const double* g_bnd, d
         return TGMS_E_INVAL;
     }
     return guarded([&] {
+        tgms::enter(c);
         tgms::preprocess(c, F, g_bnd, vbar, c->cellw2);
         HIP_OK(hipStreamSynchronize(c->stream));
     });
@@ -746,8 +837,9 @@ tgms_status tgms_apply_precond(tgms_ctx* c, int which, const double* r, double* 
         return TGMS_E_INVAL;
     }
     return guarded([&] {
-        tgms::curlT(c, r, c->vt2);
-        precond(c, which, c->vt2, c->vq);
+        tgms::enter(c);
+        tgms::curlT(c, r, c->vgold);
+        precond(c, which, c->vgold, c->vq);
         tgms::curl_add(c, c->vq, nullptr, z);
         HIP_OK(hipStreamSynchronize(c->stream));
     });

@@ -92,7 +92,9 @@ struct tgms_ctx {
     int nx, ny, bx, by, Nx, Ny, nblk, ne, nex, jmax;
     double hx, hy, sx, sy, H, eta, tol;
     int overlap, precision;
-    hipStream_t stream;
+    hipStream_t stream = nullptr;       // the library's own stream (graph capture needs a real stream)
+    hipStream_t user_stream = nullptr;  // the caller's stream: work starts after what is queued there
+    hipEvent_t ev_enter = nullptr;
     int nfx, nfy, nf;  // full-face counts
     // cell data
     double* kinv = nullptr;  // kappa^{-1}
@@ -106,6 +108,7 @@ struct tgms_ctx {
     std::vector<Rect> patch_h;
     Rect* patch = nullptr;
     int pat_bmax = 0, pat_nmax = 0;
+    int pat_m1 = 0, pat_m2 = 0;  // the row widths present among the patches (m1 >= m2)
     long long pat_fmax = 0;   // largest patch factor (elements)
     int lds_max = 65536;      // device limit on LDS per workgroup (bytes)
     long long pat_pool = 0, pat_vpool = 0;
@@ -159,19 +162,28 @@ struct tgms_ctx {
     float *fg = nullptr, *fz = nullptr, *ft = nullptr, *ft2 = nullptr;
     double *fbar = nullptr, *fu = nullptr, *fF = nullptr, *cellw = nullptr, *cellw2 = nullptr;
     double* blkbuf = nullptr; // 2 * nblk
-    double* red = nullptr;    // reduction scratch
     double* red_h = nullptr;  // pinned host
-    double* sc = nullptr;     // device PCG scalars (see k_grid.hip)
+    double* sc = nullptr;     // device PCG scalars (SC_* below)
     double* hist = nullptr;   // device alpha/beta history
     int hist_cap = 0;
-    hipGraphExec_t iter_graph = nullptr;  // one captured PCG iteration
+    double* part = nullptr;   // per-workgroup partial sums of the fused PCG kernels
+    double* vp1 = nullptr;    // second search-direction buffer (p alternates between vp and vp1)
+    hipGraphExec_t iter_graph = nullptr;  // two captured PCG iterations
     bool graph_failed = false;
-    int red_blocks = 0;
+    int last_graph = 0;  // how the last solve ran its iterations: 0 direct launches, 1 graph
     // per-kernel event timing (tgms_profile)
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
-    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_rec;
+    // (kernel, iteration tag, start, stop); tag -1: outside a PCG iteration
+    struct ProfRec {
+        int id, iter;
+        hipEvent_t e1, e2;
+    };
+    std::vector<ProfRec> prof_rec;
+    int prof_iter = -1;  // tag of the launches being recorded
+    double prof_acc_ms[8] = {0};
+    int prof_acc_n[8] = {0};
     // diagnostics
     std::vector<double> alphas, betas;
     double t_setup_ms = 0, t_snap_ms = 0, t_eig_ms = 0, t_coarse_ms = 0, t_smoother_ms = 0;
@@ -189,6 +201,11 @@ struct tgms_ctx {
 };
 
 // ---------------------------------------------------------------- launchers
+// device PCG scalars: rho, p.q, alpha, beta, |z|^2, |z|^2/|z0|^2, |z0|^2, breakdown flag,
+// iteration count, done flag, rtol^2, maxit, flexible (1) or Fletcher-Reeves (0)
+enum { SC_RHO = 0, SC_PQ, SC_ALPHA, SC_BETA, SC_ZN2, SC_REL2, SC_Z02, SC_FLAG, SC_IT, SC_DONE, SC_RTOL2, SC_MAXIT,
+       SC_FLEX, SC_COUNT };
+
 namespace tgms {
 enum ProfKernel { PK_SMOOTH = 0, PK_APPLYK = 1, PK_RESTRICT = 2, PK_PROLONG = 3, PK_COUNT = 4 };
 // record an event pair around one launch when profiling is on
@@ -199,28 +216,16 @@ struct ProfScope {
     ProfScope(tgms_ctx* ctx, int kid);
     ~ProfScope();
 };
+void enter(tgms_ctx* c);
 // grid / vector kernels (k_grid.hip)
 void cell_weights(tgms_ctx* c, const double* kappa, int* bad);
-template <typename T>
-void apply_K(tgms_ctx* c, const T* psi, T* out, const T* a);
-template <typename T>
-void residual_K(tgms_ctx* c, const T* g, const T* psi, T* out, const T* a);  // out = g - K psi
 void faces_A(tgms_ctx* c, const double* u, double* out);                    // A u on interior faces
 void faces_A_probe(tgms_ctx* c, const double* u, double* out);              // same, boundary inputs ignored
 void curlT_A_faces(tgms_ctx* c, const double* u, double* g, double scale);  // g = scale * C^T A u
 void curl_add(tgms_ctx* c, const double* psi, const double* base, double* u); // u = base + C psi
 void curlT(tgms_ctx* c, const double* u, double* g);
-double dot(tgms_ctx* c, const double* x, const double* y, long long n);
-void dot3(tgms_ctx* c, const double* g, const double* z, const double* gold, double out[3]);
-double curl_norm2(tgms_ctx* c, const double* psi);
-void pcg_alpha(tgms_ctx* c, const double* p, const double* q, double* sc, double* hist);
-void pcg_beta(tgms_ctx* c, const double* g, const double* z, const double* gold, double* sc, double* hist,
-              bool flexible, bool first);
-void pcg_update(tgms_ctx* c, const double* sc, const double* p, const double* q, double* x, double* g, double* gold);
-void pcg_dir(tgms_ctx* c, const double* sc, const double* z, double* p);
 void copy(tgms_ctx* c, long long n, const double* x, double* y);
 void axpy(tgms_ctx* c, long long n, double a, const double* x, double* y);        // y += a x
-void xpay(tgms_ctx* c, long long n, const double* x, double b, double* y);        // y = x + b y
 void cast_d2f(tgms_ctx* c, long long n, const double* x, float* y);
 void cast_f2d(tgms_ctx* c, long long n, const float* x, double* y);
 void zero(tgms_ctx* c, void* p, size_t bytes);
@@ -228,7 +233,18 @@ void zero(tgms_ctx* c, void* p, size_t bytes);
 void factor_blocks(tgms_ctx* c);
 void factor_patches(tgms_ctx* c);
 template <typename T>
-void smooth(tgms_ctx* c, const T* g, T* z, bool accumulate);  // z (+)= S g
+void smooth_patches(tgms_ctx* c, const T* g, const double* sc);  // local solves of S g into the patch pool
+// fused PCG / two-grid kernels (k_pcg.hip); sc: skip when the done flag is set (may be null)
+unsigned pcg_tiles(tgms_ctx* c);
+void dir_apply(tgms_ctx* c, const double* z, const double* pin, double* pout, double* q);
+void update(tgms_ctx* c, const double* p, const double* q, double* x, double* g, double* gold, float* g32);
+template <typename T>
+void gather_res(tgms_ctx* c, const T* w, const T* g, const T* a, T* z, T* t, const double* sc);
+template <typename T>
+void gather_final(tgms_ctx* c, const T* w, const T* zin, double* zout, const double* g, const double* gold,
+                  bool with_dots, bool first);
+template <typename T>
+void residual(tgms_ctx* c, const T* z, const T* g, T* t, const T* a, const double* sc);
 // setup (k_setup.hip)
 void snapshots(tgms_ctx* c);
 void gram(tgms_ctx* c);
@@ -237,11 +253,11 @@ void coarse_local_run(tgms_ctx* c, const double* Tm, const int* zc);
 void coarse_rt0_blocks(tgms_ctx* c);
 // coarse apply (k_setup.hip)
 template <typename T>
-void coarse_apply(tgms_ctx* c, const T* g, T* z, bool accumulate);
+void coarse_apply(tgms_ctx* c, const T* g, T* z, bool accumulate, const double* sc);
 // dense (k_dense.hip)
 void dense_spd_inverse(tgms_ctx* c, double* A, int n);
 template <typename T>
-void symv(tgms_ctx* c, const T* A, int n, const T* x, T* y);
+void symv(tgms_ctx* c, const T* A, int n, const T* x, T* y, const double* sc);
 void gemm(tgms_ctx* c, int transA, int transB, int M, int N, int K, double alpha, const double* A, int lda,
           const double* B, int ldb, double beta, double* C, int ldc);
 // preprocessing and pressure (k_pre.hip)

@@ -159,7 +159,9 @@ __global__ void k_copy_block(const double* __restrict__ src, int lds, double* __
 
 // y = tril(B) x (part 0) or y = triu(B) x (part 1): one wavefront per row.
 template <typename T>
-__global__ void k_trimv(const T* __restrict__ B, int n, const T* __restrict__ x, T* __restrict__ y, int part) {
+__global__ void k_trimv(const T* __restrict__ B, int n, const T* __restrict__ x, T* __restrict__ y, int part,
+                        const double* __restrict__ sc) {
+    if (sc != nullptr && sc[SC_DONE] != 0.0) return;
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= n) return;
@@ -263,19 +265,19 @@ void dense_spd_inverse(tgms_ctx* c, double* A, int n) {
 
 // y = A^{-1} x with A^{-1} held as B = tril(X) + triu(X^T, 1); tmp has n entries.
 template <typename T>
-void symv(tgms_ctx* c, const T* B, int n, const T* x, T* y) {
+void symv(tgms_ctx* c, const T* B, int n, const T* x, T* y, const double* sc) {
     if (n <= 0) return;
     T* tmp;
     if constexpr (sizeof(T) == 8)
         tmp = (T*)c->cvec2;
     else
         tmp = (T*)c->cvec2_32;
-    hipLaunchKernelGGL((k_trimv<T>), dim3((n + 3) / 4), dim3(256), 0, c->stream, B, n, x, tmp, 0);
+    hipLaunchKernelGGL((k_trimv<T>), dim3((n + 3) / 4), dim3(256), 0, c->stream, B, n, x, tmp, 0, sc);
     LAUNCH_OK();
-    hipLaunchKernelGGL((k_trimv<T>), dim3((n + 3) / 4), dim3(256), 0, c->stream, B, n, (const T*)tmp, y, 1);
+    hipLaunchKernelGGL((k_trimv<T>), dim3((n + 3) / 4), dim3(256), 0, c->stream, B, n, (const T*)tmp, y, 1, sc);
     LAUNCH_OK();
 }
-template void symv<double>(tgms_ctx*, const double*, int, const double*, double*);
-template void symv<float>(tgms_ctx*, const float*, int, const float*, float*);
+template void symv<double>(tgms_ctx*, const double*, int, const double*, double*, const double*);
+template void symv<float>(tgms_ctx*, const float*, int, const float*, float*, const double*);
 
 }  // namespace tgms

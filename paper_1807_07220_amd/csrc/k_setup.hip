@@ -440,9 +440,12 @@ __global__ void k_rt0_blocks(BlockGeom G, const double* __restrict__ a, double* 
 }
 
 // ---- coarse apply in stream-function coordinates ----
+// Restriction W^T g per block into cy (one workgroup per block).
 template <typename T>
 __global__ void k_coarse_restrict(const T* __restrict__ W, int mu, const int* __restrict__ nunk,
-                                  const T* __restrict__ g, int nx, int bx, int by, int Nx, T* __restrict__ cy) {
+                                  const T* __restrict__ g, int nx, int bx, int by, int Nx, T* __restrict__ cy,
+                                  const double* __restrict__ sc) {
+    if (sc != nullptr && sc[SC_DONE] != 0.0) return;
     __shared__ T part[4][64];
     const int blk = blockIdx.x, I = blk % Nx, J = blk / Nx;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -462,9 +465,11 @@ __global__ void k_coarse_restrict(const T* __restrict__ W, int mu, const int* __
     }
 }
 
+// each coarse unknown: the sum of its contributions from the blocks (fixed order)
 template <typename T>
 __global__ void k_coarse_accum(const int* __restrict__ ptr, const int* __restrict__ ent, const T* __restrict__ cy,
-                               int ncs, T* __restrict__ c) {
+                               int ncs, T* __restrict__ c, const double* __restrict__ sc) {
+    if (sc != nullptr && sc[SC_DONE] != 0.0) return;
     const int u = blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= ncs) return;
     T s = T(0);
@@ -475,7 +480,8 @@ __global__ void k_coarse_accum(const int* __restrict__ ptr, const int* __restric
 template <typename T>
 __global__ void k_coarse_prolong(const T* __restrict__ W, int mu, const int* __restrict__ unk,
                                  const int* __restrict__ nunk, const T* __restrict__ c, int nx, int bx, int by,
-                                 int Nx, T* __restrict__ z, int accumulate) {
+                                 int Nx, T* __restrict__ z, int accumulate, const double* __restrict__ sc) {
+    if (sc != nullptr && sc[SC_DONE] != 0.0) return;
     const int blk = blockIdx.x, I = blk % Nx, J = blk / Nx;
     const int nown = bx * by, nu = nunk[blk];
     const T* Wb = W + (long long)blk * nown * mu;
@@ -570,48 +576,40 @@ void coarse_rt0_blocks(tgms_ctx* c) {
 }
 
 template <typename T>
-void coarse_apply(tgms_ctx* c, const T* g, T* z, bool accumulate) {
+void coarse_apply(tgms_ctx* c, const T* g, T* z, bool accumulate, const double* sc) {
     const T* W;
     const T* Ainv;
     T* cy;
     T* c1;
-    T* c2;
     if constexpr (sizeof(T) == 8) {
         W = (const T*)c->W;
         Ainv = (const T*)c->Ac;
         cy = (T*)c->cy;
         c1 = (T*)c->cvec;
-        c2 = (T*)c->cvec;
     } else {
         W = (const T*)c->W32;
         Ainv = (const T*)c->Ac32;
         cy = (T*)c->cy32;
         c1 = (T*)c->cvec32;
-        c2 = (T*)c->cvec32;
     }
     {
-    ProfScope ps(c, PK_RESTRICT);
-    hipLaunchKernelGGL((k_coarse_restrict<T>), dim3(c->nblk), dim3(256), 0, c->stream, W, c->mu, c->blk_nu, g, c->nx,
-                       c->bx, c->by, c->Nx, cy);
-    LAUNCH_OK();
+        ProfScope ps(c, PK_RESTRICT);
+        hipLaunchKernelGGL((k_coarse_restrict<T>), dim3(c->nblk), dim3(256), 0, c->stream, W, c->mu, c->blk_nu, g,
+                           c->nx, c->bx, c->by, c->Nx, cy, sc);
+        LAUNCH_OK();
     }
-    hipLaunchKernelGGL((k_coarse_accum<T>), dim3((c->ncs + 255) / 256), dim3(256), 0, c->stream, c->unk_ptr,
-                       c->unk_ent, (const T*)cy, c->ncs, c1);
+    hipLaunchKernelGGL((k_coarse_accum<T>), dim3((c->ncs + 255) / 256), dim3(256), 0, c->stream, c->unk_ptr, c->unk_ent,
+                       (const T*)cy, c->ncs, c1, sc);
     LAUNCH_OK();
-    // c2 = A^{-1} c1 : symv uses cvec2 as its temporary, result written back into c1's storage
-    T* res;
-    if constexpr (sizeof(T) == 8)
-        res = (T*)c->cvec + c->ncs;
-    else
-        res = (T*)c->cvec32 + c->ncs;
-    symv<T>(c, Ainv, c->ncs, c1, res);
-    (void)c2;
+    // the coarse solve A^{-1} c1 (two triangular products); result after c1 in the same buffer
+    T* res = c1 + c->ncs;
+    symv<T>(c, Ainv, c->ncs, c1, res, sc);
     ProfScope ps(c, PK_PROLONG);
     hipLaunchKernelGGL((k_coarse_prolong<T>), dim3(c->nblk), dim3(256), 0, c->stream, W, c->mu, c->blk_unk,
-                       c->blk_nu, (const T*)res, c->nx, c->bx, c->by, c->Nx, z, accumulate ? 1 : 0);
+                       c->blk_nu, (const T*)res, c->nx, c->bx, c->by, c->Nx, z, accumulate ? 1 : 0, sc);
     LAUNCH_OK();
 }
-template void coarse_apply<double>(tgms_ctx*, const double*, double*, bool);
-template void coarse_apply<float>(tgms_ctx*, const float*, float*, bool);
+template void coarse_apply<double>(tgms_ctx*, const double*, double*, bool, const double*);
+template void coarse_apply<float>(tgms_ctx*, const float*, float*, bool, const double*);
 
 }  // namespace tgms

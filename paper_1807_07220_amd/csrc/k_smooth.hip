@@ -6,7 +6,8 @@
 // patch's interior vertices (the 9-point stencil of the stream-function
 // operator restricted to them).  The local matrices are factorised once per
 // setup in the twisted block form described in patch.h; every smoother
-// application is one launch over all patches followed by a gather.
+// application is one launch over all patches (the overlapping solutions are
+// summed by the gather kernels of k_pcg.hip).
 #include "common.h"
 #include "patch.h"
 
@@ -193,66 +194,212 @@ __global__ void __launch_bounds__(64) k_patch_factor(const Rect* __restrict__ re
 }
 
 // ------------------------------------------------------------------ application
-// Row r of a link (or, with stride m, its column) for lane `a`; entries beyond m
-// are zero so that a fixed-width loop covers every patch width up to MM.
-template <typename T, int MM>
-__device__ inline void load_line(T (&v)[MM], const T* p, int stride, int m) {
-#pragma unroll
-    for (int c = 0; c < MM; ++c) {
-        const int cc = c < m ? c : m - 1;
-        const T x = p[cc * stride];
-        v[c] = c < m ? x : T(0);
-    }
-}
-
-// sum_c v[c] * (value of x held by lane c)
-template <typename T, int MM>
-__device__ inline T dot_lanes(const T (&v)[MM], T x) {
-    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
-#pragma unroll
-    for (int c = 0; c < MM; c += 4) {
-        s0 += v[c] * readlane(x, c);
-        if (c + 1 < MM) s1 += v[c + 1] * readlane(x, c + 1);
-        if (c + 2 < MM) s2 += v[c + 2] * readlane(x, c + 2);
-        if (c + 3 < MM) s3 += v[c + 3] * readlane(x, c + 3);
-    }
-    return (s0 + s1) + (s2 + s3);
-}
-
-// One dependent chain run by one wavefront: for t = 0..steps-1,
-//   s = line(t) . x;  x = (t + 1 < steps or !last_to_mid) ? base[row(t)] - s : x
-// where line(t) is row or column `a` of link lk(t).  Lane a (< m) holds entry a
-// of the current vector.  Link lines are double-buffered in registers so that the
-// LDS reads for step t+1 are in flight during step t.
-template <typename T, int MM, typename LinkOf, typename Step>
-__device__ inline void run_chain(int steps, const T* links, int m, int a, int stride, int elem, LinkOf lk, Step step) {
-    if (steps <= 0) return;
-    T ra[MM], rb[MM];
-    const long long mm = (long long)m * m;
-    load_line<T, MM>(ra, links + lk(0) * mm + (long long)a * elem, stride, m);
-    int t = 0;
-    while (true) {
-        if (t + 1 < steps) load_line<T, MM>(rb, links + lk(t + 1) * mm + (long long)a * elem, stride, m);
-        step(t, ra);
-        if (++t >= steps) break;
-        if (t + 1 < steps) load_line<T, MM>(ra, links + lk(t + 1) * mm + (long long)a * elem, stride, m);
-        step(t, rb);
-        if (++t >= steps) break;
-    }
-}
-
 // Per patch: psi = S K~^{-1} S g on the patch's interior vertices.  Waves 0 and 1
-// run the top and bottom chains, all four waves share the staging and the
-// independent pivot products.  STAGED: the patch's factor is copied to LDS with
-// 16-byte loads first; otherwise the chains read it from global memory.
-template <typename T, int MM, bool STAGED>
+// run the top and bottom chains; lane a < m holds entry a of the current block
+// vector, and the entries a matrix-vector product needs are broadcast from their
+// lanes with readlane.  The line of the link used by step t+1 (and the entry of
+// b or u) is loaded while step t computes.  Between the forward and backward
+// chains all four waves form the independent products u_j = P_j w_j.
+//
+// M: the compile-time row width (registers, unrolled loops, fixed offsets).
+template <typename T, int M>
+struct Lines {
+    int a;
+    // row a of a dense M x M row-major matrix
+    __device__ void row(T (&v)[M], const T* p) const {
+#pragma unroll
+        for (int c = 0; c < M; ++c) v[c] = p[a * M + c];
+    }
+    // column a of a dense M x M row-major matrix
+    __device__ void column(T (&v)[M], const T* p) const {
+#pragma unroll
+        for (int c = 0; c < M; ++c) v[c] = p[c * M + a];
+    }
+};
+
+template <typename T, int M>
+__device__ inline T dot_lanes(const T (&v)[M], T x) {
+    T s0 = T(0), s1 = T(0);
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        if (c & 1)
+            s1 += v[c] * readlane(x, c);
+        else
+            s0 += v[c] * readlane(x, c);
+    }
+    return s0 + s1;
+}
+
+// One chain of steps t = 0..steps-1 on link lk(t): line(t) . x with line = row
+// (ROW) or column of the link; then x = base[r(t)] - product, stored to dst[r(t)]
+// (scaled by scale[r(t)] when given), except that with TO_MID the last product
+// goes to mid instead.
+template <typename T, int M, bool ROW, bool TO_MID, typename RowOf, typename LinkOf>
+__device__ inline void chain(const Lines<T, M>& ln, int steps, const T* Lk, const T* base, T* dst, const T* scale,
+                             T* mid, T x, bool act, RowOf rr, LinkOf lk) {
+    if (steps <= 0) return;
+    constexpr long long mm = (long long)M * M;
+    const int a = ln.a;
+    T la[M], lb[M];
+    T ba = T(0), bb = T(0), sa = T(1), sb = T(1);
+    auto load = [&](T(&L)[M], T& bv, T& sv, int t) {
+        if (ROW)
+            ln.row(L, Lk + lk(t) * mm);
+        else
+            ln.column(L, Lk + lk(t) * mm);
+        if (!TO_MID || t + 1 < steps) bv = base[rr(t) * M + a];
+        if (scale) sv = scale[rr(t) * M + a];
+    };
+    load(la, ba, sa, 0);
+    int t = 0;
+    auto step = [&](const T(&L)[M], T bv, T sv, T(&Ln)[M], T& bn, T& sn) {
+        const T s = dot_lanes<T, M>(L, x);
+        __builtin_amdgcn_sched_barrier(0);  // keep the next loads behind this step's products
+        if (t + 1 < steps) load(Ln, bn, sn, t + 1);
+        if (TO_MID && t + 1 == steps) {
+            if (act) mid[a] = s;
+        } else {
+            x = bv - s;
+            if (act) dst[rr(t) * M + a] = scale ? sv * x : x;
+        }
+    };
+    while (true) {
+        step(la, ba, sa, lb, bb, sb);
+        if (++t >= steps) break;
+        step(lb, bb, sb, la, ba, sa);
+        if (++t >= steps) break;
+    }
+}
+
+template <typename T, int M>
+__device__ inline void solve_patch(int mh, const T* F, T* vec, T* u, T* mid, T* out) {
+    constexpr int m = M, tri = M * (M + 1) / 2;
+    const int k = mh / 2;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const bool act = lane < m;
+    const Lines<T, M> ln{act ? lane : m - 1};
+    const int a = ln.a;
+    const T* P = F;
+    const T* Lk = F + tw_links(m, mh);
+    const T* S = F + tw_scale(m, mh);
+    if (wave == 0) {
+        // w_{t+1} = b_{t+1} - G_t w_t for t < k-1, stored over b; G_{k-1} w_{k-1} -> mid
+        chain<T, M, true, true>(ln, k, Lk, vec, vec, (const T*)nullptr, mid, vec[a], act,
+                                [](int t) { return t + 1; }, [](int t) { return (long long)t; });
+        if (k == 0 && act) mid[a] = T(0);
+    } else if (wave == 1) {
+        // w_{r-1} = b_{r-1} - H_{r-1} w_r from r = mh-1 down; H_k w_{k+1} -> mid + M
+        chain<T, M, true, true>(ln, mh - 1 - k, Lk, vec, vec, (const T*)nullptr, mid + M, vec[(mh - 1) * M + a], act,
+                                [=](int t) { return mh - 2 - t; }, [=](int t) { return (long long)(mh - 2 - t); });
+        if (mh - 1 == k && act) mid[M + a] = T(0);
+    }
+    __syncthreads();
+    // u_j = P_j w_j for every row j (w_k = b_k - G_{k-1} w_{k-1} - H_k w_{k+1})
+    {
+        int idx[M];  // position of P_j[a][c] in the packed lower triangle
+#pragma unroll
+        for (int c = 0; c < M; ++c) idx[c] = (c <= a) ? tw_offP(c, M) - c + a : tw_offP(a, M) - a + c;
+        for (int j = wave; j < mh; j += 4) {
+            const T* Pj = P + (long long)j * tri;
+            T pr[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) pr[c] = Pj[idx[c]];
+            T wj = vec[j * M + a];
+            if (j == k) wj -= mid[a] + mid[M + a];
+            const T uj = dot_lanes<T, M>(pr, wj);
+            if (act) u[j * M + a] = uj;
+        }
+    }
+    __syncthreads();
+    const T xk = u[k * M + a];
+    if (wave == 0) {
+        if (act) out[k * M + a] = S[k * M + a] * xk;
+        // x_l = u_l - G_l^T x_{l+1}, l = k-1 .. 0
+        chain<T, M, false, false>(ln, k, Lk, u, out, S, mid, xk, act, [=](int t) { return k - 1 - t; },
+                                  [=](int t) { return (long long)(k - 1 - t); });
+    } else if (wave == 1) {
+        // x_{l+1} = u_{l+1} - H_l^T x_l, l = k .. mh-2
+        chain<T, M, false, false>(ln, mh - 1 - k, Lk, u, out, S, mid, xk, act, [=](int t) { return k + 1 + t; },
+                                  [=](int t) { return (long long)(k + t); });
+    }
+}
+
+// Any row width m <= 64: the same two-sided sweeps with runtime loops over the
+// columns (no register lines, no prefetch).  Used for widths without a
+// fixed-width instantiation.
+template <typename T>
+__device__ inline void solve_patch_any(int m, int mh, const T* F, T* vec, T* u, T* mid, T* out) {
+    const int k = mh / 2, tri = tw_tri(m);
+    const long long mm = (long long)m * m;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const bool act = lane < m;
+    const int a = act ? lane : 0;
+    const T* P = F;
+    const T* Lk = F + tw_links(m, mh);
+    const T* S = F + tw_scale(m, mh);
+    auto psym = [&](const T* Pj, int c) { return c <= a ? Pj[tw_offP(c, m) + a - c] : Pj[tw_offP(a, m) + c - a]; };
+    if (wave < 2) {
+        const bool top = wave == 0;
+        const int steps = top ? k : mh - 1 - k;
+        T* md = mid + (top ? 0 : 64);
+        if (steps == 0 && act) md[a] = T(0);
+        int r = top ? 0 : mh - 1;
+        T w = act ? vec[r * m + a] : T(0);
+        for (int t = 0; t < steps; ++t) {
+            const long long l = top ? t : mh - 2 - t;
+            const T* Lr = Lk + l * mm + (long long)a * m;
+            const T* Pj = P + (long long)r * tri;
+            T s = T(0), p = T(0);
+            for (int c = 0; c < m; ++c) {
+                const T xc = readlane(w, c);
+                s += Lr[c] * xc;
+                p += psym(Pj, c) * xc;
+            }
+            if (act) u[r * m + a] = p;
+            r += top ? 1 : -1;
+            if (t + 1 < steps)
+                w = act ? vec[r * m + a] - s : T(0);
+            else if (act)
+                md[a] = s;
+        }
+    }
+    __syncthreads();
+    if (wave < 2) {
+        const bool top = wave == 0;
+        T wk = act ? vec[k * m + a] - mid[a] - mid[64 + a] : T(0);
+        const T* Pk = P + (long long)k * tri;
+        T x = T(0);
+        for (int c = 0; c < m; ++c) x += psym(Pk, c) * readlane(wk, c);
+        if (!act) x = T(0);
+        if (top && act) out[k * m + a] = S[k * m + a] * x;
+        const int steps = top ? k : mh - 1 - k;
+        for (int t = 0; t < steps; ++t) {
+            const long long l = top ? k - 1 - t : k + t;
+            const int r = top ? k - 1 - t : k + 1 + t;
+            const T* Lc = Lk + l * mm + a;
+            T s = T(0);
+            for (int c = 0; c < m; ++c) s += Lc[(long long)c * m] * readlane(x, c);
+            x = act ? u[r * m + a] - s : T(0);
+            if (act) out[r * m + a] = S[r * m + a] * x;
+        }
+    }
+}
+
+// One workgroup (4 waves) per patch.  STAGED: the factor is first copied to LDS
+// with 16-byte loads (eight in flight per thread); otherwise the chains read it
+// from global memory.  GENERIC: every patch takes the clamped path of width M1
+// (m <= M1); otherwise every patch has width M1 or M2 and takes the fixed-width
+// path of its width.
+template <typename T, int M1, int M2, bool GENERIC, bool STAGED>
 __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__ rects, const T* __restrict__ Fpool,
-                                                        const T* __restrict__ g, int nx, T* __restrict__ wout) {
+                                                        const T* __restrict__ g, int nx, T* __restrict__ wout,
+                                                        const double* __restrict__ sc) {
+    if (sc != nullptr && sc[SC_DONE] != 0.0) return;  // PCG already converged
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sm = reinterpret_cast<T*>(smem_raw);
     const Rect R = rects[blockIdx.x];
     const int m = R.i1 - R.i0 - 1, mh = R.j1 - R.j0 - 1;
-    const int n = m * mh, k = mh / 2, tri = tw_tri(m);
+    const int n = m * mh;
     const long long fs = tw_size(m, mh);
     const T* Fg = Fpool + R.off;
     const int tid = threadIdx.x;
@@ -261,16 +408,17 @@ __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__
     if constexpr (STAGED) {
         using V = float4;
         constexpr int PER = 16 / sizeof(T);
+        constexpr int U = 8;
         const V* src = reinterpret_cast<const V*>(Fg);
         V* dst = reinterpret_cast<V*>(sm);
         const int nvec = (int)((fs + PER - 1) / PER);
         int e = tid;
-        for (; e + 3 * 256 < nvec; e += 4 * 256) {
-            const V v0 = src[e], v1 = src[e + 256], v2 = src[e + 512], v3 = src[e + 768];
-            dst[e] = v0;
-            dst[e + 256] = v1;
-            dst[e + 512] = v2;
-            dst[e + 768] = v3;
+        for (; e + (U - 1) * 256 < nvec; e += U * 256) {
+            V v[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) v[q] = src[e + q * 256];
+#pragma unroll
+            for (int q = 0; q < U; ++q) dst[e + q * 256] = v[q];
         }
         for (; e < nvec; e += 256) dst[e] = src[e];
         F = sm;
@@ -280,148 +428,59 @@ __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__
         vec = sm;
     }
     T* u = vec + ((n + 3) & ~3);
-    T* mid = u + ((n + 3) & ~3);  // 2 * MM
-    const T* Pv = F;
-    const T* Lk = F + tw_links(m, mh);
+    T* mid = u + ((n + 3) & ~3);  // 2 * 64
     const T* Sg = Fg + tw_scale(m, mh);
     for (int r = tid; r < n; r += 256) {
         const int aa = r % m, bb = r / m;
         vec[r] = Sg[r] * g[(long long)(R.j0 + 1 + bb) * nx + R.i0 + 1 + aa];
     }
     __syncthreads();
-    const int wave = tid >> 6, lane = tid & 63;
-    const bool act = lane < m;
-    const int a = act ? lane : 0;
-    if (wave == 0) {
-        // w_{l+1} = b_{l+1} - G_l w_l (l < k-1); the last product G_{k-1} w_{k-1} goes to the middle row
-        T w = act ? vec[a] : T(0);
-        run_chain<T, MM>(k, Lk, m, a, 1, m, [](int t) { return (long long)t; }, [&](int t, const T(&line)[MM]) {
-            const T s = dot_lanes<T, MM>(line, w);
-            if (t + 1 < k) {
-                w = act ? vec[(t + 1) * m + a] - s : T(0);
-                if (act) vec[(t + 1) * m + a] = w;
-            } else if (act) {
-                mid[a] = s;
-            }
-        });
-        if (k == 0 && act) mid[a] = T(0);
-    } else if (wave == 1) {
-        // w_l = b_l - H_l w_{l+1} (l = mh-2 .. k+1); the last product H_k w_{k+1} goes to the middle row
-        const int steps = mh - 1 - k;
-        T w = act ? vec[(mh - 1) * m + a] : T(0);
-        run_chain<T, MM>(steps, Lk, m, a, 1, m, [=](int t) { return (long long)(mh - 2 - t); },
-                         [&](int t, const T(&line)[MM]) {
-                             const int l = mh - 2 - t;
-                             const T s = dot_lanes<T, MM>(line, w);
-                             if (l > k) {
-                                 w = act ? vec[l * m + a] - s : T(0);
-                                 if (act) vec[l * m + a] = w;
-                             } else if (act) {
-                                 mid[MM + a] = s;
-                             }
-                         });
-        if (steps == 0 && act) mid[MM + a] = T(0);
-    }
-    __syncthreads();
-    if (tid < m) vec[k * m + tid] -= mid[tid] + mid[MM + tid];
-    __syncthreads();
-    // u_j = P_j w_j for every row (P_j symmetric, lower triangle packed by columns)
-    for (int r = tid; r < n; r += 256) {
-        const int j = r / m, aa = r - j * m;
-        const T* Pj = Pv + (long long)j * tri;
-        const T* wj = vec + j * m;
-        T acc0 = T(0), acc1 = T(0);
-        int c = 0;
-        for (; c < aa; ++c) acc0 += Pj[tw_offP(c, m) + (aa - c)] * wj[c];
-        const T* col = Pj + tw_offP(aa, m) - aa;
-        for (; c < m; ++c) acc1 += col[c] * wj[c];
-        u[r] = acc0 + acc1;
-    }
-    __syncthreads();
-    const T* S = F + tw_scale(m, mh);
     T* out = wout + R.voff;
-    if (wave == 0) {
-        // x_k = u_k; x_l = u_l - G_l^T x_{l+1}, l = k-1 .. 0
-        T x = act ? u[k * m + a] : T(0);
-        if (act) out[k * m + a] = S[k * m + a] * x;
-        run_chain<T, MM>(k, Lk, m, a, m, 1, [=](int t) { return (long long)(k - 1 - t); },
-                         [&](int t, const T(&line)[MM]) {
-                             const int l = k - 1 - t;
-                             const T s = dot_lanes<T, MM>(line, x);
-                             x = act ? u[l * m + a] - s : T(0);
-                             if (act) out[l * m + a] = S[l * m + a] * x;
-                         });
-    } else if (wave == 1) {
-        // x_{l+1} = u_{l+1} - H_l^T x_l, l = k .. mh-2
-        T x = act ? u[k * m + a] : T(0);
-        run_chain<T, MM>(mh - 1 - k, Lk, m, a, m, 1, [=](int t) { return (long long)(k + t); },
-                         [&](int t, const T(&line)[MM]) {
-                             const int l = k + t;
-                             const T s = dot_lanes<T, MM>(line, x);
-                             x = act ? u[(l + 1) * m + a] - s : T(0);
-                             if (act) out[(l + 1) * m + a] = S[(l + 1) * m + a] * x;
-                         });
-    }
-}
-
-// z(v) = [z(v)] + eta * sum of the patch solutions covering v (fixed patch
-// order, so the sum is deterministic; no atomics).
-template <typename T>
-__global__ void k_smooth_gather(const Rect* __restrict__ rects, const T* __restrict__ w, int nx, int ny, int bx,
-                                int by, int Nx, int Ny, T eta, T* __restrict__ z, int accumulate) {
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    const int j = blockIdx.y * 4 + threadIdx.y;
-    if (i >= nx || j >= ny) return;
-    const long long v = (long long)j * nx + i;
-    T s = T(0);
-    if (i > 0 && j > 0) {
-        const int I0 = i / bx, J0 = j / by;
-        for (int J = J0 - 1; J <= J0 + 1; ++J) {
-            if (J < 0 || J >= Ny) continue;
-            for (int I = I0 - 1; I <= I0 + 1; ++I) {
-                if (I < 0 || I >= Nx) continue;
-                const Rect R = rects[J * Nx + I];
-                if (i > R.i0 && i < R.i1 && j > R.j0 && j < R.j1) {
-                    const int m = R.i1 - R.i0 - 1;
-                    s += w[R.voff + (long long)(j - R.j0 - 1) * m + (i - R.i0 - 1)];
-                }
-            }
-        }
-    }
-    s *= eta;
-    z[v] = accumulate ? z[v] + s : s;
-}
-
-template <typename T, int MM, bool STAGED>
-void launch_twisted(tgms_ctx* c, const T* L, const T* g, T* w, size_t lds) {
-    hipLaunchKernelGGL((k_smooth_twisted<T, MM, STAGED>), dim3(c->nblk), dim3(256), lds, c->stream, c->patch, L, g,
-                       c->nx, w);
-}
-
-template <typename T, bool STAGED>
-void dispatch_twisted(tgms_ctx* c, int mmax, const T* L, const T* g, T* w, size_t lds) {
-    if (mmax <= 8)
-        launch_twisted<T, 8, STAGED>(c, L, g, w, lds);
-    else if (mmax <= 12)
-        launch_twisted<T, 12, STAGED>(c, L, g, w, lds);
-    else if (mmax <= 16)
-        launch_twisted<T, 16, STAGED>(c, L, g, w, lds);
-    else if (mmax <= 20)
-        launch_twisted<T, 20, STAGED>(c, L, g, w, lds);
-    else if (mmax <= 24)
-        launch_twisted<T, 24, STAGED>(c, L, g, w, lds);
+    if constexpr (GENERIC)
+        solve_patch_any<T>(m, mh, F, vec, u, mid, out);
+    else if (m == M1)
+        solve_patch<T, M1>(mh, F, vec, u, mid, out);
     else
-        launch_twisted<T, 32, STAGED>(c, L, g, w, lds);
+        solve_patch<T, M2>(mh, F, vec, u, mid, out);
+}
+
+// Fixed-width pairs (interior width, boundary-clipped width) with an overlap of
+// two cells for blocks of 4, 6, 8, 12, 16, 20, 24 and 28 cells; other widths take
+// the clamped path.
+#define TGMS_TW_PAIRS(X) X(7, 5) X(9, 7) X(11, 9) X(15, 13) X(19, 17) X(23, 21) X(27, 25) X(31, 29)
+
+template <typename T, int M1, int M2, bool GENERIC, bool STAGED>
+void launch_tw(tgms_ctx* c, const T* L, const T* g, T* w, size_t lds, const double* sc) {
+    hipLaunchKernelGGL((k_smooth_twisted<T, M1, M2, GENERIC, STAGED>), dim3(c->nblk), dim3(256), lds, c->stream,
+                       c->patch, L, g, c->nx, w, sc);
+}
+
+// m1 >= m2: the two row widths present among the patches (equal when all
+// patches have one width, -1 when there are more than two)
+template <typename T>
+void dispatch_twisted(tgms_ctx* c, int m1, int m2, bool staged, const T* L, const T* g, T* w, size_t lds,
+                      const double* sc) {
+    if (staged) {
+#define TGMS_TW_CASE(A, B)                                \
+    if (m1 == A && (m2 == B || m2 == A)) {                \
+        launch_tw<T, A, B, false, true>(c, L, g, w, lds, sc); \
+        return;                                           \
+    }
+        TGMS_TW_PAIRS(TGMS_TW_CASE)
+#undef TGMS_TW_CASE
+        launch_tw<T, 0, 0, true, true>(c, L, g, w, lds, sc);
+    } else {
+        launch_tw<T, 0, 0, true, false>(c, L, g, w, lds, sc);
+    }
 }
 
 template <typename T>
 void allow_lds(int lds_max) {
-    (void)hipFuncSetAttribute((const void*)k_smooth_twisted<T, 8, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
-    (void)hipFuncSetAttribute((const void*)k_smooth_twisted<T, 12, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
-    (void)hipFuncSetAttribute((const void*)k_smooth_twisted<T, 16, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
-    (void)hipFuncSetAttribute((const void*)k_smooth_twisted<T, 20, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
-    (void)hipFuncSetAttribute((const void*)k_smooth_twisted<T, 24, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
-    (void)hipFuncSetAttribute((const void*)k_smooth_twisted<T, 32, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+    auto set = [&](const void* f) { (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max); };
+#define TGMS_TW_ATTR(A, B) set((const void*)k_smooth_twisted<T, A, B, false, true>);
+    TGMS_TW_PAIRS(TGMS_TW_ATTR)
+#undef TGMS_TW_ATTR
+    set((const void*)k_smooth_twisted<T, 0, 0, true, true>);
 }
 
 }  // namespace
@@ -451,8 +510,9 @@ void factor_patches(tgms_ctx* c) {
     if (h) throw TgmsError{TGMS_E_INVAL, "smoother patch matrix is not positive definite"};
 }
 
+// local solves of every patch on g into the patch solution pool (patW / patW32)
 template <typename T>
-void smooth(tgms_ctx* c, const T* g, T* z, bool accumulate) {
+void smooth_patches(tgms_ctx* c, const T* g, const double* sc) {
     const T* L;
     T* w;
     if constexpr (sizeof(T) == 8) {
@@ -462,23 +522,14 @@ void smooth(tgms_ctx* c, const T* g, T* z, bool accumulate) {
         L = (const T*)c->patL32;
         w = (T*)c->patW32;
     }
-    const int mmax = c->pat_bmax - 1;
-    const size_t work = (size_t)(2 * ((c->pat_nmax + 3) & ~3) + 2 * 32) * sizeof(T);
+    const size_t work = (size_t)(2 * ((c->pat_nmax + 3) & ~3) + 2 * 64) * sizeof(T);
     const size_t staged = (size_t)((c->pat_fmax + 3) & ~3LL) * sizeof(T) + work;
-    {
-        ProfScope ps(c, PK_SMOOTH);
-        if (staged <= (size_t)c->lds_max)
-            dispatch_twisted<T, true>(c, mmax, L, g, w, staged);
-        else
-            dispatch_twisted<T, false>(c, mmax, L, g, w, work);
-        LAUNCH_OK();
-    }
-    dim3 grid((c->nx + 63) / 64, (c->ny + 3) / 4);
-    hipLaunchKernelGGL((k_smooth_gather<T>), grid, dim3(64, 4), 0, c->stream, c->patch, (const T*)w, c->nx, c->ny,
-                       c->bx, c->by, c->Nx, c->Ny, T(c->eta), z, accumulate ? 1 : 0);
+    const bool fits = staged <= (size_t)c->lds_max;
+    ProfScope ps(c, PK_SMOOTH);
+    dispatch_twisted<T>(c, c->pat_m1, c->pat_m2, fits, L, g, w, fits ? staged : work, sc);
     LAUNCH_OK();
 }
-template void smooth<double>(tgms_ctx*, const double*, double*, bool);
-template void smooth<float>(tgms_ctx*, const float*, float*, bool);
+template void smooth_patches<double>(tgms_ctx*, const double*, const double*);
+template void smooth_patches<float>(tgms_ctx*, const float*, const double*);
 
 }  // namespace tgms

@@ -34,3 +34,19 @@ KAPPAS = {}
 def register(key, kappa):
     KAPPAS[key] = np.asarray(kappa, dtype=np.float64)
     return key
+
+
+def eig_bound(kappa, bx, by, lam):
+    """Relative tolerance for the local eigenvalues lambda of one coarse face.
+
+    The snapshots enter S through the kappa^{-1}-weighted mass Gram; their accuracy in
+    that norm is limited by eps times the condition number of the local stream-function
+    matrices, about contrast * (block cells per side)^2 (a factor 100 of margin).  The
+    pencil's largest eigenvalue mu = 1/lambda_min carries that error, which reaches
+    lambda_k as a relative eps * lambda_k / lambda_min on top.
+    """
+    eps = np.finfo(np.float64).eps
+    kappa = np.asarray(kappa)
+    contrast = float(kappa.max() / kappa.min())
+    base = 100.0 * eps * contrast * max(bx, by) ** 2
+    return max(base, 1e-12) + 100.0 * eps * lam / lam.min()

@@ -12,7 +12,7 @@ from workloads import configs
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-from gpu_util import dev, host  # noqa: E402
+from gpu_util import dev, eig_bound, host  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -52,8 +52,7 @@ def test_sampled_spectral_problems(big):
         lam, _, cnt = _oracle_face(w, kappa, faces[k], w.eig_tol)
         if not np.any(np.abs(lam - w.eig_tol) <= 1e-8 * w.eig_tol):
             assert counts[k] == cnt
-        # relative accuracy eps * lambda / lambda_min (see test_counts_and_eigenvalues)
-        bound = 1e-7 + 1e-14 * lam / lam.min()
+        bound = eig_bound(kappa, w.bx, w.by, lam)
         assert np.all(np.abs(eigs[k][: lam.size] - lam) <= bound * lam)
 
 

@@ -20,7 +20,7 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-from gpu_util import dev, host, oracle_for, register, rel  # noqa: E402
+from gpu_util import dev, eig_bound, host, oracle_for, register, rel  # noqa: E402
 
 # Probe tolerances follow the conditioning of the local and coarse problems:
 # two backward-stable solvers of the same system agree to about eps * cond.
@@ -58,7 +58,7 @@ def test_apply_A(name):
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_counts_and_eigenvalues(name):
-    s, o, _ = case(name)
+    s, o, kappa = case(name)
     counts = s.counts()
     eigs = s.eigs()
     tol = CASES[name][5]
@@ -66,10 +66,7 @@ def test_counts_and_eigenvalues(name):
     assert np.array_equal(counts[~near], o.counts[~near])
     for k, e in enumerate(o.eigs):
         J = e.size
-        # T = D^{-1/2} S D^{-1/2} has eigenvalues mu = 1/lambda; both solvers resolve mu to
-        # about eps * mu_max, i.e. lambda_k to a relative eps * lambda_k / lambda_min, on top of
-        # the relative accuracy of S itself (~1e-10 at contrast 1e6, from the snapshot solves).
-        bound = 1e-7 + 1e-14 * e / e.min()
+        bound = eig_bound(kappa, CASES[name][2], CASES[name][3], e)
         assert np.all(np.abs(eigs[k, :J] - e) <= bound * e), (k, eigs[k, :J], e)
     info = s.info()
     assert info["dim"] == o.dim
@@ -103,7 +100,7 @@ def test_solve(name):
     res = s.solve(dev(F), rtol=1e-8)
     ro = o.solve(F, rtol=1e-8)
     assert res["converged"]
-    assert abs(res["iters"] - ro["iters"]) <= 1
+    assert ro["cond"] < 1e4 and abs(res["iters"] - ro["iters"]) <= 1
     assert rel(host(res["u"]), ro["u"]) < 1e-10 or np.linalg.norm(host(res["u"]) - ro["u"]) <= 1e-10 * np.linalg.norm(ro["u"])
     assert np.linalg.norm(host(res["p"]) - ro["p"]) <= 1e-10 * np.linalg.norm(ro["p"])
 
@@ -174,7 +171,13 @@ def test_solve_256_full_oracle():
           f"u err {eu:.3e}, p err {ep:.3e}, relres gpu {res['relres']:.3e} oracle {ro['relres']:.3e}")
     print("oracle relres tail", np.array(ro["hist"][-8:]))
     assert res["converged"]
-    assert abs(res["iters"] - ro["iters"]) <= 1
+    # Iteration parity: +-1 where the preconditioned system is well conditioned (every
+    # other case).  Here Cond ~7e5, and the count is sensitive to rounding in the local
+    # solves: the GPU smoother differs from the exact (refined) local solves by ~3e-11
+    # relative (FP64 conditioning of the patch problems at contrast 1e6), and the oracle
+    # itself, with its smoother output perturbed by random relative noise of that size,
+    # needs 174, 175, 175 and 176 iterations (four seeds).  The bound is that spread.
+    assert abs(res["iters"] - ro["iters"]) <= (1 if ro["cond"] < 1e4 else 2)
     # At Cond ~7e5 a 1e-10 difference between the two preconditioners (the coarse and
     # local problems' conditioning at contrast 1e6) grows over ~170 iterations, so at
     # rtol 1e-8 the two iterates agree to the rtol level only ...
@@ -192,17 +195,27 @@ def test_solve_256_full_oracle():
 
 
 def test_graph_replay_matches_eager():
-    """A PCG iteration is captured once as a HIP graph and replayed; repeated solves
-    through the graph must match the eagerly launched iteration (profiling forces the
-    eager path) in iteration count and result, with other work in between."""
-    s, o, _ = case("chan64")
+    """Two PCG iterations are captured once as a HIP graph and replayed; repeated solves
+    through the graph must match a context that launches every kernel directly, and a
+    profiled solve (direct launches, four iterations queued per check) must count the
+    launches of exactly the iterations that ran."""
+    import paper_1807_07220_amd as tg
+    s, o, kappa = case("chan64")
     F = fields.corner_source(o.g.nx, o.g.ny).ravel()
     r_graph = [s.solve(dev(F), rtol=1e-10) for _ in range(3)]
+    assert s.info()["pcg_graph"] == 1
     s.profile(True)
-    r_eager = s.solve(dev(F), rtol=1e-10)
+    r_prof = s.solve(dev(F), rtol=1e-10)
+    assert s.info()["pcg_graph"] == 0
+    n, t = s.profile_get("smoother")
     s.profile(False)
+    assert n == 2 * r_prof["iters"] + 2 and t > 0.0  # two per iteration and two for z_0
     r_again = s.solve(dev(F), rtol=1e-10)
-    for r in r_graph + [r_again]:
+    assert s.info()["pcg_graph"] == 1
+    e = tg.Solver(dev(kappa), o.g.bx, o.g.by, CASES["chan64"][5], graphs=False)
+    r_eager = e.solve(dev(F), rtol=1e-10)
+    assert e.info()["pcg_graph"] == 0
+    for r in r_graph + [r_prof, r_again]:
         assert r["iters"] == r_eager["iters"]
         assert rel(host(r["u"]), host(r_eager["u"])) < 1e-13
 
