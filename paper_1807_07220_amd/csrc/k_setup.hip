@@ -103,6 +103,184 @@ __global__ void __launch_bounds__(64) k_snapshots(BlockGeom G, const double* __r
     }
 }
 
+// Snapshots with one lane per snapshot column (4*jmax <= 64 columns, one wavefront
+// per block).  The explicit particular flux of column (side s, fine face l) has a
+// closed form: the construction of particular_flux with a single unit boundary
+// flux f on side s and the uniform source (outward flux)/|K| gives
+//   s = 0 (west, row l):  Fx = f (1 - a/bx) on row l,  Fy(b) = (-b f/by + [b > l] f)/bx
+//   s = 1 (east, row l):  Fx = f a/bx on row l,        Fy(b) = (b f/by - [b > l] f)/bx
+//   s = 2 (south, col l): Fx(0, a) = -a f/bx + [a > l] f, Fy(0, a) = [a == l] f,
+//                         Fy(b) = f (1 - b/by)/bx (0 < b < by)
+//   s = 3 (north, col l): Fx(by-1, a) = a f/bx - [a > l] f, Fy(by, a) = [a == l] f,
+//                         Fy(b) = b f/(by bx) (0 < b < by)
+// (fluxes; every other entry zero).  Any particular flux gives the same snapshot.
+// The block's band factor, its cell weights and the 64 right-hand sides /
+// solutions ([vertex][column]) live in LDS; each lane runs the block-row sweeps
+// of band.h on its own column with the factor entries read as broadcasts.
+// The closed forms above, branch-free per lane: the x-fluxes are nonzero on one
+// row xr only, Fx(xr, a) = c0 + c1 a + [a > l] c2; interior y-fluxes are uniform
+// along a row, Fy(b) = d0 + d1 b + [b > l] d2; the boundary rows carry f at a = l
+// on the south (s = 2) or north (s = 3) side.
+struct SnapCol {
+    int l, xr, by;
+    double c0, c1, c2, d0, d1, d2, fs, fn;  // fs, fn: flux at a = l on rows 0 and by
+    __device__ void init(int s, int ll, int bx, int byy, double f) {
+        l = ll;
+        by = byy;
+        const double fb = f / bx, fbb = f / ((double)bx * byy);
+        xr = s == 0 || s == 1 ? ll : (s == 2 ? 0 : byy - 1);
+        c0 = s == 0 ? f : 0.0;
+        c1 = (s == 0 || s == 2) ? -fb : fb;
+        c2 = s == 2 ? f : (s == 3 ? -f : 0.0);
+        d0 = s == 2 ? fb : 0.0;
+        d1 = (s == 0 || s == 2) ? -fbb : fbb;
+        d2 = s == 0 ? fb : (s == 1 ? -fb : 0.0);
+        fs = s == 2 ? f : 0.0;
+        fn = s == 3 ? f : 0.0;
+    }
+    __device__ double Fx(int b, int a) const { return b == xr ? c0 + c1 * a + (a > l ? c2 : 0.0) : 0.0; }
+    __device__ double Fy(int b, int a) const {
+        if (b == 0) return a == l ? fs : 0.0;
+        if (b == by) return a == l ? fn : 0.0;
+        return d0 + d1 * b + (b > l ? d2 : 0.0);
+    }
+};
+
+template <int M>
+__global__ void __launch_bounds__(64) k_snapshots_cols(BlockGeom G, const double* __restrict__ a,
+                                                       const double* __restrict__ blkL, double* __restrict__ Psi) {
+    extern __shared__ __align__(16) double sm[];
+    constexpr int TILE = 32;  // faces per transposed output chunk
+    const int bx = G.bx, by = G.by;
+    const int m = M, mh = by - 1, nloc = m * mh;
+    const int tri = btri_tri(m), bs = tri + btri_hes(m);
+    const long long fsz = btri_size(m, mh);
+    const int areg = (int)((fsz > TILE * 64 ? fsz : TILE * 64) + 1) & ~1;
+    double* F = sm;                 // band factor, later the output transpose tile [TILE][64]
+    double* aK = sm + areg;         // cell weights [by][bx]
+    double* V = aK + bx * by + 1;   // right-hand sides / solutions [vertex][64]
+    const int blk = blockIdx.x, I = blk % G.Nx, J = blk / G.Nx;
+    const int lane = threadIdx.x;
+    {
+        const double* src = blkL + (long long)blk * fsz;
+        for (long long e = lane; e < fsz; e += 64) F[e] = src[e];
+        for (int e = lane; e < bx * by; e += 64)
+            aK[e] = a[(long long)(J * by + e / bx) * G.nx + I * bx + e % bx];
+    }
+    __syncthreads();
+    // this lane's column: side s, fine face l (an all-zero column when the side is on dD
+    // or the side has fewer than l+1 fine faces)
+    const int side = lane / G.jmax, fl = lane % G.jmax;
+    const bool valid = lane < G.ncol &&
+                       ((side == 0 && I > 0) || (side == 1 && I < G.Nx - 1) || (side == 2 && J > 0) ||
+                        (side == 3 && J < G.Ny - 1)) &&
+                       fl < (side < 2 ? by : bx);
+    SnapCol col;
+    col.init(side < 4 ? side : 3, fl, bx, by, valid ? (side < 2 ? G.hy : G.hx) : 0.0);
+    const double c3 = 1.0 / 3.0, c6 = 1.0 / 6.0, ihx = 1.0 / G.hx, ihy = 1.0 / G.hy;
+    auto vx = [&](int b, int aa) { return col.Fx(b, aa) * ihy; };
+    auto vy = [&](int b, int aa) { return col.Fy(b, aa) * ihx; };
+    auto AK = [&](int b, int aa) { return aK[b * bx + aa]; };
+    auto wy = [&](int b, int aa) {  // (A v_p) on y-face (b, aa), 0 < b < by
+        return AK(b - 1, aa) * (vy(b, aa) * c3 + vy(b - 1, aa) * c6) + AK(b, aa) * (vy(b, aa) * c3 + vy(b + 1, aa) * c6);
+    };
+    auto wxr = [&](int aa) {  // (A v_p) on x-face (xr, aa), 0 < aa < bx (zero on every other row)
+        const int b = col.xr;
+        return AK(b, aa - 1) * (vx(b, aa) * c3 + vx(b, aa - 1) * c6) + AK(b, aa) * (vx(b, aa) * c3 + vx(b, aa + 1) * c6);
+    };
+    // g = -C_K^T A_K v_p on the interior vertices (p, q), p = 1..bx-1, q = 1..by-1
+    for (int q = 1; q < by; ++q) {
+        double wprev = wy(q, 0);
+        for (int p = 1; p < bx; ++p) {
+            const double wcur = wy(q, p);
+            double xpart = 0.0;
+            if (q - 1 == col.xr) xpart += wxr(p);
+            if (q == col.xr) xpart -= wxr(p);
+            V[((q - 1) * m + p - 1) * 64 + lane] = -(G.sx * xpart + G.sy * (wcur - wprev));
+            wprev = wcur;
+        }
+    }
+    // psi = (C^T A C)^{-1} g by the block-row sweeps (lane-local; factor entries broadcast)
+    const double* S = F + (long long)mh * bs;
+    double y[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) y[k] = 0.0;
+    for (int j = 0; j < mh; ++j) {
+        const double* D = F + (long long)j * bs;
+        double t[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) t[k] = V[(j * m + k) * 64 + lane] * S[j * m + k];
+        if (j > 0) {
+            const double* E = F + (long long)(j - 1) * bs + tri;
+#pragma unroll
+            for (int c = 0; c < M; ++c)
+#pragma unroll
+                for (int k = 0; k <= c + 1 && k < M; ++k) t[k] -= E[btri_offE(c) + k] * y[c];
+        }
+#pragma unroll
+        for (int k = 0; k < M; ++k) y[k] = 0.0;
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+#pragma unroll
+            for (int k = c; k < M; ++k) y[k] += D[btri_offD(c, m) + k - c] * t[c];
+#pragma unroll
+        for (int k = 0; k < M; ++k) V[(j * m + k) * 64 + lane] = y[k];
+    }
+    double w[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) w[k] = 0.0;
+    for (int j = mh - 1; j >= 0; --j) {
+        const double* D = F + (long long)j * bs;
+        double t[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) t[k] = V[(j * m + k) * 64 + lane];
+        if (j + 1 < mh) {
+            const double* E = F + (long long)j * bs + tri;
+#pragma unroll
+            for (int k = 0; k < M; ++k)
+#pragma unroll
+                for (int r = 0; r <= k + 1 && r < M; ++r) t[k] -= E[btri_offE(k) + r] * w[r];
+        }
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            double acc = 0.0;
+#pragma unroll
+            for (int r = k; r < M; ++r) acc += D[btri_offD(k, m) + r - k] * t[r];
+            w[k] = acc;
+        }
+#pragma unroll
+        for (int k = 0; k < M; ++k) V[(j * m + k) * 64 + lane] = w[k] * S[j * m + k];
+    }
+    __syncthreads();  // the factor region becomes the output tile
+    // v = v_p + C_K psi on all block faces, written column by column in chunks of TILE faces
+    auto P = [&](int pp, int qq) -> double {
+        return (pp <= 0 || pp >= bx || qq <= 0 || qq >= by) ? 0.0 : V[((qq - 1) * m + pp - 1) * 64 + lane];
+    };
+    const int nfx = by * (bx + 1), nfk = G.nfk;
+    double* out = Psi + (long long)blk * G.ncol * nfk;
+    for (int f0 = 0; f0 < nfk; f0 += TILE) {
+        for (int k = 0; k < TILE && f0 + k < nfk; ++k) {
+            const int e = f0 + k;
+            double v;
+            if (e < nfx) {
+                const int b = e / (bx + 1), aa = e % (bx + 1);
+                v = vx(b, aa) + (P(aa, b + 1) - P(aa, b)) * G.sx;
+            } else {
+                const int e2 = e - nfx, b = e2 / bx, aa = e2 % bx;
+                v = vy(b, aa) - (P(aa + 1, b) - P(aa, b)) * G.sy;
+            }
+            F[k * 64 + lane] = v;
+        }
+        __syncthreads();
+        const int nk = (nfk - f0) < TILE ? (nfk - f0) : TILE;
+        for (int cidx = 0; cidx < G.ncol; cidx += 2) {
+            const int cc = cidx + (lane >> 5), k = lane & 31;
+            if (cc < G.ncol && k < nk) out[(long long)cc * nfk + f0 + k] = F[k * 64 + cc];
+        }
+        __syncthreads();
+    }
+}
+
 // APsi = A_K Psi_K (block-local mass applied to every snapshot column); one wavefront per (block, column).
 __global__ void k_apply_AK_cols(BlockGeom G, const double* __restrict__ a, const double* __restrict__ Psi,
                                 double* __restrict__ APsi) {
@@ -517,8 +695,31 @@ BlockGeom geom(tgms_ctx* c) {
 
 namespace tgms {
 
+template <int M>
+static void launch_snap_cols(tgms_ctx* c, const BlockGeom& G, size_t lds) {
+    (void)hipFuncSetAttribute((const void*)k_snapshots_cols<M>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
+    hipLaunchKernelGGL((k_snapshots_cols<M>), dim3(c->nblk), dim3(64), lds, c->stream, G, c->a, c->blkL, c->Psi);
+}
+
 void snapshots(tgms_ctx* c) {
     BlockGeom G = geom(c);
+    // one lane per snapshot column: needs 4*jmax <= 64 and the block's factor,
+    // weights and 64 columns of interior-vertex values in LDS
+    const int m = c->bx - 1, mh = c->by - 1;
+    const long long fsz = btri_size(m, mh);
+    const size_t lds_cols =
+        sizeof(double) * ((((fsz > 32 * 64 ? fsz : 32 * 64) + 1) & ~1LL) + c->bx * c->by + 1 + (size_t)m * mh * 64);
+    if (c->ncol <= 64 && lds_cols <= (size_t)c->lds_max) {
+        switch (m) {
+            case 3: launch_snap_cols<3>(c, G, lds_cols); LAUNCH_OK(); return;
+            case 5: launch_snap_cols<5>(c, G, lds_cols); LAUNCH_OK(); return;
+            case 7: launch_snap_cols<7>(c, G, lds_cols); LAUNCH_OK(); return;
+            case 9: launch_snap_cols<9>(c, G, lds_cols); LAUNCH_OK(); return;
+            case 11: launch_snap_cols<11>(c, G, lds_cols); LAUNCH_OK(); return;
+            case 15: launch_snap_cols<15>(c, G, lds_cols); LAUNCH_OK(); return;
+            default: break;
+        }
+    }
     const int nfx = c->by * (c->bx + 1), nfy = (c->by + 1) * c->bx, nloc = (c->bx - 1) * (c->by - 1);
     size_t lds = sizeof(double) * (2 * c->by + 2 * c->bx + c->bx * c->by + 2 * (nfx + nfy) + nloc + c->by + 2 + 128);
     if (lds > 65536) throw TgmsError{TGMS_E_UNSUPPORTED, "coarse block too large for the snapshot kernel"};

@@ -27,13 +27,15 @@ from gpu_util import dev, eig_bound, host, oracle_for, register, rel  # noqa: E4
 # At contrast <= 1e3 that is below 1e-11; at contrast 1e6 the coarse and
 # block problems reach cond ~ 1e6 after equilibration, hence 1e-8 there.
 # The final velocity and pressure are held to 1e-10 in every case.
-PROBE_TOL = {"cfg32": 1e-11, "rect36x24": 1e-11, "chan64": 1e-8}
+PROBE_TOL = {"cfg32": 1e-11, "rect36x24": 1e-11, "chan64": 1e-8, "odd35x21": 1e-11}
 
 CASES = {
     # name: (nx, ny, bx, by, kappa generator, tol)
     "cfg32": (32, 32, 8, 8, lambda: configs.get("darcy2d_32_b8").make_inputs()[0], 0.5),
     "rect36x24": (36, 24, 6, 4, lambda: np.exp(2.0 * np.random.default_rng(7).standard_normal((24, 36))), 0.5),
     "chan64": (64, 64, 8, 8, lambda: fields.field_channelized(64, 64, 11, contrast=1e6), 2.0),
+    # block and patch widths without a fixed-width kernel instantiation (generic paths)
+    "odd35x21": (35, 21, 7, 7, lambda: np.exp(1.5 * np.random.default_rng(11).standard_normal((21, 35))), 0.5),
 }
 
 
