@@ -4,14 +4,27 @@ One step = one full pass of the hot path over one synthetic input: setup on
 the permeability (block factors, snapshots, Gram products, local
 eigenproblems and adaptive selection, coarse operator and its Cholesky,
 smoother factors) followed by a solve (preprocessing, PCG to 1e-8, velocity
-and pressure).  Inputs are resident on the GPU before the timed region.
+and pressure).  Inputs are resident on the GPU before the timed region; the PCG
+iterations run as HIP graph replays, as in production use.
 
-Prints one JSON line (see --help).  The CPU baseline times the FP64 oracle on
-a bounded sample of the same workload on this host's cores.
+Kernel durations for the roofline come from HIP events recorded around each
+launch on the library's stream during a profiled solve of the same input,
+right after the timed steps (event pairs cannot be placed inside a replayed
+graph, and a profiled solve launches its kernels directly).  HBM traffic per
+launch is read from the committed rocprofv3 counter results when they were
+taken on the current kernel source.
+
+Prints one JSON line.  The CPU baseline times the FP64 oracle on a bounded
+sample of the same workload on this host's cores.
+
+  --copy-calibration BYTES  instead of the benchmark, run plain device copies of
+                            BYTES bytes (the reference for scaling rocprofv3's
+                            FETCH_SIZE / WRITE_SIZE counters)
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -21,6 +34,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+SMOOTHER_SRC = os.path.join(ROOT, "paper_1807_07220_amd", "csrc", "k_smooth.hip")
+PMC_RESULTS = os.path.join(ROOT, "profiles", "smoother_pmc_traffic.json")
 
 
 def smoother_bytes(nx, ny, bx, by, overlap, word):
@@ -44,10 +59,27 @@ def smoother_bytes(nx, ny, bx, by, overlap, word):
     return total * word
 
 
+def source_hash(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per smoother launch from the committed counter runs, or None."""
+    try:
+        with open(PMC_RESULTS) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256_16") != source_hash(SMOOTHER_SRC):
+        return None  # the kernel changed since the counters were taken
+    ent = rec.get("workloads", {}).get(f"{workload}/{precision}")
+    return None if ent is None else ent.get("bytes_per_launch")
+
+
 def cpu_baseline(w, kappa, F, gpu_iters, budget_iters=20):
     """Time the oracle on a bounded sample: full setup, preprocessing, `budget_iters`
     PCG iterations and the pressure; scale the PCG part to the GPU's iteration count."""
-    import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle import Grid2D, OracleSolver
@@ -77,6 +109,17 @@ def cpu_baseline(w, kappa, F, gpu_iters, budget_iters=20):
             "setup_s": t_setup, "solve_s": est - t_setup}
 
 
+def copy_calibration(nbytes, reps=5):
+    import torch
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n * 8, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,11 +129,16 @@ def main():
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
     ap.add_argument("--eig-tol", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the mixed-precision comparison")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a design "
               "described in DESIGN.md and is not built", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     import numpy as np
     import torch
@@ -108,45 +156,47 @@ def main():
     Fd = torch.tensor(F, device=dev)
     torch.cuda.synchronize()
 
-    def step(profile=False):
+    def step(prec):
         t0 = time.perf_counter()
-        s = tg.Solver(kd, w.bx, w.by, tol, precision=precision)
+        s = tg.Solver(kd, w.bx, w.by, tol, precision=prec)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        if profile:
-            s.profile(True)
         r = s.solve(Fd, rtol=w.rtol)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         return s, r, t1 - t0, t2 - t1
 
     for _ in range(args.warmup):
-        s, r, _, _ = step()
+        s, r, _, _ = step(precision)
         s.close()
+    # timed region: K whole steps (setup + solve), graph replay of the PCG iterations
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    setups, solves, prof = [], [], {}
+    setups, solves = [], []
     for k in range(args.steps):
-        s, r, ts, tv = step(profile=True)
+        s, r, ts, tv = step(precision)
         setups.append(ts)
         solves.append(tv)
-        for name in ("smoother", "apply_K", "coarse_restrict", "coarse_prolong"):
-            n, t = s.profile_get(name)
-            a = prof.setdefault(name, [0, 0.0])
-            a[0] += n
-            a[1] += t
-        info, iters, relres, cond = s.info(), r["iters"], r["relres"], s.cond()
-        converged = r["converged"]
         if k + 1 < args.steps:
             s.close()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ms_per_step = 1000.0 * elapsed / args.steps
+    info, iters, relres, cond, converged = s.info(), r["iters"], r["relres"], s.cond(), r["converged"]
+    pcg_graph = info["pcg_graph"]
+    # kernel durations: HIP events around each launch in a profiled solve of the same input
+    s.profile(True)
+    rp = s.solve(Fd, rtol=w.rtol)
+    prof = {name: s.profile_get(name) for name in ("smoother", "apply_K", "coarse_restrict", "coarse_prolong")}
+    s.profile(False)
+    s.close()
+    assert rp["iters"] == iters
     word = 8 if precision == "fp64" else 4
     nbytes = smoother_bytes(w.nx, w.ny, w.bx, w.by, 2, word)
     n_sm, t_sm = prof["smoother"]
     avg_ms = t_sm / max(n_sm, 1)
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(w.name, precision)
     kernels = {k: {"launches": v[0], "avg_us": 1000.0 * v[1] / max(v[0], 1)} for k, v in prof.items()}
     eig_s = (info["t_snap_ms"] + info["t_eig_ms"]) * 1e-3
     out = {
@@ -170,16 +220,29 @@ def main():
         "cond": cond,
         "dim": info["dim"],
         "coarse_spd_unknowns": info["n_coarse_spd"],
-        "lds_max": info["lds_max"],
+        "pcg_graph": bool(pcg_graph),
         "setup_s": float(np.median(setups)),
         "solve_s": float(np.median(solves)),
         "eigensolves_per_s": info["n_coarse_faces"] / eig_s if eig_s > 0 else None,
         "kernels": kernels,
         "roofline": {"kernel": "smoother patch solve (k_smooth_twisted)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "bytes_per_launch": nbytes, "avg_launch_us": avg_ms * 1000.0, "traffic": None},
+                     "traffic": traffic, "bytes_per_launch": nbytes, "avg_launch_us": avg_ms * 1000.0,
+                     "timing": "HIP events around each launch, profiled solve after the timed steps"},
     }
-    s.close()
+    if not args.no_compare and precision == "fp64":
+        # the same workload with the FP32 preconditioner inside the flexible FP64 PCG
+        s, r, _, _ = step("mixed")
+        s.close()
+        ts_m, tv_m, it_m = [], [], []
+        for _ in range(2):
+            s, r, ts, tv = step("mixed")
+            ts_m.append(ts)
+            tv_m.append(tv)
+            it_m.append(r["iters"])
+            s.close()
+        out["compare_mixed"] = {"s_per_solve": float(np.median(np.add(ts_m, tv_m))), "setup_s": float(np.median(ts_m)),
+                                "solve_s": float(np.median(tv_m)), "iters": it_m[-1]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, kappa, F, iters)
     print(json.dumps(out), flush=True)

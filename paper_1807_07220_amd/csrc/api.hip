@@ -20,7 +20,7 @@
 namespace tgms {
 void bnd_faces(tgms_ctx* c, const double* g, double* gb);
 
-static hipEvent_t take_event(tgms_ctx* c) {
+hipEvent_t take_event(tgms_ctx* c) {
     if (c->ev_used == c->ev_pool.size()) {
         hipEvent_t e;
         HIP_OK(hipEventCreate(&e));
@@ -479,6 +479,13 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
             if (c->precision) {
                 c->patL32 = c->alloc<float>(off);
                 c->patW32 = c->alloc<float>(voff);
+            }
+            // a vertex is covered by its own block's patch and, when blocks are at least
+            // twice the overlap, by at most one neighbour per direction: four slots
+            c->slots = bx >= 2 * o.overlap && by >= 2 * o.overlap;
+            if (c->slots) {
+                c->patW4 = c->alloc<double>(4 * (size_t)ncell);  // zero: slots no patch covers stay zero
+                if (c->precision) c->patW4_32 = c->alloc<float>(4 * (size_t)ncell);
             }
             tgms::factor_patches(c);
             c->t_smoother_ms = t.ms();

@@ -116,6 +116,9 @@ struct tgms_ctx {
     float* patL32 = nullptr;
     double* patW = nullptr;  // per-patch local solution (vpool)
     float* patW32 = nullptr;
+    bool slots = false;        // patch solutions go to four slots per vertex (blocks >= 2 * overlap)
+    double* patW4 = nullptr;   // 4 * nx * ny
+    float* patW4_32 = nullptr;
     // snapshots and Gram
     int nfk, ncol;            // faces per block (full, incl. block boundary), snapshot columns per block
     double* Psi = nullptr;    // nblk * ncol * nfk  (column major per block)
@@ -217,6 +220,7 @@ struct ProfScope {
     ~ProfScope();
 };
 void enter(tgms_ctx* c);
+hipEvent_t take_event(tgms_ctx* c);  // from the profiling event pool
 // grid / vector kernels (k_grid.hip)
 void cell_weights(tgms_ctx* c, const double* kappa, int* bad);
 void faces_A(tgms_ctx* c, const double* u, double* out);                    // A u on interior faces

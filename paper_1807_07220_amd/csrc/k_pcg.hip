@@ -167,10 +167,21 @@ struct GatherGeom {
     int nx, ny, bx, by, Nx, Ny;
 };
 
+// the sum of the patch solutions at vertex (i, j): the four slots when present
+template <typename T>
+__device__ inline T patch_sum(const Rect* __restrict__ rects, const T* __restrict__ w, const T* __restrict__ w4,
+                              const GatherGeom& G, int i, int j) {
+    if (w4) {
+        const T* q = w4 + ((long long)j * G.nx + i) * 4;
+        return (q[0] + q[1]) + (q[2] + q[3]);
+    }
+    return gather_w<T>(rects, w, i, j, G.bx, G.by, G.Nx, G.Ny);
+}
+
 // First smoothing of the two-grid cycle: z = eta * sum_i ext(w_i), t = g - K z.
 template <typename T>
 __global__ void __launch_bounds__(NT) k_gather_res(const Rect* __restrict__ rects, const T* __restrict__ w,
-                                                   GatherGeom G, T eta, const T* __restrict__ g,
+                                                   const T* __restrict__ w4, GatherGeom G, T eta, const T* __restrict__ g,
                                                    const T* __restrict__ a, T sx2, T sy2, T* __restrict__ z,
                                                    T* __restrict__ t, const double* __restrict__ sc) {
     if (finished(sc)) return;
@@ -180,7 +191,7 @@ __global__ void __launch_bounds__(NT) k_gather_res(const Rect* __restrict__ rect
     for (int e = tid; e < (TX + 2) * (TY + 2); e += NT) {
         const int ii = i0 - 1 + e % (TX + 2), jj = j0 - 1 + e / (TX + 2);
         T val = T(0);
-        if (ii >= 1 && ii < G.nx && jj >= 1 && jj < G.ny) val = eta * gather_w<T>(rects, w, ii, jj, G.bx, G.by, G.Nx, G.Ny);
+        if (ii >= 1 && ii < G.nx && jj >= 1 && jj < G.ny) val = eta * patch_sum<T>(rects, w, w4, G, ii, jj);
         Z[e / (TX + 2)][e % (TX + 2)] = val;
     }
     __syncthreads();
@@ -196,7 +207,7 @@ __global__ void __launch_bounds__(NT) k_gather_res(const Rect* __restrict__ rect
 // and |C z|^2 (NRED workgroups loop over the tiles).
 template <typename T>
 __global__ void __launch_bounds__(NT) k_gather_final(const Rect* __restrict__ rects, const T* __restrict__ w,
-                                                     GatherGeom G, T eta, const T* __restrict__ zin,
+                                                     const T* __restrict__ w4, GatherGeom G, T eta, const T* __restrict__ zin,
                                                      double* __restrict__ zout, double sx, double sy,
                                                      const double* __restrict__ g, const double* __restrict__ gold,
                                                      const double* __restrict__ sc, double* __restrict__ part) {
@@ -212,7 +223,7 @@ __global__ void __launch_bounds__(NT) k_gather_final(const Rect* __restrict__ re
             const int ii = i0 + e % (TX + 1), jj = j0 + e / (TX + 1);
             double val = 0.0;
             if (ii >= 1 && ii < G.nx && jj >= 1 && jj < G.ny) {
-                T s = eta * gather_w<T>(rects, w, ii, jj, G.bx, G.by, G.Nx, G.Ny);
+                T s = eta * patch_sum<T>(rects, w, w4, G, ii, jj);
                 if (zin) s += zin[(long long)jj * G.nx + ii];
                 val = (double)s;
             }
@@ -302,6 +313,11 @@ __global__ void __launch_bounds__(NT) k_residual(const T* __restrict__ z, const 
 
 inline dim3 tiles(tgms_ctx* c) { return dim3((c->nx + TX - 1) / TX, (c->ny + TY - 1) / TY); }
 inline GatherGeom ggeom(tgms_ctx* c) { return GatherGeom{c->nx, c->ny, c->bx, c->by, c->Nx, c->Ny}; }
+template <typename T>
+inline const T* slots(tgms_ctx* c) {
+    if (!c->slots) return nullptr;
+    return sizeof(T) == 8 ? (const T*)c->patW4 : (const T*)c->patW4_32;
+}
 
 }  // namespace
 
@@ -325,8 +341,8 @@ void update(tgms_ctx* c, const double* p, const double* q, double* x, double* g,
 
 template <typename T>
 void gather_res(tgms_ctx* c, const T* w, const T* g, const T* a, T* z, T* t, const double* sc) {
-    hipLaunchKernelGGL((k_gather_res<T>), tiles(c), dim3(TX, TY), 0, c->stream, c->patch, w, ggeom(c), T(c->eta), g,
-                       a, T(c->sx * c->sx), T(c->sy * c->sy), z, t, sc);
+    hipLaunchKernelGGL((k_gather_res<T>), tiles(c), dim3(TX, TY), 0, c->stream, c->patch, w, slots<T>(c), ggeom(c),
+                       T(c->eta), g, a, T(c->sx * c->sx), T(c->sy * c->sy), z, t, sc);
     LAUNCH_OK();
 }
 template void gather_res<double>(tgms_ctx*, const double*, const double*, const double*, double*, double*,
@@ -338,11 +354,11 @@ void gather_final(tgms_ctx* c, const T* w, const T* zin, double* zout, const dou
                   bool with_dots, bool first) {
     const double* sc = with_dots ? c->sc : nullptr;
     if (with_dots)
-        hipLaunchKernelGGL((k_gather_final<T>), dim3(NRED), dim3(TX, TY), 0, c->stream, c->patch, w, ggeom(c),
-                           T(c->eta), zin, zout, c->sx, c->sy, g, gold, sc, c->part);
+        hipLaunchKernelGGL((k_gather_final<T>), dim3(NRED), dim3(TX, TY), 0, c->stream, c->patch, w, slots<T>(c),
+                           ggeom(c), T(c->eta), zin, zout, c->sx, c->sy, g, gold, sc, c->part);
     else
         hipLaunchKernelGGL((k_gather_final<T>), dim3(tiles(c).x * tiles(c).y), dim3(TX, TY), 0, c->stream, c->patch,
-                           w, ggeom(c), T(c->eta), zin, zout, c->sx, c->sy, g, gold, sc, (double*)nullptr);
+                           w, slots<T>(c), ggeom(c), T(c->eta), zin, zout, c->sx, c->sy, g, gold, sc, (double*)nullptr);
     LAUNCH_OK();
     if (with_dots) {
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(TX, TY), 0, c->stream, c->sc, c->hist, (const double*)c->part,

@@ -8,6 +8,8 @@
 // setup in the twisted block form described in patch.h; every smoother
 // application is one launch over all patches (the overlapping solutions are
 // summed by the gather kernels of k_pcg.hip).
+#include <hip/hip_ext.h>
+
 #include "common.h"
 #include "patch.h"
 
@@ -230,12 +232,33 @@ __device__ inline T dot_lanes(const T (&v)[M], T x) {
     return s0 + s1;
 }
 
+// Where a patch solution goes: the patch's own vector (slot layout off), or the
+// slot of the patch in a four-slot array per vertex (own block, x neighbour,
+// y neighbour, diagonal neighbour), so that summing the overlapping solutions
+// is one contiguous read per vertex.
+template <typename T>
+struct PatchOut {
+    T* base;        // own vector (m*mh entries), used when w4 is null
+    T* w4;          // four slots per global vertex
+    int m, nx, i0, j0;
+    int bxlo, bxhi, bylo, byhi;  // the cells of the patch's own coarse block
+    __device__ void put(int row, int a, T v) const {
+        if (!w4) {
+            base[row * m + a] = v;
+            return;
+        }
+        const int i = i0 + 1 + a, j = j0 + 1 + row;
+        const int slot = (i < bxlo || i >= bxhi ? 1 : 0) + (j < bylo || j >= byhi ? 2 : 0);
+        w4[((long long)j * nx + i) * 4 + slot] = v;
+    }
+};
+
 // One chain of steps t = 0..steps-1 on link lk(t): line(t) . x with line = row
-// (ROW) or column of the link; then x = base[r(t)] - product, stored to dst[r(t)]
+// (ROW) or column of the link; then x = base[r(t)] - product, handed to put(r(t), .)
 // (scaled by scale[r(t)] when given), except that with TO_MID the last product
 // goes to mid instead.
-template <typename T, int M, bool ROW, bool TO_MID, typename RowOf, typename LinkOf>
-__device__ inline void chain(const Lines<T, M>& ln, int steps, const T* Lk, const T* base, T* dst, const T* scale,
+template <typename T, int M, bool ROW, bool TO_MID, typename RowOf, typename LinkOf, typename Put>
+__device__ inline void chain(const Lines<T, M>& ln, int steps, const T* Lk, const T* base, Put put, const T* scale,
                              T* mid, T x, bool act, RowOf rr, LinkOf lk) {
     if (steps <= 0) return;
     constexpr long long mm = (long long)M * M;
@@ -260,7 +283,7 @@ __device__ inline void chain(const Lines<T, M>& ln, int steps, const T* Lk, cons
             if (act) mid[a] = s;
         } else {
             x = bv - s;
-            if (act) dst[rr(t) * M + a] = scale ? sv * x : x;
+            if (act) put(rr(t), scale ? sv * x : x);
         }
     };
     while (true) {
@@ -272,7 +295,7 @@ __device__ inline void chain(const Lines<T, M>& ln, int steps, const T* Lk, cons
 }
 
 template <typename T, int M>
-__device__ inline void solve_patch(int mh, const T* F, T* vec, T* u, T* mid, T* out) {
+__device__ inline void solve_patch(int mh, const T* F, T* vec, T* u, T* mid, const PatchOut<T>& out) {
     constexpr int m = M, tri = M * (M + 1) / 2;
     const int k = mh / 2;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -284,13 +307,15 @@ __device__ inline void solve_patch(int mh, const T* F, T* vec, T* u, T* mid, T* 
     const T* S = F + tw_scale(m, mh);
     if (wave == 0) {
         // w_{t+1} = b_{t+1} - G_t w_t for t < k-1, stored over b; G_{k-1} w_{k-1} -> mid
-        chain<T, M, true, true>(ln, k, Lk, vec, vec, (const T*)nullptr, mid, vec[a], act,
+        auto to_vec = [&](int row, T v) { vec[row * M + a] = v; };
+        chain<T, M, true, true>(ln, k, Lk, vec, to_vec, (const T*)nullptr, mid, vec[a], act,
                                 [](int t) { return t + 1; }, [](int t) { return (long long)t; });
         if (k == 0 && act) mid[a] = T(0);
     } else if (wave == 1) {
         // w_{r-1} = b_{r-1} - H_{r-1} w_r from r = mh-1 down; H_k w_{k+1} -> mid + M
-        chain<T, M, true, true>(ln, mh - 1 - k, Lk, vec, vec, (const T*)nullptr, mid + M, vec[(mh - 1) * M + a], act,
-                                [=](int t) { return mh - 2 - t; }, [=](int t) { return (long long)(mh - 2 - t); });
+        auto to_vec = [&](int row, T v) { vec[row * M + a] = v; };
+        chain<T, M, true, true>(ln, mh - 1 - k, Lk, vec, to_vec, (const T*)nullptr, mid + M, vec[(mh - 1) * M + a],
+                                act, [=](int t) { return mh - 2 - t; }, [=](int t) { return (long long)(mh - 2 - t); });
         if (mh - 1 == k && act) mid[M + a] = T(0);
     }
     __syncthreads();
@@ -312,14 +337,15 @@ __device__ inline void solve_patch(int mh, const T* F, T* vec, T* u, T* mid, T* 
     }
     __syncthreads();
     const T xk = u[k * M + a];
+    auto to_out = [&](int row, T v) { out.put(row, a, v); };
     if (wave == 0) {
-        if (act) out[k * M + a] = S[k * M + a] * xk;
+        if (act) out.put(k, a, S[k * M + a] * xk);
         // x_l = u_l - G_l^T x_{l+1}, l = k-1 .. 0
-        chain<T, M, false, false>(ln, k, Lk, u, out, S, mid, xk, act, [=](int t) { return k - 1 - t; },
+        chain<T, M, false, false>(ln, k, Lk, u, to_out, S, mid, xk, act, [=](int t) { return k - 1 - t; },
                                   [=](int t) { return (long long)(k - 1 - t); });
     } else if (wave == 1) {
         // x_{l+1} = u_{l+1} - H_l^T x_l, l = k .. mh-2
-        chain<T, M, false, false>(ln, mh - 1 - k, Lk, u, out, S, mid, xk, act, [=](int t) { return k + 1 + t; },
+        chain<T, M, false, false>(ln, mh - 1 - k, Lk, u, to_out, S, mid, xk, act, [=](int t) { return k + 1 + t; },
                                   [=](int t) { return (long long)(k + t); });
     }
 }
@@ -328,7 +354,7 @@ __device__ inline void solve_patch(int mh, const T* F, T* vec, T* u, T* mid, T* 
 // columns (no register lines, no prefetch).  Used for widths without a
 // fixed-width instantiation.
 template <typename T>
-__device__ inline void solve_patch_any(int m, int mh, const T* F, T* vec, T* u, T* mid, T* out) {
+__device__ inline void solve_patch_any(int m, int mh, const T* F, T* vec, T* u, T* mid, const PatchOut<T>& out) {
     const int k = mh / 2, tri = tw_tri(m);
     const long long mm = (long long)m * m;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -371,7 +397,7 @@ __device__ inline void solve_patch_any(int m, int mh, const T* F, T* vec, T* u, 
         T x = T(0);
         for (int c = 0; c < m; ++c) x += psym(Pk, c) * readlane(wk, c);
         if (!act) x = T(0);
-        if (top && act) out[k * m + a] = S[k * m + a] * x;
+        if (top && act) out.put(k, a, S[k * m + a] * x);
         const int steps = top ? k : mh - 1 - k;
         for (int t = 0; t < steps; ++t) {
             const long long l = top ? k - 1 - t : k + t;
@@ -380,7 +406,7 @@ __device__ inline void solve_patch_any(int m, int mh, const T* F, T* vec, T* u, 
             T s = T(0);
             for (int c = 0; c < m; ++c) s += Lc[(long long)c * m] * readlane(x, c);
             x = act ? u[r * m + a] - s : T(0);
-            if (act) out[r * m + a] = S[r * m + a] * x;
+            if (act) out.put(r, a, S[r * m + a] * x);
         }
     }
 }
@@ -393,6 +419,7 @@ __device__ inline void solve_patch_any(int m, int mh, const T* F, T* vec, T* u, 
 template <typename T, int M1, int M2, bool GENERIC, bool STAGED>
 __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__ rects, const T* __restrict__ Fpool,
                                                         const T* __restrict__ g, int nx, T* __restrict__ wout,
+                                                        T* __restrict__ w4, int bx, int by, int Nx,
                                                         const double* __restrict__ sc) {
     if (sc != nullptr && sc[SC_DONE] != 0.0) return;  // PCG already converged
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -435,7 +462,8 @@ __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__
         vec[r] = Sg[r] * g[(long long)(R.j0 + 1 + bb) * nx + R.i0 + 1 + aa];
     }
     __syncthreads();
-    T* out = wout + R.voff;
+    const int I = blockIdx.x % Nx, J = blockIdx.x / Nx;
+    const PatchOut<T> out{wout + R.voff, w4, m, nx, R.i0, R.j0, I * bx, (I + 1) * bx, J * by, (J + 1) * by};
     if constexpr (GENERIC)
         solve_patch_any<T>(m, mh, F, vec, u, mid, out);
     else if (m == M1)
@@ -451,8 +479,18 @@ __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__
 
 template <typename T, int M1, int M2, bool GENERIC, bool STAGED>
 void launch_tw(tgms_ctx* c, const T* L, const T* g, T* w, size_t lds, const double* sc) {
-    hipLaunchKernelGGL((k_smooth_twisted<T, M1, M2, GENERIC, STAGED>), dim3(c->nblk), dim3(256), lds, c->stream,
-                       c->patch, L, g, c->nx, w, sc);
+    T* w4 = nullptr;
+    if (c->slots) w4 = sizeof(T) == 8 ? (T*)c->patW4 : (T*)c->patW4_32;
+    if (c->prof) {
+        // events recorded by the dispatch itself (kernel execution only)
+        hipEvent_t e1 = tgms::take_event(c), e2 = tgms::take_event(c);
+        hipExtLaunchKernelGGL((k_smooth_twisted<T, M1, M2, GENERIC, STAGED>), dim3(c->nblk), dim3(256), lds,
+                              c->stream, e1, e2, 0, c->patch, L, g, c->nx, w, w4, c->bx, c->by, c->Nx, sc);
+        c->prof_rec.push_back({tgms::PK_SMOOTH, c->prof_iter, e1, e2});
+    } else {
+        hipLaunchKernelGGL((k_smooth_twisted<T, M1, M2, GENERIC, STAGED>), dim3(c->nblk), dim3(256), lds, c->stream,
+                           c->patch, L, g, c->nx, w, w4, c->bx, c->by, c->Nx, sc);
+    }
 }
 
 // m1 >= m2: the two row widths present among the patches (equal when all
@@ -525,7 +563,6 @@ void smooth_patches(tgms_ctx* c, const T* g, const double* sc) {
     const size_t work = (size_t)(2 * ((c->pat_nmax + 3) & ~3) + 2 * 64) * sizeof(T);
     const size_t staged = (size_t)((c->pat_fmax + 3) & ~3LL) * sizeof(T) + work;
     const bool fits = staged <= (size_t)c->lds_max;
-    ProfScope ps(c, PK_SMOOTH);
     dispatch_twisted<T>(c, c->pat_m1, c->pat_m2, fits, L, g, w, fits ? staged : work, sc);
     LAUNCH_OK();
 }
