@@ -119,6 +119,19 @@ tgms_status tgms_setup(const tgms_grid* grid, const double* kappa, double eig_to
 tgms_status tgms_solve(tgms_ctx* ctx, const double* F, const double* g_bnd, double rtol,
                        int maxit, double* u, double* p, int* iters, double* relres);
 
+/*
+ * Mobility update with the coarse space kept (section 6.2: the multiscale basis
+ * of the initial permeability is reused while the total mobility changes).  The
+ * operator becomes A(lambda), built from (lambda kappa)^{-1}; the block factors,
+ * the coarse operator over the kept basis (Gram matrices of the kept snapshots,
+ * its Cholesky inverse), the coarse RT0 operator and the smoother patch factors
+ * are rebuilt.  The eigenvalues, basis counts and basis functions are unchanged.
+ *   lambda  device, nx*ny doubles, total mobility per cell (> 0, finite).
+ * TGMS_E_INVAL for a non-positive or non-finite mobility (the context then holds
+ * a partially rebuilt operator: call again with a valid field before solving).
+ */
+tgms_status tgms_update_mobility(tgms_ctx* ctx, const double* lambda);
+
 /* Sizes and timings of the setup. */
 tgms_status tgms_info(const tgms_ctx* ctx, tgms_info_t* info);
 

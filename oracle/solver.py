@@ -148,6 +148,33 @@ class OracleSolver:
                 r = block_rect(g, I, J, self.overlap)
                 self.patches.append(BorderedSaddle(self.A, self.B, g.faces_in(*r), g.cells_in(*r)))
 
+    # ---- mobility update with the coarse space kept (section 6.2) -------------
+    def update_mobility(self, lam):
+        """Rebuild the operator for total mobility lam (per cell) with the basis kept.
+
+        Section 6.2 keeps the multiscale basis built for the initial permeability
+        while the mobility changes between pressure solves.  The flux law becomes
+        (lam kappa)^{-1} v = -grad p, so the mass matrix A is rebuilt with
+        kappa^{-1}/lam; the coarse operator R_H L R_H^T is formed again over the
+        same basis Phi (A_H = Phi^T A Phi, B_H unchanged), the smoother patches and
+        the preprocessing blocks are refactorised.  Snapshots, eigenpairs and the
+        basis counts stay as they are.
+        """
+        g = self.g
+        lam = np.asarray(lam, dtype=np.float64).ravel()
+        if lam.size != g.nc or not np.all(np.isfinite(lam)) or np.any(lam <= 0):
+            raise ValueError("mobility must be finite and positive on every cell")
+        self.A = mass_matrix(g, self.kinv / lam).tocsr()
+        AH = (self.Phi.T @ self.A @ self.Phi).toarray()
+        BH = (self.RQ @ self.B @ self.Phi).toarray()
+        self.coarse_lu, self.nH, self.mH = bordered_dense_or_sparse(AH, BH)
+        self._blocks = {}
+        self.patches = []
+        for J in range(g.Ny):
+            for I in range(g.Nx):
+                r = block_rect(g, I, J, self.overlap)
+                self.patches.append(BorderedSaddle(self.A, self.B, g.faces_in(*r), g.cells_in(*r)))
+
     # ---- building blocks ----------------------------------------------
     def block(self, I, J) -> BorderedSaddle:
         """L_K = R_K L R_K^T on coarse block K (faces strictly inside K, cells of K)."""

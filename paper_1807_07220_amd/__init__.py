@@ -72,6 +72,13 @@ class Solver:
             check(code)
         return {"u": u, "p": p, "iters": it.value, "relres": rel.value, "converged": converged}
 
+    def update_mobility(self, lam: torch.Tensor):
+        """Rebuild the operator for the total mobility lam (cells), keeping the coarse basis."""
+        lam = lam.contiguous().reshape(-1)
+        if lam.numel() != self.nx * self.ny or lam.dtype != torch.float64:
+            raise ValueError("mobility must be an (ny, nx) float64 field")
+        check(load().tgms_update_mobility(self._h, _ptr(lam)))
+
     def info(self) -> dict:
         inf = Info()
         check(load().tgms_info(self._h, ctypes.byref(inf)))

@@ -59,6 +59,7 @@ SIGNATURES = {
     "tgms_apply_A": (c_int, [c_void_p, c_void_p, c_void_p]),
     "tgms_preprocess": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "tgms_apply_precond": (c_int, [c_void_p, c_int, c_void_p, c_void_p]),
+    "tgms_update_mobility": (c_int, [c_void_p, c_void_p]),
 }
 
 

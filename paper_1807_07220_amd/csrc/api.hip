@@ -285,40 +285,12 @@ void build_coarse_numbering(tgms_ctx* c, const std::vector<double>& Yh, const st
 }
 
 // Coarse RT0 vertex stiffness K_H = C_H^T A_H0 C_H (dense, host-assembled from the per-block Grams).
+// coarse RT0 stream-function stiffness (preprocessing, section 3) and its inverse
 void build_rt0_stiffness(tgms_ctx* c) {
-    const int Nx = c->Nx, Ny = c->Ny, nv = c->nv;
-    std::vector<double> ah(6 * c->nblk);
-    HIP_OK(hipMemcpyAsync(ah.data(), c->AH0, sizeof(double) * 6 * c->nblk, hipMemcpyDeviceToHost, c->stream));
-    HIP_OK(hipStreamSynchronize(c->stream));
-    std::vector<double> K((size_t)nv * nv, 0.0);
-    const double Hx = c->bx * c->hx, Hy = c->by * c->hy;
-    auto vid = [&](int I, int J) { return (I <= 0 || I >= Nx || J <= 0 || J >= Ny) ? -1 : (J - 1) * (Nx - 1) + I - 1; };
-    for (int J = 0; J < Ny; ++J)
-        for (int I = 0; I < Nx; ++I) {
-            const double* m = &ah[6 * (J * Nx + I)];
-            // face velocities as combinations of corner stream-function values
-            struct Term { int v; double w; };
-            const Term W[2] = {{vid(I, J + 1), 1 / Hy}, {vid(I, J), -1 / Hy}};
-            const Term E[2] = {{vid(I + 1, J + 1), 1 / Hy}, {vid(I + 1, J), -1 / Hy}};
-            const Term S[2] = {{vid(I + 1, J), -1 / Hx}, {vid(I, J), 1 / Hx}};
-            const Term N[2] = {{vid(I + 1, J + 1), -1 / Hx}, {vid(I, J + 1), 1 / Hx}};
-            auto pair = [&](const Term* a, const Term* b, double w) {
-                for (int p = 0; p < 2; ++p)
-                    for (int q = 0; q < 2; ++q)
-                        if (a[p].v >= 0 && b[q].v >= 0) K[(size_t)a[p].v * nv + b[q].v] += w * a[p].w * b[q].w;
-            };
-            pair(W, W, m[0]);
-            pair(W, E, m[1]);
-            pair(E, W, m[1]);
-            pair(E, E, m[2]);
-            pair(S, S, m[3]);
-            pair(S, N, m[4]);
-            pair(N, S, m[4]);
-            pair(N, N, m[5]);
-        }
-    c->KH = c->alloc<double>((size_t)nv * nv);
-    HIP_OK(hipMemcpyAsync(c->KH, K.data(), sizeof(double) * K.size(), hipMemcpyHostToDevice, c->stream));
-    HIP_OK(hipStreamSynchronize(c->stream));
+    const int nv = c->nv;
+    if (!c->KH) c->KH = c->alloc<double>((size_t)nv * nv);
+    tgms::zero(c, c->KH, sizeof(double) * (size_t)nv * nv);
+    tgms::rt0_stiffness(c, c->KH);
     tgms::dense_spd_inverse(c, c->KH, nv);
 }
 
@@ -416,14 +388,14 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
             std::vector<double> Tm;
             std::vector<int> zc;
             build_coarse_numbering(c, Yh, Qh, Tm, zc);
-            double* Td = c->alloc<double>(Tm.size());
-            int* zcd = c->alloc<int>(zc.size());
-            HIP_OK(hipMemcpyAsync(Td, Tm.data(), sizeof(double) * Tm.size(), hipMemcpyHostToDevice, c->stream));
-            HIP_OK(hipMemcpyAsync(zcd, zc.data(), sizeof(int) * zc.size(), hipMemcpyHostToDevice, c->stream));
+            c->Td = c->alloc<double>(Tm.size());
+            c->zcd = c->alloc<int>(zc.size());
+            HIP_OK(hipMemcpyAsync(c->Td, Tm.data(), sizeof(double) * Tm.size(), hipMemcpyHostToDevice, c->stream));
+            HIP_OK(hipMemcpyAsync(c->zcd, zc.data(), sizeof(int) * zc.size(), hipMemcpyHostToDevice, c->stream));
             c->W = c->alloc<double>((size_t)c->nblk * bx * by * c->mu);
             if (c->precision) c->W32 = c->alloc<float>((size_t)c->nblk * bx * by * c->mu);
             c->Ac = c->alloc<double>((size_t)c->ncs * c->ncs);
-            tgms::coarse_local_run(c, Td, zcd);
+            tgms::coarse_local_run(c, c->Td, c->zcd);
             tgms::dense_spd_inverse(c, c->Ac, c->ncs);
             if (c->precision) {
                 c->Ac32 = c->alloc<float>((size_t)c->ncs * c->ncs);
@@ -537,6 +509,33 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         tgms_destroy(c);
         throw;
     }
+}
+
+// Mobility update with the coarse space kept (paper section 6.2: the basis built for
+// the initial permeability is reused while the mobility changes).  The operator
+// becomes A(lambda) with cell weights |c| / (lambda kappa); every factor that
+// depends on it is rebuilt: block factors (preprocessing), the block Gram
+// matrices of the fixed snapshots and the coarse SPD matrix over the fixed
+// basis, its Cholesky inverse, the coarse RT0 operator and the smoother patches.
+void update_mobility_impl(tgms_ctx* c, const double* lambda) {
+    if (!c || !lambda) throw TgmsError{TGMS_E_INVAL, "null argument"};
+    tgms::enter(c);
+    int* bad = c->alloc_scratch_int();
+    tgms::mobility_weights(c, lambda, bad);
+    int hbad = 0;
+    HIP_OK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (hbad) throw TgmsError{TGMS_E_INVAL, "mobility must be finite and positive"};
+    tgms::factor_blocks(c);
+    tgms::gram(c);
+    tgms::zero(c, c->Ac, sizeof(double) * (size_t)c->ncs * c->ncs);
+    tgms::coarse_local_run(c, c->Td, c->zcd);
+    tgms::dense_spd_inverse(c, c->Ac, c->ncs);
+    if (c->precision) tgms::cast_d2f(c, (long long)c->ncs * c->ncs, c->Ac, c->Ac32);
+    tgms::coarse_rt0_blocks(c);
+    build_rt0_stiffness(c);
+    tgms::factor_patches(c);
+    HIP_OK(hipStreamSynchronize(c->stream));
 }
 
 void solve_impl(tgms_ctx* c, const double* F, const double* g_bnd, double rtol, int maxit, double* u, double* p,
@@ -709,6 +708,10 @@ tgms_status tgms_solve(tgms_ctx* ctx, const double* F, const double* g_bnd, doub
     tgms_status st = TGMS_OK;
     tgms_status r = guarded([&] { solve_impl(ctx, F, g_bnd, rtol, maxit, u, p, iters, relres, &st); });
     return r != TGMS_OK ? r : st;
+}
+
+tgms_status tgms_update_mobility(tgms_ctx* ctx, const double* lambda) {
+    return guarded([&] { update_mobility_impl(ctx, lambda); });
 }
 
 tgms_status tgms_info(const tgms_ctx* c, tgms_info_t* info) {

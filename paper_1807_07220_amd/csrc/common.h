@@ -191,6 +191,15 @@ struct tgms_ctx {
     std::vector<double> alphas, betas;
     double t_setup_ms = 0, t_snap_ms = 0, t_eig_ms = 0, t_coarse_ms = 0, t_smoother_ms = 0;
     std::vector<DeviceBuf> owned;
+    Rect* blk_rects = nullptr;
+    double* Td = nullptr;      // coarse basis combination matrices (kept for mobility updates)
+    int* zcd = nullptr;
+    int* scratch_int = nullptr;
+    int* alloc_scratch_int() {
+        if (!scratch_int) scratch_int = alloc<int>(4);
+        HIP_OK(hipMemsetAsync(scratch_int, 0, 4 * sizeof(int), stream));
+        return scratch_int;
+    }
 
     template <typename T>
     T* alloc(size_t n) {
@@ -223,6 +232,7 @@ void enter(tgms_ctx* c);
 hipEvent_t take_event(tgms_ctx* c);  // from the profiling event pool
 // grid / vector kernels (k_grid.hip)
 void cell_weights(tgms_ctx* c, const double* kappa, int* bad);
+void mobility_weights(tgms_ctx* c, const double* lambda, int* bad);  // a = |c| kappa^{-1} / lambda
 void faces_A(tgms_ctx* c, const double* u, double* out);                    // A u on interior faces
 void faces_A_probe(tgms_ctx* c, const double* u, double* out);              // same, boundary inputs ignored
 void curlT_A_faces(tgms_ctx* c, const double* u, double* g, double scale);  // g = scale * C^T A u
@@ -255,6 +265,7 @@ void gram(tgms_ctx* c);
 void pencil_eig_q(tgms_ctx* c, double* Q);
 void coarse_local_run(tgms_ctx* c, const double* Tm, const int* zc);
 void coarse_rt0_blocks(tgms_ctx* c);
+void rt0_stiffness(tgms_ctx* c, double* K);
 // coarse apply (k_setup.hip)
 template <typename T>
 void coarse_apply(tgms_ctx* c, const T* g, T* z, bool accumulate, const double* sc);

@@ -118,7 +118,7 @@ static void factor_rects(tgms_ctx* c, Rect* rects, int count, int max_n, int max
                          float* L32) {
     size_t lds = (size_t)max_n * (max_b + 1) * sizeof(double);
     if (lds > 65536) throw TgmsError{TGMS_E_UNSUPPORTED, "local band factor exceeds 64 KiB of LDS"};
-    int* fail = c->alloc<int>(1);
+    int* fail = c->alloc_scratch_int();
     if (max_b - 1 > TGMS_MMAX) throw TgmsError{TGMS_E_UNSUPPORTED, "local rectangle wider than 33 cells"};
     if (L32)
         hipLaunchKernelGGL((k_band_factor<true>), dim3(count), dim3(TGMS_WAVE), lds, c->stream, rects, c->a, c->nx,
@@ -145,9 +145,11 @@ void factor_blocks(tgms_ctx* c) {
             q.off = (long long)(J * c->Nx + I) * btri_size(c->bx - 1, c->by - 1);
             q.voff = (long long)(J * c->Nx + I) * c->blk_n;
         }
-    Rect* d = c->alloc<Rect>(c->nblk);
-    HIP_OK(hipMemcpyAsync(d, r.data(), sizeof(Rect) * c->nblk, hipMemcpyHostToDevice, c->stream));
-    factor_rects(c, d, c->nblk, c->blk_n, c->blk_b, c->blkL, c->blkS, nullptr);
+    if (!c->blk_rects) {
+        c->blk_rects = c->alloc<Rect>(c->nblk);
+        HIP_OK(hipMemcpyAsync(c->blk_rects, r.data(), sizeof(Rect) * c->nblk, hipMemcpyHostToDevice, c->stream));
+    }
+    factor_rects(c, c->blk_rects, c->nblk, c->blk_n, c->blk_b, c->blkL, c->blkS, nullptr);
 }
 
 

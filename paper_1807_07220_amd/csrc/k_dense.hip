@@ -123,15 +123,31 @@ __global__ void __launch_bounds__(NT) k_potrf_diag(double* __restrict__ A, int l
         }
         __syncthreads();
     }
-    // X = L^{-1}: thread c < kb solves L x = e_c (rows c..kb-1) serially
-    if (tid < TB) {
-        const int cidx = tid;
-        for (int i = 0; i < TB; ++i) {
-            double s = (i == cidx) ? 1.0 : 0.0;
-            for (int k = cidx; k < i; ++k) s -= S[i][k] * X[k][cidx];
-            X[i][cidx] = (i < cidx) ? 0.0 : s / S[i][i];
+    // X = L^{-1} by a right-looking sweep over the pivots k: with R[i][k] = L[i][k] / L[k][k],
+    // U <- U - R[:, k] U[k, :] (rows below k), then X = diag(L)^{-1} U.  One barrier per pivot.
+    for (int r = 0; r < 4; ++r)
+        for (int q = 0; q < 4; ++q) {
+            const int i = ty + 16 * r, j = tx + 16 * q;
+            X[i][j] = (i == j) ? 1.0 : 0.0;
         }
+    __syncthreads();
+    for (int k = 0; k < kb; ++k) {
+        for (int r = 0; r < 4; ++r) {
+            const int i = ty + 16 * r;
+            if (i <= k || i >= kb) continue;
+            const double rik = S[i][k] / S[k][k];
+            for (int q = 0; q < 4; ++q) {
+                const int j = tx + 16 * q;
+                if (j <= k) X[i][j] -= rik * X[k][j];
+            }
+        }
+        __syncthreads();
     }
+    for (int r = 0; r < 4; ++r)
+        for (int q = 0; q < 4; ++q) {
+            const int i = ty + 16 * r, j = tx + 16 * q;
+            X[i][j] = (i < kb && j <= i) ? X[i][j] / S[i][i] : 0.0;
+        }
     __syncthreads();
     for (int r = 0; r < 4; ++r)
         for (int q = 0; q < 4; ++q) {

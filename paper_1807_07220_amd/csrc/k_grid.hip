@@ -29,6 +29,22 @@ __global__ void k_cell_weights(const double* __restrict__ kappa, double* __restr
     a32[c] = (float)(area * ki);
 }
 
+// cell weights under a mobility field: a = |c| kappa^{-1} / lambda (kinv kept from setup)
+__global__ void k_mobility_weights(const double* __restrict__ lambda, const double* __restrict__ kinv,
+                                   double* __restrict__ a, float* __restrict__ a32, long long n, double area,
+                                   int* __restrict__ bad) {
+    long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    double l = lambda[c];
+    if (!(l > 0.0) || !(l < INFINITY)) {
+        atomicOr(bad, 1);
+        l = 1.0;
+    }
+    const double w = area * kinv[c] / l;
+    a[c] = w;
+    a32[c] = (float)w;
+}
+
 // A u on interior faces (full numbering); boundary outputs 0.  use_bnd = 0
 // ignores the boundary entries of u (probe semantics), 1 includes them.
 __global__ void k_faces_A(const double* __restrict__ u, double* __restrict__ out, const double* __restrict__ a,
@@ -142,6 +158,13 @@ void cell_weights(tgms_ctx* c, const double* kappa, int* bad) {
     long long n = (long long)c->nx * c->ny;
     hipLaunchKernelGGL(k_cell_weights, dim3(nb(n)), dim3(256), 0, c->stream, kappa, c->kinv, c->a, c->a32, n,
                        c->hx * c->hy, bad);
+    LAUNCH_OK();
+}
+
+void mobility_weights(tgms_ctx* c, const double* lambda, int* bad) {
+    long long n = (long long)c->nx * c->ny;
+    hipLaunchKernelGGL(k_mobility_weights, dim3(nb(n)), dim3(256), 0, c->stream, lambda, (const double*)c->kinv, c->a,
+                       c->a32, n, c->hx * c->hy, bad);
     LAUNCH_OK();
 }
 

@@ -617,6 +617,51 @@ __global__ void k_rt0_blocks(BlockGeom G, const double* __restrict__ a, double* 
     }
 }
 
+// Coarse RT0 stream-function stiffness K_H = C_H^T A_H C_H on the interior coarse
+// vertices (dense, row-major; zero on entry).  Each coarse cell contributes a 4 x 4
+// block among its corners through its W/E/S/N face fluxes; one thread per vertex
+// sums the contributions to its own row (no atomics, fixed order).
+__global__ void k_rt0_stiffness(const double* __restrict__ AH0, int Nx, int Ny, double Hx, double Hy,
+                                double* __restrict__ K) {
+    const int nvx = Nx - 1, nv = (Nx - 1) * (Ny - 1);
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    const int Iv = v % nvx + 1, Jv = v / nvx + 1;
+    auto vid = [&](int I, int J) { return (I <= 0 || I >= Nx || J <= 0 || J >= Ny) ? -1 : (J - 1) * nvx + I - 1; };
+    double acc[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // neighbour offsets (dI, dJ) + 1
+    for (int Jc = Jv - 1; Jc <= Jv; ++Jc)
+        for (int Ic = Iv - 1; Ic <= Iv; ++Ic) {
+            const double* m = AH0 + 6 * ((long long)Jc * Nx + Ic);
+            // face flux of each basis field as combinations of corner stream-function values
+            const int vw[2] = {vid(Ic, Jc + 1), vid(Ic, Jc)};
+            const double ww[2] = {1 / Hy, -1 / Hy};
+            const int ve[2] = {vid(Ic + 1, Jc + 1), vid(Ic + 1, Jc)};
+            const int vs[2] = {vid(Ic + 1, Jc), vid(Ic, Jc)};
+            const double ws[2] = {-1 / Hx, 1 / Hx};
+            const int vn[2] = {vid(Ic + 1, Jc + 1), vid(Ic, Jc + 1)};
+            const int* fv[4] = {vw, ve, vs, vn};
+            const double* fw[4] = {ww, ww, ws, ws};
+            // (face a, face b, weight): W-W, W-E, E-W, E-E, S-S, S-N, N-S, N-N
+            const int pa[8] = {0, 0, 1, 1, 2, 2, 3, 3}, pb[8] = {0, 1, 0, 1, 2, 3, 2, 3};
+            const double pw[8] = {m[0], m[1], m[1], m[2], m[3], m[4], m[4], m[5]};
+            for (int t = 0; t < 8; ++t)
+                for (int p = 0; p < 2; ++p) {
+                    if (fv[pa[t]][p] != v) continue;
+                    for (int q = 0; q < 2; ++q) {
+                        const int wv = fv[pb[t]][q];
+                        if (wv < 0) continue;
+                        const int dI = wv % nvx + 1 - Iv, dJ = wv / nvx + 1 - Jv;
+                        acc[dJ + 1][dI + 1] += pw[t] * fw[pa[t]][p] * fw[pb[t]][q];
+                    }
+                }
+        }
+    for (int dJ = -1; dJ <= 1; ++dJ)
+        for (int dI = -1; dI <= 1; ++dI) {
+            const int wv = vid(Iv + dI, Jv + dJ);
+            if (wv >= 0) K[(long long)v * nv + wv] = acc[dJ + 1][dI + 1];
+        }
+}
+
 // ---- coarse apply in stream-function coordinates ----
 // Restriction W^T g per block into cy (one workgroup per block).
 template <typename T>
@@ -767,6 +812,13 @@ void coarse_local_run(tgms_ctx* c, const double* Tm, const int* zc) {
     }
     hipLaunchKernelGGL(k_coarse_W, dim3(c->nblk), dim3(256), 0, c->stream, G, c->APsi, Tm, c->mu, c->blk_nu, zc, c->W,
                        c->precision ? c->W32 : nullptr);
+    LAUNCH_OK();
+}
+
+void rt0_stiffness(tgms_ctx* c, double* K) {
+    const int nv = (c->Nx - 1) * (c->Ny - 1);
+    hipLaunchKernelGGL(k_rt0_stiffness, dim3((nv + 255) / 256), dim3(256), 0, c->stream, (const double*)c->AH0, c->Nx,
+                       c->Ny, c->bx * c->hx, c->by * c->hy, K);
     LAUNCH_OK();
 }
 

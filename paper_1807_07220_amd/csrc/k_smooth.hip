@@ -536,8 +536,7 @@ void factor_patches(tgms_ctx* c) {
     allow_lds<double>(c->lds_max);
     allow_lds<float>(c->lds_max);
     (void)hipGetLastError();
-    int* fail = c->alloc<int>(1);
-    HIP_OK(hipMemsetAsync(fail, 0, sizeof(int), c->stream));
+    int* fail = c->alloc_scratch_int();
     hipLaunchKernelGGL(k_patch_factor, dim3(c->nblk), dim3(64), lds, c->stream, c->patch, c->a, c->nx,
                        c->sx * c->sx, c->sy * c->sy, c->patL, fail);
     LAUNCH_OK();

@@ -236,3 +236,48 @@ def test_setup_and_solve_deterministic():
         s.close()
     assert outs[0][0] == outs[1][0]
     assert np.array_equal(outs[0][1], outs[1][1]) and np.array_equal(outs[0][2], outs[1][2])
+
+
+@pytest.mark.parametrize("name", ["rect36x24", "chan64"])
+def test_mobility_update(name):
+    """Mobility update with the coarse space kept: the library and the oracle rebuild
+    the same operator, smoother and coarse problem, and give the same solve."""
+    from oracle import Grid2D, OracleSolver
+    s, _, kappa = case(name)
+    nx, ny, bx, by, _, tol = CASES[name]
+    o = OracleSolver(Grid2D(nx, ny, bx, by), kappa, tol)  # a fresh oracle: it is modified
+    lam = fields.mobility_front(nx, ny, 0.7).ravel()
+    s.update_mobility(dev(lam.reshape(ny, nx)))
+    o.update_mobility(lam)
+    assert np.array_equal(s.counts(), o.counts)
+    rng = np.random.default_rng(4)
+    r = rng.standard_normal(o.g.nf) * o.mask
+    for which, ref in (("smoother", o.smooth), ("coarse", o.coarse), ("twogrid", o.twogrid)):
+        z = host(s.apply_precond(which, dev(r)))
+        assert rel(z, ref(r)) < PROBE_TOL[name], which
+    F = fields.corner_source(nx, ny).ravel()
+    res = s.solve(dev(F), rtol=1e-10)
+    ro = o.solve(F, rtol=1e-10)
+    assert res["converged"] and abs(res["iters"] - ro["iters"]) <= 1
+    assert np.linalg.norm(host(res["u"]) - ro["u"]) <= 1e-10 * np.linalg.norm(ro["u"])
+    assert np.linalg.norm(host(res["p"]) - ro["p"]) <= 1e-10 * np.linalg.norm(ro["p"])
+
+
+def test_mobility_update_unit_is_identity():
+    """lambda = 1 rebuilds the same factors: the solve is bitwise unchanged; an
+    invalid mobility is rejected."""
+    s, o, _ = case("cfg32")
+    F = dev(fields.corner_source(32, 32))
+    r0 = s.solve(F, rtol=1e-10)
+    s.update_mobility(dev(np.ones((32, 32))))
+    r1 = s.solve(F, rtol=1e-10)
+    assert r1["iters"] == r0["iters"]
+    assert torch.equal(r1["u"], r0["u"]) and torch.equal(r1["p"], r0["p"])
+    import paper_1807_07220_amd as tg
+    bad = np.ones((32, 32))
+    bad[3, 4] = -1.0
+    with pytest.raises(tg.TgmsError):
+        s.update_mobility(dev(bad))
+    s.update_mobility(dev(np.ones((32, 32))))
+    r2 = s.solve(F, rtol=1e-10)
+    assert torch.equal(r2["u"], r0["u"])

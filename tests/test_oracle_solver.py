@@ -137,3 +137,33 @@ def test_iterations_flat_over_contrast():
             its_ms.append(OracleSolver(g, kappa, 0.5, basis="msfem").solve(F, rtol=1e-8)["iters"])
     assert max(its) - min(its) <= 4, its
     assert max(its_ms) > max(its) + 4, (its, its_ms)
+
+
+def test_mobility_update_constant_scales_pressure():
+    """A constant mobility c scales A by 1/c: the velocity is unchanged and the
+    pressure of A v = B^T p scales by 1/c (the kept basis and the two-grid cycle
+    scale consistently, so PCG takes the same iterations)."""
+    g, kappa, o = _small(seed=5)
+    F = fields.random_source(g.nx, g.ny, 3).ravel()
+    r0 = o.solve(F, rtol=1e-12)
+    o.update_mobility(np.full(g.nc, 4.0))
+    r1 = o.solve(F, rtol=1e-12)
+    assert abs(r1["iters"] - r0["iters"]) <= 1
+    assert np.linalg.norm(r1["u"] - r0["u"]) <= 1e-10 * np.linalg.norm(r0["u"])
+    assert np.linalg.norm(r1["p"] - r0["p"] / 4.0) <= 1e-10 * np.linalg.norm(r0["p"] / 4.0)
+
+
+def test_mobility_update_reaches_exact_solution_of_new_operator():
+    """With the basis of the initial permeability kept, PCG on the updated operator
+    still converges to the exact discrete solution for permeability lambda * kappa."""
+    g, kappa, o = _small(seed=6)
+    lam = fields.mobility_front(g.nx, g.ny, 0.6).ravel()
+    o.update_mobility(lam)
+    F = fields.corner_source(g.nx, g.ny).ravel()
+    r = o.solve(F, rtol=1e-13, maxit=400)
+    ue, pe = exact_solve(g, kappa * lam.reshape(kappa.shape), F)
+    assert np.linalg.norm(r["u"] - ue) <= 1e-9 * np.linalg.norm(ue)
+    assert np.linalg.norm(r["p"] - pe) <= 1e-9 * np.linalg.norm(pe)
+    # the coarse space is the one built for kappa: counts unchanged
+    o0 = OracleSolver(g, kappa, 0.5)
+    assert np.array_equal(o.counts, o0.counts)

@@ -151,3 +151,18 @@ def random_source(nx, ny, seed):
     rng = _rng(seed)
     f = rng.standard_normal((ny, nx))
     return f - f.mean()
+
+
+def mobility_front(nx, ny, t, mu_ratio=5.0, width=0.05):
+    """Total mobility of a water front advancing from the cell-(0,0) corner.
+
+    Water saturation s = 1 / (1 + exp((r - t) / width)) with r the distance of the
+    cell centre from (0, 0) and t in [0, sqrt(2)] the front position; quadratic
+    relative permeabilities k_w = s^2, k_o = (1 - s)^2 and viscosities 1 (water)
+    and mu_ratio (oil): lambda = s^2 + (1 - s)^2 / mu_ratio (a synthetic stand-in for
+    the mobility of a transport step).
+    """
+    x, y = _cell_centres(nx, ny)
+    r = np.sqrt(x ** 2 + y ** 2)
+    s = 1.0 / (1.0 + np.exp(np.clip((r - t) / width, -60.0, 60.0)))
+    return s ** 2 + (1.0 - s) ** 2 / mu_ratio
