@@ -69,6 +69,10 @@ typedef struct {
     void* stream;      /* hipStream_t to run on; NULL = the default stream */
     int graphs;        /* 1: PCG iterations replayed from a captured HIP graph (falls back to
                           direct launches if capture fails); 0: every kernel launched directly */
+    int autotune;      /* 1: time the candidate launch configurations (reduction grid, smoother
+                          staging) at setup, once per shape and device; 0: fixed defaults */
+    const char* tune_cache;  /* file keeping tuned configurations across processes (read and
+                                rewritten by setup); NULL: keep them in this process only */
 } tgms_options;
 
 typedef struct {
@@ -80,11 +84,14 @@ typedef struct {
     double t_snap_ms, t_eig_ms, t_coarse_ms, t_smoother_ms;  /* setup phases */
     int lds_max;          /* LDS bytes per workgroup the device allows (picks the smoother kernel) */
     int pcg_graph;        /* last solve: 0 kernels launched directly, 1 iterations replayed from a
-                             HIP graph, 2 the same with event timing recorded inside the graph */
+                             HIP graph */
+    int tuned;            /* launch configuration: 0 defaults, 1 timed at this setup, 2 from the cache */
+    int nred;             /* workgroups of the reducing PCG kernels */
+    int smooth_staged;    /* smoother factor: 1 staged in LDS, 0 read from global, -1 by LDS fit */
 } tgms_info_t;
 
 /* Paper defaults: eta 0.2, overlap 2, FP64, s_scale = |K|^(1/2), default stream,
- * graph replay on. */
+ * graph replay on, autotuning on without a cache file. */
 void tgms_default_options(tgms_options* opt);
 
 /*

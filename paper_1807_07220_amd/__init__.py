@@ -35,7 +35,7 @@ class Solver:
 
     def __init__(self, kappa: torch.Tensor, bx: int, by: int, eig_tol: float, eta: float = 0.2, overlap: int = 2,
                  precision: str = "fp64", s_scale: float = 0.0, stream: torch.cuda.Stream | None = None,
-                 graphs: bool = True):
+                 graphs: bool = True, autotune: bool = True, tune_cache: str | None = None):
         lib = load()
         if kappa.dim() != 2:
             raise ValueError("kappa must be (ny, nx)")
@@ -49,6 +49,9 @@ class Solver:
         opt.precision = {"fp64": 0, "mixed": 1}[precision]
         opt.stream = ctypes.c_void_p(self.stream.cuda_stream)
         opt.graphs = 1 if graphs else 0
+        opt.autotune = 1 if autotune else 0
+        self._tune_cache = None if tune_cache is None else str(tune_cache).encode()
+        opt.tune_cache = self._tune_cache
         grid = Grid(self.nx, self.ny, self.bx, self.by)
         handle = ctypes.c_void_p()
         kappa = kappa.contiguous()

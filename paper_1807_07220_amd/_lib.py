@@ -31,13 +31,14 @@ class Grid(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("eta", c_double), ("overlap", c_int), ("precision", c_int), ("s_scale", c_double),
-                ("stream", c_void_p), ("graphs", c_int)]
+                ("stream", c_void_p), ("graphs", c_int), ("autotune", c_int), ("tune_cache", c_char_p)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("n_coarse_faces", c_int), ("n_blocks", c_int), ("dim", c_int), ("n_coarse_spd", c_int),
                 ("t_setup_ms", c_double), ("t_snap_ms", c_double), ("t_eig_ms", c_double),
-                ("t_coarse_ms", c_double), ("t_smoother_ms", c_double), ("lds_max", c_int), ("pcg_graph", c_int)]
+                ("t_coarse_ms", c_double), ("t_smoother_ms", c_double), ("lds_max", c_int), ("pcg_graph", c_int),
+                ("tuned", c_int), ("nred", c_int), ("smooth_staged", c_int)]
 
 
 _lib = None

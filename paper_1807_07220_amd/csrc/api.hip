@@ -502,6 +502,7 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         c->part = c->alloc<double>(3 * (size_t)tgms::pcg_tiles(c));
         c->vp1 = c->alloc<double>(nvtx);
         HIP_OK(hipHostMalloc((void**)&c->red_h, SC_COUNT * sizeof(double), hipHostMallocDefault));
+        if (o.autotune) tgms::autotune(c, o.tune_cache);
         HIP_OK(hipStreamSynchronize(c->stream));
         c->t_setup_ms = total.ms();
         *out = c;
@@ -695,6 +696,8 @@ void tgms_default_options(tgms_options* opt) {
     opt->s_scale = 0.0;
     opt->stream = nullptr;
     opt->graphs = 1;
+    opt->autotune = 1;
+    opt->tune_cache = nullptr;
 }
 
 tgms_status tgms_setup(const tgms_grid* grid, const double* kappa, double eig_tol, const tgms_options* opt,
@@ -732,6 +735,9 @@ tgms_status tgms_info(const tgms_ctx* c, tgms_info_t* info) {
     info->t_smoother_ms = c->t_smoother_ms;
     info->lds_max = c->lds_max;
     info->pcg_graph = c->last_graph;
+    info->tuned = c->tuned;
+    info->nred = c->nred;
+    info->smooth_staged = c->smooth_staged;
     return TGMS_OK;
 }
 

@@ -170,6 +170,10 @@ struct tgms_ctx {
     double* hist = nullptr;   // device alpha/beta history
     int hist_cap = 0;
     double* part = nullptr;   // per-workgroup partial sums of the fused PCG kernels
+    int nred = 256;           // workgroups of the reducing PCG kernels (autotuned)
+    int smooth_staged = -1;   // smoother: 1 factor staged in LDS, 0 read from global, -1 by LDS fit
+    int snap_cols = 1;        // snapshots: 1 one lane per column where supported, 0 one wave per block
+    int tuned = 0;            // 0 defaults, 1 timed at setup, 2 taken from the tuning cache
     double* vp1 = nullptr;    // second search-direction buffer (p alternates between vp and vp1)
     hipGraphExec_t iter_graph = nullptr;  // two captured PCG iterations
     bool graph_failed = false;
@@ -250,6 +254,8 @@ template <typename T>
 void smooth_patches(tgms_ctx* c, const T* g, const double* sc);  // local solves of S g into the patch pool
 // fused PCG / two-grid kernels (k_pcg.hip); sc: skip when the done flag is set (may be null)
 unsigned pcg_tiles(tgms_ctx* c);
+int nred_max();
+void autotune(tgms_ctx* c, const char* cache_path);  // picks nred, smoother staging (k_tune.hip)
 void dir_apply(tgms_ctx* c, const double* z, const double* pin, double* pout, double* q);
 void update(tgms_ctx* c, const double* p, const double* q, double* x, double* g, double* gold, float* g32);
 template <typename T>

@@ -7,9 +7,9 @@
 //   z = B_TG g                                             (smoother, k_gather_res, coarse, residual,
 //                                                            smoother, k_gather_final)
 //   rho' = g.z, beta = rho'/rho (or (g.z - gold.z)/rho), |C z|^2  (k_gather_final)
-// The kernels that form inner products run on a fixed grid of NRED workgroups
-// that loop over the tiles, and write one partial sum per workgroup; the next
-// kernel sums those NRED partials in a fixed order (so results do not depend on
+// The kernels that form inner products run on a fixed grid of nred <= NRED
+// workgroups (chosen by the autotuner) that loop over the tiles, and write one
+// partial sum per workgroup; the next kernel sums those partials in a fixed order (so results do not depend on
 // scheduling, and the kernel boundary makes the partials visible without device
 // fences).  Every kernel first checks the done flag in sc and returns when it is
 // set, so iterations queued after convergence cost only their launches.
@@ -43,12 +43,12 @@ __device__ inline void group_sum(double (&v)[NV]) {
     __syncthreads();
 }
 
-constexpr int NRED = 256;  // workgroups of the reducing kernels (one partial each)
+constexpr int NRED = 256;  // most workgroups of a reducing kernel (stride of the partial arrays)
 
-// Sum of the NRED partials of array k, in fixed order, returned to every thread.
-__device__ inline double sum_partials(const double* __restrict__ part, int k) {
+// Sum of the nred partials of array k, in fixed order, returned to every thread.
+__device__ inline double sum_partials(const double* __restrict__ part, int k, int nred) {
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
-    double v[1] = {tid < NRED ? part[k * NRED + tid] : 0.0};
+    double v[1] = {tid < nred ? part[k * NRED + tid] : 0.0};
     group_sum<1>(v);
     return v[0];
 }
@@ -70,7 +70,7 @@ __device__ inline T stencil_tile(const T (&P)[TY + 2][TX + 2], int tx, int ty, c
 }
 
 // p_out = z + beta p_in (beta = 0 on the first iteration), q = K p_out, and the
-// workgroup's partial sum of p_out . q.  NRED workgroups loop over the tiles.
+// workgroup's partial sum of p_out . q.  The workgroups loop over the tiles.
 __global__ void __launch_bounds__(NT) k_dir_apply(const double* __restrict__ z, const double* __restrict__ pin,
                                                   double* __restrict__ pout, double* __restrict__ q,
                                                   const double* __restrict__ a, int nx, int ny, double sx2,
@@ -114,12 +114,12 @@ __global__ void __launch_bounds__(NT) k_dir_apply(const double* __restrict__ z, 
 // workgroup 0 records it), then x += alpha p ; gold = g (flexible) ; g -= alpha q ;
 // g32 = (float) g (mixed precision).  A non-positive p . q stops the iteration.
 __global__ void __launch_bounds__(NT) k_update(long long n, double* __restrict__ sc, double* __restrict__ hist,
-                                               const double* __restrict__ part, const double* __restrict__ p,
+                                               const double* __restrict__ part, int nred, const double* __restrict__ p,
                                                const double* __restrict__ q, double* __restrict__ x,
                                                double* __restrict__ g, double* __restrict__ gold,
                                                float* __restrict__ g32) {
     if (finished(sc)) return;
-    const double pq = sum_partials(part, 0);
+    const double pq = sum_partials(part, 0, nred);
     const double al = sc[SC_RHO] / pq;
     const bool bad = !(pq > 0.0) || !(pq < INFINITY);
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
@@ -204,7 +204,7 @@ __global__ void __launch_bounds__(NT) k_gather_res(const Rect* __restrict__ rect
 
 // Last smoothing of the two-grid cycle: z = zin + eta * sum_i ext(w_i) (zin may be
 // null), written as FP64.  With part: the workgroup's partial sums of g.z, gold.z
-// and |C z|^2 (NRED workgroups loop over the tiles).
+// and |C z|^2 (the workgroups loop over the tiles).
 template <typename T>
 __global__ void __launch_bounds__(NT) k_gather_final(const Rect* __restrict__ rects, const T* __restrict__ w,
                                                      const T* __restrict__ w4, GatherGeom G, T eta, const T* __restrict__ zin,
@@ -262,9 +262,10 @@ __global__ void __launch_bounds__(NT) k_gather_final(const Rect* __restrict__ re
 // rho, beta, the relative residual, the iteration count and the done flag from the
 // partials of k_gather_final (first: rho_0 and |z_0|^2).  One workgroup.
 __global__ void __launch_bounds__(NT) k_finalize(double* __restrict__ sc, double* __restrict__ hist,
-                                                 const double* __restrict__ part, int first) {
+                                                 const double* __restrict__ part, int nred, int first) {
     if (finished(sc)) return;
-    const double gz = sum_partials(part, 0), zgold = sum_partials(part, 1), zn2 = sum_partials(part, 2);
+    const double gz = sum_partials(part, 0, nred), zgold = sum_partials(part, 1, nred),
+                 zn2 = sum_partials(part, 2, nred);
     if (threadIdx.x != 0 || threadIdx.y != 0) return;
     if (first) {
         sc[SC_RHO] = gz;
@@ -324,18 +325,19 @@ inline const T* slots(tgms_ctx* c) {
 namespace tgms {
 
 unsigned pcg_tiles(tgms_ctx*) { return NRED; }
+int nred_max() { return NRED; }
 
 void dir_apply(tgms_ctx* c, const double* z, const double* pin, double* pout, double* q) {
     ProfScope ps(c, PK_APPLYK);
-    hipLaunchKernelGGL(k_dir_apply, dim3(NRED), dim3(TX, TY), 0, c->stream, z, pin, pout, q, (const double*)c->a,
+    hipLaunchKernelGGL(k_dir_apply, dim3(c->nred), dim3(TX, TY), 0, c->stream, z, pin, pout, q, (const double*)c->a,
                        c->nx, c->ny, c->sx * c->sx, c->sy * c->sy, (const double*)c->sc, c->part);
     LAUNCH_OK();
 }
 
 void update(tgms_ctx* c, const double* p, const double* q, double* x, double* g, double* gold, float* g32) {
     const long long n = (long long)c->nx * c->ny;
-    hipLaunchKernelGGL(k_update, dim3(NRED), dim3(TX, TY), 0, c->stream, n, c->sc, c->hist, (const double*)c->part,
-                       p, q, x, g, gold, g32);
+    hipLaunchKernelGGL(k_update, dim3(c->nred), dim3(TX, TY), 0, c->stream, n, c->sc, c->hist, (const double*)c->part,
+                       c->nred, p, q, x, g, gold, g32);
     LAUNCH_OK();
 }
 
@@ -354,7 +356,7 @@ void gather_final(tgms_ctx* c, const T* w, const T* zin, double* zout, const dou
                   bool with_dots, bool first) {
     const double* sc = with_dots ? c->sc : nullptr;
     if (with_dots)
-        hipLaunchKernelGGL((k_gather_final<T>), dim3(NRED), dim3(TX, TY), 0, c->stream, c->patch, w, slots<T>(c),
+        hipLaunchKernelGGL((k_gather_final<T>), dim3(c->nred), dim3(TX, TY), 0, c->stream, c->patch, w, slots<T>(c),
                            ggeom(c), T(c->eta), zin, zout, c->sx, c->sy, g, gold, sc, c->part);
     else
         hipLaunchKernelGGL((k_gather_final<T>), dim3(tiles(c).x * tiles(c).y), dim3(TX, TY), 0, c->stream, c->patch,
@@ -362,7 +364,7 @@ void gather_final(tgms_ctx* c, const T* w, const T* zin, double* zout, const dou
     LAUNCH_OK();
     if (with_dots) {
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(TX, TY), 0, c->stream, c->sc, c->hist, (const double*)c->part,
-                           first ? 1 : 0);
+                           c->nred, first ? 1 : 0);
         LAUNCH_OK();
     }
 }

@@ -754,7 +754,7 @@ void snapshots(tgms_ctx* c) {
     const long long fsz = btri_size(m, mh);
     const size_t lds_cols =
         sizeof(double) * ((((fsz > 32 * 64 ? fsz : 32 * 64) + 1) & ~1LL) + c->bx * c->by + 1 + (size_t)m * mh * 64);
-    if (c->ncol <= 64 && lds_cols <= (size_t)c->lds_max) {
+    if (c->snap_cols && c->ncol <= 64 && lds_cols <= (size_t)c->lds_max) {
         switch (m) {
             case 3: launch_snap_cols<3>(c, G, lds_cols); LAUNCH_OK(); return;
             case 5: launch_snap_cols<5>(c, G, lds_cols); LAUNCH_OK(); return;

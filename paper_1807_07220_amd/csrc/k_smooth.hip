@@ -561,7 +561,7 @@ void smooth_patches(tgms_ctx* c, const T* g, const double* sc) {
     }
     const size_t work = (size_t)(2 * ((c->pat_nmax + 3) & ~3) + 2 * 64) * sizeof(T);
     const size_t staged = (size_t)((c->pat_fmax + 3) & ~3LL) * sizeof(T) + work;
-    const bool fits = staged <= (size_t)c->lds_max;
+    const bool fits = staged <= (size_t)c->lds_max && c->smooth_staged != 0;
     dispatch_twisted<T>(c, c->pat_m1, c->pat_m2, fits, L, g, w, fits ? staged : work, sc);
     LAUNCH_OK();
 }

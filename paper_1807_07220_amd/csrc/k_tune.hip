@@ -1,0 +1,136 @@
+// Autotuner: picks, per problem shape and device, the launch configuration of
+// the kernels whose best shape is not known in advance, by timing every
+// candidate on the context's own data once (HIP events) and keeping the
+// fastest.  Results are kept per process and, when a path is given, in a small
+// text file (one "shape nred staged" line per shape) so that later setups of the
+// same shape skip the timing.
+//
+// Tuned:
+//   nred           workgroups of the reducing PCG kernels (64, 128, 256): fewer
+//                  partials to sum against more tiles per workgroup;
+//   smooth_staged  smoother patch factor staged in LDS with 16-byte copies, or
+//                  read by the chains from global memory.
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "common.h"
+
+namespace {
+
+struct TuneRec {
+    int nred = 256;
+    int staged = 1;
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, TuneRec> g_tune;
+
+std::string tune_key(tgms_ctx* c) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "%s/%dx%d/b%dx%d/ov%d/p%d", arch.c_str(), c->nx, c->ny, c->bx, c->by, c->overlap,
+                  c->precision);
+    return buf;
+}
+
+// the cache file: one line per shape, "key nred staged"
+void load_cache(const char* path) {
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char key[256];
+    int nred = 0, staged = 0;
+    while (std::fscanf(f, "%255s %d %d", key, &nred, &staged) == 3) {
+        if (nred >= 1 && nred <= tgms::nred_max() && (staged == 0 || staged == 1)) g_tune[key] = TuneRec{nred, staged};
+    }
+    std::fclose(f);
+}
+
+void save_cache(const char* path) {
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "w");
+    if (!f) return;
+    for (auto& kv : g_tune) std::fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.nred, kv.second.staged);
+    std::fclose(f);
+}
+
+template <typename F>
+double time_ms(tgms_ctx* c, int reps, F&& body) {
+    hipEvent_t a, b;
+    HIP_OK(hipEventCreate(&a));
+    HIP_OK(hipEventCreate(&b));
+    body();  // warm-up
+    HIP_OK(hipEventRecord(a, c->stream));
+    for (int r = 0; r < reps; ++r) body();
+    HIP_OK(hipEventRecord(b, c->stream));
+    HIP_OK(hipEventSynchronize(b));
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms / reps;
+}
+
+}  // namespace
+
+namespace tgms {
+
+void autotune(tgms_ctx* c, const char* cache_path) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    load_cache(cache_path);
+    const std::string key = tune_key(c);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+        c->nred = it->second.nred;
+        c->smooth_staged = it->second.staged;
+        c->tuned = 2;
+        return;
+    }
+    const long long nv = (long long)c->nx * c->ny;
+    // scalars that let the PCG kernels run (done flag clear), on zero vectors
+    for (int k = 0; k < SC_COUNT; ++k) c->red_h[k] = 0.0;
+    c->red_h[SC_MAXIT] = 1e9;
+    c->red_h[SC_RTOL2] = 0.0;
+    HIP_OK(hipMemcpyAsync(c->sc, c->red_h, SC_COUNT * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    zero(c, c->vz, sizeof(double) * nv);
+    zero(c, c->vp, sizeof(double) * nv);
+    zero(c, c->vg, sizeof(double) * nv);
+    TuneRec best;
+    double tbest = 1e30;
+    for (int nred : {64, 128, 256}) {
+        c->nred = nred;
+        const double t = time_ms(c, 5, [&] { dir_apply(c, c->vz, c->vp, c->vp1, c->vq); });
+        if (t < tbest) {
+            tbest = t;
+            best.nred = nred;
+        }
+    }
+    c->nred = best.nred;
+    // smoother: staged copy vs direct reads (only a choice where the staged form fits)
+    const bool prec32 = c->precision != 0;
+    double ts[2] = {1e30, 1e30};
+    for (int st = 0; st < 2; ++st) {
+        c->smooth_staged = st;
+        ts[st] = time_ms(c, 3, [&] {
+            if (prec32)
+                smooth_patches<float>(c, c->fz, nullptr);
+            else
+                smooth_patches<double>(c, c->vz, nullptr);
+        });
+    }
+    best.staged = ts[1] <= ts[0] ? 1 : 0;
+    c->smooth_staged = best.staged;
+    HIP_OK(hipStreamSynchronize(c->stream));
+    c->tuned = 1;
+    g_tune[key] = best;
+    save_cache(cache_path);
+}
+
+}  // namespace tgms

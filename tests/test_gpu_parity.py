@@ -281,3 +281,31 @@ def test_mobility_update_unit_is_identity():
     s.update_mobility(dev(np.ones((32, 32))))
     r2 = s.solve(F, rtol=1e-10)
     assert torch.equal(r2["u"], r0["u"])
+
+
+def test_autotune_cache(tmp_path):
+    """The autotuner times the candidate launch configurations once per shape, keeps
+    them in the cache file, and later setups of the shape take them from there; the
+    tuned solver still matches the oracle."""
+    import paper_1807_07220_amd as tg
+    from oracle import Grid2D, OracleSolver
+    nx, ny, bx, by = 40, 24, 8, 8
+    kappa = np.exp(np.random.default_rng(21).standard_normal((ny, nx)))
+    cache = tmp_path / "tune.txt"
+    s1 = tg.Solver(dev(kappa), bx, by, 0.5, tune_cache=str(cache))
+    i1 = s1.info()
+    assert i1["tuned"] in (1, 2) and i1["nred"] in (64, 128, 256) and i1["smooth_staged"] in (0, 1)
+    text = cache.read_text()
+    assert "40x24/b8x8" in text
+    s2 = tg.Solver(dev(kappa), bx, by, 0.5, tune_cache=str(cache))
+    i2 = s2.info()
+    assert i2["tuned"] == 2 and i2["nred"] == i1["nred"] and i2["smooth_staged"] == i1["smooth_staged"]
+    s0 = tg.Solver(dev(kappa), bx, by, 0.5, autotune=False)
+    assert s0.info()["tuned"] == 0
+    o = OracleSolver(Grid2D(nx, ny, bx, by), kappa, 0.5)
+    F = fields.corner_source(nx, ny).ravel()
+    ro = o.solve(F, rtol=1e-10)
+    for s in (s1, s2, s0):
+        r = s.solve(dev(F), rtol=1e-10)
+        assert abs(r["iters"] - ro["iters"]) <= 1
+        assert np.linalg.norm(host(r["u"]) - ro["u"]) <= 1e-10 * np.linalg.norm(ro["u"])
