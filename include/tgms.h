@@ -163,6 +163,14 @@ tgms_status tgms_last_cond(const tgms_ctx* ctx, double* cond);
 tgms_status tgms_profile(tgms_ctx* ctx, int enable);
 tgms_status tgms_profile_get(tgms_ctx* ctx, int kernel, int* launches, double* total_ms);
 
+/* Kernel-only timing of the smoother patch solve: `reps` back-to-back launches
+ * (after one untimed launch) on the context's stream over the context's own
+ * work vector, bracketed by one HIP event pair; *avg_ms = elapsed / reps.  The
+ * launches do the full work whatever the vector holds (the device done flag is
+ * not consulted).  Requires a completed setup.  reps in [1, 100000], else
+ * TGMS_E_INVAL.  Blocks the host until the launches have finished. */
+tgms_status tgms_time_smoother(tgms_ctx* ctx, int reps, double* avg_ms);
+
 void tgms_destroy(tgms_ctx* ctx);
 const char* tgms_last_error(void);
 

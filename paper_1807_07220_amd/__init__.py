@@ -117,6 +117,13 @@ class Solver:
         check(load().tgms_profile_get(self._h, self.KERNELS[kernel], ctypes.byref(n), ctypes.byref(t)))
         return n.value, t.value
 
+    def time_smoother(self, reps: int = 200) -> float:
+        """Average duration (ms) of one smoother patch-solve launch over `reps`
+        back-to-back launches bracketed by one HIP event pair."""
+        ms = ctypes.c_double(0.0)
+        check(load().tgms_time_smoother(self._h, int(reps), ctypes.byref(ms)))
+        return ms.value
+
     # ---- probes -----------------------------------------------------------
     def apply_A(self, x: torch.Tensor) -> torch.Tensor:
         y = torch.empty_like(x)

@@ -55,6 +55,7 @@ SIGNATURES = {
     "tgms_last_cond": (c_int, [c_void_p, ctypes.POINTER(c_double)]),
     "tgms_profile": (c_int, [c_void_p, c_int]),
     "tgms_profile_get": (c_int, [c_void_p, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_double)]),
+    "tgms_time_smoother": (c_int, [c_void_p, c_int, ctypes.POINTER(c_double)]),
     "tgms_destroy": (None, [c_void_p]),
     "tgms_last_error": (c_char_p, []),
     "tgms_apply_A": (c_int, [c_void_p, c_void_p, c_void_p]),

@@ -128,20 +128,13 @@ double lanczos_cond(const std::vector<double>& al, const std::vector<double>& be
     return mn > 0 ? mx / mn : INFINITY;
 }
 
-template <typename T>
-const T* cell_a(tgms_ctx* c) {
-    if constexpr (sizeof(T) == 8)
-        return c->a;
-    else
-        return c->a32;
-}
-
 // z = B_TG g (paper section 5): pre-smoothing, coarse correction, post-smoothing,
 // with the residual recomputed after each.  g: the right-hand side in the
-// preconditioner's precision (T); z: FP64 output.  With dots, the final gather
-// also forms the PCG scalars from g64 (and gold for the flexible variant).
+// preconditioner's precision (T), gd: the same right-hand side in FP64 (the
+// residuals are formed in FP64 from it); z: FP64 output.  With dots, the final
+// gather also forms the PCG scalars from gd (and gold for the flexible variant).
 template <typename T>
-void twogrid(tgms_ctx* c, const T* g, double* z, const double* g64, const double* gold, bool dots, bool first) {
+void twogrid(tgms_ctx* c, const T* g, const double* gd, double* z, const double* gold, bool dots, bool first) {
     const double* sc = dots ? c->sc : nullptr;
     T *w, *z1, *t;
     if constexpr (sizeof(T) == 8) {
@@ -154,11 +147,11 @@ void twogrid(tgms_ctx* c, const T* g, double* z, const double* g64, const double
         t = (T*)c->ft;
     }
     tgms::smooth_patches<T>(c, g, sc);
-    tgms::gather_res<T>(c, w, g, cell_a<T>(c), z1, t, sc);
+    tgms::gather_res<T>(c, w, gd, z1, t, sc);
     tgms::coarse_apply<T>(c, t, z1, true, sc);
-    tgms::residual<T>(c, z1, g, t, cell_a<T>(c), sc);
+    tgms::residual<T>(c, z1, gd, t, sc);
     tgms::smooth_patches<T>(c, t, sc);
-    tgms::gather_final<T>(c, w, z1, z, g64, gold, dots, first);
+    tgms::gather_final<T>(c, w, z1, z, dots ? gd : nullptr, gold, dots, first);
 }
 
 // probes: which = 0 smoother, 1 coarse correction, 2 two-grid; g, z FP64 vertex arrays
@@ -171,7 +164,7 @@ void precond(tgms_ctx* c, int which, const double* g, double* z) {
         } else if (which == 1) {
             tgms::coarse_apply<double>(c, g, z, false, nullptr);
         } else {
-            twogrid<double>(c, g, z, nullptr, nullptr, false, false);
+            twogrid<double>(c, g, g, z, nullptr, false, false);
         }
     } else {
         tgms::cast_d2f(c, nv, g, c->fg);
@@ -182,7 +175,7 @@ void precond(tgms_ctx* c, int which, const double* g, double* z) {
             tgms::coarse_apply<float>(c, c->fg, c->fz, false, nullptr);
             tgms::cast_f2d(c, nv, c->fz, z);
         } else {
-            twogrid<float>(c, c->fg, z, nullptr, nullptr, false, false);
+            twogrid<float>(c, c->fg, g, z, nullptr, false, false);
         }
     }
 }
@@ -343,7 +336,6 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         Timer total(c->stream);
         c->kinv = c->alloc<double>(ncell);
         c->a = c->alloc<double>(ncell);
-        c->a32 = c->alloc<float>(ncell);
         int* bad = c->alloc<int>(1);
         tgms::cell_weights(c, kappa, bad);
         int hbad = 0;
@@ -580,17 +572,17 @@ void solve_impl(tgms_ctx* c, const double* F, const double* g_bnd, double rtol, 
     c->prof_iter = 0;
     if (flexible) {
         tgms::cast_d2f(c, nv, c->vg, c->fg);
-        twogrid<float>(c, c->fg, c->vz, c->vg, nullptr, true, true);
+        twogrid<float>(c, c->fg, c->vg, c->vz, nullptr, true, true);
     } else {
-        twogrid<double>(c, c->vg, c->vz, c->vg, nullptr, true, true);
+        twogrid<double>(c, c->vg, c->vg, c->vz, nullptr, true, true);
     }
     auto iteration = [&](const double* pin, double* pout) {
         tgms::dir_apply(c, c->vz, pin, pout, c->vq);
         tgms::update(c, pout, c->vq, c->vx, c->vg, flexible ? c->vgold : nullptr, flexible ? c->fg : nullptr);
         if (flexible)
-            twogrid<float>(c, c->fg, c->vz, c->vg, c->vgold, true, false);
+            twogrid<float>(c, c->fg, c->vg, c->vz, c->vgold, true, false);
         else
-            twogrid<double>(c, c->vg, c->vz, c->vg, nullptr, true, false);
+            twogrid<double>(c, c->vg, c->vg, c->vz, nullptr, true, false);
     };
     const bool use_graph = !c->prof && !c->graph_failed;
     if (use_graph && !c->iter_graph) {
@@ -784,6 +776,38 @@ tgms_status tgms_profile(tgms_ctx* c, int enable) {
             c->prof_acc_ms[k] = 0.0;
             c->prof_acc_n[k] = 0;
         }
+    });
+}
+
+tgms_status tgms_time_smoother(tgms_ctx* c, int reps, double* avg_ms) {
+    if (!c || !avg_ms || reps < 1 || reps > 100000) {
+        g_last_error = "bad argument";
+        return TGMS_E_INVAL;
+    }
+    return guarded([&] {
+        tgms::enter(c);
+        const bool prof = c->prof;
+        c->prof = false;
+        auto body = [&] {
+            if (c->precision != 0)
+                tgms::smooth_patches<float>(c, c->fz, nullptr);
+            else
+                tgms::smooth_patches<double>(c, c->vz, nullptr);
+        };
+        hipEvent_t a, b;
+        HIP_OK(hipEventCreate(&a));
+        HIP_OK(hipEventCreate(&b));
+        body();  // warm-up
+        HIP_OK(hipEventRecord(a, c->stream));
+        for (int r = 0; r < reps; ++r) body();
+        HIP_OK(hipEventRecord(b, c->stream));
+        HIP_OK(hipEventSynchronize(b));
+        float ms = 0.f;
+        HIP_OK(hipEventElapsedTime(&ms, a, b));
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        c->prof = prof;
+        *avg_ms = ms / reps;
     });
 }
 

@@ -99,7 +99,6 @@ struct tgms_ctx {
     // cell data
     double* kinv = nullptr;  // kappa^{-1}
     double* a = nullptr;     // |c| kappa^{-1}
-    float* a32 = nullptr;
     // block (K_i) stream-function factors
     int blk_m, blk_n, blk_b;  // m = bx-1 columns, n = (bx-1)(by-1), b = bx
     double* blkL = nullptr;   // nblk * n * (b+1)
@@ -259,12 +258,12 @@ void autotune(tgms_ctx* c, const char* cache_path);  // picks nred, smoother sta
 void dir_apply(tgms_ctx* c, const double* z, const double* pin, double* pout, double* q);
 void update(tgms_ctx* c, const double* p, const double* q, double* x, double* g, double* gold, float* g32);
 template <typename T>
-void gather_res(tgms_ctx* c, const T* w, const T* g, const T* a, T* z, T* t, const double* sc);
+void gather_res(tgms_ctx* c, const T* w, const double* g, T* z, T* t, const double* sc);
 template <typename T>
 void gather_final(tgms_ctx* c, const T* w, const T* zin, double* zout, const double* g, const double* gold,
                   bool with_dots, bool first);
 template <typename T>
-void residual(tgms_ctx* c, const T* z, const T* g, T* t, const T* a, const double* sc);
+void residual(tgms_ctx* c, const T* z, const double* g, T* t, const double* sc);
 // setup (k_setup.hip)
 void snapshots(tgms_ctx* c);
 void gram(tgms_ctx* c);

@@ -14,8 +14,7 @@ namespace {
 constexpr int TX = 64, TY = 4;
 
 __global__ void k_cell_weights(const double* __restrict__ kappa, double* __restrict__ kinv,
-                               double* __restrict__ a, float* __restrict__ a32, long long n, double area,
-                               int* __restrict__ bad) {
+                               double* __restrict__ a, long long n, double area, int* __restrict__ bad) {
     long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (c >= n) return;
     double k = kappa[c];
@@ -26,13 +25,11 @@ __global__ void k_cell_weights(const double* __restrict__ kappa, double* __restr
     double ki = 1.0 / k;
     kinv[c] = ki;
     a[c] = area * ki;
-    a32[c] = (float)(area * ki);
 }
 
 // cell weights under a mobility field: a = |c| kappa^{-1} / lambda (kinv kept from setup)
 __global__ void k_mobility_weights(const double* __restrict__ lambda, const double* __restrict__ kinv,
-                                   double* __restrict__ a, float* __restrict__ a32, long long n, double area,
-                                   int* __restrict__ bad) {
+                                   double* __restrict__ a, long long n, double area, int* __restrict__ bad) {
     long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (c >= n) return;
     double l = lambda[c];
@@ -42,7 +39,6 @@ __global__ void k_mobility_weights(const double* __restrict__ lambda, const doub
     }
     const double w = area * kinv[c] / l;
     a[c] = w;
-    a32[c] = (float)w;
 }
 
 // A u on interior faces (full numbering); boundary outputs 0.  use_bnd = 0
@@ -156,7 +152,7 @@ namespace tgms {
 
 void cell_weights(tgms_ctx* c, const double* kappa, int* bad) {
     long long n = (long long)c->nx * c->ny;
-    hipLaunchKernelGGL(k_cell_weights, dim3(nb(n)), dim3(256), 0, c->stream, kappa, c->kinv, c->a, c->a32, n,
+    hipLaunchKernelGGL(k_cell_weights, dim3(nb(n)), dim3(256), 0, c->stream, kappa, c->kinv, c->a, n,
                        c->hx * c->hy, bad);
     LAUNCH_OK();
 }
@@ -164,7 +160,7 @@ void cell_weights(tgms_ctx* c, const double* kappa, int* bad) {
 void mobility_weights(tgms_ctx* c, const double* lambda, int* bad) {
     long long n = (long long)c->nx * c->ny;
     hipLaunchKernelGGL(k_mobility_weights, dim3(nb(n)), dim3(256), 0, c->stream, lambda, (const double*)c->kinv, c->a,
-                       c->a32, n, c->hx * c->hy, bad);
+                       n, c->hx * c->hy, bad);
     LAUNCH_OK();
 }
 

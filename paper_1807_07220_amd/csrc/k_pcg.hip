@@ -181,25 +181,28 @@ __device__ inline T patch_sum(const Rect* __restrict__ rects, const T* __restric
 // First smoothing of the two-grid cycle: z = eta * sum_i ext(w_i), t = g - K z.
 template <typename T>
 __global__ void __launch_bounds__(NT) k_gather_res(const Rect* __restrict__ rects, const T* __restrict__ w,
-                                                   const T* __restrict__ w4, GatherGeom G, T eta, const T* __restrict__ g,
-                                                   const T* __restrict__ a, T sx2, T sy2, T* __restrict__ z,
-                                                   T* __restrict__ t, const double* __restrict__ sc) {
+                                                   const T* __restrict__ w4, GatherGeom G, T eta,
+                                                   const double* __restrict__ g, const double* __restrict__ a,
+                                                   double sx2, double sy2, T* __restrict__ z, T* __restrict__ t,
+                                                   const double* __restrict__ sc) {
     if (finished(sc)) return;
-    __shared__ T Z[TY + 2][TX + 2];
+    // the tile holds z exactly as stored (in T); the residual is formed in FP64 and
+    // rounded once, so an FP32 z does not lose the small residual to cancellation
+    __shared__ double Z[TY + 2][TX + 2];
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
     const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
     for (int e = tid; e < (TX + 2) * (TY + 2); e += NT) {
         const int ii = i0 - 1 + e % (TX + 2), jj = j0 - 1 + e / (TX + 2);
         T val = T(0);
         if (ii >= 1 && ii < G.nx && jj >= 1 && jj < G.ny) val = eta * patch_sum<T>(rects, w, w4, G, ii, jj);
-        Z[e / (TX + 2)][e % (TX + 2)] = val;
+        Z[e / (TX + 2)][e % (TX + 2)] = double(val);
     }
     __syncthreads();
     const int i = i0 + tx, j = j0 + ty;
     if (i >= G.nx || j >= G.ny) return;
     const long long v = (long long)j * G.nx + i;
-    z[v] = Z[ty + 1][tx + 1];
-    t[v] = (i > 0 && j > 0) ? g[v] - stencil_tile<T>(Z, tx, ty, a, v, G.nx, sx2, sy2) : T(0);
+    z[v] = T(Z[ty + 1][tx + 1]);
+    t[v] = (i > 0 && j > 0) ? T(g[v] - stencil_tile<double>(Z, tx, ty, a, v, G.nx, sx2, sy2)) : T(0);
 }
 
 // Last smoothing of the two-grid cycle: z = zin + eta * sum_i ext(w_i) (zin may be
@@ -294,22 +297,23 @@ __global__ void __launch_bounds__(NT) k_finalize(double* __restrict__ sc, double
 
 // t = g - K z
 template <typename T>
-__global__ void __launch_bounds__(NT) k_residual(const T* __restrict__ z, const T* __restrict__ g,
-                                                 T* __restrict__ t, const T* __restrict__ a, int nx, int ny, T sx2,
-                                                 T sy2, const double* __restrict__ sc) {
+__global__ void __launch_bounds__(NT) k_residual(const T* __restrict__ z, const double* __restrict__ g,
+                                                 T* __restrict__ t, const double* __restrict__ a, int nx, int ny,
+                                                 double sx2, double sy2, const double* __restrict__ sc) {
     if (finished(sc)) return;
-    __shared__ T P[TY + 2][TX + 2];
+    __shared__ double P[TY + 2][TX + 2];  // z as stored, widened; FP64 residual rounded once to T
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
     const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
     for (int e = tid; e < (TX + 2) * (TY + 2); e += NT) {
         const int ii = i0 - 1 + e % (TX + 2), jj = j0 - 1 + e / (TX + 2);
-        P[e / (TX + 2)][e % (TX + 2)] = (ii >= 1 && ii < nx && jj >= 1 && jj < ny) ? z[(long long)jj * nx + ii] : T(0);
+        P[e / (TX + 2)][e % (TX + 2)] =
+            (ii >= 1 && ii < nx && jj >= 1 && jj < ny) ? double(z[(long long)jj * nx + ii]) : 0.0;
     }
     __syncthreads();
     const int i = i0 + tx, j = j0 + ty;
     if (i >= nx || j >= ny) return;
     const long long v = (long long)j * nx + i;
-    t[v] = (i > 0 && j > 0) ? g[v] - stencil_tile<T>(P, tx, ty, a, v, nx, sx2, sy2) : T(0);
+    t[v] = (i > 0 && j > 0) ? T(g[v] - stencil_tile<double>(P, tx, ty, a, v, nx, sx2, sy2)) : T(0);
 }
 
 inline dim3 tiles(tgms_ctx* c) { return dim3((c->nx + TX - 1) / TX, (c->ny + TY - 1) / TY); }
@@ -342,14 +346,13 @@ void update(tgms_ctx* c, const double* p, const double* q, double* x, double* g,
 }
 
 template <typename T>
-void gather_res(tgms_ctx* c, const T* w, const T* g, const T* a, T* z, T* t, const double* sc) {
+void gather_res(tgms_ctx* c, const T* w, const double* g, T* z, T* t, const double* sc) {
     hipLaunchKernelGGL((k_gather_res<T>), tiles(c), dim3(TX, TY), 0, c->stream, c->patch, w, slots<T>(c), ggeom(c),
-                       T(c->eta), g, a, T(c->sx * c->sx), T(c->sy * c->sy), z, t, sc);
+                       T(c->eta), g, (const double*)c->a, c->sx * c->sx, c->sy * c->sy, z, t, sc);
     LAUNCH_OK();
 }
-template void gather_res<double>(tgms_ctx*, const double*, const double*, const double*, double*, double*,
-                                 const double*);
-template void gather_res<float>(tgms_ctx*, const float*, const float*, const float*, float*, float*, const double*);
+template void gather_res<double>(tgms_ctx*, const double*, const double*, double*, double*, const double*);
+template void gather_res<float>(tgms_ctx*, const float*, const double*, float*, float*, const double*);
 
 template <typename T>
 void gather_final(tgms_ctx* c, const T* w, const T* zin, double* zout, const double* g, const double* gold,
@@ -374,13 +377,13 @@ template void gather_final<float>(tgms_ctx*, const float*, const float*, double*
                                   bool);
 
 template <typename T>
-void residual(tgms_ctx* c, const T* z, const T* g, T* t, const T* a, const double* sc) {
+void residual(tgms_ctx* c, const T* z, const double* g, T* t, const double* sc) {
     ProfScope ps(c, PK_APPLYK);
-    hipLaunchKernelGGL((k_residual<T>), tiles(c), dim3(TX, TY), 0, c->stream, z, g, t, a, c->nx, c->ny,
-                       T(c->sx * c->sx), T(c->sy * c->sy), sc);
+    hipLaunchKernelGGL((k_residual<T>), tiles(c), dim3(TX, TY), 0, c->stream, z, g, t, (const double*)c->a, c->nx,
+                       c->ny, c->sx * c->sx, c->sy * c->sy, sc);
     LAUNCH_OK();
 }
-template void residual<double>(tgms_ctx*, const double*, const double*, double*, const double*, const double*);
-template void residual<float>(tgms_ctx*, const float*, const float*, float*, const float*, const double*);
+template void residual<double>(tgms_ctx*, const double*, const double*, double*, const double*);
+template void residual<float>(tgms_ctx*, const float*, const double*, float*, const double*);
 
 }  // namespace tgms

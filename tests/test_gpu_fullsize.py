@@ -85,3 +85,44 @@ def test_preconditioner_symmetric(big):
     m = Grid2D(w.nx, w.ny).interior
     a, b = x[m] @ zy[m], y[m] @ zx[m]
     assert abs(a - b) <= 1e-10 * abs(a)
+
+
+def test_mixed_twogrid_matches_fp64(big):
+    """FP32 factors with residuals formed in FP64: the mixed two-grid application
+    stays within a few FP32 roundings of the FP64 one at contrast 1e6 (with the
+    residuals between the smoothing and coarse steps taken in FP32 instead, the
+    cancellation in g - K z leaves about 5e-4 here), and the flexible PCG needs
+    about the FP64 iteration count."""
+    import paper_1807_07220_amd as tg
+    from oracle.discretization import Grid2D
+    w, kappa, F, s = big
+    sm = tg.Solver(dev(kappa), w.bx, w.by, w.eig_tol, precision="mixed")
+    try:
+        x = np.random.default_rng(8).standard_normal((w.nx + 1) * w.ny + w.nx * (w.ny + 1))
+        m = Grid2D(w.nx, w.ny).interior
+        a = host(s.apply_precond("twogrid", dev(x)))[m]
+        b = host(sm.apply_precond("twogrid", dev(x)))[m]
+        assert np.linalg.norm(a - b) <= 1e-6 * np.linalg.norm(a)
+        r64 = s.solve(dev(F), rtol=w.rtol)
+        rm = sm.solve(dev(F), rtol=w.rtol)
+        assert rm["converged"] and rm["iters"] <= int(1.25 * r64["iters"]) + 2
+    finally:
+        sm.close()
+
+
+def test_mixed_solve_256_iterations():
+    """At 256 x 256 (cond ~ 7e5 under the tol 0.2 coarse space) the mixed solve
+    converges in about the FP64 iteration count."""
+    import paper_1807_07220_amd as tg
+    w = configs.get("darcy2d_256_b16")
+    kappa, F = w.make_inputs()
+    s64 = tg.Solver(dev(kappa), w.bx, w.by, w.eig_tol)
+    sm = tg.Solver(dev(kappa), w.bx, w.by, w.eig_tol, precision="mixed")
+    try:
+        r64 = s64.solve(dev(F), rtol=w.rtol)
+        rm = sm.solve(dev(F), rtol=w.rtol)
+        assert r64["converged"] and rm["converged"]
+        assert rm["iters"] <= int(1.25 * r64["iters"]) + 2
+    finally:
+        s64.close()
+        sm.close()
