@@ -73,6 +73,18 @@ typedef struct {
                           staging) at setup, once per shape and device; 0: fixed defaults */
     const char* tune_cache;  /* file keeping tuned configurations across processes (read and
                                 rewritten by setup); NULL: keep them in this process only */
+    int warm_start;    /* local spectral problems (section 4.2):
+                          0: dense cyclic Jacobi on every face's pencil;
+                          1: Rayleigh-Ritz subspace iteration from the DCT-II basis (k = 8
+                             vectors, at most 8 iterations), accepted when the selected modes
+                             are certified (inertia count of 1/tol - T, Ritz residuals
+                             <= rq_tol), else the dense solve for that face;
+                          2: as 1, the initial vectors from the warm-start network
+                             (tgms_cnn_forward) on the face's permeability; needs square
+                             blocks of at most 16 x 16 cells and cnn_weights */
+    const float* cnn_weights;  /* device, tgms_cnn_nparams() floats (warm_start 2; read during
+                                  setup only) */
+    double rq_tol;     /* relative Ritz residual |T u - theta u| / theta for acceptance (1e-6) */
 } tgms_options;
 
 typedef struct {
@@ -88,10 +100,14 @@ typedef struct {
     int tuned;            /* launch configuration: 0 defaults, 1 timed at this setup, 2 from the cache */
     int nred;             /* workgroups of the reducing PCG kernels */
     int smooth_staged;    /* smoother factor: 1 staged in LDS, 0 read from global, -1 by LDS fit */
+    int warm_accepted;    /* warm start: faces whose modes were certified without the dense solve */
+    int warm_iters;       /* warm start: subspace iterations summed over the accepted faces */
+    double t_cnn_ms;      /* warm start 2: network inputs and forward pass (inside t_eig_ms) */
 } tgms_info_t;
 
 /* Paper defaults: eta 0.2, overlap 2, FP64, s_scale = |K|^(1/2), default stream,
- * graph replay on, autotuning on without a cache file. */
+ * graph replay on, autotuning on without a cache file, dense local eigensolves
+ * (warm_start 0, rq_tol 1e-6). */
 void tgms_default_options(tgms_options* opt);
 
 /*
@@ -170,6 +186,48 @@ tgms_status tgms_profile_get(tgms_ctx* ctx, int kernel, int* launches, double* t
  * not consulted).  Requires a completed setup.  reps in [1, 100000], else
  * TGMS_E_INVAL.  Blocks the host until the launches have finished. */
 tgms_status tgms_time_smoother(tgms_ctx* ctx, int reps, double* avg_ms);
+
+/* Per-face outcome of the warm-started eigensolves of a context set up with
+ * warm_start 1 or 2: wstat (host, n_coarse_faces ints) receives the subspace
+ * iteration at which the face was accepted (0 = the initial block), or -1 when it
+ * fell back to the dense solve.  TGMS_E_INVAL without a warm start. */
+tgms_status tgms_get_warm_status(const tgms_ctx* ctx, int* wstat);
+
+/* ---- warm-start network (section 4.2 eigenproblem, learned initial vectors) ----
+ * A fully convolutional network on a face's permeability window: input X[h][w] =
+ * log10(kappa)/3 on the cells of omega_i = K1 u K2 (rows across the coarse face,
+ * H = 2 b; columns along it, W = b, in the pencil's fine-face order); four 3x3
+ * convolutions with zero padding, channels 1 -> 16 -> 16 -> 16 -> 8, ReLU after the
+ * first three; output: the first 8 DCT-II vectors of length W (unit norm, zero
+ * beyond W) plus the mean over the rows, 8 vectors of length W.  Parameters:
+ * one flat float array, per layer the weights [cout][cin][3][3] then the biases
+ * [cout].  FP32 throughout.  Shapes: 1 <= H, W <= 64, H * W <= 512; n >= 1.
+ * Every pointer is device memory owned by the caller; calls run on `stream`
+ * (hipStream_t, NULL = the null stream) and return after it has finished them. */
+int tgms_cnn_nparams(void);
+
+/* Y [n][8][W] = network(X [n][H][W]). */
+tgms_status tgms_cnn_forward(const float* params, const float* X, int n, int H, int W, float* Y, void* stream);
+
+/* Floats of the workspace one training step on n samples needs (0 for bad shapes). */
+size_t tgms_cnn_train_workspace(int n, int H, int W);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; t = step number from 1, lr the
+ * learning rate) on the batch-mean loss sum_{c<k} |y_c/|y_c| - s_c v_c|^2 with
+ * s_c = sign(y_c . v_c): X [n][H][W] inputs, V [n][8][W] unit target vectors (rows
+ * c < k read, 1 <= k <= min(8, W)); params, adam_m, adam_v (tgms_cnn_nparams()
+ * floats each) are updated in place; work: tgms_cnn_train_workspace(n, H, W)
+ * floats; *loss (host, may be NULL) = the batch-mean loss before the step. */
+tgms_status tgms_cnn_train_step(float* params, float* adam_m, float* adam_v, int t, float lr, const float* X,
+                                const float* V, int n, int H, int W, int k, float* work, double* loss,
+                                void* stream);
+
+/* Training samples from a set-up context (square blocks b x b, b <= 16): X
+ * [n_coarse_faces][2b][b] network inputs and V [n_coarse_faces][8][b] the unit
+ * eigenvectors of T = D^{-1/2} S D^{-1/2} (section 4.2 pencil) for its 8 largest
+ * mu (rows beyond b are 0), from the dense solve.  Not available after
+ * tgms_update_mobility (TGMS_E_INVAL). */
+tgms_status tgms_cnn_samples(tgms_ctx* ctx, float* X, float* V);
 
 void tgms_destroy(tgms_ctx* ctx);
 const char* tgms_last_error(void);

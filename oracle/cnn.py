@@ -20,8 +20,9 @@ the permeability of omega_i = K1 u K2:
           of E, in the order of the pencil's index);
   layers  four 3x3 convolutions with zero padding, channels 1 -> C -> C -> C
           -> 8, ReLU after the first three;
-  output  the mean over the rows: 8 vectors of length J (the first
-          k = min(8, J) are used).
+  output  the normalised DCT-II basis (see dct_start) plus the mean over the
+          rows: 8 vectors of length J (the first k = min(8, J) are used); the
+          network learns a correction to the homogeneous-medium start.
 
 Training minimises, per sample, sum_c |y_c / |y_c| - s_c v_c|^2 over the first
 k channels, where v_c are the eigenvectors of T for the k largest mu and
@@ -64,11 +65,13 @@ def pack(params) -> np.ndarray:
 
 
 def init_params(C: int, seed: int = 0) -> np.ndarray:
-    """He-normal weights, zero biases."""
+    """He-normal weights (the last layer scaled by 0.1: the start is close to the DCT
+    basis), zero biases."""
     rng = np.random.default_rng(seed)
     out = []
-    for co, ci in layer_shapes(C):
-        out.append((rng.standard_normal((co, ci, 3, 3)) * np.sqrt(2.0 / (ci * 9)), np.zeros(co)))
+    for li, (co, ci) in enumerate(layer_shapes(C)):
+        scale = np.sqrt(2.0 / (ci * 9)) * (0.1 if li == 3 else 1.0)
+        out.append((rng.standard_normal((co, ci, 3, 3)) * scale, np.zeros(co)))
     return pack(out)
 
 
@@ -117,6 +120,16 @@ def conv3x3_backward(x, w, gy):
     return gxp[:, 1:-1, 1:-1], gw, gy.sum(axis=(1, 2))
 
 
+def dct_unit(W: int) -> np.ndarray:
+    """The first 8 DCT-II columns of length W, unit norm, as rows [8][W] (rows
+    beyond W are zero)."""
+    D = np.zeros((KOUT, W))
+    k = min(KOUT, W)
+    B = dct_start(W, k)
+    D[:k] = (B / np.linalg.norm(B, axis=0)).T
+    return D
+
+
 def forward(theta: np.ndarray, C: int, x: np.ndarray):
     """x [H][W] -> (y [8][W], cache of (layer input, pre-activation) per layer)."""
     a = x[None, :, :]
@@ -125,7 +138,7 @@ def forward(theta: np.ndarray, C: int, x: np.ndarray):
         z = conv3x3(a, w, b)
         cache.append((a, z))
         a = np.maximum(z, 0.0) if li < 3 else z
-    return a.mean(axis=1), cache
+    return dct_unit(x.shape[1]) + a.mean(axis=1), cache
 
 
 def sample_loss(y: np.ndarray, v: np.ndarray, k: int):

@@ -35,7 +35,8 @@ class Solver:
 
     def __init__(self, kappa: torch.Tensor, bx: int, by: int, eig_tol: float, eta: float = 0.2, overlap: int = 2,
                  precision: str = "fp64", s_scale: float = 0.0, stream: torch.cuda.Stream | None = None,
-                 graphs: bool = True, autotune: bool = True, tune_cache: str | None = None):
+                 graphs: bool = True, autotune: bool = True, tune_cache: str | None = None,
+                 warm_start: str = "exact", cnn_weights: torch.Tensor | None = None, rq_tol: float = 1e-6):
         lib = load()
         if kappa.dim() != 2:
             raise ValueError("kappa must be (ny, nx)")
@@ -52,6 +53,12 @@ class Solver:
         opt.autotune = 1 if autotune else 0
         self._tune_cache = None if tune_cache is None else str(tune_cache).encode()
         opt.tune_cache = self._tune_cache
+        opt.warm_start = {"exact": 0, "dct": 1, "cnn": 2}[warm_start]
+        if cnn_weights is not None:
+            if not (cnn_weights.is_cuda and cnn_weights.dtype == torch.float32 and cnn_weights.is_contiguous()):
+                raise ValueError("cnn_weights must be a contiguous float32 CUDA tensor")
+            opt.cnn_weights = ctypes.c_void_p(cnn_weights.data_ptr())
+        opt.rq_tol = float(rq_tol)
         grid = Grid(self.nx, self.ny, self.bx, self.by)
         handle = ctypes.c_void_p()
         kappa = kappa.contiguous()
@@ -93,6 +100,22 @@ class Solver:
         out = np.zeros(n, dtype=np.int32)
         check(load().tgms_get_counts(self._h, out.ctypes.data_as(ctypes.c_void_p)))
         return out
+
+    def warm_status(self):
+        """Per coarse face: the subspace iteration that accepted it, or -1 (dense fallback)."""
+        import numpy as np
+        out = np.zeros(self.info()["n_coarse_faces"], dtype=np.int32)
+        check(load().tgms_get_warm_status(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def cnn_samples(self):
+        """Network inputs [faces][2b][b] and target eigenvectors [faces][8][b] (float32, GPU)."""
+        b = self.bx
+        n = self.info()["n_coarse_faces"]
+        X = torch.empty((n, 2 * b, b), dtype=torch.float32, device=self.device)
+        V = torch.empty((n, 8, b), dtype=torch.float32, device=self.device)
+        check(load().tgms_cnn_samples(self._h, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(V.data_ptr())))
+        return X, V
 
     def eigs(self):
         import numpy as np

@@ -31,14 +31,16 @@ class Grid(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("eta", c_double), ("overlap", c_int), ("precision", c_int), ("s_scale", c_double),
-                ("stream", c_void_p), ("graphs", c_int), ("autotune", c_int), ("tune_cache", c_char_p)]
+                ("stream", c_void_p), ("graphs", c_int), ("autotune", c_int), ("tune_cache", c_char_p),
+                ("warm_start", c_int), ("cnn_weights", c_void_p), ("rq_tol", c_double)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("n_coarse_faces", c_int), ("n_blocks", c_int), ("dim", c_int), ("n_coarse_spd", c_int),
                 ("t_setup_ms", c_double), ("t_snap_ms", c_double), ("t_eig_ms", c_double),
                 ("t_coarse_ms", c_double), ("t_smoother_ms", c_double), ("lds_max", c_int), ("pcg_graph", c_int),
-                ("tuned", c_int), ("nred", c_int), ("smooth_staged", c_int)]
+                ("tuned", c_int), ("nred", c_int), ("smooth_staged", c_int), ("warm_accepted", c_int),
+                ("warm_iters", c_int), ("t_cnn_ms", c_double)]
 
 
 _lib = None
@@ -62,6 +64,13 @@ SIGNATURES = {
     "tgms_preprocess": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "tgms_apply_precond": (c_int, [c_void_p, c_int, c_void_p, c_void_p]),
     "tgms_update_mobility": (c_int, [c_void_p, c_void_p]),
+    "tgms_get_warm_status": (c_int, [c_void_p, c_void_p]),
+    "tgms_cnn_nparams": (c_int, []),
+    "tgms_cnn_forward": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_void_p]),
+    "tgms_cnn_train_workspace": (ctypes.c_size_t, [c_int, c_int, c_int]),
+    "tgms_cnn_train_step": (c_int, [c_void_p, c_void_p, c_void_p, c_int, ctypes.c_float, c_void_p, c_void_p, c_int,
+                                    c_int, c_int, c_int, c_void_p, ctypes.POINTER(c_double), c_void_p]),
+    "tgms_cnn_samples": (c_int, [c_void_p, c_void_p, c_void_p]),
 }
 
 

@@ -304,6 +304,12 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
     const int ex = std::min(bx + 2 * o.overlap, nx), ey = std::min(by + 2 * o.overlap, ny);
     if (ex > 33) throw TgmsError{TGMS_E_UNSUPPORTED, "smoother patches wider than 33 cells"};
     (void)ey;
+    if (o.warm_start < 0 || o.warm_start > 2) throw TgmsError{TGMS_E_INVAL, "warm_start must be 0, 1 or 2"};
+    if (o.warm_start == 2) {
+        if (!o.cnn_weights) throw TgmsError{TGMS_E_INVAL, "warm_start 2 needs cnn_weights"};
+        if (bx != by || !tgms::cnn_shape_ok(2 * bx, bx))
+            throw TgmsError{TGMS_E_UNSUPPORTED, "the network warm start needs square blocks of at most 16 x 16 cells"};
+    }
     auto* c = new tgms_ctx();
     try {
         // All work runs on a stream of the library's own (default priority); each call
@@ -323,6 +329,8 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         c->H = o.s_scale > 0 ? o.s_scale : std::sqrt(bx * c->hx * by * c->hy);
         c->eta = o.eta; c->tol = eig_tol; c->overlap = o.overlap; c->precision = o.precision ? 1 : 0;
         c->graph_failed = o.graphs == 0;  // never capture: launch every kernel directly
+        c->warm = o.warm_start;
+        c->rq_tol = o.rq_tol > 0 ? o.rq_tol : 1e-6;
         c->nfx = (nx + 1) * ny; c->nfy = nx * (ny + 1); c->nf = c->nfx + c->nfy;
         c->nfk = by * (bx + 1) + (by + 1) * bx;
         c->ncol = 4 * c->jmax;
@@ -366,7 +374,19 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         double* Qd = c->alloc<double>((size_t)c->ne * c->jmax * c->jmax);
         {
             Timer t(c->stream);
-            tgms::pencil_eig_q(c, Qd);
+            const float* Y0 = nullptr;
+            if (c->warm) c->wstat = c->alloc<int>(c->ne);
+            if (c->warm == 2) {
+                // network inputs of every face and the initial blocks [ne][8][b]
+                Timer tc(c->stream);
+                float* Xw = c->alloc<float>((size_t)c->ne * 2 * bx * bx);
+                float* Yw = c->alloc<float>((size_t)c->ne * tgms::cnn_kout() * bx);
+                tgms::cnn_windows(c, Xw);
+                tgms::cnn_forward(c->stream, o.cnn_weights, Xw, c->ne, 2 * bx, bx, Yw, nullptr);
+                Y0 = Yw;
+                c->t_cnn_ms = tc.ms();
+            }
+            tgms::pencil_eig_q(c, Qd, Y0, nullptr);
             c->t_eig_ms = t.ms();
         }
         {
@@ -376,7 +396,17 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
             HIP_OK(hipMemcpyAsync(c->counts_h.data(), c->counts, sizeof(int) * c->ne, hipMemcpyDeviceToHost, c->stream));
             HIP_OK(hipMemcpyAsync(Yh.data(), c->Y, sizeof(double) * Yh.size(), hipMemcpyDeviceToHost, c->stream));
             HIP_OK(hipMemcpyAsync(Qh.data(), Qd, sizeof(double) * Qh.size(), hipMemcpyDeviceToHost, c->stream));
+            if (c->warm) {
+                c->wstat_h.resize(c->ne);
+                HIP_OK(hipMemcpyAsync(c->wstat_h.data(), c->wstat, sizeof(int) * c->ne, hipMemcpyDeviceToHost,
+                                      c->stream));
+            }
             HIP_OK(hipStreamSynchronize(c->stream));
+            for (int w : c->wstat_h)
+                if (w >= 0) {
+                    ++c->warm_accepted;
+                    c->warm_iters += w;
+                }
             std::vector<double> Tm;
             std::vector<int> zc;
             build_coarse_numbering(c, Yh, Qh, Tm, zc);
@@ -519,6 +549,7 @@ void update_mobility_impl(tgms_ctx* c, const double* lambda) {
     HIP_OK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
     if (hbad) throw TgmsError{TGMS_E_INVAL, "mobility must be finite and positive"};
+    c->mobility_updated = true;
     tgms::factor_blocks(c);
     tgms::gram(c);
     tgms::zero(c, c->Ac, sizeof(double) * (size_t)c->ncs * c->ncs);
@@ -690,6 +721,9 @@ void tgms_default_options(tgms_options* opt) {
     opt->graphs = 1;
     opt->autotune = 1;
     opt->tune_cache = nullptr;
+    opt->warm_start = 0;
+    opt->cnn_weights = nullptr;
+    opt->rq_tol = 1e-6;
 }
 
 tgms_status tgms_setup(const tgms_grid* grid, const double* kappa, double eig_tol, const tgms_options* opt,
@@ -730,7 +764,109 @@ tgms_status tgms_info(const tgms_ctx* c, tgms_info_t* info) {
     info->tuned = c->tuned;
     info->nred = c->nred;
     info->smooth_staged = c->smooth_staged;
+    info->warm_accepted = c->warm_accepted;
+    info->warm_iters = c->warm_iters;
+    info->t_cnn_ms = c->t_cnn_ms;
     return TGMS_OK;
+}
+
+tgms_status tgms_get_warm_status(const tgms_ctx* c, int* wstat) {
+    if (!c || !wstat) {
+        g_last_error = "null argument";
+        return TGMS_E_INVAL;
+    }
+    if (!c->warm) {
+        g_last_error = "the context was set up without a warm start";
+        return TGMS_E_INVAL;
+    }
+    std::copy(c->wstat_h.begin(), c->wstat_h.end(), wstat);
+    return TGMS_OK;
+}
+
+int tgms_cnn_nparams(void) { return tgms::cnn_nparams(); }
+
+size_t tgms_cnn_train_workspace(int n, int H, int W) {
+    if (n < 1 || !tgms::cnn_shape_ok(H, W)) return 0;
+    return tgms::cnn_train_workspace(n, H, W);
+}
+
+tgms_status tgms_cnn_forward(const float* params, const float* X, int n, int H, int W, float* Y, void* stream) {
+    if (!params || !X || !Y || n < 1 || !tgms::cnn_shape_ok(H, W)) {
+        g_last_error = "bad argument (null pointer, n < 1, or H, W outside [1, 64] with H * W <= 512)";
+        return TGMS_E_INVAL;
+    }
+    return guarded([&] {
+        tgms::cnn_forward((hipStream_t)stream, params, X, n, H, W, Y, nullptr);
+        HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+    });
+}
+
+tgms_status tgms_cnn_train_step(float* params, float* adam_m, float* adam_v, int t, float lr, const float* X,
+                                const float* V, int n, int H, int W, int k, float* work, double* loss, void* stream) {
+    if (!params || !adam_m || !adam_v || !X || !V || !work || t < 1 || !(lr > 0) || n < 1 ||
+        !tgms::cnn_shape_ok(H, W) || k < 1 || k > tgms::cnn_kout() || k > W) {
+        g_last_error = "bad argument";
+        return TGMS_E_INVAL;
+    }
+    return guarded([&] {
+        const double L = tgms::cnn_train_step((hipStream_t)stream, params, adam_m, adam_v, t, lr, X, V, n, H, W, k,
+                                              work);
+        if (loss) *loss = L;
+    });
+}
+
+tgms_status tgms_cnn_samples(tgms_ctx* c, float* X, float* V) {
+    if (!c || !X || !V) {
+        g_last_error = "null argument";
+        return TGMS_E_INVAL;
+    }
+    if (c->bx != c->by || !tgms::cnn_shape_ok(2 * c->bx, c->bx)) {
+        g_last_error = "network samples need square blocks of at most 16 x 16 cells";
+        return TGMS_E_UNSUPPORTED;
+    }
+    if (c->mobility_updated) {
+        g_last_error = "network samples describe the setup permeability; not available after a mobility update";
+        return TGMS_E_INVAL;
+    }
+    return guarded([&] {
+        tgms::enter(c);
+        tgms::cnn_windows(c, X);
+        // the dense solve of every face again (same results as setup's), keeping the targets
+        // (into scratch outputs: the context's own spectral results stay as set up)
+        const int warm = c->warm;
+        double* eigs = c->eigs;
+        int* counts = c->counts;
+        double* Y = c->Y;
+        std::vector<DeviceBuf> tmp(4);
+        auto get = [&](DeviceBuf& b, size_t bytes) {
+            HIP_OK(hipMalloc(&b.p, bytes));
+            b.bytes = bytes;
+            return b.p;
+        };
+        auto release = [&] {
+            for (auto& b : tmp)
+                if (b.p) (void)hipFree(b.p);
+            c->eigs = eigs;
+            c->counts = counts;
+            c->Y = Y;
+            c->warm = warm;
+        };
+        try {
+            const size_t nq = (size_t)c->ne * c->jmax * c->jmax;
+            c->eigs = (double*)get(tmp[0], sizeof(double) * c->ne * c->jmax);
+            c->counts = (int*)get(tmp[1], sizeof(int) * c->ne);
+            c->Y = (double*)get(tmp[2], sizeof(double) * nq);
+            double* Qd = (double*)get(tmp[3], sizeof(double) * nq);
+            c->warm = 0;
+            tgms::pencil_eig_q(c, Qd, nullptr, V);
+            HIP_OK(hipStreamSynchronize(c->stream));
+        } catch (...) {
+            (void)hipStreamSynchronize(c->stream);
+            release();
+            throw;
+        }
+        release();
+    });
 }
 
 tgms_status tgms_get_counts(const tgms_ctx* c, int* counts) {

@@ -197,6 +197,15 @@ struct tgms_ctx {
     Rect* blk_rects = nullptr;
     double* Td = nullptr;      // coarse basis combination matrices (kept for mobility updates)
     int* zcd = nullptr;
+    // warm-started local eigensolves (tgms_options.warm_start)
+    int warm = 0;               // 0 dense Jacobi, 1 DCT-II start, 2 network start
+    double rq_tol = 1e-6;       // relative Ritz residual for acceptance
+    int warm_maxit = 8;         // subspace iterations before the dense fallback
+    int* wstat = nullptr;       // per face: accepting iteration, or -1 (fallback)
+    std::vector<int> wstat_h;
+    int warm_accepted = 0, warm_iters = 0;
+    double t_cnn_ms = 0;
+    bool mobility_updated = false;
     int* scratch_int = nullptr;
     int* alloc_scratch_int() {
         if (!scratch_int) scratch_int = alloc<int>(4);
@@ -267,7 +276,16 @@ void residual(tgms_ctx* c, const T* z, const double* g, T* t, const double* sc);
 // setup (k_setup.hip)
 void snapshots(tgms_ctx* c);
 void gram(tgms_ctx* c);
-void pencil_eig_q(tgms_ctx* c, double* Q);
+void pencil_eig_q(tgms_ctx* c, double* Q, const float* Y0, float* Vtop);
+// warm-start network (k_cnn.hip)
+int cnn_nparams();
+int cnn_kout();
+bool cnn_shape_ok(int H, int W);
+size_t cnn_train_workspace(long long n, int H, int W);
+void cnn_forward(hipStream_t st, const float* prm, const float* X, long long n, int H, int W, float* Y, float* act);
+double cnn_train_step(hipStream_t st, float* prm, float* m, float* v, int t, float lr, const float* X, const float* V,
+                      long long n, int H, int W, int k, float* work);
+void cnn_windows(tgms_ctx* c, float* X);
 void coarse_local_run(tgms_ctx* c, const double* Tm, const int* zc);
 void coarse_rt0_blocks(tgms_ctx* c);
 void rt0_stiffness(tgms_ctx* c, double* K);

@@ -342,10 +342,124 @@ __global__ void k_gram(BlockGeom G, const double* __restrict__ Psi, const double
         for (int s = 0; s < 4; ++s) Gb[(r0 + r) * ncol + c0 + s] = acc[r][s];
 }
 
-// Pencil, Jacobi eigensolve, selection and recombination: one wavefront per coarse face.
-__global__ void k_pencil_eig(BlockGeom G, const double* __restrict__ kinv, const double* __restrict__ Gm,
-                             double tol, double invH, double* __restrict__ eigs, int* __restrict__ counts,
-                             double* __restrict__ Yout, double* __restrict__ Qout) {
+// ---- local spectral problems: one wavefront per coarse face --------------------
+
+// Cyclic Jacobi on the symmetric n x n matrix A (row stride ld, LDS), round-robin
+// ordering over the pairs, one wavefront: A becomes diagonal (the eigenvalues), and
+// V (the identity on entry) accumulates the rotations (eigenvectors in its columns).
+__device__ void jacobi_rr(double* A, double* V, int ld, int n, double (*cs)[2], int* rot_flag) {
+    const int lane = threadIdx.x;
+    const int N = (n + 1) & ~1, half = N / 2;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        if (lane == 0) *rot_flag = 0;
+        __syncthreads();
+        for (int rnd = 0; rnd < N - 1; ++rnd) {
+            auto pos = [&](int x) { return x == 0 ? 0 : 1 + (x - 1 + rnd) % (N - 1); };
+            if (lane < half) {
+                const int p = pos(lane), qq = pos(N - 1 - lane);
+                double c = 1.0, s = 0.0;
+                if (p < n && qq < n) {
+                    const double apq = A[p * ld + qq], app = A[p * ld + p], aqq = A[qq * ld + qq];
+                    if (fabs(apq) > 1e-300 && fabs(apq) > 1e-17 * sqrt(fabs(app * aqq))) {
+                        const double th = (aqq - app) / (2.0 * apq);
+                        const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                        c = 1.0 / sqrt(t * t + 1.0);
+                        s = t * c;
+                        *rot_flag = 1;
+                    }
+                }
+                cs[lane][0] = c;
+                cs[lane][1] = s;
+            }
+            __syncthreads();
+            for (int e = lane; e < half * n; e += 64) {  // rows: A <- P^T A
+                const int k = e / n, x = e % n;
+                const int p = pos(k), qq = pos(N - 1 - k);
+                if (p < n && qq < n) {
+                    const double c = cs[k][0], s = cs[k][1];
+                    const double tp = A[p * ld + x], tq = A[qq * ld + x];
+                    A[p * ld + x] = c * tp - s * tq;
+                    A[qq * ld + x] = s * tp + c * tq;
+                }
+            }
+            __syncthreads();
+            for (int e = lane; e < half * n; e += 64) {  // columns: A <- A P, V <- V P
+                const int k = e / n, x = e % n;
+                const int p = pos(k), qq = pos(N - 1 - k);
+                if (p < n && qq < n) {
+                    const double c = cs[k][0], s = cs[k][1];
+                    const double tp = A[x * ld + p], tq = A[x * ld + qq];
+                    A[x * ld + p] = c * tp - s * tq;
+                    A[x * ld + qq] = s * tp + c * tq;
+                    const double vp = V[x * ld + p], vq = V[x * ld + qq];
+                    V[x * ld + p] = c * vp - s * vq;
+                    V[x * ld + qq] = s * vp + c * vq;
+                }
+            }
+            __syncthreads();
+        }
+        if (!*rot_flag) break;
+        __syncthreads();
+    }
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, TGMS_WAVE));
+    return v;
+}
+
+// Number of eigenvalues of the symmetric n x n matrix T above sigma: the negative
+// pivots of the LDL^T factorisation of sigma I - T without pivoting (Sylvester's law of
+// inertia), computed in the workspace A (row stride 65); -1 when a pivot is zero
+// relative to the largest entry of sigma I - T.
+__device__ int inertia_above(const double (*T)[65], double* A, int n, double sigma) {
+    const int lane = threadIdx.x;
+    double mx = 0.0;
+    if (lane < n)
+        for (int m = 0; m < n; ++m) {
+            const double v = (lane == m ? sigma : 0.0) - T[lane][m];
+            A[lane * 65 + m] = v;
+            mx = fmax(mx, fabs(v));
+        }
+    mx = wave_max(mx);
+    __syncthreads();
+    int neg = 0;
+    for (int j = 0; j < n; ++j) {
+        const double d = A[j * 65 + j];
+        if (fabs(d) <= 1e-14 * mx) return -1;  // the same value in every lane
+        neg += d < 0.0;
+        if (lane > j && lane < n) {
+            const double l = A[lane * 65 + j] / d;
+            for (int m = j + 1; m < n; ++m) A[lane * 65 + m] -= l * A[j * 65 + m];
+        }
+        __syncthreads();
+    }
+    return neg;
+}
+
+constexpr int KW = 8;  // largest warm-start block
+
+// Pencil (eq. spectral_eqn) of every interior coarse face, its eigenproblem and the
+// adaptive selection (section 4.2), and the recombination of the kept modes.
+//
+// WARM = 0: dense cyclic Jacobi on T = D^{-1/2} S D^{-1/2}.  Vtop (optional) receives the
+// eigenvectors of T of the 8 largest mu as float [ne][8][jmax] (training targets).
+// WARM = 1: Rayleigh-Ritz subspace iteration on T from a block of kblk vectors (Y0
+// [ne][8][jmax] as float, or the DCT-II basis when Y0 is null).  With cnt = #{mu > 1/tol}
+// from the inertia of 1/tol - T and l = max(1, cnt), a face is accepted at the first
+// iteration where l < k, exactly cnt Ritz values exceed 1/tol, the first l Ritz pairs have
+// |T u - theta u| / theta <= rq_tol, and (cnt = 0) exactly one eigenvalue lies above
+// theta_1 (1 - 4 rq_tol); otherwise the face falls back to the Jacobi solve.  wstat[f]:
+// the accepting iteration, or -1 (fallback).  For accepted faces only the first k
+// eigenvalues are computed (the rest are stored as 0).
+template <int WARM>
+__global__ void __launch_bounds__(64) k_pencil_eig(BlockGeom G, const double* __restrict__ kinv,
+                                                   const double* __restrict__ Gm, double tol, double invH,
+                                                   double* __restrict__ eigs, int* __restrict__ counts,
+                                                   double* __restrict__ Yout, double* __restrict__ Qout,
+                                                   const float* __restrict__ Y0, int kblk, double rq_tol, int max_it,
+                                                   int* __restrict__ wstat, float* __restrict__ Vtop) {
     __shared__ double T[64][65];
     __shared__ double V[64][65];
     __shared__ double D[64];
@@ -391,7 +505,6 @@ __global__ void k_pencil_eig(BlockGeom G, const double* __restrict__ kinv, const
                           G2[(s2 * G.jmax + l) * G.ncol + s2 * G.jmax + mm] + 2.0 * elen * elen / areaK) *
                          invH;
         T[l][mm] = s / sqrt(D[l] * D[mm]);
-        V[l][mm] = (l == mm) ? 1.0 : 0.0;
     }
     __syncthreads();
     // symmetrise (the two Gram halves are symmetric up to round-off)
@@ -404,88 +517,187 @@ __global__ void k_pencil_eig(BlockGeom G, const double* __restrict__ kinv, const
         }
     }
     __syncthreads();
-    // cyclic Jacobi, round-robin ordering over N (even) players
-    const int N = (Jn + 1) & ~1, half = N / 2;
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        if (lane == 0) rot_flag = 0;
-        __syncthreads();
-        for (int rnd = 0; rnd < N - 1; ++rnd) {
-            if (lane < half) {
-                auto pos = [&](int x) { return x == 0 ? 0 : 1 + (x - 1 + rnd) % (N - 1); };
-                const int p = pos(lane), qq = pos(N - 1 - lane);
-                double c = 1.0, s = 0.0;
-                if (p < Jn && qq < Jn) {
-                    const double apq = T[p][qq], app = T[p][p], aqq = T[qq][qq];
-                    if (fabs(apq) > 1e-300 && fabs(apq) > 1e-17 * sqrt(fabs(app * aqq))) {
-                        const double th = (aqq - app) / (2.0 * apq);
-                        const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-                        c = 1.0 / sqrt(t * t + 1.0);
-                        s = t * c;
-                        rot_flag = 1;
+    double* ev = eigs + (long long)fid * G.jmax;
+    double* Yf = Yout + (long long)fid * G.jmax * G.jmax;
+    int cnt = 0;
+    bool accepted = false;
+    if constexpr (WARM) {
+        const double sigma = 1.0 / tol;
+        const int kk = min(kblk, Jn);
+        double* A = &V[0][0];  // LDS workspace (V is not needed before a fallback)
+        const int cnt0 = inertia_above(T, A, Jn, sigma);
+        const int l = max(cnt0, 1);
+        if (cnt0 >= 0 && l < kk) {
+            double* Xs = A;            // [64][KW] rows of X, then of U
+            double* Ws = A + 64 * KW;  // [64][KW] rows of T X
+            double* Hs = Ws + 64 * KW; // [KW][9]  X^T T X, then its diagonal form
+            double* Zs = Hs + KW * 9;  // [KW][9]  its eigenvectors
+            double x[KW], w[KW];
+#pragma unroll
+            for (int c = 0; c < KW; ++c) {
+                double v = 0.0;
+                if (c < kk && lane < Jn)
+                    v = Y0 ? (double)Y0[((long long)fid * KW + c) * G.jmax + lane]
+                           : cos(M_PI * (lane + 0.5) * c / Jn);
+                x[c] = v;
+            }
+            for (int it = 0; it <= max_it; ++it) {
+                // modified Gram-Schmidt on the columns of X (lane = row)
+                bool rank_ok = true;
+#pragma unroll
+                for (int c = 0; c < KW; ++c) {
+                    if (c < kk && rank_ok) {
+                        const double n0 = sqrt(wave_sum(x[c] * x[c]));
+#pragma unroll
+                        for (int p = 0; p < KW; ++p)
+                            if (p < c) x[c] -= wave_sum(x[p] * x[c]) * x[p];
+                        const double nq = sqrt(wave_sum(x[c] * x[c]));
+                        if (!(nq > 1e-12 * fmax(n0, 1e-300)))
+                            rank_ok = false;
+                        else
+                            x[c] /= nq;
                     }
                 }
-                cs[lane][0] = c;
-                cs[lane][1] = s;
-            }
-            __syncthreads();
-            // rows: T <- P^T T
-            for (int e = lane; e < half * Jn; e += 64) {
-                const int k = e / Jn, x = e % Jn;
-                auto pos = [&](int y) { return y == 0 ? 0 : 1 + (y - 1 + rnd) % (N - 1); };
-                const int p = pos(k), qq = pos(N - 1 - k);
-                if (p < Jn && qq < Jn) {
-                    const double c = cs[k][0], s = cs[k][1];
-                    const double tp = T[p][x], tq = T[qq][x];
-                    T[p][x] = c * tp - s * tq;
-                    T[qq][x] = s * tp + c * tq;
+                if (!rank_ok) break;
+                // W = T X
+#pragma unroll
+                for (int c = 0; c < KW; ++c) Xs[lane * KW + c] = x[c];
+                __syncthreads();
+#pragma unroll
+                for (int c = 0; c < KW; ++c) w[c] = 0.0;
+                if (lane < Jn)
+                    for (int m = 0; m < Jn; ++m) {
+                        const double t = T[lane][m];
+#pragma unroll
+                        for (int c = 0; c < KW; ++c) w[c] += t * Xs[m * KW + c];
+                    }
+#pragma unroll
+                for (int c = 0; c < KW; ++c) Ws[lane * KW + c] = w[c];
+                __syncthreads();
+                // H = X^T W (kk x kk), symmetrised, and its eigenpairs
+                if (lane < kk * kk) {
+                    const int a = lane / kk, b = lane % kk;
+                    double h = 0.0, hT = 0.0;
+                    for (int m = 0; m < Jn; ++m) {
+                        h += Xs[m * KW + a] * Ws[m * KW + b];
+                        hT += Xs[m * KW + b] * Ws[m * KW + a];
+                    }
+                    Hs[a * 9 + b] = 0.5 * (h + hT);
+                    Zs[a * 9 + b] = (a == b) ? 1.0 : 0.0;
                 }
-            }
-            __syncthreads();
-            // columns: T <- T P, V <- V P
-            for (int e = lane; e < half * Jn; e += 64) {
-                const int k = e / Jn, x = e % Jn;
-                auto pos = [&](int y) { return y == 0 ? 0 : 1 + (y - 1 + rnd) % (N - 1); };
-                const int p = pos(k), qq = pos(N - 1 - k);
-                if (p < Jn && qq < Jn) {
-                    const double c = cs[k][0], s = cs[k][1];
-                    const double tp = T[x][p], tq = T[x][qq];
-                    T[x][p] = c * tp - s * tq;
-                    T[x][qq] = s * tp + c * tq;
-                    const double vp = V[x][p], vq = V[x][qq];
-                    V[x][p] = c * vp - s * vq;
-                    V[x][qq] = s * vp + c * vq;
+                __syncthreads();
+                jacobi_rr(Hs, Zs, 9, kk, cs, &rot_flag);
+                if (lane < kk) {
+                    const double th = Hs[lane * 9 + lane];
+                    int rank = 0;
+                    for (int k = 0; k < kk; ++k) {
+                        const double o = Hs[k * 9 + k];
+                        rank += (o > th) || (o == th && k < lane);
+                    }
+                    order[rank] = lane;
                 }
+                __syncthreads();
+                // Ritz vectors U = X Z and T U = W Z (columns by descending theta)
+                double u[KW], tu[KW], th[KW];
+#pragma unroll
+                for (int c = 0; c < KW; ++c) {
+                    u[c] = 0.0;
+                    tu[c] = 0.0;
+                    th[c] = 0.0;
+                    if (c < kk) {
+                        const int oc = order[c];
+                        th[c] = Hs[oc * 9 + oc];
+#pragma unroll
+                        for (int a = 0; a < KW; ++a)
+                            if (a < kk) {
+                                u[c] += x[a] * Zs[a * 9 + oc];
+                                tu[c] += w[a] * Zs[a * 9 + oc];
+                            }
+                    }
+                }
+                int nabove = 0;
+                bool ok = true;
+#pragma unroll
+                for (int c = 0; c < KW; ++c) {
+                    if (c < kk) nabove += th[c] > sigma;
+                    if (c < l) {
+                        const double r = tu[c] - th[c] * u[c];
+                        ok = ok && sqrt(wave_sum(r * r)) / fabs(th[c]) <= rq_tol;
+                    }
+                }
+                ok = ok && nabove == cnt0;
+                if (ok) {
+                    // outputs from the Ritz pairs (U staged through LDS, row = lane)
+                    __syncthreads();
+#pragma unroll
+                    for (int c = 0; c < KW; ++c) Xs[lane * KW + c] = u[c];
+                    for (int k = lane; k < G.jmax; k += 64) {
+                        double val = 0.0;
+#pragma unroll
+                        for (int c = 0; c < KW; ++c)
+                            if (c == k && c < kk) val = 1.0 / th[c];
+                        ev[k] = val;
+                    }
+                    __syncthreads();
+                    for (int e = lane; e < G.jmax * G.jmax; e += 64) {
+                        const int r = e / G.jmax, k = e % G.jmax;
+                        Yf[e] = (r < Jn && k < l) ? Xs[r * KW + k] / sqrt(D[r]) : 0.0;
+                    }
+                    __syncthreads();
+                    accepted = true;
+                    if (cnt0 == 0) accepted = inertia_above(T, A, Jn, th[0] * (1.0 - 4.0 * rq_tol)) == 1;
+                    if (accepted) {
+                        cnt = l;
+                        if (lane == 0) {
+                            counts[fid] = cnt;
+                            wstat[fid] = it;
+                        }
+                    }
+                    break;
+                }
+#pragma unroll
+                for (int c = 0; c < KW; ++c) x[c] = tu[c];
+                __syncthreads();
             }
-            __syncthreads();
         }
-        if (!rot_flag) break;
+        if (!accepted && lane == 0) wstat[fid] = -1;
         __syncthreads();
     }
-    // sort mu descending (lambda = 1/mu ascending)
-    if (lane < Jn) {
-        const double mu = T[lane][lane];
-        int rank = 0;
-        for (int k = 0; k < Jn; ++k) {
-            const double o = T[k][k];
-            rank += (o > mu) || (o == mu && k < lane);
+    if (!accepted) {
+        for (int e = lane; e < Jn * Jn; e += 64) {
+            const int l = e / Jn, mm = e % Jn;
+            V[l][mm] = (l == mm) ? 1.0 : 0.0;
         }
-        order[rank] = lane;
+        __syncthreads();
+        jacobi_rr(&T[0][0], &V[0][0], 65, Jn, cs, &rot_flag);
+        // sort mu descending (lambda = 1/mu ascending)
+        if (lane < Jn) {
+            const double mu = T[lane][lane];
+            int rank = 0;
+            for (int k = 0; k < Jn; ++k) {
+                const double o = T[k][k];
+                rank += (o > mu) || (o == mu && k < lane);
+            }
+            order[rank] = lane;
+        }
+        __syncthreads();
+        for (int k = lane; k < G.jmax; k += 64) ev[k] = (k < Jn) ? 1.0 / T[order[k]][order[k]] : 0.0;
+        __syncthreads();
+        for (int k = 0; k < Jn; ++k) cnt += (1.0 / T[order[k]][order[k]] < tol);
+        cnt = cnt < 1 ? 1 : cnt;
+        if (lane == 0) counts[fid] = cnt;
+        // Y[:, k] = D^{-1/2} v_k for the kept modes; flux f_k = |e| sum_l Y[l][k]
+        for (int e = lane; e < G.jmax * G.jmax; e += 64) {
+            const int l = e / G.jmax, k = e % G.jmax;
+            Yf[e] = (l < Jn && k < cnt) ? V[l][order[k]] / sqrt(D[l]) : 0.0;
+        }
+        if (Vtop)
+            for (int e = lane; e < KW * G.jmax; e += 64) {
+                const int c = e / G.jmax, r = e % G.jmax;
+                Vtop[(long long)fid * KW * G.jmax + e] = (c < Jn && r < Jn) ? (float)V[r][order[c]] : 0.f;
+            }
+        __syncthreads();
     }
-    __syncthreads();
-    double* ev = eigs + (long long)fid * G.jmax;
-    for (int k = lane; k < G.jmax; k += 64) ev[k] = (k < Jn) ? 1.0 / T[order[k]][order[k]] : 0.0;
-    __syncthreads();
-    int cnt = 0;
-    for (int k = 0; k < Jn; ++k) cnt += (1.0 / T[order[k]][order[k]] < tol);
-    cnt = cnt < 1 ? 1 : cnt;
-    if (lane == 0) counts[fid] = cnt;
-    // Y[:, k] = D^{-1/2} v_k for the kept modes; flux f_k = |e| sum_l Y[l][k]
-    double* Yf = Yout + (long long)fid * G.jmax * G.jmax;
-    for (int e = lane; e < G.jmax * G.jmax; e += 64) {
-        const int l = e / G.jmax, k = e % G.jmax;
-        Yf[e] = (l < Jn && k < cnt) ? V[l][order[k]] / sqrt(D[l]) : 0.0;
-    }
-    __syncthreads();
     // recombination Q (cnt x cnt, stored jmax x jmax): column 0 = f/|f|^2 (unit-flux carrier),
     // columns 1.. = an orthonormal basis of f^perp (Householder reflector mapping f/|f| to e_1).
     if (lane == 0) {
@@ -793,10 +1005,16 @@ void gram(tgms_ctx* c) {
 // Entry points used by the host orchestrator (api.hip) that need the kernels above.
 namespace tgms {
 
-void pencil_eig_q(tgms_ctx* c, double* Q) {
+void pencil_eig_q(tgms_ctx* c, double* Q, const float* Y0, float* Vtop) {
     BlockGeom G = geom(c);
-    hipLaunchKernelGGL(k_pencil_eig, dim3(c->ne), dim3(64), 0, c->stream, G, c->kinv, c->G, c->tol, 1.0 / c->H,
-                       c->eigs, c->counts, c->Y, Q);
+    if (c->warm)
+        hipLaunchKernelGGL(k_pencil_eig<1>, dim3(c->ne), dim3(64), 0, c->stream, G, c->kinv, c->G, c->tol,
+                           1.0 / c->H, c->eigs, c->counts, c->Y, Q, Y0, KW, c->rq_tol, c->warm_maxit, c->wstat,
+                           (float*)nullptr);
+    else
+        hipLaunchKernelGGL(k_pencil_eig<0>, dim3(c->ne), dim3(64), 0, c->stream, G, c->kinv, c->G, c->tol,
+                           1.0 / c->H, c->eigs, c->counts, c->Y, Q, (const float*)nullptr, 0, 0.0, 0, (int*)nullptr,
+                           Vtop);
     LAUNCH_OK();
 }
 

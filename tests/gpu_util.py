@@ -50,3 +50,30 @@ def eig_bound(kappa, bx, by, lam):
     contrast = float(kappa.max() / kappa.min())
     base = 100.0 * eps * contrast * max(bx, by) ** 2
     return max(base, 1e-12) + 100.0 * eps * lam / lam.min()
+
+
+def oracle_face(kappa, bx, by, fid):
+    """The oracle's pencil of coarse face fid (x-faces first, then y-faces, each row
+    by row): returns (T = D^{-1/2} S D^{-1/2}, D, S)."""
+    from oracle.discretization import Grid2D, div_matrix, mass_matrix
+    from oracle.local import BorderedSaddle
+    from oracle.spectral import block_rect, pencil, snapshots
+    ny, nx = kappa.shape
+    g = Grid2D(nx, ny, bx, by)
+    Nx = nx // bx
+    nex = (Nx - 1) * (ny // by)
+    if fid < nex:
+        face = ("x", fid % (Nx - 1) + 1, fid // (Nx - 1))
+    else:
+        f = fid - nex
+        face = ("y", f % Nx, f // Nx + 1)
+    kinv = (1.0 / kappa).ravel()
+    A, B = mass_matrix(g, kinv).tocsr(), div_matrix(g).tocsr()
+
+    def block(I, J):
+        r = block_rect(g, I, J)
+        return BorderedSaddle(A, B, g.faces_in(*r), g.cells_in(*r))
+    fa, Psi = snapshots(g, A, B, block, face)
+    Dg, S = pencil(g, A, B, kinv, face, fa, Psi)
+    d = 1.0 / np.sqrt(Dg)
+    return d[:, None] * S * d[None, :], Dg, S

@@ -1,0 +1,211 @@
+"""Warm-started local eigensolves and the warm-start network against the oracle (needs an MI355X).
+
+The network's forward pass and training step are compared with oracle/cnn.py on
+the same parameters and inputs (FP32 kernels against FP64); the warm-started
+eigensolves with the oracle's subspace iteration on the oracle's own pencils.
+"""
+import numpy as np
+import pytest
+
+from workloads import fields
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+from gpu_util import dev, host, oracle_face  # noqa: E402
+from oracle import cnn as ocnn  # noqa: E402
+
+C = 16
+
+
+def f32(a):
+    return torch.tensor(np.asarray(a, dtype=np.float32)).cuda()
+
+
+def params_with_biases(seed):
+    theta = ocnn.init_params(C, seed=seed)
+    rng = np.random.default_rng(seed + 100)
+    o = 0
+    for co, ci in ocnn.layer_shapes(C):
+        o += co * ci * 9
+        theta[o:o + co] = 0.1 * rng.standard_normal(co)
+        o += co
+    return theta
+
+
+@pytest.mark.parametrize("H,W", [(8, 4), (32, 16), (5, 7), (64, 8)])
+def test_cnn_forward_matches_oracle(H, W):
+    from paper_1807_07220_amd import warmstart as ws
+    theta = params_with_biases(1)
+    X = np.random.default_rng(H * 100 + W).standard_normal((3, H, W))
+    Yg = host(ws.forward(f32(theta), f32(X)))
+    Yo = np.stack([ocnn.forward(theta, C, x)[0] for x in X])
+    assert Yg.shape == (3, ocnn.KOUT, W)
+    # FP32 sums of at most 16 x 9 products per layer, four layers
+    assert np.abs(Yg - Yo).max() <= 1e-4 * np.abs(Yo).max()
+
+
+@pytest.mark.parametrize("k", [8, 3])
+def test_cnn_train_step_matches_oracle(k):
+    from paper_1807_07220_amd import warmstart as ws
+    H, W, n, lr = 32, 16, 4, 1e-3
+    rng = np.random.default_rng(9 + k)
+    theta = params_with_biases(2)
+    X = rng.standard_normal((n, H, W))
+    V = np.stack([np.linalg.qr(rng.standard_normal((W, 8)))[0].T for _ in range(n)])
+    Lo, Go = ocnn.batch_loss_grad(theta, C, X, V[:, :k], k)
+    tr = ws.Trainer(f32(theta), n, H, W)
+    L = tr.step(f32(X), f32(V), k, lr)
+    assert abs(L - Lo) <= 1e-4 * abs(Lo)
+    G = host(tr.m) / (1.0 - ocnn.ADAM_B1)          # first Adam step: m = (1 - beta1) g
+    assert np.abs(G - Go).max() <= 1e-3 * np.abs(Go).max()
+    th1, _, _ = ocnn.adam_step(theta, np.zeros_like(theta), np.zeros_like(theta), Go, 1, lr)
+    big = np.abs(Go) > 1e-3 * np.abs(Go).max()     # the step is lr * sign(g) where |g| >> eps
+    assert np.abs(host(tr.w)[big] - th1[big]).max() <= 1e-6
+
+
+def test_cnn_samples_match_oracle():
+    import paper_1807_07220_amd as tg
+    kappa = fields.field_channelized(64, 64, 31, contrast=1e6)
+    s = tg.Solver(dev(kappa), 16, 16, 0.2)
+    X, V = s.cnn_samples()
+    X, V = host(X), host(V)
+    s.close()
+    assert X.shape == (24, 32, 16) and V.shape == (24, 8, 16)
+    for fid in (0, 5, 11, 12, 17, 23):
+        assert np.allclose(X[fid], ocnn.face_window(kappa, 16, 16, fid), rtol=1e-6, atol=1e-6)
+        T, _, _ = oracle_face(kappa, 16, 16, fid)
+        mu, Q = np.linalg.eigh(T)
+        mu, Q = mu[::-1], Q[:, ::-1]
+        for c in range(8):
+            gap = min(abs(mu[c] - mu[c - 1]) if c > 0 else np.inf, abs(mu[c] - mu[c + 1]))
+            if gap > 1e-3 * mu[0]:     # well-separated eigenvectors are defined up to sign
+                assert abs(abs(V[fid, c] @ Q[:, c]) - 1.0) <= 1e-5
+
+
+def _face_starts(mode, kappa, w, nf):
+    if mode == "dct":
+        return [ocnn.dct_start(16, 8) for _ in range(nf)]
+    from paper_1807_07220_amd import warmstart as ws
+    Xw = np.stack([ocnn.face_window(kappa, 16, 16, f) for f in range(nf)])
+    # the library starts from its FP32 network output; the oracle from the same values
+    Y = host(ws.forward(w, f32(Xw))).astype(np.float64)
+    return [Y[f].T for f in range(nf)]
+
+
+@pytest.mark.parametrize("mode", ["dct", "cnn"])
+def test_warm_start_matches_oracle(mode):
+    import paper_1807_07220_amd as tg
+    from paper_1807_07220_amd import warmstart as ws
+    tol = 0.2
+    kappa = fields.field_channelized(64, 64, 41, contrast=1e6)
+    w = ws.init_weights(seed=5) if mode == "cnn" else None
+    s_ex = tg.Solver(dev(kappa), 16, 16, tol)
+    s = tg.Solver(dev(kappa), 16, 16, tol, warm_start=mode, cnn_weights=w)
+    wst, cnt, cnt_ex = s.warm_status(), s.counts(), s_ex.counts()
+    eg = s.eigs()
+    assert np.array_equal(cnt, cnt_ex)
+    nf = len(cnt)
+    starts = _face_starts(mode, kappa, w, nf)
+    agree, accepted = 0, 0
+    for f in range(nf):
+        T, Dg, S = oracle_face(kappa, 16, 16, f)
+        ok, it, c0, th, U = ocnn.warm_eigensolve(T, starts[f], tol)
+        agree += (wst[f] >= 0) == ok
+        if wst[f] >= 0:
+            accepted += 1
+            if ok:
+                assert abs(int(wst[f]) - it) <= 1
+            lam = np.sort(1.0 / np.linalg.eigvalsh(T)[::-1][:8])
+            l = cnt[f]
+            assert np.allclose(eg[f, :l], lam[:l], rtol=1e-9)
+        else:
+            # the dense fallback reproduces the exact path
+            assert np.array_equal(eg[f], s_ex.eigs()[f])
+    assert accepted > 0
+    assert agree >= nf - 1          # a decision at the residual threshold may differ
+    # the coarse space is the same up to the Ritz accuracy: same solve
+    F = fields.corner_source(64, 64)
+    r = s.solve(dev(F), rtol=1e-10)
+    rx = s_ex.solve(dev(F), rtol=1e-10)
+    assert r["converged"] and abs(r["iters"] - rx["iters"]) <= 1
+    assert np.linalg.norm(host(r["u"]) - host(rx["u"])) <= 1e-7 * np.linalg.norm(host(rx["u"]))
+    s.close()
+    s_ex.close()
+
+
+def test_warm_start_falls_back_when_the_block_is_too_small():
+    """With every eigenvalue below tol (l = J = 16 >= k = 8) no face can be certified:
+    all fall back to the dense solve, with the exact path's results."""
+    import paper_1807_07220_amd as tg
+    kappa = fields.field_channelized(64, 64, 43, contrast=1e6)
+    s = tg.Solver(dev(kappa), 16, 16, 1e6, warm_start="dct")
+    s_ex = tg.Solver(dev(kappa), 16, 16, 1e6)
+    assert np.all(s.warm_status() == -1)
+    assert np.array_equal(s.counts(), s_ex.counts()) and np.array_equal(s.eigs(), s_ex.eigs())
+    assert s.info()["warm_accepted"] == 0
+    s.close()
+    s_ex.close()
+
+
+def test_warm_start_errors():
+    import paper_1807_07220_amd as tg
+    from paper_1807_07220_amd import TgmsError
+    from paper_1807_07220_amd import warmstart as ws
+    kappa = dev(fields.field_channelized(64, 64, 44, contrast=1e6))
+    with pytest.raises(TgmsError) as e:
+        tg.Solver(kappa, 16, 16, 0.2, warm_start="cnn")
+    assert e.value.status == "INVAL"
+    w = ws.init_weights(seed=0)
+    with pytest.raises(TgmsError) as e:
+        tg.Solver(kappa, 16, 8, 0.2, warm_start="cnn", cnn_weights=w)
+    assert e.value.status == "UNSUPPORTED"
+    with pytest.raises(TgmsError) as e:
+        tg.Solver(dev(np.ones((64, 64))), 32, 32, 0.2, warm_start="cnn", cnn_weights=w)
+    assert e.value.status == "UNSUPPORTED"
+    s = tg.Solver(kappa, 16, 16, 0.2)
+    with pytest.raises(TgmsError):
+        s.warm_status()
+    s.update_mobility(dev(np.full((64, 64), 2.0)))
+    with pytest.raises(TgmsError):
+        s.cnn_samples()
+    s.close()
+
+
+def test_cnn_training_reduces_loss():
+    from paper_1807_07220_amd import warmstart as ws
+    X, V = ws.collect_samples([fields.field_channelized(64, 64, s, contrast=1e6) for s in (21, 22, 23)], 16, 0.2)
+    _, losses = ws.train(X, V, k=8, steps=300, batch=64, lr=3e-3, seed=0)
+    assert np.mean(losses[-20:]) < 0.8 * np.mean(losses[:5])
+
+
+def test_trained_weights_on_held_out_field():
+    """The committed weights (paper_1807_07220_amd/train_warmstart.py, trained on
+    other seeds) on the 1024 x 1024 workload's field: every face is accounted for,
+    the certified faces keep the exact counts, and the solve is unchanged."""
+    import os
+
+    import paper_1807_07220_amd as tg
+    from paper_1807_07220_amd import warmstart as ws
+    from workloads import configs
+    path = os.path.join(os.path.dirname(tg.__file__), "data", "warmstart_b16.npy")
+    w8 = ws.load_weights(path)
+    wl = configs.get("darcy2d_1024_b16")
+    kappa, F = wl.make_inputs()
+    kd = dev(kappa)
+    s = tg.Solver(kd, 16, 16, wl.eig_tol, warm_start="cnn", cnn_weights=w8)
+    s_ex = tg.Solver(kd, 16, 16, wl.eig_tol)
+    st = s.warm_status()
+    assert np.array_equal(s.counts(), s_ex.counts())
+    assert np.mean(st >= 0) >= 0.9
+    r, rx = s.solve(dev(F), rtol=wl.rtol), s_ex.solve(dev(F), rtol=wl.rtol)
+    assert abs(r["iters"] - rx["iters"]) <= 1
+    s.close()
+    s_ex.close()

@@ -60,6 +60,18 @@ def test_backward_matches_finite_differences():
     assert o == cnn.nparams(C) == theta.size
 
 
+def test_zero_network_gives_the_dct_start():
+    theta = cnn.init_params(4, seed=0)
+    o = sum(co * ci * 9 + co for co, ci in cnn.layer_shapes(4)[:3])
+    theta[o:] = 0.0                                     # last layer: zero weights and biases
+    x = np.random.default_rng(0).standard_normal((6, 11))
+    y, _ = cnn.forward(theta, 4, x)
+    D = cnn.dct_start(11, 8)
+    assert np.allclose(y, (D / np.linalg.norm(D, axis=0)).T, atol=1e-15)
+    y3, _ = cnn.forward(theta, 4, x[:, :3])            # W < 8: the rows beyond W are zero
+    assert np.all(y3[3:] == 0.0) and np.allclose(np.linalg.norm(y3[:3], axis=1), 1.0)
+
+
 def test_adam_first_step_closed_form():
     g = np.array([0.5, -2.0, 1e-3])
     th, m, v = cnn.adam_step(np.zeros(3), np.zeros(3), np.zeros(3), g, 1, 0.01)
