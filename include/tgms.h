@@ -174,8 +174,11 @@ tgms_status tgms_last_cond(const tgms_ctx* ctx, double* cond);
  * measurements).  tgms_profile(ctx, 1) starts recording every launch of the
  * instrumented kernels (and clears earlier records); tgms_profile_get
  * returns the number of launches and their summed duration in ms.
- * kernel: 0 = smoother patch solve, 1 = stream-function operator apply
- * (K psi = C^T A C psi), 2 = coarse restriction, 3 = coarse prolongation. */
+ * kernel: 0 = smoother patch solve, 1 = search-direction update with the
+ * stream-function operator apply (q = K p, K = C^T A C), 2 = first gather of the
+ * patch solutions with the residual and the coarse restriction (and, in the
+ * probes, the plain restriction), 3 = coarse prolongation with the second
+ * residual (in the probes, the plain prolongation). */
 tgms_status tgms_profile(tgms_ctx* ctx, int enable);
 tgms_status tgms_profile_get(tgms_ctx* ctx, int kernel, int* launches, double* total_ms);
 

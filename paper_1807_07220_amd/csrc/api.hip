@@ -136,22 +136,24 @@ double lanczos_cond(const std::vector<double>& al, const std::vector<double>& be
 template <typename T>
 void twogrid(tgms_ctx* c, const T* g, const double* gd, double* z, const double* gold, bool dots, bool first) {
     const double* sc = dots ? c->sc : nullptr;
-    T *w, *z1, *t;
+    T *w, *z1, *z2, *t;
     if constexpr (sizeof(T) == 8) {
         w = (T*)c->patW;
         z1 = (T*)c->vt2;
+        z2 = (T*)c->vt3;
         t = (T*)c->vt;
     } else {
         w = (T*)c->patW32;
         z1 = (T*)c->fz;
+        z2 = (T*)c->ft2;
         t = (T*)c->ft;
     }
     tgms::smooth_patches<T>(c, g, sc);
-    tgms::gather_res<T>(c, w, gd, z1, t, sc);
-    tgms::coarse_apply<T>(c, t, z1, true, sc);
-    tgms::residual<T>(c, z1, gd, t, sc);
+    tgms::gather_res_restrict<T>(c, w, gd, z1, t, tgms::coarse_cy<T>(c), sc);
+    const T* cres = tgms::coarse_solve<T>(c, sc);
+    tgms::prolong_residual<T>(c, cres, z1, z2, gd, t, sc);
     tgms::smooth_patches<T>(c, t, sc);
-    tgms::gather_final<T>(c, w, z1, z, dots ? gd : nullptr, gold, dots, first);
+    tgms::gather_final<T>(c, w, z2, z, dots ? gd : nullptr, gold, dots, first);
 }
 
 // probes: which = 0 smoother, 1 coarse correction, 2 two-grid; g, z FP64 vertex arrays
@@ -486,35 +488,17 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         }
         // snapshot storage is no longer needed
         // pressure: orthonormal DCT-II matrices and the 1D Neumann eigenvalues
-        {
-            auto dct = [](int n, std::vector<double>& Q, std::vector<double>& lam) {
-                Q.assign((size_t)n * n, 0.0);
-                lam.assign(n, 0.0);
-                for (int i = 0; i < n; ++i)
-                    for (int k = 0; k < n; ++k)
-                        Q[(size_t)i * n + k] = (k == 0 ? std::sqrt(1.0 / n) : std::sqrt(2.0 / n)) *
-                                               std::cos(M_PI * k * (i + 0.5) / n);
-                for (int k = 0; k < n; ++k) lam[k] = 2.0 - 2.0 * std::cos(M_PI * k / n);
-            };
-            std::vector<double> Q, lam;
-            dct(nx, Q, lam);
-            c->Qx = c->alloc<double>(Q.size());
-            c->lamx = c->alloc<double>(nx);
-            HIP_OK(hipMemcpyAsync(c->Qx, Q.data(), sizeof(double) * Q.size(), hipMemcpyHostToDevice, c->stream));
-            HIP_OK(hipMemcpyAsync(c->lamx, lam.data(), sizeof(double) * nx, hipMemcpyHostToDevice, c->stream));
-            HIP_OK(hipStreamSynchronize(c->stream));
-            dct(ny, Q, lam);
-            c->Qy = c->alloc<double>(Q.size());
-            c->lamy = c->alloc<double>(ny);
-            HIP_OK(hipMemcpyAsync(c->Qy, Q.data(), sizeof(double) * Q.size(), hipMemcpyHostToDevice, c->stream));
-            HIP_OK(hipMemcpyAsync(c->lamy, lam.data(), sizeof(double) * ny, hipMemcpyHostToDevice, c->stream));
-            HIP_OK(hipStreamSynchronize(c->stream));
-        }
+        c->Qx = c->alloc<double>((size_t)nx * nx);
+        c->lamx = c->alloc<double>(nx);
+        c->Qy = c->alloc<double>((size_t)ny * ny);
+        c->lamy = c->alloc<double>(ny);
+        tgms::dct_matrix(c, nx, c->Qx, c->lamx);
+        tgms::dct_matrix(c, ny, c->Qy, c->lamy);
         // solve workspaces
         const long long nvtx = ncell;
         c->vx = c->alloc<double>(nvtx); c->vg = c->alloc<double>(nvtx); c->vz = c->alloc<double>(nvtx);
         c->vp = c->alloc<double>(nvtx); c->vq = c->alloc<double>(nvtx); c->vt = c->alloc<double>(nvtx);
-        c->vt2 = c->alloc<double>(nvtx); c->vgold = c->alloc<double>(nvtx);
+        c->vt2 = c->alloc<double>(nvtx); c->vt3 = c->alloc<double>(nvtx); c->vgold = c->alloc<double>(nvtx);
         c->fg = c->alloc<float>(nvtx); c->fz = c->alloc<float>(nvtx); c->ft = c->alloc<float>(nvtx);
         c->ft2 = c->alloc<float>(nvtx);
         c->fbar = c->alloc<double>(c->nf); c->fu = c->alloc<double>(c->nf); c->fF = c->alloc<double>(c->nf);
@@ -522,6 +506,8 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         c->blkbuf = c->alloc<double>(2 * (size_t)c->nblk);
         c->sc = c->alloc<double>(SC_COUNT);
         c->part = c->alloc<double>(3 * (size_t)tgms::pcg_tiles(c));
+        c->part2 = c->alloc<double>((size_t)tgms::pcg_tiles(c));
+        tgms::allow_fused_lds(c);
         c->vp1 = c->alloc<double>(nvtx);
         HIP_OK(hipHostMalloc((void**)&c->red_h, SC_COUNT * sizeof(double), hipHostMallocDefault));
         if (o.autotune) tgms::autotune(c, o.tune_cache);
@@ -660,6 +646,8 @@ void solve_impl(tgms_ctx* c, const double* F, const double* g_bnd, double rtol, 
                     iteration(c->vp1, c->vp);
             }
         }
+        // the last queued iteration's scalars (the next iteration would finalise them)
+        tgms::finalize(c, false);
         read_sc();
     }
     c->prof_iter = -1;

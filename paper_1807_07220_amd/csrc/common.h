@@ -168,7 +168,9 @@ struct tgms_ctx {
     double* sc = nullptr;     // device PCG scalars (SC_* below)
     double* hist = nullptr;   // device alpha/beta history
     int hist_cap = 0;
-    double* part = nullptr;   // per-workgroup partial sums of the fused PCG kernels
+    double* part = nullptr;   // per-workgroup partial sums of the final gather (3 x NRED)
+    double* part2 = nullptr;  // per-workgroup partial sums of p.q (NRED)
+    double* vt3 = nullptr;    // z1 after the coarse correction (FP64 preconditioner)
     int nred = 256;           // workgroups of the reducing PCG kernels (autotuned)
     int smooth_staged = -1;   // smoother: 1 factor staged in LDS, 0 read from global, -1 by LDS fit
     int snap_cols = 1;        // snapshots: 1 one lane per column where supported, 0 one wave per block
@@ -226,9 +228,11 @@ struct tgms_ctx {
 
 // ---------------------------------------------------------------- launchers
 // device PCG scalars: rho, p.q, alpha, beta, |z|^2, |z|^2/|z0|^2, |z0|^2, breakdown flag,
-// iteration count, done flag, rtol^2, maxit, flexible (1) or Fletcher-Reeves (0)
+// iteration count, done flag, rtol^2, maxit, flexible (1) or Fletcher-Reeves (0), the
+// rho of the latest finalisation (moved into rho by the next update), and the flag
+// of gather partials not finalised yet
 enum { SC_RHO = 0, SC_PQ, SC_ALPHA, SC_BETA, SC_ZN2, SC_REL2, SC_Z02, SC_FLAG, SC_IT, SC_DONE, SC_RTOL2, SC_MAXIT,
-       SC_FLEX, SC_COUNT };
+       SC_FLEX, SC_RHO_NEW, SC_PENDING, SC_COUNT };
 
 namespace tgms {
 enum ProfKernel { PK_SMOOTH = 0, PK_APPLYK = 1, PK_RESTRICT = 2, PK_PROLONG = 3, PK_COUNT = 4 };
@@ -266,13 +270,15 @@ int nred_max();
 void autotune(tgms_ctx* c, const char* cache_path);  // picks nred, smoother staging (k_tune.hip)
 void dir_apply(tgms_ctx* c, const double* z, const double* pin, double* pout, double* q);
 void update(tgms_ctx* c, const double* p, const double* q, double* x, double* g, double* gold, float* g32);
+void finalize(tgms_ctx* c, bool first);  // scalars from pending gather partials (first: rho_0, |z_0|^2)
+void allow_fused_lds(tgms_ctx* c);      // LDS limit of the per-block fused kernels (large blocks)
 template <typename T>
-void gather_res(tgms_ctx* c, const T* w, const double* g, T* z, T* t, const double* sc);
+void gather_res_restrict(tgms_ctx* c, const T* w, const double* g, T* z, T* t, T* cy, const double* sc);
+template <typename T>
+void prolong_residual(tgms_ctx* c, const T* cres, const T* zin, T* zout, const double* g, T* t, const double* sc);
 template <typename T>
 void gather_final(tgms_ctx* c, const T* w, const T* zin, double* zout, const double* g, const double* gold,
                   bool with_dots, bool first);
-template <typename T>
-void residual(tgms_ctx* c, const T* z, const double* g, T* t, const double* sc);
 // setup (k_setup.hip)
 void snapshots(tgms_ctx* c);
 void gram(tgms_ctx* c);
@@ -292,6 +298,10 @@ void rt0_stiffness(tgms_ctx* c, double* K);
 // coarse apply (k_setup.hip)
 template <typename T>
 void coarse_apply(tgms_ctx* c, const T* g, T* z, bool accumulate, const double* sc);
+template <typename T>
+T* coarse_cy(tgms_ctx* c);  // the block restriction buffer of the coarse correction
+template <typename T>
+const T* coarse_solve(tgms_ctx* c, const double* sc);  // accumulate the restrictions, apply the coarse inverse
 // dense (k_dense.hip)
 void dense_spd_inverse(tgms_ctx* c, double* A, int n);
 template <typename T>
@@ -301,4 +311,5 @@ void gemm(tgms_ctx* c, int transA, int transB, int M, int N, int K, double alpha
 // preprocessing and pressure (k_pre.hip)
 void preprocess(tgms_ctx* c, const double* F, const double* g_bnd, double* vbar, double* Fp);
 void pressure(tgms_ctx* c, const double* u, double* p);
+void dct_matrix(tgms_ctx* c, int n, double* Q, double* lam);  // orthonormal DCT-II and Neumann eigenvalues
 }  // namespace tgms

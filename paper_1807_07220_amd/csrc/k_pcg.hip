@@ -1,18 +1,28 @@
 // Fused kernels of the PCG iteration (paper section 5, Step 3) and of the
 // two-grid preconditioner around the smoother and coarse solves.
 //
-// One PCG iteration in stream-function coordinates is
-//   p = z + beta p;  q = K p;  alpha = rho / p.q           (k_dir_apply)
-//   x += alpha p;  g -= alpha q                            (k_update)
-//   z = B_TG g                                             (smoother, k_gather_res, coarse, residual,
-//                                                            smoother, k_gather_final)
-//   rho' = g.z, beta = rho'/rho (or (g.z - gold.z)/rho), |C z|^2  (k_gather_final)
-// The kernels that form inner products run on a fixed grid of nred <= NRED
-// workgroups (chosen by the autotuner) that loop over the tiles, and write one
-// partial sum per workgroup; the next kernel sums those partials in a fixed order (so results do not depend on
-// scheduling, and the kernel boundary makes the partials visible without device
-// fences).  Every kernel first checks the done flag in sc and returns when it is
-// set, so iterations queued after convergence cost only their launches.
+// One PCG iteration in stream-function coordinates is 9 kernels:
+//   [finalise the last iteration: rho' = g.z, beta, |C z|^2 test]
+//   p = z + beta p;  q = K p;  partial p.q                        (k_dir_apply)
+//   alpha = rho / p.q;  x += alpha p;  g -= alpha q               (k_update)
+//   z = B_TG g: smoother; z1 = eta sum ext(w), t = g - K z1 and the
+//   block restriction W_b^T t (k_gather_res_restrict); coarse accumulation and
+//   the two triangular products; z1' = z1 + W c, t = g - K z1'
+//   (k_prolong_residual); smoother; z = z1' + eta sum ext(w) with the partials of
+//   g.z, gold.z and |C z|^2 (k_gather_final).
+// The partials of k_gather_final are finalised by the next iteration's
+// k_dir_apply (every workgroup forms the same sums; workgroup 0 records them),
+// or by k_finalize where the host needs the scalars (after the first
+// preconditioning and at the end of each group of queued iterations).  A
+// "pending" flag in sc tells which: set by k_gather_final, cleared by k_finalize
+// or by k_update (the kernel after the one that finalised), so that no
+// workgroup reads a scalar another workgroup of the same kernel writes.
+// The reducing kernels run on a fixed grid of nred <= NRED workgroups (chosen by
+// the autotuner) that loop over the tiles and write one partial each; the
+// consumer sums them in a fixed order (results do not depend on scheduling, and
+// the kernel boundary makes them visible without device fences).  Every kernel
+// first checks the done flag in sc, so iterations queued after convergence cost
+// only their launches.
 #include "common.h"
 
 namespace {
@@ -53,55 +63,98 @@ __device__ inline double sum_partials(const double* __restrict__ part, int k, in
     return v[0];
 }
 
-// 9-point stencil K at tile position (ty+1, tx+1) of an LDS tile with a one-vertex halo
-template <typename T>
-__device__ inline T stencil_tile(const T (&P)[TY + 2][TX + 2], int tx, int ty, const T* __restrict__ a, long long v,
-                                 int nx, T sx2, T sy2) {
-    const T A00 = a[v - nx - 1], A10 = a[v - nx], A01 = a[v - 1], A11 = a[v];
-    const T s = sx2 + sy2;
-    const T c6 = T(1.0 / 6.0), c3 = T(1.0 / 3.0);
-    const T kx = sx2 * c6 - sy2 * c3, ky = sy2 * c6 - sx2 * c3;
+// 9-point stencil K at tile position (ty+1, tx+1) of an LDS tile with a one-vertex halo,
+// with the four cell weights around the vertex (SW, SE, NW, NE) already loaded
+__device__ inline double stencil_tile4(const double (&P)[TY + 2][TX + 2], int tx, int ty, const double (&A)[4],
+                                       double sx2, double sy2) {
+    const double A00 = A[0], A10 = A[1], A01 = A[2], A11 = A[3];
+    const double s = sx2 + sy2;
+    const double c6 = 1.0 / 6.0, c3 = 1.0 / 3.0;
+    const double kx = sx2 * c6 - sy2 * c3, ky = sy2 * c6 - sx2 * c3;
     const int x = tx + 1, y = ty + 1;
-    T r = s * c3 * (A00 + A10 + A01 + A11) * P[y][x];
+    double r = s * c3 * (A00 + A10 + A01 + A11) * P[y][x];
     r += kx * ((A10 + A11) * P[y][x + 1] + (A00 + A01) * P[y][x - 1]);
     r += ky * ((A01 + A11) * P[y + 1][x] + (A00 + A10) * P[y - 1][x]);
     r -= s * c6 * (A11 * P[y + 1][x + 1] + A01 * P[y + 1][x - 1] + A10 * P[y - 1][x + 1] + A00 * P[y - 1][x - 1]);
     return r;
 }
 
-// p_out = z + beta p_in (beta = 0 on the first iteration), q = K p_out, and the
-// workgroup's partial sum of p_out . q.  The workgroups loop over the tiles.
+// The scalars after an iteration's last gather, from its partials gpart (g.z, gold.z,
+// |C z|^2): beta, rho' and the relative residual; recorded by the calling thread
+// when rec.  Returns true when the iteration stops here: converged, a breakdown,
+// or (rec only: the other workgroups do not read the iteration count, which rec
+// updates) maxit reached.
+__device__ inline bool finalise(double* __restrict__ sc, double* __restrict__ hist, const double* __restrict__ gpart,
+                                int nred, bool rec, double* beta_out) {
+    const double gz = sum_partials(gpart, 0, nred), zgold = sum_partials(gpart, 1, nred),
+                 zn2 = sum_partials(gpart, 2, nred);
+    const double rho = sc[SC_RHO];
+    const double beta = (sc[SC_FLEX] != 0.0) ? (gz - zgold) / rho : gz / rho;
+    const double rel2 = zn2 / sc[SC_Z02];
+    const bool bad = !(rel2 < INFINITY) || !(beta == beta);
+    bool stop = bad || rel2 <= sc[SC_RTOL2];
+    if (rec) {
+        const int it = (int)sc[SC_IT];
+        stop = stop || it + 1 >= (int)sc[SC_MAXIT];
+        sc[SC_BETA] = beta;
+        sc[SC_RHO_NEW] = gz;
+        sc[SC_ZN2] = zn2;
+        sc[SC_REL2] = rel2;
+        hist[2 * it + 1] = beta;
+        sc[SC_IT] = it + 1;
+        if (bad) sc[SC_FLAG] = 1.0;
+        if (stop) sc[SC_DONE] = 1.0;
+    }
+    *beta_out = beta;
+    return stop;
+}
+
+// p_out = z + beta p_in, q = K p_out, and the workgroup's partial sum of p_out . q
+// (part).  beta comes from finalising the pending partials gpart, else from sc.  The
+// workgroups loop over the tiles.
 __global__ void __launch_bounds__(NT) k_dir_apply(const double* __restrict__ z, const double* __restrict__ pin,
                                                   double* __restrict__ pout, double* __restrict__ q,
                                                   const double* __restrict__ a, int nx, int ny, double sx2,
-                                                  double sy2, const double* __restrict__ sc,
+                                                  double sy2, double* __restrict__ sc, double* __restrict__ hist,
+                                                  const double* __restrict__ gpart, int nred,
                                                   double* __restrict__ part) {
     if (finished(sc)) return;
     __shared__ double P[TY + 2][TX + 2];
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
     const int ntx = (nx + TX - 1) / TX, ntiles = ntx * ((ny + TY - 1) / TY);
-    const double beta = sc[SC_BETA];
+    double beta = sc[SC_BETA];
+    if (sc[SC_PENDING] != 0.0) {
+        const bool rec = blockIdx.x == 0 && tid == 0;
+        if (finalise(sc, hist, gpart, nred, rec, &beta)) return;
+    }
     double v[1] = {0.0};
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * TY;
+        const int i = i0 + tx, j = j0 + ty;
+        const long long vv = (long long)j * nx + i;
+        const bool in = i > 0 && j > 0 && i < nx && j < ny;
+        double A[4] = {0.0, 0.0, 0.0, 0.0};  // weights load with the tile
+        if (in) {
+            A[0] = a[vv - nx - 1];
+            A[1] = a[vv - nx];
+            A[2] = a[vv - 1];
+            A[3] = a[vv];
+        }
         __syncthreads();
         for (int e = tid; e < (TX + 2) * (TY + 2); e += NT) {
             const int ii = i0 - 1 + e % (TX + 2), jj = j0 - 1 + e / (TX + 2);
             double val = 0.0;
             if (ii >= 1 && ii < nx && jj >= 1 && jj < ny) {
-                const long long vv = (long long)jj * nx + ii;
-                val = z[vv] + beta * pin[vv];
+                const long long ve = (long long)jj * nx + ii;
+                val = z[ve] + beta * pin[ve];
             }
             P[e / (TX + 2)][e % (TX + 2)] = val;
         }
         __syncthreads();
-        const int i = i0 + tx, j = j0 + ty;
         if (i < nx && j < ny) {
-            const long long vv = (long long)j * nx + i;
             const double pc = P[ty + 1][tx + 1];
             pout[vv] = pc;
-            double r = 0.0;
-            if (i > 0 && j > 0) r = stencil_tile<double>(P, tx, ty, a, vv, nx, sx2, sy2);
+            const double r = in ? stencil_tile4(P, tx, ty, A, sx2, sy2) : 0.0;
             q[vv] = r;
             v[0] += pc * r;
         }
@@ -111,8 +164,9 @@ __global__ void __launch_bounds__(NT) k_dir_apply(const double* __restrict__ z, 
 }
 
 // alpha = rho / (p . q) from the partials of k_dir_apply (every workgroup forms it;
-// workgroup 0 records it), then x += alpha p ; gold = g (flexible) ; g -= alpha q ;
-// g32 = (float) g (mixed precision).  A non-positive p . q stops the iteration.
+// workgroup 0 records it, moves rho' into rho and clears the pending flag), then
+// x += alpha p ; gold = g (flexible) ; g -= alpha q ; g32 = (float) g (mixed
+// precision).  A non-positive p . q stops the iteration.
 __global__ void __launch_bounds__(NT) k_update(long long n, double* __restrict__ sc, double* __restrict__ hist,
                                                const double* __restrict__ part, int nred, const double* __restrict__ p,
                                                const double* __restrict__ q, double* __restrict__ x,
@@ -120,10 +174,13 @@ __global__ void __launch_bounds__(NT) k_update(long long n, double* __restrict__
                                                float* __restrict__ g32) {
     if (finished(sc)) return;
     const double pq = sum_partials(part, 0, nred);
-    const double al = sc[SC_RHO] / pq;
+    const double rho = sc[SC_RHO_NEW];
+    const double al = rho / pq;
     const bool bad = !(pq > 0.0) || !(pq < INFINITY);
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
     if (blockIdx.x == 0 && tid == 0) {
+        sc[SC_RHO] = rho;
+        sc[SC_PENDING] = 0.0;
         sc[SC_PQ] = pq;
         sc[SC_ALPHA] = al;
         hist[2 * (int)sc[SC_IT]] = al;
@@ -178,42 +235,180 @@ __device__ inline T patch_sum(const Rect* __restrict__ rects, const T* __restric
     return gather_w<T>(rects, w, i, j, G.bx, G.by, G.Nx, G.Ny);
 }
 
-// First smoothing of the two-grid cycle: z = eta * sum_i ext(w_i), t = g - K z.
+// 9-point stencil K at (x, y) of an FP64 LDS tile with row pitch pw, with the four
+// cell weights around the vertex already loaded
+__device__ inline double stencil_at4(const double* __restrict__ P, int pw, int x, int y, const double (&A)[4],
+                                     double sx2, double sy2) {
+    const double A00 = A[0], A10 = A[1], A01 = A[2], A11 = A[3];
+    const double s = sx2 + sy2;
+    const double c6 = 1.0 / 6.0, c3 = 1.0 / 3.0;
+    const double kx = sx2 * c6 - sy2 * c3, ky = sy2 * c6 - sx2 * c3;
+    const double* r0 = P + (y - 1) * pw + x;
+    const double* r1 = P + y * pw + x;
+    const double* r2 = P + (y + 1) * pw + x;
+    double r = s * c3 * (A00 + A10 + A01 + A11) * r1[0];
+    r += kx * ((A10 + A11) * r1[1] + (A00 + A01) * r1[-1]);
+    r += ky * ((A01 + A11) * r2[0] + (A00 + A10) * r0[0]);
+    r -= s * c6 * (A11 * r2[1] + A01 * r2[-1] + A10 * r0[1] + A00 * r0[-1]);
+    return r;
+}
+
+// g and the four cell weights of interior vertex v (zeros elsewhere): loaded before a
+// tile barrier so that their latency overlaps the tile's
+struct VertexData {
+    double g, A[4];
+};
+__device__ inline VertexData vertex_data(const double* __restrict__ g, const double* __restrict__ a, long long v,
+                                         int nx, bool interior) {
+    VertexData d{0.0, {0.0, 0.0, 0.0, 0.0}};
+    if (interior) {
+        d.g = g[v];
+        d.A[0] = a[v - nx - 1];
+        d.A[1] = a[v - nx];
+        d.A[2] = a[v - 1];
+        d.A[3] = a[v];
+    }
+    return d;
+}
+
+// Coarse-space data of the fused two-grid kernels: stream functions W
+// [block][owned vertex][slot], per-block unknown ids and counts.
 template <typename T>
-__global__ void __launch_bounds__(NT) k_gather_res(const Rect* __restrict__ rects, const T* __restrict__ w,
-                                                   const T* __restrict__ w4, GatherGeom G, T eta,
-                                                   const double* __restrict__ g, const double* __restrict__ a,
-                                                   double sx2, double sy2, T* __restrict__ z, T* __restrict__ t,
-                                                   const double* __restrict__ sc) {
+struct CoarseW {
+    const T* W;
+    int mu;
+    const int* unk;
+    const int* nunk;
+};
+
+// First gather and restriction, one workgroup per coarse block: z1 = eta * (sum of the
+// patch solutions), t = g - K z1 (formed in FP64 from z1 as stored, rounded once) on
+// the block's vertices, and cy[b] = W_b^T t.  LDS: the block with a one-vertex halo
+// (FP64), t on the block, and the restriction partials.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_gather_res_restrict(const Rect* __restrict__ rects, const T* __restrict__ w,
+                                                            const T* __restrict__ w4, GatherGeom G, T eta,
+                                                            const double* __restrict__ g,
+                                                            const double* __restrict__ a, double sx2, double sy2,
+                                                            T* __restrict__ z, T* __restrict__ t, CoarseW<T> C,
+                                                            T* __restrict__ cy, const double* __restrict__ sc) {
     if (finished(sc)) return;
-    // the tile holds z exactly as stored (in T); the residual is formed in FP64 and
-    // rounded once, so an FP32 z does not lose the small residual to cancellation
-    __shared__ double Z[TY + 2][TX + 2];
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
-    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
-    for (int e = tid; e < (TX + 2) * (TY + 2); e += NT) {
-        const int ii = i0 - 1 + e % (TX + 2), jj = j0 - 1 + e / (TX + 2);
+    extern __shared__ double smem[];
+    const int bx = G.bx, by = G.by, pw = bx + 2, nown = bx * by;
+    double* Z = smem;                                  // (by + 2) x (bx + 2)
+    T* tb = reinterpret_cast<T*>(Z + (by + 2) * pw);  // nown
+    const int tid = threadIdx.y * TX + threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int blk = blockIdx.x, i0 = (blk % G.Nx) * bx, j0 = (blk / G.Nx) * by;
+    // the first owned vertex of this thread: its g and weights load with the tile
+    VertexData d0{};
+    if (tid < nown) {
+        const int i = i0 + tid % bx, j = j0 + tid / bx;
+        d0 = vertex_data(g, a, (long long)j * G.nx + i, G.nx, i > 0 && j > 0);
+    }
+    for (int e = tid; e < (bx + 2) * (by + 2); e += NT) {
+        const int ii = i0 - 1 + e % pw, jj = j0 - 1 + e / pw;
         T val = T(0);
         if (ii >= 1 && ii < G.nx && jj >= 1 && jj < G.ny) val = eta * patch_sum<T>(rects, w, w4, G, ii, jj);
-        Z[e / (TX + 2)][e % (TX + 2)] = double(val);
+        Z[e] = double(val);
     }
     __syncthreads();
-    const int i = i0 + tx, j = j0 + ty;
-    if (i >= G.nx || j >= G.ny) return;
-    const long long v = (long long)j * G.nx + i;
-    z[v] = T(Z[ty + 1][tx + 1]);
-    t[v] = (i > 0 && j > 0) ? T(g[v] - stencil_tile<double>(Z, tx, ty, a, v, G.nx, sx2, sy2)) : T(0);
+    for (int vl = tid; vl < nown; vl += NT) {
+        const int aa = vl % bx, bb = vl / bx, i = i0 + aa, j = j0 + bb;
+        const long long v = (long long)j * G.nx + i;
+        const bool in = i > 0 && j > 0;
+        const VertexData d = vl == tid ? d0 : vertex_data(g, a, v, G.nx, in);
+        z[v] = T(Z[(bb + 1) * pw + aa + 1]);
+        const T tv = in ? T(d.g - stencil_at4(Z, pw, aa + 1, bb + 1, d.A, sx2, sy2)) : T(0);
+        t[v] = tv;
+        tb[vl] = tv;
+    }
+    __syncthreads();
+    // restriction cy[b][u] = sum_v W[v][u] t[v]: one wavefront per unknown, lanes over v
+    const int nu = C.nunk[blk];
+    const T* Wb = C.W + (long long)blk * nown * C.mu;
+    for (int u = wv; u < nu; u += NT / 64) {
+        T acc = T(0);
+        for (int vl = lane; vl < nown; vl += 64) acc += Wb[(long long)vl * C.mu + u] * tb[vl];
+        acc = wave_sum(acc);
+        if (lane == 0) cy[(long long)blk * C.mu + u] = acc;
+    }
+}
+
+// Coarse prolongation and the second residual, one workgroup per coarse block:
+// z1' = z1 + W c on the block (and, recomputed the same way, on its one-vertex halo),
+// t = g - K z1' (FP64, rounded once).  z1' goes to its own buffer: the halo reads z1
+// of the neighbouring blocks.  The coarse coefficients c[unk[b][u]] of the block and
+// its eight neighbours are gathered into LDS first.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_prolong_residual(CoarseW<T> C, const T* __restrict__ c, GatherGeom G,
+                                                         const T* __restrict__ zin, T* __restrict__ zout,
+                                                         const double* __restrict__ g, const double* __restrict__ a,
+                                                         double sx2, double sy2, T* __restrict__ t,
+                                                         const double* __restrict__ sc) {
+    if (finished(sc)) return;
+    extern __shared__ double smem[];
+    const int bx = G.bx, by = G.by, pw = bx + 2, nown = bx * by, mu = C.mu;
+    double* Z = smem;                                  // (by + 2) x (bx + 2)
+    T* cb = reinterpret_cast<T*>(Z + (by + 2) * pw);  // [9][mu]
+    const int tid = threadIdx.y * TX + threadIdx.x;
+    const int blk = blockIdx.x, I = blk % G.Nx, J = blk / G.Nx, i0 = I * bx, j0 = J * by;
+    for (int e = tid; e < 9 * mu; e += NT) {
+        const int nb = e / mu, u = e % mu, Ib = I + nb % 3 - 1, Jb = J + nb / 3 - 1;
+        T val = T(0);
+        if (Ib >= 0 && Ib < G.Nx && Jb >= 0 && Jb < G.Ny) {
+            const int b = Jb * G.Nx + Ib;
+            if (u < C.nunk[b]) val = c[C.unk[(long long)b * mu + u]];
+        }
+        cb[e] = val;
+    }
+    VertexData d0{};
+    if (tid < nown) {
+        const int i = i0 + tid % bx, j = j0 + tid / bx;
+        d0 = vertex_data(g, a, (long long)j * G.nx + i, G.nx, i > 0 && j > 0);
+    }
+    __syncthreads();
+    for (int e = tid; e < (bx + 2) * (by + 2); e += NT) {
+        const int xl = e % pw, yl = e / pw, ii = i0 - 1 + xl, jj = j0 - 1 + yl;
+        const bool own = xl >= 1 && xl <= bx && yl >= 1 && yl <= by;
+        double val = 0.0;
+        if (ii >= 1 && ii < G.nx && jj >= 1 && jj < G.ny) {
+            const long long v = (long long)jj * G.nx + ii;
+            // vertex (ii, jj) lies in block (ii / bx, jj / by): neighbour nb of this block
+            const int Ib = ii / bx, Jb = jj / by, b = Jb * G.Nx + Ib;
+            const int nb = (Jb - J + 1) * 3 + (Ib - I + 1);
+            const T* Wv = C.W + ((long long)b * nown + (jj % by) * bx + ii % bx) * mu;
+            const T* cv = cb + nb * mu;
+            const int nu = C.nunk[b];
+            T s = T(0);
+            for (int u = 0; u < nu; ++u) s += Wv[u] * cv[u];
+            const T zz = zin[v] + s;
+            val = double(zz);
+            if (own) zout[v] = zz;
+        } else if (own) {
+            zout[(long long)jj * G.nx + ii] = T(0);
+        }
+        Z[e] = val;
+    }
+    __syncthreads();
+    for (int vl = tid; vl < nown; vl += NT) {
+        const int aa = vl % bx, bb = vl / bx, i = i0 + aa, j = j0 + bb;
+        const long long v = (long long)j * G.nx + i;
+        const bool in = i > 0 && j > 0;
+        const VertexData d = vl == tid ? d0 : vertex_data(g, a, v, G.nx, in);
+        t[v] = in ? T(d.g - stencil_at4(Z, pw, aa + 1, bb + 1, d.A, sx2, sy2)) : T(0);
+    }
 }
 
 // Last smoothing of the two-grid cycle: z = zin + eta * sum_i ext(w_i) (zin may be
 // null), written as FP64.  With part: the workgroup's partial sums of g.z, gold.z
-// and |C z|^2 (the workgroups loop over the tiles).
+// and |C z|^2 (the workgroups loop over the tiles), and the pending flag set.
 template <typename T>
 __global__ void __launch_bounds__(NT) k_gather_final(const Rect* __restrict__ rects, const T* __restrict__ w,
                                                      const T* __restrict__ w4, GatherGeom G, T eta, const T* __restrict__ zin,
                                                      double* __restrict__ zout, double sx, double sy,
                                                      const double* __restrict__ g, const double* __restrict__ gold,
-                                                     const double* __restrict__ sc, double* __restrict__ part) {
+                                                     const double* __restrict__ sc, double* __restrict__ part,
+                                                     double* __restrict__ sc_pending) {
     if (finished(sc)) return;
     __shared__ double Z[TY + 1][TX + 1];  // the tile and one vertex beyond it in +x and +y
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
@@ -221,6 +416,13 @@ __global__ void __launch_bounds__(NT) k_gather_final(const Rect* __restrict__ re
     double v[3] = {0.0, 0.0, 0.0};
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * TY;
+        const int i = i0 + tx, j = j0 + ty;
+        const long long vv = (long long)j * G.nx + i;
+        double gv = 0.0, gov = 0.0;  // loaded with the tile
+        if (part && i < G.nx && j < G.ny) {
+            gv = g[vv];
+            if (gold) gov = gold[vv];
+        }
         __syncthreads();
         for (int e = tid; e < (TX + 1) * (TY + 1); e += NT) {
             const int ii = i0 + e % (TX + 1), jj = j0 + e / (TX + 1);
@@ -233,14 +435,12 @@ __global__ void __launch_bounds__(NT) k_gather_final(const Rect* __restrict__ re
             Z[e / (TX + 1)][e % (TX + 1)] = val;
         }
         __syncthreads();
-        const int i = i0 + tx, j = j0 + ty;
         if (i < G.nx && j < G.ny) {
-            const long long vv = (long long)j * G.nx + i;
             const double pc = Z[ty][tx];
             zout[vv] = pc;
             if (part) {
-                v[0] += g[vv] * pc;
-                if (gold) v[1] += gold[vv] * pc;
+                v[0] += gv * pc;
+                if (gold) v[1] += gov * pc;
                 // faces keyed by vertex (i, j): x-face (i, j) for i >= 1, y-face (i, j) for j >= 1
                 if (i > 0) {
                     const double d = (Z[ty + 1][tx] - pc) * sx;
@@ -259,61 +459,37 @@ __global__ void __launch_bounds__(NT) k_gather_final(const Rect* __restrict__ re
         part[blockIdx.x] = v[0];
         part[NRED + blockIdx.x] = v[1];
         part[2 * NRED + blockIdx.x] = v[2];
+        if (blockIdx.x == 0) sc_pending[0] = 1.0;
     }
 }
 
-// rho, beta, the relative residual, the iteration count and the done flag from the
-// partials of k_gather_final (first: rho_0 and |z_0|^2).  One workgroup.
+// The scalars from the partials of k_gather_final, one workgroup.  first: rho_0 and
+// |z_0|^2 of the initial preconditioning; otherwise finalise the pending partials
+// (if any) as k_dir_apply would, and clear the flag.
 __global__ void __launch_bounds__(NT) k_finalize(double* __restrict__ sc, double* __restrict__ hist,
                                                  const double* __restrict__ part, int nred, int first) {
     if (finished(sc)) return;
-    const double gz = sum_partials(part, 0, nred), zgold = sum_partials(part, 1, nred),
-                 zn2 = sum_partials(part, 2, nred);
-    if (threadIdx.x != 0 || threadIdx.y != 0) return;
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
     if (first) {
+        const double gz = sum_partials(part, 0, nred), zn2 = sum_partials(part, 2, nred);
+        if (tid != 0) return;
         sc[SC_RHO] = gz;
+        sc[SC_RHO_NEW] = gz;
         sc[SC_Z02] = zn2;
         sc[SC_ZN2] = zn2;
         sc[SC_REL2] = 1.0;
         sc[SC_IT] = 0.0;
         sc[SC_FLAG] = 0.0;
         sc[SC_BETA] = 0.0;
+        sc[SC_PENDING] = 0.0;
         sc[SC_DONE] = (zn2 > 0.0 && sc[SC_MAXIT] > 0.0) ? 0.0 : 1.0;
         return;
     }
-    const int it = (int)sc[SC_IT];
-    const double rho = sc[SC_RHO];
-    const double beta = (sc[SC_FLEX] != 0.0) ? (gz - zgold) / rho : gz / rho;
-    sc[SC_BETA] = beta;
-    sc[SC_RHO] = gz;
-    sc[SC_ZN2] = zn2;
-    const double rel2 = zn2 / sc[SC_Z02];
-    sc[SC_REL2] = rel2;
-    hist[2 * it + 1] = beta;
-    sc[SC_IT] = it + 1;
-    if (!(rel2 < INFINITY) || !(beta == beta)) sc[SC_FLAG] = 1.0;
-    if (sc[SC_FLAG] != 0.0 || rel2 <= sc[SC_RTOL2] || it + 1 >= (int)sc[SC_MAXIT]) sc[SC_DONE] = 1.0;
-}
-
-// t = g - K z
-template <typename T>
-__global__ void __launch_bounds__(NT) k_residual(const T* __restrict__ z, const double* __restrict__ g,
-                                                 T* __restrict__ t, const double* __restrict__ a, int nx, int ny,
-                                                 double sx2, double sy2, const double* __restrict__ sc) {
-    if (finished(sc)) return;
-    __shared__ double P[TY + 2][TX + 2];  // z as stored, widened; FP64 residual rounded once to T
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
-    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
-    for (int e = tid; e < (TX + 2) * (TY + 2); e += NT) {
-        const int ii = i0 - 1 + e % (TX + 2), jj = j0 - 1 + e / (TX + 2);
-        P[e / (TX + 2)][e % (TX + 2)] =
-            (ii >= 1 && ii < nx && jj >= 1 && jj < ny) ? double(z[(long long)jj * nx + ii]) : 0.0;
-    }
-    __syncthreads();
-    const int i = i0 + tx, j = j0 + ty;
-    if (i >= nx || j >= ny) return;
-    const long long v = (long long)j * nx + i;
-    t[v] = (i > 0 && j > 0) ? T(g[v] - stencil_tile<double>(P, tx, ty, a, v, nx, sx2, sy2)) : T(0);
+    if (sc[SC_PENDING] == 0.0) return;
+    double beta;
+    __syncthreads();  // every thread has read the flag before thread 0 clears it
+    finalise(sc, hist, part, nred, tid == 0, &beta);
+    if (tid == 0) sc[SC_PENDING] = 0.0;
 }
 
 inline dim3 tiles(tgms_ctx* c) { return dim3((c->nx + TX - 1) / TX, (c->ny + TY - 1) / TY); }
@@ -334,25 +510,81 @@ int nred_max() { return NRED; }
 void dir_apply(tgms_ctx* c, const double* z, const double* pin, double* pout, double* q) {
     ProfScope ps(c, PK_APPLYK);
     hipLaunchKernelGGL(k_dir_apply, dim3(c->nred), dim3(TX, TY), 0, c->stream, z, pin, pout, q, (const double*)c->a,
-                       c->nx, c->ny, c->sx * c->sx, c->sy * c->sy, (const double*)c->sc, c->part);
+                       c->nx, c->ny, c->sx * c->sx, c->sy * c->sy, c->sc, c->hist, (const double*)c->part, c->nred,
+                       c->part2);
     LAUNCH_OK();
 }
 
 void update(tgms_ctx* c, const double* p, const double* q, double* x, double* g, double* gold, float* g32) {
     const long long n = (long long)c->nx * c->ny;
-    hipLaunchKernelGGL(k_update, dim3(c->nred), dim3(TX, TY), 0, c->stream, n, c->sc, c->hist, (const double*)c->part,
+    hipLaunchKernelGGL(k_update, dim3(c->nred), dim3(TX, TY), 0, c->stream, n, c->sc, c->hist, (const double*)c->part2,
                        c->nred, p, q, x, g, gold, g32);
     LAUNCH_OK();
 }
 
-template <typename T>
-void gather_res(tgms_ctx* c, const T* w, const double* g, T* z, T* t, const double* sc) {
-    hipLaunchKernelGGL((k_gather_res<T>), tiles(c), dim3(TX, TY), 0, c->stream, c->patch, w, slots<T>(c), ggeom(c),
-                       T(c->eta), g, (const double*)c->a, c->sx * c->sx, c->sy * c->sy, z, t, sc);
+void finalize(tgms_ctx* c, bool first) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(TX, TY), 0, c->stream, c->sc, c->hist, (const double*)c->part,
+                       c->nred, first ? 1 : 0);
     LAUNCH_OK();
 }
-template void gather_res<double>(tgms_ctx*, const double*, const double*, double*, double*, const double*);
-template void gather_res<float>(tgms_ctx*, const float*, const double*, float*, float*, const double*);
+
+template <typename T>
+static CoarseW<T> coarse_w(tgms_ctx* c) {
+    CoarseW<T> C;
+    C.W = sizeof(T) == 8 ? (const T*)c->W : (const T*)c->W32;
+    C.mu = c->mu;
+    C.unk = c->blk_unk;
+    C.nunk = c->blk_nu;
+    return C;
+}
+
+template <typename T>
+static size_t gather_res_lds(tgms_ctx* c) {
+    return sizeof(double) * (c->bx + 2) * (c->by + 2) + sizeof(T) * (size_t)c->bx * c->by;
+}
+template <typename T>
+static size_t prolong_res_lds(tgms_ctx* c) {
+    return sizeof(double) * (c->bx + 2) * (c->by + 2) + sizeof(T) * 9 * (size_t)c->mu;
+}
+
+void allow_fused_lds(tgms_ctx* c) {
+    const size_t need = std::max(gather_res_lds<double>(c), prolong_res_lds<double>(c));
+    if (need <= 65536) return;
+    if ((long long)need > c->lds_max) throw TgmsError{TGMS_E_UNSUPPORTED, "coarse blocks too large for the LDS tiles"};
+    auto set = [&](const void* f) {
+        HIP_OK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need));
+    };
+    set((const void*)k_gather_res_restrict<double>);
+    set((const void*)k_gather_res_restrict<float>);
+    set((const void*)k_prolong_residual<double>);
+    set((const void*)k_prolong_residual<float>);
+}
+
+template <typename T>
+void gather_res_restrict(tgms_ctx* c, const T* w, const double* g, T* z, T* t, T* cy, const double* sc) {
+    ProfScope ps(c, PK_RESTRICT);
+    hipLaunchKernelGGL((k_gather_res_restrict<T>), dim3(c->nblk), dim3(TX, TY), gather_res_lds<T>(c), c->stream,
+                       c->patch, w, slots<T>(c), ggeom(c), T(c->eta), g, (const double*)c->a, c->sx * c->sx,
+                       c->sy * c->sy, z, t, coarse_w<T>(c), cy, sc);
+    LAUNCH_OK();
+}
+template void gather_res_restrict<double>(tgms_ctx*, const double*, const double*, double*, double*, double*,
+                                          const double*);
+template void gather_res_restrict<float>(tgms_ctx*, const float*, const double*, float*, float*, float*,
+                                         const double*);
+
+template <typename T>
+void prolong_residual(tgms_ctx* c, const T* cres, const T* zin, T* zout, const double* g, T* t, const double* sc) {
+    ProfScope ps(c, PK_PROLONG);
+    hipLaunchKernelGGL((k_prolong_residual<T>), dim3(c->nblk), dim3(TX, TY), prolong_res_lds<T>(c), c->stream,
+                       coarse_w<T>(c), cres, ggeom(c), zin,
+                       zout, g, (const double*)c->a, c->sx * c->sx, c->sy * c->sy, t, sc);
+    LAUNCH_OK();
+}
+template void prolong_residual<double>(tgms_ctx*, const double*, const double*, double*, const double*, double*,
+                                       const double*);
+template void prolong_residual<float>(tgms_ctx*, const float*, const float*, float*, const double*, float*,
+                                      const double*);
 
 template <typename T>
 void gather_final(tgms_ctx* c, const T* w, const T* zin, double* zout, const double* g, const double* gold,
@@ -360,30 +592,17 @@ void gather_final(tgms_ctx* c, const T* w, const T* zin, double* zout, const dou
     const double* sc = with_dots ? c->sc : nullptr;
     if (with_dots)
         hipLaunchKernelGGL((k_gather_final<T>), dim3(c->nred), dim3(TX, TY), 0, c->stream, c->patch, w, slots<T>(c),
-                           ggeom(c), T(c->eta), zin, zout, c->sx, c->sy, g, gold, sc, c->part);
+                           ggeom(c), T(c->eta), zin, zout, c->sx, c->sy, g, gold, sc, c->part, c->sc + SC_PENDING);
     else
         hipLaunchKernelGGL((k_gather_final<T>), dim3(tiles(c).x * tiles(c).y), dim3(TX, TY), 0, c->stream, c->patch,
-                           w, slots<T>(c), ggeom(c), T(c->eta), zin, zout, c->sx, c->sy, g, gold, sc, (double*)nullptr);
+                           w, slots<T>(c), ggeom(c), T(c->eta), zin, zout, c->sx, c->sy, g, gold, sc, (double*)nullptr,
+                           (double*)nullptr);
     LAUNCH_OK();
-    if (with_dots) {
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(TX, TY), 0, c->stream, c->sc, c->hist, (const double*)c->part,
-                           c->nred, first ? 1 : 0);
-        LAUNCH_OK();
-    }
+    if (with_dots && first) finalize(c, true);
 }
 template void gather_final<double>(tgms_ctx*, const double*, const double*, double*, const double*, const double*,
                                    bool, bool);
 template void gather_final<float>(tgms_ctx*, const float*, const float*, double*, const double*, const double*, bool,
                                   bool);
-
-template <typename T>
-void residual(tgms_ctx* c, const T* z, const double* g, T* t, const double* sc) {
-    ProfScope ps(c, PK_APPLYK);
-    hipLaunchKernelGGL((k_residual<T>), tiles(c), dim3(TX, TY), 0, c->stream, z, g, t, (const double*)c->a, c->nx,
-                       c->ny, c->sx * c->sx, c->sy * c->sy, sc);
-    LAUNCH_OK();
-}
-template void residual<double>(tgms_ctx*, const double*, const double*, double*, const double*);
-template void residual<float>(tgms_ctx*, const float*, const double*, float*, const double*);
 
 }  // namespace tgms

@@ -223,6 +223,17 @@ __global__ void k_press_scale(double* __restrict__ P, const double* __restrict__
 
 inline unsigned nb(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
+// Orthonormal DCT-II matrix Q[i][k] = s_k cos(pi k (i + 1/2) / n) (s_0 = sqrt(1/n),
+// s_k = sqrt(2/n)) and the eigenvalues 2 - 2 cos(pi k / n) of the 1-D Neumann
+// Laplacian it diagonalises.
+__global__ void k_dct_matrix(int n, double* __restrict__ Q, double* __restrict__ lam) {
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= (long long)n * n) return;
+    const int i = (int)(e / n), k = (int)(e % n);
+    Q[e] = (k == 0 ? sqrt(1.0 / n) : sqrt(2.0 / n)) * cos(M_PI * k * (i + 0.5) / n);
+    if (i == 0) lam[k] = 2.0 - 2.0 * cos(M_PI * k / n);
+}
+
 }  // namespace
 
 namespace tgms {
@@ -336,6 +347,12 @@ void bnd_faces(tgms_ctx* c, const double* g, double* gb) {
 }
 
 // p = argmin |B_I^T p - (A u)_I| with zero mean, via the DCT-II diagonalisation of B B^T.
+void dct_matrix(tgms_ctx* c, int n, double* Q, double* lam) {
+    const long long tot = (long long)n * n;
+    hipLaunchKernelGGL(k_dct_matrix, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, n, Q, lam);
+    LAUNCH_OK();
+}
+
 void pressure(tgms_ctx* c, const double* u, double* p) {
     const long long ncell = (long long)c->nx * c->ny;
     faces_A(c, u, c->fu);

@@ -1047,37 +1047,55 @@ void coarse_rt0_blocks(tgms_ctx* c) {
 }
 
 template <typename T>
-void coarse_apply(tgms_ctx* c, const T* g, T* z, bool accumulate, const double* sc) {
+struct CoarseBufs {
     const T* W;
     const T* Ainv;
     T* cy;
     T* c1;
-    if constexpr (sizeof(T) == 8) {
-        W = (const T*)c->W;
-        Ainv = (const T*)c->Ac;
-        cy = (T*)c->cy;
-        c1 = (T*)c->cvec;
-    } else {
-        W = (const T*)c->W32;
-        Ainv = (const T*)c->Ac32;
-        cy = (T*)c->cy32;
-        c1 = (T*)c->cvec32;
-    }
+};
+template <typename T>
+static CoarseBufs<T> coarse_bufs(tgms_ctx* c) {
+    if constexpr (sizeof(T) == 8)
+        return CoarseBufs<T>{(const T*)c->W, (const T*)c->Ac, (T*)c->cy, (T*)c->cvec};
+    else
+        return CoarseBufs<T>{(const T*)c->W32, (const T*)c->Ac32, (T*)c->cy32, (T*)c->cvec32};
+}
+
+template <typename T>
+T* coarse_cy(tgms_ctx* c) {
+    return coarse_bufs<T>(c).cy;
+}
+template double* coarse_cy<double>(tgms_ctx*);
+template float* coarse_cy<float>(tgms_ctx*);
+
+// the coarse unknowns from the block restrictions cy, then A^{-1} of them (two
+// triangular products); returns the result (after c1 in the same buffer)
+template <typename T>
+const T* coarse_solve(tgms_ctx* c, const double* sc) {
+    const CoarseBufs<T> B = coarse_bufs<T>(c);
+    hipLaunchKernelGGL((k_coarse_accum<T>), dim3((c->ncs + 255) / 256), dim3(256), 0, c->stream, c->unk_ptr, c->unk_ent,
+                       (const T*)B.cy, c->ncs, B.c1, sc);
+    LAUNCH_OK();
+    T* res = B.c1 + c->ncs;
+    symv<T>(c, B.Ainv, c->ncs, B.c1, res, sc);
+    return res;
+}
+template const double* coarse_solve<double>(tgms_ctx*, const double*);
+template const float* coarse_solve<float>(tgms_ctx*, const double*);
+
+template <typename T>
+void coarse_apply(tgms_ctx* c, const T* g, T* z, bool accumulate, const double* sc) {
+    const CoarseBufs<T> B = coarse_bufs<T>(c);
     {
         ProfScope ps(c, PK_RESTRICT);
-        hipLaunchKernelGGL((k_coarse_restrict<T>), dim3(c->nblk), dim3(256), 0, c->stream, W, c->mu, c->blk_nu, g,
-                           c->nx, c->bx, c->by, c->Nx, cy, sc);
+        hipLaunchKernelGGL((k_coarse_restrict<T>), dim3(c->nblk), dim3(256), 0, c->stream, B.W, c->mu, c->blk_nu, g,
+                           c->nx, c->bx, c->by, c->Nx, B.cy, sc);
         LAUNCH_OK();
     }
-    hipLaunchKernelGGL((k_coarse_accum<T>), dim3((c->ncs + 255) / 256), dim3(256), 0, c->stream, c->unk_ptr, c->unk_ent,
-                       (const T*)cy, c->ncs, c1, sc);
-    LAUNCH_OK();
-    // the coarse solve A^{-1} c1 (two triangular products); result after c1 in the same buffer
-    T* res = c1 + c->ncs;
-    symv<T>(c, Ainv, c->ncs, c1, res, sc);
+    const T* res = coarse_solve<T>(c, sc);
     ProfScope ps(c, PK_PROLONG);
-    hipLaunchKernelGGL((k_coarse_prolong<T>), dim3(c->nblk), dim3(256), 0, c->stream, W, c->mu, c->blk_unk,
-                       c->blk_nu, (const T*)res, c->nx, c->bx, c->by, c->Nx, z, accumulate ? 1 : 0, sc);
+    hipLaunchKernelGGL((k_coarse_prolong<T>), dim3(c->nblk), dim3(256), 0, c->stream, B.W, c->mu, c->blk_unk,
+                       c->blk_nu, res, c->nx, c->bx, c->by, c->Nx, z, accumulate ? 1 : 0, sc);
     LAUNCH_OK();
 }
 template void coarse_apply<double>(tgms_ctx*, const double*, double*, bool, const double*);
