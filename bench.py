@@ -233,7 +233,8 @@ def main():
                      "traffic": traffic, "bytes_per_launch": nbytes, "avg_launch_us": avg_ms * 1000.0,
                      "timing": (f"{SMOOTH_REPS} back-to-back launches on the library stream between one HIP "
                                 "event pair, right after the timed steps, same setup and data")},
-        "tuning": {"nred": info["nred"], "smooth_staged": info["smooth_staged"], "tuned": info["tuned"]},
+        "tuning": {"nred": info["nred"], "rows_per_thread": info["rows_per_thread"],
+                   "smooth_staged": info["smooth_staged"], "tuned": info["tuned"]},
     }
     if not args.no_compare and precision == "fp64":
         # the same workload with the FP32 preconditioner inside the flexible FP64 PCG

@@ -103,6 +103,7 @@ typedef struct {
     int warm_accepted;    /* warm start: faces whose modes were certified without the dense solve */
     int warm_iters;       /* warm start: subspace iterations summed over the accepted faces */
     double t_cnn_ms;      /* warm start 2: network inputs and forward pass (inside t_eig_ms) */
+    int rows_per_thread;  /* vertex rows per thread in the tiled PCG kernels (1 or 4) */
 } tgms_info_t;
 
 /* Paper defaults: eta 0.2, overlap 2, FP64, s_scale = |K|^(1/2), default stream,

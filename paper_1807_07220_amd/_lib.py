@@ -40,7 +40,7 @@ class Info(ctypes.Structure):
                 ("t_setup_ms", c_double), ("t_snap_ms", c_double), ("t_eig_ms", c_double),
                 ("t_coarse_ms", c_double), ("t_smoother_ms", c_double), ("lds_max", c_int), ("pcg_graph", c_int),
                 ("tuned", c_int), ("nred", c_int), ("smooth_staged", c_int), ("warm_accepted", c_int),
-                ("warm_iters", c_int), ("t_cnn_ms", c_double)]
+                ("warm_iters", c_int), ("t_cnn_ms", c_double), ("rows_per_thread", c_int)]
 
 
 _lib = None

@@ -755,6 +755,7 @@ tgms_status tgms_info(const tgms_ctx* c, tgms_info_t* info) {
     info->warm_accepted = c->warm_accepted;
     info->warm_iters = c->warm_iters;
     info->t_cnn_ms = c->t_cnn_ms;
+    info->rows_per_thread = c->rpt;
     return TGMS_OK;
 }
 

@@ -172,6 +172,7 @@ struct tgms_ctx {
     double* part2 = nullptr;  // per-workgroup partial sums of p.q (NRED)
     double* vt3 = nullptr;    // z1 after the coarse correction (FP64 preconditioner)
     int nred = 256;           // workgroups of the reducing PCG kernels (autotuned)
+    int rpt = 1;              // vertex rows per thread in the tiled PCG kernels (1 or 4; autotuned)
     int smooth_staged = -1;   // smoother: 1 factor staged in LDS, 0 read from global, -1 by LDS fit
     int snap_cols = 1;        // snapshots: 1 one lane per column where supported, 0 one wave per block
     int tuned = 0;            // 0 defaults, 1 timed at setup, 2 taken from the tuning cache
@@ -306,6 +307,8 @@ const T* coarse_solve(tgms_ctx* c, const double* sc);  // accumulate the restric
 void dense_spd_inverse(tgms_ctx* c, double* A, int n);
 template <typename T>
 void symv(tgms_ctx* c, const T* A, int n, const T* x, T* y, const double* sc);
+template <typename T>
+bool symv_acc(tgms_ctx* c, const T* B, int n, const int* ptr, const int* ent, const T* cy, T* y, const double* sc);
 void gemm(tgms_ctx* c, int transA, int transB, int M, int N, int K, double alpha, const double* A, int lda,
           const double* B, int ldb, double beta, double* C, int ldc);
 // preprocessing and pressure (k_pre.hip)

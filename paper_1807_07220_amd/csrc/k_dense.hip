@@ -173,6 +173,46 @@ __global__ void k_copy_block(const double* __restrict__ src, int lds, double* __
     dst[(long long)i * ldd + j] = src[(long long)i * lds + j];
 }
 
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+    using type = double2;
+    __device__ static double dot(const double2& b, const double* x) { return b.x * x[0] + b.y * x[1]; }
+};
+template <>
+struct Vec16<float> {
+    using type = float4;
+    __device__ static float dot(const float4& b, const float* x) { return b.x * x[0] + b.y * x[1] + b.z * x[2] + b.w * x[3]; }
+};
+
+// sum over j in [j0, j1) of row[j] x[j] by one wavefront (row = B + base): the
+// 16-byte-aligned body with vector loads, four in flight per lane, the unaligned
+// head and tail one element per lane; the total in every lane.
+template <typename T>
+__device__ inline T row_dot(const T* __restrict__ B, long long base, int j0, int j1, const T* __restrict__ x, int lane) {
+    constexpr int PER = 16 / sizeof(T);
+    using V = typename Vec16<T>::type;
+    int ja = j0 + (int)((PER - (base + j0) % PER) % PER);
+    if (ja > j1) ja = j1;
+    const int jb = ja + ((j1 - ja) / PER) * PER;
+    T s = T(0);
+    for (int j = j0 + lane; j < ja; j += 64) s += B[base + j] * x[j];
+    for (int j = jb + lane; j < j1; j += 64) s += B[base + j] * x[j];
+    const V* bv = reinterpret_cast<const V*>(B + base + ja);
+    const int nv = (jb - ja) / PER;
+    for (int q = lane; q < nv; q += 256) {
+        V b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (q + 64 * u < nv) b[u] = bv[q + 64 * u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (q + 64 * u < nv) s += Vec16<T>::dot(b[u], x + ja + (q + 64 * u) * PER);
+    }
+    return wave_sum(s);
+}
+
 // y = tril(B) x (part 0) or y = triu(B) x (part 1): one wavefront per row.
 template <typename T>
 __global__ void k_trimv(const T* __restrict__ B, int n, const T* __restrict__ x, T* __restrict__ y, int part,
@@ -181,11 +221,29 @@ __global__ void k_trimv(const T* __restrict__ B, int n, const T* __restrict__ x,
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= n) return;
-    const T* br = B + (long long)row * n;
-    const int j0 = part ? row : 0, j1 = part ? n : row + 1;
-    T s = T(0);
-    for (int j = j0 + lane; j < j1; j += 64) s += br[j] * x[j];
-    s = wave_sum(s);
+    const T s = row_dot<T>(B, (long long)row * n, part ? row : 0, part ? n : row + 1, x, lane);
+    if (lane == 0) y[row] = s;
+}
+
+// Small coarse systems: y = tril(B) c with c accumulated from the block restrictions
+// first (every workgroup forms all of c in LDS, in the fixed order of the
+// accumulation kernel): one launch instead of two.
+constexpr int ACC_MAX = 1024;
+template <typename T>
+__global__ void k_trimv_acc(const T* __restrict__ B, int n, const int* __restrict__ ptr, const int* __restrict__ ent,
+                            const T* __restrict__ cy, T* __restrict__ y, const double* __restrict__ sc) {
+    if (sc != nullptr && sc[SC_DONE] != 0.0) return;
+    __shared__ T cs[ACC_MAX];
+    for (int u = threadIdx.x; u < n; u += blockDim.x) {
+        T v = T(0);
+        for (int k = ptr[u]; k < ptr[u + 1]; ++k) v += cy[ent[k]];
+        cs[u] = v;
+    }
+    __syncthreads();
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    const T s = row_dot<T>(B, (long long)row * n, 0, row + 1, cs, lane);
     if (lane == 0) y[row] = s;
 }
 
@@ -295,5 +353,26 @@ void symv(tgms_ctx* c, const T* B, int n, const T* x, T* y, const double* sc) {
 }
 template void symv<double>(tgms_ctx*, const double*, int, const double*, double*, const double*);
 template void symv<float>(tgms_ctx*, const float*, int, const float*, float*, const double*);
+
+// y = A^{-1} c with c the accumulation (CSR ptr/ent) of the block restrictions cy;
+// false when n is too large for the fused first product (then nothing is launched)
+template <typename T>
+bool symv_acc(tgms_ctx* c, const T* B, int n, const int* ptr, const int* ent, const T* cy, T* y, const double* sc) {
+    if (n <= 0 || n > ACC_MAX) return false;
+    T* tmp;
+    if constexpr (sizeof(T) == 8)
+        tmp = (T*)c->cvec2;
+    else
+        tmp = (T*)c->cvec2_32;
+    hipLaunchKernelGGL((k_trimv_acc<T>), dim3((n + 3) / 4), dim3(256), 0, c->stream, B, n, ptr, ent, cy, tmp, sc);
+    LAUNCH_OK();
+    hipLaunchKernelGGL((k_trimv<T>), dim3((n + 3) / 4), dim3(256), 0, c->stream, B, n, (const T*)tmp, y, 1, sc);
+    LAUNCH_OK();
+    return true;
+}
+template bool symv_acc<double>(tgms_ctx*, const double*, int, const int*, const int*, const double*, double*,
+                               const double*);
+template bool symv_acc<float>(tgms_ctx*, const float*, int, const int*, const int*, const float*, float*,
+                              const double*);
 
 }  // namespace tgms

@@ -63,15 +63,17 @@ __device__ inline double sum_partials(const double* __restrict__ part, int k, in
     return v[0];
 }
 
-// 9-point stencil K at tile position (ty+1, tx+1) of an LDS tile with a one-vertex halo,
-// with the four cell weights around the vertex (SW, SE, NW, NE) already loaded
-__device__ inline double stencil_tile4(const double (&P)[TY + 2][TX + 2], int tx, int ty, const double (&A)[4],
+// 9-point stencil K at tile position (y, tx+1) of an LDS tile of H rows with a
+// one-vertex halo, with the four cell weights around the vertex (SW, SE, NW, NE)
+// already loaded
+template <int H>
+__device__ inline double stencil_tile4(const double (&P)[H + 2][TX + 2], int tx, int y, const double (&A)[4],
                                        double sx2, double sy2) {
     const double A00 = A[0], A10 = A[1], A01 = A[2], A11 = A[3];
     const double s = sx2 + sy2;
     const double c6 = 1.0 / 6.0, c3 = 1.0 / 3.0;
     const double kx = sx2 * c6 - sy2 * c3, ky = sy2 * c6 - sx2 * c3;
-    const int x = tx + 1, y = ty + 1;
+    const int x = tx + 1;
     double r = s * c3 * (A00 + A10 + A01 + A11) * P[y][x];
     r += kx * ((A10 + A11) * P[y][x + 1] + (A00 + A01) * P[y][x - 1]);
     r += ky * ((A01 + A11) * P[y + 1][x] + (A00 + A10) * P[y - 1][x]);
@@ -111,7 +113,8 @@ __device__ inline bool finalise(double* __restrict__ sc, double* __restrict__ hi
 
 // p_out = z + beta p_in, q = K p_out, and the workgroup's partial sum of p_out . q
 // (part).  beta comes from finalising the pending partials gpart, else from sc.  The
-// workgroups loop over the tiles.
+// workgroups loop over tiles of 64 x 4 RPT vertices, RPT rows per thread.
+template <int RPT>
 __global__ void __launch_bounds__(NT) k_dir_apply(const double* __restrict__ z, const double* __restrict__ pin,
                                                   double* __restrict__ pout, double* __restrict__ q,
                                                   const double* __restrict__ a, int nx, int ny, double sx2,
@@ -119,9 +122,10 @@ __global__ void __launch_bounds__(NT) k_dir_apply(const double* __restrict__ z, 
                                                   const double* __restrict__ gpart, int nred,
                                                   double* __restrict__ part) {
     if (finished(sc)) return;
-    __shared__ double P[TY + 2][TX + 2];
+    constexpr int H = TY * RPT;
+    __shared__ double P[H + 2][TX + 2];
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
-    const int ntx = (nx + TX - 1) / TX, ntiles = ntx * ((ny + TY - 1) / TY);
+    const int ntx = (nx + TX - 1) / TX, ntiles = ntx * ((ny + H - 1) / H);
     double beta = sc[SC_BETA];
     if (sc[SC_PENDING] != 0.0) {
         const bool rec = blockIdx.x == 0 && tid == 0;
@@ -129,19 +133,21 @@ __global__ void __launch_bounds__(NT) k_dir_apply(const double* __restrict__ z, 
     }
     double v[1] = {0.0};
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * TY;
-        const int i = i0 + tx, j = j0 + ty;
-        const long long vv = (long long)j * nx + i;
-        const bool in = i > 0 && j > 0 && i < nx && j < ny;
-        double A[4] = {0.0, 0.0, 0.0, 0.0};  // weights load with the tile
-        if (in) {
-            A[0] = a[vv - nx - 1];
-            A[1] = a[vv - nx];
-            A[2] = a[vv - 1];
-            A[3] = a[vv];
+        const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * H;
+        const int i = i0 + tx;
+        double A[RPT][4];  // weights load with the tile
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int j = j0 + ty + TY * r;
+            const long long vv = (long long)j * nx + i;
+            const bool in = i > 0 && j > 0 && i < nx && j < ny;
+            A[r][0] = in ? a[vv - nx - 1] : 0.0;
+            A[r][1] = in ? a[vv - nx] : 0.0;
+            A[r][2] = in ? a[vv - 1] : 0.0;
+            A[r][3] = in ? a[vv] : 0.0;
         }
         __syncthreads();
-        for (int e = tid; e < (TX + 2) * (TY + 2); e += NT) {
+        for (int e = tid; e < (TX + 2) * (H + 2); e += NT) {
             const int ii = i0 - 1 + e % (TX + 2), jj = j0 - 1 + e / (TX + 2);
             double val = 0.0;
             if (ii >= 1 && ii < nx && jj >= 1 && jj < ny) {
@@ -151,12 +157,17 @@ __global__ void __launch_bounds__(NT) k_dir_apply(const double* __restrict__ z, 
             P[e / (TX + 2)][e % (TX + 2)] = val;
         }
         __syncthreads();
-        if (i < nx && j < ny) {
-            const double pc = P[ty + 1][tx + 1];
-            pout[vv] = pc;
-            const double r = in ? stencil_tile4(P, tx, ty, A, sx2, sy2) : 0.0;
-            q[vv] = r;
-            v[0] += pc * r;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int y = ty + TY * r, j = j0 + y;
+            if (i < nx && j < ny) {
+                const long long vv = (long long)j * nx + i;
+                const double pc = P[y + 1][tx + 1];
+                pout[vv] = pc;
+                const double qv = (i > 0 && j > 0) ? stencil_tile4<H>(P, tx, y + 1, A[r], sx2, sy2) : 0.0;
+                q[vv] = qv;
+                v[0] += pc * qv;
+            }
         }
     }
     group_sum<1>(v);
@@ -190,13 +201,31 @@ __global__ void __launch_bounds__(NT) k_update(long long n, double* __restrict__
         }
     }
     if (bad) return;
-    for (long long t = blockIdx.x * (long long)NT + tid; t < n; t += (long long)gridDim.x * NT) {
-        x[t] += al * p[t];
-        const double gv = g[t];
-        if (gold) gold[t] = gv;
-        const double gn = gv - al * q[t];
-        g[t] = gn;
-        if (g32) g32[t] = (float)gn;
+    // four independent vertices per thread and pass (their loads in flight together)
+    const long long stride = (long long)gridDim.x * NT;
+    for (long long t0 = blockIdx.x * (long long)NT + tid; t0 < n; t0 += 4 * stride) {
+        double xv[4], pv[4], gv[4], qv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const long long t = t0 + u * stride;
+            if (t < n) {
+                xv[u] = x[t];
+                pv[u] = p[t];
+                gv[u] = g[t];
+                qv[u] = q[t];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const long long t = t0 + u * stride;
+            if (t < n) {
+                x[t] = xv[u] + al * pv[u];
+                if (gold) gold[t] = gv[u];
+                const double gn = gv[u] - al * qv[u];
+                g[t] = gn;
+                if (g32) g32[t] = (float)gn;
+            }
+        }
     }
 }
 
@@ -401,8 +430,9 @@ __global__ void __launch_bounds__(NT) k_prolong_residual(CoarseW<T> C, const T* 
 
 // Last smoothing of the two-grid cycle: z = zin + eta * sum_i ext(w_i) (zin may be
 // null), written as FP64.  With part: the workgroup's partial sums of g.z, gold.z
-// and |C z|^2 (the workgroups loop over the tiles), and the pending flag set.
-template <typename T>
+// and |C z|^2 (the workgroups loop over tiles of 64 x 4 RPT vertices), and the
+// pending flag set.
+template <typename T, int RPT>
 __global__ void __launch_bounds__(NT) k_gather_final(const Rect* __restrict__ rects, const T* __restrict__ w,
                                                      const T* __restrict__ w4, GatherGeom G, T eta, const T* __restrict__ zin,
                                                      double* __restrict__ zout, double sx, double sy,
@@ -410,21 +440,25 @@ __global__ void __launch_bounds__(NT) k_gather_final(const Rect* __restrict__ re
                                                      const double* __restrict__ sc, double* __restrict__ part,
                                                      double* __restrict__ sc_pending) {
     if (finished(sc)) return;
-    __shared__ double Z[TY + 1][TX + 1];  // the tile and one vertex beyond it in +x and +y
+    constexpr int H = TY * RPT;
+    __shared__ double Z[H + 1][TX + 1];  // the tile and one vertex beyond it in +x and +y
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
-    const int ntx = (G.nx + TX - 1) / TX, ntiles = ntx * ((G.ny + TY - 1) / TY);
+    const int ntx = (G.nx + TX - 1) / TX, ntiles = ntx * ((G.ny + H - 1) / H);
     double v[3] = {0.0, 0.0, 0.0};
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * TY;
-        const int i = i0 + tx, j = j0 + ty;
-        const long long vv = (long long)j * G.nx + i;
-        double gv = 0.0, gov = 0.0;  // loaded with the tile
-        if (part && i < G.nx && j < G.ny) {
-            gv = g[vv];
-            if (gold) gov = gold[vv];
+        const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * H;
+        const int i = i0 + tx;
+        double gv[RPT], gov[RPT];  // loaded with the tile
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int j = j0 + ty + TY * r;
+            const long long vv = (long long)j * G.nx + i;
+            const bool in = part && i < G.nx && j < G.ny;
+            gv[r] = in ? g[vv] : 0.0;
+            gov[r] = (in && gold) ? gold[vv] : 0.0;
         }
         __syncthreads();
-        for (int e = tid; e < (TX + 1) * (TY + 1); e += NT) {
+        for (int e = tid; e < (TX + 1) * (H + 1); e += NT) {
             const int ii = i0 + e % (TX + 1), jj = j0 + e / (TX + 1);
             double val = 0.0;
             if (ii >= 1 && ii < G.nx && jj >= 1 && jj < G.ny) {
@@ -435,20 +469,25 @@ __global__ void __launch_bounds__(NT) k_gather_final(const Rect* __restrict__ re
             Z[e / (TX + 1)][e % (TX + 1)] = val;
         }
         __syncthreads();
-        if (i < G.nx && j < G.ny) {
-            const double pc = Z[ty][tx];
-            zout[vv] = pc;
-            if (part) {
-                v[0] += gv * pc;
-                if (gold) v[1] += gov * pc;
-                // faces keyed by vertex (i, j): x-face (i, j) for i >= 1, y-face (i, j) for j >= 1
-                if (i > 0) {
-                    const double d = (Z[ty + 1][tx] - pc) * sx;
-                    v[2] += d * d;
-                }
-                if (j > 0) {
-                    const double d = (Z[ty][tx + 1] - pc) * sy;
-                    v[2] += d * d;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int y = ty + TY * r, j = j0 + y;
+            if (i < G.nx && j < G.ny) {
+                const long long vv = (long long)j * G.nx + i;
+                const double pc = Z[y][tx];
+                zout[vv] = pc;
+                if (part) {
+                    v[0] += gv[r] * pc;
+                    if (gold) v[1] += gov[r] * pc;
+                    // faces keyed by vertex (i, j): x-face (i, j) for i >= 1, y-face (i, j) for j >= 1
+                    if (i > 0) {
+                        const double d = (Z[y + 1][tx] - pc) * sx;
+                        v[2] += d * d;
+                    }
+                    if (j > 0) {
+                        const double d = (Z[y][tx + 1] - pc) * sy;
+                        v[2] += d * d;
+                    }
                 }
             }
         }
@@ -509,9 +548,14 @@ int nred_max() { return NRED; }
 
 void dir_apply(tgms_ctx* c, const double* z, const double* pin, double* pout, double* q) {
     ProfScope ps(c, PK_APPLYK);
-    hipLaunchKernelGGL(k_dir_apply, dim3(c->nred), dim3(TX, TY), 0, c->stream, z, pin, pout, q, (const double*)c->a,
-                       c->nx, c->ny, c->sx * c->sx, c->sy * c->sy, c->sc, c->hist, (const double*)c->part, c->nred,
-                       c->part2);
+    if (c->rpt == 4)
+        hipLaunchKernelGGL(k_dir_apply<4>, dim3(c->nred), dim3(TX, TY), 0, c->stream, z, pin, pout, q,
+                           (const double*)c->a, c->nx, c->ny, c->sx * c->sx, c->sy * c->sy, c->sc, c->hist,
+                           (const double*)c->part, c->nred, c->part2);
+    else
+        hipLaunchKernelGGL(k_dir_apply<1>, dim3(c->nred), dim3(TX, TY), 0, c->stream, z, pin, pout, q,
+                           (const double*)c->a, c->nx, c->ny, c->sx * c->sx, c->sy * c->sy, c->sc, c->hist,
+                           (const double*)c->part, c->nred, c->part2);
     LAUNCH_OK();
 }
 
@@ -590,13 +634,18 @@ template <typename T>
 void gather_final(tgms_ctx* c, const T* w, const T* zin, double* zout, const double* g, const double* gold,
                   bool with_dots, bool first) {
     const double* sc = with_dots ? c->sc : nullptr;
-    if (with_dots)
-        hipLaunchKernelGGL((k_gather_final<T>), dim3(c->nred), dim3(TX, TY), 0, c->stream, c->patch, w, slots<T>(c),
-                           ggeom(c), T(c->eta), zin, zout, c->sx, c->sy, g, gold, sc, c->part, c->sc + SC_PENDING);
+    if (with_dots && c->rpt == 4)
+        hipLaunchKernelGGL((k_gather_final<T, 4>), dim3(c->nred), dim3(TX, TY), 0, c->stream, c->patch, w,
+                           slots<T>(c), ggeom(c), T(c->eta), zin, zout, c->sx, c->sy, g, gold, sc, c->part,
+                           c->sc + SC_PENDING);
+    else if (with_dots)
+        hipLaunchKernelGGL((k_gather_final<T, 1>), dim3(c->nred), dim3(TX, TY), 0, c->stream, c->patch, w,
+                           slots<T>(c), ggeom(c), T(c->eta), zin, zout, c->sx, c->sy, g, gold, sc, c->part,
+                           c->sc + SC_PENDING);
     else
-        hipLaunchKernelGGL((k_gather_final<T>), dim3(tiles(c).x * tiles(c).y), dim3(TX, TY), 0, c->stream, c->patch,
-                           w, slots<T>(c), ggeom(c), T(c->eta), zin, zout, c->sx, c->sy, g, gold, sc, (double*)nullptr,
-                           (double*)nullptr);
+        hipLaunchKernelGGL((k_gather_final<T, 1>), dim3(tiles(c).x * tiles(c).y), dim3(TX, TY), 0, c->stream,
+                           c->patch, w, slots<T>(c), ggeom(c), T(c->eta), zin, zout, c->sx, c->sy, g, gold, sc,
+                           (double*)nullptr, (double*)nullptr);
     LAUNCH_OK();
     if (with_dots && first) finalize(c, true);
 }

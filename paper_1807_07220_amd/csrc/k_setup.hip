@@ -1073,10 +1073,11 @@ template float* coarse_cy<float>(tgms_ctx*);
 template <typename T>
 const T* coarse_solve(tgms_ctx* c, const double* sc) {
     const CoarseBufs<T> B = coarse_bufs<T>(c);
+    T* res = B.c1 + c->ncs;
+    if (symv_acc<T>(c, B.Ainv, c->ncs, c->unk_ptr, c->unk_ent, (const T*)B.cy, res, sc)) return res;
     hipLaunchKernelGGL((k_coarse_accum<T>), dim3((c->ncs + 255) / 256), dim3(256), 0, c->stream, c->unk_ptr, c->unk_ent,
                        (const T*)B.cy, c->ncs, B.c1, sc);
     LAUNCH_OK();
-    T* res = B.c1 + c->ncs;
     symv<T>(c, B.Ainv, c->ncs, B.c1, res, sc);
     return res;
 }

@@ -2,12 +2,14 @@
 // the kernels whose best shape is not known in advance, by timing every
 // candidate on the context's own data once (HIP events) and keeping the
 // fastest.  Results are kept per process and, when a path is given, in a small
-// text file (one "shape nred staged" line per shape) so that later setups of the
+// text file (one "shape nred staged rpt" line per shape) so that later setups of the
 // same shape skip the timing.
 //
 // Tuned:
-//   nred           workgroups of the reducing PCG kernels (64, 128, 256): fewer
-//                  partials to sum against more tiles per workgroup;
+//   nred, rpt      workgroups of the reducing PCG kernels (64, 128, 256) and vertex
+//                  rows per thread in their tiles (1, 4): fewer partials to sum
+//                  against more tiles per workgroup, and more loads in flight per
+//                  thread against fewer workgroups with work;
 //   smooth_staged  smoother patch factor staged in LDS with 16-byte copies, or
 //                  read by the chains from global memory.
 #include <cstdio>
@@ -23,6 +25,7 @@ namespace {
 struct TuneRec {
     int nred = 256;
     int staged = 1;
+    int rpt = 1;
 };
 
 std::mutex g_tune_mu;
@@ -35,20 +38,22 @@ std::string tune_key(tgms_ctx* c) {
     std::string arch = "unknown";
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
     char buf[256];
-    std::snprintf(buf, sizeof(buf), "%s/%dx%d/b%dx%d/ov%d/p%d", arch.c_str(), c->nx, c->ny, c->bx, c->by, c->overlap,
-                  c->precision);
+    std::snprintf(buf, sizeof(buf), "v2/%s/%dx%d/b%dx%d/ov%d/p%d", arch.c_str(), c->nx, c->ny, c->bx, c->by,
+                  c->overlap, c->precision);
     return buf;
 }
 
-// the cache file: one line per shape, "key nred staged"
+// the cache file: one line per shape, "key nred staged rpt"
 void load_cache(const char* path) {
     if (!path || !*path) return;
     FILE* f = std::fopen(path, "r");
     if (!f) return;
-    char key[256];
-    int nred = 0, staged = 0;
-    while (std::fscanf(f, "%255s %d %d", key, &nred, &staged) == 3) {
-        if (nred >= 1 && nred <= tgms::nred_max() && (staged == 0 || staged == 1)) g_tune[key] = TuneRec{nred, staged};
+    char line[512], key[256];
+    int nred = 0, staged = 0, rpt = 0;
+    while (std::fgets(line, sizeof(line), f)) {
+        if (std::sscanf(line, "%255s %d %d %d", key, &nred, &staged, &rpt) != 4) continue;
+        if (nred >= 1 && nred <= tgms::nred_max() && (staged == 0 || staged == 1) && (rpt == 1 || rpt == 4))
+            g_tune[key] = TuneRec{nred, staged, rpt};
     }
     std::fclose(f);
 }
@@ -57,7 +62,8 @@ void save_cache(const char* path) {
     if (!path || !*path) return;
     FILE* f = std::fopen(path, "w");
     if (!f) return;
-    for (auto& kv : g_tune) std::fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.nred, kv.second.staged);
+    for (auto& kv : g_tune)
+        std::fprintf(f, "%s %d %d %d\n", kv.first.c_str(), kv.second.nred, kv.second.staged, kv.second.rpt);
     std::fclose(f);
 }
 
@@ -90,6 +96,7 @@ void autotune(tgms_ctx* c, const char* cache_path) {
     if (it != g_tune.end()) {
         c->nred = it->second.nred;
         c->smooth_staged = it->second.staged;
+        c->rpt = it->second.rpt;
         c->tuned = 2;
         return;
     }
@@ -104,15 +111,19 @@ void autotune(tgms_ctx* c, const char* cache_path) {
     zero(c, c->vg, sizeof(double) * nv);
     TuneRec best;
     double tbest = 1e30;
-    for (int nred : {64, 128, 256}) {
-        c->nred = nred;
-        const double t = time_ms(c, 5, [&] { dir_apply(c, c->vz, c->vp, c->vp1, c->vq); });
-        if (t < tbest) {
-            tbest = t;
-            best.nred = nred;
+    for (int nred : {64, 128, 256})
+        for (int rpt : {1, 4}) {
+            c->nred = nred;
+            c->rpt = rpt;
+            const double t = time_ms(c, 5, [&] { dir_apply(c, c->vz, c->vp, c->vp1, c->vq); });
+            if (t < tbest) {
+                tbest = t;
+                best.nred = nred;
+                best.rpt = rpt;
+            }
         }
-    }
     c->nred = best.nred;
+    c->rpt = best.rpt;
     // smoother: staged copy vs direct reads (only a choice where the staged form fits)
     const bool prec32 = c->precision != 0;
     double ts[2] = {1e30, 1e30};

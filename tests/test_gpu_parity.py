@@ -295,11 +295,13 @@ def test_autotune_cache(tmp_path):
     s1 = tg.Solver(dev(kappa), bx, by, 0.5, tune_cache=str(cache))
     i1 = s1.info()
     assert i1["tuned"] in (1, 2) and i1["nred"] in (64, 128, 256) and i1["smooth_staged"] in (0, 1)
+    assert i1["rows_per_thread"] in (1, 4)
     text = cache.read_text()
     assert "40x24/b8x8" in text
     s2 = tg.Solver(dev(kappa), bx, by, 0.5, tune_cache=str(cache))
     i2 = s2.info()
     assert i2["tuned"] == 2 and i2["nred"] == i1["nred"] and i2["smooth_staged"] == i1["smooth_staged"]
+    assert i2["rows_per_thread"] == i1["rows_per_thread"]
     s0 = tg.Solver(dev(kappa), bx, by, 0.5, autotune=False)
     assert s0.info()["tuned"] == 0
     o = OracleSolver(Grid2D(nx, ny, bx, by), kappa, 0.5)
