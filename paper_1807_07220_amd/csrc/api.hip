@@ -182,9 +182,12 @@ void precond(tgms_ctx* c, int which, const double* g, double* z) {
     }
 }
 
-void build_coarse_numbering(tgms_ctx* c, const std::vector<double>& Yh, const std::vector<double>& Qh,
-                            std::vector<double>& Tm, std::vector<int>& zc) {
-    const int Nx = c->Nx, Ny = c->Ny, jm = c->jmax, ncol = c->ncol;
+// Coarse unknowns (the zero-flux modes of every face, then one stream function per
+// interior coarse vertex), the unknowns touching each block (slots, ordered by id) and
+// their CSR inverse, and the description of each slot's combination of the face
+// modes (uploaded as meta for k_fill_td, which forms Td on the device from YQ).
+void build_coarse_numbering(tgms_ctx* c, std::vector<int>& meta) {
+    const int Nx = c->Nx, Ny = c->Ny;
     const std::vector<int>& cnt = c->counts_h;
     std::vector<int> zoff(c->ne + 1, 0);
     for (int i = 0; i < c->ne; ++i) zoff[i + 1] = zoff[i] + cnt[i] - 1;
@@ -192,90 +195,91 @@ void build_coarse_numbering(tgms_ctx* c, const std::vector<double>& Yh, const st
     c->nv = (Nx - 1) * (Ny - 1);
     c->ncs = nz + c->nv;
     auto vid = [&](int I, int J) { return (I <= 0 || I >= Nx || J <= 0 || J >= Ny) ? -1 : nz + (J - 1) * (Nx - 1) + I - 1; };
-    // YQ_i = Y_i Q_i (jmax x cnt): coefficients over the face's snapshots
-    auto YQ = [&](int f, int l, int k) {
-        double s = 0.0;
-        for (int k2 = 0; k2 < cnt[f]; ++k2) s += Yh[(size_t)f * jm * jm + l * jm + k2] * Qh[(size_t)f * jm * jm + k2 * jm + k];
-        return s;
-    };
     struct Slot {
-        int id;
-        int corner;
-        std::vector<double> col;
+        int id, corner, n;
+        int f[2], side[2], k[2], sign[2];
     };
     std::vector<std::vector<Slot>> slots(c->nblk);
     int mu = 1;
     for (int J = 0; J < Ny; ++J)
         for (int I = 0; I < Nx; ++I) {
             const int blk = J * Nx + I;
+            std::vector<Slot>& m = slots[blk];
             int face[4] = {-1, -1, -1, -1};
             if (I > 0) face[0] = J * (Nx - 1) + I - 1;
             if (I + 1 < Nx) face[1] = J * (Nx - 1) + I;
             if (J > 0) face[2] = c->nex + (J - 1) * Nx + I;
             if (J + 1 < Ny) face[3] = c->nex + J * Nx + I;
-            std::map<int, Slot> m;
             for (int s = 0; s < 4; ++s) {
                 const int f = face[s];
                 if (f < 0) continue;
-                const int nl = (s < 2) ? c->by : c->bx;
-                for (int k = 1; k < cnt[f]; ++k) {
-                    Slot sl{zoff[f] + k - 1, 0, std::vector<double>(ncol, 0.0)};
-                    for (int l = 0; l < nl; ++l) sl.col[s * jm + l] = YQ(f, l, k);
-                    m[sl.id] = sl;
-                }
+                for (int k = 1; k < cnt[f]; ++k) m.push_back(Slot{zoff[f] + k - 1, 0, 1, {f, 0}, {s, 0}, {k, 0}, {1, 0}});
                 // carrier of this face enters the coarse-curl combination of its two end vertices
                 int v0I, v0J, v1I, v1J;
-                double s0, s1;
-                if (s == 0) { v0I = I; v0J = J + 1; s0 = 1; v1I = I; v1J = J; s1 = -1; }
-                else if (s == 1) { v0I = I + 1; v0J = J + 1; s0 = 1; v1I = I + 1; v1J = J; s1 = -1; }
-                else if (s == 2) { v0I = I; v0J = J; s0 = 1; v1I = I + 1; v1J = J; s1 = -1; }
-                else { v0I = I; v0J = J + 1; s0 = 1; v1I = I + 1; v1J = J + 1; s1 = -1; }
+                if (s == 0) { v0I = I; v0J = J + 1; v1I = I; v1J = J; }
+                else if (s == 1) { v0I = I + 1; v0J = J + 1; v1I = I + 1; v1J = J; }
+                else if (s == 2) { v0I = I; v0J = J; v1I = I + 1; v1J = J; }
+                else { v0I = I; v0J = J + 1; v1I = I + 1; v1J = J + 1; }
                 const int vv[2] = {vid(v0I, v0J), vid(v1I, v1J)};
-                const double ss[2] = {s0, s1};
+                const int ss[2] = {1, -1};
                 const int VI[2] = {v0I, v1I}, VJ[2] = {v0J, v1J};
                 for (int e = 0; e < 2; ++e) {
                     if (vv[e] < 0) continue;
-                    auto it = m.find(vv[e]);
-                    if (it == m.end()) {
+                    Slot* sl = nullptr;
+                    for (auto& x : m)
+                        if (x.id == vv[e]) sl = &x;
+                    if (!sl) {
                         const int ci = (VI[e] == I + 1) ? 0 : c->bx, cj = (VJ[e] == J + 1) ? 0 : c->by;
-                        Slot sl{vv[e], cj * (c->bx + 1) + ci, std::vector<double>(ncol, 0.0)};
-                        it = m.emplace(vv[e], sl).first;
+                        m.push_back(Slot{vv[e], cj * (c->bx + 1) + ci, 0, {0, 0}, {0, 0}, {0, 0}, {0, 0}});
+                        sl = &m.back();
                     }
-                    for (int l = 0; l < nl; ++l) it->second.col[s * jm + l] += ss[e] * YQ(f, l, 0);
+                    if (sl->n >= 2) throw TgmsError{TGMS_E_DEVICE, "coarse numbering: more than two carriers at a corner"};
+                    sl->f[sl->n] = f;
+                    sl->side[sl->n] = s;
+                    sl->k[sl->n] = 0;
+                    sl->sign[sl->n] = ss[e];
+                    ++sl->n;
                 }
             }
-            for (auto& kv : m) slots[blk].push_back(kv.second);
-            mu = std::max(mu, (int)slots[blk].size());
+            std::sort(m.begin(), m.end(), [](const Slot& a, const Slot& b) { return a.id < b.id; });
+            mu = std::max(mu, (int)m.size());
         }
     c->mu = mu;
-    Tm.assign((size_t)c->nblk * ncol * mu, 0.0);
-    zc.assign((size_t)c->nblk * mu, 0);
-    std::vector<int> unk((size_t)c->nblk * mu, 0), nu(c->nblk);
-    std::vector<std::vector<int>> ent(c->ncs);
+    meta.assign((size_t)c->nblk * mu * 11, 0);
+    std::vector<int> zc((size_t)c->nblk * mu, 0), unk((size_t)c->nblk * mu, 0), nu(c->nblk), ptr(c->ncs + 1, 0);
+    for (int b = 0; b < c->nblk; ++b)
+        for (const Slot& sl : slots[b]) ++ptr[sl.id + 1];
+    for (int u = 0; u < c->ncs; ++u) ptr[u + 1] += ptr[u];
+    std::vector<int> flat(std::max(ptr[c->ncs], 1)), fill(ptr.begin(), ptr.end() - 1);
     for (int b = 0; b < c->nblk; ++b) {
         nu[b] = (int)slots[b].size();
         for (int u = 0; u < nu[b]; ++u) {
             const Slot& sl = slots[b][u];
             unk[(size_t)b * mu + u] = sl.id;
             zc[(size_t)b * mu + u] = sl.corner;
-            for (int k = 0; k < ncol; ++k) Tm[((size_t)b * ncol + k) * mu + u] = sl.col[k];
-            ent[sl.id].push_back(b * mu + u);
+            flat[fill[sl.id]++] = b * mu + u;  // blocks in increasing order: the accumulation order
+            int* mm = &meta[((size_t)b * mu + u) * 11];
+            mm[0] = sl.id;
+            mm[1] = sl.corner;
+            mm[2] = sl.n;
+            for (int q = 0; q < sl.n; ++q) {
+                mm[3 + 4 * q] = sl.f[q];
+                mm[4 + 4 * q] = sl.side[q];
+                mm[5 + 4 * q] = sl.k[q];
+                mm[6 + 4 * q] = sl.sign[q];
+            }
         }
-    }
-    std::vector<int> ptr(c->ncs + 1, 0), flat;
-    for (int u = 0; u < c->ncs; ++u) {
-        ptr[u + 1] = ptr[u] + (int)ent[u].size();
-        flat.insert(flat.end(), ent[u].begin(), ent[u].end());
     }
     c->blk_unk = c->alloc<int>((size_t)c->nblk * mu);
     c->blk_nu = c->alloc<int>(c->nblk);
     c->unk_ptr = c->alloc<int>(c->ncs + 1);
-    c->unk_ent = c->alloc<int>(std::max<size_t>(flat.size(), 1));
+    c->unk_ent = c->alloc<int>(flat.size());
+    c->zcd = c->alloc<int>(zc.size());
     HIP_OK(hipMemcpyAsync(c->blk_unk, unk.data(), sizeof(int) * unk.size(), hipMemcpyHostToDevice, c->stream));
     HIP_OK(hipMemcpyAsync(c->blk_nu, nu.data(), sizeof(int) * nu.size(), hipMemcpyHostToDevice, c->stream));
     HIP_OK(hipMemcpyAsync(c->unk_ptr, ptr.data(), sizeof(int) * ptr.size(), hipMemcpyHostToDevice, c->stream));
-    if (!flat.empty())
-        HIP_OK(hipMemcpyAsync(c->unk_ent, flat.data(), sizeof(int) * flat.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(c->unk_ent, flat.data(), sizeof(int) * flat.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(c->zcd, zc.data(), sizeof(int) * zc.size(), hipMemcpyHostToDevice, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
 }
 
@@ -373,7 +377,7 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         c->eigs = c->alloc<double>((size_t)c->ne * c->jmax);
         c->counts = c->alloc<int>(c->ne);
         c->Y = c->alloc<double>((size_t)c->ne * c->jmax * c->jmax);
-        double* Qd = c->alloc<double>((size_t)c->ne * c->jmax * c->jmax);
+        double* YQd = c->alloc<double>((size_t)c->ne * c->jmax * c->jmax);
         {
             Timer t(c->stream);
             const float* Y0 = nullptr;
@@ -388,16 +392,13 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                 Y0 = Yw;
                 c->t_cnn_ms = tc.ms();
             }
-            tgms::pencil_eig_q(c, Qd, Y0, nullptr);
+            tgms::pencil_eig_q(c, YQd, Y0, nullptr);
             c->t_eig_ms = t.ms();
         }
         {
             Timer t(c->stream);
             c->counts_h.resize(c->ne);
-            std::vector<double> Yh((size_t)c->ne * c->jmax * c->jmax), Qh(Yh.size());
             HIP_OK(hipMemcpyAsync(c->counts_h.data(), c->counts, sizeof(int) * c->ne, hipMemcpyDeviceToHost, c->stream));
-            HIP_OK(hipMemcpyAsync(Yh.data(), c->Y, sizeof(double) * Yh.size(), hipMemcpyDeviceToHost, c->stream));
-            HIP_OK(hipMemcpyAsync(Qh.data(), Qd, sizeof(double) * Qh.size(), hipMemcpyDeviceToHost, c->stream));
             if (c->warm) {
                 c->wstat_h.resize(c->ne);
                 HIP_OK(hipMemcpyAsync(c->wstat_h.data(), c->wstat, sizeof(int) * c->ne, hipMemcpyDeviceToHost,
@@ -409,13 +410,12 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                     ++c->warm_accepted;
                     c->warm_iters += w;
                 }
-            std::vector<double> Tm;
-            std::vector<int> zc;
-            build_coarse_numbering(c, Yh, Qh, Tm, zc);
-            c->Td = c->alloc<double>(Tm.size());
-            c->zcd = c->alloc<int>(zc.size());
-            HIP_OK(hipMemcpyAsync(c->Td, Tm.data(), sizeof(double) * Tm.size(), hipMemcpyHostToDevice, c->stream));
-            HIP_OK(hipMemcpyAsync(c->zcd, zc.data(), sizeof(int) * zc.size(), hipMemcpyHostToDevice, c->stream));
+            std::vector<int> meta;
+            build_coarse_numbering(c, meta);
+            int* metad = c->alloc<int>(meta.size());
+            HIP_OK(hipMemcpyAsync(metad, meta.data(), sizeof(int) * meta.size(), hipMemcpyHostToDevice, c->stream));
+            c->Td = c->alloc<double>((size_t)c->nblk * c->ncol * c->mu);
+            tgms::fill_td(c, metad, YQd, c->Td);
             c->W = c->alloc<double>((size_t)c->nblk * bx * by * c->mu);
             if (c->precision) c->W32 = c->alloc<float>((size_t)c->nblk * bx * by * c->mu);
             c->Ac = c->alloc<double>((size_t)c->ncs * c->ncs);

@@ -283,7 +283,8 @@ void gather_final(tgms_ctx* c, const T* w, const T* zin, double* zout, const dou
 // setup (k_setup.hip)
 void snapshots(tgms_ctx* c);
 void gram(tgms_ctx* c);
-void pencil_eig_q(tgms_ctx* c, double* Q, const float* Y0, float* Vtop);
+void pencil_eig_q(tgms_ctx* c, double* YQ, const float* Y0, float* Vtop);  // YQ: kept modes times recombination
+void fill_td(tgms_ctx* c, const int* meta, const double* YQ, double* Td);     // coarse basis combinations
 // warm-start network (k_cnn.hip)
 int cnn_nparams();
 int cnn_kout();

@@ -698,8 +698,10 @@ __global__ void __launch_bounds__(64) k_pencil_eig(BlockGeom G, const double* __
             }
         __syncthreads();
     }
-    // recombination Q (cnt x cnt, stored jmax x jmax): column 0 = f/|f|^2 (unit-flux carrier),
-    // columns 1.. = an orthonormal basis of f^perp (Householder reflector mapping f/|f| to e_1).
+    // recombination Q (cnt x cnt): column 0 = f/|f|^2 (unit-flux carrier), columns 1.. = an
+    // orthonormal basis of f^perp (Householder reflector mapping f/|f| to e_1); stored in LDS
+    // (V is free now), then YQ = Y Q (jmax x jmax, rows l < Jn, columns k < cnt) to Qout.
+    double* Qs = &V[0][0];  // Qs[k2 * 65 + k]
     if (lane == 0) {
         double f[64], nrm2 = 0.0;
         for (int k = 0; k < cnt; ++k) {
@@ -708,9 +710,7 @@ __global__ void __launch_bounds__(64) k_pencil_eig(BlockGeom G, const double* __
             f[k] = elen * s;
             nrm2 += f[k] * f[k];
         }
-        double* Qf = Qout + (long long)fid * G.jmax * G.jmax;
-        for (int e = 0; e < G.jmax * G.jmax; ++e) Qf[e] = 0.0;
-        for (int k = 0; k < cnt; ++k) Qf[k * G.jmax] = f[k] / nrm2;
+        for (int k = 0; k < cnt; ++k) Qs[k * 65] = f[k] / nrm2;
         if (cnt > 1) {
             const double nr = sqrt(nrm2);
             double w[64], ww = 0.0;
@@ -718,9 +718,37 @@ __global__ void __launch_bounds__(64) k_pencil_eig(BlockGeom G, const double* __
             w[0] += (w[0] >= 0 ? 1.0 : -1.0);
             for (int k = 0; k < cnt; ++k) ww += w[k] * w[k];
             for (int r = 0; r < cnt; ++r)
-                for (int cc = 1; cc < cnt; ++cc)
-                    Qf[r * G.jmax + cc] = ((r == cc) ? 1.0 : 0.0) - 2.0 * w[r] * w[cc] / ww;
+                for (int cc = 1; cc < cnt; ++cc) Qs[r * 65 + cc] = ((r == cc) ? 1.0 : 0.0) - 2.0 * w[r] * w[cc] / ww;
         }
+    }
+    __syncthreads();
+    double* Qf = Qout + (long long)fid * G.jmax * G.jmax;
+    for (int e = lane; e < G.jmax * G.jmax; e += 64) {
+        const int l = e / G.jmax, k = e % G.jmax;
+        double s = 0.0;
+        if (l < Jn && k < cnt)
+            for (int k2 = 0; k2 < cnt; ++k2) s += Yf[l * G.jmax + k2] * Qs[k2 * 65 + k];
+        Qf[e] = s;
+    }
+}
+
+// Td = the coarse basis combination of each block: column kc = side * jmax + l of slot u
+// (a coarse unknown touching the block) is sum over the slot's contributions c of
+// sign_c * YQ[face_c][l][mode_c] on the contribution's side (l < that side's face count).
+// meta[(b * mu + u) * 11]: id, corner, count, then (face, side, mode, sign) twice.
+__global__ void k_fill_td(BlockGeom G, int mu, const int* __restrict__ meta, const double* __restrict__ YQ,
+                          double* __restrict__ Td) {
+    const int b = blockIdx.x;
+    for (int e = threadIdx.x; e < G.ncol * mu; e += blockDim.x) {
+        const int kc = e / mu, u = e % mu, side = kc / G.jmax, l = kc % G.jmax;
+        const int* m = meta + ((long long)b * mu + u) * 11;
+        const int nl = side < 2 ? G.by : G.bx;
+        double val = 0.0;
+        for (int q = 0; q < m[2]; ++q) {
+            const int f = m[3 + 4 * q], sd = m[4 + 4 * q], k = m[5 + 4 * q], sg = m[6 + 4 * q];
+            if (sd == side && l < nl) val += sg * YQ[((long long)f * G.jmax + l) * G.jmax + k];
+        }
+        Td[((long long)b * G.ncol + kc) * mu + u] = val;
     }
 }
 
@@ -1015,6 +1043,11 @@ void pencil_eig_q(tgms_ctx* c, double* Q, const float* Y0, float* Vtop) {
         hipLaunchKernelGGL(k_pencil_eig<0>, dim3(c->ne), dim3(64), 0, c->stream, G, c->kinv, c->G, c->tol,
                            1.0 / c->H, c->eigs, c->counts, c->Y, Q, (const float*)nullptr, 0, 0.0, 0, (int*)nullptr,
                            Vtop);
+    LAUNCH_OK();
+}
+
+void fill_td(tgms_ctx* c, const int* meta, const double* YQ, double* Td) {
+    hipLaunchKernelGGL(k_fill_td, dim3(c->nblk), dim3(256), 0, c->stream, geom(c), c->mu, meta, YQ, Td);
     LAUNCH_OK();
 }
 
