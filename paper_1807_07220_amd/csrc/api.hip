@@ -317,6 +317,20 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
             throw TgmsError{TGMS_E_UNSUPPORTED, "the network warm start needs square blocks of at most 16 x 16 cells"};
     }
     auto* c = new tgms_ctx();
+    // second stream (default priority) for the preprocessing's coarse RT0 inverse, which
+    // runs concurrently with the spectral setup; declared before the queued inverse so
+    // that the inverse's clean-up still finds it
+    struct Side {
+        hipStream_t s = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Side() {
+            if (s) (void)hipStreamSynchronize(s);
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            if (s) (void)hipStreamDestroy(s);
+        }
+    } side;
+    tgms::DenseInvAsync kh_inv;
     try {
         // All work runs on a stream of the library's own (default priority); each call
         // first waits for what the caller queued on its stream (NULL: the null stream)
@@ -356,6 +370,29 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         HIP_OK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
         HIP_OK(hipStreamSynchronize(c->stream));
         if (hbad) throw TgmsError{TGMS_E_INVAL, "permeability must be finite and positive"};
+        // the coarse RT0 stiffness of the preprocessing (section 3) and its inverse, queued on
+        // the second stream; joined before the end of the coarse phase
+        c->nv = (c->Nx - 1) * (c->Ny - 1);
+        c->AH0 = c->alloc<double>((size_t)c->nblk * 6);
+        c->KH = c->alloc<double>((size_t)c->nv * c->nv);
+        HIP_OK(hipStreamCreateWithFlags(&side.s, hipStreamNonBlocking));
+        HIP_OK(hipEventCreateWithFlags(&side.e0, hipEventDisableTiming));
+        HIP_OK(hipEventCreateWithFlags(&side.e1, hipEventDisableTiming));
+        HIP_OK(hipEventRecord(side.e0, c->stream));
+        HIP_OK(hipStreamWaitEvent(side.s, side.e0, 0));
+        {
+            const hipStream_t main_stream = c->stream;
+            struct Restore {
+                tgms_ctx* c;
+                hipStream_t s;
+                ~Restore() { c->stream = s; }
+            } restore{c, main_stream};
+            c->stream = side.s;
+            tgms::coarse_rt0_blocks(c);
+            tgms::rt0_stiffness(c, c->KH);
+            tgms::dense_spd_inverse_begin(c, c->KH, c->nv, kh_inv);
+        }
+        HIP_OK(hipEventRecord(side.e1, side.s));
         // block factors
         c->blk_m = bx - 1;
         c->blk_n = (bx - 1) * (by - 1);
@@ -431,10 +468,9 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
             c->cy32 = c->alloc<float>((size_t)c->nblk * c->mu);
             c->cvec32 = c->alloc<float>(2 * (size_t)c->ncs + 1);
             c->cvec2_32 = c->alloc<float>((size_t)c->ncs + 1);
-            // coarse RT0 for the preprocessing
-            c->AH0 = c->alloc<double>((size_t)c->nblk * 6);
-            tgms::coarse_rt0_blocks(c);
-            build_rt0_stiffness(c);
+            // coarse RT0 for the preprocessing: join the second stream
+            HIP_OK(hipStreamWaitEvent(c->stream, side.e1, 0));
+            tgms::dense_spd_inverse_end(kh_inv);
             c->cflux = c->alloc<double>(2 * ((size_t)c->Ny * (c->Nx + 1) + (size_t)(c->Ny + 1) * c->Nx));
             c->svec = c->alloc<double>((size_t)c->nv + 1);
             c->svec2 = c->alloc<double>(2 * (size_t)c->nv + 1);
@@ -515,6 +551,7 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         c->t_setup_ms = total.ms();
         *out = c;
     } catch (...) {
+        if (side.s) (void)hipStreamSynchronize(side.s);  // its work writes into the context's buffers
         tgms_destroy(c);
         throw;
     }

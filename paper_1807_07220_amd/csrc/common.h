@@ -306,6 +306,24 @@ template <typename T>
 const T* coarse_solve(tgms_ctx* c, const double* sc);  // accumulate the restrictions, apply the coarse inverse
 // dense (k_dense.hip)
 void dense_spd_inverse(tgms_ctx* c, double* A, int n);
+struct DenseInvWork {
+    double* Dinv = nullptr;
+    int* fail = nullptr;
+    double* X = nullptr;
+    double* Tm = nullptr;
+};
+// an inverse queued on a stream without waiting (dense_spd_inverse_begin / _end)
+struct DenseInvAsync {
+    DenseInvWork w;
+    hipStream_t stream = nullptr;
+    DenseInvAsync() = default;
+    DenseInvAsync(const DenseInvAsync&) = delete;
+    DenseInvAsync& operator=(const DenseInvAsync&) = delete;
+    ~DenseInvAsync();
+    void release();
+};
+void dense_spd_inverse_begin(tgms_ctx* c, double* A, int n, DenseInvAsync& h);
+void dense_spd_inverse_end(DenseInvAsync& h);
 template <typename T>
 void symv(tgms_ctx* c, const T* A, int n, const T* x, T* y, const double* sc);
 template <typename T>

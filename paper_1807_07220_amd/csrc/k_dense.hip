@@ -262,17 +262,18 @@ void gemm(tgms_ctx* c, int transA, int transB, int M, int N, int K, double alpha
     LAUNCH_OK();
 }
 
-// In place: A (n x n, row-major, symmetric positive definite) -> B = tril(L^{-1}) + triu(L^{-T}, 1).
-void dense_spd_inverse(tgms_ctx* c, double* A, int n) {
-    if (n <= 0) return;
+// The launches of the inverse on c->stream, with no host synchronisation:
+//   1. blocked Cholesky (lower), failures flagged in w.fail;
+//   2. X = L^{-1} by recursive halving: [L11 0; L21 L22]^{-1} = [X11 0; -X22 L21 X11, X22],
+//      whose products are large square GEMMs; the 64 x 64 leaves are the inverses from 1;
+//   3. A = tril(X) + triu(X^T, 1).
+static void dense_inverse_enqueue(tgms_ctx* c, double* A, int n, const DenseInvWork& w) {
     const int nblk = (n + TB - 1) / TB;
-    double* Dinv = c->alloc<double>((size_t)nblk * TB * TB);
-    int* fail = c->alloc<int>(1);
-    // 1. blocked Cholesky (lower)
+    double* Dinv = w.Dinv;
     for (int kb0 = 0; kb0 < nblk; ++kb0) {
         const int k0 = kb0 * TB, kb = std::min(TB, n - k0), k1 = k0 + kb;
         hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(NT), 0, c->stream, A, n, k0, kb, Dinv + (size_t)kb0 * TB * TB,
-                           fail);
+                           w.fail);
         LAUNCH_OK();
         const int m = n - k1;
         if (m <= 0) break;
@@ -293,14 +294,6 @@ void dense_spd_inverse(tgms_ctx* c, double* A, int n) {
             LAUNCH_OK();
         }
     }
-    int h = 0;
-    HIP_OK(hipMemcpyAsync(&h, fail, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    HIP_OK(hipStreamSynchronize(c->stream));
-    if (h) throw TgmsError{TGMS_E_INVAL, "coarse operator is not positive definite"};
-    // 2. X = L^{-1} by recursive halving: [L11 0; L21 L22]^{-1} = [X11 0; -X22 L21 X11, X22],
-    //    whose products are large square GEMMs; the 64 x 64 leaves are the inverses from step 1.
-    double* X = c->alloc<double>((size_t)n * n);
-    double* Tm = c->alloc<double>((size_t)n * (n / 2 + TB));
     struct Rec {
         tgms_ctx* c;
         double* A;
@@ -324,17 +317,75 @@ void dense_spd_inverse(tgms_ctx* c, double* A, int n) {
             gemm(c, 0, 0, n2, n1, n2, -1.0, X + (size_t)(o + n1) * n + o + n1, n, Tm, n1, 0.0,
                  X + (size_t)(o + n1) * n + o, n);
         }
-    } rec{c, A, X, Tm, Dinv, n};
+    } rec{c, A, w.X, w.Tm, Dinv, n};
     rec.run(0, n);
-    // 3. pack
-    hipLaunchKernelGGL(k_pack_inverse, dim3(nb((long long)n * n)), dim3(256), 0, c->stream, (const double*)X, A, n);
+    hipLaunchKernelGGL(k_pack_inverse, dim3(nb((long long)n * n)), dim3(256), 0, c->stream, (const double*)w.X, A, n);
     LAUNCH_OK();
+}
+
+static void dense_inverse_sizes(int n, size_t& dinv, size_t& x, size_t& tm) {
+    const int nblk = (n + TB - 1) / TB;
+    dinv = (size_t)nblk * TB * TB;
+    x = (size_t)n * n;
+    tm = (size_t)n * (n / 2 + TB);
+}
+
+// In place: A (n x n, row-major, symmetric positive definite) -> B = tril(L^{-1}) + triu(L^{-T}, 1).
+void dense_spd_inverse(tgms_ctx* c, double* A, int n) {
+    if (n <= 0) return;
+    size_t nd, nx, nt;
+    dense_inverse_sizes(n, nd, nx, nt);
+    DenseInvWork w;
+    w.Dinv = c->alloc<double>(nd);
+    w.fail = c->alloc<int>(1);
+    w.X = c->alloc<double>(nx);
+    w.Tm = c->alloc<double>(nt);
+    dense_inverse_enqueue(c, A, n, w);
+    int h = 0;
+    HIP_OK(hipMemcpyAsync(&h, w.fail, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
     // release the temporaries (they are the last allocations)
     for (int k = 0; k < 4; ++k) {
         HIP_OK(hipFree(c->owned.back().p));
         c->owned.pop_back();
     }
+    if (h) throw TgmsError{TGMS_E_INVAL, "coarse operator is not positive definite"};
+}
+
+// The same, queued on c->stream without waiting: the workspace is allocated here
+// (released by dense_spd_inverse_end, or by the destructor if that is not reached).
+void dense_spd_inverse_begin(tgms_ctx* c, double* A, int n, DenseInvAsync& h) {
+    if (n <= 0) return;
+    size_t nd, nx, nt;
+    dense_inverse_sizes(n, nd, nx, nt);
+    HIP_OK(hipMalloc(&h.w.Dinv, sizeof(double) * nd));
+    HIP_OK(hipMalloc(&h.w.fail, sizeof(int) * 64));
+    HIP_OK(hipMalloc(&h.w.X, sizeof(double) * nx));
+    HIP_OK(hipMalloc(&h.w.Tm, sizeof(double) * nt));
+    h.stream = c->stream;
+    zero(c, h.w.fail, sizeof(int) * 64);
+    dense_inverse_enqueue(c, A, n, h.w);
+}
+
+// Waits for the queued inverse, releases its workspace and reports a failed factorisation.
+void dense_spd_inverse_end(DenseInvAsync& h) {
+    if (!h.w.fail) return;
+    int f = 0;
+    HIP_OK(hipStreamSynchronize(h.stream));
+    HIP_OK(hipMemcpy(&f, h.w.fail, sizeof(int), hipMemcpyDeviceToHost));
+    h.release();
+    if (f) throw TgmsError{TGMS_E_INVAL, "coarse operator is not positive definite"};
+}
+
+DenseInvAsync::~DenseInvAsync() {
+    if (w.fail && stream) (void)hipStreamSynchronize(stream);
+    release();
+}
+
+void DenseInvAsync::release() {
+    for (void* p : {(void*)w.Dinv, (void*)w.fail, (void*)w.X, (void*)w.Tm})
+        if (p) (void)hipFree(p);
+    w = DenseInvWork{};
 }
 
 // y = A^{-1} x with A^{-1} held as B = tril(X) + triu(X^T, 1); tmp has n entries.
