@@ -258,8 +258,8 @@ template <typename T>
 __device__ inline T patch_sum(const Rect* __restrict__ rects, const T* __restrict__ w, const T* __restrict__ w4,
                               const GatherGeom& G, int i, int j) {
     if (w4) {
-        const T* q = w4 + ((long long)j * G.nx + i) * 4;
-        return (q[0] + q[1]) + (q[2] + q[3]);
+        const long long plane = (long long)G.nx * G.ny, v = (long long)j * G.nx + i;
+        return (w4[v] + w4[plane + v]) + (w4[2 * plane + v] + w4[3 * plane + v]);
     }
     return gather_w<T>(rects, w, i, j, G.bx, G.by, G.Nx, G.Ny);
 }

@@ -233,13 +233,15 @@ __device__ inline T dot_lanes(const T (&v)[M], T x) {
 }
 
 // Where a patch solution goes: the patch's own vector (slot layout off), or the
-// slot of the patch in a four-slot array per vertex (own block, x neighbour,
-// y neighbour, diagonal neighbour), so that summing the overlapping solutions
-// is one contiguous read per vertex.
+// slot of the patch among four vertex planes (own block, x neighbour, y neighbour,
+// diagonal neighbour): every vertex lies in at most one patch of each kind, so a
+// patch writes whole row segments of each plane and summing the overlapping
+// solutions is four coalesced reads per vertex.
 template <typename T>
 struct PatchOut {
     T* base;        // own vector (m*mh entries), used when w4 is null
-    T* w4;          // four slots per global vertex
+    T* w4;          // four planes of nx*ny vertices
+    long long plane;
     int m, nx, i0, j0;
     int bxlo, bxhi, bylo, byhi;  // the cells of the patch's own coarse block
     __device__ void put(int row, int a, T v) const {
@@ -249,7 +251,7 @@ struct PatchOut {
         }
         const int i = i0 + 1 + a, j = j0 + 1 + row;
         const int slot = (i < bxlo || i >= bxhi ? 1 : 0) + (j < bylo || j >= byhi ? 2 : 0);
-        w4[((long long)j * nx + i) * 4 + slot] = v;
+        w4[slot * plane + (long long)j * nx + i] = v;
     }
 };
 
@@ -418,7 +420,7 @@ __device__ inline void solve_patch_any(int m, int mh, const T* F, T* vec, T* u, 
 // path of its width.
 template <typename T, int M1, int M2, bool GENERIC, bool STAGED>
 __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__ rects, const T* __restrict__ Fpool,
-                                                        const T* __restrict__ g, int nx, T* __restrict__ wout,
+                                                        const T* __restrict__ g, int nx, int ny, T* __restrict__ wout,
                                                         T* __restrict__ w4, int bx, int by, int Nx,
                                                         const double* __restrict__ sc) {
     if (sc != nullptr && sc[SC_DONE] != 0.0) return;  // PCG already converged
@@ -456,14 +458,17 @@ __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__
     }
     T* u = vec + ((n + 3) & ~3);
     T* mid = u + ((n + 3) & ~3);  // 2 * 64
-    const T* Sg = Fg + tw_scale(m, mh);
+    // the scale from the staged copy (read once from global memory)
+    if constexpr (STAGED) __syncthreads();
+    const T* Sg = F + tw_scale(m, mh);
     for (int r = tid; r < n; r += 256) {
         const int aa = r % m, bb = r / m;
         vec[r] = Sg[r] * g[(long long)(R.j0 + 1 + bb) * nx + R.i0 + 1 + aa];
     }
     __syncthreads();
     const int I = blockIdx.x % Nx, J = blockIdx.x / Nx;
-    const PatchOut<T> out{wout + R.voff, w4, m, nx, R.i0, R.j0, I * bx, (I + 1) * bx, J * by, (J + 1) * by};
+    const long long plane = (long long)nx * ny;
+    const PatchOut<T> out{wout + R.voff, w4, plane, m, nx, R.i0, R.j0, I * bx, (I + 1) * bx, J * by, (J + 1) * by};
     if constexpr (GENERIC)
         solve_patch_any<T>(m, mh, F, vec, u, mid, out);
     else if (m == M1)
@@ -485,11 +490,11 @@ void launch_tw(tgms_ctx* c, const T* L, const T* g, T* w, size_t lds, const doub
         // events recorded by the dispatch itself (kernel execution only)
         hipEvent_t e1 = tgms::take_event(c), e2 = tgms::take_event(c);
         hipExtLaunchKernelGGL((k_smooth_twisted<T, M1, M2, GENERIC, STAGED>), dim3(c->nblk), dim3(256), lds,
-                              c->stream, e1, e2, 0, c->patch, L, g, c->nx, w, w4, c->bx, c->by, c->Nx, sc);
+                              c->stream, e1, e2, 0, c->patch, L, g, c->nx, c->ny, w, w4, c->bx, c->by, c->Nx, sc);
         c->prof_rec.push_back({tgms::PK_SMOOTH, c->prof_iter, e1, e2});
     } else {
         hipLaunchKernelGGL((k_smooth_twisted<T, M1, M2, GENERIC, STAGED>), dim3(c->nblk), dim3(256), lds, c->stream,
-                           c->patch, L, g, c->nx, w, w4, c->bx, c->by, c->Nx, sc);
+                           c->patch, L, g, c->nx, c->ny, w, w4, c->bx, c->by, c->Nx, sc);
     }
 }
 
