@@ -85,6 +85,9 @@ typedef struct {
     const float* cnn_weights;  /* device, tgms_cnn_nparams() floats (warm_start 2; read during
                                   setup only) */
     double rq_tol;     /* relative Ritz residual |T u - theta u| / theta for acceptance (1e-6) */
+    int smoother_staging;  /* -1: chosen by the autotuner (without it: staged where the factor
+                              fits in LDS); 0: the patch solves read their factor from global
+                              memory; 1: the factor is first staged in LDS */
 } tgms_options;
 
 typedef struct {
@@ -108,7 +111,7 @@ typedef struct {
 
 /* Paper defaults: eta 0.2, overlap 2, FP64, s_scale = |K|^(1/2), default stream,
  * graph replay on, autotuning on without a cache file, dense local eigensolves
- * (warm_start 0, rq_tol 1e-6). */
+ * (warm_start 0, rq_tol 1e-6), smoother staging chosen by the autotuner. */
 void tgms_default_options(tgms_options* opt);
 
 /*

@@ -36,7 +36,8 @@ class Solver:
     def __init__(self, kappa: torch.Tensor, bx: int, by: int, eig_tol: float, eta: float = 0.2, overlap: int = 2,
                  precision: str = "fp64", s_scale: float = 0.0, stream: torch.cuda.Stream | None = None,
                  graphs: bool = True, autotune: bool = True, tune_cache: str | None = None,
-                 warm_start: str = "exact", cnn_weights: torch.Tensor | None = None, rq_tol: float = 1e-6):
+                 warm_start: str = "exact", cnn_weights: torch.Tensor | None = None, rq_tol: float = 1e-6,
+                 smoother_staging: int = -1):
         lib = load()
         if kappa.dim() != 2:
             raise ValueError("kappa must be (ny, nx)")
@@ -59,6 +60,7 @@ class Solver:
                 raise ValueError("cnn_weights must be a contiguous float32 CUDA tensor")
             opt.cnn_weights = ctypes.c_void_p(cnn_weights.data_ptr())
         opt.rq_tol = float(rq_tol)
+        opt.smoother_staging = int(smoother_staging)
         grid = Grid(self.nx, self.ny, self.bx, self.by)
         handle = ctypes.c_void_p()
         kappa = kappa.contiguous()

@@ -547,6 +547,7 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         c->vp1 = c->alloc<double>(nvtx);
         HIP_OK(hipHostMalloc((void**)&c->red_h, SC_COUNT * sizeof(double), hipHostMallocDefault));
         if (o.autotune) tgms::autotune(c, o.tune_cache);
+        if (o.smoother_staging >= 0) c->smooth_staged = o.smoother_staging ? 1 : 0;
         HIP_OK(hipStreamSynchronize(c->stream));
         c->t_setup_ms = total.ms();
         *out = c;
@@ -749,6 +750,7 @@ void tgms_default_options(tgms_options* opt) {
     opt->warm_start = 0;
     opt->cnn_weights = nullptr;
     opt->rq_tol = 1e-6;
+    opt->smoother_staging = -1;
 }
 
 tgms_status tgms_setup(const tgms_grid* grid, const double* kappa, double eig_tol, const tgms_options* opt,

@@ -13,6 +13,10 @@
 #include "common.h"
 #include "patch.h"
 
+#ifndef TGMS_PF_DIRECT
+#define TGMS_PF_DIRECT 1  // link lines in flight per chain when the factor is read from global memory
+#endif
+
 namespace {
 
 // ------------------------------------------------------------------ factorisation
@@ -258,45 +262,49 @@ struct PatchOut {
 // One chain of steps t = 0..steps-1 on link lk(t): line(t) . x with line = row
 // (ROW) or column of the link; then x = base[r(t)] - product, handed to put(r(t), .)
 // (scaled by scale[r(t)] when given), except that with TO_MID the last product
-// goes to mid instead.
-template <typename T, int M, bool ROW, bool TO_MID, typename RowOf, typename LinkOf, typename Put>
+// goes to mid instead.  The lines of the next PF steps are in flight while a step
+// computes (PF + 1 register buffers, rotated by unrolling).
+template <typename T, int M, bool ROW, bool TO_MID, int PF, typename RowOf, typename LinkOf, typename Put>
 __device__ inline void chain(const Lines<T, M>& ln, int steps, const T* Lk, const T* base, Put put, const T* scale,
                              T* mid, T x, bool act, RowOf rr, LinkOf lk) {
     if (steps <= 0) return;
     constexpr long long mm = (long long)M * M;
+    constexpr int NB = PF + 1;
     const int a = ln.a;
-    T la[M], lb[M];
-    T ba = T(0), bb = T(0), sa = T(1), sb = T(1);
-    auto load = [&](T(&L)[M], T& bv, T& sv, int t) {
+    T L[NB][M];
+    T bv[NB], sv[NB];
+    auto load = [&](T(&Ld)[M], T& b, T& sc, int t) {
         if (ROW)
-            ln.row(L, Lk + lk(t) * mm);
+            ln.row(Ld, Lk + lk(t) * mm);
         else
-            ln.column(L, Lk + lk(t) * mm);
-        if (!TO_MID || t + 1 < steps) bv = base[rr(t) * M + a];
-        if (scale) sv = scale[rr(t) * M + a];
+            ln.column(Ld, Lk + lk(t) * mm);
+        b = (!TO_MID || t + 1 < steps) ? base[rr(t) * M + a] : T(0);
+        sc = scale ? scale[rr(t) * M + a] : T(1);
     };
-    load(la, ba, sa, 0);
-    int t = 0;
-    auto step = [&](const T(&L)[M], T bv, T sv, T(&Ln)[M], T& bn, T& sn) {
-        const T s = dot_lanes<T, M>(L, x);
-        __builtin_amdgcn_sched_barrier(0);  // keep the next loads behind this step's products
-        if (t + 1 < steps) load(Ln, bn, sn, t + 1);
-        if (TO_MID && t + 1 == steps) {
-            if (act) mid[a] = s;
-        } else {
-            x = bv - s;
-            if (act) put(rr(t), scale ? sv * x : x);
+#pragma unroll
+    for (int d = 0; d < PF; ++d)
+        if (d < steps) load(L[d], bv[d], sv[d], d);
+    for (int t0 = 0; t0 < steps; t0 += NB) {
+#pragma unroll
+        for (int d = 0; d < NB; ++d) {
+            const int t = t0 + d;
+            if (t < steps) {
+                const T s = dot_lanes<T, M>(L[d], x);
+                __builtin_amdgcn_sched_barrier(0);  // keep the next loads behind this step's products
+                const int dn = (d + PF) % NB;  // a constant once the loop is unrolled
+                if (t + PF < steps) load(L[dn], bv[dn], sv[dn], t + PF);
+                if (TO_MID && t + 1 == steps) {
+                    if (act) mid[a] = s;
+                } else {
+                    x = bv[d] - s;
+                    if (act) put(rr(t), scale ? sv[d] * x : x);
+                }
+            }
         }
-    };
-    while (true) {
-        step(la, ba, sa, lb, bb, sb);
-        if (++t >= steps) break;
-        step(lb, bb, sb, la, ba, sa);
-        if (++t >= steps) break;
     }
 }
 
-template <typename T, int M>
+template <typename T, int M, int PF>
 __device__ inline void solve_patch(int mh, const T* F, T* vec, T* u, T* mid, const PatchOut<T>& out) {
     constexpr int m = M, tri = M * (M + 1) / 2;
     const int k = mh / 2;
@@ -310,13 +318,13 @@ __device__ inline void solve_patch(int mh, const T* F, T* vec, T* u, T* mid, con
     if (wave == 0) {
         // w_{t+1} = b_{t+1} - G_t w_t for t < k-1, stored over b; G_{k-1} w_{k-1} -> mid
         auto to_vec = [&](int row, T v) { vec[row * M + a] = v; };
-        chain<T, M, true, true>(ln, k, Lk, vec, to_vec, (const T*)nullptr, mid, vec[a], act,
+        chain<T, M, true, true, PF>(ln, k, Lk, vec, to_vec, (const T*)nullptr, mid, vec[a], act,
                                 [](int t) { return t + 1; }, [](int t) { return (long long)t; });
         if (k == 0 && act) mid[a] = T(0);
     } else if (wave == 1) {
         // w_{r-1} = b_{r-1} - H_{r-1} w_r from r = mh-1 down; H_k w_{k+1} -> mid + M
         auto to_vec = [&](int row, T v) { vec[row * M + a] = v; };
-        chain<T, M, true, true>(ln, mh - 1 - k, Lk, vec, to_vec, (const T*)nullptr, mid + M, vec[(mh - 1) * M + a],
+        chain<T, M, true, true, PF>(ln, mh - 1 - k, Lk, vec, to_vec, (const T*)nullptr, mid + M, vec[(mh - 1) * M + a],
                                 act, [=](int t) { return mh - 2 - t; }, [=](int t) { return (long long)(mh - 2 - t); });
         if (mh - 1 == k && act) mid[M + a] = T(0);
     }
@@ -343,11 +351,11 @@ __device__ inline void solve_patch(int mh, const T* F, T* vec, T* u, T* mid, con
     if (wave == 0) {
         if (act) out.put(k, a, S[k * M + a] * xk);
         // x_l = u_l - G_l^T x_{l+1}, l = k-1 .. 0
-        chain<T, M, false, false>(ln, k, Lk, u, to_out, S, mid, xk, act, [=](int t) { return k - 1 - t; },
+        chain<T, M, false, false, PF>(ln, k, Lk, u, to_out, S, mid, xk, act, [=](int t) { return k - 1 - t; },
                                   [=](int t) { return (long long)(k - 1 - t); });
     } else if (wave == 1) {
         // x_{l+1} = u_{l+1} - H_l^T x_l, l = k .. mh-2
-        chain<T, M, false, false>(ln, mh - 1 - k, Lk, u, to_out, S, mid, xk, act, [=](int t) { return k + 1 + t; },
+        chain<T, M, false, false, PF>(ln, mh - 1 - k, Lk, u, to_out, S, mid, xk, act, [=](int t) { return k + 1 + t; },
                                   [=](int t) { return (long long)(k + t); });
     }
 }
@@ -415,7 +423,7 @@ __device__ inline void solve_patch_any(int m, int mh, const T* F, T* vec, T* u, 
 
 // One workgroup (4 waves) per patch.  STAGED: the factor is first copied to LDS
 // with 16-byte loads (eight in flight per thread); otherwise the chains read it
-// from global memory.  GENERIC: every patch takes the clamped path of width M1
+// from global memory with the lines of the next steps in flight.  GENERIC: every patch takes the clamped path of width M1
 // (m <= M1); otherwise every patch has width M1 or M2 and takes the fixed-width
 // path of its width.
 template <typename T, int M1, int M2, bool GENERIC, bool STAGED>
@@ -472,9 +480,9 @@ __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__
     if constexpr (GENERIC)
         solve_patch_any<T>(m, mh, F, vec, u, mid, out);
     else if (m == M1)
-        solve_patch<T, M1>(mh, F, vec, u, mid, out);
+        solve_patch<T, M1, STAGED ? 1 : TGMS_PF_DIRECT>(mh, F, vec, u, mid, out);
     else
-        solve_patch<T, M2>(mh, F, vec, u, mid, out);
+        solve_patch<T, M2, STAGED ? 1 : TGMS_PF_DIRECT>(mh, F, vec, u, mid, out);
 }
 
 // Fixed-width pairs (interior width, boundary-clipped width) with an overlap of
@@ -513,6 +521,13 @@ void dispatch_twisted(tgms_ctx* c, int m1, int m2, bool staged, const T* L, cons
 #undef TGMS_TW_CASE
         launch_tw<T, 0, 0, true, true>(c, L, g, w, lds, sc);
     } else {
+#define TGMS_TW_CASE_D(A, B)                                  \
+    if (m1 == A && (m2 == B || m2 == A)) {                    \
+        launch_tw<T, A, B, false, false>(c, L, g, w, lds, sc); \
+        return;                                               \
+    }
+        TGMS_TW_PAIRS(TGMS_TW_CASE_D)
+#undef TGMS_TW_CASE_D
         launch_tw<T, 0, 0, true, false>(c, L, g, w, lds, sc);
     }
 }
