@@ -134,7 +134,8 @@ double lanczos_cond(const std::vector<double>& al, const std::vector<double>& be
 // residuals are formed in FP64 from it); z: FP64 output.  With dots, the final
 // gather also forms the PCG scalars from gd (and gold for the flexible variant).
 template <typename T>
-void twogrid(tgms_ctx* c, const T* g, const double* gd, double* z, const double* gold, bool dots, bool first) {
+void twogrid(tgms_ctx* c, const T* g, const double* gd, double* z, const double* gold, bool dots, bool first,
+             const FusedUpdate* fu = nullptr) {
     const double* sc = dots ? c->sc : nullptr;
     T *w, *z1, *z2, *t;
     if constexpr (sizeof(T) == 8) {
@@ -148,7 +149,7 @@ void twogrid(tgms_ctx* c, const T* g, const double* gd, double* z, const double*
         z2 = (T*)c->ft2;
         t = (T*)c->ft;
     }
-    tgms::smooth_patches<T>(c, g, sc);
+    tgms::smooth_patches<T>(c, g, sc, fu);
     tgms::gather_res_restrict<T>(c, w, gd, z1, t, tgms::coarse_cy<T>(c), sc);
     const T* cres = tgms::coarse_solve<T>(c, sc);
     tgms::prolong_residual<T>(c, cres, z1, z2, gd, t, sc);
@@ -535,6 +536,7 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         c->vx = c->alloc<double>(nvtx); c->vg = c->alloc<double>(nvtx); c->vz = c->alloc<double>(nvtx);
         c->vp = c->alloc<double>(nvtx); c->vq = c->alloc<double>(nvtx); c->vt = c->alloc<double>(nvtx);
         c->vt2 = c->alloc<double>(nvtx); c->vt3 = c->alloc<double>(nvtx); c->vgold = c->alloc<double>(nvtx);
+        c->vg2 = c->alloc<double>(nvtx);
         c->fg = c->alloc<float>(nvtx); c->fz = c->alloc<float>(nvtx); c->ft = c->alloc<float>(nvtx);
         c->ft2 = c->alloc<float>(nvtx);
         c->fbar = c->alloc<double>(c->nf); c->fu = c->alloc<double>(c->nf); c->fF = c->alloc<double>(c->nf);
@@ -631,22 +633,37 @@ void solve_impl(tgms_ctx* c, const double* F, const double* g_bnd, double rtol, 
     } else {
         twogrid<double>(c, c->vg, c->vg, c->vz, nullptr, true, true);
     }
-    auto iteration = [&](const double* pin, double* pout) {
+    // With overlapping patches (every vertex of a block lies inside its patch) the
+    // update x += alpha p, g -= alpha q runs inside the first smoothing, which reads g
+    // from one buffer and writes the new g to the other (gin / gout alternate with the
+    // search direction; gin is also the old residual the flexible beta needs).
+    const bool fused = c->overlap >= 1;
+    auto iteration = [&](const double* pin, double* pout, double* gin, double* gout) {
         tgms::dir_apply(c, c->vz, pin, pout, c->vq);
+        if (fused) {
+            const FusedUpdate fu{c->part2, c->nred, c->sc, c->hist, pout, c->vq, c->vx, gin, gout};
+            if (flexible)
+                twogrid<float>(c, nullptr, gout, c->vz, gin, true, false, &fu);
+            else
+                twogrid<double>(c, nullptr, gout, c->vz, nullptr, true, false, &fu);
+            return;
+        }
         tgms::update(c, pout, c->vq, c->vx, c->vg, flexible ? c->vgold : nullptr, flexible ? c->fg : nullptr);
         if (flexible)
             twogrid<float>(c, c->fg, c->vg, c->vz, c->vgold, true, false);
         else
             twogrid<double>(c, c->vg, c->vg, c->vz, nullptr, true, false);
     };
+    double* const gA = c->vg;
+    double* const gB = fused ? c->vg2 : c->vg;
     const bool use_graph = !c->prof && !c->graph_failed;
     if (use_graph && !c->iter_graph) {
         hipGraph_t graph = nullptr;
         bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
         if (ok) {
             try {
-                iteration(c->vp, c->vp1);
-                iteration(c->vp1, c->vp);
+                iteration(c->vp, c->vp1, gA, gB);
+                iteration(c->vp1, c->vp, gB, gA);
             } catch (...) {
                 ok = false;
             }
@@ -679,9 +696,9 @@ void solve_impl(tgms_ctx* c, const double* F, const double* g_bnd, double rtol, 
             for (int l = 0; l < 4; ++l) {
                 c->prof_iter = ++launched;
                 if (launched % 2)
-                    iteration(c->vp, c->vp1);
+                    iteration(c->vp, c->vp1, gA, gB);
                 else
-                    iteration(c->vp1, c->vp);
+                    iteration(c->vp1, c->vp, gB, gA);
             }
         }
         // the last queued iteration's scalars (the next iteration would finalise them)

@@ -171,6 +171,7 @@ struct tgms_ctx {
     double* part = nullptr;   // per-workgroup partial sums of the final gather (3 x NRED)
     double* part2 = nullptr;  // per-workgroup partial sums of p.q (NRED)
     double* vt3 = nullptr;    // z1 after the coarse correction (FP64 preconditioner)
+    double* vg2 = nullptr;    // second residual buffer (residual updates fused into the smoother)
     int nred = 256;           // workgroups of the reducing PCG kernels (autotuned)
     int rpt = 1;              // vertex rows per thread in the tiled PCG kernels (1 or 4; autotuned)
     int smooth_staged = -1;   // smoother: 1 factor staged in LDS, 0 read from global, -1 by LDS fit
@@ -235,6 +236,22 @@ struct tgms_ctx {
 enum { SC_RHO = 0, SC_PQ, SC_ALPHA, SC_BETA, SC_ZN2, SC_REL2, SC_Z02, SC_FLAG, SC_IT, SC_DONE, SC_RTOL2, SC_MAXIT,
        SC_FLEX, SC_RHO_NEW, SC_PENDING, SC_COUNT };
 
+// The PCG update fused into an iteration's first smoothing: with this, the smoother's
+// right-hand side is g = gin - alpha q with alpha = rho' / (sum of the p.q partials),
+// and each patch writes g to gout and x += alpha p on its own block's vertices
+// (workgroup 0 records the scalars, as the separate update kernel would).
+struct FusedUpdate {
+    const double* part;
+    int nred;
+    double* sc;
+    double* hist;
+    const double* p;
+    const double* q;
+    double* x;
+    const double* gin;
+    double* gout;
+};
+
 namespace tgms {
 enum ProfKernel { PK_SMOOTH = 0, PK_APPLYK = 1, PK_RESTRICT = 2, PK_PROLONG = 3, PK_COUNT = 4 };
 // record an event pair around one launch when profiling is on
@@ -264,7 +281,8 @@ void zero(tgms_ctx* c, void* p, size_t bytes);
 void factor_blocks(tgms_ctx* c);
 void factor_patches(tgms_ctx* c);
 template <typename T>
-void smooth_patches(tgms_ctx* c, const T* g, const double* sc);  // local solves of S g into the patch pool
+void smooth_patches(tgms_ctx* c, const T* g, const double* sc,
+                    const struct FusedUpdate* fu = nullptr);  // local solves of S g into the patch pool
 // fused PCG / two-grid kernels (k_pcg.hip); sc: skip when the done flag is set (may be null)
 unsigned pcg_tiles(tgms_ctx* c);
 int nred_max();

@@ -430,8 +430,34 @@ template <typename T, int M1, int M2, bool GENERIC, bool STAGED>
 __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__ rects, const T* __restrict__ Fpool,
                                                         const T* __restrict__ g, int nx, int ny, T* __restrict__ wout,
                                                         T* __restrict__ w4, int bx, int by, int Nx,
-                                                        const double* __restrict__ sc) {
+                                                        const double* __restrict__ sc, FusedUpdate U) {
     if (sc != nullptr && sc[SC_DONE] != 0.0) return;  // PCG already converged
+    double al = 0.0;
+    if (U.gin) {
+        // alpha = rho' / p.q from the partials (the same sums as the separate update kernel)
+        __shared__ double red[4];
+        const int t = threadIdx.x;
+        double v = t < U.nred ? U.part[t] : 0.0;
+        v = wave_sum(v);
+        if ((t & 63) == 0) red[t >> 6] = v;
+        __syncthreads();
+        const double pq = red[0] + red[1] + red[2] + red[3];
+        const double rho = U.sc[SC_RHO_NEW];
+        al = rho / pq;
+        const bool bad = !(pq > 0.0) || !(pq < INFINITY);
+        if (blockIdx.x == 0 && t == 0) {
+            U.sc[SC_RHO] = rho;
+            U.sc[SC_PENDING] = 0.0;
+            U.sc[SC_PQ] = pq;
+            U.sc[SC_ALPHA] = al;
+            U.hist[2 * (int)U.sc[SC_IT]] = al;
+            if (bad) {
+                U.sc[SC_FLAG] = 1.0;
+                U.sc[SC_DONE] = 1.0;
+            }
+        }
+        if (bad) return;
+    }
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sm = reinterpret_cast<T*>(smem_raw);
     const Rect R = rects[blockIdx.x];
@@ -469,12 +495,24 @@ __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__
     // the scale from the staged copy (read once from global memory)
     if constexpr (STAGED) __syncthreads();
     const T* Sg = F + tw_scale(m, mh);
+    const int I = blockIdx.x % Nx, J = blockIdx.x / Nx;
     for (int r = tid; r < n; r += 256) {
-        const int aa = r % m, bb = r / m;
-        vec[r] = Sg[r] * g[(long long)(R.j0 + 1 + bb) * nx + R.i0 + 1 + aa];
+        const int aa = r % m, bb = r / m, i = R.i0 + 1 + aa, j = R.j0 + 1 + bb;
+        const long long v = (long long)j * nx + i;
+        T gv;
+        if (U.gin) {
+            const double gn = U.gin[v] - al * U.q[v];
+            if (i >= I * bx && i < (I + 1) * bx && j >= J * by && j < (J + 1) * by) {
+                U.gout[v] = gn;
+                U.x[v] += al * U.p[v];
+            }
+            gv = T(gn);
+        } else {
+            gv = g[v];
+        }
+        vec[r] = Sg[r] * gv;
     }
     __syncthreads();
-    const int I = blockIdx.x % Nx, J = blockIdx.x / Nx;
     const long long plane = (long long)nx * ny;
     const PatchOut<T> out{wout + R.voff, w4, plane, m, nx, R.i0, R.j0, I * bx, (I + 1) * bx, J * by, (J + 1) * by};
     if constexpr (GENERIC)
@@ -491,18 +529,18 @@ __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__
 #define TGMS_TW_PAIRS(X) X(7, 5) X(9, 7) X(11, 9) X(15, 13) X(19, 17) X(23, 21) X(27, 25) X(31, 29)
 
 template <typename T, int M1, int M2, bool GENERIC, bool STAGED>
-void launch_tw(tgms_ctx* c, const T* L, const T* g, T* w, size_t lds, const double* sc) {
+void launch_tw(tgms_ctx* c, const T* L, const T* g, T* w, size_t lds, const double* sc, const FusedUpdate& U) {
     T* w4 = nullptr;
     if (c->slots) w4 = sizeof(T) == 8 ? (T*)c->patW4 : (T*)c->patW4_32;
     if (c->prof) {
         // events recorded by the dispatch itself (kernel execution only)
         hipEvent_t e1 = tgms::take_event(c), e2 = tgms::take_event(c);
         hipExtLaunchKernelGGL((k_smooth_twisted<T, M1, M2, GENERIC, STAGED>), dim3(c->nblk), dim3(256), lds,
-                              c->stream, e1, e2, 0, c->patch, L, g, c->nx, c->ny, w, w4, c->bx, c->by, c->Nx, sc);
+                              c->stream, e1, e2, 0, c->patch, L, g, c->nx, c->ny, w, w4, c->bx, c->by, c->Nx, sc, U);
         c->prof_rec.push_back({tgms::PK_SMOOTH, c->prof_iter, e1, e2});
     } else {
         hipLaunchKernelGGL((k_smooth_twisted<T, M1, M2, GENERIC, STAGED>), dim3(c->nblk), dim3(256), lds, c->stream,
-                           c->patch, L, g, c->nx, c->ny, w, w4, c->bx, c->by, c->Nx, sc);
+                           c->patch, L, g, c->nx, c->ny, w, w4, c->bx, c->by, c->Nx, sc, U);
     }
 }
 
@@ -510,25 +548,25 @@ void launch_tw(tgms_ctx* c, const T* L, const T* g, T* w, size_t lds, const doub
 // patches have one width, -1 when there are more than two)
 template <typename T>
 void dispatch_twisted(tgms_ctx* c, int m1, int m2, bool staged, const T* L, const T* g, T* w, size_t lds,
-                      const double* sc) {
+                      const double* sc, const FusedUpdate& U) {
     if (staged) {
 #define TGMS_TW_CASE(A, B)                                \
     if (m1 == A && (m2 == B || m2 == A)) {                \
-        launch_tw<T, A, B, false, true>(c, L, g, w, lds, sc); \
+        launch_tw<T, A, B, false, true>(c, L, g, w, lds, sc, U); \
         return;                                           \
     }
         TGMS_TW_PAIRS(TGMS_TW_CASE)
 #undef TGMS_TW_CASE
-        launch_tw<T, 0, 0, true, true>(c, L, g, w, lds, sc);
+        launch_tw<T, 0, 0, true, true>(c, L, g, w, lds, sc, U);
     } else {
 #define TGMS_TW_CASE_D(A, B)                                  \
     if (m1 == A && (m2 == B || m2 == A)) {                    \
-        launch_tw<T, A, B, false, false>(c, L, g, w, lds, sc); \
+        launch_tw<T, A, B, false, false>(c, L, g, w, lds, sc, U); \
         return;                                               \
     }
         TGMS_TW_PAIRS(TGMS_TW_CASE_D)
 #undef TGMS_TW_CASE_D
-        launch_tw<T, 0, 0, true, false>(c, L, g, w, lds, sc);
+        launch_tw<T, 0, 0, true, false>(c, L, g, w, lds, sc, U);
     }
 }
 
@@ -569,7 +607,7 @@ void factor_patches(tgms_ctx* c) {
 
 // local solves of every patch on g into the patch solution pool (patW / patW32)
 template <typename T>
-void smooth_patches(tgms_ctx* c, const T* g, const double* sc) {
+void smooth_patches(tgms_ctx* c, const T* g, const double* sc, const FusedUpdate* fu) {
     const T* L;
     T* w;
     if constexpr (sizeof(T) == 8) {
@@ -581,11 +619,12 @@ void smooth_patches(tgms_ctx* c, const T* g, const double* sc) {
     }
     const size_t work = (size_t)(2 * ((c->pat_nmax + 3) & ~3) + 2 * 64) * sizeof(T);
     const size_t staged = (size_t)((c->pat_fmax + 3) & ~3LL) * sizeof(T) + work;
-    const bool fits = staged <= (size_t)c->lds_max && c->smooth_staged != 0;
-    dispatch_twisted<T>(c, c->pat_m1, c->pat_m2, fits, L, g, w, fits ? staged : work, sc);
+    const bool fits = staged + 64 <= (size_t)c->lds_max && c->smooth_staged != 0;  // + the static scalars
+    const FusedUpdate none{};
+    dispatch_twisted<T>(c, c->pat_m1, c->pat_m2, fits, L, g, w, fits ? staged : work, sc, fu ? *fu : none);
     LAUNCH_OK();
 }
-template void smooth_patches<double>(tgms_ctx*, const double*, const double*);
-template void smooth_patches<float>(tgms_ctx*, const float*, const double*);
+template void smooth_patches<double>(tgms_ctx*, const double*, const double*, const FusedUpdate*);
+template void smooth_patches<float>(tgms_ctx*, const float*, const double*, const FusedUpdate*);
 
 }  // namespace tgms
