@@ -405,7 +405,11 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
             tgms::factor_blocks(c);
             // snapshots + Gram
             c->Psi = c->alloc<double>((size_t)c->nblk * c->ncol * c->nfk);
-            c->APsi = c->alloc<double>((size_t)c->nblk * c->ncol * c->nfk);
+            // A_K Psi for the Gram kernel without matrix cores; the path integrals of the
+            // coarse assembly reuse it (nblk * (bx+1)(by+1) * ncol)
+            const bool gram_mfma = tgms::gram_uses_mfma(c);
+            const size_t nvk = (size_t)(bx + 1) * (by + 1);
+            c->APsi = c->alloc<double>((size_t)c->nblk * c->ncol * (gram_mfma ? nvk : (size_t)c->nfk));
             c->G = c->alloc<double>((size_t)c->nblk * c->ncol * c->ncol);
             tgms::snapshots(c);
             tgms::gram(c);

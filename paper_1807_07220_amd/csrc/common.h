@@ -301,6 +301,7 @@ void gather_final(tgms_ctx* c, const T* w, const T* zin, double* zout, const dou
 // setup (k_setup.hip)
 void snapshots(tgms_ctx* c);
 void gram(tgms_ctx* c);
+inline bool gram_uses_mfma(const tgms_ctx* c) { return c->ncol == 64 || c->ncol == 32; }  // blocks of 16 or 8 cells
 void pencil_eig_q(tgms_ctx* c, double* YQ, const float* Y0, float* Vtop);  // YQ: kept modes times recombination
 void fill_td(tgms_ctx* c, const int* meta, const double* YQ, double* Td);     // coarse basis combinations
 // warm-start network (k_cnn.hip)

@@ -342,6 +342,70 @@ __global__ void k_gram(BlockGeom G, const double* __restrict__ Psi, const double
         for (int s = 0; s < 4; ++s) Gb[(r0 + r) * ncol + c0 + s] = acc[r][s];
 }
 
+// G_K = Psi_K^T A_K Psi_K with FP64 matrix cores (v_mfma_f64_16x16x4): one workgroup
+// of four wavefronts per block.  Chunks of FC faces of Psi and of A_K Psi (A_K applied
+// while staging: the two-point line stencil of the RT0 mass on the block's faces) go
+// to LDS; wavefront w owns NTL*NTL/4 of the 16 x 16 output tiles.  Operand layout of
+// the 16x16x4 instruction: lane l holds A[l%16][l/16] and B[l/16][l%16], and element r
+// of the result is D[4r + l/16][l%16].
+typedef double d4g_t __attribute__((ext_vector_type(4)));
+template <int NTL>
+__global__ void __launch_bounds__(256) k_gram_mfma(BlockGeom G, const double* __restrict__ a,
+                                                   const double* __restrict__ Psi, double* __restrict__ Gout) {
+    constexpr int NC = 16 * NTL, FC = 32, TPW = NTL * NTL / 4;
+    __shared__ double Ps[NC][FC + 1];
+    __shared__ double As[NC][FC + 1];
+    const int blk = blockIdx.x, I = blk % G.Nx, J = blk / G.Nx;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+    const int bxl = G.bx, byl = G.by, nfx = byl * (bxl + 1), nfk = G.nfk;
+    const double* aK = a + (long long)J * byl * G.nx + (long long)I * bxl;
+    const double* P = Psi + (long long)blk * NC * nfk;
+    const double c3 = 1.0 / 3.0, c6 = 1.0 / 6.0;
+    d4g_t acc[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) acc[t] = d4g_t{0.0, 0.0, 0.0, 0.0};
+    for (int f0 = 0; f0 < nfk; f0 += FC) {
+        for (int e = tid; e < NC * FC; e += 256) {
+            const int cc = e / FC, ff = e % FC, f = f0 + ff;
+            double pv = 0.0, av = 0.0;
+            if (f < nfk) {
+                const double* v = P + (long long)cc * nfk;
+                pv = v[f];
+                if (f < nfx) {
+                    const int b = f / (bxl + 1), aa = f % (bxl + 1);
+                    if (aa > 0) av += aK[(long long)b * G.nx + aa - 1] * (pv * c3 + v[f - 1] * c6);
+                    if (aa < bxl) av += aK[(long long)b * G.nx + aa] * (pv * c3 + v[f + 1] * c6);
+                } else {
+                    const int q = f - nfx, b = q / bxl, aa = q % bxl;
+                    if (b > 0) av += aK[(long long)(b - 1) * G.nx + aa] * (pv * c3 + v[f - bxl] * c6);
+                    if (b < byl) av += aK[(long long)b * G.nx + aa] * (pv * c3 + v[f + bxl] * c6);
+                }
+            }
+            Ps[cc][ff] = pv;
+            As[cc][ff] = av;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k4 = 0; k4 < FC; k4 += 4) {
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+                const int id = wave * TPW + t, ti = id / NTL, tj = id % NTL;
+                const double x = Ps[16 * ti + li][k4 + lk];
+                const double y = As[16 * tj + li][k4 + lk];
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc[t], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    double* Gb = Gout + (long long)blk * NC * NC;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        const int id = wave * TPW + t, ti = id / NTL, tj = id % NTL;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Gb[(16 * ti + 4 * r + lk) * NC + 16 * tj + li] = acc[t][r];
+    }
+}
+
 // ---- local spectral problems: one wavefront per coarse face --------------------
 
 // Cyclic Jacobi on the symmetric n x n matrix A (row stride ld, LDS), round-robin
@@ -1020,6 +1084,14 @@ void snapshots(tgms_ctx* c) {
 
 void gram(tgms_ctx* c) {
     BlockGeom G = geom(c);
+    if (gram_uses_mfma(c)) {
+        if (c->ncol == 64)
+            hipLaunchKernelGGL(k_gram_mfma<4>, dim3(c->nblk), dim3(256), 0, c->stream, G, c->a, c->Psi, c->G);
+        else
+            hipLaunchKernelGGL(k_gram_mfma<2>, dim3(c->nblk), dim3(256), 0, c->stream, G, c->a, c->Psi, c->G);
+        LAUNCH_OK();
+        return;
+    }
     hipLaunchKernelGGL(k_apply_AK_cols, dim3(c->nblk, c->ncol), dim3(256), 0, c->stream, G, c->a, c->Psi, c->APsi);
     LAUNCH_OK();
     const int q4 = c->ncol / 4;
