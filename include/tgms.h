@@ -60,7 +60,9 @@ typedef struct {
 
 typedef struct {
     double eta;        /* smoother weight, eq. smooth (paper: 0.2) */
-    int overlap;       /* K_i^+ = K_i enlarged by this many fine cells, clipped to D (paper: 2) */
+    int overlap;       /* K_i^+ = K_i enlarged by this many fine cells, clipped to D (paper: 2);
+                          at least 1: without oversampling the smoother misses the fluxes
+                          across block edges and the preconditioner is singular */
     int precision;     /* 0: FP64 preconditioner and PCG;
                           1: FP32 preconditioner (smoother factors, coarse basis, coarse
                              inverse, inner operator applies) inside a flexible FP64 PCG */
@@ -88,6 +90,8 @@ typedef struct {
     int smoother_staging;  /* -1: chosen by the autotuner (without it: staged where the factor
                               fits in LDS); 0: the patch solves read their factor from global
                               memory; 1: the factor is first staged in LDS */
+    int rows_per_thread;   /* vertex rows per thread in the tiled PCG kernels: 0 chosen by the
+                              autotuner (without it: 1); 1 or 4 */
 } tgms_options;
 
 typedef struct {

@@ -106,6 +106,10 @@ class OracleSolver:
             raise ValueError("permeability must be finite and positive")
         self.kinv = (1.0 / self.kappa).ravel()
         self.eig_tol, self.eta, self.overlap = float(eig_tol), float(eta), int(overlap)
+        if self.overlap < 1:
+            # without oversampling (K_i^+ = K_i) the smoother misses the fine fluxes
+            # across block edges and the two-grid preconditioner is singular on ker B
+            raise ValueError("overlap must be at least 1 (oversampled smoother domains)")
         self.A = mass_matrix(g, self.kinv).tocsr()
         self.B = div_matrix(g).tocsr()
         self.mask = g.interior.astype(np.float64)

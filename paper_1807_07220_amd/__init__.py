@@ -37,7 +37,7 @@ class Solver:
                  precision: str = "fp64", s_scale: float = 0.0, stream: torch.cuda.Stream | None = None,
                  graphs: bool = True, autotune: bool = True, tune_cache: str | None = None,
                  warm_start: str = "exact", cnn_weights: torch.Tensor | None = None, rq_tol: float = 1e-6,
-                 smoother_staging: int = -1):
+                 smoother_staging: int = -1, rows_per_thread: int = 0):
         lib = load()
         if kappa.dim() != 2:
             raise ValueError("kappa must be (ny, nx)")
@@ -61,6 +61,7 @@ class Solver:
             opt.cnn_weights = ctypes.c_void_p(cnn_weights.data_ptr())
         opt.rq_tol = float(rq_tol)
         opt.smoother_staging = int(smoother_staging)
+        opt.rows_per_thread = int(rows_per_thread)
         grid = Grid(self.nx, self.ny, self.bx, self.by)
         handle = ctypes.c_void_p()
         kappa = kappa.contiguous()

@@ -33,7 +33,7 @@ class Options(ctypes.Structure):
     _fields_ = [("eta", c_double), ("overlap", c_int), ("precision", c_int), ("s_scale", c_double),
                 ("stream", c_void_p), ("graphs", c_int), ("autotune", c_int), ("tune_cache", c_char_p),
                 ("warm_start", c_int), ("cnn_weights", c_void_p), ("rq_tol", c_double),
-                ("smoother_staging", c_int)]
+                ("smoother_staging", c_int), ("rows_per_thread", c_int)]
 
 
 class Info(ctypes.Structure):

@@ -303,7 +303,11 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
     const int nx = grid->nx, ny = grid->ny, bx = grid->bx, by = grid->by;
     if (nx <= 0 || ny <= 0 || bx <= 0 || by <= 0 || nx % bx || ny % by)
         throw TgmsError{TGMS_E_INVAL, "grid sizes must be positive and divisible by the block size"};
-    if (!(eig_tol > 0) || !(o.eta > 0) || o.overlap < 0) throw TgmsError{TGMS_E_INVAL, "bad tolerance, eta or overlap"};
+    if (!(eig_tol > 0) || !(o.eta > 0)) throw TgmsError{TGMS_E_INVAL, "bad tolerance or eta"};
+    // Without oversampling the smoother never touches the fine fluxes across block
+    // edges; the coarse space spans only part of them, so the two-grid preconditioner
+    // is singular on the divergence-free fields and PCG stops at a wrong solution.
+    if (o.overlap < 1) throw TgmsError{TGMS_E_INVAL, "overlap must be at least 1"};
     if (bx < 3 || by < 3 || nx / bx < 2 || ny / by < 2)
         throw TgmsError{TGMS_E_UNSUPPORTED, "need blocks of at least 3x3 cells and at least 2x2 blocks"};
     if (o.overlap >= std::min(bx, by)) throw TgmsError{TGMS_E_UNSUPPORTED, "overlap must be smaller than a block"};
@@ -312,6 +316,8 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
     if (ex > 33) throw TgmsError{TGMS_E_UNSUPPORTED, "smoother patches wider than 33 cells"};
     (void)ey;
     if (o.warm_start < 0 || o.warm_start > 2) throw TgmsError{TGMS_E_INVAL, "warm_start must be 0, 1 or 2"};
+    if (o.rows_per_thread != 0 && o.rows_per_thread != 1 && o.rows_per_thread != 4)
+        throw TgmsError{TGMS_E_INVAL, "rows_per_thread must be 0, 1 or 4"};
     if (o.warm_start == 2) {
         if (!o.cnn_weights) throw TgmsError{TGMS_E_INVAL, "warm_start 2 needs cnn_weights"};
         if (bx != by || !tgms::cnn_shape_ok(2 * bx, bx))
@@ -554,6 +560,7 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         HIP_OK(hipHostMalloc((void**)&c->red_h, SC_COUNT * sizeof(double), hipHostMallocDefault));
         if (o.autotune) tgms::autotune(c, o.tune_cache);
         if (o.smoother_staging >= 0) c->smooth_staged = o.smoother_staging ? 1 : 0;
+        if (o.rows_per_thread == 1 || o.rows_per_thread == 4) c->rpt = o.rows_per_thread;
         HIP_OK(hipStreamSynchronize(c->stream));
         c->t_setup_ms = total.ms();
         *out = c;
@@ -637,29 +644,20 @@ void solve_impl(tgms_ctx* c, const double* F, const double* g_bnd, double rtol, 
     } else {
         twogrid<double>(c, c->vg, c->vg, c->vz, nullptr, true, true);
     }
-    // With overlapping patches (every vertex of a block lies inside its patch) the
-    // update x += alpha p, g -= alpha q runs inside the first smoothing, which reads g
-    // from one buffer and writes the new g to the other (gin / gout alternate with the
+    // Every vertex of a block lies inside its own (oversampled) patch, so the update
+    // x += alpha p, g -= alpha q runs inside the first smoothing, which reads g from
+    // one buffer and writes the new g to the other (gin / gout alternate with the
     // search direction; gin is also the old residual the flexible beta needs).
-    const bool fused = c->overlap >= 1;
     auto iteration = [&](const double* pin, double* pout, double* gin, double* gout) {
         tgms::dir_apply(c, c->vz, pin, pout, c->vq);
-        if (fused) {
-            const FusedUpdate fu{c->part2, c->nred, c->sc, c->hist, pout, c->vq, c->vx, gin, gout};
-            if (flexible)
-                twogrid<float>(c, nullptr, gout, c->vz, gin, true, false, &fu);
-            else
-                twogrid<double>(c, nullptr, gout, c->vz, nullptr, true, false, &fu);
-            return;
-        }
-        tgms::update(c, pout, c->vq, c->vx, c->vg, flexible ? c->vgold : nullptr, flexible ? c->fg : nullptr);
+        const FusedUpdate fu{c->part2, c->nred, c->sc, c->hist, pout, c->vq, c->vx, gin, gout};
         if (flexible)
-            twogrid<float>(c, c->fg, c->vg, c->vz, c->vgold, true, false);
+            twogrid<float>(c, nullptr, gout, c->vz, gin, true, false, &fu);
         else
-            twogrid<double>(c, c->vg, c->vg, c->vz, nullptr, true, false);
+            twogrid<double>(c, nullptr, gout, c->vz, nullptr, true, false, &fu);
     };
     double* const gA = c->vg;
-    double* const gB = fused ? c->vg2 : c->vg;
+    double* const gB = c->vg2;
     const bool use_graph = !c->prof && !c->graph_failed;
     if (use_graph && !c->iter_graph) {
         hipGraph_t graph = nullptr;
@@ -772,6 +770,7 @@ void tgms_default_options(tgms_options* opt) {
     opt->cnn_weights = nullptr;
     opt->rq_tol = 1e-6;
     opt->smoother_staging = -1;
+    opt->rows_per_thread = 0;
 }
 
 tgms_status tgms_setup(const tgms_grid* grid, const double* kappa, double eig_tol, const tgms_options* opt,

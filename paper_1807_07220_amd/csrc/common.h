@@ -288,7 +288,6 @@ unsigned pcg_tiles(tgms_ctx* c);
 int nred_max();
 void autotune(tgms_ctx* c, const char* cache_path);  // picks nred, smoother staging (k_tune.hip)
 void dir_apply(tgms_ctx* c, const double* z, const double* pin, double* pout, double* q);
-void update(tgms_ctx* c, const double* p, const double* q, double* x, double* g, double* gold, float* g32);
 void finalize(tgms_ctx* c, bool first);  // scalars from pending gather partials (first: rho_0, |z_0|^2)
 void allow_fused_lds(tgms_ctx* c);      // LDS limit of the per-block fused kernels (large blocks)
 template <typename T>

@@ -4,8 +4,8 @@
 // One PCG iteration in stream-function coordinates is 9 kernels:
 //   [finalise the last iteration: rho' = g.z, beta, |C z|^2 test]
 //   p = z + beta p;  q = K p;  partial p.q                        (k_dir_apply)
-//   alpha = rho / p.q;  x += alpha p;  g -= alpha q               (k_update)
-//   z = B_TG g: smoother; z1 = eta sum ext(w), t = g - K z1 and the
+//   z = B_TG g: alpha = rho / p.q, x += alpha p and g -= alpha q inside the
+//   first smoothing; z1 = eta sum ext(w), t = g - K z1 and the
 //   block restriction W_b^T t (k_gather_res_restrict); coarse accumulation and
 //   the two triangular products; z1' = z1 + W c, t = g - K z1'
 //   (k_prolong_residual); smoother; z = z1' + eta sum ext(w) with the partials of
@@ -15,7 +15,7 @@
 // or by k_finalize where the host needs the scalars (after the first
 // preconditioning and at the end of each group of queued iterations).  A
 // "pending" flag in sc tells which: set by k_gather_final, cleared by k_finalize
-// or by k_update (the kernel after the one that finalised), so that no
+// or by the first smoothing (the kernel after the one that finalised), so that no
 // workgroup reads a scalar another workgroup of the same kernel writes.
 // The reducing kernels run on a fixed grid of nred <= NRED workgroups (chosen by
 // the autotuner) that loop over the tiles and write one partial each; the
@@ -172,61 +172,6 @@ __global__ void __launch_bounds__(NT) k_dir_apply(const double* __restrict__ z, 
     }
     group_sum<1>(v);
     if (tid == 0) part[blockIdx.x] = v[0];
-}
-
-// alpha = rho / (p . q) from the partials of k_dir_apply (every workgroup forms it;
-// workgroup 0 records it, moves rho' into rho and clears the pending flag), then
-// x += alpha p ; gold = g (flexible) ; g -= alpha q ; g32 = (float) g (mixed
-// precision).  A non-positive p . q stops the iteration.
-__global__ void __launch_bounds__(NT) k_update(long long n, double* __restrict__ sc, double* __restrict__ hist,
-                                               const double* __restrict__ part, int nred, const double* __restrict__ p,
-                                               const double* __restrict__ q, double* __restrict__ x,
-                                               double* __restrict__ g, double* __restrict__ gold,
-                                               float* __restrict__ g32) {
-    if (finished(sc)) return;
-    const double pq = sum_partials(part, 0, nred);
-    const double rho = sc[SC_RHO_NEW];
-    const double al = rho / pq;
-    const bool bad = !(pq > 0.0) || !(pq < INFINITY);
-    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
-    if (blockIdx.x == 0 && tid == 0) {
-        sc[SC_RHO] = rho;
-        sc[SC_PENDING] = 0.0;
-        sc[SC_PQ] = pq;
-        sc[SC_ALPHA] = al;
-        hist[2 * (int)sc[SC_IT]] = al;
-        if (bad) {
-            sc[SC_FLAG] = 1.0;
-            sc[SC_DONE] = 1.0;
-        }
-    }
-    if (bad) return;
-    // four independent vertices per thread and pass (their loads in flight together)
-    const long long stride = (long long)gridDim.x * NT;
-    for (long long t0 = blockIdx.x * (long long)NT + tid; t0 < n; t0 += 4 * stride) {
-        double xv[4], pv[4], gv[4], qv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const long long t = t0 + u * stride;
-            if (t < n) {
-                xv[u] = x[t];
-                pv[u] = p[t];
-                gv[u] = g[t];
-                qv[u] = q[t];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const long long t = t0 + u * stride;
-            if (t < n) {
-                x[t] = xv[u] + al * pv[u];
-                if (gold) gold[t] = gv[u];
-                const double gn = gv[u] - al * qv[u];
-                g[t] = gn;
-                if (g32) g32[t] = (float)gn;
-            }
-        }
-    }
 }
 
 // eta * (sum of the patch solutions covering vertex (i, j)), in fixed patch order
@@ -556,13 +501,6 @@ void dir_apply(tgms_ctx* c, const double* z, const double* pin, double* pout, do
         hipLaunchKernelGGL(k_dir_apply<1>, dim3(c->nred), dim3(TX, TY), 0, c->stream, z, pin, pout, q,
                            (const double*)c->a, c->nx, c->ny, c->sx * c->sx, c->sy * c->sy, c->sc, c->hist,
                            (const double*)c->part, c->nred, c->part2);
-    LAUNCH_OK();
-}
-
-void update(tgms_ctx* c, const double* p, const double* q, double* x, double* g, double* gold, float* g32) {
-    const long long n = (long long)c->nx * c->ny;
-    hipLaunchKernelGGL(k_update, dim3(c->nred), dim3(TX, TY), 0, c->stream, n, c->sc, c->hist, (const double*)c->part2,
-                       c->nred, p, q, x, g, gold, g32);
     LAUNCH_OK();
 }
 

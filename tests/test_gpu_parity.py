@@ -311,3 +311,58 @@ def test_autotune_cache(tmp_path):
         r = s.solve(dev(F), rtol=1e-10)
         assert abs(r["iters"] - ro["iters"]) <= 1
         assert np.linalg.norm(host(r["u"]) - ro["u"]) <= 1e-10 * np.linalg.norm(ro["u"])
+
+
+@pytest.mark.parametrize("staging,rpt", [(0, 1), (1, 1), (0, 4), (1, 4)])
+def test_launch_variants_match_oracle(staging, rpt):
+    """Every launch variant the autotuner can pick (smoother factor read from global
+    memory or staged in LDS; one or four vertex rows per thread in the tiled PCG
+    kernels) gives the oracle's preconditioner and solution."""
+    import paper_1807_07220_amd as tg
+    nx, ny, bx, by, gen, tol = CASES["chan64"]
+    kappa = gen()
+    register("chan64", kappa)
+    o = oracle_for(nx, ny, bx, by, "chan64", tol)
+    s = tg.Solver(dev(kappa), bx, by, tol, autotune=False, smoother_staging=staging, rows_per_thread=rpt)
+    inf = s.info()
+    assert inf["smooth_staged"] == staging and inf["rows_per_thread"] == rpt
+    r = np.random.default_rng(3).standard_normal(o.g.nf) * o.mask
+    for which in ("smoother", "twogrid"):
+        z = host(s.apply_precond(which, dev(r)))
+        zo = o.smooth(r) if which == "smoother" else o.twogrid(r)
+        assert rel(z * o.mask, zo) <= PROBE_TOL["chan64"]
+    F = fields.corner_source(nx, ny).ravel()
+    res, ro = s.solve(dev(F), rtol=1e-10), o.solve(F, rtol=1e-10)
+    assert abs(res["iters"] - ro["iters"]) <= 1
+    assert np.linalg.norm(host(res["u"]) - ro["u"]) <= 1e-10 * np.linalg.norm(ro["u"])
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_overlap_one_matches_oracle(precision):
+    """Overlap 1 (patch widths without a fixed-width smoother kernel) against the
+    oracle with the same overlap; mixed precision takes the flexible update."""
+    import paper_1807_07220_amd as tg
+    from oracle import Grid2D, OracleSolver
+    nx, ny, bx, by = 48, 40, 8, 8
+    kappa = fields.field_channelized(nx, ny, 17, contrast=1e4)
+    o = OracleSolver(Grid2D(nx, ny, bx, by), kappa, 1.0, overlap=1)
+    s = tg.Solver(dev(kappa), bx, by, 1.0, overlap=1, precision=precision)
+    F = fields.random_source(nx, ny, 5).ravel()
+    res, ro = s.solve(dev(F), rtol=1e-10), o.solve(F, rtol=1e-10)
+    assert res["converged"] and ro["iters"] > 20
+    if precision == "fp64":
+        r = np.random.default_rng(4).standard_normal(o.g.nf) * o.mask
+        z = host(s.apply_precond("twogrid", dev(r)))
+        assert rel(z * o.mask, o.twogrid(r)) <= 1e-9
+        assert abs(res["iters"] - ro["iters"]) <= 1
+        assert np.linalg.norm(host(res["u"]) - ro["u"]) <= 1e-10 * np.linalg.norm(ro["u"])
+    else:
+        assert np.linalg.norm(host(res["u"]) - ro["u"]) <= 1e-8 * np.linalg.norm(ro["u"])
+    s.close()
+
+
+def test_overlap_zero_rejected():
+    import paper_1807_07220_amd as tg
+    with pytest.raises(tg.TgmsError):
+        tg.Solver(dev(np.ones((32, 32))), 8, 8, 0.5, overlap=0)

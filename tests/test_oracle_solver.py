@@ -167,3 +167,16 @@ def test_mobility_update_reaches_exact_solution_of_new_operator():
     # the coarse space is the one built for kappa: counts unchanged
     o0 = OracleSolver(g, kappa, 0.5)
     assert np.array_equal(o.counts, o0.counts)
+
+
+def test_overlap_one_reaches_exact_solution_and_zero_is_refused():
+    """Overlap 1 (the smallest oversampling) still converges to the direct solution;
+    overlap 0 (K_i^+ = K_i) is refused: there the smoother never changes the fine
+    fluxes across block edges and the two-grid operator is singular on ker B."""
+    g, kappa, o = _small(n=24, b=6, tol=0.5, overlap=1)
+    F = fields.random_source(g.nx, g.ny, 6).ravel()
+    res = o.solve(F, rtol=1e-13, maxit=300)
+    u, _ = exact_solve(g, kappa, F)
+    assert np.linalg.norm(res["u"] - u) <= 1e-10 * np.linalg.norm(u)
+    with pytest.raises(ValueError):
+        OracleSolver(g, kappa, 0.5, overlap=0)
