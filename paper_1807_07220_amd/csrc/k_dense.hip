@@ -270,6 +270,9 @@ void gemm(tgms_ctx* c, int transA, int transB, int M, int N, int K, double alpha
 static void dense_inverse_enqueue(tgms_ctx* c, double* A, int n, const DenseInvWork& w) {
     const int nblk = (n + TB - 1) / TB;
     double* Dinv = w.Dinv;
+    // the recursion multiplies whole square blocks of X, whose parts above the
+    // diagonal it never writes: they must be zero
+    zero(c, w.X, sizeof(double) * (size_t)n * n);
     for (int kb0 = 0; kb0 < nblk; ++kb0) {
         const int k0 = kb0 * TB, kb = std::min(TB, n - k0), k1 = k0 + kb;
         hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(NT), 0, c->stream, A, n, k0, kb, Dinv + (size_t)kb0 * TB * TB,

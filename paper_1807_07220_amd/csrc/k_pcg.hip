@@ -466,7 +466,10 @@ __global__ void __launch_bounds__(NT) k_finalize(double* __restrict__ sc, double
         sc[SC_FLAG] = 0.0;
         sc[SC_BETA] = 0.0;
         sc[SC_PENDING] = 0.0;
-        sc[SC_DONE] = (zn2 > 0.0 && sc[SC_MAXIT] > 0.0) ? 0.0 : 1.0;
+        // a non-finite preconditioned residual is a breakdown, not convergence
+        const bool finite = zn2 < INFINITY && gz == gz;
+        sc[SC_FLAG] = finite ? 0.0 : 1.0;
+        sc[SC_DONE] = (finite && zn2 > 0.0 && sc[SC_MAXIT] > 0.0) ? 0.0 : 1.0;
         return;
     }
     if (sc[SC_PENDING] == 0.0) return;

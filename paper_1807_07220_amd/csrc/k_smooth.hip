@@ -434,7 +434,7 @@ __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__
     if (sc != nullptr && sc[SC_DONE] != 0.0) return;  // PCG already converged
     double al = 0.0;
     if (U.gin) {
-        // alpha = rho' / p.q from the partials (the same sums as the separate update kernel)
+        // alpha = rho' / p.q from the partials of k_dir_apply (every workgroup forms it)
         __shared__ double red[4];
         const int t = threadIdx.x;
         double v = t < U.nred ? U.part[t] : 0.0;

@@ -126,3 +126,30 @@ def test_mixed_solve_256_iterations():
     finally:
         s64.close()
         sm.close()
+
+
+def test_setups_in_sequence_are_independent():
+    """Contexts created one after another in a process (FP64, mixed, FP64 again) give
+    the same preprocessing and solve: a later setup must not depend on what earlier
+    contexts left in memory they freed (the coarse RT0 inverse's workspace once did)."""
+    import paper_1807_07220_amd as tg
+    w = configs.get("darcy2d_256_b16")
+    kappa, F = w.make_inputs()
+    out = []
+    for prec in ("fp64", "mixed", "fp64", "mixed", "fp64"):
+        s = tg.Solver(dev(kappa), w.bx, w.by, w.eig_tol, precision=prec)
+        try:
+            vb = host(s.preprocess(dev(F)))
+            r = s.solve(dev(F), rtol=w.rtol)
+            out.append((prec, vb, r["iters"], r["converged"], host(r["u"])))
+        finally:
+            s.close()
+    assert all(np.isfinite(o[1]).all() and o[3] for o in out)
+    ref = out[0]
+    for prec, vb, it, _, u in out[1:]:
+        assert np.array_equal(vb, ref[1])
+        if prec == "fp64":
+            assert it == ref[2] and np.array_equal(u, ref[4])
+        else:
+            assert it <= int(1.25 * ref[2]) + 2
+            assert np.linalg.norm(u - ref[4]) <= 1e-6 * np.linalg.norm(ref[4])
