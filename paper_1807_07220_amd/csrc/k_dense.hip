@@ -91,69 +91,71 @@ __global__ void __launch_bounds__(NT) k_gemm(int transA, int transB, int M, int 
 
 // Cholesky of the kb x kb diagonal block at (k0, k0) in place, and its inverse into Dinv (kb x kb, ld 64).
 // Thread (ty, tx) owns rows ty + 16 r and columns tx + 16 s of the 64 x 64 tile.
+//
+// One right-looking sweep forms both, with one barrier per pivot: with d_j the
+// pivot and m_ij = S[i][j] / d_j (the unit lower factor, A = Lu diag(d) Lu^T), step j
+// updates the trailing lower triangle S[i][k] -= m_ij S[k][j] (j < k <= i) and the
+// rows below j of U (U = I at the start, Lu^{-1} at the end) U[i][c] -= m_ij U[j][c]
+// (c <= j).  Column j of S and row j of U are final when step j reads them, and step
+// j writes neither, so the reads and writes of one step do not overlap.  Then
+// L = Lu diag(d)^{1/2} and L^{-1} = diag(d)^{-1/2} U.  (The 64 dependent steps bound
+// the kernel: keeping the tiles in registers and publishing one column per step
+// through LDS measured slower.)
 __global__ void __launch_bounds__(NT) k_potrf_diag(double* __restrict__ A, int lda, int k0, int kb,
                                                    double* __restrict__ Dinv, int* __restrict__ fail) {
     __shared__ double S[TB][TB + 1];
-    __shared__ double X[TB][TB + 1];
+    __shared__ double U[TB][TB + 1];
     const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
     for (int r = 0; r < 4; ++r)
         for (int q = 0; q < 4; ++q) {
             const int i = ty + 16 * r, j = tx + 16 * q;
             S[i][j] = (i < kb && j < kb && j <= i) ? A[(long long)(k0 + i) * lda + k0 + j] : (i == j ? 1.0 : 0.0);
+            U[i][j] = i == j ? 1.0 : 0.0;
         }
     __syncthreads();
     for (int j = 0; j < kb; ++j) {
         const double d = S[j][j];
-        if (!(d > 0.0)) {
+        if (!(d > 0.0)) {  // every thread reads the same pivot: all leave together
             if (tid == 0) atomicOr(fail, 1);
             return;
         }
-        const double inv = 1.0 / sqrt(d);
-        __syncthreads();
-        if (tid < TB && tid >= j) S[tid][j] = (tid == j) ? d * inv : S[tid][j] * inv;
-        __syncthreads();
+        const double rd = 1.0 / d;
+        double skj[4], ujk[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = tx + 16 * q;
+            skj[q] = S[k][j];
+            ujk[q] = U[j][k];
+        }
+#pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int i = ty + 16 * r;
-            if (i <= j) continue;
-            const double lij = S[i][j];
+            if (i <= j || i >= kb) continue;
+            const double mij = S[i][j] * rd;
+#pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int k = tx + 16 * q;
-                if (k > j && k <= i) S[i][k] -= lij * S[k][j];
+                if (k > j && k <= i) S[i][k] -= mij * skj[q];
+                if (k <= j) U[i][k] -= mij * ujk[q];
             }
         }
         __syncthreads();
     }
-    // X = L^{-1} by a right-looking sweep over the pivots k: with R[i][k] = L[i][k] / L[k][k],
-    // U <- U - R[:, k] U[k, :] (rows below k), then X = diag(L)^{-1} U.  One barrier per pivot.
-    for (int r = 0; r < 4; ++r)
-        for (int q = 0; q < 4; ++q) {
-            const int i = ty + 16 * r, j = tx + 16 * q;
-            X[i][j] = (i == j) ? 1.0 : 0.0;
-        }
-    __syncthreads();
-    for (int k = 0; k < kb; ++k) {
-        for (int r = 0; r < 4; ++r) {
-            const int i = ty + 16 * r;
-            if (i <= k || i >= kb) continue;
-            const double rik = S[i][k] / S[k][k];
-            for (int q = 0; q < 4; ++q) {
-                const int j = tx + 16 * q;
-                if (j <= k) X[i][j] -= rik * X[k][j];
-            }
-        }
-        __syncthreads();
+    double si[4], sk[4];  // sqrt(d) of the owned rows and columns
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = ty + 16 * r, k = tx + 16 * r;
+        si[r] = i < kb ? sqrt(S[i][i]) : 1.0;
+        sk[r] = k < kb ? sqrt(S[k][k]) : 1.0;
     }
+#pragma unroll
     for (int r = 0; r < 4; ++r)
+#pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int i = ty + 16 * r, j = tx + 16 * q;
-            X[i][j] = (i < kb && j <= i) ? X[i][j] / S[i][i] : 0.0;
-        }
-    __syncthreads();
-    for (int r = 0; r < 4; ++r)
-        for (int q = 0; q < 4; ++q) {
-            const int i = ty + 16 * r, j = tx + 16 * q;
-            if (i < kb && j < kb && j <= i) A[(long long)(k0 + i) * lda + k0 + j] = S[i][j];
-            Dinv[i * TB + j] = (i < kb && j < kb) ? X[i][j] : 0.0;
+            const int i = ty + 16 * r, k = tx + 16 * q;
+            const bool in = i < kb && k < kb && k <= i;
+            if (in) A[(long long)(k0 + i) * lda + k0 + k] = (k == i) ? si[r] : S[i][k] / sk[q];
+            Dinv[i * TB + k] = in ? U[i][k] / si[r] : 0.0;
         }
 }
 

@@ -366,3 +366,20 @@ def test_overlap_zero_rejected():
     import paper_1807_07220_amd as tg
     with pytest.raises(tg.TgmsError):
         tg.Solver(dev(np.ones((32, 32))), 8, 8, 0.5, overlap=0)
+
+
+@pytest.mark.parametrize("staging", [0, 1])
+def test_mixed_smoother_modes_match_oracle(staging):
+    """The FP32 smoother with its factor read from global memory or staged in LDS
+    keeps the mixed-precision solution within 1e-8 of the FP64 oracle's."""
+    import paper_1807_07220_amd as tg
+    nx, ny, bx, by, gen, tol = CASES["chan64"]
+    kappa = gen()
+    register("chan64", kappa)
+    o = oracle_for(nx, ny, bx, by, "chan64", tol)
+    s = tg.Solver(dev(kappa), bx, by, tol, precision="mixed", autotune=False, smoother_staging=staging)
+    F = fields.corner_source(nx, ny).ravel()
+    res, ro = s.solve(dev(F), rtol=1e-10), o.solve(F, rtol=1e-10)
+    assert res["converged"]
+    assert np.linalg.norm(host(res["u"]) - ro["u"]) <= 1e-8 * np.linalg.norm(ro["u"])
+    s.close()
