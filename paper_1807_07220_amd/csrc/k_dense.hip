@@ -8,6 +8,9 @@
 //     B = tril(X) + triu(X^T, 1),
 // so A^{-1} g = X^T (X g) costs two triangular matrix-vector products that
 // each stream one triangle of B row by row.
+#include <functional>
+#include <vector>
+
 #include "common.h"
 
 namespace {
@@ -23,11 +26,9 @@ constexpr int NT = 256;  // threads (16 x 16), 4 x 4 outputs each
 // holds A[l%16][l/16] and B[l/16][l%16]; result element r of lane l is D[4*r + l/16][l%16].
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(NT) k_gemm(int transA, int transB, int M, int N, int K, double alpha,
-                                             const double* __restrict__ A, int lda, const double* __restrict__ B,
-                                             int ldb, double beta, double* C, int ldc, int lower_only) {
-    const int tm = blockIdx.y, tn = blockIdx.x;
-    if (lower_only && tm < tn) return;
+__device__ inline void gemm_tile(int tm, int tn, int transA, int transB, int M, int N, int K, double alpha,
+                                 const double* __restrict__ A, int lda, const double* __restrict__ B, int ldb,
+                                 double beta, double* C, int ldc) {
     __shared__ double As[TK][TB + 1];
     __shared__ double Bs[TK][TB + 1];
     const int tid = threadIdx.x;
@@ -87,6 +88,50 @@ __global__ void __launch_bounds__(NT) k_gemm(int transA, int transB, int M, int 
                 double* cp = C + (long long)gm * ldc + gn;
                 *cp = alpha * acc[a][b][r] + (beta == 0.0 ? 0.0 : beta * *cp);
             }
+}
+
+__global__ void __launch_bounds__(NT) k_gemm(int transA, int transB, int M, int N, int K, double alpha,
+                                             const double* __restrict__ A, int lda, const double* __restrict__ B,
+                                             int ldb, double beta, double* C, int ldc, int lower_only) {
+    const int tm = blockIdx.y, tn = blockIdx.x;
+    if (lower_only && tm < tn) return;
+    gemm_tile(tm, tn, transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+// One level of the recursive inversion X = L^{-1} (n x n, row-major): for every node
+// [o, o + n1 + n2) of the level, with X11 and X22 already formed,
+//   step 0:  T = L21 X11          (n2 x n1, at Tm + toff, ld n1)
+//   step 1:  X21 = -X22 T
+// the nodes of a level are disjoint, so one launch covers all of them (blockIdx.z).
+constexpr int LEVEL_MAX = 64;
+struct InvLevel {
+    int count;
+    int o[LEVEL_MAX], n1[LEVEL_MAX], n2[LEVEL_MAX];
+    long long toff[LEVEL_MAX];
+};
+
+__global__ void __launch_bounds__(NT) k_inv_level(InvLevel lv, int step, const double* __restrict__ L,
+                                                  double* __restrict__ X, double* __restrict__ Tm, int n) {
+    const int z = blockIdx.z;
+    const int o = lv.o[z], n1 = lv.n1[z], n2 = lv.n2[z];
+    const int tm = blockIdx.y, tn = blockIdx.x;
+    if (tm * TB >= n2 || tn * TB >= n1) return;  // tiles beyond this node's output
+    double* T = Tm + lv.toff[z];
+    if (step == 0)
+        gemm_tile(tm, tn, 0, 0, n2, n1, n1, 1.0, L + (long long)(o + n1) * n + o, n, X + (long long)o * n + o, n, 0.0,
+                  T, n1);
+    else
+        gemm_tile(tm, tn, 0, 0, n2, n1, n2, -1.0, X + (long long)(o + n1) * n + o + n1, n, T, n1, 0.0,
+                  X + (long long)(o + n1) * n + o, n);
+}
+
+// the inverses of the diagonal blocks (Dinv, [block][64][64]) into the diagonal of X
+__global__ void k_copy_diag_blocks(const double* __restrict__ Dinv, double* __restrict__ X, int n) {
+    const int b = blockIdx.x, o = b * TB, len = min(TB, n - o);
+    for (int e = threadIdx.x; e < len * len; e += blockDim.x) {
+        const int i = e / len, j = e % len;
+        X[(long long)(o + i) * n + o + j] = Dinv[(long long)b * TB * TB + i * TB + j];
+    }
 }
 
 // Cholesky of the kb x kb diagonal block at (k0, k0) in place, and its inverse into Dinv (kb x kb, ld 64).
@@ -165,14 +210,6 @@ __global__ void k_pack_inverse(const double* __restrict__ X, double* __restrict_
     if (e >= (long long)n * n) return;
     int i = (int)(e / n), j = (int)(e % n);
     B[e] = (j <= i) ? X[e] : X[(long long)j * n + i];
-}
-
-__global__ void k_copy_block(const double* __restrict__ src, int lds, double* __restrict__ dst, int ldd, int rows,
-                             int cols) {
-    long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (e >= (long long)rows * cols) return;
-    int i = (int)(e / cols), j = (int)(e % cols);
-    dst[(long long)i * ldd + j] = src[(long long)i * lds + j];
 }
 
 template <typename T>
@@ -299,31 +336,54 @@ static void dense_inverse_enqueue(tgms_ctx* c, double* A, int n, const DenseInvW
             LAUNCH_OK();
         }
     }
-    struct Rec {
-        tgms_ctx* c;
-        double* A;
-        double* X;
-        double* Tm;
-        double* Dinv;
-        int n;
-        void run(int o, int len) {  // block [o, o+len) of L, o and len multiples of 64 except the last
-            if (len <= TB) {
-                hipLaunchKernelGGL(k_copy_block, dim3(nb((long long)len * len)), dim3(256), 0, c->stream,
-                                   (const double*)(Dinv + (size_t)(o / TB) * TB * TB), TB, X + (size_t)o * n + o, n,
-                                   len, len);
+    // X = L^{-1} by recursive halving, [L11 0; L21 L22]^{-1} = [X11 0; -X22 L21 X11, X22]:
+    // the 64 x 64 leaves are the diagonal-block inverses of the factorisation; the
+    // internal nodes are grouped by height (children first) and each group is two
+    // batched launches of square MFMA GEMMs
+    hipLaunchKernelGGL(k_copy_diag_blocks, dim3(nblk), dim3(256), 0, c->stream, (const double*)Dinv, w.X, n);
+    LAUNCH_OK();
+    struct Node {
+        int o, n1, n2, height;
+    };
+    std::vector<Node> nodes;
+    std::function<int(int, int)> build = [&](int o, int len) -> int {
+        if (len <= TB) return 0;
+        const int n1 = ((len / TB + 1) / 2) * TB, n2 = len - n1;
+        const int h = 1 + std::max(build(o, n1), build(o + n1, n2));
+        nodes.push_back(Node{o, n1, n2, h});
+        return h;
+    };
+    const int hmax = build(0, n);
+    for (int h = 1; h <= hmax; ++h) {
+        InvLevel lv{};
+        long long toff = 0;
+        int mx1 = 0, mx2 = 0;
+        auto flush = [&]() {
+            if (lv.count == 0) return;
+            const dim3 grid((mx1 + TB - 1) / TB, (mx2 + TB - 1) / TB, lv.count);
+            for (int step = 0; step < 2; ++step) {
+                hipLaunchKernelGGL(k_inv_level, grid, dim3(NT), 0, c->stream, lv, step, (const double*)A, w.X, w.Tm,
+                                   n);
                 LAUNCH_OK();
-                return;
             }
-            const int n1 = ((len / TB + 1) / 2) * TB, n2 = len - n1;
-            run(o, n1);
-            run(o + n1, n2);
-            // Tm (n2 x n1) = L21 X11 ; X21 = -X22 Tm
-            gemm(c, 0, 0, n2, n1, n1, 1.0, A + (size_t)(o + n1) * n + o, n, X + (size_t)o * n + o, n, 0.0, Tm, n1);
-            gemm(c, 0, 0, n2, n1, n2, -1.0, X + (size_t)(o + n1) * n + o + n1, n, Tm, n1, 0.0,
-                 X + (size_t)(o + n1) * n + o, n);
+            lv.count = 0;
+            toff = 0;
+            mx1 = mx2 = 0;
+        };
+        for (const Node& nd : nodes) {
+            if (nd.height != h) continue;
+            if (lv.count == LEVEL_MAX) flush();
+            lv.o[lv.count] = nd.o;
+            lv.n1[lv.count] = nd.n1;
+            lv.n2[lv.count] = nd.n2;
+            lv.toff[lv.count] = toff;
+            toff += (long long)nd.n1 * nd.n2;
+            mx1 = std::max(mx1, nd.n1);
+            mx2 = std::max(mx2, nd.n2);
+            ++lv.count;
         }
-    } rec{c, A, w.X, w.Tm, Dinv, n};
-    rec.run(0, n);
+        flush();
+    }
     hipLaunchKernelGGL(k_pack_inverse, dim3(nb((long long)n * n)), dim3(256), 0, c->stream, (const double*)w.X, A, n);
     LAUNCH_OK();
 }
