@@ -8,6 +8,7 @@
 // stream-function coordinates with the two-grid preconditioner (section 5),
 // v = vbar + C psi, pressure.
 #include <algorithm>
+#include <mutex>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -52,6 +53,68 @@ void enter(tgms_ctx* c) {
 }  // namespace tgms
 
 namespace {
+struct DevPool {
+    std::mutex mu;
+    std::map<int, std::multimap<size_t, void*>> blocks;  // free blocks by size, per device
+    std::map<int, size_t> cached;
+};
+DevPool& dev_pool() {
+    static DevPool* p = new DevPool();  // never destroyed: no HIP calls at static destruction
+    return *p;
+}
+constexpr size_t POOL_CAP = 16ull << 30;  // most bytes kept per device
+}  // namespace
+
+void* tgms::dev_alloc(size_t bytes, size_t* got) {
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    DevPool& P = dev_pool();
+    {
+        std::lock_guard<std::mutex> lock(P.mu);
+        auto& fl = P.blocks[dev];
+        auto it = fl.lower_bound(bytes);
+        // a cached block, unless it is much larger than asked for
+        if (it != fl.end() && it->first <= bytes + bytes / 4 + (1u << 20)) {
+            void* p = it->second;
+            *got = it->first;
+            P.cached[dev] -= it->first;
+            fl.erase(it);
+            return p;
+        }
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        // return the cached blocks of this device to the runtime and try again
+        std::lock_guard<std::mutex> lock(P.mu);
+        for (auto& kv : P.blocks[dev]) (void)hipFree(kv.second);
+        P.blocks[dev].clear();
+        P.cached[dev] = 0;
+        HIP_OK(hipMalloc(&p, bytes));
+    }
+    *got = bytes;
+    return p;
+}
+
+void tgms::dev_free(void* p, size_t bytes) {
+    if (!p) return;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipFree(p);
+        return;
+    }
+    DevPool& P = dev_pool();
+    std::lock_guard<std::mutex> lock(P.mu);
+    if (P.cached[dev] + bytes > POOL_CAP) {
+        (void)hipFree(p);
+        return;
+    }
+    P.blocks[dev].emplace(bytes, p);
+    P.cached[dev] += bytes;
+}
+
+namespace {
+
 thread_local std::string g_last_error;
 
 struct Timer {
@@ -1022,7 +1085,7 @@ void tgms_destroy(tgms_ctx* c) {
     else (void)hipDeviceSynchronize();
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->iter_graph) (void)hipGraphExecDestroy(c->iter_graph);
-    for (auto& b : c->owned) (void)hipFree(b.p);
+    for (auto& b : c->owned) tgms::dev_free(b.p, b.bytes);
     if (c->red_h) (void)hipHostFree(c->red_h);
     if (c->ev_enter) (void)hipEventDestroy(c->ev_enter);
     if (c->stream) (void)hipStreamDestroy(c->stream);

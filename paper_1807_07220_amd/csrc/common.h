@@ -87,6 +87,17 @@ struct DeviceBuf {
     size_t bytes = 0;
 };
 
+namespace tgms {
+// Device memory through a per-device cache of freed blocks: setups of the same
+// shape allocate the same sizes, and hipMalloc / hipFree of the large dense
+// workspaces cost milliseconds each.  dev_alloc returns a block of at least
+// `bytes` (its size in *got); dev_free takes it back (the caller has synchronised
+// the work that used it).  The cache keeps at most a fixed total per device and
+// is emptied when hipMalloc fails.
+void* dev_alloc(size_t bytes, size_t* got);
+void dev_free(void* p, size_t bytes);
+}  // namespace tgms
+
 struct tgms_ctx {
     // grid
     int nx, ny, bx, by, Nx, Ny, nblk, ne, nex, jmax;
@@ -220,8 +231,7 @@ struct tgms_ctx {
     template <typename T>
     T* alloc(size_t n) {
         DeviceBuf b;
-        b.bytes = n * sizeof(T) + 256;
-        HIP_OK(hipMalloc(&b.p, b.bytes));
+        b.p = tgms::dev_alloc(n * sizeof(T) + 256, &b.bytes);
         HIP_OK(hipMemsetAsync(b.p, 0, b.bytes, stream));
         owned.push_back(b);
         return reinterpret_cast<T*>(b.p);
@@ -329,6 +339,7 @@ struct DenseInvWork {
     int* fail = nullptr;
     double* X = nullptr;
     double* Tm = nullptr;
+    size_t bytes[4] = {0, 0, 0, 0};  // block sizes of Dinv, fail, X, Tm
 };
 // an inverse queued on a stream without waiting (dense_spd_inverse_begin / _end)
 struct DenseInvAsync {

@@ -411,7 +411,7 @@ void dense_spd_inverse(tgms_ctx* c, double* A, int n) {
     HIP_OK(hipStreamSynchronize(c->stream));
     // release the temporaries (they are the last allocations)
     for (int k = 0; k < 4; ++k) {
-        HIP_OK(hipFree(c->owned.back().p));
+        dev_free(c->owned.back().p, c->owned.back().bytes);
         c->owned.pop_back();
     }
     if (h) throw TgmsError{TGMS_E_INVAL, "coarse operator is not positive definite"};
@@ -423,10 +423,10 @@ void dense_spd_inverse_begin(tgms_ctx* c, double* A, int n, DenseInvAsync& h) {
     if (n <= 0) return;
     size_t nd, nx, nt;
     dense_inverse_sizes(n, nd, nx, nt);
-    HIP_OK(hipMalloc(&h.w.Dinv, sizeof(double) * nd));
-    HIP_OK(hipMalloc(&h.w.fail, sizeof(int) * 64));
-    HIP_OK(hipMalloc(&h.w.X, sizeof(double) * nx));
-    HIP_OK(hipMalloc(&h.w.Tm, sizeof(double) * nt));
+    h.w.Dinv = (double*)dev_alloc(sizeof(double) * nd, &h.w.bytes[0]);
+    h.w.fail = (int*)dev_alloc(sizeof(int) * 64, &h.w.bytes[1]);
+    h.w.X = (double*)dev_alloc(sizeof(double) * nx, &h.w.bytes[2]);
+    h.w.Tm = (double*)dev_alloc(sizeof(double) * nt, &h.w.bytes[3]);
     h.stream = c->stream;
     zero(c, h.w.fail, sizeof(int) * 64);
     dense_inverse_enqueue(c, A, n, h.w);
@@ -448,8 +448,9 @@ DenseInvAsync::~DenseInvAsync() {
 }
 
 void DenseInvAsync::release() {
-    for (void* p : {(void*)w.Dinv, (void*)w.fail, (void*)w.X, (void*)w.Tm})
-        if (p) (void)hipFree(p);
+    void* ps[4] = {(void*)w.Dinv, (void*)w.fail, (void*)w.X, (void*)w.Tm};
+    for (int k = 0; k < 4; ++k)
+        if (ps[k]) dev_free(ps[k], w.bytes[k]);
     w = DenseInvWork{};
 }
 
