@@ -136,6 +136,28 @@ struct Timer {
     }
 };
 
+// the elapsed time between two events recorded on a stream (read after both)
+struct SpanTimer {
+    hipEvent_t a = nullptr, b = nullptr;
+    void start(hipStream_t s) {
+        HIP_OK(hipEventCreate(&a));
+        HIP_OK(hipEventCreate(&b));
+        HIP_OK(hipEventRecord(a, s));
+    }
+    void stop(hipStream_t s) { HIP_OK(hipEventRecord(b, s)); }
+    double ms() {
+        if (!a || !b) return 0.0;
+        HIP_OK(hipEventSynchronize(b));
+        float t = 0;
+        HIP_OK(hipEventElapsedTime(&t, a, b));
+        return t;
+    }
+    ~SpanTimer() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
 template <typename F>
 tgms_status guarded(F&& f) {
     try {
@@ -392,15 +414,18 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
     // that the inverse's clean-up still finds it
     struct Side {
         hipStream_t s = nullptr;
-        hipEvent_t e0 = nullptr, e1 = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
         ~Side() {
             if (s) (void)hipStreamSynchronize(s);
             if (e0) (void)hipEventDestroy(e0);
             if (e1) (void)hipEventDestroy(e1);
+            if (e2) (void)hipEventDestroy(e2);
             if (s) (void)hipStreamDestroy(s);
         }
     } side;
     tgms::DenseInvAsync kh_inv;
+    SpanTimer pat_timer;     // the smoother factorisation on the second stream
+    int* pat_fail = nullptr;
     try {
         // All work runs on a stream of the library's own (default priority); each call
         // first waits for what the caller queued on its stream (NULL: the null stream)
@@ -440,38 +465,40 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         HIP_OK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
         HIP_OK(hipStreamSynchronize(c->stream));
         if (hbad) throw TgmsError{TGMS_E_INVAL, "permeability must be finite and positive"};
-        // the coarse RT0 stiffness of the preprocessing (section 3) and its inverse, queued on
-        // the second stream; joined before the end of the coarse phase
-        c->nv = (c->Nx - 1) * (c->Ny - 1);
-        c->AH0 = c->alloc<double>((size_t)c->nblk * 6);
-        c->KH = c->alloc<double>((size_t)c->nv * c->nv);
-        HIP_OK(hipStreamCreateWithFlags(&side.s, hipStreamNonBlocking));
-        HIP_OK(hipEventCreateWithFlags(&side.e0, hipEventDisableTiming));
-        HIP_OK(hipEventCreateWithFlags(&side.e1, hipEventDisableTiming));
-        HIP_OK(hipEventRecord(side.e0, c->stream));
-        HIP_OK(hipStreamWaitEvent(side.s, side.e0, 0));
-        {
-            const hipStream_t main_stream = c->stream;
-            struct Restore {
-                tgms_ctx* c;
-                hipStream_t s;
-                ~Restore() { c->stream = s; }
-            } restore{c, main_stream};
-            c->stream = side.s;
-            tgms::coarse_rt0_blocks(c);
-            tgms::rt0_stiffness(c, c->KH);
-            tgms::dense_spd_inverse_begin(c, c->KH, c->nv, kh_inv);
-        }
-        HIP_OK(hipEventRecord(side.e1, side.s));
         // block factors
         c->blk_m = bx - 1;
         c->blk_n = (bx - 1) * (by - 1);
         c->blk_b = bx;
         c->blkL = c->alloc<double>((size_t)c->nblk * btri_size(bx - 1, by - 1));
         c->blkS = c->alloc<double>((size_t)c->nblk * c->blk_n);
+        // the coarse RT0 stiffness of the preprocessing (section 3) and its inverse go to a
+        // second stream, joined before the end of the coarse phase; they are queued after the
+        // block factorisation is launched, so that the GPU works while the host queues them
+        c->nv = (c->Nx - 1) * (c->Ny - 1);
+        c->AH0 = c->alloc<double>((size_t)c->nblk * 6);
+        c->KH = c->alloc<double>((size_t)c->nv * c->nv);
+        HIP_OK(hipStreamCreateWithFlags(&side.s, hipStreamNonBlocking));
+        HIP_OK(hipEventCreateWithFlags(&side.e0, hipEventDisableTiming));
+        HIP_OK(hipEventCreateWithFlags(&side.e1, hipEventDisableTiming));
+        HIP_OK(hipEventCreateWithFlags(&side.e2, hipEventDisableTiming));
+        HIP_OK(hipEventRecord(side.e0, c->stream));
+        HIP_OK(hipStreamWaitEvent(side.s, side.e0, 0));
         {
             Timer t(c->stream);
             tgms::factor_blocks(c);
+            {
+                const hipStream_t main_stream = c->stream;
+                struct Restore {
+                    tgms_ctx* c;
+                    hipStream_t s;
+                    ~Restore() { c->stream = s; }
+                } restore{c, main_stream};
+                c->stream = side.s;
+                tgms::coarse_rt0_blocks(c);
+                tgms::rt0_stiffness(c, c->KH);
+                tgms::dense_spd_inverse_begin(c, c->KH, c->nv, kh_inv);
+            }
+            HIP_OK(hipEventRecord(side.e1, side.s));
             // snapshots + Gram
             c->Psi = c->alloc<double>((size_t)c->nblk * c->ncol * c->nfk);
             // A_K Psi for the Gram kernel without matrix cores; the path integrals of the
@@ -531,28 +558,8 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
             if (c->precision) c->W32 = c->alloc<float>((size_t)c->nblk * bx * by * c->mu);
             c->Ac = c->alloc<double>((size_t)c->ncs * c->ncs);
             tgms::coarse_local_run(c, c->Td, c->zcd);
-            tgms::dense_spd_inverse(c, c->Ac, c->ncs);
-            if (c->precision) {
-                c->Ac32 = c->alloc<float>((size_t)c->ncs * c->ncs);
-                tgms::cast_d2f(c, (long long)c->ncs * c->ncs, c->Ac, c->Ac32);
-            }
-            c->cy = c->alloc<double>((size_t)c->nblk * c->mu);
-            c->cvec = c->alloc<double>(2 * (size_t)c->ncs + 1);
-            c->cvec2 = c->alloc<double>((size_t)c->ncs + 1);
-            c->cy32 = c->alloc<float>((size_t)c->nblk * c->mu);
-            c->cvec32 = c->alloc<float>(2 * (size_t)c->ncs + 1);
-            c->cvec2_32 = c->alloc<float>((size_t)c->ncs + 1);
-            // coarse RT0 for the preprocessing: join the second stream
-            HIP_OK(hipStreamWaitEvent(c->stream, side.e1, 0));
-            tgms::dense_spd_inverse_end(kh_inv);
-            c->cflux = c->alloc<double>(2 * ((size_t)c->Ny * (c->Nx + 1) + (size_t)(c->Ny + 1) * c->Nx));
-            c->svec = c->alloc<double>((size_t)c->nv + 1);
-            c->svec2 = c->alloc<double>(2 * (size_t)c->nv + 1);
-            c->t_coarse_ms = t.ms();
-        }
-        // smoother patches
-        {
-            Timer t(c->stream);
+            // smoother patches (section 5): factorised on the second stream while the
+            // dense coarse factorisation, a chain of small kernels, runs on this one
             c->patch_h.resize(c->nblk);
             long long off = 0, voff = 0;
             std::set<int> widths;
@@ -593,10 +600,50 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                 c->patW4 = c->alloc<double>(4 * (size_t)ncell);  // zero: slots no patch covers stay zero
                 if (c->precision) c->patW4_32 = c->alloc<float>(4 * (size_t)ncell);
             }
-            tgms::factor_patches(c);
-            c->t_smoother_ms = t.ms();
+            pat_fail = c->alloc<int>(1);
+            HIP_OK(hipEventRecord(side.e0, c->stream));
+            HIP_OK(hipStreamWaitEvent(side.s, side.e0, 0));
+            {
+                const hipStream_t main_stream = c->stream;
+                struct Restore {
+                    tgms_ctx* c;
+                    hipStream_t s;
+                    ~Restore() { c->stream = s; }
+                } restore{c, main_stream};
+                c->stream = side.s;
+                pat_timer.start(side.s);
+                tgms::factor_patches_launch(c, pat_fail);
+                pat_timer.stop(side.s);
+            }
+            HIP_OK(hipEventRecord(side.e2, side.s));
+            tgms::dense_spd_inverse(c, c->Ac, c->ncs);
+            if (c->precision) {
+                c->Ac32 = c->alloc<float>((size_t)c->ncs * c->ncs);
+                tgms::cast_d2f(c, (long long)c->ncs * c->ncs, c->Ac, c->Ac32);
+            }
+            c->cy = c->alloc<double>((size_t)c->nblk * c->mu);
+            c->cvec = c->alloc<double>(2 * (size_t)c->ncs + 1);
+            c->cvec2 = c->alloc<double>((size_t)c->ncs + 1);
+            c->cy32 = c->alloc<float>((size_t)c->nblk * c->mu);
+            c->cvec32 = c->alloc<float>(2 * (size_t)c->ncs + 1);
+            c->cvec2_32 = c->alloc<float>((size_t)c->ncs + 1);
+            // coarse RT0 for the preprocessing: join the second stream
+            HIP_OK(hipStreamWaitEvent(c->stream, side.e1, 0));
+            tgms::dense_spd_inverse_end(kh_inv);
+            c->cflux = c->alloc<double>(2 * ((size_t)c->Ny * (c->Nx + 1) + (size_t)(c->Ny + 1) * c->Nx));
+            c->svec = c->alloc<double>((size_t)c->nv + 1);
+            c->svec2 = c->alloc<double>(2 * (size_t)c->nv + 1);
+            c->t_coarse_ms = t.ms();
         }
-        // snapshot storage is no longer needed
+        // smoother patches: join the second stream and check the factorisation
+        {
+            HIP_OK(hipStreamWaitEvent(c->stream, side.e2, 0));
+            int h = 0;
+            HIP_OK(hipMemcpyAsync(&h, pat_fail, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+            HIP_OK(hipStreamSynchronize(c->stream));
+            c->t_smoother_ms = pat_timer.ms();
+            if (h) throw TgmsError{TGMS_E_INVAL, "smoother patch matrix is not positive definite"};
+        }
         // pressure: orthonormal DCT-II matrices and the 1D Neumann eigenvalues
         c->Qx = c->alloc<double>((size_t)nx * nx);
         c->lamx = c->alloc<double>(nx);

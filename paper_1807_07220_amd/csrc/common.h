@@ -290,6 +290,8 @@ void zero(tgms_ctx* c, void* p, size_t bytes);
 // band factors and smoother (k_band.hip)
 void factor_blocks(tgms_ctx* c);
 void factor_patches(tgms_ctx* c);
+// the same without waiting: a failed factorisation sets *fail (zero on entry)
+void factor_patches_launch(tgms_ctx* c, int* fail);
 template <typename T>
 void smooth_patches(tgms_ctx* c, const T* g, const double* sc,
                     const struct FusedUpdate* fu = nullptr);  // local solves of S g into the patch pool

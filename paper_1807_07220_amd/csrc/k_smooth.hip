@@ -585,7 +585,7 @@ namespace tgms {
 
 long long patch_factor_size(int m, int mh) { return tw_size(m, mh); }
 
-void factor_patches(tgms_ctx* c) {
+void factor_patches_launch(tgms_ctx* c, int* fail) {
     const int m = c->pat_bmax - 1;
     if (m > 32) throw TgmsError{TGMS_E_UNSUPPORTED, "smoother patch wider than 33 cells"};
     const size_t lds = (size_t)(6 * c->pat_nmax + 3 * m * m) * sizeof(double);
@@ -594,11 +594,15 @@ void factor_patches(tgms_ctx* c) {
     allow_lds<double>(c->lds_max);
     allow_lds<float>(c->lds_max);
     (void)hipGetLastError();
-    int* fail = c->alloc_scratch_int();
     hipLaunchKernelGGL(k_patch_factor, dim3(c->nblk), dim3(64), lds, c->stream, c->patch, c->a, c->nx,
                        c->sx * c->sx, c->sy * c->sy, c->patL, fail);
     LAUNCH_OK();
     if (c->patL32) cast_d2f(c, c->pat_pool, c->patL, c->patL32);
+}
+
+void factor_patches(tgms_ctx* c) {
+    int* fail = c->alloc_scratch_int();
+    factor_patches_launch(c, fail);
     int h = 0;
     HIP_OK(hipMemcpyAsync(&h, fail, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
