@@ -189,7 +189,7 @@ def main():
     # kernel durations: HIP events around each launch in a profiled solve of the same input
     s.profile(True)
     rp = s.solve(Fd, rtol=w.rtol)
-    prof = {name: s.profile_get(name) for name in ("smoother", "dir_apply", "gather_restrict", "prolong_residual")}
+    prof = {name: s.profile_get(name) for name in ("smoother", "dir_apply", "gather_restrict")}
     s.profile(False)
     # the smoother alone: SMOOTH_REPS back-to-back launches between one event pair
     avg_ms = s.time_smoother(SMOOTH_REPS)

@@ -185,8 +185,9 @@ tgms_status tgms_last_cond(const tgms_ctx* ctx, double* cond);
  * kernel: 0 = smoother patch solve, 1 = search-direction update with the
  * stream-function operator apply (q = K p, K = C^T A C), 2 = first gather of the
  * patch solutions with the residual and the coarse restriction (and, in the
- * probes, the plain restriction), 3 = coarse prolongation with the second
- * residual (in the probes, the plain prolongation). */
+ * probes, the plain restriction), 3 = the plain coarse prolongation of the
+ * coarse-correction probe (in the PCG the second smoothing prolongs the coarse
+ * solution itself and is counted as a smoother launch). */
 tgms_status tgms_profile(tgms_ctx* ctx, int enable);
 tgms_status tgms_profile_get(tgms_ctx* ctx, int kernel, int* launches, double* total_ms);
 

@@ -133,7 +133,7 @@ class Solver:
         return c.value
 
     # ---- per-kernel event timing ------------------------------------------
-    KERNELS = {"smoother": 0, "dir_apply": 1, "gather_restrict": 2, "prolong_residual": 3}
+    KERNELS = {"smoother": 0, "dir_apply": 1, "gather_restrict": 2, "coarse_prolong": 3}
 
     def profile(self, enable: bool = True):
         check(load().tgms_profile(self._h, 1 if enable else 0))

@@ -236,9 +236,24 @@ void twogrid(tgms_ctx* c, const T* g, const double* gd, double* z, const double*
     }
     tgms::smooth_patches<T>(c, g, sc, fu);
     tgms::gather_res_restrict<T>(c, w, gd, z1, t, tgms::coarse_cy<T>(c), sc);
-    const T* cres = tgms::coarse_solve<T>(c, sc);
-    tgms::prolong_residual<T>(c, cres, z1, z2, gd, t, sc);
-    tgms::smooth_patches<T>(c, t, sc);
+    // the second smoothing prolongs the coarse solution and forms its right-hand side
+    // g - K (z1 + W c) on each patch itself; it also writes z1 + W c (z2)
+    PreResidual<T> pr;
+    pr.z1 = z1;
+    pr.z1p = z2;
+    pr.c = tgms::coarse_solve<T>(c, sc);
+    if constexpr (sizeof(T) == 8)
+        pr.W = (const T*)c->W;
+    else
+        pr.W = (const T*)c->W32;
+    pr.mu = c->mu;
+    pr.unk = c->blk_unk;
+    pr.nunk = c->blk_nu;
+    pr.g = gd;
+    pr.a = c->a;
+    pr.sx2 = c->sx * c->sx;
+    pr.sy2 = c->sy * c->sy;
+    tgms::smooth_patches<T>(c, nullptr, sc, nullptr, &pr);
     tgms::gather_final<T>(c, w, z2, z, dots ? gd : nullptr, gold, dots, first);
 }
 
@@ -575,6 +590,7 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                     r.voff = voff;
                     off += (tw_size(m, r.j1 - r.j0 - 1) + 3) & ~3LL;  // 16-byte aligned factors
                     c->pat_fmax = std::max(c->pat_fmax, tw_size(m, r.j1 - r.j0 - 1));
+                    c->pat_zmax = std::max(c->pat_zmax, (long long)(r.i1 - r.i0 + 1) * (r.j1 - r.j0 + 1));
                     voff += n;
                     c->pat_nmax = std::max(c->pat_nmax, n);
                     c->pat_bmax = std::max(c->pat_bmax, m + 1);

@@ -74,6 +74,42 @@ __host__ __device__ inline Stencil9 stencil9(double A00, double A10, double A01,
     return k;
 }
 
+// 9-point stencil K at (x, y) of an FP64 LDS tile with row pitch pw, with the four
+// cell weights around the vertex already loaded
+__device__ inline double stencil_at4(const double* __restrict__ P, int pw, int x, int y, const double (&A)[4],
+                                     double sx2, double sy2) {
+    const double A00 = A[0], A10 = A[1], A01 = A[2], A11 = A[3];
+    const double s = sx2 + sy2;
+    const double c6 = 1.0 / 6.0, c3 = 1.0 / 3.0;
+    const double kx = sx2 * c6 - sy2 * c3, ky = sy2 * c6 - sx2 * c3;
+    const double* r0 = P + (y - 1) * pw + x;
+    const double* r1 = P + y * pw + x;
+    const double* r2 = P + (y + 1) * pw + x;
+    double r = s * c3 * (A00 + A10 + A01 + A11) * r1[0];
+    r += kx * ((A10 + A11) * r1[1] + (A00 + A01) * r1[-1]);
+    r += ky * ((A01 + A11) * r2[0] + (A00 + A10) * r0[0]);
+    r -= s * c6 * (A11 * r2[1] + A01 * r2[-1] + A10 * r0[1] + A00 * r0[-1]);
+    return r;
+}
+
+// g and the four cell weights of interior vertex v (zeros elsewhere): loaded before a
+// tile barrier so that their latency overlaps the tile's
+struct VertexData {
+    double g, A[4];
+};
+__device__ inline VertexData vertex_data(const double* __restrict__ g, const double* __restrict__ a, long long v,
+                                         int nx, bool interior) {
+    VertexData d{0.0, {0.0, 0.0, 0.0, 0.0}};
+    if (interior) {
+        d.g = g[v];
+        d.A[0] = a[v - nx - 1];
+        d.A[1] = a[v - nx];
+        d.A[2] = a[v - 1];
+        d.A[3] = a[v];
+    }
+    return d;
+}
+
 // Rectangle of cells [i0, i1) x [j0, j1) with its band-factor location.
 struct Rect {
     int i0, i1, j0, j1;
@@ -120,6 +156,7 @@ struct tgms_ctx {
     int pat_bmax = 0, pat_nmax = 0;
     int pat_m1 = 0, pat_m2 = 0;  // the row widths present among the patches (m1 >= m2)
     long long pat_fmax = 0;   // largest patch factor (elements)
+    long long pat_zmax = 0;   // largest patch with its one-vertex halo (vertices)
     int lds_max = 65536;      // device limit on LDS per workgroup (bytes)
     long long pat_pool = 0, pat_vpool = 0;
     double* patL = nullptr;
@@ -250,6 +287,24 @@ enum { SC_RHO = 0, SC_PQ, SC_ALPHA, SC_BETA, SC_ZN2, SC_REL2, SC_Z02, SC_FLAG, S
 // right-hand side is g = gin - alpha q with alpha = rho' / (sum of the p.q partials),
 // and each patch writes g to gout and x += alpha p on its own block's vertices
 // (workgroup 0 records the scalars, as the separate update kernel would).
+// Inputs of the second smoothing of the two-grid cycle when it also forms its own
+// right-hand side: t = g - K z1' with z1' = z1 + W c (the coarse correction
+// prolonged), on each patch and its one-vertex halo; the patch's own block writes z1'.
+// z1 null: the smoother reads its right-hand side as given.
+template <typename T>
+struct PreResidual {
+    const T* z1 = nullptr;
+    T* z1p = nullptr;
+    const T* c = nullptr;     // coarse solution
+    const T* W = nullptr;     // [block][owned vertex][slot]
+    int mu = 0;
+    const int* unk = nullptr;
+    const int* nunk = nullptr;
+    const double* g = nullptr;  // FP64 right-hand side of the cycle
+    const double* a = nullptr;  // cell weights
+    double sx2 = 0, sy2 = 0;
+};
+
 struct FusedUpdate {
     const double* part;
     int nred;
@@ -293,8 +348,8 @@ void factor_patches(tgms_ctx* c);
 // the same without waiting: a failed factorisation sets *fail (zero on entry)
 void factor_patches_launch(tgms_ctx* c, int* fail);
 template <typename T>
-void smooth_patches(tgms_ctx* c, const T* g, const double* sc,
-                    const struct FusedUpdate* fu = nullptr);  // local solves of S g into the patch pool
+void smooth_patches(tgms_ctx* c, const T* g, const double* sc, const struct FusedUpdate* fu = nullptr,
+                    const PreResidual<T>* pr = nullptr);  // local solves of S g into the patch pool
 // fused PCG / two-grid kernels (k_pcg.hip); sc: skip when the done flag is set (may be null)
 unsigned pcg_tiles(tgms_ctx* c);
 int nred_max();
@@ -304,8 +359,6 @@ void finalize(tgms_ctx* c, bool first);  // scalars from pending gather partials
 void allow_fused_lds(tgms_ctx* c);      // LDS limit of the per-block fused kernels (large blocks)
 template <typename T>
 void gather_res_restrict(tgms_ctx* c, const T* w, const double* g, T* z, T* t, T* cy, const double* sc);
-template <typename T>
-void prolong_residual(tgms_ctx* c, const T* cres, const T* zin, T* zout, const double* g, T* t, const double* sc);
 template <typename T>
 void gather_final(tgms_ctx* c, const T* w, const T* zin, double* zout, const double* g, const double* gold,
                   bool with_dots, bool first);

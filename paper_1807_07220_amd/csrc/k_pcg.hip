@@ -1,15 +1,17 @@
 // Fused kernels of the PCG iteration (paper section 5, Step 3) and of the
 // two-grid preconditioner around the smoother and coarse solves.
 //
-// One PCG iteration in stream-function coordinates is 9 kernels:
+// One PCG iteration in stream-function coordinates is 7 kernels (8 for coarse
+// systems of more than 1024 unknowns):
 //   [finalise the last iteration: rho' = g.z, beta, |C z|^2 test]
 //   p = z + beta p;  q = K p;  partial p.q                        (k_dir_apply)
 //   z = B_TG g: alpha = rho / p.q, x += alpha p and g -= alpha q inside the
 //   first smoothing; z1 = eta sum ext(w), t = g - K z1 and the
 //   block restriction W_b^T t (k_gather_res_restrict); coarse accumulation and
-//   the two triangular products; z1' = z1 + W c, t = g - K z1'
-//   (k_prolong_residual); smoother; z = z1' + eta sum ext(w) with the partials of
-//   g.z, gold.z and |C z|^2 (k_gather_final).
+//   the two triangular products (k_dense.hip); the second smoothing, which forms
+//   z1' = z1 + W c and its right-hand side g - K z1' on each patch itself
+//   (k_smooth.hip); z = z1' + eta sum ext(w) with the partials of g.z, gold.z and
+//   |C z|^2 (k_gather_final).
 // The partials of k_gather_final are finalised by the next iteration's
 // k_dir_apply (every workgroup forms the same sums; workgroup 0 records them),
 // or by k_finalize where the host needs the scalars (after the first
@@ -209,42 +211,6 @@ __device__ inline T patch_sum(const Rect* __restrict__ rects, const T* __restric
     return gather_w<T>(rects, w, i, j, G.bx, G.by, G.Nx, G.Ny);
 }
 
-// 9-point stencil K at (x, y) of an FP64 LDS tile with row pitch pw, with the four
-// cell weights around the vertex already loaded
-__device__ inline double stencil_at4(const double* __restrict__ P, int pw, int x, int y, const double (&A)[4],
-                                     double sx2, double sy2) {
-    const double A00 = A[0], A10 = A[1], A01 = A[2], A11 = A[3];
-    const double s = sx2 + sy2;
-    const double c6 = 1.0 / 6.0, c3 = 1.0 / 3.0;
-    const double kx = sx2 * c6 - sy2 * c3, ky = sy2 * c6 - sx2 * c3;
-    const double* r0 = P + (y - 1) * pw + x;
-    const double* r1 = P + y * pw + x;
-    const double* r2 = P + (y + 1) * pw + x;
-    double r = s * c3 * (A00 + A10 + A01 + A11) * r1[0];
-    r += kx * ((A10 + A11) * r1[1] + (A00 + A01) * r1[-1]);
-    r += ky * ((A01 + A11) * r2[0] + (A00 + A10) * r0[0]);
-    r -= s * c6 * (A11 * r2[1] + A01 * r2[-1] + A10 * r0[1] + A00 * r0[-1]);
-    return r;
-}
-
-// g and the four cell weights of interior vertex v (zeros elsewhere): loaded before a
-// tile barrier so that their latency overlaps the tile's
-struct VertexData {
-    double g, A[4];
-};
-__device__ inline VertexData vertex_data(const double* __restrict__ g, const double* __restrict__ a, long long v,
-                                         int nx, bool interior) {
-    VertexData d{0.0, {0.0, 0.0, 0.0, 0.0}};
-    if (interior) {
-        d.g = g[v];
-        d.A[0] = a[v - nx - 1];
-        d.A[1] = a[v - nx];
-        d.A[2] = a[v - 1];
-        d.A[3] = a[v];
-    }
-    return d;
-}
-
 // Coarse-space data of the fused two-grid kernels: stream functions W
 // [block][owned vertex][slot], per-block unknown ids and counts.
 template <typename T>
@@ -305,71 +271,6 @@ __global__ void __launch_bounds__(NT) k_gather_res_restrict(const Rect* __restri
         for (int vl = lane; vl < nown; vl += 64) acc += Wb[(long long)vl * C.mu + u] * tb[vl];
         acc = wave_sum(acc);
         if (lane == 0) cy[(long long)blk * C.mu + u] = acc;
-    }
-}
-
-// Coarse prolongation and the second residual, one workgroup per coarse block:
-// z1' = z1 + W c on the block (and, recomputed the same way, on its one-vertex halo),
-// t = g - K z1' (FP64, rounded once).  z1' goes to its own buffer: the halo reads z1
-// of the neighbouring blocks.  The coarse coefficients c[unk[b][u]] of the block and
-// its eight neighbours are gathered into LDS first.
-template <typename T>
-__global__ void __launch_bounds__(NT) k_prolong_residual(CoarseW<T> C, const T* __restrict__ c, GatherGeom G,
-                                                         const T* __restrict__ zin, T* __restrict__ zout,
-                                                         const double* __restrict__ g, const double* __restrict__ a,
-                                                         double sx2, double sy2, T* __restrict__ t,
-                                                         const double* __restrict__ sc) {
-    if (finished(sc)) return;
-    extern __shared__ double smem[];
-    const int bx = G.bx, by = G.by, pw = bx + 2, nown = bx * by, mu = C.mu;
-    double* Z = smem;                                  // (by + 2) x (bx + 2)
-    T* cb = reinterpret_cast<T*>(Z + (by + 2) * pw);  // [9][mu]
-    const int tid = threadIdx.y * TX + threadIdx.x;
-    const int blk = blockIdx.x, I = blk % G.Nx, J = blk / G.Nx, i0 = I * bx, j0 = J * by;
-    for (int e = tid; e < 9 * mu; e += NT) {
-        const int nb = e / mu, u = e % mu, Ib = I + nb % 3 - 1, Jb = J + nb / 3 - 1;
-        T val = T(0);
-        if (Ib >= 0 && Ib < G.Nx && Jb >= 0 && Jb < G.Ny) {
-            const int b = Jb * G.Nx + Ib;
-            if (u < C.nunk[b]) val = c[C.unk[(long long)b * mu + u]];
-        }
-        cb[e] = val;
-    }
-    VertexData d0{};
-    if (tid < nown) {
-        const int i = i0 + tid % bx, j = j0 + tid / bx;
-        d0 = vertex_data(g, a, (long long)j * G.nx + i, G.nx, i > 0 && j > 0);
-    }
-    __syncthreads();
-    for (int e = tid; e < (bx + 2) * (by + 2); e += NT) {
-        const int xl = e % pw, yl = e / pw, ii = i0 - 1 + xl, jj = j0 - 1 + yl;
-        const bool own = xl >= 1 && xl <= bx && yl >= 1 && yl <= by;
-        double val = 0.0;
-        if (ii >= 1 && ii < G.nx && jj >= 1 && jj < G.ny) {
-            const long long v = (long long)jj * G.nx + ii;
-            // vertex (ii, jj) lies in block (ii / bx, jj / by): neighbour nb of this block
-            const int Ib = ii / bx, Jb = jj / by, b = Jb * G.Nx + Ib;
-            const int nb = (Jb - J + 1) * 3 + (Ib - I + 1);
-            const T* Wv = C.W + ((long long)b * nown + (jj % by) * bx + ii % bx) * mu;
-            const T* cv = cb + nb * mu;
-            const int nu = C.nunk[b];
-            T s = T(0);
-            for (int u = 0; u < nu; ++u) s += Wv[u] * cv[u];
-            const T zz = zin[v] + s;
-            val = double(zz);
-            if (own) zout[v] = zz;
-        } else if (own) {
-            zout[(long long)jj * G.nx + ii] = T(0);
-        }
-        Z[e] = val;
-    }
-    __syncthreads();
-    for (int vl = tid; vl < nown; vl += NT) {
-        const int aa = vl % bx, bb = vl / bx, i = i0 + aa, j = j0 + bb;
-        const long long v = (long long)j * G.nx + i;
-        const bool in = i > 0 && j > 0;
-        const VertexData d = vl == tid ? d0 : vertex_data(g, a, v, G.nx, in);
-        t[v] = in ? T(d.g - stencil_at4(Z, pw, aa + 1, bb + 1, d.A, sx2, sy2)) : T(0);
     }
 }
 
@@ -527,13 +428,9 @@ template <typename T>
 static size_t gather_res_lds(tgms_ctx* c) {
     return sizeof(double) * (c->bx + 2) * (c->by + 2) + sizeof(T) * (size_t)c->bx * c->by;
 }
-template <typename T>
-static size_t prolong_res_lds(tgms_ctx* c) {
-    return sizeof(double) * (c->bx + 2) * (c->by + 2) + sizeof(T) * 9 * (size_t)c->mu;
-}
 
 void allow_fused_lds(tgms_ctx* c) {
-    const size_t need = std::max(gather_res_lds<double>(c), prolong_res_lds<double>(c));
+    const size_t need = gather_res_lds<double>(c);
     if (need <= 65536) return;
     if ((long long)need > c->lds_max) throw TgmsError{TGMS_E_UNSUPPORTED, "coarse blocks too large for the LDS tiles"};
     auto set = [&](const void* f) {
@@ -541,8 +438,6 @@ void allow_fused_lds(tgms_ctx* c) {
     };
     set((const void*)k_gather_res_restrict<double>);
     set((const void*)k_gather_res_restrict<float>);
-    set((const void*)k_prolong_residual<double>);
-    set((const void*)k_prolong_residual<float>);
 }
 
 template <typename T>
@@ -557,19 +452,6 @@ template void gather_res_restrict<double>(tgms_ctx*, const double*, const double
                                           const double*);
 template void gather_res_restrict<float>(tgms_ctx*, const float*, const double*, float*, float*, float*,
                                          const double*);
-
-template <typename T>
-void prolong_residual(tgms_ctx* c, const T* cres, const T* zin, T* zout, const double* g, T* t, const double* sc) {
-    ProfScope ps(c, PK_PROLONG);
-    hipLaunchKernelGGL((k_prolong_residual<T>), dim3(c->nblk), dim3(TX, TY), prolong_res_lds<T>(c), c->stream,
-                       coarse_w<T>(c), cres, ggeom(c), zin,
-                       zout, g, (const double*)c->a, c->sx * c->sx, c->sy * c->sy, t, sc);
-    LAUNCH_OK();
-}
-template void prolong_residual<double>(tgms_ctx*, const double*, const double*, double*, const double*, double*,
-                                       const double*);
-template void prolong_residual<float>(tgms_ctx*, const float*, const float*, float*, const double*, float*,
-                                      const double*);
 
 template <typename T>
 void gather_final(tgms_ctx* c, const T* w, const T* zin, double* zout, const double* g, const double* gold,

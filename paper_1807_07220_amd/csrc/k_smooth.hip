@@ -430,7 +430,8 @@ template <typename T, int M1, int M2, bool GENERIC, bool STAGED>
 __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__ rects, const T* __restrict__ Fpool,
                                                         const T* __restrict__ g, int nx, int ny, T* __restrict__ wout,
                                                         T* __restrict__ w4, int bx, int by, int Nx,
-                                                        const double* __restrict__ sc, FusedUpdate U) {
+                                                        const double* __restrict__ sc, FusedUpdate U,
+                                                        PreResidual<T> Pr) {
     if (sc != nullptr && sc[SC_DONE] != 0.0) return;  // PCG already converged
     double al = 0.0;
     if (U.gin) {
@@ -496,6 +497,54 @@ __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__
     if constexpr (STAGED) __syncthreads();
     const T* Sg = F + tw_scale(m, mh);
     const int I = blockIdx.x % Nx, J = blockIdx.x / Nx;
+    if (Pr.z1) {
+        // z1' = z1 + W c on the patch and its one-vertex halo (LDS, FP64 of the stored
+        // value), the own block's z1' written out, then t = g - K z1' in FP64, rounded once
+        const int pw = m + 2, ph = mh + 2, mu = Pr.mu, nown = bx * by;
+        const size_t zoff = ((reinterpret_cast<size_t>(mid + 2 * 64) + 15) & ~(size_t)15);
+        double* Zt = reinterpret_cast<double*>(zoff);
+        T* cb = reinterpret_cast<T*>(Zt + pw * ph);  // [9][mu]: the 3 x 3 blocks around K_i
+        const int Ny = ny / by;
+        for (int e = tid; e < 9 * mu; e += 256) {
+            const int nb = e / mu, u = e % mu, Ib = I + nb % 3 - 1, Jb = J + nb / 3 - 1;
+            T val = T(0);
+            if (Ib >= 0 && Ib < Nx && Jb >= 0 && Jb < Ny) {
+                const int b = Jb * Nx + Ib;
+                if (u < Pr.nunk[b]) val = Pr.c[Pr.unk[(long long)b * mu + u]];
+            }
+            cb[e] = val;
+        }
+        __syncthreads();
+        for (int e = tid; e < pw * ph; e += 256) {
+            const int ii = R.i0 + e % pw, jj = R.j0 + e / pw;
+            const bool own = ii >= I * bx && ii < (I + 1) * bx && jj >= J * by && jj < (J + 1) * by;
+            const long long v = (long long)jj * nx + ii;
+            double val = 0.0;
+            if (ii >= 1 && ii < nx && jj >= 1 && jj < ny) {
+                // vertex (ii, jj) lies in block (ii / bx, jj / by): neighbour nb of K_i
+                const int Ib = ii / bx, Jb = jj / by, b = Jb * Nx + Ib;
+                const int nb = (Jb - J + 1) * 3 + (Ib - I + 1);
+                const T* Wv = Pr.W + ((long long)b * nown + (jj % by) * bx + ii % bx) * mu;
+                const T* cv = cb + nb * mu;
+                const int nu = Pr.nunk[b];
+                T s = T(0);
+                for (int u = 0; u < nu; ++u) s += Wv[u] * cv[u];
+                const T zz = Pr.z1[v] + s;
+                val = double(zz);
+                if (own) Pr.z1p[v] = zz;
+            } else if (own && ii < nx && jj < ny) {
+                Pr.z1p[v] = T(0);
+            }
+            Zt[e] = val;
+        }
+        __syncthreads();
+        for (int r = tid; r < n; r += 256) {
+            const int aa = r % m, bb = r / m;
+            const long long v = (long long)(R.j0 + 1 + bb) * nx + R.i0 + 1 + aa;
+            const VertexData d = vertex_data(Pr.g, Pr.a, v, nx, true);
+            vec[r] = Sg[r] * T(d.g - stencil_at4(Zt, pw, aa + 1, bb + 1, d.A, Pr.sx2, Pr.sy2));
+        }
+    } else
     for (int r = tid; r < n; r += 256) {
         const int aa = r % m, bb = r / m, i = R.i0 + 1 + aa, j = R.j0 + 1 + bb;
         const long long v = (long long)j * nx + i;
@@ -529,18 +578,19 @@ __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__
 #define TGMS_TW_PAIRS(X) X(7, 5) X(9, 7) X(11, 9) X(15, 13) X(19, 17) X(23, 21) X(27, 25) X(31, 29)
 
 template <typename T, int M1, int M2, bool GENERIC, bool STAGED>
-void launch_tw(tgms_ctx* c, const T* L, const T* g, T* w, size_t lds, const double* sc, const FusedUpdate& U) {
+void launch_tw(tgms_ctx* c, const T* L, const T* g, T* w, size_t lds, const double* sc, const FusedUpdate& U,
+               const PreResidual<T>& Pr) {
     T* w4 = nullptr;
     if (c->slots) w4 = sizeof(T) == 8 ? (T*)c->patW4 : (T*)c->patW4_32;
     if (c->prof) {
         // events recorded by the dispatch itself (kernel execution only)
         hipEvent_t e1 = tgms::take_event(c), e2 = tgms::take_event(c);
         hipExtLaunchKernelGGL((k_smooth_twisted<T, M1, M2, GENERIC, STAGED>), dim3(c->nblk), dim3(256), lds,
-                              c->stream, e1, e2, 0, c->patch, L, g, c->nx, c->ny, w, w4, c->bx, c->by, c->Nx, sc, U);
+                              c->stream, e1, e2, 0, c->patch, L, g, c->nx, c->ny, w, w4, c->bx, c->by, c->Nx, sc, U, Pr);
         c->prof_rec.push_back({tgms::PK_SMOOTH, c->prof_iter, e1, e2});
     } else {
         hipLaunchKernelGGL((k_smooth_twisted<T, M1, M2, GENERIC, STAGED>), dim3(c->nblk), dim3(256), lds, c->stream,
-                           c->patch, L, g, c->nx, c->ny, w, w4, c->bx, c->by, c->Nx, sc, U);
+                           c->patch, L, g, c->nx, c->ny, w, w4, c->bx, c->by, c->Nx, sc, U, Pr);
     }
 }
 
@@ -548,25 +598,25 @@ void launch_tw(tgms_ctx* c, const T* L, const T* g, T* w, size_t lds, const doub
 // patches have one width, -1 when there are more than two)
 template <typename T>
 void dispatch_twisted(tgms_ctx* c, int m1, int m2, bool staged, const T* L, const T* g, T* w, size_t lds,
-                      const double* sc, const FusedUpdate& U) {
+                      const double* sc, const FusedUpdate& U, const PreResidual<T>& Pr) {
     if (staged) {
 #define TGMS_TW_CASE(A, B)                                \
     if (m1 == A && (m2 == B || m2 == A)) {                \
-        launch_tw<T, A, B, false, true>(c, L, g, w, lds, sc, U); \
+        launch_tw<T, A, B, false, true>(c, L, g, w, lds, sc, U, Pr); \
         return;                                           \
     }
         TGMS_TW_PAIRS(TGMS_TW_CASE)
 #undef TGMS_TW_CASE
-        launch_tw<T, 0, 0, true, true>(c, L, g, w, lds, sc, U);
+        launch_tw<T, 0, 0, true, true>(c, L, g, w, lds, sc, U, Pr);
     } else {
 #define TGMS_TW_CASE_D(A, B)                                  \
     if (m1 == A && (m2 == B || m2 == A)) {                    \
-        launch_tw<T, A, B, false, false>(c, L, g, w, lds, sc, U); \
+        launch_tw<T, A, B, false, false>(c, L, g, w, lds, sc, U, Pr); \
         return;                                               \
     }
         TGMS_TW_PAIRS(TGMS_TW_CASE_D)
 #undef TGMS_TW_CASE_D
-        launch_tw<T, 0, 0, true, false>(c, L, g, w, lds, sc, U);
+        launch_tw<T, 0, 0, true, false>(c, L, g, w, lds, sc, U, Pr);
     }
 }
 
@@ -611,7 +661,7 @@ void factor_patches(tgms_ctx* c) {
 
 // local solves of every patch on g into the patch solution pool (patW / patW32)
 template <typename T>
-void smooth_patches(tgms_ctx* c, const T* g, const double* sc, const FusedUpdate* fu) {
+void smooth_patches(tgms_ctx* c, const T* g, const double* sc, const FusedUpdate* fu, const PreResidual<T>* pr) {
     const T* L;
     T* w;
     if constexpr (sizeof(T) == 8) {
@@ -621,14 +671,20 @@ void smooth_patches(tgms_ctx* c, const T* g, const double* sc, const FusedUpdate
         L = (const T*)c->patL32;
         w = (T*)c->patW32;
     }
-    const size_t work = (size_t)(2 * ((c->pat_nmax + 3) & ~3) + 2 * 64) * sizeof(T);
+    size_t work = (size_t)(2 * ((c->pat_nmax + 3) & ~3) + 2 * 64) * sizeof(T);
+    if (pr && pr->z1)  // the patch tile of z1' (16-byte aligned) and the coarse coefficients
+        work += 16 + (size_t)c->pat_zmax * sizeof(double) + 9 * (size_t)pr->mu * sizeof(T);
     const size_t staged = (size_t)((c->pat_fmax + 3) & ~3LL) * sizeof(T) + work;
     const bool fits = staged + 64 <= (size_t)c->lds_max && c->smooth_staged != 0;  // + the static scalars
     const FusedUpdate none{};
-    dispatch_twisted<T>(c, c->pat_m1, c->pat_m2, fits, L, g, w, fits ? staged : work, sc, fu ? *fu : none);
+    const PreResidual<T> plain{};
+    dispatch_twisted<T>(c, c->pat_m1, c->pat_m2, fits, L, g, w, fits ? staged : work, sc, fu ? *fu : none,
+                        pr ? *pr : plain);
     LAUNCH_OK();
 }
-template void smooth_patches<double>(tgms_ctx*, const double*, const double*, const FusedUpdate*);
-template void smooth_patches<float>(tgms_ctx*, const float*, const double*, const FusedUpdate*);
+template void smooth_patches<double>(tgms_ctx*, const double*, const double*, const FusedUpdate*,
+                                     const PreResidual<double>*);
+template void smooth_patches<float>(tgms_ctx*, const float*, const double*, const FusedUpdate*,
+                                    const PreResidual<float>*);
 
 }  // namespace tgms
