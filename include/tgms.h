@@ -221,6 +221,12 @@ int tgms_cnn_nparams(void);
 /* Y [n][8][W] = network(X [n][H][W]). */
 tgms_status tgms_cnn_forward(const float* params, const float* X, int n, int H, int W, float* Y, void* stream);
 
+/* The same network for inference on the BF16 matrix cores: weights and activations
+ * rounded to BF16 (nearest even), products accumulated in FP32, the first layer and
+ * the output in FP32 (relative difference from tgms_cnn_forward about 1e-3 to
+ * 1e-2).  The warm start of tgms_setup (warm_start = 2) uses this form. */
+tgms_status tgms_cnn_infer(const float* params, const float* X, int n, int H, int W, float* Y, void* stream);
+
 /* Floats of the workspace one training step on n samples needs (0 for bad shapes). */
 size_t tgms_cnn_train_workspace(int n, int H, int W);
 

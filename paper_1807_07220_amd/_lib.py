@@ -68,6 +68,7 @@ SIGNATURES = {
     "tgms_get_warm_status": (c_int, [c_void_p, c_void_p]),
     "tgms_cnn_nparams": (c_int, []),
     "tgms_cnn_forward": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_void_p]),
+    "tgms_cnn_infer": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_void_p]),
     "tgms_cnn_train_workspace": (ctypes.c_size_t, [c_int, c_int, c_int]),
     "tgms_cnn_train_step": (c_int, [c_void_p, c_void_p, c_void_p, c_int, ctypes.c_float, c_void_p, c_void_p, c_int,
                                     c_int, c_int, c_int, c_void_p, ctypes.POINTER(c_double), c_void_p]),

@@ -541,7 +541,7 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                 float* Xw = c->alloc<float>((size_t)c->ne * 2 * bx * bx);
                 float* Yw = c->alloc<float>((size_t)c->ne * tgms::cnn_kout() * bx);
                 tgms::cnn_windows(c, Xw);
-                tgms::cnn_forward(c->stream, o.cnn_weights, Xw, c->ne, 2 * bx, bx, Yw, nullptr);
+                tgms::cnn_infer_bf16(c->stream, o.cnn_weights, Xw, c->ne, 2 * bx, bx, Yw);
                 Y0 = Yw;
                 c->t_cnn_ms = tc.ms();
             }
@@ -971,6 +971,17 @@ tgms_status tgms_cnn_forward(const float* params, const float* X, int n, int H, 
     }
     return guarded([&] {
         tgms::cnn_forward((hipStream_t)stream, params, X, n, H, W, Y, nullptr);
+        HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+    });
+}
+
+tgms_status tgms_cnn_infer(const float* params, const float* X, int n, int H, int W, float* Y, void* stream) {
+    if (!params || !X || !Y || n < 1 || !tgms::cnn_shape_ok(H, W)) {
+        g_last_error = "bad argument (null pointer, n < 1, or H, W outside [1, 64] with H * W <= 512)";
+        return TGMS_E_INVAL;
+    }
+    return guarded([&] {
+        tgms::cnn_infer_bf16((hipStream_t)stream, params, X, n, H, W, Y);
         HIP_OK(hipStreamSynchronize((hipStream_t)stream));
     });
 }

@@ -377,6 +377,8 @@ void cnn_forward(hipStream_t st, const float* prm, const float* X, long long n, 
 double cnn_train_step(hipStream_t st, float* prm, float* m, float* v, int t, float lr, const float* X, const float* V,
                       long long n, int H, int W, int k, float* work);
 void cnn_windows(tgms_ctx* c, float* X);
+// inference only, BF16 matrix cores with FP32 accumulation (no saved activations)
+void cnn_infer_bf16(hipStream_t st, const float* prm, const float* X, long long n, int H, int W, float* Y);
 void coarse_local_run(tgms_ctx* c, const double* Tm, const int* zc);
 void coarse_rt0_blocks(tgms_ctx* c);
 void rt0_stiffness(tgms_ctx* c, double* K);

@@ -303,6 +303,111 @@ __global__ void k_cnn_windows(const double* __restrict__ kinv, int nx, int Nx, i
     X[e] = (float)(-log10(kinv[cell]) / 3.0);
 }
 
+// ------------------------------------------------------------------ BF16 inference
+// The same forward pass (no saved activations) on the BF16 matrix cores with FP32
+// accumulation: one workgroup per sample; activations in LDS as BF16 with the 16
+// channels innermost ([H+2][W+2][16], zero ring); layer 0 (one input channel) in
+// FP32 on the vector ALU; layers 1-3 as, per tile of 16 positions and per tap of the
+// 3x3 stencil, one v_mfma_f32_16x16x16_bf16 (rows: positions, k: input channels,
+// columns: output channels).  Operand layout of that instruction: lane l holds
+// A[l%16][4(l/16) + e] and B[4(l/16) + e][l%16] (e < 4); result item j of lane l is
+// D[4(l/16) + j][l%16].
+typedef short bf4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline unsigned short f2bf(float x) {  // round to nearest even
+    const unsigned u = __float_as_uint(x);
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+template <int COUT, bool HIDDEN>
+__device__ void conv_mfma(const Shape& S, const unsigned short* __restrict__ in, unsigned short* __restrict__ out,
+                          float* __restrict__ yout, const float* __restrict__ wg, const float* __restrict__ bg) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int col = lane & 15, kg = lane >> 4;  // output channel / input-channel group of this lane
+    bf4_t bfr[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int ci = 4 * kg + e;
+            bfr[t][e] = (short)f2bf(col < COUT ? wg[(col * C + ci) * 9 + t] : 0.f);
+        }
+    const float bias = col < COUT ? bg[col] : 0.f;
+    const int ntiles = (S.HW + 15) / 16;
+    for (int tile = wave; tile < ntiles; tile += NT / 64) {
+        const int p = tile * 16 + col;  // the A row (position) this lane loads
+        const bool valid = p < S.HW;
+        const int q = valid ? padpos(S, p) : 0;
+        f4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            bf4_t a = {0, 0, 0, 0};
+            if (valid) a = *reinterpret_cast<const bf4_t*>(in + (q + tapoff(S, t)) * C + 4 * kg);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bfr[t], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int pos = tile * 16 + 4 * kg + j;
+            if (pos >= S.HW || col >= COUT) continue;
+            const float v = acc[j] + bias;
+            if (HIDDEN)
+                out[padpos(S, pos) * C + col] = f2bf(fmaxf(v, 0.f));
+            else
+                yout[pos * KOUT + col] = v;
+        }
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(NT) k_cnn_infer_bf16(const float* __restrict__ prm, const float* __restrict__ X,
+                                                       int H, int W, float* __restrict__ Y) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const Shape S = shape(H, W);
+    unsigned short* A0 = reinterpret_cast<unsigned short*>(smem_raw);  // [plane][16] BF16
+    unsigned short* A1 = A0 + (size_t)S.plane * C;
+    float* xin = reinterpret_cast<float*>(A1 + (size_t)S.plane * C);    // padded input plane
+    float* yout = reinterpret_cast<float*>(A1);                         // [HW][8], over A1 after layer 2
+    const long long s = blockIdx.x;
+    const int tid = threadIdx.x;
+    uint4* z = reinterpret_cast<uint4*>(smem_raw);
+    const int nz = (int)((2 * (size_t)S.plane * C * sizeof(unsigned short) + (size_t)S.plane * sizeof(float) + 15) / 16);
+    for (int e = tid; e < nz; e += NT) z[e] = make_uint4(0u, 0u, 0u, 0u);
+    __syncthreads();
+    for (int p = tid; p < S.HW; p += NT) xin[padpos(S, p)] = X[s * S.HW + p];
+    __syncthreads();
+    // layer 0: 1 -> 16 channels, FP32
+    for (int p = tid; p < S.HW; p += NT) {
+        const int q = padpos(S, p);
+        float x[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) x[t] = xin[q + tapoff(S, t)];
+#pragma unroll
+        for (int co = 0; co < C; ++co) {
+            float a = prm[BL0 + co];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) a += prm[WL0 + co * 9 + t] * x[t];
+            A0[q * C + co] = f2bf(fmaxf(a, 0.f));
+        }
+    }
+    __syncthreads();
+    conv_mfma<C, true>(S, A0, A1, nullptr, prm + WL1, prm + BL1);
+    conv_mfma<C, true>(S, A1, A0, nullptr, prm + WL2, prm + BL2);
+    conv_mfma<KOUT, false>(S, A0, nullptr, yout, prm + WL3, prm + BL3);
+    for (int e = tid; e < KOUT * W; e += NT) {
+        const int c = e / W, w = e % W;
+        float sum = 0.f;
+        for (int h = 0; h < H; ++h) sum += yout[(h * W + w) * KOUT + c];
+        const double d = c < W ? cos(M_PI * (w + 0.5) * c / W) * sqrt((c == 0 ? 1.0 : 2.0) / W) : 0.0;
+        Y[s * KOUT * W + e] = sum / H + (float)d;
+    }
+}
+
+size_t infer_lds(int H, int W) {  // both activation buffers and the input plane, in 16-byte units
+    const size_t plane = (size_t)shape(H, W).plane;
+    return (2 * plane * C * sizeof(unsigned short) + plane * sizeof(float) + 15) / 16 * 16;
+}
+
 size_t fwd_lds(int H, int W) { return sizeof(float) * (2 * C * shape(H, W).plane + C * C * 9 + C); }
 size_t bwd_lds(int H, int W) { return sizeof(float) * (2 * C * shape(H, W).plane + C * C * 9 + KOUT * 64 + KOUT); }
 
@@ -358,6 +463,11 @@ double cnn_train_step(hipStream_t st, float* prm, float* m, float* v, int t, flo
     double L = 0.0;
     for (float x : lh) L += x;
     return L / n;
+}
+
+void cnn_infer_bf16(hipStream_t st, const float* prm, const float* X, long long n, int H, int W, float* Y) {
+    hipLaunchKernelGGL(k_cnn_infer_bf16, dim3((unsigned)n), dim3(NT), infer_lds(H, W), st, prm, X, H, W, Y);
+    LAUNCH_OK();
 }
 
 void cnn_windows(tgms_ctx* c, float* X) {

@@ -45,13 +45,15 @@ def init_weights(seed: int = 0, device="cuda:0", C: int = 16, kout: int = 8) -> 
     return torch.tensor(w, device=device)
 
 
-def forward(w: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
-    """Network outputs [n][8][W] for inputs X [n][H][W] (float32, GPU)."""
+def forward(w: torch.Tensor, X: torch.Tensor, bf16: bool = False) -> torch.Tensor:
+    """Network outputs [n][8][W] for inputs X [n][H][W] (float32, GPU); bf16: the
+    inference form on the BF16 matrix cores that the warm start uses."""
     n, H, W = X.shape
     X = X.contiguous()
     Y = torch.empty((n, 8, W), dtype=torch.float32, device=X.device)
     stream = torch.cuda.current_stream(X.device).cuda_stream
-    check(load().tgms_cnn_forward(_fptr(w), _fptr(X), n, H, W, _fptr(Y), ctypes.c_void_p(stream)))
+    fn = load().tgms_cnn_infer if bf16 else load().tgms_cnn_forward
+    check(fn(_fptr(w), _fptr(X), n, H, W, _fptr(Y), ctypes.c_void_p(stream)))
     return Y
 
 

@@ -52,6 +52,23 @@ def test_cnn_forward_matches_oracle(H, W):
     assert np.abs(Yg - Yo).max() <= 1e-4 * np.abs(Yo).max()
 
 
+@pytest.mark.parametrize("H,W", [(8, 4), (32, 16), (5, 7), (64, 8)])
+def test_cnn_bf16_inference_matches_oracle(H, W):
+    """BF16 matrix-core inference against the FP64 network.  BF16 keeps 8 significant
+    bits (unit roundoff u = 2^-9); weights and the activations of three layers are
+    rounded once each and every output sums at most 144 products, so the error of
+    the learned part stays within a few tens of u of its magnitude: bound 3e-2 of
+    max |Y - DCT| (the DCT part is exact in both)."""
+    from paper_1807_07220_amd import warmstart as ws
+    theta = params_with_biases(1)
+    X = np.random.default_rng(H * 100 + W).standard_normal((3, H, W))
+    Yg = host(ws.forward(f32(theta), f32(X), bf16=True))
+    Yo = np.stack([ocnn.forward(theta, C, x)[0] for x in X])
+    D = ocnn.dct_unit(W)
+    assert Yg.shape == (3, ocnn.KOUT, W)
+    assert np.abs(Yg - Yo).max() <= 3e-2 * np.abs(Yo - D).max()
+
+
 @pytest.mark.parametrize("k", [8, 3])
 def test_cnn_train_step_matches_oracle(k):
     from paper_1807_07220_amd import warmstart as ws
