@@ -522,7 +522,8 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
             const size_t nvk = (size_t)(bx + 1) * (by + 1);
             c->APsi = c->alloc<double>((size_t)c->nblk * c->ncol * (gram_mfma ? nvk : (size_t)c->nfk));
             c->G = c->alloc<double>((size_t)c->nblk * c->ncol * c->ncol);
-            tgms::snapshots(c);
+            // the A Psi array is free until the Gram products: the snapshot solves' scratch
+            tgms::snapshots(c, c->APsi, (long long)c->ncol * (gram_mfma ? (long long)nvk : (long long)c->nfk));
             tgms::gram(c);
             c->t_snap_ms = t.ms();
         }

@@ -363,7 +363,7 @@ template <typename T>
 void gather_final(tgms_ctx* c, const T* w, const T* zin, double* zout, const double* g, const double* gold,
                   bool with_dots, bool first);
 // setup (k_setup.hip)
-void snapshots(tgms_ctx* c);
+void snapshots(tgms_ctx* c, double* scratch, long long scratch_per_block);  // scratch: a workspace free during the call
 void gram(tgms_ctx* c);
 inline bool gram_uses_mfma(const tgms_ctx* c) { return c->ncol == 64 || c->ncol == 32; }  // blocks of 16 or 8 cells
 void pencil_eig_q(tgms_ctx* c, double* YQ, const float* Y0, float* Vtop);  // YQ: kept modes times recombination

@@ -146,9 +146,10 @@ struct SnapCol {
     }
 };
 
-template <int M>
+template <int M, bool VGLOBAL>
 __global__ void __launch_bounds__(64) k_snapshots_cols(BlockGeom G, const double* __restrict__ a,
-                                                       const double* __restrict__ blkL, double* __restrict__ Psi) {
+                                                       const double* __restrict__ blkL, double* __restrict__ Psi,
+                                                       double* __restrict__ Vg, long long vstride) {
     extern __shared__ __align__(16) double sm[];
     constexpr int TILE = 32;  // faces per transposed output chunk
     const int bx = G.bx, by = G.by;
@@ -158,7 +159,10 @@ __global__ void __launch_bounds__(64) k_snapshots_cols(BlockGeom G, const double
     const int areg = (int)((fsz > TILE * 64 ? fsz : TILE * 64) + 1) & ~1;
     double* F = sm;                 // band factor, later the output transpose tile [TILE][64]
     double* aK = sm + areg;         // cell weights [by][bx]
-    double* V = aK + bx * by + 1;   // right-hand sides / solutions [vertex][64]
+    // right-hand sides / solutions [vertex][64]: in LDS, or (VGLOBAL) in a global scratch
+    // of vstride doubles per block, so that the LDS of a workgroup is the factor only and
+    // several workgroups share a CU
+    double* V = VGLOBAL ? Vg + (long long)blockIdx.x * vstride : aK + bx * by + 1;
     const int blk = blockIdx.x, I = blk % G.Nx, J = blk / G.Nx;
     const int lane = threadIdx.x;
     {
@@ -1045,27 +1049,44 @@ BlockGeom geom(tgms_ctx* c) {
 namespace tgms {
 
 template <int M>
-static void launch_snap_cols(tgms_ctx* c, const BlockGeom& G, size_t lds) {
-    (void)hipFuncSetAttribute((const void*)k_snapshots_cols<M>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max);
-    hipLaunchKernelGGL((k_snapshots_cols<M>), dim3(c->nblk), dim3(64), lds, c->stream, G, c->a, c->blkL, c->Psi);
+static void launch_snap_cols(tgms_ctx* c, const BlockGeom& G, size_t lds, double* Vg, long long vstride) {
+    if (Vg) {
+        (void)hipFuncSetAttribute((const void*)k_snapshots_cols<M, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  c->lds_max);
+        hipLaunchKernelGGL((k_snapshots_cols<M, true>), dim3(c->nblk), dim3(64), lds, c->stream, G, c->a, c->blkL,
+                           c->Psi, Vg, vstride);
+    } else {
+        (void)hipFuncSetAttribute((const void*)k_snapshots_cols<M, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  c->lds_max);
+        hipLaunchKernelGGL((k_snapshots_cols<M, false>), dim3(c->nblk), dim3(64), lds, c->stream, G, c->a, c->blkL,
+                           c->Psi, Vg, vstride);
+    }
 }
 
-void snapshots(tgms_ctx* c) {
+void snapshots(tgms_ctx* c, double* scratch, long long scratch_per_block) {
     BlockGeom G = geom(c);
-    // one lane per snapshot column: needs 4*jmax <= 64 and the block's factor,
-    // weights and 64 columns of interior-vertex values in LDS
+    // one lane per snapshot column: needs 4*jmax <= 64 and the block's factor and
+    // weights in LDS; the 64 columns of interior-vertex values go to LDS too when the
+    // blocks are few (one workgroup per CU at most), else to the scratch (when it holds
+    // them), which lets several workgroups share a CU
     const int m = c->bx - 1, mh = c->by - 1;
     const long long fsz = btri_size(m, mh);
-    const size_t lds_cols =
-        sizeof(double) * ((((fsz > 32 * 64 ? fsz : 32 * 64) + 1) & ~1LL) + c->bx * c->by + 1 + (size_t)m * mh * 64);
-    if (c->snap_cols && c->ncol <= 64 && lds_cols <= (size_t)c->lds_max) {
+    const size_t lds_fac = sizeof(double) * ((((fsz > 32 * 64 ? fsz : 32 * 64) + 1) & ~1LL) + c->bx * c->by + 1);
+    const size_t lds_cols = lds_fac + sizeof(double) * (size_t)m * mh * 64;
+    int cus = 0, dev = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+    const bool vglobal = scratch && scratch_per_block >= (long long)m * mh * 64 && c->nblk > 2 * cus;
+    const size_t lds_use = vglobal ? lds_fac : lds_cols;
+    double* Vg = vglobal ? scratch : nullptr;
+    if (c->snap_cols && c->ncol <= 64 && lds_use <= (size_t)c->lds_max) {
         switch (m) {
-            case 3: launch_snap_cols<3>(c, G, lds_cols); LAUNCH_OK(); return;
-            case 5: launch_snap_cols<5>(c, G, lds_cols); LAUNCH_OK(); return;
-            case 7: launch_snap_cols<7>(c, G, lds_cols); LAUNCH_OK(); return;
-            case 9: launch_snap_cols<9>(c, G, lds_cols); LAUNCH_OK(); return;
-            case 11: launch_snap_cols<11>(c, G, lds_cols); LAUNCH_OK(); return;
-            case 15: launch_snap_cols<15>(c, G, lds_cols); LAUNCH_OK(); return;
+            case 3: launch_snap_cols<3>(c, G, lds_use, Vg, scratch_per_block); LAUNCH_OK(); return;
+            case 5: launch_snap_cols<5>(c, G, lds_use, Vg, scratch_per_block); LAUNCH_OK(); return;
+            case 7: launch_snap_cols<7>(c, G, lds_use, Vg, scratch_per_block); LAUNCH_OK(); return;
+            case 9: launch_snap_cols<9>(c, G, lds_use, Vg, scratch_per_block); LAUNCH_OK(); return;
+            case 11: launch_snap_cols<11>(c, G, lds_use, Vg, scratch_per_block); LAUNCH_OK(); return;
+            case 15: launch_snap_cols<15>(c, G, lds_use, Vg, scratch_per_block); LAUNCH_OK(); return;
             default: break;
         }
     }
