@@ -441,6 +441,7 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
     tgms::DenseInvAsync kh_inv;
     SpanTimer pat_timer;     // the smoother factorisation on the second stream
     int* pat_fail = nullptr;
+    int* blk_fail = nullptr;  // the block factorisation (checked at the end)
     try {
         // All work runs on a stream of the library's own (default priority); each call
         // first waits for what the caller queued on its stream (NULL: the null stream)
@@ -500,7 +501,8 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         HIP_OK(hipStreamWaitEvent(side.s, side.e0, 0));
         {
             Timer t(c->stream);
-            tgms::factor_blocks(c);
+            blk_fail = c->alloc<int>(1);
+            tgms::factor_blocks(c, blk_fail);
             {
                 const hipStream_t main_stream = c->stream;
                 struct Restore {
@@ -526,6 +528,12 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
             tgms::snapshots(c, c->APsi, (long long)c->ncol * (gram_mfma ? (long long)nvk : (long long)c->nfk));
             tgms::gram(c);
             c->t_snap_ms = t.ms();
+            // the block factorisation, checked once the GPU has reached this point (before
+            // the spectral problems use the snapshots)
+            int hb = 0;
+            HIP_OK(hipMemcpyAsync(&hb, blk_fail, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+            HIP_OK(hipStreamSynchronize(c->stream));
+            if (hb) throw TgmsError{TGMS_E_INVAL, "local stream-function matrix is not positive definite"};
         }
         // pencils and eigenproblems
         c->eigs = c->alloc<double>((size_t)c->ne * c->jmax);

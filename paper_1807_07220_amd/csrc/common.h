@@ -343,7 +343,7 @@ void cast_d2f(tgms_ctx* c, long long n, const double* x, float* y);
 void cast_f2d(tgms_ctx* c, long long n, const float* x, double* y);
 void zero(tgms_ctx* c, void* p, size_t bytes);
 // band factors and smoother (k_band.hip)
-void factor_blocks(tgms_ctx* c);
+void factor_blocks(tgms_ctx* c, int* fail = nullptr);  // fail: checked later by the caller (null: here)
 void factor_patches(tgms_ctx* c);
 // the same without waiting: a failed factorisation sets *fail (zero on entry)
 void factor_patches_launch(tgms_ctx* c, int* fail);

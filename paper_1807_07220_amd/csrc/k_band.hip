@@ -13,8 +13,9 @@
 
 namespace {
 
-// One wavefront per rectangle; band matrix in LDS (n * (b+1) doubles).
-template <bool WRITE32>
+// One wavefront per rectangle; band matrix in LDS (n * (b+1) doubles).  NQ: pairs of
+// the trailing update per lane (ceil(b (b+1) / 2 / 64)).
+template <bool WRITE32, int NQ>
 __global__ void k_band_factor(const Rect* __restrict__ rects, const double* __restrict__ a, int nx, double sx2,
                               double sy2, double* __restrict__ Lpool, double* __restrict__ Spool,
                               float* __restrict__ L32, int* __restrict__ fail) {
@@ -49,8 +50,24 @@ __global__ void k_band_factor(const Rect* __restrict__ rects, const double* __re
         for (int t = 0; t < ld && r + t < n; ++t) col[t] *= sr * Spool[R.voff + r + t];
     }
     __syncthreads();
-    // right-looking band Cholesky
+    // right-looking band Cholesky; the pairs (u, t') of a column's trailing update
+    // (u = 1..b, t' = 0..b-u, enumerated column by column) this lane handles, decoded once
     const int npair = b * (b + 1) / 2;
+    int pu[NQ], pt[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        int u = 1, rem = lane + TGMS_WAVE * q;
+        if (rem < npair) {
+            while (rem > b - u) {
+                rem -= b - u + 1;
+                ++u;
+            }
+        } else {
+            u = 0;  // no pair
+        }
+        pu[q] = u;
+        pt[q] = rem;
+    }
     for (int cidx = 0; cidx < n; ++cidx) {
         double* col = M + (long long)cidx * ld;
         const double d = col[0];
@@ -62,15 +79,10 @@ __global__ void k_band_factor(const Rect* __restrict__ rects, const double* __re
         __syncthreads();
         if (lane >= 1 && lane <= b && cidx + lane < n) col[lane] *= inv;
         __syncthreads();
-        for (int p = lane; p < npair; p += TGMS_WAVE) {
-            // p -> (u, t'): u = 1..b, t' = 0..b-u, enumerated column by column
-            int u = 1, rem = p;
-            while (rem > b - u) {
-                rem -= b - u + 1;
-                ++u;
-            }
-            const int tp = rem;
-            if (cidx + u + tp < n) M[(long long)(cidx + u) * ld + tp] -= col[u] * col[u + tp];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int u = pu[q], tp = pt[q];
+            if (u > 0 && cidx + u + tp < n) M[(long long)(cidx + u) * ld + tp] -= col[u] * col[u + tp];
         }
         __syncthreads();
         if (lane == 0) col[0] = inv;
@@ -114,26 +126,32 @@ __global__ void k_band_factor(const Rect* __restrict__ rects, const double* __re
 
 namespace tgms {
 
+// fail_out: a zeroed device flag that a failed factorisation sets, checked by the
+// caller later (null: checked here, after waiting)
 static void factor_rects(tgms_ctx* c, Rect* rects, int count, int max_n, int max_b, double* L, double* S,
-                         float* L32) {
+                         int* fail_out) {
     size_t lds = (size_t)max_n * (max_b + 1) * sizeof(double);
     if (lds > 65536) throw TgmsError{TGMS_E_UNSUPPORTED, "local band factor exceeds 64 KiB of LDS"};
-    int* fail = c->alloc_scratch_int();
+    int* fail = fail_out ? fail_out : c->alloc_scratch_int();
     if (max_b - 1 > TGMS_MMAX) throw TgmsError{TGMS_E_UNSUPPORTED, "local rectangle wider than 33 cells"};
-    if (L32)
-        hipLaunchKernelGGL((k_band_factor<true>), dim3(count), dim3(TGMS_WAVE), lds, c->stream, rects, c->a, c->nx,
-                           c->sx * c->sx, c->sy * c->sy, L, S, L32, fail);
-    else
-        hipLaunchKernelGGL((k_band_factor<false>), dim3(count), dim3(TGMS_WAVE), lds, c->stream, rects, c->a,
+    const int npair = max_b * (max_b + 1) / 2;
+    float* L32 = nullptr;
+    if (npair <= 3 * TGMS_WAVE)
+        hipLaunchKernelGGL((k_band_factor<false, 3>), dim3(count), dim3(TGMS_WAVE), lds, c->stream, rects, c->a,
                            c->nx, c->sx * c->sx, c->sy * c->sy, L, S, L32, fail);
+    else
+        hipLaunchKernelGGL((k_band_factor<false, (34 * 35 / 2 + TGMS_WAVE - 1) / TGMS_WAVE>), dim3(count),
+                           dim3(TGMS_WAVE), lds, c->stream, rects, c->a, c->nx, c->sx * c->sx, c->sy * c->sy, L, S,
+                           L32, fail);
     LAUNCH_OK();
+    if (fail_out) return;
     int h = 0;
     HIP_OK(hipMemcpyAsync(&h, fail, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
     if (h) throw TgmsError{TGMS_E_INVAL, "local stream-function matrix is not positive definite"};
 }
 
-void factor_blocks(tgms_ctx* c) {
+void factor_blocks(tgms_ctx* c, int* fail) {
     std::vector<Rect> r(c->nblk);
     for (int J = 0; J < c->Ny; ++J)
         for (int I = 0; I < c->Nx; ++I) {
@@ -149,7 +167,7 @@ void factor_blocks(tgms_ctx* c) {
         c->blk_rects = c->alloc<Rect>(c->nblk);
         HIP_OK(hipMemcpyAsync(c->blk_rects, r.data(), sizeof(Rect) * c->nblk, hipMemcpyHostToDevice, c->stream));
     }
-    factor_rects(c, c->blk_rects, c->nblk, c->blk_n, c->blk_b, c->blkL, c->blkS, nullptr);
+    factor_rects(c, c->blk_rects, c->nblk, c->blk_n, c->blk_b, c->blkL, c->blkS, fail);
 }
 
 
