@@ -16,7 +16,6 @@
 namespace {
 
 constexpr int TB = 64;   // output tile
-constexpr int TK = 16;   // k step
 constexpr int NT = 256;  // threads (16 x 16), 4 x 4 outputs each
 
 // C = alpha * op(A) * op(B) + beta * C ; row-major; op(A) is M x K, op(B) is K x N.
@@ -26,11 +25,17 @@ constexpr int NT = 256;  // threads (16 x 16), 4 x 4 outputs each
 // holds A[l%16][l/16] and B[l/16][l%16]; result element r of lane l is D[4*r + l/16][l%16].
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
+constexpr int TKG = 32;                  // k step of the GEMM tile
+constexpr int GLD = TB * TKG / NT;       // elements of A (and of B) each thread loads per k step
+
+// 64 x 64 output tile of C = alpha op(A) op(B) + beta C.  Software-pipelined: the next
+// k step's operands are loaded into registers while the current one is multiplied
+// from LDS.
 __device__ inline void gemm_tile(int tm, int tn, int transA, int transB, int M, int N, int K, double alpha,
                                  const double* __restrict__ A, int lda, const double* __restrict__ B, int ldb,
                                  double beta, double* C, int ldc) {
-    __shared__ double As[TK][TB + 1];
-    __shared__ double Bs[TK][TB + 1];
+    __shared__ double As[TKG][TB + 1];
+    __shared__ double Bs[TKG][TB + 1];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -39,38 +44,39 @@ __device__ inline void gemm_tile(int tm, int tn, int transA, int transB, int M, 
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) acc[a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
     const int li = lane & 15, lk = lane >> 4;
-    for (int k0 = 0; k0 < K; k0 += TK) {
-        for (int e = tid; e < TB * TK; e += NT) {
-            int mm, kk;
-            if (transA) {
-                kk = e / TB;
-                mm = e % TB;
-            } else {
-                mm = e / TK;
-                kk = e % TK;
-            }
-            const int gm = m0 + mm, gk = k0 + kk;
-            double v = 0.0;
-            if (gm < M && gk < K) v = transA ? A[(long long)gk * lda + gm] : A[(long long)gm * lda + gk];
-            As[kk][mm] = v;
-        }
-        for (int e = tid; e < TB * TK; e += NT) {
-            int nn, kk;
-            if (transB) {
-                nn = e / TK;
-                kk = e % TK;
-            } else {
-                kk = e / TB;
-                nn = e % TB;
-            }
-            const int gn = n0 + nn, gk = k0 + kk;
-            double v = 0.0;
-            if (gn < N && gk < K) v = transB ? B[(long long)gn * ldb + gk] : B[(long long)gk * ldb + gn];
-            Bs[kk][nn] = v;
-        }
-        __syncthreads();
+    double ra[GLD], rb[GLD];
+    // element e of a k step: (row or column of the tile, k) with consecutive threads on
+    // consecutive addresses of the operand as stored
+    auto gload = [&](int k0) {
 #pragma unroll
-        for (int k4 = 0; k4 < TK; k4 += 4) {
+        for (int q = 0; q < GLD; ++q) {
+            const int e = tid + NT * q;
+            const int mm = transA ? e % TB : e / TKG, kk = transA ? e / TB : e % TKG;
+            const int gm = m0 + mm, gk = k0 + kk;
+            ra[q] = (gm < M && gk < K) ? (transA ? A[(long long)gk * lda + gm] : A[(long long)gm * lda + gk]) : 0.0;
+            const int nn = transB ? e / TKG : e % TB, kb = transB ? e % TKG : e / TB;
+            const int gn = n0 + nn, gk2 = k0 + kb;
+            rb[q] = (gn < N && gk2 < K) ? (transB ? B[(long long)gn * ldb + gk2] : B[(long long)gk2 * ldb + gn]) : 0.0;
+        }
+    };
+    auto lstore = [&]() {
+#pragma unroll
+        for (int q = 0; q < GLD; ++q) {
+            const int e = tid + NT * q;
+            const int mm = transA ? e % TB : e / TKG, kk = transA ? e / TB : e % TKG;
+            As[kk][mm] = ra[q];
+            const int nn = transB ? e / TKG : e % TB, kb = transB ? e % TKG : e / TB;
+            Bs[kb][nn] = rb[q];
+        }
+    };
+    gload(0);
+    lstore();
+    __syncthreads();
+    for (int k0 = 0; k0 < K; k0 += TKG) {
+        const bool more = k0 + TKG < K;
+        if (more) gload(k0 + TKG);  // in flight while this step multiplies
+#pragma unroll
+        for (int k4 = 0; k4 < TKG; k4 += 4) {
             const double a0 = As[k4 + lk][wm + li], a1 = As[k4 + lk][wm + 16 + li];
             const double b0 = Bs[k4 + lk][wn + li], b1 = Bs[k4 + lk][wn + 16 + li];
             acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
@@ -79,6 +85,10 @@ __device__ inline void gemm_tile(int tm, int tn, int transA, int transB, int M, 
             acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
         }
         __syncthreads();
+        if (more) {
+            lstore();
+            __syncthreads();
+        }
     }
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
