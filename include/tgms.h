@@ -89,7 +89,9 @@ typedef struct {
     double rq_tol;     /* relative Ritz residual |T u - theta u| / theta for acceptance (1e-6) */
     int smoother_staging;  /* -1: chosen by the autotuner (without it: staged where the factor
                               fits in LDS); 0: the patch solves read their factor from global
-                              memory; 1: the factor is first staged in LDS */
+                              memory; 1: the factor is first staged in LDS; 2: staged in LDS by
+                              two waves while the other two run the forward sweeps from global
+                              memory (1 and 2 fall back to 0 where the factor does not fit) */
     int rows_per_thread;   /* vertex rows per thread in the tiled PCG kernels: 0 chosen by the
                               autotuner (without it: 1); 1 or 4 */
 } tgms_options;

@@ -283,6 +283,12 @@ void precond(tgms_ctx* c, int which, const double* g, double* z) {
     }
 }
 
+}  // namespace
+
+void tgms::twogrid_probe(tgms_ctx* c) { precond(c, 2, c->vz, c->vq); }
+
+namespace {
+
 // Coarse unknowns (the zero-flux modes of every face, then one stream function per
 // interior coarse vertex), the unknowns touching each block (slots, ordered by id) and
 // their CSR inverse, and the description of each slot's combination of the face
@@ -416,6 +422,8 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
     if (ex > 33) throw TgmsError{TGMS_E_UNSUPPORTED, "smoother patches wider than 33 cells"};
     (void)ey;
     if (o.warm_start < 0 || o.warm_start > 2) throw TgmsError{TGMS_E_INVAL, "warm_start must be 0, 1 or 2"};
+    if (o.smoother_staging < -1 || o.smoother_staging > 2)
+        throw TgmsError{TGMS_E_INVAL, "smoother_staging must be -1, 0, 1 or 2"};
     if (o.rows_per_thread != 0 && o.rows_per_thread != 1 && o.rows_per_thread != 4)
         throw TgmsError{TGMS_E_INVAL, "rows_per_thread must be 0, 1 or 4"};
     if (o.warm_start == 2) {
@@ -694,7 +702,7 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         c->vp1 = c->alloc<double>(nvtx);
         HIP_OK(hipHostMalloc((void**)&c->red_h, SC_COUNT * sizeof(double), hipHostMallocDefault));
         if (o.autotune) tgms::autotune(c, o.tune_cache);
-        if (o.smoother_staging >= 0) c->smooth_staged = o.smoother_staging ? 1 : 0;
+        if (o.smoother_staging >= 0) c->smooth_staged = o.smoother_staging;
         if (o.rows_per_thread == 1 || o.rows_per_thread == 4) c->rpt = o.rows_per_thread;
         HIP_OK(hipStreamSynchronize(c->stream));
         c->t_setup_ms = total.ms();

@@ -354,6 +354,7 @@ void smooth_patches(tgms_ctx* c, const T* g, const double* sc, const struct Fuse
 unsigned pcg_tiles(tgms_ctx* c);
 int nred_max();
 void autotune(tgms_ctx* c, const char* cache_path);  // picks nred, smoother staging (k_tune.hip)
+void twogrid_probe(tgms_ctx* c);  // one two-grid application on the context's zeroed vectors (timing)
 void dir_apply(tgms_ctx* c, const double* z, const double* pin, double* pout, double* q);
 void finalize(tgms_ctx* c, bool first);  // scalars from pending gather partials (first: rho_0, |z_0|^2)
 void allow_fused_lds(tgms_ctx* c);      // LDS limit of the per-block fused kernels (large blocks)

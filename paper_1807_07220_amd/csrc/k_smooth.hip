@@ -304,8 +304,12 @@ __device__ inline void chain(const Lines<T, M>& ln, int steps, const T* Lk, cons
     }
 }
 
+// Fg: the factor in global memory, read by the forward sweeps; F: the factor the rest
+// reads (Fg, or its LDS copy).  With stage (F in LDS, not yet filled): waves 2 and 3
+// copy the factor from Fg to F while waves 0 and 1 run the forward sweeps.
 template <typename T, int M, int PF>
-__device__ inline void solve_patch(int mh, const T* F, T* vec, T* u, T* mid, const PatchOut<T>& out) {
+__device__ inline void solve_patch(int mh, const T* F, const T* Fg, T* vec, T* u, T* mid, const PatchOut<T>& out,
+                                   long long stage) {
     constexpr int m = M, tri = M * (M + 1) / 2;
     const int k = mh / 2;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -314,17 +318,35 @@ __device__ inline void solve_patch(int mh, const T* F, T* vec, T* u, T* mid, con
     const int a = ln.a;
     const T* P = F;
     const T* Lk = F + tw_links(m, mh);
+    const T* Lf = Fg + tw_links(m, mh);  // the forward sweeps' links
     const T* S = F + tw_scale(m, mh);
+    if (stage > 0 && wave >= 2) {
+        // 16-byte copies, eight in flight per thread (128 threads)
+        using V = float4;
+        constexpr int PER = 16 / sizeof(T), U = 8;
+        const V* src = reinterpret_cast<const V*>(Fg);
+        V* dst = reinterpret_cast<V*>(const_cast<T*>(F));
+        const int nvec = (int)((stage + PER - 1) / PER), t2 = tid - 128;
+        int e = t2;
+        for (; e + (U - 1) * 128 < nvec; e += U * 128) {
+            V v[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) v[q] = src[e + q * 128];
+#pragma unroll
+            for (int q = 0; q < U; ++q) dst[e + q * 128] = v[q];
+        }
+        for (; e < nvec; e += 128) dst[e] = src[e];
+    }
     if (wave == 0) {
         // w_{t+1} = b_{t+1} - G_t w_t for t < k-1, stored over b; G_{k-1} w_{k-1} -> mid
         auto to_vec = [&](int row, T v) { vec[row * M + a] = v; };
-        chain<T, M, true, true, PF>(ln, k, Lk, vec, to_vec, (const T*)nullptr, mid, vec[a], act,
+        chain<T, M, true, true, PF>(ln, k, Lf, vec, to_vec, (const T*)nullptr, mid, vec[a], act,
                                 [](int t) { return t + 1; }, [](int t) { return (long long)t; });
         if (k == 0 && act) mid[a] = T(0);
     } else if (wave == 1) {
         // w_{r-1} = b_{r-1} - H_{r-1} w_r from r = mh-1 down; H_k w_{k+1} -> mid + M
         auto to_vec = [&](int row, T v) { vec[row * M + a] = v; };
-        chain<T, M, true, true, PF>(ln, mh - 1 - k, Lk, vec, to_vec, (const T*)nullptr, mid + M, vec[(mh - 1) * M + a],
+        chain<T, M, true, true, PF>(ln, mh - 1 - k, Lf, vec, to_vec, (const T*)nullptr, mid + M, vec[(mh - 1) * M + a],
                                 act, [=](int t) { return mh - 2 - t; }, [=](int t) { return (long long)(mh - 2 - t); });
         if (mh - 1 == k && act) mid[M + a] = T(0);
     }
@@ -421,12 +443,15 @@ __device__ inline void solve_patch_any(int m, int mh, const T* F, T* vec, T* u, 
     }
 }
 
-// One workgroup (4 waves) per patch.  STAGED: the factor is first copied to LDS
-// with 16-byte loads (eight in flight per thread); otherwise the chains read it
-// from global memory with the lines of the next steps in flight.  GENERIC: every patch takes the clamped path of width M1
-// (m <= M1); otherwise every patch has width M1 or M2 and takes the fixed-width
-// path of its width.
-template <typename T, int M1, int M2, bool GENERIC, bool STAGED>
+// One workgroup (4 waves) per patch.  MODE 1: the factor is first copied to LDS
+// with 16-byte loads (eight in flight per thread); MODE 0: the chains read it from
+// global memory with the lines of the next steps in flight; MODE 2: the forward
+// chains read global memory while waves 2 and 3 copy the factor to LDS, which the
+// pivot products and the backward chains then read (the staging is hidden behind
+// the forward sweeps and the links are read from HBM once).  GENERIC: every patch
+// takes the clamped path of width M1 (m <= M1; MODE 2 runs as MODE 0); otherwise
+// every patch has width M1 or M2 and takes the fixed-width path of its width.
+template <typename T, int M1, int M2, bool GENERIC, int MODE>
 __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__ rects, const T* __restrict__ Fpool,
                                                         const T* __restrict__ g, int nx, int ny, T* __restrict__ wout,
                                                         T* __restrict__ w4, int bx, int by, int Nx,
@@ -469,6 +494,8 @@ __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__
     const int tid = threadIdx.x;
     const T* F;
     T* vec;
+    constexpr bool STAGED = MODE == 1;          // staged before the sweeps
+    constexpr bool OVERLAP = MODE == 2 && !GENERIC;  // staged during the forward sweeps
     if constexpr (STAGED) {
         using V = float4;
         constexpr int PER = 16 / sizeof(T);
@@ -487,6 +514,9 @@ __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__
         for (; e < nvec; e += 256) dst[e] = src[e];
         F = sm;
         vec = sm + ((fs + 3) & ~3LL);
+    } else if constexpr (OVERLAP) {
+        F = sm;  // filled by waves 2 and 3 during the forward sweeps
+        vec = sm + ((fs + 3) & ~3LL);
     } else {
         F = Fg;
         vec = sm;
@@ -495,7 +525,7 @@ __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__
     T* mid = u + ((n + 3) & ~3);  // 2 * 64
     // the scale from the staged copy (read once from global memory)
     if constexpr (STAGED) __syncthreads();
-    const T* Sg = F + tw_scale(m, mh);
+    const T* Sg = (OVERLAP ? Fg : F) + tw_scale(m, mh);
     const int I = blockIdx.x % Nx, J = blockIdx.x / Nx;
     if (Pr.z1) {
         // z1' = z1 + W c on the patch and its one-vertex halo (LDS, FP64 of the stored
@@ -567,9 +597,9 @@ __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__
     if constexpr (GENERIC)
         solve_patch_any<T>(m, mh, F, vec, u, mid, out);
     else if (m == M1)
-        solve_patch<T, M1, STAGED ? 1 : TGMS_PF_DIRECT>(mh, F, vec, u, mid, out);
+        solve_patch<T, M1, STAGED ? 1 : TGMS_PF_DIRECT>(mh, F, STAGED ? F : Fg, vec, u, mid, out, OVERLAP ? fs : 0);
     else
-        solve_patch<T, M2, STAGED ? 1 : TGMS_PF_DIRECT>(mh, F, vec, u, mid, out);
+        solve_patch<T, M2, STAGED ? 1 : TGMS_PF_DIRECT>(mh, F, STAGED ? F : Fg, vec, u, mid, out, OVERLAP ? fs : 0);
 }
 
 // Fixed-width pairs (interior width, boundary-clipped width) with an overlap of
@@ -577,7 +607,7 @@ __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__
 // the clamped path.
 #define TGMS_TW_PAIRS(X) X(7, 5) X(9, 7) X(11, 9) X(15, 13) X(19, 17) X(23, 21) X(27, 25) X(31, 29)
 
-template <typename T, int M1, int M2, bool GENERIC, bool STAGED>
+template <typename T, int M1, int M2, bool GENERIC, int MODE>
 void launch_tw(tgms_ctx* c, const T* L, const T* g, T* w, size_t lds, const double* sc, const FusedUpdate& U,
                const PreResidual<T>& Pr) {
     T* w4 = nullptr;
@@ -585,48 +615,50 @@ void launch_tw(tgms_ctx* c, const T* L, const T* g, T* w, size_t lds, const doub
     if (c->prof) {
         // events recorded by the dispatch itself (kernel execution only)
         hipEvent_t e1 = tgms::take_event(c), e2 = tgms::take_event(c);
-        hipExtLaunchKernelGGL((k_smooth_twisted<T, M1, M2, GENERIC, STAGED>), dim3(c->nblk), dim3(256), lds,
+        hipExtLaunchKernelGGL((k_smooth_twisted<T, M1, M2, GENERIC, MODE>), dim3(c->nblk), dim3(256), lds,
                               c->stream, e1, e2, 0, c->patch, L, g, c->nx, c->ny, w, w4, c->bx, c->by, c->Nx, sc, U, Pr);
         c->prof_rec.push_back({tgms::PK_SMOOTH, c->prof_iter, e1, e2});
     } else {
-        hipLaunchKernelGGL((k_smooth_twisted<T, M1, M2, GENERIC, STAGED>), dim3(c->nblk), dim3(256), lds, c->stream,
+        hipLaunchKernelGGL((k_smooth_twisted<T, M1, M2, GENERIC, MODE>), dim3(c->nblk), dim3(256), lds, c->stream,
                            c->patch, L, g, c->nx, c->ny, w, w4, c->bx, c->by, c->Nx, sc, U, Pr);
     }
 }
 
 // m1 >= m2: the two row widths present among the patches (equal when all
 // patches have one width, -1 when there are more than two)
-template <typename T>
-void dispatch_twisted(tgms_ctx* c, int m1, int m2, bool staged, const T* L, const T* g, T* w, size_t lds,
-                      const double* sc, const FusedUpdate& U, const PreResidual<T>& Pr) {
-    if (staged) {
-#define TGMS_TW_CASE(A, B)                                \
-    if (m1 == A && (m2 == B || m2 == A)) {                \
-        launch_tw<T, A, B, false, true>(c, L, g, w, lds, sc, U, Pr); \
-        return;                                           \
+template <typename T, int MODE>
+void dispatch_mode(tgms_ctx* c, int m1, int m2, const T* L, const T* g, T* w, size_t lds, const double* sc,
+                   const FusedUpdate& U, const PreResidual<T>& Pr) {
+#define TGMS_TW_CASE(A, B)                                        \
+    if (m1 == A && (m2 == B || m2 == A)) {                        \
+        launch_tw<T, A, B, false, MODE>(c, L, g, w, lds, sc, U, Pr); \
+        return;                                                   \
     }
-        TGMS_TW_PAIRS(TGMS_TW_CASE)
+    TGMS_TW_PAIRS(TGMS_TW_CASE)
 #undef TGMS_TW_CASE
-        launch_tw<T, 0, 0, true, true>(c, L, g, w, lds, sc, U, Pr);
-    } else {
-#define TGMS_TW_CASE_D(A, B)                                  \
-    if (m1 == A && (m2 == B || m2 == A)) {                    \
-        launch_tw<T, A, B, false, false>(c, L, g, w, lds, sc, U, Pr); \
-        return;                                               \
-    }
-        TGMS_TW_PAIRS(TGMS_TW_CASE_D)
-#undef TGMS_TW_CASE_D
-        launch_tw<T, 0, 0, true, false>(c, L, g, w, lds, sc, U, Pr);
-    }
+    launch_tw<T, 0, 0, true, MODE == 1 ? 1 : 0>(c, L, g, w, lds, sc, U, Pr);
+}
+
+template <typename T>
+void dispatch_twisted(tgms_ctx* c, int m1, int m2, int mode, const T* L, const T* g, T* w, size_t lds,
+                      const double* sc, const FusedUpdate& U, const PreResidual<T>& Pr) {
+    if (mode == 1)
+        dispatch_mode<T, 1>(c, m1, m2, L, g, w, lds, sc, U, Pr);
+    else if (mode == 2)
+        dispatch_mode<T, 2>(c, m1, m2, L, g, w, lds, sc, U, Pr);
+    else
+        dispatch_mode<T, 0>(c, m1, m2, L, g, w, lds, sc, U, Pr);
 }
 
 template <typename T>
 void allow_lds(int lds_max) {
     auto set = [&](const void* f) { (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max); };
-#define TGMS_TW_ATTR(A, B) set((const void*)k_smooth_twisted<T, A, B, false, true>);
+#define TGMS_TW_ATTR(A, B)                                 \
+    set((const void*)k_smooth_twisted<T, A, B, false, 1>); \
+    set((const void*)k_smooth_twisted<T, A, B, false, 2>);
     TGMS_TW_PAIRS(TGMS_TW_ATTR)
 #undef TGMS_TW_ATTR
-    set((const void*)k_smooth_twisted<T, 0, 0, true, true>);
+    set((const void*)k_smooth_twisted<T, 0, 0, true, 1>);
 }
 
 }  // namespace
@@ -675,10 +707,13 @@ void smooth_patches(tgms_ctx* c, const T* g, const double* sc, const FusedUpdate
     if (pr && pr->z1)  // the patch tile of z1' (16-byte aligned) and the coarse coefficients
         work += 16 + (size_t)c->pat_zmax * sizeof(double) + 9 * (size_t)pr->mu * sizeof(T);
     const size_t staged = (size_t)((c->pat_fmax + 3) & ~3LL) * sizeof(T) + work;
-    const bool fits = staged + 64 <= (size_t)c->lds_max && c->smooth_staged != 0;  // + the static scalars
+    // 1 / 2 (staged before / during the forward sweeps) where the factor fits in LDS (+ the
+    // static scalars), else 0 (direct reads); -1: staged before where it fits
+    int mode = c->smooth_staged < 0 ? 1 : c->smooth_staged;
+    if (mode != 0 && staged + 64 > (size_t)c->lds_max) mode = 0;
     const FusedUpdate none{};
     const PreResidual<T> plain{};
-    dispatch_twisted<T>(c, c->pat_m1, c->pat_m2, fits, L, g, w, fits ? staged : work, sc, fu ? *fu : none,
+    dispatch_twisted<T>(c, c->pat_m1, c->pat_m2, mode, L, g, w, mode ? staged : work, sc, fu ? *fu : none,
                         pr ? *pr : plain);
     LAUNCH_OK();
 }

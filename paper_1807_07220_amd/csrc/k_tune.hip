@@ -10,8 +10,9 @@
 //                  rows per thread in their tiles (1, 4): fewer partials to sum
 //                  against more tiles per workgroup, and more loads in flight per
 //                  thread against fewer workgroups with work;
-//   smooth_staged  smoother patch factor staged in LDS with 16-byte copies, or
-//                  read by the chains from global memory.
+//   smooth_staged  smoother patch factor read by the chains from global memory (0),
+//                  staged in LDS with 16-byte copies before the sweeps (1), or staged by
+//                  two waves while the other two run the forward sweeps (2).
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -38,7 +39,7 @@ std::string tune_key(tgms_ctx* c) {
     std::string arch = "unknown";
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
     char buf[256];
-    std::snprintf(buf, sizeof(buf), "v2/%s/%dx%d/b%dx%d/ov%d/p%d", arch.c_str(), c->nx, c->ny, c->bx, c->by,
+    std::snprintf(buf, sizeof(buf), "v3/%s/%dx%d/b%dx%d/ov%d/p%d", arch.c_str(), c->nx, c->ny, c->bx, c->by,
                   c->overlap, c->precision);
     return buf;
 }
@@ -52,7 +53,7 @@ void load_cache(const char* path) {
     int nred = 0, staged = 0, rpt = 0;
     while (std::fgets(line, sizeof(line), f)) {
         if (std::sscanf(line, "%255s %d %d %d", key, &nred, &staged, &rpt) != 4) continue;
-        if (nred >= 1 && nred <= tgms::nred_max() && (staged == 0 || staged == 1) && (rpt == 1 || rpt == 4))
+        if (nred >= 1 && nred <= tgms::nred_max() && staged >= 0 && staged <= 2 && (rpt == 1 || rpt == 4))
             g_tune[key] = TuneRec{nred, staged, rpt};
     }
     std::fclose(f);
@@ -124,19 +125,20 @@ void autotune(tgms_ctx* c, const char* cache_path) {
         }
     c->nred = best.nred;
     c->rpt = best.rpt;
-    // smoother: staged copy vs direct reads (only a choice where the staged form fits)
+    // smoother: direct reads, staged before or during the forward sweeps (a staged mode
+    // whose factor does not fit in LDS runs as direct reads)
     const bool prec32 = c->precision != 0;
-    double ts[2] = {1e30, 1e30};
-    for (int st = 0; st < 2; ++st) {
+    double ts[3] = {1e30, 1e30, 1e30};
+    // timed as whole two-grid applications: the solve's smoothings also form their
+    // right-hand sides, which changes the balance between the modes
+    (void)prec32;
+    for (int st = 0; st < 3; ++st) {
         c->smooth_staged = st;
-        ts[st] = time_ms(c, 3, [&] {
-            if (prec32)
-                smooth_patches<float>(c, c->fz, nullptr);
-            else
-                smooth_patches<double>(c, c->vz, nullptr);
-        });
+        ts[st] = time_ms(c, 3, [&] { twogrid_probe(c); });
     }
-    best.staged = ts[1] <= ts[0] ? 1 : 0;
+    best.staged = 0;
+    for (int st = 1; st < 3; ++st)
+        if (ts[st] < ts[best.staged]) best.staged = st;
     c->smooth_staged = best.staged;
     HIP_OK(hipStreamSynchronize(c->stream));
     c->tuned = 1;
