@@ -66,8 +66,9 @@ def source_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(workload, precision):
-    """HBM bytes per smoother launch from the committed counter runs, or None."""
+def measured_traffic(workload, precision, staged):
+    """HBM bytes per smoother launch from the committed counter runs, or None (also when
+    the counters were taken with another smoother launch mode)."""
     try:
         with open(PMC_RESULTS) as f:
             rec = json.load(f)
@@ -76,7 +77,9 @@ def measured_traffic(workload, precision):
     if rec.get("source_sha256_16") != source_hash(SMOOTHER_SRC):
         return None  # the kernel changed since the counters were taken
     ent = rec.get("workloads", {}).get(f"{workload}/{precision}")
-    return None if ent is None else ent.get("bytes_per_launch")
+    if ent is None or ent.get("smooth_staged", staged) != staged:
+        return None
+    return ent.get("bytes_per_launch")
 
 
 def cpu_baseline(w, kappa, F, gpu_iters, budget_iters=20):
@@ -132,6 +135,9 @@ def main():
     ap.add_argument("--eig-tol", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the mixed-precision comparison")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file (read, and written when a shape is tuned): runs that share it "
+                         "use the same launch configuration")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -160,7 +166,7 @@ def main():
 
     def step(prec):
         t0 = time.perf_counter()
-        s = tg.Solver(kd, w.bx, w.by, tol, precision=prec)
+        s = tg.Solver(kd, w.bx, w.by, tol, precision=prec, tune_cache=args.tune_cache)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         r = s.solve(Fd, rtol=w.rtol)
@@ -198,7 +204,7 @@ def main():
     word = 8 if precision == "fp64" else 4
     nbytes = smoother_bytes(w.nx, w.ny, w.bx, w.by, 2, word)
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(w.name, precision)
+    traffic = measured_traffic(w.name, precision, info["smooth_staged"])
     # per-launch event pairs (each pair adds its own overhead to the launch it brackets)
     kernels = {k: {"launches": v[0], "avg_us_with_event_pair": 1000.0 * v[1] / max(v[0], 1)} for k, v in prof.items()}
     eig_s = (info["t_snap_ms"] + info["t_eig_ms"]) * 1e-3
