@@ -1,4 +1,4 @@
-"""Full-size (1024 x 1024) checks in the configuration the benchmark times (needs an MI355X).
+"""Full-size (1024 x 1024) checks with 16 x 16 and 8 x 8 coarse blocks (needs an MI355X).
 
 The oracle cannot solve this size in test time, so it checks sampled
 outputs one by one (the local spectral problems of sampled coarse faces)
@@ -15,14 +15,18 @@ torch = pytest.importorskip("torch")
 from gpu_util import dev, eig_bound, host  # noqa: E402
 
 
-@pytest.fixture(scope="module")
-def big():
+# 64 x 64 blocks of 16 x 16 cells, and 128 x 128 blocks of 8 x 8 cells (16239 coarse
+# unknowns: the largest dense coarse factorisation)
+@pytest.fixture(scope="module", params=["darcy2d_1024_b16", "darcy2d_1024_b8"])
+def big(request):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import paper_1807_07220_amd as tg
-    w = configs.get("darcy2d_1024_b16")
+    w = configs.get(request.param)
     kappa, F = w.make_inputs()
-    return w, kappa, F, tg.Solver(dev(kappa), w.bx, w.by, w.eig_tol)
+    s = tg.Solver(dev(kappa), w.bx, w.by, w.eig_tol)
+    yield w, kappa, F, s
+    s.close()
 
 
 def _oracle_face(w, kappa, face, tol):
