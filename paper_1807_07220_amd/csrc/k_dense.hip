@@ -322,27 +322,46 @@ static void dense_inverse_enqueue(tgms_ctx* c, double* A, int n, const DenseInvW
     // the recursion multiplies whole square blocks of X, whose parts above the
     // diagonal it never writes: they must be zero
     zero(c, w.X, sizeof(double) * (size_t)n * n);
-    for (int kb0 = 0; kb0 < nblk; ++kb0) {
-        const int k0 = kb0 * TB, kb = std::min(TB, n - k0), k1 = k0 + kb;
-        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(NT), 0, c->stream, A, n, k0, kb, Dinv + (size_t)kb0 * TB * TB,
-                           w.fail);
-        LAUNCH_OK();
-        const int m = n - k1;
-        if (m <= 0) break;
-        // panel: A[k1:, k0:k1] = A[k1:, k0:k1] * Dinv^T (each output row tile reads only its own row tile)
-        {
-            dim3 grid(1, (m + TB - 1) / TB);
-            hipLaunchKernelGGL(k_gemm, grid, dim3(NT), 0, c->stream, 0, 1, m, kb, kb, 1.0,
-                               (const double*)(A + (size_t)k1 * n + k0), n,
-                               (const double*)(Dinv + (size_t)kb0 * TB * TB), TB, 0.0, A + (size_t)k1 * n + k0, n, 0);
+    // Two-level right-looking blocking: outer panels of OB columns are factorised by
+    // inner steps of 64 (diagonal block, panel below it, update of the rest of the outer
+    // panel only); the trailing matrix is then updated once per outer panel, with
+    // k = OB (OB / 64 times fewer passes over it than 64-wide updates).
+    constexpr int OB = 4 * TB;
+    for (int c0 = 0; c0 < n; c0 += OB) {
+        const int c1 = std::min(n, c0 + OB);
+        for (int k0 = c0; k0 < c1; k0 += TB) {
+            const int kb0 = k0 / TB, kb = std::min(TB, n - k0), k1 = k0 + kb;
+            hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(NT), 0, c->stream, A, n, k0, kb,
+                               Dinv + (size_t)kb0 * TB * TB, w.fail);
             LAUNCH_OK();
+            const int m = n - k1;
+            if (m <= 0) break;
+            // panel: A[k1:, k0:k1] = A[k1:, k0:k1] * Dinv^T (each output row tile reads only its own row tile)
+            {
+                dim3 grid(1, (m + TB - 1) / TB);
+                hipLaunchKernelGGL(k_gemm, grid, dim3(NT), 0, c->stream, 0, 1, m, kb, kb, 1.0,
+                                   (const double*)(A + (size_t)k1 * n + k0), n,
+                                   (const double*)(Dinv + (size_t)kb0 * TB * TB), TB, 0.0, A + (size_t)k1 * n + k0,
+                                   n, 0);
+                LAUNCH_OK();
+            }
+            // the rest of the outer panel: A[k1:, k1:c1] -= P P[k1:c1]^T (above the diagonal
+            // of the panel's square part the result is never read)
+            if (c1 > k1) {
+                dim3 grid((c1 - k1 + TB - 1) / TB, (m + TB - 1) / TB);
+                hipLaunchKernelGGL(k_gemm, grid, dim3(NT), 0, c->stream, 0, 1, m, c1 - k1, kb, -1.0,
+                                   (const double*)(A + (size_t)k1 * n + k0), n,
+                                   (const double*)(A + (size_t)k1 * n + k0), n, 1.0, A + (size_t)k1 * n + k1, n, 0);
+                LAUNCH_OK();
+            }
         }
-        // trailing: A[k1:, k1:] -= P P^T (lower tiles only)
-        {
-            dim3 grid((m + TB - 1) / TB, (m + TB - 1) / TB);
-            hipLaunchKernelGGL(k_gemm, grid, dim3(NT), 0, c->stream, 0, 1, m, m, kb, -1.0,
-                               (const double*)(A + (size_t)k1 * n + k0), n, (const double*)(A + (size_t)k1 * n + k0),
-                               n, 1.0, A + (size_t)k1 * n + k1, n, 1);
+        // trailing: A[c1:, c1:] -= Q Q^T with Q = A[c1:, c0:c1] (lower tiles only)
+        const int mt = n - c1;
+        if (mt > 0) {
+            dim3 grid((mt + TB - 1) / TB, (mt + TB - 1) / TB);
+            hipLaunchKernelGGL(k_gemm, grid, dim3(NT), 0, c->stream, 0, 1, mt, mt, c1 - c0, -1.0,
+                               (const double*)(A + (size_t)c1 * n + c0), n, (const double*)(A + (size_t)c1 * n + c0),
+                               n, 1.0, A + (size_t)c1 * n + c1, n, 1);
             LAUNCH_OK();
         }
     }
