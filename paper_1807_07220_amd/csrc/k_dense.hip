@@ -322,11 +322,11 @@ static void dense_inverse_enqueue(tgms_ctx* c, double* A, int n, const DenseInvW
     // the recursion multiplies whole square blocks of X, whose parts above the
     // diagonal it never writes: they must be zero
     zero(c, w.X, sizeof(double) * (size_t)n * n);
-    // Two-level right-looking blocking: outer panels of OB columns are factorised by
+    // Two-level right-looking blocking: outer panels of OB (512) columns are factorised by
     // inner steps of 64 (diagonal block, panel below it, update of the rest of the outer
     // panel only); the trailing matrix is then updated once per outer panel, with
     // k = OB (OB / 64 times fewer passes over it than 64-wide updates).
-    constexpr int OB = 4 * TB;
+    constexpr int OB = 8 * TB;
     for (int c0 = 0; c0 < n; c0 += OB) {
         const int c1 = std::min(n, c0 + OB);
         for (int k0 = c0; k0 < c1; k0 += TB) {
