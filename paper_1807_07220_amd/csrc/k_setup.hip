@@ -479,27 +479,28 @@ __device__ inline double wave_max(double v) {
 
 // Number of eigenvalues of the symmetric n x n matrix T above sigma: the negative
 // pivots of the LDL^T factorisation of sigma I - T without pivoting (Sylvester's law of
-// inertia), computed in the workspace A (row stride 65); -1 when a pivot is zero
+// inertia), computed in the workspace A (row stride LD); -1 when a pivot is zero
 // relative to the largest entry of sigma I - T.
-__device__ int inertia_above(const double (*T)[65], double* A, int n, double sigma) {
+template <int LD>
+__device__ int inertia_above(const double (*T)[LD], double* A, int n, double sigma) {
     const int lane = threadIdx.x;
     double mx = 0.0;
     if (lane < n)
         for (int m = 0; m < n; ++m) {
             const double v = (lane == m ? sigma : 0.0) - T[lane][m];
-            A[lane * 65 + m] = v;
+            A[lane * LD + m] = v;
             mx = fmax(mx, fabs(v));
         }
     mx = wave_max(mx);
     __syncthreads();
     int neg = 0;
     for (int j = 0; j < n; ++j) {
-        const double d = A[j * 65 + j];
+        const double d = A[j * LD + j];
         if (fabs(d) <= 1e-14 * mx) return -1;  // the same value in every lane
         neg += d < 0.0;
         if (lane > j && lane < n) {
-            const double l = A[lane * 65 + j] / d;
-            for (int m = j + 1; m < n; ++m) A[lane * 65 + m] -= l * A[j * 65 + m];
+            const double l = A[lane * LD + j] / d;
+            for (int m = j + 1; m < n; ++m) A[lane * LD + m] -= l * A[j * LD + m];
         }
         __syncthreads();
     }
@@ -521,19 +522,24 @@ constexpr int KW = 8;  // largest warm-start block
 // theta_1 (1 - 4 rq_tol); otherwise the face falls back to the Jacobi solve.  wstat[f]:
 // the accepting iteration, or -1 (fallback).  For accepted faces only the first k
 // eigenvalues are computed (the rest are stored as 0).
-template <int WARM>
+// JM >= jmax: the LDS tiles are sized for the widest face of the grid (several
+// workgroups share a CU when the faces are short).
+template <int WARM, int JM>
 __global__ void __launch_bounds__(64) k_pencil_eig(BlockGeom G, const double* __restrict__ kinv,
                                                    const double* __restrict__ Gm, double tol, double invH,
                                                    double* __restrict__ eigs, int* __restrict__ counts,
                                                    double* __restrict__ Yout, double* __restrict__ Qout,
                                                    const float* __restrict__ Y0, int kblk, double rq_tol, int max_it,
                                                    int* __restrict__ wstat, float* __restrict__ Vtop) {
-    __shared__ double T[64][65];
-    __shared__ double V[64][65];
-    __shared__ double D[64];
-    __shared__ double cs[32][2];
-    __shared__ int order[64];
+    constexpr int LD = JM + 1;
+    __shared__ double T[JM][LD];
+    __shared__ double V[JM][LD];
+    __shared__ double D[JM];
+    __shared__ double cs[JM / 2][2];
+    __shared__ int order[JM];
     __shared__ int rot_flag;
+    // the subspace iteration's X, T X (rows < JM) and Rayleigh-Ritz matrices
+    __shared__ double Wk[WARM ? 2 * JM * KW + 2 * KW * 9 : 1];
     const int fid = blockIdx.x, lane = threadIdx.x;
     const int nex = (G.Nx - 1) * G.Ny;
     int K1, K2, s1, s2, Jn;
@@ -592,13 +598,13 @@ __global__ void __launch_bounds__(64) k_pencil_eig(BlockGeom G, const double* __
     if constexpr (WARM) {
         const double sigma = 1.0 / tol;
         const int kk = min(kblk, Jn);
-        double* A = &V[0][0];  // LDS workspace (V is not needed before a fallback)
-        const int cnt0 = inertia_above(T, A, Jn, sigma);
+        double* A = &V[0][0];  // LDS workspace of the inertia count (V is not needed before a fallback)
+        const int cnt0 = inertia_above<LD>(T, A, Jn, sigma);
         const int l = max(cnt0, 1);
         if (cnt0 >= 0 && l < kk) {
-            double* Xs = A;            // [64][KW] rows of X, then of U
-            double* Ws = A + 64 * KW;  // [64][KW] rows of T X
-            double* Hs = Ws + 64 * KW; // [KW][9]  X^T T X, then its diagonal form
+            double* Xs = Wk;           // [JM][KW] rows of X, then of U
+            double* Ws = Wk + JM * KW;  // [JM][KW] rows of T X
+            double* Hs = Ws + JM * KW; // [KW][9]  X^T T X, then its diagonal form
             double* Zs = Hs + KW * 9;  // [KW][9]  its eigenvectors
             double x[KW], w[KW];
 #pragma unroll
@@ -628,8 +634,9 @@ __global__ void __launch_bounds__(64) k_pencil_eig(BlockGeom G, const double* __
                 }
                 if (!rank_ok) break;
                 // W = T X
+                if (lane < JM)
 #pragma unroll
-                for (int c = 0; c < KW; ++c) Xs[lane * KW + c] = x[c];
+                    for (int c = 0; c < KW; ++c) Xs[lane * KW + c] = x[c];
                 __syncthreads();
 #pragma unroll
                 for (int c = 0; c < KW; ++c) w[c] = 0.0;
@@ -639,8 +646,9 @@ __global__ void __launch_bounds__(64) k_pencil_eig(BlockGeom G, const double* __
 #pragma unroll
                         for (int c = 0; c < KW; ++c) w[c] += t * Xs[m * KW + c];
                     }
+                if (lane < JM)
 #pragma unroll
-                for (int c = 0; c < KW; ++c) Ws[lane * KW + c] = w[c];
+                    for (int c = 0; c < KW; ++c) Ws[lane * KW + c] = w[c];
                 __syncthreads();
                 // H = X^T W (kk x kk), symmetrised, and its eigenpairs
                 if (lane < kk * kk) {
@@ -697,8 +705,9 @@ __global__ void __launch_bounds__(64) k_pencil_eig(BlockGeom G, const double* __
                 if (ok) {
                     // outputs from the Ritz pairs (U staged through LDS, row = lane)
                     __syncthreads();
+                    if (lane < JM)
 #pragma unroll
-                    for (int c = 0; c < KW; ++c) Xs[lane * KW + c] = u[c];
+                        for (int c = 0; c < KW; ++c) Xs[lane * KW + c] = u[c];
                     for (int k = lane; k < G.jmax; k += 64) {
                         double val = 0.0;
 #pragma unroll
@@ -713,7 +722,7 @@ __global__ void __launch_bounds__(64) k_pencil_eig(BlockGeom G, const double* __
                     }
                     __syncthreads();
                     accepted = true;
-                    if (cnt0 == 0) accepted = inertia_above(T, A, Jn, th[0] * (1.0 - 4.0 * rq_tol)) == 1;
+                    if (cnt0 == 0) accepted = inertia_above<LD>(T, A, Jn, th[0] * (1.0 - 4.0 * rq_tol)) == 1;
                     if (accepted) {
                         cnt = l;
                         if (lane == 0) {
@@ -737,7 +746,7 @@ __global__ void __launch_bounds__(64) k_pencil_eig(BlockGeom G, const double* __
             V[l][mm] = (l == mm) ? 1.0 : 0.0;
         }
         __syncthreads();
-        jacobi_rr(&T[0][0], &V[0][0], 65, Jn, cs, &rot_flag);
+        jacobi_rr(&T[0][0], &V[0][0], LD, Jn, cs, &rot_flag);
         // sort mu descending (lambda = 1/mu ascending)
         if (lane < Jn) {
             const double mu = T[lane][lane];
@@ -769,24 +778,24 @@ __global__ void __launch_bounds__(64) k_pencil_eig(BlockGeom G, const double* __
     // recombination Q (cnt x cnt): column 0 = f/|f|^2 (unit-flux carrier), columns 1.. = an
     // orthonormal basis of f^perp (Householder reflector mapping f/|f| to e_1); stored in LDS
     // (V is free now), then YQ = Y Q (jmax x jmax, rows l < Jn, columns k < cnt) to Qout.
-    double* Qs = &V[0][0];  // Qs[k2 * 65 + k]
+    double* Qs = &V[0][0];  // Qs[k2 * LD + k]
     if (lane == 0) {
-        double f[64], nrm2 = 0.0;
+        double f[JM], nrm2 = 0.0;
         for (int k = 0; k < cnt; ++k) {
             double s = 0.0;
             for (int l = 0; l < Jn; ++l) s += Yf[l * G.jmax + k];
             f[k] = elen * s;
             nrm2 += f[k] * f[k];
         }
-        for (int k = 0; k < cnt; ++k) Qs[k * 65] = f[k] / nrm2;
+        for (int k = 0; k < cnt; ++k) Qs[k * LD] = f[k] / nrm2;
         if (cnt > 1) {
             const double nr = sqrt(nrm2);
-            double w[64], ww = 0.0;
+            double w[JM], ww = 0.0;
             for (int k = 0; k < cnt; ++k) w[k] = f[k] / nr;
             w[0] += (w[0] >= 0 ? 1.0 : -1.0);
             for (int k = 0; k < cnt; ++k) ww += w[k] * w[k];
             for (int r = 0; r < cnt; ++r)
-                for (int cc = 1; cc < cnt; ++cc) Qs[r * 65 + cc] = ((r == cc) ? 1.0 : 0.0) - 2.0 * w[r] * w[cc] / ww;
+                for (int cc = 1; cc < cnt; ++cc) Qs[r * LD + cc] = ((r == cc) ? 1.0 : 0.0) - 2.0 * w[r] * w[cc] / ww;
         }
     }
     __syncthreads();
@@ -795,7 +804,7 @@ __global__ void __launch_bounds__(64) k_pencil_eig(BlockGeom G, const double* __
         const int l = e / G.jmax, k = e % G.jmax;
         double s = 0.0;
         if (l < Jn && k < cnt)
-            for (int k2 = 0; k2 < cnt; ++k2) s += Yf[l * G.jmax + k2] * Qs[k2 * 65 + k];
+            for (int k2 = 0; k2 < cnt; ++k2) s += Yf[l * G.jmax + k2] * Qs[k2 * LD + k];
         Qf[e] = s;
     }
 }
@@ -1126,17 +1135,32 @@ void gram(tgms_ctx* c) {
 // Entry points used by the host orchestrator (api.hip) that need the kernels above.
 namespace tgms {
 
-void pencil_eig_q(tgms_ctx* c, double* Q, const float* Y0, float* Vtop) {
-    BlockGeom G = geom(c);
+template <int JM>
+static void pencil_eig_launch(tgms_ctx* c, const BlockGeom& G, double* Q, const float* Y0, float* Vtop) {
     if (c->warm)
-        hipLaunchKernelGGL(k_pencil_eig<1>, dim3(c->ne), dim3(64), 0, c->stream, G, c->kinv, c->G, c->tol,
+        hipLaunchKernelGGL((k_pencil_eig<1, JM>), dim3(c->ne), dim3(64), 0, c->stream, G, c->kinv, c->G, c->tol,
                            1.0 / c->H, c->eigs, c->counts, c->Y, Q, Y0, KW, c->rq_tol, c->warm_maxit, c->wstat,
                            (float*)nullptr);
     else
-        hipLaunchKernelGGL(k_pencil_eig<0>, dim3(c->ne), dim3(64), 0, c->stream, G, c->kinv, c->G, c->tol,
+        hipLaunchKernelGGL((k_pencil_eig<0, JM>), dim3(c->ne), dim3(64), 0, c->stream, G, c->kinv, c->G, c->tol,
                            1.0 / c->H, c->eigs, c->counts, c->Y, Q, (const float*)nullptr, 0, 0.0, 0, (int*)nullptr,
                            Vtop);
     LAUNCH_OK();
+}
+
+void pencil_eig_q(tgms_ctx* c, double* Q, const float* Y0, float* Vtop) {
+    BlockGeom G = geom(c);
+    // LDS tiles sized for the widest face (jmax = max(bx, by) cells)
+    if (G.jmax <= 8)
+        pencil_eig_launch<8>(c, G, Q, Y0, Vtop);
+    else if (G.jmax <= 16)
+        pencil_eig_launch<16>(c, G, Q, Y0, Vtop);
+    else if (G.jmax <= 32)
+        pencil_eig_launch<32>(c, G, Q, Y0, Vtop);
+    else if (G.jmax <= 64)
+        pencil_eig_launch<64>(c, G, Q, Y0, Vtop);
+    else
+        throw TgmsError{TGMS_E_UNSUPPORTED, "coarse face wider than 64 cells"};
 }
 
 void fill_td(tgms_ctx* c, const int* meta, const double* YQ, double* Td) {
