@@ -145,72 +145,97 @@ __global__ void k_copy_diag_blocks(const double* __restrict__ Dinv, double* __re
 }
 
 // Cholesky of the kb x kb diagonal block at (k0, k0) in place, and its inverse into Dinv (kb x kb, ld 64).
-// Thread (ty, tx) owns rows ty + 16 r and columns tx + 16 s of the 64 x 64 tile.
 //
-// One right-looking sweep forms both, with one barrier per pivot: with d_j the
-// pivot and m_ij = S[i][j] / d_j (the unit lower factor, A = Lu diag(d) Lu^T), step j
-// updates the trailing lower triangle S[i][k] -= m_ij S[k][j] (j < k <= i) and the
-// rows below j of U (U = I at the start, Lu^{-1} at the end) U[i][c] -= m_ij U[j][c]
-// (c <= j).  Column j of S and row j of U are final when step j reads them, and step
-// j writes neither, so the reads and writes of one step do not overlap.  Then
-// L = Lu diag(d)^{1/2} and L^{-1} = diag(d)^{-1/2} U.  (The 64 dependent steps bound
-// the kernel: keeping the tiles in registers and publishing one column per step
-// through LDS measured slower.)
+// One right-looking sweep forms both: with d_j the pivot and m_ij = S[i][j] / d_j (the
+// unit lower factor, A = Lu diag(d) Lu^T), step j updates the trailing lower triangle
+// S[i][k] -= m_ij S[k][j] (j < k <= i) and the rows below j of U (U = I at the start,
+// Lu^{-1} at the end) U[i][c] -= m_ij U[j][c] (c <= j).  Then L = Lu diag(d)^{1/2} and
+// L^{-1} = diag(d)^{-1/2} U.
+//
+// Thread (ty, tx) keeps rows 4 ty .. 4 ty + 3 by columns 4 tx .. 4 tx + 3 of S and U
+// in registers.  Column j of S and row j of U are final when step j starts; their
+// owners publish them to LDS, double-buffered by the parity of j, so each step has
+// one barrier (a buffer is rewritten two steps later, after every thread has passed
+// the barrier that follows its last read).
 __global__ void __launch_bounds__(NT) k_potrf_diag(double* __restrict__ A, int lda, int k0, int kb,
                                                    double* __restrict__ Dinv, int* __restrict__ fail) {
-    __shared__ double S[TB][TB + 1];
-    __shared__ double U[TB][TB + 1];
+    __shared__ __align__(16) double colb[2][TB];
+    __shared__ __align__(16) double rowb[2][TB];
+    __shared__ __align__(16) double dg[TB];
     const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+    const int i0 = 4 * ty, c0 = 4 * tx;
+    double S[4][4], U[4][4];
+#pragma unroll
     for (int r = 0; r < 4; ++r)
-        for (int q = 0; q < 4; ++q) {
-            const int i = ty + 16 * r, j = tx + 16 * q;
-            S[i][j] = (i < kb && j < kb && j <= i) ? A[(long long)(k0 + i) * lda + k0 + j] : (i == j ? 1.0 : 0.0);
-            U[i][j] = i == j ? 1.0 : 0.0;
-        }
-    __syncthreads();
-    for (int j = 0; j < kb; ++j) {
-        const double d = S[j][j];
-        if (!(d > 0.0)) {  // every thread reads the same pivot: all leave together
-            if (tid == 0) atomicOr(fail, 1);
-            return;
-        }
-        const double rd = 1.0 / d;
-        double skj[4], ujk[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int k = tx + 16 * q;
-            skj[q] = S[k][j];
-            ujk[q] = U[j][k];
+            const int i = i0 + r, k = c0 + q;
+            S[r][q] = (i < kb && k <= i) ? A[(long long)(k0 + i) * lda + k0 + k] : (i == k ? 1.0 : 0.0);
+            U[r][q] = i == k ? 1.0 : 0.0;
         }
+    const int jtn = (kb + 3) / 4;
+    for (int jt = 0; jt < jtn; ++jt) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = ty + 16 * r;
-            if (i <= j || i >= kb) continue;
-            const double mij = S[i][j] * rd;
+        for (int jq = 0; jq < 4; ++jq) {
+            const int j = 4 * jt + jq;
+            if (j < kb) {  // the same value in every thread
+                double* cb = colb[j & 1];
+                double* rb = rowb[j & 1];
+                if (tx == jt)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int k = tx + 16 * q;
-                if (k > j && k <= i) S[i][k] -= mij * skj[q];
-                if (k <= j) U[i][k] -= mij * ujk[q];
+                    for (int r = 0; r < 4; ++r) cb[i0 + r] = S[r][jq];
+                if (ty == jt)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) rb[c0 + q] = U[jq][q];
+                __syncthreads();
+                const double d = cb[j];
+                if (!(d > 0.0)) {  // every thread reads the same pivot: all leave together
+                    if (tid == 0) atomicOr(fail, 1);
+                    return;
+                }
+                const double rd = 1.0 / d;
+                const double2 ci0 = *reinterpret_cast<const double2*>(cb + i0);
+                const double2 ci1 = *reinterpret_cast<const double2*>(cb + i0 + 2);
+                const double2 ck0 = *reinterpret_cast<const double2*>(cb + c0);
+                const double2 ck1 = *reinterpret_cast<const double2*>(cb + c0 + 2);
+                const double2 uj0 = *reinterpret_cast<const double2*>(rb + c0);
+                const double2 uj1 = *reinterpret_cast<const double2*>(rb + c0 + 2);
+                const double ci[4] = {ci0.x, ci0.y, ci1.x, ci1.y};
+                const double ck[4] = {ck0.x, ck0.y, ck1.x, ck1.y};
+                const double uj[4] = {uj0.x, uj0.y, uj1.x, uj1.y};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = i0 + r;
+                    const double m = i > j ? ci[r] * rd : 0.0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int k = c0 + q;
+                        const double sv = S[r][q] - m * ck[q], uv = U[r][q] - m * uj[q];
+                        S[r][q] = (k > j && k <= i) ? sv : S[r][q];
+                        U[r][q] = (k <= j) ? uv : U[r][q];
+                    }
+                }
             }
         }
-        __syncthreads();
     }
+    if (tx == ty)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dg[i0 + r] = S[r][r];
+    __syncthreads();
     double si[4], sk[4];  // sqrt(d) of the owned rows and columns
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int i = ty + 16 * r, k = tx + 16 * r;
-        si[r] = i < kb ? sqrt(S[i][i]) : 1.0;
-        sk[r] = k < kb ? sqrt(S[k][k]) : 1.0;
+        si[r] = i0 + r < kb ? sqrt(dg[i0 + r]) : 1.0;
+        sk[r] = c0 + r < kb ? sqrt(dg[c0 + r]) : 1.0;
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int i = ty + 16 * r, k = tx + 16 * q;
+            const int i = i0 + r, k = c0 + q;
             const bool in = i < kb && k < kb && k <= i;
-            if (in) A[(long long)(k0 + i) * lda + k0 + k] = (k == i) ? si[r] : S[i][k] / sk[q];
-            Dinv[i * TB + k] = in ? U[i][k] / si[r] : 0.0;
+            if (in) A[(long long)(k0 + i) * lda + k0 + k] = (k == i) ? si[r] : S[r][q] / sk[q];
+            Dinv[i * TB + k] = in ? U[r][q] / si[r] : 0.0;
         }
 }
 
