@@ -511,6 +511,19 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
             Timer t(c->stream);
             blk_fail = c->alloc<int>(1);
             tgms::factor_blocks(c, blk_fail);
+            // snapshots + Gram (queued before the coarse RT0 inverse on the second stream:
+            // queueing that inverse's few hundred launches takes the host milliseconds,
+            // which these kernels then cover)
+            c->Psi = c->alloc<double>((size_t)c->nblk * c->ncol * c->nfk);
+            // A_K Psi for the Gram kernel without matrix cores; the path integrals of the
+            // coarse assembly reuse it (nblk * (bx+1)(by+1) * ncol)
+            const bool gram_mfma = tgms::gram_uses_mfma(c);
+            const size_t nvk = (size_t)(bx + 1) * (by + 1);
+            c->APsi = c->alloc<double>((size_t)c->nblk * c->ncol * (gram_mfma ? nvk : (size_t)c->nfk));
+            c->G = c->alloc<double>((size_t)c->nblk * c->ncol * c->ncol);
+            // the A Psi array is free until the Gram products: the snapshot solves' scratch
+            tgms::snapshots(c, c->APsi, (long long)c->ncol * (gram_mfma ? (long long)nvk : (long long)c->nfk));
+            tgms::gram(c);
             {
                 const hipStream_t main_stream = c->stream;
                 struct Restore {
@@ -524,17 +537,6 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                 tgms::dense_spd_inverse_begin(c, c->KH, c->nv, kh_inv);
             }
             HIP_OK(hipEventRecord(side.e1, side.s));
-            // snapshots + Gram
-            c->Psi = c->alloc<double>((size_t)c->nblk * c->ncol * c->nfk);
-            // A_K Psi for the Gram kernel without matrix cores; the path integrals of the
-            // coarse assembly reuse it (nblk * (bx+1)(by+1) * ncol)
-            const bool gram_mfma = tgms::gram_uses_mfma(c);
-            const size_t nvk = (size_t)(bx + 1) * (by + 1);
-            c->APsi = c->alloc<double>((size_t)c->nblk * c->ncol * (gram_mfma ? nvk : (size_t)c->nfk));
-            c->G = c->alloc<double>((size_t)c->nblk * c->ncol * c->ncol);
-            // the A Psi array is free until the Gram products: the snapshot solves' scratch
-            tgms::snapshots(c, c->APsi, (long long)c->ncol * (gram_mfma ? (long long)nvk : (long long)c->nfk));
-            tgms::gram(c);
             c->t_snap_ms = t.ms();
             // the block factorisation, checked once the GPU has reached this point (before
             // the spectral problems use the snapshots)
@@ -645,7 +647,12 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                 } restore{c, main_stream};
                 c->stream = side.s;
                 pat_timer.start(side.s);
-                tgms::factor_patches_launch(c, pat_fail);
+                // two workgroups per CU: the serial chain of the coarse Cholesky on the
+                // main stream keeps CUs to run on
+                int cus = 0, dev = 0;
+                HIP_OK(hipGetDevice(&dev));
+                if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+                tgms::factor_patches_launch(c, pat_fail, 2 * cus);
                 pat_timer.stop(side.s);
             }
             HIP_OK(hipEventRecord(side.e2, side.s));

@@ -345,8 +345,9 @@ void zero(tgms_ctx* c, void* p, size_t bytes);
 // band factors and smoother (k_band.hip)
 void factor_blocks(tgms_ctx* c, int* fail = nullptr);  // fail: checked later by the caller (null: here)
 void factor_patches(tgms_ctx* c);
-// the same without waiting: a failed factorisation sets *fail (zero on entry)
-void factor_patches_launch(tgms_ctx* c, int* fail);
+// the same without waiting: a failed factorisation sets *fail (zero on entry);
+// max_groups > 0 bounds the workgroups (each then factors several patches in turn)
+void factor_patches_launch(tgms_ctx* c, int* fail, int max_groups);
 template <typename T>
 void smooth_patches(tgms_ctx* c, const T* g, const double* sc, const struct FusedUpdate* fu = nullptr,
                     const PreResidual<T>* pr = nullptr);  // local solves of S g into the patch pool

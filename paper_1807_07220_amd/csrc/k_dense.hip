@@ -146,21 +146,28 @@ __global__ void k_copy_diag_blocks(const double* __restrict__ Dinv, double* __re
 
 // Cholesky of the kb x kb diagonal block at (k0, k0) in place, and its inverse into Dinv (kb x kb, ld 64).
 //
-// One right-looking sweep forms both: with d_j the pivot and m_ij = S[i][j] / d_j (the
-// unit lower factor, A = Lu diag(d) Lu^T), step j updates the trailing lower triangle
-// S[i][k] -= m_ij S[k][j] (j < k <= i) and the rows below j of U (U = I at the start,
-// Lu^{-1} at the end) U[i][c] -= m_ij U[j][c] (c <= j).  Then L = Lu diag(d)^{1/2} and
+// Right-looking LDL^T with both factors formed in one sweep: with d_j the pivots and
+// Lu the unit lower factor (A = Lu diag(d) Lu^T), S ends holding Lu[i][j] d_j below the
+// diagonal and d_i on it, and U (= I at the start) ends holding Lu^{-1}, by the row
+// operations U[i] -= Lu[i][j] U[j].  Then L = Lu diag(d)^{1/2} and
 // L^{-1} = diag(d)^{-1/2} U.
 //
-// Thread (ty, tx) keeps rows 4 ty .. 4 ty + 3 by columns 4 tx .. 4 tx + 3 of S and U
-// in registers.  Column j of S and row j of U are final when step j starts; their
-// owners publish them to LDS, double-buffered by the parity of j, so each step has
-// one barrier (a buffer is rewritten two steps later, after every thread has passed
-// the barrier that follows its last read).
+// Pivots are taken in panels of 4 (one barrier each).  Thread (ty, tx) keeps rows
+// 4 ty .. 4 ty + 3 by columns 4 tx .. 4 tx + 3 of S and U in registers.  The owners
+// of the panel's columns of S and rows of U publish them to LDS (double-buffered by
+// the panel's parity: a buffer is rewritten two panels later, after every thread
+// has passed the barrier that follows its last read).  Every thread then factors the
+// 4 x 4 pivot block itself, forward-substitutes the panel entries of its own rows
+// and columns (w_i[a] = Lu[i][j+a] d_{j+a}), eliminates within the panel rows of U,
+// and applies the rank-4 update S[i][k] -= sum_a Lu[i][j+a] w_k[a],
+// U[i] -= sum_a Lu[i][j+a] U[j+a] to rows below the panel.  The multipliers of rows
+// at or above the panel and the w of columns at or left of it are zero, so those
+// entries are unchanged exactly; entries above the diagonal of S are never read.
+// Rows and columns past kb are the identity (unit pivots, no coupling).
 __global__ void __launch_bounds__(NT) k_potrf_diag(double* __restrict__ A, int lda, int k0, int kb,
                                                    double* __restrict__ Dinv, int* __restrict__ fail) {
-    __shared__ __align__(16) double colb[2][TB];
-    __shared__ __align__(16) double rowb[2][TB];
+    __shared__ __align__(16) double colp[2][TB][4];
+    __shared__ __align__(16) double rowp[2][4][TB];
     __shared__ __align__(16) double dg[TB];
     const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
     const int i0 = 4 * ty, c0 = 4 * tx;
@@ -175,48 +182,144 @@ __global__ void __launch_bounds__(NT) k_potrf_diag(double* __restrict__ A, int l
         }
     const int jtn = (kb + 3) / 4;
     for (int jt = 0; jt < jtn; ++jt) {
+        const int j = 4 * jt, pb = jt & 1;
+        if (tx == jt)
 #pragma unroll
-        for (int jq = 0; jq < 4; ++jq) {
-            const int j = 4 * jt + jq;
-            if (j < kb) {  // the same value in every thread
-                double* cb = colb[j & 1];
-                double* rb = rowb[j & 1];
-                if (tx == jt)
+            for (int r = 0; r < 4; ++r) {
+                *reinterpret_cast<double2*>(&colp[pb][i0 + r][0]) = make_double2(S[r][0], S[r][1]);
+                *reinterpret_cast<double2*>(&colp[pb][i0 + r][2]) = make_double2(S[r][2], S[r][3]);
+            }
+        if (ty == jt)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) cb[i0 + r] = S[r][jq];
-                if (ty == jt)
+            for (int a = 0; a < 4; ++a) {
+                *reinterpret_cast<double2*>(&rowp[pb][a][c0]) = make_double2(U[a][0], U[a][1]);
+                *reinterpret_cast<double2*>(&rowp[pb][a][c0 + 2]) = make_double2(U[a][2], U[a][3]);
+            }
+        __syncthreads();
+        // LDL^T of the pivot block: w[a][b] (b < a) = Lu[j+a][j+b] d_{j+b}, l[a][b] = Lu[j+a][j+b]
+        double P[4][4];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) rb[c0 + q] = U[jq][q];
-                __syncthreads();
-                const double d = cb[j];
-                if (!(d > 0.0)) {  // every thread reads the same pivot: all leave together
-                    if (tid == 0) atomicOr(fail, 1);
-                    return;
+        for (int a = 0; a < 4; ++a) {
+            const double2 x = *reinterpret_cast<const double2*>(&colp[pb][j + a][0]);
+            const double2 y = *reinterpret_cast<const double2*>(&colp[pb][j + a][2]);
+            P[a][0] = x.x;
+            P[a][1] = x.y;
+            P[a][2] = y.x;
+            P[a][3] = y.y;
+        }
+        double d[4], rd[4], w[4][4], l[4][4];
+        bool ok = true;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            double da = P[a][a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (b < a) {
+                    double t = P[a][b];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (e < b) t -= l[b][e] * w[a][e];
+                    w[a][b] = t;
+                    l[a][b] = t * rd[b];
+                    da -= l[a][b] * t;
                 }
-                const double rd = 1.0 / d;
-                const double2 ci0 = *reinterpret_cast<const double2*>(cb + i0);
-                const double2 ci1 = *reinterpret_cast<const double2*>(cb + i0 + 2);
-                const double2 ck0 = *reinterpret_cast<const double2*>(cb + c0);
-                const double2 ck1 = *reinterpret_cast<const double2*>(cb + c0 + 2);
-                const double2 uj0 = *reinterpret_cast<const double2*>(rb + c0);
-                const double2 uj1 = *reinterpret_cast<const double2*>(rb + c0 + 2);
-                const double ci[4] = {ci0.x, ci0.y, ci1.x, ci1.y};
-                const double ck[4] = {ck0.x, ck0.y, ck1.x, ck1.y};
-                const double uj[4] = {uj0.x, uj0.y, uj1.x, uj1.y};
+            d[a] = da;
+            ok = ok && da > 0.0;
+            rd[a] = 1.0 / da;
+        }
+        if (!ok) {  // every thread computed the same pivots: all leave together
+            if (tid == 0) atomicOr(fail, 1);
+            return;
+        }
+        // panel entries of the own rows (w, and the multipliers v of rows below the panel)
+        double wr[4][4], vr[4][4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = i0 + r;
-                    const double m = i > j ? ci[r] * rd : 0.0;
+        for (int r = 0; r < 4; ++r) {
+            const double2 x = *reinterpret_cast<const double2*>(&colp[pb][i0 + r][0]);
+            const double2 y = *reinterpret_cast<const double2*>(&colp[pb][i0 + r][2]);
+            const double sv[4] = {x.x, x.y, y.x, y.y};
+            const bool below = i0 + r >= j + 4;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int k = c0 + q;
-                        const double sv = S[r][q] - m * ck[q], uv = U[r][q] - m * uj[q];
-                        S[r][q] = (k > j && k <= i) ? sv : S[r][q];
-                        U[r][q] = (k <= j) ? uv : U[r][q];
-                    }
-                }
+            for (int a = 0; a < 4; ++a) {
+                double t = sv[a];
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (e < a) t -= l[a][e] * wr[r][e];
+                wr[r][a] = t;
+                vr[r][a] = below ? t * rd[a] : 0.0;
             }
         }
+        // panel entries of the own columns (zero for columns at or left of the panel)
+        double wc[4][4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double2 x = *reinterpret_cast<const double2*>(&colp[pb][c0 + q][0]);
+            const double2 y = *reinterpret_cast<const double2*>(&colp[pb][c0 + q][2]);
+            const double sv[4] = {x.x, x.y, y.x, y.y};
+            double t4[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                double t = sv[a];
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (e < a) t -= l[a][e] * t4[e];
+                t4[a] = t;
+            }
+            const bool right = c0 + q >= j + 4;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) wc[q][a] = right ? t4[a] : 0.0;
+        }
+        // the panel rows of U, eliminated within the panel (own columns)
+        double uf[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const double2 x = *reinterpret_cast<const double2*>(&rowp[pb][a][c0]);
+            const double2 y = *reinterpret_cast<const double2*>(&rowp[pb][a][c0 + 2]);
+            const double uv[4] = {x.x, x.y, y.x, y.y};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                double t = uv[q];
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (e < a) t -= l[a][e] * uf[e][q];
+                uf[a][q] = t;
+            }
+        }
+        // rank-4 update of the rows below the panel
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                double sv = S[r][q], uv = U[r][q];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    sv -= vr[r][a] * wc[q][a];
+                    uv -= vr[r][a] * uf[a][q];
+                }
+                S[r][q] = sv;
+                U[r][q] = uv;
+            }
+        // final values of the panel's columns of S and rows of U
+        if (tx == jt) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (i0 + r >= j + 4)
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) S[r][a] = wr[r][a];
+            if (ty == jt)
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        if (b < a) S[a][b] = w[a][b];
+                    S[a][a] = d[a];
+                }
+        }
+        if (ty == jt)
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) U[a][q] = uf[a][q];
     }
     if (tx == ty)
 #pragma unroll

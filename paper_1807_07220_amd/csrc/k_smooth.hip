@@ -75,128 +75,133 @@ struct PatchStencil {
 
 __global__ void __launch_bounds__(64) k_patch_factor(const Rect* __restrict__ rects, const double* __restrict__ a,
                                                      int nx, double sx2, double sy2, double* __restrict__ Fpool,
-                                                     int* __restrict__ fail) {
+                                                     int* __restrict__ fail, int npatch) {
     extern __shared__ double sm[];
-    const Rect R = rects[blockIdx.x];
-    const int m = R.i1 - R.i0 - 1, mh = R.j1 - R.j0 - 1;
-    const int n = m * mh, mm = m * m, k = mh / 2;
-    const int lane = threadIdx.x;
-    double* kc = sm;
-    double* ke = kc + n;
-    double* kn = ke + n;
-    double* kne = kn + n;
-    double* knw = kne + n;
-    double* S = knw + n;
-    double* W = S + n;
-    double* G = W + mm;
-    double* Mid = G + mm;
-    double* F = Fpool + R.off;
-    double* Pout = F;
-    double* Lout = F + tw_links(m, mh);
-    double* Sout = F + tw_scale(m, mh);
-    // stencil couplings of each interior vertex with its east, north, north-east
-    // and north-west neighbours (zero where the neighbour is not a patch vertex)
-    for (int r = lane; r < n; r += 64) {
-        const int aa = r % m, bb = r / m;
-        const int i = R.i0 + 1 + aa, j = R.j0 + 1 + bb;
-        const long long v = (long long)j * nx + i;
-        const Stencil9 st = stencil9(a[v - nx - 1], a[v - nx], a[v - 1], a[v], sx2, sy2);
-        kc[r] = st.c;
-        ke[r] = (aa + 1 < m) ? st.e : 0.0;
-        const bool up = bb + 1 < mh;
-        kn[r] = up ? st.n : 0.0;
-        kne[r] = (up && aa + 1 < m) ? st.ne : 0.0;
-        knw[r] = (up && aa >= 1) ? st.nw : 0.0;
-        S[r] = 1.0 / sqrt(st.c);
-    }
-    __syncthreads();
-    for (int r = lane; r < n; r += 64) {
-        const int aa = r % m, bb = r / m;
-        const double s = S[r];
-        kc[r] *= s * s;
-        if (aa + 1 < m) ke[r] *= s * S[r + 1];
-        if (bb + 1 < mh) {
-            kn[r] *= s * S[r + m];
-            if (aa + 1 < m) kne[r] *= s * S[r + m + 1];
-            if (aa >= 1) knw[r] *= s * S[r + m - 1];
+    // a grid-stride loop over the patches: a smaller grid leaves room on the GPU for
+    // kernels of other streams
+    for (int pid = blockIdx.x; pid < npatch; pid += gridDim.x) {
+        const Rect R = rects[pid];
+        const int m = R.i1 - R.i0 - 1, mh = R.j1 - R.j0 - 1;
+        const int n = m * mh, mm = m * m, k = mh / 2;
+        const int lane = threadIdx.x;
+        double* kc = sm;
+        double* ke = kc + n;
+        double* kn = ke + n;
+        double* kne = kn + n;
+        double* knw = kne + n;
+        double* S = knw + n;
+        double* W = S + n;
+        double* G = W + mm;
+        double* Mid = G + mm;
+        double* F = Fpool + R.off;
+        double* Pout = F;
+        double* Lout = F + tw_links(m, mh);
+        double* Sout = F + tw_scale(m, mh);
+        // stencil couplings of each interior vertex with its east, north, north-east
+        // and north-west neighbours (zero where the neighbour is not a patch vertex)
+        for (int r = lane; r < n; r += 64) {
+            const int aa = r % m, bb = r / m;
+            const int i = R.i0 + 1 + aa, j = R.j0 + 1 + bb;
+            const long long v = (long long)j * nx + i;
+            const Stencil9 st = stencil9(a[v - nx - 1], a[v - nx], a[v - 1], a[v], sx2, sy2);
+            kc[r] = st.c;
+            ke[r] = (aa + 1 < m) ? st.e : 0.0;
+            const bool up = bb + 1 < mh;
+            kn[r] = up ? st.n : 0.0;
+            kne[r] = (up && aa + 1 < m) ? st.ne : 0.0;
+            knw[r] = (up && aa >= 1) ? st.nw : 0.0;
+            S[r] = 1.0 / sqrt(st.c);
         }
-        Sout[r] = s;
-    }
-    __syncthreads();
-    const PatchStencil P{kc, ke, kn, kne, knw, m};
-    for (int e = lane; e < mm; e += 64) Mid[e] = P.A(k, e / m, e % m);
-    auto store_pivot = [&](int j) {
-        for (int e = lane; e < mm; e += 64) {
-            const int r = e / m, s = e - r * m;
-            if (r >= s) Pout[(long long)j * tw_tri(m) + tw_offP(s, m) + (r - s)] = W[e];
+        __syncthreads();
+        for (int r = lane; r < n; r += 64) {
+            const int aa = r % m, bb = r / m;
+            const double s = S[r];
+            kc[r] *= s * s;
+            if (aa + 1 < m) ke[r] *= s * S[r + 1];
+            if (bb + 1 < mh) {
+                kn[r] *= s * S[r + m];
+                if (aa + 1 < m) kne[r] *= s * S[r + m + 1];
+                if (aa >= 1) knw[r] *= s * S[r + m - 1];
+            }
+            Sout[r] = s;
         }
-    };
-    // top sweep: rows 0..k-1
-    if (k >= 1)
-        for (int e = lane; e < mm; e += 64) W[e] = P.A(0, e / m, e % m);
-    __syncthreads();
-    for (int j = 0; j < k; ++j) {
+        __syncthreads();
+        const PatchStencil P{kc, ke, kn, kne, knw, m};
+        for (int e = lane; e < mm; e += 64) Mid[e] = P.A(k, e / m, e % m);
+        auto store_pivot = [&](int j) {
+            for (int e = lane; e < mm; e += 64) {
+                const int r = e / m, s = e - r * m;
+                if (r >= s) Pout[(long long)j * tw_tri(m) + tw_offP(s, m) + (r - s)] = W[e];
+            }
+        };
+        // top sweep: rows 0..k-1
+        if (k >= 1)
+            for (int e = lane; e < mm; e += 64) W[e] = P.A(0, e / m, e % m);
+        __syncthreads();
+        for (int j = 0; j < k; ++j) {
+            gj_invert(W, m, fail);
+            store_pivot(j);
+            // G = B_j T_j^{-1}; B_j[r][s] = kn(s) (r = s), kne(s) (r = s+1), knw(s) (r = s-1) at row j
+            const int o = j * m;
+            for (int e = lane; e < mm; e += 64) {
+                const int r = e / m, s = e - r * m;
+                double g = kn[o + r] * W[r * m + s];
+                if (r >= 1) g += kne[o + r - 1] * W[(r - 1) * m + s];
+                if (r + 1 < m) g += knw[o + r + 1] * W[(r + 1) * m + s];
+                G[e] = g;
+                Lout[(long long)j * mm + e] = g;
+            }
+            __syncthreads();
+            // G B_j^T, subtracted from the next diagonal block (or from the middle one)
+            for (int e = lane; e < mm; e += 64) {
+                const int r = e / m, s = e - r * m;
+                double cb = G[r * m + s] * kn[o + s];
+                if (s >= 1) cb += G[r * m + s - 1] * kne[o + s - 1];
+                if (s + 1 < m) cb += G[r * m + s + 1] * knw[o + s + 1];
+                if (j + 1 < k)
+                    W[e] = P.A(j + 1, r, s) - cb;
+                else
+                    Mid[e] -= cb;
+            }
+            __syncthreads();
+        }
+        // bottom sweep: rows mh-1..k+1
+        if (mh - 1 > k)
+            for (int e = lane; e < mm; e += 64) W[e] = P.A(mh - 1, e / m, e % m);
+        __syncthreads();
+        for (int j = mh - 1; j > k; --j) {
+            gj_invert(W, m, fail);
+            store_pivot(j);
+            // H = B_{j-1}^T U_j^{-1}
+            const int o = (j - 1) * m;
+            for (int e = lane; e < mm; e += 64) {
+                const int r = e / m, s = e - r * m;
+                double h = kn[o + r] * W[r * m + s];
+                if (r + 1 < m) h += kne[o + r] * W[(r + 1) * m + s];
+                if (r >= 1) h += knw[o + r] * W[(r - 1) * m + s];
+                G[e] = h;
+                Lout[(long long)(j - 1) * mm + e] = h;
+            }
+            __syncthreads();
+            // H B_{j-1}
+            for (int e = lane; e < mm; e += 64) {
+                const int r = e / m, s = e - r * m;
+                double cb = G[r * m + s] * kn[o + s];
+                if (s + 1 < m) cb += G[r * m + s + 1] * kne[o + s];
+                if (s >= 1) cb += G[r * m + s - 1] * knw[o + s];
+                if (j - 1 > k)
+                    W[e] = P.A(j - 1, r, s) - cb;
+                else
+                    Mid[e] -= cb;
+            }
+            __syncthreads();
+        }
+        for (int e = lane; e < mm; e += 64) W[e] = Mid[e];
+        __syncthreads();
         gj_invert(W, m, fail);
-        store_pivot(j);
-        // G = B_j T_j^{-1}; B_j[r][s] = kn(s) (r = s), kne(s) (r = s+1), knw(s) (r = s-1) at row j
-        const int o = j * m;
-        for (int e = lane; e < mm; e += 64) {
-            const int r = e / m, s = e - r * m;
-            double g = kn[o + r] * W[r * m + s];
-            if (r >= 1) g += kne[o + r - 1] * W[(r - 1) * m + s];
-            if (r + 1 < m) g += knw[o + r + 1] * W[(r + 1) * m + s];
-            G[e] = g;
-            Lout[(long long)j * mm + e] = g;
-        }
-        __syncthreads();
-        // G B_j^T, subtracted from the next diagonal block (or from the middle one)
-        for (int e = lane; e < mm; e += 64) {
-            const int r = e / m, s = e - r * m;
-            double cb = G[r * m + s] * kn[o + s];
-            if (s >= 1) cb += G[r * m + s - 1] * kne[o + s - 1];
-            if (s + 1 < m) cb += G[r * m + s + 1] * knw[o + s + 1];
-            if (j + 1 < k)
-                W[e] = P.A(j + 1, r, s) - cb;
-            else
-                Mid[e] -= cb;
-        }
-        __syncthreads();
+        store_pivot(k);
+        __syncthreads();  // LDS is reused by the next patch
     }
-    // bottom sweep: rows mh-1..k+1
-    if (mh - 1 > k)
-        for (int e = lane; e < mm; e += 64) W[e] = P.A(mh - 1, e / m, e % m);
-    __syncthreads();
-    for (int j = mh - 1; j > k; --j) {
-        gj_invert(W, m, fail);
-        store_pivot(j);
-        // H = B_{j-1}^T U_j^{-1}
-        const int o = (j - 1) * m;
-        for (int e = lane; e < mm; e += 64) {
-            const int r = e / m, s = e - r * m;
-            double h = kn[o + r] * W[r * m + s];
-            if (r + 1 < m) h += kne[o + r] * W[(r + 1) * m + s];
-            if (r >= 1) h += knw[o + r] * W[(r - 1) * m + s];
-            G[e] = h;
-            Lout[(long long)(j - 1) * mm + e] = h;
-        }
-        __syncthreads();
-        // H B_{j-1}
-        for (int e = lane; e < mm; e += 64) {
-            const int r = e / m, s = e - r * m;
-            double cb = G[r * m + s] * kn[o + s];
-            if (s + 1 < m) cb += G[r * m + s + 1] * kne[o + s];
-            if (s >= 1) cb += G[r * m + s - 1] * knw[o + s];
-            if (j - 1 > k)
-                W[e] = P.A(j - 1, r, s) - cb;
-            else
-                Mid[e] -= cb;
-        }
-        __syncthreads();
-    }
-    for (int e = lane; e < mm; e += 64) W[e] = Mid[e];
-    __syncthreads();
-    gj_invert(W, m, fail);
-    store_pivot(k);
 }
 
 // ------------------------------------------------------------------ application
@@ -667,7 +672,7 @@ namespace tgms {
 
 long long patch_factor_size(int m, int mh) { return tw_size(m, mh); }
 
-void factor_patches_launch(tgms_ctx* c, int* fail) {
+void factor_patches_launch(tgms_ctx* c, int* fail, int max_groups) {
     const int m = c->pat_bmax - 1;
     if (m > 32) throw TgmsError{TGMS_E_UNSUPPORTED, "smoother patch wider than 33 cells"};
     const size_t lds = (size_t)(6 * c->pat_nmax + 3 * m * m) * sizeof(double);
@@ -676,15 +681,16 @@ void factor_patches_launch(tgms_ctx* c, int* fail) {
     allow_lds<double>(c->lds_max);
     allow_lds<float>(c->lds_max);
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_patch_factor, dim3(c->nblk), dim3(64), lds, c->stream, c->patch, c->a, c->nx,
-                       c->sx * c->sx, c->sy * c->sy, c->patL, fail);
+    const int groups = max_groups > 0 ? std::min(c->nblk, max_groups) : c->nblk;
+    hipLaunchKernelGGL(k_patch_factor, dim3(groups), dim3(64), lds, c->stream, c->patch, c->a, c->nx,
+                       c->sx * c->sx, c->sy * c->sy, c->patL, fail, c->nblk);
     LAUNCH_OK();
     if (c->patL32) cast_d2f(c, c->pat_pool, c->patL, c->patL32);
 }
 
 void factor_patches(tgms_ctx* c) {
     int* fail = c->alloc_scratch_int();
-    factor_patches_launch(c, fail);
+    factor_patches_launch(c, fail, 0);
     int h = 0;
     HIP_OK(hipMemcpyAsync(&h, fail, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
