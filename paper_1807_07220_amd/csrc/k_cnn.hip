@@ -304,14 +304,16 @@ __global__ void k_cnn_windows(const double* __restrict__ kinv, int nx, int Nx, i
 }
 
 // ------------------------------------------------------------------ BF16 inference
-// The same forward pass (no saved activations) on the BF16 matrix cores with FP32
-// accumulation: one workgroup per sample; activations in LDS as BF16 with the 16
-// channels innermost ([H+2][W+2][16], zero ring); layer 0 (one input channel) in
-// FP32 on the vector ALU; layers 1-3 as, per tile of 16 positions and per tap of the
-// 3x3 stencil, one v_mfma_f32_16x16x16_bf16 (rows: positions, k: input channels,
-// columns: output channels).  Operand layout of that instruction: lane l holds
-// A[l%16][4(l/16) + e] and B[4(l/16) + e][l%16] (e < 4); result item j of lane l is
-// D[4(l/16) + j][l%16].
+// The same forward pass (no saved activations) on the matrix cores: one workgroup
+// per sample; activations in LDS as BF16 with the 16 channels innermost
+// ([H+2][W+2][16], zero ring).  A tile is 16 consecutive positions of one row (the
+// columns past W repeat column W - 1 and their outputs are dropped).  Layer 0 (one
+// input channel) runs in FP32 as three v_mfma_f32_16x16x4_f32 per tile (k: the 9
+// taps, padded to 12 with zero weights); layers 1-3 as one v_mfma_f32_16x16x16_bf16
+// per tap (rows: positions, k: input channels, columns: output channels), FP32
+// accumulation.  Operand layout of both instructions: lane l holds A[l%16][kq(l/16) + e]
+// and B[kq(l/16) + e][l%16] (e < q, q = 1 or 4 elements per lane); result item j of
+// lane l is D[4(l/16) + j][l%16].
 typedef short bf4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 
@@ -320,42 +322,79 @@ __device__ inline unsigned short f2bf(float x) {  // round to nearest even
     return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
 }
 
+// The tile's outputs (item j of this lane: position 4 kg + j of the tile, channel col):
+// bias and ReLU to the next activation plane, or the raw values to yout [H W][KOUT].
+template <int COUT, bool HIDDEN>
+__device__ inline void tile_out(const Shape& S, int h, int w0, int col, int kg, const f4_t& acc, float bias,
+                                unsigned short* __restrict__ out, float* __restrict__ yout) {
+    const int orow = (h + 1) * S.PW + 1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int w = w0 + 4 * kg + j;
+        if (w < S.W && col < COUT) {
+            const float v = acc[j] + bias;
+            if (HIDDEN)
+                out[(orow + w) * C + col] = f2bf(fmaxf(v, 0.f));
+            else
+                yout[(h * S.W + w) * KOUT + col] = v;
+        }
+    }
+}
+
+// layer 0: xin (padded FP32 plane) -> out (BF16, 16 channels), FP32 matrix cores
+__device__ void conv0_mfma(const Shape& S, const float* __restrict__ xin, unsigned short* __restrict__ out,
+                           const float* __restrict__ wg, const float* __restrict__ bg) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, kg = lane >> 4;
+    float bw[3];
+    int toff[3];
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk) {
+        const int t = 4 * kk + kg;
+        bw[kk] = t < 9 ? wg[col * 9 + t] : 0.f;
+        toff[kk] = t < 9 ? tapoff(S, t) : 0;
+    }
+    const float bias = bg[col];
+    const int nch = (S.W + 15) >> 4, ntiles = S.H * nch;
+    for (int tile = wave; tile < ntiles; tile += NT / 64) {
+        const int h = tile / nch, w0 = (tile - h * nch) * 16;
+        const int q = (h + 1) * S.PW + min(w0 + col, S.W - 1) + 1;
+        f4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(xin[q + toff[kk]], bw[kk], acc, 0, 0, 0);
+        tile_out<C, true>(S, h, w0, col, kg, acc, bias, out, nullptr);
+    }
+    __syncthreads();
+}
+
 template <int COUT, bool HIDDEN>
 __device__ void conv_mfma(const Shape& S, const unsigned short* __restrict__ in, unsigned short* __restrict__ out,
                           float* __restrict__ yout, const float* __restrict__ wg, const float* __restrict__ bg) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, kg = lane >> 4;  // output channel / input-channel group of this lane
     bf4_t bfr[9];
+    int toff[9];
 #pragma unroll
-    for (int t = 0; t < 9; ++t)
+    for (int t = 0; t < 9; ++t) {
+        toff[t] = tapoff(S, t) * C;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int ci = 4 * kg + e;
             bfr[t][e] = (short)f2bf(col < COUT ? wg[(col * C + ci) * 9 + t] : 0.f);
         }
+    }
     const float bias = col < COUT ? bg[col] : 0.f;
-    const int ntiles = (S.HW + 15) / 16;
+    const int nch = (S.W + 15) >> 4, ntiles = S.H * nch;
     for (int tile = wave; tile < ntiles; tile += NT / 64) {
-        const int p = tile * 16 + col;  // the A row (position) this lane loads
-        const bool valid = p < S.HW;
-        const int q = valid ? padpos(S, p) : 0;
+        const int h = tile / nch, w0 = (tile - h * nch) * 16;
+        const int base = ((h + 1) * S.PW + min(w0 + col, S.W - 1) + 1) * C + 4 * kg;
         f4_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
-            bf4_t a = {0, 0, 0, 0};
-            if (valid) a = *reinterpret_cast<const bf4_t*>(in + (q + tapoff(S, t)) * C + 4 * kg);
+            const bf4_t a = *reinterpret_cast<const bf4_t*>(in + base + toff[t]);
             acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bfr[t], acc, 0, 0, 0);
         }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int pos = tile * 16 + 4 * kg + j;
-            if (pos >= S.HW || col >= COUT) continue;
-            const float v = acc[j] + bias;
-            if (HIDDEN)
-                out[padpos(S, pos) * C + col] = f2bf(fmaxf(v, 0.f));
-            else
-                yout[pos * KOUT + col] = v;
-        }
+        tile_out<COUT, HIDDEN>(S, h, w0, col, kg, acc, bias, out, yout);
     }
     __syncthreads();
 }
@@ -376,21 +415,7 @@ __global__ void __launch_bounds__(NT) k_cnn_infer_bf16(const float* __restrict__
     __syncthreads();
     for (int p = tid; p < S.HW; p += NT) xin[padpos(S, p)] = X[s * S.HW + p];
     __syncthreads();
-    // layer 0: 1 -> 16 channels, FP32
-    for (int p = tid; p < S.HW; p += NT) {
-        const int q = padpos(S, p);
-        float x[9];
-#pragma unroll
-        for (int t = 0; t < 9; ++t) x[t] = xin[q + tapoff(S, t)];
-#pragma unroll
-        for (int co = 0; co < C; ++co) {
-            float a = prm[BL0 + co];
-#pragma unroll
-            for (int t = 0; t < 9; ++t) a += prm[WL0 + co * 9 + t] * x[t];
-            A0[q * C + co] = f2bf(fmaxf(a, 0.f));
-        }
-    }
-    __syncthreads();
+    conv0_mfma(S, xin, A0, prm + WL0, prm + BL0);
     conv_mfma<C, true>(S, A0, A1, nullptr, prm + WL1, prm + BL1);
     conv_mfma<C, true>(S, A1, A0, nullptr, prm + WL2, prm + BL2);
     conv_mfma<KOUT, false>(S, A0, nullptr, yout, prm + WL3, prm + BL3);
