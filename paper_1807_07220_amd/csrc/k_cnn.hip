@@ -307,13 +307,14 @@ __global__ void k_cnn_windows(const double* __restrict__ kinv, int nx, int Nx, i
 // The same forward pass (no saved activations) on the matrix cores: one workgroup
 // per sample; activations in LDS as BF16 with the 16 channels innermost
 // ([H+2][W+2][16], zero ring).  A tile is 16 consecutive positions of one row (the
-// columns past W repeat column W - 1 and their outputs are dropped).  Layer 0 (one
-// input channel) runs in FP32 as three v_mfma_f32_16x16x4_f32 per tile (k: the 9
-// taps, padded to 12 with zero weights); layers 1-3 as one v_mfma_f32_16x16x16_bf16
-// per tap (rows: positions, k: input channels, columns: output channels), FP32
-// accumulation.  Operand layout of both instructions: lane l holds A[l%16][kq(l/16) + e]
-// and B[kq(l/16) + e][l%16] (e < q, q = 1 or 4 elements per lane); result item j of
-// lane l is D[4(l/16) + j][l%16].
+// columns past W repeat column W - 1 and their outputs are dropped).  Each tile
+// computes D = Wt X^T (rows: output channels, k: input channels or taps, columns:
+// positions): layer 0 (one input channel) in FP32 as three v_mfma_f32_16x16x4_f32
+// (k: the 9 taps, padded to 12 with zero weights), layers 1-3 as one
+// v_mfma_f32_16x16x16_bf16 per tap, FP32 accumulation.  Operand layout of both
+// instructions: lane l holds A[l%16][kq(l/16) + e] and B[kq(l/16) + e][l%16] (e < q,
+// q = 1 or 4 elements per lane); result item j of lane l is D[4(l/16) + j][l%16], so
+// a lane ends with 4 consecutive channels of one position (one 8-byte store).
 typedef short bf4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 
@@ -322,22 +323,22 @@ __device__ inline unsigned short f2bf(float x) {  // round to nearest even
     return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
 }
 
-// The tile's outputs (item j of this lane: position 4 kg + j of the tile, channel col):
-// bias and ReLU to the next activation plane, or the raw values to yout [H W][KOUT].
+// The tile's outputs of this lane (channels 4 kg .. 4 kg + 3 at column w0 + col): bias
+// and ReLU to the next activation plane, or the raw values to yout [H W][KOUT].
 template <int COUT, bool HIDDEN>
-__device__ inline void tile_out(const Shape& S, int h, int w0, int col, int kg, const f4_t& acc, float bias,
+__device__ inline void tile_out(const Shape& S, int h, int w0, int col, int kg, const f4_t& acc, const float* bias4,
                                 unsigned short* __restrict__ out, float* __restrict__ yout) {
-    const int orow = (h + 1) * S.PW + 1;
+    const int w = w0 + col;
+    if (w >= S.W || 4 * kg >= COUT) return;
+    if (HIDDEN) {
+        unsigned short v[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int w = w0 + 4 * kg + j;
-        if (w < S.W && col < COUT) {
-            const float v = acc[j] + bias;
-            if (HIDDEN)
-                out[(orow + w) * C + col] = f2bf(fmaxf(v, 0.f));
-            else
-                yout[(h * S.W + w) * KOUT + col] = v;
-        }
+        for (int j = 0; j < 4; ++j) v[j] = f2bf(fmaxf(acc[j] + bias4[j], 0.f));
+        *reinterpret_cast<uint2*>(out + ((h + 1) * S.PW + w + 1) * C + 4 * kg) =
+            make_uint2(v[0] | ((unsigned)v[1] << 16), v[2] | ((unsigned)v[3] << 16));
+    } else {
+        *reinterpret_cast<float4*>(yout + (h * S.W + w) * KOUT + 4 * kg) =
+            make_float4(acc[0] + bias4[0], acc[1] + bias4[1], acc[2] + bias4[2], acc[3] + bias4[3]);
     }
 }
 
@@ -346,23 +347,24 @@ __device__ void conv0_mfma(const Shape& S, const float* __restrict__ xin, unsign
                            const float* __restrict__ wg, const float* __restrict__ bg) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, kg = lane >> 4;
-    float bw[3];
+    float bw[3], bias4[4];
     int toff[3];
 #pragma unroll
     for (int kk = 0; kk < 3; ++kk) {
         const int t = 4 * kk + kg;
-        bw[kk] = t < 9 ? wg[col * 9 + t] : 0.f;
+        bw[kk] = t < 9 ? wg[col * 9 + t] : 0.f;  // A[cout = col][tap t]
         toff[kk] = t < 9 ? tapoff(S, t) : 0;
     }
-    const float bias = bg[col];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bias4[j] = bg[4 * kg + j];
     const int nch = (S.W + 15) >> 4, ntiles = S.H * nch;
     for (int tile = wave; tile < ntiles; tile += NT / 64) {
         const int h = tile / nch, w0 = (tile - h * nch) * 16;
         const int q = (h + 1) * S.PW + min(w0 + col, S.W - 1) + 1;
         f4_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kk = 0; kk < 3; ++kk) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(xin[q + toff[kk]], bw[kk], acc, 0, 0, 0);
-        tile_out<C, true>(S, h, w0, col, kg, acc, bias, out, nullptr);
+        for (int kk = 0; kk < 3; ++kk) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(bw[kk], xin[q + toff[kk]], acc, 0, 0, 0);
+        tile_out<C, true>(S, h, w0, col, kg, acc, bias4, out, nullptr);
     }
     __syncthreads();
 }
@@ -371,8 +373,8 @@ template <int COUT, bool HIDDEN>
 __device__ void conv_mfma(const Shape& S, const unsigned short* __restrict__ in, unsigned short* __restrict__ out,
                           float* __restrict__ yout, const float* __restrict__ wg, const float* __restrict__ bg) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int col = lane & 15, kg = lane >> 4;  // output channel / input-channel group of this lane
-    bf4_t bfr[9];
+    const int col = lane & 15, kg = lane >> 4;
+    bf4_t wfr[9];  // A[cout = col][cin = 4 kg + e] of each tap
     int toff[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
@@ -380,10 +382,12 @@ __device__ void conv_mfma(const Shape& S, const unsigned short* __restrict__ in,
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int ci = 4 * kg + e;
-            bfr[t][e] = (short)f2bf(col < COUT ? wg[(col * C + ci) * 9 + t] : 0.f);
+            wfr[t][e] = (short)f2bf(col < COUT ? wg[(col * C + ci) * 9 + t] : 0.f);
         }
     }
-    const float bias = col < COUT ? bg[col] : 0.f;
+    float bias4[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bias4[j] = 4 * kg + j < COUT ? bg[4 * kg + j] : 0.f;
     const int nch = (S.W + 15) >> 4, ntiles = S.H * nch;
     for (int tile = wave; tile < ntiles; tile += NT / 64) {
         const int h = tile / nch, w0 = (tile - h * nch) * 16;
@@ -391,10 +395,10 @@ __device__ void conv_mfma(const Shape& S, const unsigned short* __restrict__ in,
         f4_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
-            const bf4_t a = *reinterpret_cast<const bf4_t*>(in + base + toff[t]);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bfr[t], acc, 0, 0, 0);
+            const bf4_t x = *reinterpret_cast<const bf4_t*>(in + base + toff[t]);  // B[cin][position col]
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wfr[t], x, acc, 0, 0, 0);
         }
-        tile_out<COUT, HIDDEN>(S, h, w0, col, kg, acc, bias, out, yout);
+        tile_out<COUT, HIDDEN>(S, h, w0, col, kg, acc, bias4, out, yout);
     }
     __syncthreads();
 }
