@@ -656,7 +656,10 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                 pat_timer.stop(side.s);
             }
             HIP_OK(hipEventRecord(side.e2, side.s));
-            tgms::dense_spd_inverse(c, c->Ac, c->ncs);
+            // FP64 with a small coarse space: the explicit inverse too, applied in one launch
+            if (!c->precision && c->ncs <= tgms::symv_acc_max())
+                c->Acf = c->alloc<double>((size_t)c->ncs * c->ncs);
+            tgms::dense_spd_inverse(c, c->Ac, c->ncs, c->Acf);
             if (c->precision) {
                 c->Ac32 = c->alloc<float>((size_t)c->ncs * c->ncs);
                 tgms::cast_d2f(c, (long long)c->ncs * c->ncs, c->Ac, c->Ac32);
@@ -741,7 +744,7 @@ void update_mobility_impl(tgms_ctx* c, const double* lambda) {
     tgms::gram(c);
     tgms::zero(c, c->Ac, sizeof(double) * (size_t)c->ncs * c->ncs);
     tgms::coarse_local_run(c, c->Td, c->zcd);
-    tgms::dense_spd_inverse(c, c->Ac, c->ncs);
+    tgms::dense_spd_inverse(c, c->Ac, c->ncs, c->Acf);
     if (c->precision) tgms::cast_d2f(c, (long long)c->ncs * c->ncs, c->Ac, c->Ac32);
     tgms::coarse_rt0_blocks(c);
     build_rt0_stiffness(c);

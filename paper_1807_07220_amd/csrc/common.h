@@ -187,6 +187,7 @@ struct tgms_ctx {
     int* unk_ptr = nullptr;   // ncs+1 CSR of (block, slot) touching each unknown
     int* unk_ent = nullptr;
     double* Ac = nullptr;     // ncs * ncs (dense, then its inverse)
+    double* Acf = nullptr;    // FP64 with small ncs: the explicit inverse (ncs * ncs, symmetric)
     float* Ac32 = nullptr;
     double* cy = nullptr;     // nblk * mu restricted values
     float* cy32 = nullptr;
@@ -392,7 +393,8 @@ T* coarse_cy(tgms_ctx* c);  // the block restriction buffer of the coarse correc
 template <typename T>
 const T* coarse_solve(tgms_ctx* c, const double* sc);  // accumulate the restrictions, apply the coarse inverse
 // dense (k_dense.hip)
-void dense_spd_inverse(tgms_ctx* c, double* A, int n);
+// A -> tril(L^{-1}) + triu(L^{-T}, 1) in place; full (optional): the explicit inverse
+void dense_spd_inverse(tgms_ctx* c, double* A, int n, double* full = nullptr);
 struct DenseInvWork {
     double* Dinv = nullptr;
     int* fail = nullptr;
@@ -416,6 +418,10 @@ template <typename T>
 void symv(tgms_ctx* c, const T* A, int n, const T* x, T* y, const double* sc);
 template <typename T>
 bool symv_acc(tgms_ctx* c, const T* B, int n, const int* ptr, const int* ent, const T* cy, T* y, const double* sc);
+// the same with the explicit inverse F (one launch); false when n > symv_acc_max() or F is null
+bool symv_full_acc(tgms_ctx* c, const double* F, int n, const int* ptr, const int* ent, const double* cy, double* y,
+                   const double* sc);
+int symv_acc_max();
 void gemm(tgms_ctx* c, int transA, int transB, int M, int N, int K, double alpha, const double* A, int lda,
           const double* B, int ldb, double beta, double* C, int ldc);
 // preprocessing and pressure (k_pre.hip)

@@ -424,6 +424,34 @@ __global__ void k_trimv_acc(const T* __restrict__ B, int n, const int* __restric
     if (lane == 0) y[row] = s;
 }
 
+// The same with the explicit inverse F = A^{-1} (symmetric, full rows): y = F c in
+// one launch, c accumulated as above.
+template <typename T>
+__global__ void k_symv_acc(const T* __restrict__ F, int n, const int* __restrict__ ptr, const int* __restrict__ ent,
+                           const T* __restrict__ cy, T* __restrict__ y, const double* __restrict__ sc) {
+    if (sc != nullptr && sc[SC_DONE] != 0.0) return;
+    __shared__ T cs[ACC_MAX];
+    for (int u = threadIdx.x; u < n; u += blockDim.x) {
+        T v = T(0);
+        for (int k = ptr[u]; k < ptr[u + 1]; ++k) v += cy[ent[k]];
+        cs[u] = v;
+    }
+    __syncthreads();
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    const T s = row_dot<T>(F, (long long)row * n, 0, n, cs, lane);
+    if (lane == 0) y[row] = s;
+}
+
+// F[i][j] = F[j][i] for j > i (the upper triangle from the lower one)
+__global__ void k_mirror_lower(double* __restrict__ F, int n) {
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= (long long)n * n) return;
+    const int i = (int)(e / n), j = (int)(e % n);
+    if (j > i) F[e] = F[(long long)j * n + i];
+}
+
 inline unsigned nb(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -552,8 +580,9 @@ static void dense_inverse_sizes(int n, size_t& dinv, size_t& x, size_t& tm) {
     tm = (size_t)n * (n / 2 + TB);
 }
 
-// In place: A (n x n, row-major, symmetric positive definite) -> B = tril(L^{-1}) + triu(L^{-T}, 1).
-void dense_spd_inverse(tgms_ctx* c, double* A, int n) {
+// In place: A (n x n, row-major, symmetric positive definite) -> B = tril(L^{-1}) + triu(L^{-T}, 1);
+// full (optional, n x n): the explicit inverse L^{-T} L^{-1}, exactly symmetric.
+void dense_spd_inverse(tgms_ctx* c, double* A, int n, double* full) {
     if (n <= 0) return;
     size_t nd, nx, nt;
     dense_inverse_sizes(n, nd, nx, nt);
@@ -563,6 +592,12 @@ void dense_spd_inverse(tgms_ctx* c, double* A, int n) {
     w.X = c->alloc<double>(nx);
     w.Tm = c->alloc<double>(nt);
     dense_inverse_enqueue(c, A, n, w);
+    if (full) {
+        // X = L^{-1} (zero above the diagonal): full = X^T X, its lower triangle mirrored
+        gemm(c, 1, 0, n, n, n, 1.0, w.X, n, w.X, n, 0.0, full, n);
+        hipLaunchKernelGGL(k_mirror_lower, dim3(nb((long long)n * n)), dim3(256), 0, c->stream, full, n);
+        LAUNCH_OK();
+    }
     int h = 0;
     HIP_OK(hipMemcpyAsync(&h, w.fail, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
@@ -646,6 +681,16 @@ bool symv_acc(tgms_ctx* c, const T* B, int n, const int* ptr, const int* ent, co
 }
 template bool symv_acc<double>(tgms_ctx*, const double*, int, const int*, const int*, const double*, double*,
                                const double*);
+
+// y = F c with F the explicit inverse and c accumulated from cy (one launch)
+bool symv_full_acc(tgms_ctx* c, const double* F, int n, const int* ptr, const int* ent, const double* cy, double* y,
+                   const double* sc) {
+    if (n <= 0 || n > ACC_MAX || F == nullptr) return false;
+    hipLaunchKernelGGL((k_symv_acc<double>), dim3((n + 3) / 4), dim3(256), 0, c->stream, F, n, ptr, ent, cy, y, sc);
+    LAUNCH_OK();
+    return true;
+}
+int symv_acc_max() { return ACC_MAX; }
 template bool symv_acc<float>(tgms_ctx*, const float*, int, const int*, const int*, const float*, float*,
                               const double*);
 

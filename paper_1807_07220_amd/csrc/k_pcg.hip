@@ -1,14 +1,15 @@
 // Fused kernels of the PCG iteration (paper section 5, Step 3) and of the
 // two-grid preconditioner around the smoother and coarse solves.
 //
-// One PCG iteration in stream-function coordinates is 7 kernels (8 for coarse
-// systems of more than 1024 unknowns):
+// One PCG iteration in stream-function coordinates is 7 kernels (6 in FP64 with
+// at most 1024 coarse unknowns, 8 with more than 1024):
 //   [finalise the last iteration: rho' = g.z, beta, |C z|^2 test]
 //   p = z + beta p;  q = K p;  partial p.q                        (k_dir_apply)
 //   z = B_TG g: alpha = rho / p.q, x += alpha p and g -= alpha q inside the
 //   first smoothing; z1 = eta sum ext(w), t = g - K z1 and the
 //   block restriction W_b^T t (k_gather_res_restrict); coarse accumulation and
-//   the two triangular products (k_dense.hip); the second smoothing, which forms
+//   the two triangular products, or one product with the explicit inverse
+//   (k_dense.hip); the second smoothing, which forms
 //   z1' = z1 + W c and its right-hand side g - K z1' on each patch itself
 //   (k_smooth.hip); z = z1' + eta sum ext(w) with the partials of g.z, gold.z and
 //   |C z|^2 (k_gather_final).

@@ -1219,11 +1219,15 @@ template double* coarse_cy<double>(tgms_ctx*);
 template float* coarse_cy<float>(tgms_ctx*);
 
 // the coarse unknowns from the block restrictions cy, then A^{-1} of them (two
-// triangular products); returns the result (after c1 in the same buffer)
+// triangular products, or one product with the explicit inverse); returns the
+// result (after c1 in the same buffer)
 template <typename T>
 const T* coarse_solve(tgms_ctx* c, const double* sc) {
     const CoarseBufs<T> B = coarse_bufs<T>(c);
     T* res = B.c1 + c->ncs;
+    if constexpr (sizeof(T) == 8)
+        if (symv_full_acc(c, c->Acf, c->ncs, c->unk_ptr, c->unk_ent, (const double*)B.cy, (double*)res, sc))
+            return res;
     if (symv_acc<T>(c, B.Ainv, c->ncs, c->unk_ptr, c->unk_ent, (const T*)B.cy, res, sc)) return res;
     hipLaunchKernelGGL((k_coarse_accum<T>), dim3((c->ncs + 255) / 256), dim3(256), 0, c->stream, c->unk_ptr, c->unk_ent,
                        (const T*)B.cy, c->ncs, B.c1, sc);
