@@ -230,15 +230,10 @@ struct Lines {
 
 template <typename T, int M>
 __device__ inline T dot_lanes(const T (&v)[M], T x) {
-    T s0 = T(0), s1 = T(0);
+    T s[4] = {T(0), T(0), T(0), T(0)};  // four independent accumulation chains
 #pragma unroll
-    for (int c = 0; c < M; ++c) {
-        if (c & 1)
-            s1 += v[c] * readlane(x, c);
-        else
-            s0 += v[c] * readlane(x, c);
-    }
-    return s0 + s1;
+    for (int c = 0; c < M; ++c) s[c & 3] += v[c] * readlane(x, c);
+    return (s[0] + s[1]) + (s[2] + s[3]);
 }
 
 // Where a patch solution goes: the patch's own vector (slot layout off), or the
