@@ -415,15 +415,21 @@ __global__ void __launch_bounds__(256) k_gram_mfma(BlockGeom G, const double* __
 // Cyclic Jacobi on the symmetric n x n matrix A (row stride ld, LDS), round-robin
 // ordering over the pairs, one wavefront: A becomes diagonal (the eigenvalues), and
 // V (the identity on entry) accumulates the rotations (eigenvectors in its columns).
-__device__ void jacobi_rr(double* A, double* V, int ld, int n, double (*cs)[2], int* rot_flag) {
+// NM: a power of two >= n (the element loops' stride); pq: LDS room for the pairs of
+// one round ([NM / 2][2]), published with their rotations so that the update loops
+// do no index arithmetic beyond shifts and masks.
+template <int NM>
+__device__ void jacobi_rr(double* A, double* V, int ld, int n, double (*cs)[2], int (*pq)[2], int* rot_flag) {
+    static_assert((NM & (NM - 1)) == 0, "NM must be a power of two");
+    constexpr int SH = NM == 1 ? 0 : NM == 2 ? 1 : NM == 4 ? 2 : NM == 8 ? 3 : NM == 16 ? 4 : NM == 32 ? 5 : 6;
     const int lane = threadIdx.x;
     const int N = (n + 1) & ~1, half = N / 2;
     for (int sweep = 0; sweep < 60; ++sweep) {
         if (lane == 0) *rot_flag = 0;
         __syncthreads();
         for (int rnd = 0; rnd < N - 1; ++rnd) {
-            auto pos = [&](int x) { return x == 0 ? 0 : 1 + (x - 1 + rnd) % (N - 1); };
             if (lane < half) {
+                auto pos = [&](int x) { return x == 0 ? 0 : 1 + (x - 1 + rnd) % (N - 1); };
                 const int p = pos(lane), qq = pos(N - 1 - lane);
                 double c = 1.0, s = 0.0;
                 if (p < n && qq < n) {
@@ -438,12 +444,14 @@ __device__ void jacobi_rr(double* A, double* V, int ld, int n, double (*cs)[2], 
                 }
                 cs[lane][0] = c;
                 cs[lane][1] = s;
+                pq[lane][0] = (p < n && qq < n) ? p : -1;  // -1: no rotation on this pair
+                pq[lane][1] = qq;
             }
             __syncthreads();
-            for (int e = lane; e < half * n; e += 64) {  // rows: A <- P^T A
-                const int k = e / n, x = e % n;
-                const int p = pos(k), qq = pos(N - 1 - k);
-                if (p < n && qq < n) {
+            for (int e = lane; e < (half << SH); e += 64) {  // rows: A <- P^T A
+                const int k = e >> SH, x = e & (NM - 1);
+                const int p = pq[k][0], qq = pq[k][1];
+                if (x < n && p >= 0) {
                     const double c = cs[k][0], s = cs[k][1];
                     const double tp = A[p * ld + x], tq = A[qq * ld + x];
                     A[p * ld + x] = c * tp - s * tq;
@@ -451,10 +459,10 @@ __device__ void jacobi_rr(double* A, double* V, int ld, int n, double (*cs)[2], 
                 }
             }
             __syncthreads();
-            for (int e = lane; e < half * n; e += 64) {  // columns: A <- A P, V <- V P
-                const int k = e / n, x = e % n;
-                const int p = pos(k), qq = pos(N - 1 - k);
-                if (p < n && qq < n) {
+            for (int e = lane; e < (half << SH); e += 64) {  // columns: A <- A P, V <- V P
+                const int k = e >> SH, x = e & (NM - 1);
+                const int p = pq[k][0], qq = pq[k][1];
+                if (x < n && p >= 0) {
                     const double c = cs[k][0], s = cs[k][1];
                     const double tp = A[x * ld + p], tq = A[x * ld + qq];
                     A[x * ld + p] = c * tp - s * tq;
@@ -536,6 +544,7 @@ __global__ void __launch_bounds__(64) k_pencil_eig(BlockGeom G, const double* __
     __shared__ double V[JM][LD];
     __shared__ double D[JM];
     __shared__ double cs[JM / 2][2];
+    __shared__ int pq[JM / 2][2];
     __shared__ int order[JM];
     __shared__ int rot_flag;
     // the subspace iteration's X, T X (rows < JM) and Rayleigh-Ritz matrices
@@ -662,7 +671,7 @@ __global__ void __launch_bounds__(64) k_pencil_eig(BlockGeom G, const double* __
                     Zs[a * 9 + b] = (a == b) ? 1.0 : 0.0;
                 }
                 __syncthreads();
-                jacobi_rr(Hs, Zs, 9, kk, cs, &rot_flag);
+                jacobi_rr<KW>(Hs, Zs, 9, kk, cs, pq, &rot_flag);
                 if (lane < kk) {
                     const double th = Hs[lane * 9 + lane];
                     int rank = 0;
@@ -746,7 +755,7 @@ __global__ void __launch_bounds__(64) k_pencil_eig(BlockGeom G, const double* __
             V[l][mm] = (l == mm) ? 1.0 : 0.0;
         }
         __syncthreads();
-        jacobi_rr(&T[0][0], &V[0][0], LD, Jn, cs, &rot_flag);
+        jacobi_rr<JM>(&T[0][0], &V[0][0], LD, Jn, cs, pq, &rot_flag);
         // sort mu descending (lambda = 1/mu ascending)
         if (lane < Jn) {
             const double mu = T[lane][lane];
