@@ -787,24 +787,26 @@ __global__ void __launch_bounds__(64) k_pencil_eig(BlockGeom G, const double* __
     // recombination Q (cnt x cnt): column 0 = f/|f|^2 (unit-flux carrier), columns 1.. = an
     // orthonormal basis of f^perp (Householder reflector mapping f/|f| to e_1); stored in LDS
     // (V is free now), then YQ = Y Q (jmax x jmax, rows l < Jn, columns k < cnt) to Qout.
+    // (lane k holds f_k and w_k; w is staged in LDS for the rows of the reflector)
     double* Qs = &V[0][0];  // Qs[k2 * LD + k]
-    if (lane == 0) {
-        double f[JM], nrm2 = 0.0;
-        for (int k = 0; k < cnt; ++k) {
-            double s = 0.0;
-            for (int l = 0; l < Jn; ++l) s += Yf[l * G.jmax + k];
-            f[k] = elen * s;
-            nrm2 += f[k] * f[k];
+    __shared__ double wsh[JM];
+    {
+        double fk = 0.0;
+        if (lane < cnt) {
+            for (int l = 0; l < Jn; ++l) fk += Yf[l * G.jmax + lane];
+            fk *= elen;
         }
-        for (int k = 0; k < cnt; ++k) Qs[k * LD] = f[k] / nrm2;
+        const double nrm2 = wave_sum(fk * fk);
+        if (lane < cnt) Qs[lane * LD] = fk / nrm2;
         if (cnt > 1) {
             const double nr = sqrt(nrm2);
-            double w[JM], ww = 0.0;
-            for (int k = 0; k < cnt; ++k) w[k] = f[k] / nr;
-            w[0] += (w[0] >= 0 ? 1.0 : -1.0);
-            for (int k = 0; k < cnt; ++k) ww += w[k] * w[k];
-            for (int r = 0; r < cnt; ++r)
-                for (int cc = 1; cc < cnt; ++cc) Qs[r * LD + cc] = ((r == cc) ? 1.0 : 0.0) - 2.0 * w[r] * w[cc] / ww;
+            double wk = lane < cnt ? fk / nr : 0.0;
+            if (lane == 0) wk += (wk >= 0 ? 1.0 : -1.0);
+            const double ww = wave_sum(wk * wk);
+            if (lane < cnt) wsh[lane] = wk;
+            __syncthreads();
+            if (lane < cnt)
+                for (int cc = 1; cc < cnt; ++cc) Qs[lane * LD + cc] = ((lane == cc) ? 1.0 : 0.0) - 2.0 * wk * wsh[cc] / ww;
         }
     }
     __syncthreads();
