@@ -156,18 +156,23 @@ __global__ void __launch_bounds__(64) k_snapshots_cols(BlockGeom G, const double
     const int m = M, mh = by - 1, nloc = m * mh;
     const int tri = btri_tri(m), bs = tri + btri_hes(m);
     const long long fsz = btri_size(m, mh);
-    const int areg = (int)((fsz > TILE * 64 ? fsz : TILE * 64) + 1) & ~1;
-    double* F = sm;                 // band factor, later the output transpose tile [TILE][64]
-    double* aK = sm + areg;         // cell weights [by][bx]
-    // right-hand sides / solutions [vertex][64]: in LDS, or (VGLOBAL) in a global scratch
-    // of vstride doubles per block, so that the LDS of a workgroup is the factor only and
-    // several workgroups share a CU
+    // LDS: the output transpose tile [TILE][64] (without VGLOBAL, the band factor first,
+    // in the same region) and the cell weights [by][bx].  With VGLOBAL the right-hand
+    // sides / solutions [vertex][64] live in a global scratch of vstride doubles per
+    // block and the factor is read from global memory (the same entry in every lane:
+    // scalar loads), so that a workgroup's LDS is small and several share a CU.
+    const int areg = VGLOBAL ? TILE * 64 : (int)((fsz > TILE * 64 ? fsz : TILE * 64) + 1) & ~1;
+    double* Tt = sm;
+    double* aK = sm + areg;
     double* V = VGLOBAL ? Vg + (long long)blockIdx.x * vstride : aK + bx * by + 1;
     const int blk = blockIdx.x, I = blk % G.Nx, J = blk / G.Nx;
     const int lane = threadIdx.x;
+    const double* F = VGLOBAL ? blkL + (long long)blk * fsz : sm;
     {
-        const double* src = blkL + (long long)blk * fsz;
-        for (long long e = lane; e < fsz; e += 64) F[e] = src[e];
+        if (!VGLOBAL) {
+            const double* src = blkL + (long long)blk * fsz;
+            for (long long e = lane; e < fsz; e += 64) sm[e] = src[e];
+        }
         for (int e = lane; e < bx * by; e += 64)
             aK[e] = a[(long long)(J * by + e / bx) * G.nx + I * bx + e % bx];
     }
@@ -255,7 +260,7 @@ __global__ void __launch_bounds__(64) k_snapshots_cols(BlockGeom G, const double
 #pragma unroll
         for (int k = 0; k < M; ++k) V[(j * m + k) * 64 + lane] = w[k] * S[j * m + k];
     }
-    __syncthreads();  // the factor region becomes the output tile
+    __syncthreads();  // the factor region (without VGLOBAL) becomes the output tile
     // v = v_p + C_K psi on all block faces, written column by column in chunks of TILE faces
     auto P = [&](int pp, int qq) -> double {
         return (pp <= 0 || pp >= bx || qq <= 0 || qq >= by) ? 0.0 : V[((qq - 1) * m + pp - 1) * 64 + lane];
@@ -273,13 +278,13 @@ __global__ void __launch_bounds__(64) k_snapshots_cols(BlockGeom G, const double
                 const int e2 = e - nfx, b = e2 / bx, aa = e2 % bx;
                 v = vy(b, aa) - (P(aa + 1, b) - P(aa, b)) * G.sy;
             }
-            F[k * 64 + lane] = v;
+            Tt[k * 64 + lane] = v;
         }
         __syncthreads();
         const int nk = (nfk - f0) < TILE ? (nfk - f0) : TILE;
         for (int cidx = 0; cidx < G.ncol; cidx += 2) {
             const int cc = cidx + (lane >> 5), k = lane & 31;
-            if (cc < G.ncol && k < nk) out[(long long)cc * nfk + f0 + k] = F[k * 64 + cc];
+            if (cc < G.ncol && k < nk) out[(long long)cc * nfk + f0 + k] = Tt[k * 64 + cc];
         }
         __syncthreads();
     }
@@ -1093,11 +1098,12 @@ void snapshots(tgms_ctx* c, double* scratch, long long scratch_per_block) {
     const long long fsz = btri_size(m, mh);
     const size_t lds_fac = sizeof(double) * ((((fsz > 32 * 64 ? fsz : 32 * 64) + 1) & ~1LL) + c->bx * c->by + 1);
     const size_t lds_cols = lds_fac + sizeof(double) * (size_t)m * mh * 64;
+    const size_t lds_tile = sizeof(double) * ((size_t)32 * 64 + c->bx * c->by + 1);  // factor read from global
     int cus = 0, dev = 0;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
     const bool vglobal = scratch && scratch_per_block >= (long long)m * mh * 64 && c->nblk > 2 * cus;
-    const size_t lds_use = vglobal ? lds_fac : lds_cols;
+    const size_t lds_use = vglobal ? lds_tile : lds_cols;
     double* Vg = vglobal ? scratch : nullptr;
     if (c->snap_cols && c->ncol <= 64 && lds_use <= (size_t)c->lds_max) {
         switch (m) {
