@@ -292,6 +292,25 @@ enum { SC_RHO = 0, SC_PQ, SC_ALPHA, SC_BETA, SC_ZN2, SC_REL2, SC_Z02, SC_FLAG, S
 // right-hand side: t = g - K z1' with z1' = z1 + W c (the coarse correction
 // prolonged), on each patch and its one-vertex halo; the patch's own block writes z1'.
 // z1 null: the smoother reads its right-hand side as given.
+// sum of cy[ent[k]] for k in [k0, k1), added in order; the index and value loads of
+// four terms are issued together (two memory round trips per four terms, not eight)
+template <typename T>
+__device__ inline T gather_sum(const int* __restrict__ ent, const T* __restrict__ cy, int k0, int k1) {
+    T v = T(0);
+    for (int k = k0; k < k1; k += 4) {
+        int e[4];
+        T c[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) e[q] = k + q < k1 ? ent[k + q] : -1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) c[q] = e[q] >= 0 ? cy[e[q]] : T(0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (k + q < k1) v += c[q];
+    }
+    return v;
+}
+
 template <typename T>
 struct PreResidual {
     const T* z1 = nullptr;

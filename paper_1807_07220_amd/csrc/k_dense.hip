@@ -412,9 +412,7 @@ __global__ void k_trimv_acc(const T* __restrict__ B, int n, const int* __restric
     if (sc != nullptr && sc[SC_DONE] != 0.0) return;
     __shared__ T cs[ACC_MAX];
     for (int u = threadIdx.x; u < n; u += blockDim.x) {
-        T v = T(0);
-        for (int k = ptr[u]; k < ptr[u + 1]; ++k) v += cy[ent[k]];
-        cs[u] = v;
+        cs[u] = gather_sum<T>(ent, cy, ptr[u], ptr[u + 1]);
     }
     __syncthreads();
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -432,9 +430,7 @@ __global__ void k_symv_acc(const T* __restrict__ F, int n, const int* __restrict
     if (sc != nullptr && sc[SC_DONE] != 0.0) return;
     __shared__ T cs[ACC_MAX];
     for (int u = threadIdx.x; u < n; u += blockDim.x) {
-        T v = T(0);
-        for (int k = ptr[u]; k < ptr[u + 1]; ++k) v += cy[ent[k]];
-        cs[u] = v;
+        cs[u] = gather_sum<T>(ent, cy, ptr[u], ptr[u + 1]);
     }
     __syncthreads();
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);

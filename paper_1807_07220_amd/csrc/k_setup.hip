@@ -1028,9 +1028,7 @@ __global__ void k_coarse_accum(const int* __restrict__ ptr, const int* __restric
     if (sc != nullptr && sc[SC_DONE] != 0.0) return;
     const int u = blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= ncs) return;
-    T s = T(0);
-    for (int k = ptr[u]; k < ptr[u + 1]; ++k) s += cy[ent[k]];
-    c[u] = s;
+    c[u] = gather_sum<T>(ent, cy, ptr[u], ptr[u + 1]);
 }
 
 template <typename T>
