@@ -108,6 +108,24 @@ __global__ void __launch_bounds__(NT) k_gemm(int transA, int transB, int M, int 
     gemm_tile(tm, tn, transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
 }
 
+// The lower tiles (tn <= tm) of an nt x nt tile grid on a 1D grid of nt (nt + 1) / 2
+// workgroups.  Workgroups are dealt to the 8 XCDs in turn; tile t of a contiguous,
+// equal share of the row-major triangle goes to each XCD, so the tiles of one tile row
+// (which read the same rows of op(A)) mostly meet in one L2.
+__global__ void __launch_bounds__(NT) k_gemm_lower(int transA, int transB, int M, int N, int K, double alpha,
+                                                   const double* __restrict__ A, int lda, const double* __restrict__ B,
+                                                   int ldb, double beta, double* C, int ldc) {
+    constexpr int NX = 8;
+    const int T = gridDim.x, lin = blockIdx.x;
+    const int x = lin % NX, l = lin / NX, q = T / NX, r = T % NX;
+    const int t = x * q + min(x, r) + l;  // a bijection of [0, T)
+    int tm = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
+    while (tm * (tm + 1) / 2 > t) --tm;
+    const int tn = t - tm * (tm + 1) / 2;
+    gemm_tile(tm, tn, transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
 // One level of the recursive inversion X = L^{-1} (n x n, row-major): for every node
 // [o, o + n1 + n2) of the level, with X11 and X22 already formed,
 //   step 0:  T = L21 X11          (n2 x n1, at Tm + toff, ld n1)
@@ -510,10 +528,10 @@ static void dense_inverse_enqueue(tgms_ctx* c, double* A, int n, const DenseInvW
         // trailing: A[c1:, c1:] -= Q Q^T with Q = A[c1:, c0:c1] (lower tiles only)
         const int mt = n - c1;
         if (mt > 0) {
-            dim3 grid((mt + TB - 1) / TB, (mt + TB - 1) / TB);
-            hipLaunchKernelGGL(k_gemm, grid, dim3(NT), 0, c->stream, 0, 1, mt, mt, c1 - c0, -1.0,
-                               (const double*)(A + (size_t)c1 * n + c0), n, (const double*)(A + (size_t)c1 * n + c0),
-                               n, 1.0, A + (size_t)c1 * n + c1, n, 1);
+            const int nt = (mt + TB - 1) / TB;
+            hipLaunchKernelGGL(k_gemm_lower, dim3(nt * (nt + 1) / 2), dim3(NT), 0, c->stream, 0, 1, mt, mt, c1 - c0,
+                               -1.0, (const double*)(A + (size_t)c1 * n + c0), n,
+                               (const double*)(A + (size_t)c1 * n + c0), n, 1.0, A + (size_t)c1 * n + c1, n);
             LAUNCH_OK();
         }
     }
