@@ -226,3 +226,40 @@ def test_trained_weights_on_held_out_field():
     assert abs(r["iters"] - rx["iters"]) <= 1
     s.close()
     s_ex.close()
+
+
+def _start_loss(Y, V, k):
+    """Mean over faces of sum_c |y_c/|y_c| - s_c v_c|^2 over the first k columns
+    (s_c = sign(y_c . v_c)): the training objective, the distance of a start block to
+    the exact eigenvectors."""
+    Y = np.asarray(Y, dtype=np.float64)[:, :k]
+    V = np.asarray(V, dtype=np.float64)[:, :k]
+    y = Y / np.linalg.norm(Y, axis=2, keepdims=True)
+    s = np.sign(np.sum(y * V, axis=2, keepdims=True))
+    s[s == 0] = 1.0
+    return float(np.mean(np.sum((y - s * V) ** 2, axis=(1, 2))))
+
+
+def test_trained_network_gains_over_its_starting_points():
+    """What training buys: on a field none of the committed weights were trained on
+    (256 x 256, contrast 1e6, seed 77), the trained network's start blocks are closer
+    to the exact eigenvectors of every face's pencil than both the DCT-II basis (the
+    network's output with a zero correction) and a freshly initialised network.
+    Measured: k = 8 loss 5.11 (trained) against 5.26 (DCT) and 5.66 (untrained);
+    k = 1 loss 0.60 against 0.72 and 0.78.  (In the solver this does not shorten the
+    certified Rayleigh-Ritz solve at 16-cell faces: no network start reaches the
+    1e-6 Ritz residual at iteration 0, and after one iteration every start is there.)"""
+    import os
+
+    import paper_1807_07220_amd as tg
+    from paper_1807_07220_amd import warmstart as ws
+    path = os.path.join(os.path.dirname(tg.__file__), "data", "warmstart_b16.npy")
+    trained = ws.load_weights(path)
+    X, V = ws.collect_samples([fields.field_channelized(256, 256, 77, contrast=1e6)], 16, 0.2)
+    Vn = host(V)
+    loss = {name: {k: _start_loss(host(ws.forward(w, X)), Vn, k) for k in (1, 8)}
+            for name, w in (("trained", trained), ("untrained", ws.init_weights(0)),
+                            ("dct", trained * 0.0))}
+    for k in (1, 8):
+        assert loss["trained"][k] < 0.99 * loss["dct"][k], loss
+        assert loss["trained"][k] < 0.97 * loss["untrained"][k], loss
