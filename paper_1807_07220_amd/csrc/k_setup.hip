@@ -554,6 +554,7 @@ __global__ void __launch_bounds__(64) k_pencil_eig(BlockGeom G, const double* __
     __shared__ int rot_flag;
     // the subspace iteration's X, T X (rows < JM) and Rayleigh-Ritz matrices
     __shared__ double Wk[WARM ? 2 * JM * KW + 2 * KW * 9 : 1];
+    __shared__ double thS[WARM ? KW : 1];  // the Ritz values by descending theta
     const int fid = blockIdx.x, lane = threadIdx.x;
     const int nex = (G.Nx - 1) * G.Ny;
     int K1, K2, s1, s2, Jn;
@@ -687,56 +688,45 @@ __global__ void __launch_bounds__(64) k_pencil_eig(BlockGeom G, const double* __
                     order[rank] = lane;
                 }
                 __syncthreads();
-                // Ritz vectors U = X Z and T U = W Z (columns by descending theta)
-                double u[KW], tu[KW], th[KW];
-#pragma unroll
-                for (int c = 0; c < KW; ++c) {
-                    u[c] = 0.0;
-                    tu[c] = 0.0;
-                    th[c] = 0.0;
-                    if (c < kk) {
-                        const int oc = order[c];
-                        th[c] = Hs[oc * 9 + oc];
-#pragma unroll
-                        for (int a = 0; a < KW; ++a)
-                            if (a < kk) {
-                                u[c] += x[a] * Zs[a * 9 + oc];
-                                tu[c] += w[a] * Zs[a * 9 + oc];
-                            }
-                    }
-                }
+                // Ritz vectors U = X Z (to the rows of Xs: X is not read again this
+                // iteration) and T U = W Z (the next start), columns by descending theta
+                double xn[KW];
                 int nabove = 0;
                 bool ok = true;
 #pragma unroll
                 for (int c = 0; c < KW; ++c) {
-                    if (c < kk) nabove += th[c] > sigma;
-                    if (c < l) {
-                        const double r = tu[c] - th[c] * u[c];
-                        ok = ok && sqrt(wave_sum(r * r)) / fabs(th[c]) <= rq_tol;
+                    double uc = 0.0, tuc = 0.0, thc = 0.0;
+                    if (c < kk) {
+                        const int oc = order[c];
+                        thc = Hs[oc * 9 + oc];
+#pragma unroll
+                        for (int a = 0; a < KW; ++a)
+                            if (a < kk) {
+                                uc += x[a] * Zs[a * 9 + oc];
+                                tuc += w[a] * Zs[a * 9 + oc];
+                            }
+                        nabove += thc > sigma;
                     }
+                    if (c < l) {
+                        const double r = tuc - thc * uc;
+                        ok = ok && sqrt(wave_sum(r * r)) / fabs(thc) <= rq_tol;
+                    }
+                    if (lane < JM) Xs[lane * KW + c] = uc;
+                    if (lane == 0) thS[c] = thc;
+                    xn[c] = tuc;
                 }
                 ok = ok && nabove == cnt0;
+                __syncthreads();
                 if (ok) {
-                    // outputs from the Ritz pairs (U staged through LDS, row = lane)
-                    __syncthreads();
-                    if (lane < JM)
-#pragma unroll
-                        for (int c = 0; c < KW; ++c) Xs[lane * KW + c] = u[c];
-                    for (int k = lane; k < G.jmax; k += 64) {
-                        double val = 0.0;
-#pragma unroll
-                        for (int c = 0; c < KW; ++c)
-                            if (c == k && c < kk) val = 1.0 / th[c];
-                        ev[k] = val;
-                    }
-                    __syncthreads();
+                    // outputs from the Ritz pairs (U in Xs, row = lane)
+                    for (int k = lane; k < G.jmax; k += 64) ev[k] = (k < kk && k < KW) ? 1.0 / thS[k] : 0.0;
                     for (int e = lane; e < G.jmax * G.jmax; e += 64) {
                         const int r = e / G.jmax, k = e % G.jmax;
                         Yf[e] = (r < Jn && k < l) ? Xs[r * KW + k] / sqrt(D[r]) : 0.0;
                     }
                     __syncthreads();
                     accepted = true;
-                    if (cnt0 == 0) accepted = inertia_above<LD>(T, A, Jn, th[0] * (1.0 - 4.0 * rq_tol)) == 1;
+                    if (cnt0 == 0) accepted = inertia_above<LD>(T, A, Jn, thS[0] * (1.0 - 4.0 * rq_tol)) == 1;
                     if (accepted) {
                         cnt = l;
                         if (lane == 0) {
@@ -747,7 +737,7 @@ __global__ void __launch_bounds__(64) k_pencil_eig(BlockGeom G, const double* __
                     break;
                 }
 #pragma unroll
-                for (int c = 0; c < KW; ++c) x[c] = tu[c];
+                for (int c = 0; c < KW; ++c) x[c] = xn[c];
                 __syncthreads();
             }
         }
