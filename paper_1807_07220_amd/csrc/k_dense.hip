@@ -31,9 +31,10 @@ constexpr int GLD = TB * TKG / NT;       // elements of A (and of B) each thread
 // 64 x 64 output tile of C = alpha op(A) op(B) + beta C.  Software-pipelined: the next
 // k step's operands are loaded into registers while the current one is multiplied
 // from LDS.
+// kbeg (a multiple of TKG): the sum starts there (the terms before it are known zeros).
 __device__ inline void gemm_tile(int tm, int tn, int transA, int transB, int M, int N, int K, double alpha,
                                  const double* __restrict__ A, int lda, const double* __restrict__ B, int ldb,
-                                 double beta, double* C, int ldc) {
+                                 double beta, double* C, int ldc, int kbeg = 0) {
     __shared__ double As[TKG][TB + 1];
     __shared__ double Bs[TKG][TB + 1];
     const int tid = threadIdx.x;
@@ -69,10 +70,10 @@ __device__ inline void gemm_tile(int tm, int tn, int transA, int transB, int M, 
             Bs[kb][nn] = rb[q];
         }
     };
-    gload(0);
+    gload(kbeg);
     lstore();
     __syncthreads();
-    for (int k0 = 0; k0 < K; k0 += TKG) {
+    for (int k0 = kbeg; k0 < K; k0 += TKG) {
         const bool more = k0 + TKG < K;
         if (more) gload(k0 + TKG);  // in flight while this step multiplies
 #pragma unroll
@@ -145,12 +146,14 @@ __global__ void __launch_bounds__(NT) k_inv_level(InvLevel lv, int step, const d
     const int tm = blockIdx.y, tn = blockIdx.x;
     if (tm * TB >= n2 || tn * TB >= n1) return;  // tiles beyond this node's output
     double* T = Tm + lv.toff[z];
+    // X11 and X22 are lower triangular (zero above the diagonal, written so): the k blocks
+    // above tn (step 0) and beyond tm (step 1) contribute nothing and are skipped
     if (step == 0)
         gemm_tile(tm, tn, 0, 0, n2, n1, n1, 1.0, L + (long long)(o + n1) * n + o, n, X + (long long)o * n + o, n, 0.0,
-                  T, n1);
+                  T, n1, tn * TB);
     else
-        gemm_tile(tm, tn, 0, 0, n2, n1, n2, -1.0, X + (long long)(o + n1) * n + o + n1, n, T, n1, 0.0,
-                  X + (long long)(o + n1) * n + o, n);
+        gemm_tile(tm, tn, 0, 0, n2, n1, min(n2, (tm + 1) * TB), -1.0, X + (long long)(o + n1) * n + o + n1, n, T, n1,
+                  0.0, X + (long long)(o + n1) * n + o, n);
 }
 
 // the inverses of the diagonal blocks (Dinv, [block][64][64]) into the diagonal of X
