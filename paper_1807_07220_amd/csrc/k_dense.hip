@@ -346,11 +346,12 @@ __global__ void __launch_bounds__(NT) k_potrf_diag(double* __restrict__ A, int l
 #pragma unroll
         for (int r = 0; r < 4; ++r) dg[i0 + r] = S[r][r];
     __syncthreads();
-    double si[4], sk[4];  // sqrt(d) of the owned rows and columns
+    double si[4], rsi[4], rsk[4];  // sqrt(d) of the owned rows, reciprocals for rows and columns
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         si[r] = i0 + r < kb ? sqrt(dg[i0 + r]) : 1.0;
-        sk[r] = c0 + r < kb ? sqrt(dg[c0 + r]) : 1.0;
+        rsi[r] = 1.0 / si[r];
+        rsk[r] = 1.0 / (c0 + r < kb ? sqrt(dg[c0 + r]) : 1.0);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -358,8 +359,8 @@ __global__ void __launch_bounds__(NT) k_potrf_diag(double* __restrict__ A, int l
         for (int q = 0; q < 4; ++q) {
             const int i = i0 + r, k = c0 + q;
             const bool in = i < kb && k < kb && k <= i;
-            if (in) A[(long long)(k0 + i) * lda + k0 + k] = (k == i) ? si[r] : S[r][q] / sk[q];
-            Dinv[i * TB + k] = in ? U[r][q] / si[r] : 0.0;
+            if (in) A[(long long)(k0 + i) * lda + k0 + k] = (k == i) ? si[r] : S[r][q] * rsk[q];
+            Dinv[i * TB + k] = in ? U[r][q] * rsi[r] : 0.0;
         }
 }
 
