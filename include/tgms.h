@@ -66,8 +66,12 @@ typedef struct {
     int precision;     /* 0: FP64 preconditioner and PCG;
                           1: FP32 preconditioner (smoother factors, coarse basis, coarse
                              inverse, inner operator applies) inside a flexible FP64 PCG */
-    double s_scale;    /* H in the 1/H prefactor of the s-form (eq. spectral_eqn);
-                          <= 0 selects |K|^(1/2), the coarse block side */
+    double s_scale;    /* H in the 1/H prefactor of the s-form (eq. spectral_eqn).  Default 1
+                          (a unit prefactor): with the printed 1/H and H the block side, a
+                          homogeneous medium keeps about seven modes per face at the
+                          tolerance 10 of section 6, whose tables report one (the coarse RT0
+                          dimension); the unit prefactor reproduces them.  <= 0 selects the
+                          printed |K|^(1/2), the coarse block side */
     void* stream;      /* hipStream_t to run on; NULL = the default stream */
     int graphs;        /* 1: PCG iterations replayed from a captured HIP graph (falls back to
                           direct launches if capture fails); 0: every kernel launched directly */
@@ -115,7 +119,7 @@ typedef struct {
     int rows_per_thread;  /* vertex rows per thread in the tiled PCG kernels (1 or 4) */
 } tgms_info_t;
 
-/* Paper defaults: eta 0.2, overlap 2, FP64, s_scale = |K|^(1/2), default stream,
+/* Paper defaults: eta 0.2, overlap 2, FP64, s_scale = 1 (unit s-form prefactor), default stream,
  * graph replay on, autotuning on without a cache file, dense local eigensolves
  * (warm_start 0, rq_tol 1e-6), smoother staging chosen by the autotuner. */
 void tgms_default_options(tgms_options* opt);

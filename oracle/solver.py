@@ -99,7 +99,7 @@ class OracleSolver:
     """Setup (Steps 1-2 pieces that do not depend on the source) and solve."""
 
     def __init__(self, g: Grid2D, kappa: np.ndarray, eig_tol: float, eta: float = 0.2,
-                 overlap: int = 2, s_scale: float | None = None, basis: str = "gmsfem"):
+                 overlap: int = 2, s_scale: float | None = 1.0, basis: str = "gmsfem"):
         self.g = g
         self.kappa = np.asarray(kappa, dtype=np.float64).reshape(g.ny, g.nx)
         if not np.all(np.isfinite(self.kappa)) or np.any(self.kappa <= 0):

@@ -12,9 +12,19 @@ outward normal).  The spectral problem a(v,w) = lambda s(v,w) on
 span{v_l} uses
     a(v,w) = int_{E_i} kappa^{-1} (v.n_i)(w.n_i),
     s(v,w) = (1/H) ( int_omega kappa^{-1} v.w + int_omega div v div w ),
-where kappa^{-1} on E_i is the mean of the two adjacent cells' values and
-H = |K|^{1/2}.  The first l_i = max(1, #{lambda < tol}) eigenvectors
-(ascending lambda) span V_ms^i.
+where kappa^{-1} on E_i is the mean of the two adjacent cells' values.  The
+first l_i = max(1, #{lambda < tol}) eigenvectors (ascending lambda) span
+V_ms^i.
+
+The prefactor: the paper prints 1/H, but with H the coarse block side the
+zero-net-flux modes of a homogeneous medium have lambda near 1.57 m (scale
+free), so the tolerance 10 of section 6 would keep about seven modes per
+face at kappa = 1, while its tables report the coarse RT0 dimension there
+(one mode per face: model 1 and model 2 at k = 1).  A unit prefactor
+reproduces those dimensions (so does H itself); the oracle and the library
+take the unit prefactor by default.  ``s_scale`` is the H of the 1/H
+prefactor: 1.0 (default) gives the unit prefactor, None the printed
+|K|^{1/2}.
 """
 from __future__ import annotations
 
@@ -82,7 +92,7 @@ def omega_cells(g: Grid2D, face):
     return np.concatenate([g.cells_in(*block_rect(g, *K1)), g.cells_in(*block_rect(g, *K2))])
 
 
-def pencil(g: Grid2D, A, B, kinv_cells, face, faces, Psi, s_scale: float | None = None):
+def pencil(g: Grid2D, A, B, kinv_cells, face, faces, Psi, s_scale: float | None = 1.0):
     """Diagonal of the a-form and the s-form matrix on span(Psi) (eq. spectral_eqn)."""
     _, _, e, e_len, left, right = face_geometry(g, face)
     kE = 0.5 * (kinv_cells[left] + kinv_cells[right])

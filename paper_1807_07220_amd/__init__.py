@@ -34,7 +34,7 @@ class Solver:
     """Setup on construction; see include/tgms.h for the definitions."""
 
     def __init__(self, kappa: torch.Tensor, bx: int, by: int, eig_tol: float, eta: float = 0.2, overlap: int = 2,
-                 precision: str = "fp64", s_scale: float = 0.0, stream: torch.cuda.Stream | None = None,
+                 precision: str = "fp64", s_scale: float = 1.0, stream: torch.cuda.Stream | None = None,
                  graphs: bool = True, autotune: bool = True, tune_cache: str | None = None,
                  warm_start: str = "exact", cnn_weights: torch.Tensor | None = None, rq_tol: float = 1e-6,
                  smoother_staging: int = -1, rows_per_thread: int = 0):

@@ -914,7 +914,7 @@ void tgms_default_options(tgms_options* opt) {
     opt->eta = 0.2;
     opt->overlap = 2;
     opt->precision = 0;
-    opt->s_scale = 0.0;
+    opt->s_scale = 1.0;
     opt->stream = nullptr;
     opt->graphs = 1;
     opt->autotune = 1;

@@ -37,4 +37,4 @@ def test_default_options_are_the_papers():
     lib = _lib.load()
     o = _lib.Options()
     lib.tgms_default_options(ctypes.byref(o))
-    assert o.eta == 0.2 and o.overlap == 2 and o.precision == 0 and o.s_scale == 0.0
+    assert o.eta == 0.2 and o.overlap == 2 and o.precision == 0 and o.s_scale == 1.0
