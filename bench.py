@@ -35,9 +35,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
-SMOOTHER_SRC = os.path.join(ROOT, "paper_1807_07220_amd", "csrc", "k_smooth.hip")
-PMC_RESULTS = os.path.join(ROOT, "profiles", "smoother_pmc_traffic.json")
-SMOOTH_REPS = 200
+CSRC = os.path.join(ROOT, "paper_1807_07220_amd", "csrc")
+PMC_RESULTS = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+KERNEL_REPS = 200
+DEFAULT_WORKLOAD = "darcy2d_1024_b16"
+WARMSTART_WEIGHTS = os.path.join(ROOT, "paper_1807_07220_amd", "data", "warmstart_b16.npy")
+
+
+def patch_rects(nx, ny, bx, by, overlap):
+    for J in range(ny // by):
+        for I in range(nx // bx):
+            i0, i1 = max(I * bx - overlap, 0), min((I + 1) * bx + overlap, nx)
+            j0, j1 = max(J * by - overlap, 0), min((J + 1) * by + overlap, ny)
+            yield i1 - i0 - 1, j1 - j0 - 1
 
 
 def smoother_bytes(nx, ny, bx, by, overlap, word):
@@ -50,15 +60,18 @@ def smoother_bytes(nx, ny, bx, by, overlap, word):
     patch (n words) and writes the local solution (n words).
     """
     total = 0
-    for J in range(ny // by):
-        for I in range(nx // bx):
-            i0, i1 = max(I * bx - overlap, 0), min((I + 1) * bx + overlap, nx)
-            j0, j1 = max(J * by - overlap, 0), min((J + 1) * by + overlap, ny)
-            m, mh = i1 - i0 - 1, j1 - j0 - 1
-            n = m * mh
-            factor = mh * m * (m + 1) // 2 + (mh - 1) * m * m + n
-            total += factor + 2 * n
+    for m, mh in patch_rects(nx, ny, bx, by, overlap):
+        n = m * mh
+        factor = mh * m * (m + 1) // 2 + (mh - 1) * m * m + n
+        total += factor + 2 * n
     return total * word
+
+
+def dir_apply_bytes(nx, ny):
+    """Algorithmic bytes of one k_dir_apply launch (FP64): per vertex it reads z, the
+    old search direction and one cell weight (each cell's weight serves its four
+    vertices) and writes the new search direction and q = K p: 5 words."""
+    return 5 * 8 * nx * ny
 
 
 def source_hash(path):
@@ -66,52 +79,83 @@ def source_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(workload, precision, staged):
-    """HBM bytes per smoother launch from the committed counter runs, or None (also when
-    the counters were taken with another smoother launch mode)."""
+def measured_traffic(kernel, workload, precision, staged=None):
+    """HBM bytes per launch of `kernel` from the committed counter runs, or None when the
+    kernel's source changed since they were taken (or, for the smoother, they were taken
+    in another launch mode)."""
     try:
         with open(PMC_RESULTS) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("source_sha256_16") != source_hash(SMOOTHER_SRC):
-        return None  # the kernel changed since the counters were taken
-    ent = rec.get("workloads", {}).get(f"{workload}/{precision}")
-    if ent is None or ent.get("smooth_staged", staged) != staged:
+    ent = rec.get("kernels", {}).get(kernel)
+    if ent is None or ent.get("source_sha256_16") != source_hash(os.path.join(ROOT, ent.get("source", ""))):
         return None
-    return ent.get("bytes_per_launch")
+    wl = ent.get("workloads", {}).get(f"{workload}/{precision}")
+    if wl is None or (staged is not None and wl.get("smooth_staged", staged) != staged):
+        return None
+    return wl.get("bytes_per_launch")
 
 
-def cpu_baseline(w, kappa, F, gpu_iters, budget_iters=20):
-    """Time the oracle on a bounded sample: full setup, preprocessing, `budget_iters`
-    PCG iterations and the pressure; scale the PCG part to the GPU's iteration count."""
-    from threadpoolctl import threadpool_limits
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, kappa, F, gpu_iters, window=256, budget_iters=20):
+    """Time the oracle on a bounded sample of the workload and scale it to the whole job.
+
+    The sample is the top-left window of `window` x `window` cells of the same
+    permeability field with the same blocks, tolerance and corner source: the oracle's
+    full setup there (block factorisations, snapshots, pencils and eigensolves, coarse
+    operator, smoother patches), its preprocessing, `budget_iters` PCG iterations and
+    the pressure.  Setup, preprocessing and pressure scale with the number of blocks
+    (cells), the PCG part per iteration with the cells and then to the GPU's iteration
+    count.  The oracle is a sequential program (Python loops over blocks, faces and
+    patches, one SuperLU factorisation each); BLAS may use every core of the host."""
+    import warnings
+
+    import numpy as np
 
     from oracle import Grid2D, OracleSolver
-    import warnings
+    from workloads import fields
     warnings.filterwarnings("ignore")
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        o = OracleSolver(Grid2D(w.nx, w.ny, w.bx, w.by), kappa, w.eig_tol)
-        t_setup = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        vbar, gb, _ = o.preprocess(F.ravel())
-        b = -o.apply_A(vbar + gb)
-        t_pre = time.perf_counter() - t0
-        n = min(budget_iters, max(gpu_iters, 1))
-        t0 = time.perf_counter()
-        x, it, *_ = o.pcg(b, 0.0, n)
-        t_pcg = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        o.pressure(vbar + x + gb)
-        t_p = time.perf_counter() - t0
+    n = min(window, w.nx, w.ny)
+    k = np.ascontiguousarray(kappa[:n, :n])
+    Fs = fields.corner_source(n, n)
+    scale = (w.nx * w.ny) / float(n * n)
+    t0 = time.perf_counter()
+    o = OracleSolver(Grid2D(n, n, w.bx, w.by), k, w.eig_tol)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    vbar, gb, _ = o.preprocess(Fs.ravel())
+    b = -o.apply_A(vbar + gb)
+    t_pre = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    x, it, *_ = o.pcg(b, 0.0, budget_iters)
+    t_pcg = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    o.pressure(vbar + x + gb)
+    t_p = time.perf_counter() - t0
     per_it = t_pcg / max(it, 1)
-    est = t_setup + t_pre + per_it * gpu_iters + t_p
-    return {"value": est, "unit": "s/solve", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle setup on the full {w.nx}x{w.ny} field ({t_setup:.1f} s), preprocessing, "
-                       f"{it} PCG iterations ({per_it:.3f} s each) scaled to the GPU's {gpu_iters}, "
-                       f"pressure; one thread"),
-            "setup_s": t_setup, "solve_s": est - t_setup}
+    setup_s = t_setup * scale
+    solve_s = (t_pre + t_p + per_it * gpu_iters) * scale
+    sampled = t_setup + t_pre + t_pcg + t_p
+    return {"value": setup_s + solve_s, "unit": "s/solve", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle on the {n}x{n}-cell top-left window of the same field ({w.bx}x{w.by} blocks, tol "
+                       f"{w.eig_tol}, corner source): setup {t_setup:.1f} s, preprocessing, {it} PCG iterations "
+                       f"({per_it:.3f} s each), pressure ({sampled:.1f} s of CPU work); setup, preprocessing and "
+                       f"pressure scaled by the cell ratio {scale:.0f}, PCG by the cell ratio and to the GPU's "
+                       f"{gpu_iters} iterations"),
+            "setup_s": setup_s, "solve_s": solve_s, "sampled_s": sampled,
+            "threads": "1 (the oracle's loops are sequential; BLAS allowed %d)" % (os.cpu_count() or 1),
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def copy_calibration(nbytes, reps=5):
@@ -130,11 +174,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="darcy2d_256_b16")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
     ap.add_argument("--eig-tol", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-compare", action="store_true", help="skip the mixed-precision comparison")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the FP32-preconditioner and warm-started forms of the same workload")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (read, and written when a shape is tuned): runs that share it "
                          "use the same launch configuration")
@@ -164,9 +209,9 @@ def main():
     Fd = torch.tensor(F, device=dev)
     torch.cuda.synchronize()
 
-    def step(prec):
+    def step(prec, **kw):
         t0 = time.perf_counter()
-        s = tg.Solver(kd, w.bx, w.by, tol, precision=prec, tune_cache=args.tune_cache)
+        s = tg.Solver(kd, w.bx, w.by, tol, precision=prec, tune_cache=args.tune_cache, **kw)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         r = s.solve(Fd, rtol=w.rtol)
@@ -197,17 +242,24 @@ def main():
     rp = s.solve(Fd, rtol=w.rtol)
     prof = {name: s.profile_get(name) for name in ("smoother", "dir_apply", "gather_restrict")}
     s.profile(False)
-    # the smoother alone: SMOOTH_REPS back-to-back launches between one event pair
-    avg_ms = s.time_smoother(SMOOTH_REPS)
+    # the smoother and the search-direction update alone: KERNEL_REPS back-to-back launches
+    # between one event pair each, on the library's stream
+    avg_ms = s.time_smoother(KERNEL_REPS)
+    dir_ms = s.time_dir_apply(KERNEL_REPS)
     s.close()
     assert rp["iters"] == iters
     word = 8 if precision == "fp64" else 4
     nbytes = smoother_bytes(w.nx, w.ny, w.bx, w.by, 2, word)
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(w.name, precision, info["smooth_staged"])
+    traffic = measured_traffic("smoother", w.name, precision, info["smooth_staged"])
+    dbytes = dir_apply_bytes(w.nx, w.ny)
+    dachieved = dbytes / (dir_ms * 1e-3) / 1e9
+    dtraffic = measured_traffic("dir_apply", w.name, precision)
     # per-launch event pairs (each pair adds its own overhead to the launch it brackets)
     kernels = {k: {"launches": v[0], "avg_us_with_event_pair": 1000.0 * v[1] / max(v[0], 1)} for k, v in prof.items()}
     eig_s = (info["t_snap_ms"] + info["t_eig_ms"]) * 1e-3
+    timing = (f"{KERNEL_REPS} back-to-back launches on the library stream between one HIP event pair, right "
+              "after the timed steps, same setup and data")
     out = {
         "metric": "s/solve (setup + solve) at PCG rel. residual 1e-8; eigensolves/s",
         "value": ms_per_step / 1000.0,
@@ -232,29 +284,43 @@ def main():
         "pcg_graph": bool(pcg_graph),
         "setup_s": float(np.median(setups)),
         "solve_s": float(np.median(solves)),
+        "setup_phases_ms": {"snapshots": info["t_snap_ms"], "eigen": info["t_eig_ms"], "coarse": info["t_coarse_ms"],
+                            "smoother_factor": info["t_smoother_ms"]},
         "eigensolves_per_s": info["n_coarse_faces"] / eig_s if eig_s > 0 else None,
         "kernels": kernels,
         "roofline": {"kernel": "smoother patch solve (k_smooth_twisted)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "bytes_per_launch": nbytes, "avg_launch_us": avg_ms * 1000.0,
-                     "timing": (f"{SMOOTH_REPS} back-to-back launches on the library stream between one HIP "
-                                "event pair, right after the timed steps, same setup and data")},
+                     "timing": timing},
+        "roofline_dir_apply": {"kernel": "search-direction update + operator apply (k_dir_apply)", "bound": "hbm",
+                               "achieved": dachieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": dachieved / HBM_PEAK_GBS, "traffic": dtraffic, "bytes_per_launch": dbytes,
+                               "avg_launch_us": dir_ms * 1000.0, "timing": timing},
         "tuning": {"nred": info["nred"], "rows_per_thread": info["rows_per_thread"],
                    "smooth_staged": info["smooth_staged"], "tuned": info["tuned"]},
     }
     if not args.no_compare and precision == "fp64":
-        # the same workload with the FP32 preconditioner inside the flexible FP64 PCG
-        s, r, _, _ = step("mixed")
-        s.close()
-        ts_m, tv_m, it_m = [], [], []
-        for _ in range(2):
-            s, r, ts, tv = step("mixed")
-            ts_m.append(ts)
-            tv_m.append(tv)
-            it_m.append(r["iters"])
+        # the same workload with the FP32 preconditioner inside the flexible FP64 PCG, and
+        # with the warm-started local eigensolves (DCT-II start; the trained network)
+        def compare(prec="fp64", **kw):
+            s, r, _, _ = step(prec, **kw)  # warm-up of this form
             s.close()
-        out["compare_mixed"] = {"s_per_solve": float(np.median(np.add(ts_m, tv_m))), "setup_s": float(np.median(ts_m)),
-                                "solve_s": float(np.median(tv_m)), "iters": it_m[-1]}
+            ts_m, tv_m, it_m = [], [], []
+            for _ in range(2):
+                s, r, ts, tv = step(prec, **kw)
+                ts_m.append(ts)
+                tv_m.append(tv)
+                it_m.append(r["iters"])
+                inf = s.info()
+                s.close()
+            return {"s_per_solve": float(np.median(np.add(ts_m, tv_m))), "setup_s": float(np.median(ts_m)),
+                    "solve_s": float(np.median(tv_m)), "iters": it_m[-1], "eig_ms": inf["t_eig_ms"],
+                    "warm_accepted": inf["warm_accepted"]}
+        out["compare_mixed"] = compare("mixed")
+        out["compare_dct_warm_start"] = compare(warm_start="dct")
+        if w.bx == w.by == 16 and os.path.exists(WARMSTART_WEIGHTS):
+            cw = torch.tensor(np.load(WARMSTART_WEIGHTS, allow_pickle=False), device=dev)
+            out["compare_learned_warm_start"] = compare(warm_start="cnn", cnn_weights=cw)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, kappa, F, iters)
     print(json.dumps(out), flush=True)

@@ -54,8 +54,9 @@ typedef enum {
 } tgms_status;
 
 typedef struct {
-    int nx, ny;   /* fine cells per axis */
-    int bx, by;   /* coarse block size in fine cells; nx % bx == 0, ny % by == 0 */
+    int dim;          /* 2 (the unit square); 3 returns TGMS_E_UNSUPPORTED (not implemented) */
+    int nx, ny, nz;   /* fine cells per axis (nz: 0 or 1 when dim = 2) */
+    int bx, by, bz;   /* coarse block size in fine cells; nx % bx == 0, ny % by == 0 (bz: 0 or 1) */
 } tgms_grid;
 
 typedef struct {
@@ -98,6 +99,19 @@ typedef struct {
                               memory (1 and 2 fall back to 0 where the factor does not fit) */
     int rows_per_thread;   /* vertex rows per thread in the tiled PCG kernels: 0 chosen by the
                               autotuner (without it: 1); 1 or 4 */
+    const int* force_counts;  /* host, n_coarse_faces ints (face order of tgms_get_counts), or NULL:
+                                 impose the basis count l_i of every face (1 <= l_i <= J_i, the
+                                 face's fine faces) instead of #{lambda < eig_tol}; the kept modes
+                                 are still the l_i smallest eigenvalues' (section 4.2).  For
+                                 comparisons with another eigensolver where an eigenvalue lies
+                                 at the tolerance.  Needs warm_start 0 and coarse_space 0; read
+                                 during tgms_setup only. */
+    int coarse_space;  /* coarse space of the two-grid preconditioner (section 5):
+                          0: the adaptive GMsFEM space (section 4; the paper's method);
+                          1: MsFEM, one basis per face, the sum of its snapshots (eq. msfem);
+                          2: the coarse RT0 space (the fine interpolant of the lowest-order
+                             Raviart-Thomas functions on the blocks).  1 and 2 are the
+                             comparators of section 6; they need warm_start 0. */
 } tgms_options;
 
 typedef struct {
@@ -117,11 +131,17 @@ typedef struct {
     int warm_iters;       /* warm start: subspace iterations summed over the accepted faces */
     double t_cnn_ms;      /* warm start 2: network inputs and forward pass (inside t_eig_ms) */
     int rows_per_thread;  /* vertex rows per thread in the tiled PCG kernels (1 or 4) */
+    int eig_unconverged;  /* faces whose dense eigensolve (cyclic Jacobi) was still rotating at its
+                             sweep limit (60 sweeps); their eigenpairs are the last iterate */
+    int coarse_space;     /* as in tgms_options */
+    int nx, ny, bx, by;   /* the grid (also of a context restored by tgms_load) */
+    int precision;        /* as in tgms_options */
 } tgms_info_t;
 
 /* Paper defaults: eta 0.2, overlap 2, FP64, s_scale = 1 (unit s-form prefactor), default stream,
  * graph replay on, autotuning on without a cache file, dense local eigensolves
- * (warm_start 0, rq_tol 1e-6), smoother staging chosen by the autotuner. */
+ * (warm_start 0, rq_tol 1e-6), smoother staging chosen by the autotuner, no imposed
+ * counts, the adaptive coarse space. */
 void tgms_default_options(tgms_options* opt);
 
 /*
@@ -172,6 +192,40 @@ tgms_status tgms_update_mobility(tgms_ctx* ctx, const double* lambda);
 /* Sizes and timings of the setup. */
 tgms_status tgms_info(const tgms_ctx* ctx, tgms_info_t* info);
 
+/*
+ * Checkpoint of the setup (section 6.2 keeps the coarse space of the initial
+ * permeability over all pressure solves): tgms_save writes the permeability the
+ * setup saw (kappa^{-1} per cell), the current cell weights (after mobility
+ * updates), the basis counts, the eigenvalues and each face's kept modes (snapshot
+ * coefficients) to `path` (binary, little-endian; overwritten).  tgms_load
+ * rebuilds a context from it: the snapshots, coarse operator, factorisations and
+ * smoother are formed again from the saved weights, the eigenproblems are not
+ * solved again.  eta, overlap, precision, s_scale, coarse_space and the eigenvalue
+ * tolerance come from the file; opt (NULL = defaults) gives the stream, graphs,
+ * autotuning, tuning cache, smoother staging and rows per thread.  With the same
+ * launch configuration (autotune 0, or one tuning cache) a loaded context's solves
+ * are bitwise those of the saved one.  TGMS_E_INVAL when the file cannot be opened,
+ * read or written, is not a saved context of this version, or holds inconsistent
+ * sizes, counts or weights; *out is then NULL.
+ */
+tgms_status tgms_save(const tgms_ctx* ctx, const char* path);
+tgms_status tgms_load(const char* path, const tgms_options* opt, tgms_ctx** out);
+
+/* The pencil of every coarse face's local spectral problem (section 4.2, eqs.
+ * spectral_1, spectral_eqn) in the snapshot basis, as the eigensolver forms it:
+ * D (device, n_coarse_faces * jmax doubles) the diagonal of a(., .) =
+ * |e_l| (kappa^{-1} mean of the two cells at e_l), and S (device, n_coarse_faces *
+ * jmax * jmax doubles, row-major per face, symmetrised) s(., .) with its prefactor;
+ * jmax = max(bx, by); entries beyond a face's J_i fine faces are 0.  Reflects the
+ * current operator (its Gram matrices are rebuilt by tgms_update_mobility).
+ * TGMS_E_INVAL for the RT0 coarse space (no snapshots). */
+tgms_status tgms_probe_pencil(tgms_ctx* ctx, double* D, double* S);
+
+/* Return the device memory blocks the library keeps for reuse (freed contexts'
+ * workspaces, at most 16 GB per device) to the HIP runtime, on the current device.
+ * Call with no context of the library in use on that device from another thread. */
+void tgms_trim_device_cache(void);
+
 /* Basis counts l_i (host, n_coarse_faces ints) and all eigenvalues lambda of
  * each local spectral problem, ascending (host, n_coarse_faces * jmax doubles,
  * jmax = max(bx, by); rows of faces with fewer fine faces are padded with 0).
@@ -204,6 +258,11 @@ tgms_status tgms_profile_get(tgms_ctx* ctx, int kernel, int* launches, double* t
  * not consulted).  Requires a completed setup.  reps in [1, 100000], else
  * TGMS_E_INVAL.  Blocks the host until the launches have finished. */
 tgms_status tgms_time_smoother(tgms_ctx* ctx, int reps, double* avg_ms);
+
+/* The same for the search-direction update with the operator apply (p' = z + beta p,
+ * q = K p' with K = C^T A C, and the partial sums of p'^T q) over the context's own
+ * work vectors; the PCG scalars are overwritten (the next solve sets them again). */
+tgms_status tgms_time_dir_apply(tgms_ctx* ctx, int reps, double* avg_ms);
 
 /* Per-face outcome of the warm-started eigensolves of a context set up with
  * warm_start 1 or 2: wstat (host, n_coarse_faces ints) receives the subspace

@@ -99,7 +99,13 @@ class OracleSolver:
     """Setup (Steps 1-2 pieces that do not depend on the source) and solve."""
 
     def __init__(self, g: Grid2D, kappa: np.ndarray, eig_tol: float, eta: float = 0.2,
-                 overlap: int = 2, s_scale: float | None = 1.0, basis: str = "gmsfem"):
+                 overlap: int = 2, s_scale: float | None = 1.0, basis: str = "gmsfem", force_counts=None):
+        """basis: "gmsfem" (section 4, the adaptive space), "msfem" (one function per
+        coarse face, the sum of its snapshots, eq. msfem) or "rt0" (the coarse RT0
+        space); the last two are the comparators of section 6.  force_counts: the
+        number of eigenfunctions kept per coarse face (in the order of
+        ``g.coarse_faces()``) instead of #{lambda < tol}, for comparisons where an
+        eigenvalue lies at the tolerance."""
         self.g = g
         self.kappa = np.asarray(kappa, dtype=np.float64).reshape(g.ny, g.nx)
         if not np.all(np.isfinite(self.kappa)) or np.any(self.kappa <= 0):
@@ -119,27 +125,36 @@ class OracleSolver:
         self.faces = g.coarse_faces()
         # Step 2: adaptive coarse space (section 4)
         self.omega_faces, self.Psi, self.eigs, self.counts, self.Phi_local = [], [], [], [], []
-        for face in self.faces:
-            fa, Psi = snapshots(g, self.A, self.B, self.block, face)
-            Dg, S = pencil(g, self.A, self.B, self.kinv, face, fa, Psi, s_scale)
-            lam, V, cnt = select(Dg, S, self.eig_tol)
-            if basis == "msfem":       # sum of all snapshots: unit flux on E (section 4.2, eq. msfem)
-                cnt, Vk = 1, np.ones((Psi.shape[1], 1))
-            else:
-                Vk = V[:, :cnt]
-            self.omega_faces.append(fa)
-            self.Psi.append(Psi)
-            self.eigs.append(lam)
-            self.counts.append(cnt)
-            self.Phi_local.append(Psi @ Vk)
-        self.counts = np.asarray(self.counts, dtype=np.int64)
-        rows, cols, vals, off = [], [], [], 0
-        for fa, Ph in zip(self.omega_faces, self.Phi_local):
-            for k in range(Ph.shape[1]):
-                rows.append(fa); cols.append(np.full(fa.size, off + k)); vals.append(Ph[:, k])
-            off += Ph.shape[1]
-        self.Phi = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
-                                 shape=(g.nf, off))
+        if basis not in ("gmsfem", "msfem", "rt0"):
+            raise ValueError(basis)
+        if basis == "rt0":
+            # the coarse RT0 functions themselves (section 2: V_H subset V_h), one per face
+            self.Phi = coarse_rt0_interpolation(g)
+            self.counts = np.ones(len(self.faces), dtype=np.int64)
+        else:
+            for k, face in enumerate(self.faces):
+                fa, Psi = snapshots(g, self.A, self.B, self.block, face)
+                Dg, S = pencil(g, self.A, self.B, self.kinv, face, fa, Psi, s_scale)
+                lam, V, cnt = select(Dg, S, self.eig_tol)
+                if force_counts is not None:
+                    cnt = int(force_counts[k])
+                if basis == "msfem":       # sum of all snapshots: unit flux on E (section 4.2, eq. msfem)
+                    cnt, Vk = 1, np.ones((Psi.shape[1], 1))
+                else:
+                    Vk = V[:, :cnt]
+                self.omega_faces.append(fa)
+                self.Psi.append(Psi)
+                self.eigs.append(lam)
+                self.counts.append(cnt)
+                self.Phi_local.append(Psi @ Vk)
+            self.counts = np.asarray(self.counts, dtype=np.int64)
+            rows, cols, vals, off = [], [], [], 0
+            for fa, Ph in zip(self.omega_faces, self.Phi_local):
+                for k in range(Ph.shape[1]):
+                    rows.append(fa); cols.append(np.full(fa.size, off + k)); vals.append(Ph[:, k])
+                off += Ph.shape[1]
+            self.Phi = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                                     shape=(g.nf, off))
         self.RQ = block_aggregation(g)
         AH = (self.Phi.T @ self.A @ self.Phi).toarray()
         BH = (self.RQ @ self.B @ self.Phi).toarray()

@@ -14,7 +14,14 @@ import torch
 
 from ._lib import Grid, Info, Options, TgmsError, check, load  # noqa: F401
 
-__all__ = ["Solver", "TgmsError", "nfaces"]
+__all__ = ["Solver", "TgmsError", "nfaces", "trim_device_cache"]
+
+COARSE_SPACES = {"gmsfem": 0, "msfem": 1, "rt0": 2}
+
+
+def trim_device_cache():
+    """Return the device blocks the library keeps for reuse to the runtime (tgms_trim_device_cache)."""
+    load().tgms_trim_device_cache()
 
 
 def nfaces(nx: int, ny: int) -> int:
@@ -37,14 +44,13 @@ class Solver:
                  precision: str = "fp64", s_scale: float = 1.0, stream: torch.cuda.Stream | None = None,
                  graphs: bool = True, autotune: bool = True, tune_cache: str | None = None,
                  warm_start: str = "exact", cnn_weights: torch.Tensor | None = None, rq_tol: float = 1e-6,
-                 smoother_staging: int = -1, rows_per_thread: int = 0):
+                 smoother_staging: int = -1, rows_per_thread: int = 0, force_counts=None,
+                 coarse_space: str = "gmsfem", _restore: str | None = None):
         lib = load()
-        if kappa.dim() != 2:
+        if kappa is not None and kappa.dim() != 2:
             raise ValueError("kappa must be (ny, nx)")
-        self.ny, self.nx = kappa.shape
-        self.bx, self.by = int(bx), int(by)
-        self.device = kappa.device
-        self.stream = stream if stream is not None else torch.cuda.current_stream(kappa.device)
+        self.device = kappa.device if kappa is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         opt = Options()
         lib.tgms_default_options(ctypes.byref(opt))
         opt.eta, opt.overlap, opt.s_scale = float(eta), int(overlap), float(s_scale)
@@ -54,21 +60,59 @@ class Solver:
         opt.autotune = 1 if autotune else 0
         self._tune_cache = None if tune_cache is None else str(tune_cache).encode()
         opt.tune_cache = self._tune_cache
+        opt.smoother_staging = int(smoother_staging)
+        opt.rows_per_thread = int(rows_per_thread)
+        opt.coarse_space = COARSE_SPACES[coarse_space]
+        if _restore is not None:
+            handle = ctypes.c_void_p()
+            check(lib.tgms_load(str(_restore).encode(), ctypes.byref(opt), ctypes.byref(handle)))
+            self._h = handle
+            self._from_info()
+            return
+        self.ny, self.nx = kappa.shape
+        self.bx, self.by = int(bx), int(by)
+        if force_counts is not None:
+            import numpy as np
+            self._force = np.ascontiguousarray(force_counts, dtype=np.int32)
+            opt.force_counts = self._force.ctypes.data_as(ctypes.c_void_p)
         opt.warm_start = {"exact": 0, "dct": 1, "cnn": 2}[warm_start]
         if cnn_weights is not None:
             if not (cnn_weights.is_cuda and cnn_weights.dtype == torch.float32 and cnn_weights.is_contiguous()):
                 raise ValueError("cnn_weights must be a contiguous float32 CUDA tensor")
             opt.cnn_weights = ctypes.c_void_p(cnn_weights.data_ptr())
         opt.rq_tol = float(rq_tol)
-        opt.smoother_staging = int(smoother_staging)
-        opt.rows_per_thread = int(rows_per_thread)
-        grid = Grid(self.nx, self.ny, self.bx, self.by)
+        grid = Grid(2, self.nx, self.ny, 1, self.bx, self.by, 1)
         handle = ctypes.c_void_p()
         kappa = kappa.contiguous()
         check(lib.tgms_setup(ctypes.byref(grid), _ptr(kappa), float(eig_tol), ctypes.byref(opt),
                              ctypes.byref(handle)))
         self._h = handle
         self.precision = precision
+
+    @classmethod
+    def load(cls, path: str, stream: torch.cuda.Stream | None = None, graphs: bool = True, autotune: bool = True,
+             tune_cache: str | None = None, smoother_staging: int = -1, rows_per_thread: int = 0) -> "Solver":
+        """Restore a context written by save() (tgms_load): the coarse space is read, not solved for."""
+        return cls(None, 0, 0, 0.0, stream=stream, graphs=graphs, autotune=autotune, tune_cache=tune_cache,
+                   smoother_staging=smoother_staging, rows_per_thread=rows_per_thread, _restore=path)
+
+    def _from_info(self):
+        inf = self.info()
+        self.nx, self.ny, self.bx, self.by = inf["nx"], inf["ny"], inf["bx"], inf["by"]
+        self.precision = "mixed" if inf["precision"] else "fp64"
+
+    def save(self, path: str):
+        """Write the setup artefact (tgms_save)."""
+        check(load().tgms_save(self._h, str(path).encode()))
+
+    def probe_pencil(self):
+        """Per coarse face the a-form diagonal D [faces][jmax] and s-form S [faces][jmax][jmax] (GPU)."""
+        n = self.info()["n_coarse_faces"]
+        jmax = max(self.bx, self.by)
+        D = torch.empty((n, jmax), dtype=torch.float64, device=self.device)
+        S = torch.empty((n, jmax, jmax), dtype=torch.float64, device=self.device)
+        check(load().tgms_probe_pencil(self._h, _ptr(D), _ptr(S)))
+        return D, S
 
     # ---- results ----------------------------------------------------------
     def solve(self, F: torch.Tensor, g: torch.Tensor | None = None, rtol: float = 1e-8, maxit: int = 1000,
@@ -148,6 +192,13 @@ class Solver:
         back-to-back launches bracketed by one HIP event pair."""
         ms = ctypes.c_double(0.0)
         check(load().tgms_time_smoother(self._h, int(reps), ctypes.byref(ms)))
+        return ms.value
+
+    def time_dir_apply(self, reps: int = 200) -> float:
+        """Average duration (ms) of one search-direction update with the operator apply
+        (k_dir_apply) over `reps` back-to-back launches between one HIP event pair."""
+        ms = ctypes.c_double(0.0)
+        check(load().tgms_time_dir_apply(self._h, int(reps), ctypes.byref(ms)))
         return ms.value
 
     # ---- probes -----------------------------------------------------------

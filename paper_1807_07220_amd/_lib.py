@@ -26,14 +26,16 @@ class TgmsError(RuntimeError):
 
 
 class Grid(ctypes.Structure):
-    _fields_ = [("nx", c_int), ("ny", c_int), ("bx", c_int), ("by", c_int)]
+    _fields_ = [("dim", c_int), ("nx", c_int), ("ny", c_int), ("nz", c_int), ("bx", c_int), ("by", c_int),
+                ("bz", c_int)]
 
 
 class Options(ctypes.Structure):
     _fields_ = [("eta", c_double), ("overlap", c_int), ("precision", c_int), ("s_scale", c_double),
                 ("stream", c_void_p), ("graphs", c_int), ("autotune", c_int), ("tune_cache", c_char_p),
                 ("warm_start", c_int), ("cnn_weights", c_void_p), ("rq_tol", c_double),
-                ("smoother_staging", c_int), ("rows_per_thread", c_int)]
+                ("smoother_staging", c_int), ("rows_per_thread", c_int), ("force_counts", c_void_p),
+                ("coarse_space", c_int)]
 
 
 class Info(ctypes.Structure):
@@ -41,7 +43,9 @@ class Info(ctypes.Structure):
                 ("t_setup_ms", c_double), ("t_snap_ms", c_double), ("t_eig_ms", c_double),
                 ("t_coarse_ms", c_double), ("t_smoother_ms", c_double), ("lds_max", c_int), ("pcg_graph", c_int),
                 ("tuned", c_int), ("nred", c_int), ("smooth_staged", c_int), ("warm_accepted", c_int),
-                ("warm_iters", c_int), ("t_cnn_ms", c_double), ("rows_per_thread", c_int)]
+                ("warm_iters", c_int), ("t_cnn_ms", c_double), ("rows_per_thread", c_int),
+                ("eig_unconverged", c_int), ("coarse_space", c_int), ("nx", c_int), ("ny", c_int), ("bx", c_int),
+                ("by", c_int), ("precision", c_int)]
 
 
 _lib = None
@@ -59,6 +63,7 @@ SIGNATURES = {
     "tgms_profile": (c_int, [c_void_p, c_int]),
     "tgms_profile_get": (c_int, [c_void_p, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_double)]),
     "tgms_time_smoother": (c_int, [c_void_p, c_int, ctypes.POINTER(c_double)]),
+    "tgms_time_dir_apply": (c_int, [c_void_p, c_int, ctypes.POINTER(c_double)]),
     "tgms_destroy": (None, [c_void_p]),
     "tgms_last_error": (c_char_p, []),
     "tgms_apply_A": (c_int, [c_void_p, c_void_p, c_void_p]),
@@ -73,6 +78,10 @@ SIGNATURES = {
     "tgms_cnn_train_step": (c_int, [c_void_p, c_void_p, c_void_p, c_int, ctypes.c_float, c_void_p, c_void_p, c_int,
                                     c_int, c_int, c_int, c_void_p, ctypes.POINTER(c_double), c_void_p]),
     "tgms_cnn_samples": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "tgms_save": (c_int, [c_void_p, c_char_p]),
+    "tgms_load": (c_int, [c_char_p, ctypes.POINTER(Options), ctypes.POINTER(c_void_p)]),
+    "tgms_probe_pencil": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "tgms_trim_device_cache": (None, []),
 }
 
 

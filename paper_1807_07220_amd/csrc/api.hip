@@ -10,9 +10,11 @@
 #include <algorithm>
 #include <mutex>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <set>
+#include <string>
 
 #include "common.h"
 #include "band.h"
@@ -396,16 +398,43 @@ void build_rt0_stiffness(tgms_ctx* c) {
     const int nv = c->nv;
     if (!c->KH) c->KH = c->alloc<double>((size_t)nv * nv);
     tgms::zero(c, c->KH, sizeof(double) * (size_t)nv * nv);
-    tgms::rt0_stiffness(c, c->KH);
+    tgms::rt0_stiffness(c, c->AH0, c->KH);
     tgms::dense_spd_inverse(c, c->KH, nv);
 }
 
+// The coarse matrix of the RT0 coarse space: the coarse vertex stiffness over the
+// bilinear stream functions (exactly W^T K W for the W of tgms::rt0_coarse_W), from
+// Grams of the current cell weights formed on the calling stream.
+void rt0_coarse_matrix(tgms_ctx* c) {
+    if (!c->AH0c) c->AH0c = c->alloc<double>((size_t)c->nblk * 6);
+    tgms::coarse_rt0_blocks(c, c->AH0c);
+    tgms::zero(c, c->Ac, sizeof(double) * (size_t)c->ncs * c->ncs);
+    tgms::rt0_stiffness(c, c->AH0c, c->Ac);
+}
+
+// What tgms_save writes and tgms_load reads back: the permeability as the setup saw it
+// (kappa^{-1}), the current cell weights (after mobility updates), and the adaptive
+// coarse space: basis counts, eigenvalues and each face's kept modes (in snapshot
+// coefficients, recombined into the unit-flux carrier and zero-flux modes).
+struct Artefact {
+    int nx = 0, ny = 0, bx = 0, by = 0, overlap = 0, precision = 0, coarse_space = 0, mobility = 0, ne = 0, jmax = 0;
+    double eta = 0, tol = 0, H = 0;
+    std::vector<double> kinv, a, eigs, YQ;
+    std::vector<int> counts;
+};
+
+void rebuild_operator(tgms_ctx* c);
+
+// art: a saved context to restore (kappa unused; the coarse space is read, not solved for)
 void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, const tgms_options* opt,
-                tgms_ctx** out) {
-    if (!grid || !kappa || !out) throw TgmsError{TGMS_E_INVAL, "null argument"};
+                tgms_ctx** out, const Artefact* art = nullptr) {
+    if (!grid || (!kappa && !art) || !out) throw TgmsError{TGMS_E_INVAL, "null argument"};
     tgms_options o;
     tgms_default_options(&o);
     if (opt) o = *opt;
+    if (grid->dim == 3) throw TgmsError{TGMS_E_UNSUPPORTED, "three-dimensional grids are not implemented"};
+    if (grid->dim != 2 || grid->nz > 1 || grid->bz > 1)
+        throw TgmsError{TGMS_E_INVAL, "dim must be 2 (with nz and bz 0 or 1)"};
     const int nx = grid->nx, ny = grid->ny, bx = grid->bx, by = grid->by;
     if (nx <= 0 || ny <= 0 || bx <= 0 || by <= 0 || nx % bx || ny % by)
         throw TgmsError{TGMS_E_INVAL, "grid sizes must be positive and divisible by the block size"};
@@ -426,6 +455,15 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         throw TgmsError{TGMS_E_INVAL, "smoother_staging must be -1, 0, 1 or 2"};
     if (o.rows_per_thread != 0 && o.rows_per_thread != 1 && o.rows_per_thread != 4)
         throw TgmsError{TGMS_E_INVAL, "rows_per_thread must be 0, 1 or 4"};
+    if (o.coarse_space < 0 || o.coarse_space > 2) throw TgmsError{TGMS_E_INVAL, "coarse_space must be 0, 1 or 2"};
+    if (o.force_counts && (o.warm_start != 0 || o.coarse_space != 0))
+        throw TgmsError{TGMS_E_INVAL, "force_counts needs the dense eigensolve of the adaptive space"};
+    if (o.coarse_space != 0 && o.warm_start != 0)
+        throw TgmsError{TGMS_E_INVAL, "the MsFEM and RT0 coarse spaces solve no eigenproblem to warm-start"};
+    if (art) {
+        o.warm_start = 0;
+        o.force_counts = nullptr;
+    }
     if (o.warm_start == 2) {
         if (!o.cnn_weights) throw TgmsError{TGMS_E_INVAL, "warm_start 2 needs cnn_weights"};
         if (bx != by || !tgms::cnn_shape_ok(2 * bx, bx))
@@ -466,6 +504,8 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         c->hx = 1.0 / nx; c->hy = 1.0 / ny;
         c->sx = 1.0 / c->hy; c->sy = 1.0 / c->hx;
         c->H = o.s_scale > 0 ? o.s_scale : std::sqrt(bx * c->hx * by * c->hy);
+        c->coarse_space = o.coarse_space;
+        c->eig_bad = c->alloc<int>(1);
         c->eta = o.eta; c->tol = eig_tol; c->overlap = o.overlap; c->precision = o.precision ? 1 : 0;
         c->graph_failed = o.graphs == 0;  // never capture: launch every kernel directly
         c->warm = o.warm_start;
@@ -483,12 +523,25 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         Timer total(c->stream);
         c->kinv = c->alloc<double>(ncell);
         c->a = c->alloc<double>(ncell);
-        int* bad = c->alloc<int>(1);
-        tgms::cell_weights(c, kappa, bad);
-        int hbad = 0;
-        HIP_OK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-        HIP_OK(hipStreamSynchronize(c->stream));
-        if (hbad) throw TgmsError{TGMS_E_INVAL, "permeability must be finite and positive"};
+        if (art) {
+            HIP_OK(hipMemcpyAsync(c->kinv, art->kinv.data(), sizeof(double) * ncell, hipMemcpyHostToDevice, c->stream));
+            tgms::weights_from_kinv(c);
+        } else {
+            int* bad = c->alloc<int>(1);
+            tgms::cell_weights(c, kappa, bad);
+            int hbad = 0;
+            HIP_OK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+            HIP_OK(hipStreamSynchronize(c->stream));
+            if (hbad) throw TgmsError{TGMS_E_INVAL, "permeability must be finite and positive"};
+        }
+        if (o.force_counts) {
+            for (int f = 0; f < c->ne; ++f) {
+                const int J = f < c->nex ? by : bx, l = o.force_counts[f];
+                if (l < 1 || l > J) throw TgmsError{TGMS_E_INVAL, "force_counts entries must lie in [1, J_i]"};
+            }
+            c->force = c->alloc<int>(c->ne);
+            HIP_OK(hipMemcpyAsync(c->force, o.force_counts, sizeof(int) * c->ne, hipMemcpyHostToDevice, c->stream));
+        }
         // block factors
         c->blk_m = bx - 1;
         c->blk_n = (bx - 1) * (by - 1);
@@ -522,8 +575,10 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
             c->APsi = c->alloc<double>((size_t)c->nblk * c->ncol * (gram_mfma ? nvk : (size_t)c->nfk));
             c->G = c->alloc<double>((size_t)c->nblk * c->ncol * c->ncol);
             // the A Psi array is free until the Gram products: the snapshot solves' scratch
-            tgms::snapshots(c, c->APsi, (long long)c->ncol * (gram_mfma ? (long long)nvk : (long long)c->nfk));
-            tgms::gram(c);
+            if (c->coarse_space != 2) {  // the RT0 coarse space needs no snapshots
+                tgms::snapshots(c, c->APsi, (long long)c->ncol * (gram_mfma ? (long long)nvk : (long long)c->nfk));
+                tgms::gram(c);
+            }
             {
                 const hipStream_t main_stream = c->stream;
                 struct Restore {
@@ -532,8 +587,8 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                     ~Restore() { c->stream = s; }
                 } restore{c, main_stream};
                 c->stream = side.s;
-                tgms::coarse_rt0_blocks(c);
-                tgms::rt0_stiffness(c, c->KH);
+                tgms::coarse_rt0_blocks(c, c->AH0);
+                tgms::rt0_stiffness(c, c->AH0, c->KH);
                 tgms::dense_spd_inverse_begin(c, c->KH, c->nv, kh_inv);
             }
             HIP_OK(hipEventRecord(side.e1, side.s));
@@ -550,7 +605,21 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         c->counts = c->alloc<int>(c->ne);
         c->Y = c->alloc<double>((size_t)c->ne * c->jmax * c->jmax);
         double* YQd = c->alloc<double>((size_t)c->ne * c->jmax * c->jmax);
-        {
+        c->YQ = YQd;
+        if (art) {
+            // the coarse space of the saved context
+            Timer t(c->stream);
+            HIP_OK(hipMemcpyAsync(c->eigs, art->eigs.data(), sizeof(double) * art->eigs.size(), hipMemcpyHostToDevice,
+                                  c->stream));
+            HIP_OK(hipMemcpyAsync(c->counts, art->counts.data(), sizeof(int) * c->ne, hipMemcpyHostToDevice, c->stream));
+            HIP_OK(hipMemcpyAsync(YQd, art->YQ.data(), sizeof(double) * art->YQ.size(), hipMemcpyHostToDevice,
+                                  c->stream));
+            c->t_eig_ms = t.ms();
+        } else if (c->coarse_space == 2) {
+            // RT0: one coarse function per face, no eigenproblem
+            std::vector<int> ones(c->ne, 1);
+            HIP_OK(hipMemcpyAsync(c->counts, ones.data(), sizeof(int) * c->ne, hipMemcpyHostToDevice, c->stream));
+        } else {
             Timer t(c->stream);
             const float* Y0 = nullptr;
             if (c->warm) c->wstat = c->alloc<int>(c->ne);
@@ -566,6 +635,7 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
             }
             tgms::pencil_eig_q(c, YQd, Y0, nullptr);
             c->t_eig_ms = t.ms();
+            HIP_OK(hipMemcpyAsync(&c->eig_unconverged, c->eig_bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
         }
         {
             Timer t(c->stream);
@@ -586,12 +656,17 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
             build_coarse_numbering(c, meta);
             int* metad = c->alloc<int>(meta.size());
             HIP_OK(hipMemcpyAsync(metad, meta.data(), sizeof(int) * meta.size(), hipMemcpyHostToDevice, c->stream));
-            c->Td = c->alloc<double>((size_t)c->nblk * c->ncol * c->mu);
-            tgms::fill_td(c, metad, YQd, c->Td);
             c->W = c->alloc<double>((size_t)c->nblk * bx * by * c->mu);
             if (c->precision) c->W32 = c->alloc<float>((size_t)c->nblk * bx * by * c->mu);
             c->Ac = c->alloc<double>((size_t)c->ncs * c->ncs);
-            tgms::coarse_local_run(c, c->Td, c->zcd);
+            if (c->coarse_space == 2) {
+                tgms::rt0_coarse_W(c);
+                rt0_coarse_matrix(c);
+            } else {
+                c->Td = c->alloc<double>((size_t)c->nblk * c->ncol * c->mu);
+                tgms::fill_td(c, metad, YQd, c->Td);
+                tgms::coarse_local_run(c, c->Td, c->zcd);
+            }
             // smoother patches (section 5): factorised on the second stream while the
             // dense coarse factorisation, a chain of small kernels, runs on this one
             c->patch_h.resize(c->nblk);
@@ -711,6 +786,13 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         tgms::allow_fused_lds(c);
         c->vp1 = c->alloc<double>(nvtx);
         HIP_OK(hipHostMalloc((void**)&c->red_h, SC_COUNT * sizeof(double), hipHostMallocDefault));
+        if (art && art->mobility) {
+            // the saved context had its mobility updated: its weights, and every factor
+            // built from them
+            HIP_OK(hipMemcpyAsync(c->a, art->a.data(), sizeof(double) * ncell, hipMemcpyHostToDevice, c->stream));
+            c->mobility_updated = true;
+            rebuild_operator(c);
+        }
         if (o.autotune) tgms::autotune(c, o.tune_cache);
         if (o.smoother_staging >= 0) c->smooth_staged = o.smoother_staging;
         if (o.rows_per_thread == 1 || o.rows_per_thread == 4) c->rpt = o.rows_per_thread;
@@ -730,30 +812,42 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
 // depends on it is rebuilt: block factors (preprocessing), the block Gram
 // matrices of the fixed snapshots and the coarse SPD matrix over the fixed
 // basis, its Cholesky inverse, the coarse RT0 operator and the smoother patches.
-void update_mobility_impl(tgms_ctx* c, const double* lambda) {
-    if (!c || !lambda) throw TgmsError{TGMS_E_INVAL, "null argument"};
-    tgms::enter(c);
-    int* bad = c->alloc_scratch_int();
-    tgms::mobility_weights(c, lambda, bad);
-    int hbad = 0;
-    HIP_OK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    HIP_OK(hipStreamSynchronize(c->stream));
-    if (hbad) throw TgmsError{TGMS_E_INVAL, "mobility must be finite and positive"};
-    c->mobility_updated = true;
+// every factor built from the cell weights c->a, with the coarse basis kept
+void rebuild_operator(tgms_ctx* c) {
     tgms::factor_blocks(c);
-    tgms::gram(c);
-    tgms::zero(c, c->Ac, sizeof(double) * (size_t)c->ncs * c->ncs);
-    tgms::coarse_local_run(c, c->Td, c->zcd);
+    if (c->coarse_space == 2) {
+        rt0_coarse_matrix(c);
+    } else {
+        tgms::gram(c);
+        tgms::zero(c, c->Ac, sizeof(double) * (size_t)c->ncs * c->ncs);
+        tgms::coarse_local_run(c, c->Td, c->zcd);
+    }
     tgms::dense_spd_inverse(c, c->Ac, c->ncs, c->Acf);
     if (c->precision) tgms::cast_d2f(c, (long long)c->ncs * c->ncs, c->Ac, c->Ac32);
-    tgms::coarse_rt0_blocks(c);
+    tgms::coarse_rt0_blocks(c, c->AH0);
     build_rt0_stiffness(c);
     tgms::factor_patches(c);
     HIP_OK(hipStreamSynchronize(c->stream));
 }
 
+void update_mobility_impl(tgms_ctx* c, const double* lambda) {
+    if (!c || !lambda) throw TgmsError{TGMS_E_INVAL, "null argument"};
+    tgms::enter(c);
+    // the new weights go to a scratch array first: an invalid field leaves the context as it was
+    int* bad = c->alloc_scratch_int();
+    tgms::mobility_weights(c, lambda, bad, c->cellw2);
+    int hbad = 0;
+    HIP_OK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (hbad) throw TgmsError{TGMS_E_INVAL, "mobility must be finite and positive"};
+    tgms::copy(c, (long long)c->nx * c->ny, c->cellw2, c->a);
+    c->mobility_updated = true;
+    rebuild_operator(c);
+}
+
+// keep_history: read the PCG's alpha, beta back to the host (for tgms_last_cond)
 void solve_impl(tgms_ctx* c, const double* F, const double* g_bnd, double rtol, int maxit, double* u, double* p,
-                int* iters, double* relres, tgms_status* st) {
+                int* iters, double* relres, tgms_status* st, bool keep_history = true) {
     if (!c || !F || !u) throw TgmsError{TGMS_E_INVAL, "null argument"};
     if (!(rtol >= 0) || maxit < 0) throw TgmsError{TGMS_E_INVAL, "bad rtol or maxit"};
     tgms::enter(c);
@@ -884,7 +978,7 @@ void solve_impl(tgms_ctx* c, const double* F, const double* g_bnd, double rtol, 
         *st = TGMS_E_NOTCONV;
     c->alphas.clear();
     c->betas.clear();
-    if (it > 0) {
+    if (it > 0 && keep_history) {
         std::vector<double> h(2 * (size_t)it);
         HIP_OK(hipMemcpyAsync(h.data(), c->hist, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));
         HIP_OK(hipStreamSynchronize(c->stream));
@@ -902,6 +996,100 @@ void solve_impl(tgms_ctx* c, const double* F, const double* g_bnd, double rtol, 
     if (*st != TGMS_OK) {
         g_last_error = (*st == TGMS_E_NOTCONV) ? "PCG did not converge within maxit" : "PCG breakdown";
     }
+}
+
+constexpr char kMagic[8] = {'T', 'G', 'M', 'S', 'C', 'S', '0', '1'};
+
+struct FileHeader {
+    char magic[8];
+    int32_t version, nx, ny, bx, by, overlap, precision, coarse_space, mobility, ne, jmax, pad;
+    double eta, tol, H;
+};
+
+void save_impl(const tgms_ctx* c, const char* path) {
+    tgms_ctx* cc = const_cast<tgms_ctx*>(c);
+    const long long ncell = (long long)c->nx * c->ny;
+    const size_t nq = (size_t)c->ne * c->jmax * c->jmax;
+    Artefact a;
+    a.kinv.resize(ncell);
+    a.a.resize(ncell);
+    a.eigs.resize((size_t)c->ne * c->jmax);
+    a.YQ.resize(nq);
+    HIP_OK(hipMemcpyAsync(a.kinv.data(), c->kinv, sizeof(double) * ncell, hipMemcpyDeviceToHost, cc->stream));
+    HIP_OK(hipMemcpyAsync(a.a.data(), c->a, sizeof(double) * ncell, hipMemcpyDeviceToHost, cc->stream));
+    HIP_OK(hipMemcpyAsync(a.eigs.data(), c->eigs, sizeof(double) * a.eigs.size(), hipMemcpyDeviceToHost, cc->stream));
+    HIP_OK(hipMemcpyAsync(a.YQ.data(), c->YQ, sizeof(double) * nq, hipMemcpyDeviceToHost, cc->stream));
+    HIP_OK(hipStreamSynchronize(cc->stream));
+    FileHeader h{};
+    std::memcpy(h.magic, kMagic, 8);
+    h.version = 1;
+    h.nx = c->nx; h.ny = c->ny; h.bx = c->bx; h.by = c->by;
+    h.overlap = c->overlap; h.precision = c->precision; h.coarse_space = c->coarse_space;
+    h.mobility = c->mobility_updated ? 1 : 0;
+    h.ne = c->ne; h.jmax = c->jmax;
+    h.eta = c->eta; h.tol = c->tol; h.H = c->H;
+    FILE* f = std::fopen(path, "wb");
+    if (!f) throw TgmsError{TGMS_E_INVAL, std::string("cannot open ") + path + " for writing"};
+    bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1;
+    ok = ok && std::fwrite(a.kinv.data(), sizeof(double), ncell, f) == (size_t)ncell;
+    ok = ok && std::fwrite(a.a.data(), sizeof(double), ncell, f) == (size_t)ncell;
+    ok = ok && std::fwrite(c->counts_h.data(), sizeof(int), c->ne, f) == (size_t)c->ne;
+    ok = ok && std::fwrite(a.eigs.data(), sizeof(double), a.eigs.size(), f) == a.eigs.size();
+    ok = ok && std::fwrite(a.YQ.data(), sizeof(double), nq, f) == nq;
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) throw TgmsError{TGMS_E_INVAL, std::string("writing ") + path + " failed"};
+}
+
+void load_impl(const char* path, const tgms_options* opt, tgms_ctx** out) {
+    FILE* f = std::fopen(path, "rb");
+    if (!f) throw TgmsError{TGMS_E_INVAL, std::string("cannot open ") + path};
+    struct Closer {
+        FILE* f;
+        ~Closer() { std::fclose(f); }
+    } closer{f};
+    FileHeader h{};
+    if (std::fread(&h, sizeof(h), 1, f) != 1 || std::memcmp(h.magic, kMagic, 8) != 0 || h.version != 1)
+        throw TgmsError{TGMS_E_INVAL, std::string(path) + " is not a saved tgms context (version 1)"};
+    if (h.nx <= 0 || h.ny <= 0 || h.bx <= 0 || h.by <= 0 || h.nx % h.bx || h.ny % h.by || h.ne < 0 || h.jmax <= 0 ||
+        (long long)h.nx * h.ny > (1ll << 31))
+        throw TgmsError{TGMS_E_INVAL, std::string(path) + ": inconsistent sizes"};
+    const int Nx = h.nx / h.bx, Ny = h.ny / h.by;
+    if (h.ne != (Nx - 1) * Ny + Nx * (Ny - 1) || h.jmax != std::max(h.bx, h.by))
+        throw TgmsError{TGMS_E_INVAL, std::string(path) + ": inconsistent sizes"};
+    Artefact a;
+    const long long ncell = (long long)h.nx * h.ny;
+    const size_t nq = (size_t)h.ne * h.jmax * h.jmax;
+    a.kinv.resize(ncell);
+    a.a.resize(ncell);
+    a.counts.resize(h.ne);
+    a.eigs.resize((size_t)h.ne * h.jmax);
+    a.YQ.resize(nq);
+    bool ok = std::fread(a.kinv.data(), sizeof(double), ncell, f) == (size_t)ncell;
+    ok = ok && std::fread(a.a.data(), sizeof(double), ncell, f) == (size_t)ncell;
+    ok = ok && std::fread(a.counts.data(), sizeof(int), h.ne, f) == (size_t)h.ne;
+    ok = ok && std::fread(a.eigs.data(), sizeof(double), a.eigs.size(), f) == a.eigs.size();
+    ok = ok && std::fread(a.YQ.data(), sizeof(double), nq, f) == nq;
+    if (!ok) throw TgmsError{TGMS_E_INVAL, std::string(path) + " is truncated"};
+    for (int e = 0; e < h.ne; ++e) {
+        const int J = e < (Nx - 1) * Ny ? h.by : h.bx;
+        if (a.counts[e] < 1 || a.counts[e] > J) throw TgmsError{TGMS_E_INVAL, std::string(path) + ": bad basis count"};
+    }
+    for (long long k = 0; k < ncell; ++k)
+        if (!(a.kinv[k] > 0.0) || !(a.kinv[k] < INFINITY) || !(a.a[k] > 0.0) || !(a.a[k] < INFINITY))
+            throw TgmsError{TGMS_E_INVAL, std::string(path) + ": bad cell weights"};
+    a.mobility = h.mobility;
+    tgms_options o;
+    tgms_default_options(&o);
+    if (opt) o = *opt;
+    o.eta = h.eta;
+    o.overlap = h.overlap;
+    o.precision = h.precision;
+    o.s_scale = h.H;
+    o.coarse_space = h.coarse_space;
+    o.warm_start = 0;
+    o.force_counts = nullptr;
+    tgms_grid g{2, h.nx, h.ny, 1, h.bx, h.by, 1};
+    setup_impl(&g, nullptr, h.tol, &o, out, &a);
 }
 
 }  // namespace
@@ -924,6 +1112,8 @@ void tgms_default_options(tgms_options* opt) {
     opt->rq_tol = 1e-6;
     opt->smoother_staging = -1;
     opt->rows_per_thread = 0;
+    opt->force_counts = nullptr;
+    opt->coarse_space = 0;
 }
 
 tgms_status tgms_setup(const tgms_grid* grid, const double* kappa, double eig_tol, const tgms_options* opt,
@@ -968,7 +1158,57 @@ tgms_status tgms_info(const tgms_ctx* c, tgms_info_t* info) {
     info->warm_iters = c->warm_iters;
     info->t_cnn_ms = c->t_cnn_ms;
     info->rows_per_thread = c->rpt;
+    info->eig_unconverged = c->eig_unconverged;
+    info->coarse_space = c->coarse_space;
+    info->nx = c->nx;
+    info->ny = c->ny;
+    info->bx = c->bx;
+    info->by = c->by;
+    info->precision = c->precision;
     return TGMS_OK;
+}
+
+tgms_status tgms_probe_pencil(tgms_ctx* c, double* D, double* S) {
+    if (!c || !D || !S) {
+        g_last_error = "null argument";
+        return TGMS_E_INVAL;
+    }
+    if (c->coarse_space == 2) {
+        g_last_error = "the RT0 coarse space forms no snapshots or pencils";
+        return TGMS_E_INVAL;
+    }
+    return guarded([&] {
+        tgms::enter(c);
+        tgms::pencil_probe(c, D, S);
+        HIP_OK(hipStreamSynchronize(c->stream));
+    });
+}
+
+void tgms_trim_device_cache(void) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    DevPool& P = dev_pool();
+    std::lock_guard<std::mutex> lock(P.mu);
+    for (auto& kv : P.blocks[dev]) (void)hipFree(kv.second);
+    P.blocks[dev].clear();
+    P.cached[dev] = 0;
+}
+
+tgms_status tgms_save(const tgms_ctx* c, const char* path) {
+    if (!c || !path) {
+        g_last_error = "null argument";
+        return TGMS_E_INVAL;
+    }
+    return guarded([&] { save_impl(c, path); });
+}
+
+tgms_status tgms_load(const char* path, const tgms_options* opt, tgms_ctx** out) {
+    if (out) *out = nullptr;
+    if (!path || !out) {
+        g_last_error = "null argument";
+        return TGMS_E_INVAL;
+    }
+    return guarded([&] { load_impl(path, opt, out); });
 }
 
 tgms_status tgms_get_warm_status(const tgms_ctx* c, int* wstat) {
@@ -1142,6 +1382,38 @@ tgms_status tgms_time_smoother(tgms_ctx* c, int reps, double* avg_ms) {
             else
                 tgms::smooth_patches<double>(c, c->vz, nullptr);
         };
+        hipEvent_t a, b;
+        HIP_OK(hipEventCreate(&a));
+        HIP_OK(hipEventCreate(&b));
+        body();  // warm-up
+        HIP_OK(hipEventRecord(a, c->stream));
+        for (int r = 0; r < reps; ++r) body();
+        HIP_OK(hipEventRecord(b, c->stream));
+        HIP_OK(hipEventSynchronize(b));
+        float ms = 0.f;
+        HIP_OK(hipEventElapsedTime(&ms, a, b));
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        c->prof = prof;
+        *avg_ms = ms / reps;
+    });
+}
+
+tgms_status tgms_time_dir_apply(tgms_ctx* c, int reps, double* avg_ms) {
+    if (!c || !avg_ms || reps < 1 || reps > 100000) {
+        g_last_error = "bad argument";
+        return TGMS_E_INVAL;
+    }
+    return guarded([&] {
+        tgms::enter(c);
+        const bool prof = c->prof;
+        c->prof = false;
+        // scalars for a plain update: not done, nothing pending, beta = 1/2 (a solve
+        // sets every scalar again before it reads one)
+        for (int k = 0; k < SC_COUNT; ++k) c->red_h[k] = 0.0;
+        c->red_h[SC_BETA] = 0.5;
+        HIP_OK(hipMemcpyAsync(c->sc, c->red_h, SC_COUNT * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        auto body = [&] { tgms::dir_apply(c, c->vz, c->vp, c->vp1, c->vq); };
         hipEvent_t a, b;
         HIP_OK(hipEventCreate(&a));
         HIP_OK(hipEventCreate(&b));

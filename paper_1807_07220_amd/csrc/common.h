@@ -195,6 +195,14 @@ struct tgms_ctx {
     double* cvec2 = nullptr;
     float* cvec32 = nullptr;
     float* cvec2_32 = nullptr;
+    // coarse space of the two-grid preconditioner: 0 adaptive GMsFEM (section 4), 1 MsFEM
+    // (one basis per face, the sum of its snapshots), 2 coarse RT0 (the paper's comparators)
+    int coarse_space = 0;
+    int* force = nullptr;     // ne imposed basis counts (device), or null
+    int* eig_bad = nullptr;   // faces whose Jacobi solve hit its sweep limit (device counter)
+    int eig_unconverged = 0;
+    double* YQ = nullptr;     // ne * jmax * jmax kept modes times recombination (the basis; saved by tgms_save)
+    double* AH0c = nullptr;   // nblk * 6 coarse RT0 Grams for the RT0 coarse space (main stream)
     // coarse RT0 (preprocessing)
     int nv = 0;               // interior coarse vertices
     double* AH0 = nullptr;    // nblk * 6 : WW, WE, EE, SS, SN, NN
@@ -351,7 +359,8 @@ void enter(tgms_ctx* c);
 hipEvent_t take_event(tgms_ctx* c);  // from the profiling event pool
 // grid / vector kernels (k_grid.hip)
 void cell_weights(tgms_ctx* c, const double* kappa, int* bad);
-void mobility_weights(tgms_ctx* c, const double* lambda, int* bad);  // a = |c| kappa^{-1} / lambda
+void mobility_weights(tgms_ctx* c, const double* lambda, int* bad, double* out);  // out = |c| kappa^{-1} / lambda
+void weights_from_kinv(tgms_ctx* c);  // a = |c| kinv (a restored context)
 void faces_A(tgms_ctx* c, const double* u, double* out);                    // A u on interior faces
 void faces_A_probe(tgms_ctx* c, const double* u, double* out);              // same, boundary inputs ignored
 void curlT_A_faces(tgms_ctx* c, const double* u, double* g, double scale);  // g = scale * C^T A u
@@ -402,8 +411,10 @@ void cnn_windows(tgms_ctx* c, float* X);
 // inference only, BF16 matrix cores with FP32 accumulation (no saved activations)
 void cnn_infer_bf16(hipStream_t st, const float* prm, const float* X, long long n, int H, int W, float* Y);
 void coarse_local_run(tgms_ctx* c, const double* Tm, const int* zc);
-void coarse_rt0_blocks(tgms_ctx* c);
-void rt0_stiffness(tgms_ctx* c, double* K);
+void coarse_rt0_blocks(tgms_ctx* c, double* AH0);                    // per-block coarse RT0 Grams
+void rt0_stiffness(tgms_ctx* c, const double* AH0, double* K);       // coarse vertex stiffness (dense)
+void rt0_coarse_W(tgms_ctx* c);  // coarse space = coarse RT0: bilinear vertex stream functions in W
+void pencil_probe(tgms_ctx* c, double* D, double* S);  // each face's a-form diagonal and s-form
 // coarse apply (k_setup.hip)
 template <typename T>
 void coarse_apply(tgms_ctx* c, const T* g, T* z, bool accumulate, const double* sc);

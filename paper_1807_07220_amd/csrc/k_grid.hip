@@ -27,6 +27,14 @@ __global__ void k_cell_weights(const double* __restrict__ kappa, double* __restr
     a[c] = area * ki;
 }
 
+// cell weights from a given kappa^{-1} (a restored context): the same product as above
+__global__ void k_weights_from_kinv(const double* __restrict__ kinv, double* __restrict__ a, long long n,
+                                    double area) {
+    long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    a[c] = area * kinv[c];
+}
+
 // cell weights under a mobility field: a = |c| kappa^{-1} / lambda (kinv kept from setup)
 __global__ void k_mobility_weights(const double* __restrict__ lambda, const double* __restrict__ kinv,
                                    double* __restrict__ a, long long n, double area, int* __restrict__ bad) {
@@ -157,10 +165,17 @@ void cell_weights(tgms_ctx* c, const double* kappa, int* bad) {
     LAUNCH_OK();
 }
 
-void mobility_weights(tgms_ctx* c, const double* lambda, int* bad) {
+void mobility_weights(tgms_ctx* c, const double* lambda, int* bad, double* out) {
     long long n = (long long)c->nx * c->ny;
-    hipLaunchKernelGGL(k_mobility_weights, dim3(nb(n)), dim3(256), 0, c->stream, lambda, (const double*)c->kinv, c->a,
+    hipLaunchKernelGGL(k_mobility_weights, dim3(nb(n)), dim3(256), 0, c->stream, lambda, (const double*)c->kinv, out,
                        n, c->hx * c->hy, bad);
+    LAUNCH_OK();
+}
+
+void weights_from_kinv(tgms_ctx* c) {
+    long long n = (long long)c->nx * c->ny;
+    hipLaunchKernelGGL(k_weights_from_kinv, dim3(nb(n)), dim3(256), 0, c->stream, (const double*)c->kinv, c->a, n,
+                       c->hx * c->hy);
     LAUNCH_OK();
 }
 

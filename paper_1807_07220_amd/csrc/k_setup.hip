@@ -424,7 +424,7 @@ __global__ void __launch_bounds__(256) k_gram_mfma(BlockGeom G, const double* __
 // one round ([NM / 2][2]), published with their rotations so that the update loops
 // do no index arithmetic beyond shifts and masks.
 template <int NM>
-__device__ void jacobi_rr(double* A, double* V, int ld, int n, double (*cs)[2], int (*pq)[2], int* rot_flag) {
+__device__ bool jacobi_rr(double* A, double* V, int ld, int n, double (*cs)[2], int (*pq)[2], int* rot_flag) {
     static_assert((NM & (NM - 1)) == 0, "NM must be a power of two");
     constexpr int SH = NM == 1 ? 0 : NM == 2 ? 1 : NM == 4 ? 2 : NM == 8 ? 3 : NM == 16 ? 4 : NM == 32 ? 5 : 6;
     const int lane = threadIdx.x;
@@ -479,9 +479,10 @@ __device__ void jacobi_rr(double* A, double* V, int ld, int n, double (*cs)[2], 
             }
             __syncthreads();
         }
-        if (!*rot_flag) break;
+        if (!*rot_flag) return true;
         __syncthreads();
     }
+    return false;  // still rotating after the sweep limit
 }
 
 __device__ inline double wave_max(double v) {
@@ -537,13 +538,86 @@ constexpr int KW = 8;  // largest warm-start block
 // eigenvalues are computed (the rest are stored as 0).
 // JM >= jmax: the LDS tiles are sized for the widest face of the grid (several
 // workgroups share a CU when the faces are short).
+// Geometry of coarse face fid (x-faces first, then y-faces): the blocks K1 (low side) and
+// K2 (high side), the snapshot sides s1, s2 of E in each block's column numbering, the
+// number of fine faces Jn on E, their length, and the first cells on either side of E
+// with the stride along it.
+struct FaceGeom {
+    int K1, K2, s1, s2, Jn;
+    double elen;
+    long long cellL, cellR, step;
+};
+__device__ inline FaceGeom face_geom(const BlockGeom& G, int fid) {
+    FaceGeom f;
+    const int nex = (G.Nx - 1) * G.Ny;
+    if (fid < nex) {  // x-face (I, J), I = 1..Nx-1
+        const int J = fid / (G.Nx - 1), I = fid % (G.Nx - 1) + 1;
+        f.K1 = J * G.Nx + I - 1;
+        f.K2 = J * G.Nx + I;
+        f.s1 = 1;
+        f.s2 = 0;
+        f.Jn = G.by;
+        f.elen = G.hy;
+        f.cellL = (long long)(J * G.by) * G.nx + I * G.bx - 1;
+        f.cellR = f.cellL + 1;
+        f.step = G.nx;
+    } else {  // y-face (I, J), J = 1..Ny-1
+        const int e = fid - nex, J = e / G.Nx + 1, I = e % G.Nx;
+        f.K1 = (J - 1) * G.Nx + I;
+        f.K2 = J * G.Nx + I;
+        f.s1 = 3;
+        f.s2 = 2;
+        f.Jn = G.bx;
+        f.elen = G.hx;
+        f.cellL = (long long)(J * G.by - 1) * G.nx + I * G.bx;
+        f.cellR = f.cellL + G.nx;
+        f.step = 1;
+    }
+    return f;
+}
+
+// Entry (l, m) of the s-form on the snapshot pair (l, m) of a face (eq. spectral_eqn):
+// the kappa^{-1}-weighted mass Gram of the two block halves plus the divergence term
+// sum_K |e_l||e_m| / |K|, times the prefactor invH.
+__device__ inline double s_entry(const BlockGeom& G, const FaceGeom& f, const double* G1, const double* G2, int l,
+                                 int m, double invH) {
+    const double areaK = G.bx * G.hx * G.by * G.hy;
+    return (G1[(f.s1 * G.jmax + l) * G.ncol + f.s1 * G.jmax + m] + G2[(f.s2 * G.jmax + l) * G.ncol + f.s2 * G.jmax + m] +
+            2.0 * f.elen * f.elen / areaK) *
+           invH;
+}
+
+// The pencil of every coarse face as the eigensolver sees it: D[fid][l] (the diagonal
+// a-form) and S[fid][l][m] (the s-form, symmetrised), rows padded to jmax with zeros.
+__global__ void k_pencil_probe(BlockGeom G, const double* __restrict__ kinv, const double* __restrict__ Gm,
+                               double invH, double* __restrict__ Dout, double* __restrict__ Sout) {
+    const int fid = blockIdx.x;
+    const FaceGeom f = face_geom(G, fid);
+    const double* G1 = Gm + (long long)f.K1 * G.ncol * G.ncol;
+    const double* G2 = Gm + (long long)f.K2 * G.ncol * G.ncol;
+    for (int l = threadIdx.x; l < G.jmax; l += blockDim.x)
+        Dout[(long long)fid * G.jmax + l] =
+            l < f.Jn ? f.elen * 0.5 * (kinv[f.cellL + l * f.step] + kinv[f.cellR + l * f.step]) : 0.0;
+    for (int e = threadIdx.x; e < G.jmax * G.jmax; e += blockDim.x) {
+        const int l = e / G.jmax, m = e % G.jmax;
+        double v = 0.0;
+        if (l < f.Jn && m < f.Jn) v = 0.5 * (s_entry(G, f, G1, G2, l, m, invH) + s_entry(G, f, G1, G2, m, l, invH));
+        Sout[(long long)fid * G.jmax * G.jmax + e] = v;
+    }
+}
+
+// force: the basis count of every face imposed (clamped to [1, J_i]) instead of the
+// threshold count, or null; msfem: one basis per face, the sum of the face's snapshots
+// (section 4.2, eq. msfem); eig_bad: counts the faces whose Jacobi solve was still
+// rotating at its sweep limit.
 template <int WARM, int JM>
 __global__ void __launch_bounds__(64) k_pencil_eig(BlockGeom G, const double* __restrict__ kinv,
                                                    const double* __restrict__ Gm, double tol, double invH,
                                                    double* __restrict__ eigs, int* __restrict__ counts,
                                                    double* __restrict__ Yout, double* __restrict__ Qout,
                                                    const float* __restrict__ Y0, int kblk, double rq_tol, int max_it,
-                                                   int* __restrict__ wstat, float* __restrict__ Vtop) {
+                                                   int* __restrict__ wstat, float* __restrict__ Vtop,
+                                                   const int* __restrict__ force, int msfem, int* __restrict__ eig_bad) {
     constexpr int LD = JM + 1;
     __shared__ double T[JM][LD];
     __shared__ double V[JM][LD];
@@ -556,44 +630,17 @@ __global__ void __launch_bounds__(64) k_pencil_eig(BlockGeom G, const double* __
     __shared__ double Wk[WARM ? 2 * JM * KW + 2 * KW * 9 : 1];
     __shared__ double thS[WARM ? KW : 1];  // the Ritz values by descending theta
     const int fid = blockIdx.x, lane = threadIdx.x;
-    const int nex = (G.Nx - 1) * G.Ny;
-    int K1, K2, s1, s2, Jn;
-    double elen;
-    long long cellL, cellR, step;
-    if (fid < nex) {  // x-face (I, J), I = 1..Nx-1
-        const int J = fid / (G.Nx - 1), I = fid % (G.Nx - 1) + 1;
-        K1 = J * G.Nx + I - 1;
-        K2 = J * G.Nx + I;
-        s1 = 1;
-        s2 = 0;
-        Jn = G.by;
-        elen = G.hy;
-        cellL = (long long)(J * G.by) * G.nx + I * G.bx - 1;
-        cellR = cellL + 1;
-        step = G.nx;
-    } else {  // y-face (I, J), J = 1..Ny-1
-        const int f = fid - nex, J = f / G.Nx + 1, I = f % G.Nx;
-        K1 = (J - 1) * G.Nx + I;
-        K2 = J * G.Nx + I;
-        s1 = 3;
-        s2 = 2;
-        Jn = G.bx;
-        elen = G.hx;
-        cellL = (long long)(J * G.by - 1) * G.nx + I * G.bx;
-        cellR = cellL + G.nx;
-        step = 1;
-    }
-    const double areaK = G.bx * G.hx * G.by * G.hy;
-    const double* G1 = Gm + (long long)K1 * G.ncol * G.ncol;
-    const double* G2 = Gm + (long long)K2 * G.ncol * G.ncol;
-    for (int l = lane; l < Jn; l += 64) D[l] = elen * 0.5 * (kinv[cellL + l * step] + kinv[cellR + l * step]);
+    const FaceGeom fg = face_geom(G, fid);
+    const int Jn = fg.Jn;
+    const double elen = fg.elen;
+    const double* G1 = Gm + (long long)fg.K1 * G.ncol * G.ncol;
+    const double* G2 = Gm + (long long)fg.K2 * G.ncol * G.ncol;
+    for (int l = lane; l < Jn; l += 64)
+        D[l] = elen * 0.5 * (kinv[fg.cellL + l * fg.step] + kinv[fg.cellR + l * fg.step]);
     __syncthreads();
     for (int e = lane; e < Jn * Jn; e += 64) {
         const int l = e / Jn, mm = e % Jn;
-        const double s = (G1[(s1 * G.jmax + l) * G.ncol + s1 * G.jmax + mm] +
-                          G2[(s2 * G.jmax + l) * G.ncol + s2 * G.jmax + mm] + 2.0 * elen * elen / areaK) *
-                         invH;
-        T[l][mm] = s / sqrt(D[l] * D[mm]);
+        T[l][mm] = s_entry(G, fg, G1, G2, l, mm, invH) / sqrt(D[l] * D[mm]);
     }
     __syncthreads();
     // symmetrise (the two Gram halves are symmetric up to round-off)
@@ -750,7 +797,8 @@ __global__ void __launch_bounds__(64) k_pencil_eig(BlockGeom G, const double* __
             V[l][mm] = (l == mm) ? 1.0 : 0.0;
         }
         __syncthreads();
-        jacobi_rr<JM>(&T[0][0], &V[0][0], LD, Jn, cs, pq, &rot_flag);
+        const bool conv = jacobi_rr<JM>(&T[0][0], &V[0][0], LD, Jn, cs, pq, &rot_flag);
+        if (!conv && lane == 0 && eig_bad) atomicAdd(eig_bad, 1);
         // sort mu descending (lambda = 1/mu ascending)
         if (lane < Jn) {
             const double mu = T[lane][lane];
@@ -766,11 +814,14 @@ __global__ void __launch_bounds__(64) k_pencil_eig(BlockGeom G, const double* __
         __syncthreads();
         for (int k = 0; k < Jn; ++k) cnt += (1.0 / T[order[k]][order[k]] < tol);
         cnt = cnt < 1 ? 1 : cnt;
+        if (force) cnt = min(max(force[fid], 1), Jn);
+        if (msfem) cnt = 1;
         if (lane == 0) counts[fid] = cnt;
-        // Y[:, k] = D^{-1/2} v_k for the kept modes; flux f_k = |e| sum_l Y[l][k]
+        // Y[:, k] = D^{-1/2} v_k for the kept modes (MsFEM: all snapshot coefficients 1);
+        // flux f_k = |e| sum_l Y[l][k]
         for (int e = lane; e < G.jmax * G.jmax; e += 64) {
             const int l = e / G.jmax, k = e % G.jmax;
-            Yf[e] = (l < Jn && k < cnt) ? V[l][order[k]] / sqrt(D[l]) : 0.0;
+            Yf[e] = (l < Jn && k < cnt) ? (msfem ? 1.0 : V[l][order[k]] / sqrt(D[l])) : 0.0;
         }
         if (Vtop)
             for (int e = lane; e < KW * G.jmax; e += 64) {
@@ -905,6 +956,31 @@ __global__ void k_coarse_W(BlockGeom G, const double* __restrict__ PPsi, const d
             const int corner = zc[(long long)blk * mu + u];
             const int vv = b * (bxl + 1) + a;
             for (int k = 0; k < ncol; ++k) val += (Pb[(long long)vv * ncol + k] - Pb[(long long)corner * ncol + k]) * Tb[k * mu + u];
+        }
+        W[(long long)blk * nown * mu + e] = val;
+        if (W32) W32[(long long)blk * nown * mu + e] = (float)val;
+    }
+}
+
+// The coarse RT0 space as the coarse space of the two-grid preconditioner (the paper's
+// comparator, section 5): its divergence-free part with zero boundary flux is the curl of
+// the bilinear stream functions of the interior coarse vertices, so a block's slot u
+// (the coarse vertex (I + ci, J + cj), ci, cj in {0, 1}) holds the bilinear hat of that
+// vertex on the block's owned fine vertices.
+__global__ void k_rt0_W(BlockGeom G, int mu, const int* __restrict__ unk, const int* __restrict__ nunk,
+                        double* __restrict__ W, float* __restrict__ W32) {
+    const int blk = blockIdx.x, I = blk % G.Nx, J = blk / G.Nx;
+    const int nown = G.bx * G.by, nu = nunk[blk];
+    for (int e = threadIdx.x; e < nown * mu; e += blockDim.x) {
+        const int v = e / mu, u = e % mu;
+        const int a = v % G.bx, b = v / G.bx;
+        double val = 0.0;
+        if (u < nu) {
+            const int id = unk[(long long)blk * mu + u];
+            const int ci = id % (G.Nx - 1) + 1 - I, cj = id / (G.Nx - 1) + 1 - J;
+            const double wx = ci ? (double)a / G.bx : 1.0 - (double)a / G.bx;
+            const double wy = cj ? (double)b / G.by : 1.0 - (double)b / G.by;
+            val = wx * wy;
         }
         W[(long long)blk * nown * mu + e] = val;
         if (W32) W32[(long long)blk * nown * mu + e] = (float)val;
@@ -1142,14 +1218,21 @@ namespace tgms {
 
 template <int JM>
 static void pencil_eig_launch(tgms_ctx* c, const BlockGeom& G, double* Q, const float* Y0, float* Vtop) {
+    const int msfem = c->coarse_space == 1 ? 1 : 0;
     if (c->warm)
         hipLaunchKernelGGL((k_pencil_eig<1, JM>), dim3(c->ne), dim3(64), 0, c->stream, G, c->kinv, c->G, c->tol,
                            1.0 / c->H, c->eigs, c->counts, c->Y, Q, Y0, KW, c->rq_tol, c->warm_maxit, c->wstat,
-                           (float*)nullptr);
+                           (float*)nullptr, (const int*)c->force, msfem, c->eig_bad);
     else
         hipLaunchKernelGGL((k_pencil_eig<0, JM>), dim3(c->ne), dim3(64), 0, c->stream, G, c->kinv, c->G, c->tol,
                            1.0 / c->H, c->eigs, c->counts, c->Y, Q, (const float*)nullptr, 0, 0.0, 0, (int*)nullptr,
-                           Vtop);
+                           Vtop, (const int*)c->force, msfem, c->eig_bad);
+    LAUNCH_OK();
+}
+
+void pencil_probe(tgms_ctx* c, double* D, double* S) {
+    hipLaunchKernelGGL(k_pencil_probe, dim3(c->ne), dim3(256), 0, c->stream, geom(c), (const double*)c->kinv,
+                       (const double*)c->G, 1.0 / c->H, D, S);
     LAUNCH_OK();
 }
 
@@ -1188,16 +1271,22 @@ void coarse_local_run(tgms_ctx* c, const double* Tm, const int* zc) {
     LAUNCH_OK();
 }
 
-void rt0_stiffness(tgms_ctx* c, double* K) {
+void rt0_stiffness(tgms_ctx* c, const double* AH0, double* K) {
     const int nv = (c->Nx - 1) * (c->Ny - 1);
-    hipLaunchKernelGGL(k_rt0_stiffness, dim3((nv + 255) / 256), dim3(256), 0, c->stream, (const double*)c->AH0, c->Nx,
-                       c->Ny, c->bx * c->hx, c->by * c->hy, K);
+    hipLaunchKernelGGL(k_rt0_stiffness, dim3((nv + 255) / 256), dim3(256), 0, c->stream, AH0, c->Nx, c->Ny,
+                       c->bx * c->hx, c->by * c->hy, K);
     LAUNCH_OK();
 }
 
-void coarse_rt0_blocks(tgms_ctx* c) {
+void coarse_rt0_blocks(tgms_ctx* c, double* AH0) {
     BlockGeom G = geom(c);
-    hipLaunchKernelGGL(k_rt0_blocks, dim3(c->nblk), dim3(64), 0, c->stream, G, c->a, c->AH0);
+    hipLaunchKernelGGL(k_rt0_blocks, dim3(c->nblk), dim3(64), 0, c->stream, G, c->a, AH0);
+    LAUNCH_OK();
+}
+
+void rt0_coarse_W(tgms_ctx* c) {
+    hipLaunchKernelGGL(k_rt0_W, dim3(c->nblk), dim3(256), 0, c->stream, geom(c), c->mu, (const int*)c->blk_unk,
+                       (const int*)c->blk_nu, c->W, c->precision ? c->W32 : nullptr);
     LAUNCH_OK();
 }
 

@@ -27,7 +27,8 @@ from gpu_util import dev, eig_bound, host, oracle_for, register, rel  # noqa: E4
 # At contrast <= 1e3 that is below 1e-11; at contrast 1e6 the coarse and
 # block problems reach cond ~ 1e6 after equilibration, hence 1e-8 there.
 # The final velocity and pressure are held to 1e-10 in every case.
-PROBE_TOL = {"cfg32": 1e-11, "rect36x24": 1e-11, "chan64": 1e-8, "odd35x21": 1e-11}
+PROBE_TOL = {"cfg32": 1e-11, "rect36x24": 1e-11, "chan64": 1e-8, "odd35x21": 1e-11, "b16_128": 2e-9,
+             "b16_96x64": 2e-9}
 
 CASES = {
     # name: (nx, ny, bx, by, kappa generator, tol)
@@ -36,6 +37,12 @@ CASES = {
     "chan64": (64, 64, 8, 8, lambda: fields.field_channelized(64, 64, 11, contrast=1e6), 2.0),
     # block and patch widths without a fixed-width kernel instantiation (generic paths)
     "odd35x21": (35, 21, 7, 7, lambda: np.exp(1.5 * np.random.default_rng(11).standard_normal((21, 35))), 0.5),
+    # the 16 x 16-block kernels of the 256^2 and 1024^2 workloads (interior patches 20 x 20,
+    # clipped 18 x 20 and 18 x 18) at contrast 1e6 and their tolerance 0.2: square and
+    # non-square grids of blocks
+    "b16_128": (128, 128, 16, 16, lambda: fields.field_channelized(128, 128, 19, contrast=1e6), 0.2),
+    # (the paper's tolerance 10 here: Cond 9.6 instead of 2e4 at 0.2)
+    "b16_96x64": (96, 64, 16, 16, lambda: fields.field_channelized(96, 64, 13, contrast=1e6), 10.0),
 }
 
 
@@ -80,6 +87,7 @@ def test_preprocessing(name):
     F = fields.random_source(o.g.nx, o.g.ny, 5).ravel()
     vb = host(s.preprocess(dev(F)))
     vo, _, _ = o.preprocess(F)
+    print(f"preprocess {name}: rel {rel(vb, vo):.2e}")
     assert rel(vb, vo) < PROBE_TOL[name]
     assert np.abs(o.B @ vb - F).max() < 1e-12 * np.abs(F).max()
 
@@ -92,19 +100,56 @@ def test_preconditioner(name, which):
     r = rng.standard_normal(o.g.nf) * o.mask
     z = host(s.apply_precond(which, dev(r)))
     ref = {"smoother": o.smooth, "coarse": o.coarse, "twogrid": o.twogrid}[which](r)
+    print(f"{which} {name}: rel {rel(z, ref):.2e}")
     assert rel(z, ref) < PROBE_TOL[name]
+
+
+@pytest.mark.parametrize("name", ["chan64", "b16_128", "b16_96x64"])
+@pytest.mark.parametrize("which", ["smoother", "coarse", "twogrid"])
+def test_preconditioner_fp32(name, which):
+    """The FP32 preconditioner (factors, coarse basis and inverse in FP32; the residuals
+    between its steps formed in FP64) against the FP64 oracle."""
+    s, o, _ = case(name, precision="mixed")
+    rng = np.random.default_rng(2)
+    r = rng.standard_normal(o.g.nf) * o.mask
+    z = host(s.apply_precond(which, dev(r)))
+    ref = {"smoother": o.smooth, "coarse": o.coarse, "twogrid": o.twogrid}[which](r)
+    print(f"fp32 {which} {name}: rel {rel(z, ref):.2e}")
+    # bar: about 1700 FP32 unit roundoffs (6e-8), 25 times the largest difference
+    # measured here (4e-6, the FP32 coarse solve of the 96 x 64 grid at tolerance 0.2);
+    # the end-to-end FP32 solutions are held to 1e-8 (test_mixed_precision_error and
+    # the full-size tests)
+    assert rel(z, ref) < 1e-4
 
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_solve(name):
-    s, o, _ = case(name)
+    """Setup + solve against the oracle: iterations to rtol 1e-8 within one where the
+    preconditioned system is well conditioned (Cond < 1e4; at larger Cond the count
+    follows rounding-level differences of the preconditioner, see
+    test_iterations_at_high_condition_number), and at rtol 1e-12 on both sides the
+    velocity and pressure within 1e-10 -- or within twice the distance of the oracle's
+    own iterate to the direct solve of the full saddle system where that distance (the
+    attainable FP64 accuracy of the problem) is larger."""
+    from oracle.solver import exact_solve
+    s, o, kappa = case(name)
     F = fields.corner_source(o.g.nx, o.g.ny).ravel()
     res = s.solve(dev(F), rtol=1e-8)
     ro = o.solve(F, rtol=1e-8)
+    print(f"solve {name}: iters gpu {res['iters']} oracle {ro['iters']}, cond {ro['cond']:.3g}")
     assert res["converged"]
-    assert ro["cond"] < 1e4 and abs(res["iters"] - ro["iters"]) <= 1
-    assert rel(host(res["u"]), ro["u"]) < 1e-10 or np.linalg.norm(host(res["u"]) - ro["u"]) <= 1e-10 * np.linalg.norm(ro["u"])
-    assert np.linalg.norm(host(res["p"]) - ro["p"]) <= 1e-10 * np.linalg.norm(ro["p"])
+    if ro["cond"] < 1e4:
+        assert abs(res["iters"] - ro["iters"]) <= 1
+    res = s.solve(dev(F), rtol=1e-12, maxit=2000)
+    ro = o.solve(F, rtol=1e-12, maxit=2000)
+    ue, pe = exact_solve(o.g, kappa, F)
+    floor_u = np.linalg.norm(ro["u"] - ue) / np.linalg.norm(ue)
+    floor_p = np.linalg.norm(ro["p"] - pe) / np.linalg.norm(pe)
+    eu = np.linalg.norm(host(res["u"]) - ro["u"]) / np.linalg.norm(ro["u"])
+    ep = np.linalg.norm(host(res["p"]) - ro["p"]) / np.linalg.norm(ro["p"])
+    print(f"solve {name} at rtol 1e-12: u err {eu:.2e} (oracle vs direct {floor_u:.2e}), "
+          f"p err {ep:.2e} (oracle vs direct {floor_p:.2e})")
+    assert eu <= max(1e-10, 2 * floor_u) and ep <= max(1e-10, 2 * floor_p)
 
 
 def test_solve_with_boundary_data():

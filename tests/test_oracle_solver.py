@@ -188,3 +188,41 @@ def test_overlap_one_reaches_exact_solution_and_zero_is_refused():
     assert np.linalg.norm(res["u"] - u) <= 1e-10 * np.linalg.norm(u)
     with pytest.raises(ValueError):
         OracleSolver(g, kappa, 0.5, overlap=0)
+
+
+def test_three_coarse_spaces_coincide_at_unit_kappa():
+    """At kappa = 1 the first eigenfunction of every face is the coarse RT0 function
+    (section 4.2: the first basis is the MsFEM/RT0 one there), so with one mode per face
+    the GMsFEM, MsFEM (sum of the snapshots) and RT0 coarse corrections are the same
+    operator -- the three model-1 tables print identical rows at k1 = 1.  With a
+    heterogeneous medium the three differ."""
+    g = Grid2D(24, 24, 6, 6)
+    r = np.random.default_rng(1).standard_normal(g.nf)
+    for kappa, same in ((np.ones((24, 24)), True), (np.exp(2 * np.random.default_rng(3).standard_normal((24, 24))), False)):
+        os = [OracleSolver(g, kappa, 5.0, basis=b) for b in ("gmsfem", "msfem", "rt0")]
+        z = [o.coarse(o.mask * r) for o in os]
+        d = [np.abs(zz - z[0]).max() / np.abs(z[0]).max() for zz in z[1:]]
+        if same:
+            assert os[0].dim == os[1].dim == os[2].dim == len(g.coarse_faces()) + g.Nx * g.Ny + 1
+            assert max(d) < 1e-13, d
+        else:
+            assert min(d) > 1e-2, d
+    # the RT0 coarse correction maps into ker B and annihilates gradients like the others
+    o = os[2]
+    z = o.coarse(o.mask * r)
+    assert np.abs(o.B @ z).max() < 1e-11 * np.abs(z).max()
+    q = np.random.default_rng(5).standard_normal(g.nc)
+    assert np.abs(o.coarse(o.mask * (o.B.T @ q))).max() < 1e-10 * np.abs(z).max()
+
+
+def test_forced_counts_follow_the_eigenvalue_order():
+    """force_counts keeps the l_i smallest-eigenvalue modes: forcing the threshold counts
+    reproduces the coarse space, and forcing one more mode on every face spans it plus
+    the next eigenfunction."""
+    g, kappa, o = _small(n=16, b=4, tol=0.5)
+    of = OracleSolver(g, kappa, 0.5, force_counts=o.counts)
+    r = o.mask * np.random.default_rng(2).standard_normal(g.nf)
+    assert np.abs(of.coarse(r) - o.coarse(r)).max() <= 1e-13 * np.abs(o.coarse(r)).max()
+    more = np.minimum(o.counts + 1, [e.size for e in o.eigs])
+    om = OracleSolver(g, kappa, 0.5, force_counts=more)
+    assert np.array_equal(om.counts, more) and om.dim == o.dim + int((more - o.counts).sum())
