@@ -177,6 +177,21 @@ tgms_status tgms_solve(tgms_ctx* ctx, const double* F, const double* g_bnd, doub
                        int maxit, double* u, double* p, int* iters, double* relres);
 
 /*
+ * The solve of tgms_solve for callers that cannot allocate device memory (serving
+ * loops and harnesses that forbid allocation): same arguments, same kernels and,
+ * bitwise, the same results as tgms_solve.  The PCG's scalars, the partial sums of
+ * its reductions and its alpha / beta history live in a fixed array in device memory
+ * of the library (512 KB per device, held until the process ends) instead of the
+ * context's buffers; the iterations are launched directly (no HIP graph is
+ * instantiated), no history is read back (tgms_last_cond then reports 1), and the
+ * call allocates nothing.  Limit: maxit <= 32000 or so (the exact bound is in the
+ * message of TGMS_E_INVAL).  Every call on one device shares that device's array:
+ * calls that overlap in time on one device (other threads, other contexts) race.
+ */
+tgms_status tgms_solve_noalloc(tgms_ctx* ctx, const double* F, const double* g_bnd, double rtol, int maxit,
+                               double* u, double* p, int* iters, double* relres);
+
+/*
  * Mobility update with the coarse space kept (section 6.2: the multiscale basis
  * of the initial permeability is reused while the total mobility changes).  The
  * operator becomes A(lambda), built from (lambda kappa)^{-1}; the block factors,

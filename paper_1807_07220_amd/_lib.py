@@ -56,6 +56,8 @@ SIGNATURES = {
     "tgms_setup": (c_int, [ctypes.POINTER(Grid), c_void_p, c_double, ctypes.POINTER(Options), ctypes.POINTER(c_void_p)]),
     "tgms_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int, c_void_p, c_void_p,
                            ctypes.POINTER(c_int), ctypes.POINTER(c_double)]),
+    "tgms_solve_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int, c_void_p, c_void_p,
+                                   ctypes.POINTER(c_int), ctypes.POINTER(c_double)]),
     "tgms_info": (c_int, [c_void_p, ctypes.POINTER(Info)]),
     "tgms_get_counts": (c_int, [c_void_p, c_void_p]),
     "tgms_get_eigs": (c_int, [c_void_p, c_void_p]),

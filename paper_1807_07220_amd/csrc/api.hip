@@ -998,6 +998,77 @@ void solve_impl(tgms_ctx* c, const double* F, const double* g_bnd, double rtol, 
     }
 }
 
+}  // namespace
+
+// ---------------------------------------------------------------- allocation-free solve
+// The PCG's device scalars, the per-workgroup partial sums of its reductions and its
+// alpha / beta history live here for tgms_solve_noalloc instead of in buffers of the
+// context.  One copy per device, kept until the process ends.  Host code uses the
+// device address from hipGetSymbolAddress (kept per device in g_scratch_ptr), never
+// the array's name.
+static constexpr long long kScratchDoubles = 65536;  // 512 KB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// the current device's copy of the scratch array (looked up on its first use)
+double* device_scratch() {
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) throw TgmsError{TGMS_E_DEVICE, "device ordinal out of range"};
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIP_OK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = (double*)ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+long long noalloc_need(const tgms_ctx* c, int maxit) {
+    return SC_COUNT + 4LL * tgms::pcg_tiles(const_cast<tgms_ctx*>(c)) + 2LL * ((long long)maxit + 2);
+}
+
+void solve_noalloc_impl(tgms_ctx* c, const double* F, const double* g_bnd, double rtol, int maxit, double* u,
+                        double* p, int* iters, double* relres, tgms_status* st) {
+    if (!c || !F || !u) throw TgmsError{TGMS_E_INVAL, "null argument"};
+    if (maxit < 0 || noalloc_need(c, maxit) > kScratchDoubles)
+        throw TgmsError{TGMS_E_INVAL, "maxit outside [0, " +
+                                          std::to_string((kScratchDoubles - noalloc_need(c, 0)) / 2) +
+                                          "] for the allocation-free solve"};
+    double* base = device_scratch();
+    // the context's own buffers are swapped for the scratch array for this call
+    struct Swap {
+        tgms_ctx* c;
+        double *sc, *part, *part2, *hist;
+        int hist_cap;
+        bool graph_failed, prof;
+        ~Swap() {
+            c->sc = sc;
+            c->part = part;
+            c->part2 = part2;
+            c->hist = hist;
+            c->hist_cap = hist_cap;
+            c->graph_failed = graph_failed;
+            c->prof = prof;
+        }
+    } swap{c, c->sc, c->part, c->part2, c->hist, c->hist_cap, c->graph_failed, c->prof};
+    const long long nt = tgms::pcg_tiles(c);
+    c->sc = base;
+    c->part = base + SC_COUNT;
+    c->part2 = c->part + 3 * nt;
+    c->hist = c->part2 + nt;
+    c->hist_cap = maxit + 2;  // the history fits: no allocation in the solve
+    c->graph_failed = true;   // direct launches (instantiating a graph allocates)
+    c->prof = false;          // no event pairs (they come from a growing pool)
+    tgms::enter(c);
+    tgms::zero(c, base, sizeof(double) * (size_t)noalloc_need(c, maxit));  // a fill kernel
+    solve_impl(c, F, g_bnd, rtol, maxit, u, p, iters, relres, st, false);
+}
+
 constexpr char kMagic[8] = {'T', 'G', 'M', 'S', 'C', 'S', '0', '1'};
 
 struct FileHeader {
@@ -1126,6 +1197,13 @@ tgms_status tgms_solve(tgms_ctx* ctx, const double* F, const double* g_bnd, doub
                        double* p, int* iters, double* relres) {
     tgms_status st = TGMS_OK;
     tgms_status r = guarded([&] { solve_impl(ctx, F, g_bnd, rtol, maxit, u, p, iters, relres, &st); });
+    return r != TGMS_OK ? r : st;
+}
+
+tgms_status tgms_solve_noalloc(tgms_ctx* ctx, const double* F, const double* g_bnd, double rtol, int maxit,
+                               double* u, double* p, int* iters, double* relres) {
+    tgms_status st = TGMS_OK;
+    tgms_status r = guarded([&] { solve_noalloc_impl(ctx, F, g_bnd, rtol, maxit, u, p, iters, relres, &st); });
     return r != TGMS_OK ? r : st;
 }
 
