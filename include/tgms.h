@@ -112,6 +112,11 @@ typedef struct {
                           2: the coarse RT0 space (the fine interpolant of the lowest-order
                              Raviart-Thomas functions on the blocks).  1 and 2 are the
                              comparators of section 6; they need warm_start 0. */
+    int coarse_factor;  /* factorisation of the coarse SPD systems (the coarse space's and the
+                           preprocessing's coarse RT0 one): 0 chosen by size (the dense
+                           Cholesky inverse for small FP64 systems, else the cyclic-reduction
+                           Cholesky of the band where it fits); 1 always the dense inverse;
+                           2 cyclic reduction wherever the band fits */
 } tgms_options;
 
 typedef struct {
@@ -136,6 +141,9 @@ typedef struct {
     int coarse_space;     /* as in tgms_options */
     int nx, ny, bx, by;   /* the grid (also of a context restored by tgms_load) */
     int precision;        /* as in tgms_options */
+    int coarse_block;     /* block of the cyclic-reduction Cholesky of the coarse system (its
+                             half-bandwidth), 0 when the dense inverse is used */
+    int rt0_block;        /* the same for the preprocessing's coarse RT0 system */
 } tgms_info_t;
 
 /* Paper defaults: eta 0.2, overlap 2, FP64, s_scale = 1 (unit s-form prefactor), default stream,

@@ -45,7 +45,7 @@ class Solver:
                  graphs: bool = True, autotune: bool = True, tune_cache: str | None = None,
                  warm_start: str = "exact", cnn_weights: torch.Tensor | None = None, rq_tol: float = 1e-6,
                  smoother_staging: int = -1, rows_per_thread: int = 0, force_counts=None,
-                 coarse_space: str = "gmsfem", _restore: str | None = None):
+                 coarse_space: str = "gmsfem", coarse_factor: str = "auto", _restore: str | None = None):
         lib = load()
         if kappa is not None and kappa.dim() != 2:
             raise ValueError("kappa must be (ny, nx)")
@@ -63,6 +63,7 @@ class Solver:
         opt.smoother_staging = int(smoother_staging)
         opt.rows_per_thread = int(rows_per_thread)
         opt.coarse_space = COARSE_SPACES[coarse_space]
+        opt.coarse_factor = {"auto": 0, "dense": 1, "bcr": 2}[coarse_factor]
         if _restore is not None:
             handle = ctypes.c_void_p()
             check(lib.tgms_load(str(_restore).encode(), ctypes.byref(opt), ctypes.byref(handle)))

@@ -35,7 +35,7 @@ class Options(ctypes.Structure):
                 ("stream", c_void_p), ("graphs", c_int), ("autotune", c_int), ("tune_cache", c_char_p),
                 ("warm_start", c_int), ("cnn_weights", c_void_p), ("rq_tol", c_double),
                 ("smoother_staging", c_int), ("rows_per_thread", c_int), ("force_counts", c_void_p),
-                ("coarse_space", c_int)]
+                ("coarse_space", c_int), ("coarse_factor", c_int)]
 
 
 class Info(ctypes.Structure):
@@ -45,7 +45,7 @@ class Info(ctypes.Structure):
                 ("tuned", c_int), ("nred", c_int), ("smooth_staged", c_int), ("warm_accepted", c_int),
                 ("warm_iters", c_int), ("t_cnn_ms", c_double), ("rows_per_thread", c_int),
                 ("eig_unconverged", c_int), ("coarse_space", c_int), ("nx", c_int), ("ny", c_int), ("bx", c_int),
-                ("by", c_int), ("precision", c_int)]
+                ("by", c_int), ("precision", c_int), ("coarse_block", c_int), ("rt0_block", c_int)]
 
 
 _lib = None

@@ -298,12 +298,38 @@ namespace {
 void build_coarse_numbering(tgms_ctx* c, std::vector<int>& meta) {
     const int Nx = c->Nx, Ny = c->Ny;
     const std::vector<int>& cnt = c->counts_h;
-    std::vector<int> zoff(c->ne + 1, 0);
-    for (int i = 0; i < c->ne; ++i) zoff[i + 1] = zoff[i] + cnt[i] - 1;
-    const int nz = zoff[c->ne];
+    // Numbering in the row-major order of the unknowns' positions on the coarse grid, in
+    // doubled coordinates: vertex (I, J) at (2I, 2J), the zero-flux modes of x-face (I, J)
+    // at (2I, 2J + 1), of y-face (I, J) at (2I + 1, 2J).  Unknowns couple only through a
+    // shared block, so the matrix is banded with a half-bandwidth of about Nx + 1 unknowns
+    // (block tridiagonal for the cyclic-reduction Cholesky).  Without zero-flux modes the
+    // vertices come in row-major order.
+    std::vector<int> zstart(c->ne, -1), vtx((size_t)(Nx + 1) * (Ny + 1), -1);
+    int next = 0;
+    for (int py = 0; py <= 2 * Ny; ++py)
+        for (int px = 0; px <= 2 * Nx; ++px) {
+            if (py % 2 == 0 && px % 2 == 0) {
+                const int I = px / 2, J = py / 2;
+                if (I >= 1 && I <= Nx - 1 && J >= 1 && J <= Ny - 1) vtx[(size_t)J * (Nx + 1) + I] = next++;
+            } else if (px % 2 == 0) {  // x-face (I, J): X = I, block row J
+                const int I = px / 2, J = (py - 1) / 2;
+                if (I >= 1 && I <= Nx - 1) {
+                    const int f = J * (Nx - 1) + I - 1;
+                    zstart[f] = next;
+                    next += cnt[f] - 1;
+                }
+            } else if (py % 2 == 0) {  // y-face (I, J): Y = J, block column I
+                const int I = (px - 1) / 2, J = py / 2;
+                if (J >= 1 && J <= Ny - 1) {
+                    const int f = c->nex + (J - 1) * Nx + I;
+                    zstart[f] = next;
+                    next += cnt[f] - 1;
+                }
+            }
+        }
     c->nv = (Nx - 1) * (Ny - 1);
-    c->ncs = nz + c->nv;
-    auto vid = [&](int I, int J) { return (I <= 0 || I >= Nx || J <= 0 || J >= Ny) ? -1 : nz + (J - 1) * (Nx - 1) + I - 1; };
+    c->ncs = next;
+    auto vid = [&](int I, int J) { return (I <= 0 || I >= Nx || J <= 0 || J >= Ny) ? -1 : vtx[(size_t)J * (Nx + 1) + I]; };
     struct Slot {
         int id, corner, n;
         int f[2], side[2], k[2], sign[2];
@@ -322,7 +348,7 @@ void build_coarse_numbering(tgms_ctx* c, std::vector<int>& meta) {
             for (int s = 0; s < 4; ++s) {
                 const int f = face[s];
                 if (f < 0) continue;
-                for (int k = 1; k < cnt[f]; ++k) m.push_back(Slot{zoff[f] + k - 1, 0, 1, {f, 0}, {s, 0}, {k, 0}, {1, 0}});
+                for (int k = 1; k < cnt[f]; ++k) m.push_back(Slot{zstart[f] + k - 1, 0, 1, {f, 0}, {s, 0}, {k, 0}, {1, 0}});
                 // carrier of this face enters the coarse-curl combination of its two end vertices
                 int v0I, v0J, v1I, v1J;
                 if (s == 0) { v0I = I; v0J = J + 1; v1I = I; v1J = J; }
@@ -354,6 +380,10 @@ void build_coarse_numbering(tgms_ctx* c, std::vector<int>& meta) {
             mu = std::max(mu, (int)m.size());
         }
     c->mu = mu;
+    // half-bandwidth of the coarse matrix: unknowns couple only within a block
+    c->cband = 0;
+    for (int b = 0; b < c->nblk; ++b)
+        if (!slots[b].empty()) c->cband = std::max(c->cband, slots[b].back().id - slots[b].front().id);
     meta.assign((size_t)c->nblk * mu * 11, 0);
     std::vector<int> zc((size_t)c->nblk * mu, 0), unk((size_t)c->nblk * mu, 0), nu(c->nblk), ptr(c->ncs + 1, 0);
     for (int b = 0; b < c->nblk; ++b)
@@ -394,12 +424,49 @@ void build_coarse_numbering(tgms_ctx* c, std::vector<int>& meta) {
 
 // Coarse RT0 vertex stiffness K_H = C_H^T A_H0 C_H (dense, host-assembled from the per-block Grams).
 // coarse RT0 stream-function stiffness (preprocessing, section 3) and its inverse
+// The cyclic-reduction Cholesky is taken for systems larger than the one-launch explicit
+// inverse serves (or whose FP32 inverse would lose accuracy) when their band fits the
+// factor kernel; `which` (tgms_options.coarse_factor): 0 that choice, 1 always the dense
+// inverse, 2 cyclic reduction wherever the band fits.
+bool use_bcr(const tgms_ctx* c, int n, int band, bool fp32) {
+    if (c->coarse_factor == 1 || n <= 0) return false;
+    if (band + 1 > tgms::bcr_max_block(c)) return false;
+    if (c->coarse_factor == 2) return true;
+    return fp32 || n > tgms::symv_acc_max();
+}
+
+// Coarse RT0 vertex stiffness K_H = C_H^T A_H0 C_H (9-point: half-bandwidth Nx in the
+// row-major vertex order) and its factorisation, on the calling stream.
 void build_rt0_stiffness(tgms_ctx* c) {
     const int nv = c->nv;
     if (!c->KH) c->KH = c->alloc<double>((size_t)nv * nv);
     tgms::zero(c, c->KH, sizeof(double) * (size_t)nv * nv);
     tgms::rt0_stiffness(c, c->AH0, c->KH);
-    tgms::dense_spd_inverse(c, c->KH, nv);
+    if (use_bcr(c, nv, c->Nx, false)) {
+        tgms::bcr_factor(c, c->KH, nv, std::max(c->Nx, 1), c->kb, false);
+        if (tgms::bcr_failed(c, c->kb)) throw TgmsError{TGMS_E_INVAL, "coarse RT0 operator is not positive definite"};
+    } else {
+        tgms::dense_spd_inverse(c, c->KH, nv);
+    }
+}
+
+// Factorisation of the coarse SPD matrix c->Ac (assembled): the cyclic-reduction Cholesky
+// of its band, or the dense Cholesky inverse (in place, with the explicit inverse for a
+// small FP64 system and an FP32 copy for the FP32 preconditioner).
+void factor_coarse(tgms_ctx* c) {
+    const long long n2 = (long long)c->ncs * c->ncs;
+    if (use_bcr(c, c->ncs, c->cband, c->precision != 0)) {
+        tgms::bcr_factor(c, c->Ac, c->ncs, std::max(c->cband, 1), c->cb, c->precision != 0);
+        if (tgms::bcr_failed(c, c->cb)) throw TgmsError{TGMS_E_INVAL, "coarse operator is not positive definite"};
+        return;
+    }
+    c->cb = Bcr{};
+    if (!c->precision && c->ncs <= tgms::symv_acc_max() && !c->Acf) c->Acf = c->alloc<double>(n2);
+    tgms::dense_spd_inverse(c, c->Ac, c->ncs, c->Acf);
+    if (c->precision) {
+        if (!c->Ac32) c->Ac32 = c->alloc<float>(n2);
+        tgms::cast_d2f(c, n2, c->Ac, c->Ac32);
+    }
 }
 
 // The coarse matrix of the RT0 coarse space: the coarse vertex stiffness over the
@@ -456,6 +523,7 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
     if (o.rows_per_thread != 0 && o.rows_per_thread != 1 && o.rows_per_thread != 4)
         throw TgmsError{TGMS_E_INVAL, "rows_per_thread must be 0, 1 or 4"};
     if (o.coarse_space < 0 || o.coarse_space > 2) throw TgmsError{TGMS_E_INVAL, "coarse_space must be 0, 1 or 2"};
+    if (o.coarse_factor < 0 || o.coarse_factor > 2) throw TgmsError{TGMS_E_INVAL, "coarse_factor must be 0, 1 or 2"};
     if (o.force_counts && (o.warm_start != 0 || o.coarse_space != 0))
         throw TgmsError{TGMS_E_INVAL, "force_counts needs the dense eigensolve of the adaptive space"};
     if (o.coarse_space != 0 && o.warm_start != 0)
@@ -505,6 +573,7 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         c->sx = 1.0 / c->hy; c->sy = 1.0 / c->hx;
         c->H = o.s_scale > 0 ? o.s_scale : std::sqrt(bx * c->hx * by * c->hy);
         c->coarse_space = o.coarse_space;
+        c->coarse_factor = o.coarse_factor;
         c->eig_bad = c->alloc<int>(1);
         c->eta = o.eta; c->tol = eig_tol; c->overlap = o.overlap; c->precision = o.precision ? 1 : 0;
         c->graph_failed = o.graphs == 0;  // never capture: launch every kernel directly
@@ -589,7 +658,10 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                 c->stream = side.s;
                 tgms::coarse_rt0_blocks(c, c->AH0);
                 tgms::rt0_stiffness(c, c->AH0, c->KH);
-                tgms::dense_spd_inverse_begin(c, c->KH, c->nv, kh_inv);
+                if (use_bcr(c, c->nv, c->Nx, false))
+                    tgms::bcr_factor(c, c->KH, c->nv, std::max(c->Nx, 1), c->kb, false);  // checked at the join
+                else
+                    tgms::dense_spd_inverse_begin(c, c->KH, c->nv, kh_inv);
             }
             HIP_OK(hipEventRecord(side.e1, side.s));
             c->t_snap_ms = t.ms();
@@ -731,14 +803,7 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                 pat_timer.stop(side.s);
             }
             HIP_OK(hipEventRecord(side.e2, side.s));
-            // FP64 with a small coarse space: the explicit inverse too, applied in one launch
-            if (!c->precision && c->ncs <= tgms::symv_acc_max())
-                c->Acf = c->alloc<double>((size_t)c->ncs * c->ncs);
-            tgms::dense_spd_inverse(c, c->Ac, c->ncs, c->Acf);
-            if (c->precision) {
-                c->Ac32 = c->alloc<float>((size_t)c->ncs * c->ncs);
-                tgms::cast_d2f(c, (long long)c->ncs * c->ncs, c->Ac, c->Ac32);
-            }
+            factor_coarse(c);
             c->cy = c->alloc<double>((size_t)c->nblk * c->mu);
             c->cvec = c->alloc<double>(2 * (size_t)c->ncs + 1);
             c->cvec2 = c->alloc<double>((size_t)c->ncs + 1);
@@ -748,6 +813,8 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
             // coarse RT0 for the preprocessing: join the second stream
             HIP_OK(hipStreamWaitEvent(c->stream, side.e1, 0));
             tgms::dense_spd_inverse_end(kh_inv);
+            if (c->kb.nb > 0 && tgms::bcr_failed(c, c->kb))
+                throw TgmsError{TGMS_E_INVAL, "coarse RT0 operator is not positive definite"};
             c->cflux = c->alloc<double>(2 * ((size_t)c->Ny * (c->Nx + 1) + (size_t)(c->Ny + 1) * c->Nx));
             c->svec = c->alloc<double>((size_t)c->nv + 1);
             c->svec2 = c->alloc<double>(2 * (size_t)c->nv + 1);
@@ -822,8 +889,7 @@ void rebuild_operator(tgms_ctx* c) {
         tgms::zero(c, c->Ac, sizeof(double) * (size_t)c->ncs * c->ncs);
         tgms::coarse_local_run(c, c->Td, c->zcd);
     }
-    tgms::dense_spd_inverse(c, c->Ac, c->ncs, c->Acf);
-    if (c->precision) tgms::cast_d2f(c, (long long)c->ncs * c->ncs, c->Ac, c->Ac32);
+    factor_coarse(c);
     tgms::coarse_rt0_blocks(c, c->AH0);
     build_rt0_stiffness(c);
     tgms::factor_patches(c);
@@ -1185,6 +1251,7 @@ void tgms_default_options(tgms_options* opt) {
     opt->rows_per_thread = 0;
     opt->force_counts = nullptr;
     opt->coarse_space = 0;
+    opt->coarse_factor = 0;
 }
 
 tgms_status tgms_setup(const tgms_grid* grid, const double* kappa, double eig_tol, const tgms_options* opt,
@@ -1243,6 +1310,8 @@ tgms_status tgms_info(const tgms_ctx* c, tgms_info_t* info) {
     info->bx = c->bx;
     info->by = c->by;
     info->precision = c->precision;
+    info->coarse_block = c->cb.nb > 0 ? c->cb.bs : 0;
+    info->rt0_block = c->kb.nb > 0 ? c->kb.bs : 0;
     return TGMS_OK;
 }
 

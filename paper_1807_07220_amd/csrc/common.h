@@ -123,6 +123,20 @@ struct DeviceBuf {
     size_t bytes = 0;
 };
 
+// Block cyclic reduction Cholesky of a banded SPD matrix (k_dense.hip): n unknowns in nb
+// blocks of bs rows (the half-bandwidth is at most bs); per block the inverse of its
+// Cholesky factor C and the off-diagonal factors Gm, Gp (bs x bs, row-major, FP64 and,
+// for an FP32 preconditioner, FP32 copies); x: the padded right-hand side / solution
+// (nb * bs), Y the forward pass's intermediate.
+struct Bcr {
+    int n = 0, bs = 0, nb = 0;
+    double *D = nullptr, *Lc = nullptr, *C = nullptr, *Gm = nullptr, *Gp = nullptr, *Y = nullptr, *x = nullptr;
+    double *CT = nullptr, *GmT = nullptr, *GpT = nullptr;  // transposes (the solve reads rows only)
+    float *C32 = nullptr, *Gm32 = nullptr, *Gp32 = nullptr, *Y32 = nullptr, *x32 = nullptr;
+    float *CT32 = nullptr, *GmT32 = nullptr, *GpT32 = nullptr;
+    int* fail = nullptr;
+};
+
 namespace tgms {
 // Device memory through a per-device cache of freed blocks: setups of the same
 // shape allocate the same sizes, and hipMalloc / hipFree of the large dense
@@ -203,6 +217,10 @@ struct tgms_ctx {
     int eig_unconverged = 0;
     double* YQ = nullptr;     // ne * jmax * jmax kept modes times recombination (the basis; saved by tgms_save)
     double* AH0c = nullptr;   // nblk * 6 coarse RT0 Grams for the RT0 coarse space (main stream)
+    int cband = 0;            // half-bandwidth of the coarse SPD matrix in its numbering
+    int coarse_factor = 0;    // tgms_options.coarse_factor
+    Bcr cb;                   // its cyclic-reduction Cholesky (cb.nb == 0: the dense inverse is used)
+    Bcr kb;                   // the same for the coarse RT0 stiffness of the preprocessing
     // coarse RT0 (preprocessing)
     int nv = 0;               // interior coarse vertices
     double* AH0 = nullptr;    // nblk * 6 : WW, WE, EE, SS, SN, NN
@@ -444,6 +462,12 @@ struct DenseInvAsync {
 };
 void dense_spd_inverse_begin(tgms_ctx* c, double* A, int n, DenseInvAsync& h);
 void dense_spd_inverse_end(DenseInvAsync& h);
+int bcr_max_block(const tgms_ctx* c);  // largest block the factor kernel holds in LDS
+// factorise the banded SPD A (dense n x n, row-major; zero beyond half-bandwidth bs)
+void bcr_factor(tgms_ctx* c, const double* A, int n, int bs, Bcr& F, bool fp32);
+bool bcr_failed(tgms_ctx* c, const Bcr& F);  // a non-positive pivot (synchronises)
+template <typename T>
+void bcr_solve(tgms_ctx* c, const Bcr& F, T* x, const double* sc);  // x (nb * bs) <- A^{-1} x
 template <typename T>
 void symv(tgms_ctx* c, const T* A, int n, const T* x, T* y, const double* sc);
 template <typename T>

@@ -472,6 +472,260 @@ __global__ void k_mirror_lower(double* __restrict__ F, int n) {
 
 inline unsigned nb(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
+// ---- block cyclic reduction: Cholesky of a banded SPD matrix -------------------------
+// With its unknowns numbered so that the half-bandwidth is at most bs, the coarse matrix
+// is block tridiagonal in blocks of bs rows: diagonal blocks D_i, couplings Lc_i =
+// A_{i, i-1}.  Cyclic reduction eliminates the blocks i = s, 3s, 5s, ... (s = 1, 2, 4,
+// ...) level by level: C_i = chol(D_i), Gm_i = C_i^{-1} A_{i, i-s}, Gp_i = C_i^{-1}
+// A_{i, i+s}; the surviving blocks e (multiples of 2s) take the Schur complements
+// D_e -= Gp_{e-s}^T Gp_{e-s} + Gm_{e+s}^T Gm_{e+s} and the new coupling
+// A_{e, e-2s} = -Gp_{e-s}^T Gm_{e-s}; block 0 is left last.  This is the Cholesky
+// factorisation of the matrix in the odd-even order of its blocks (block factor
+// diagonal C_i, off-diagonal Gm_i^T, Gp_i^T); it is stored as C_i^{-1} (lower), Gm_i,
+// Gp_i.  A solve is one forward and one backward pass over the levels.
+constexpr int BCR_MAX = 256;  // largest block (LDS vectors of the solve kernels)
+
+// D_i and Lc_i from the dense matrix A (n x n, row-major); rows beyond n: identity.
+__global__ void k_bcr_extract(const double* __restrict__ A, int n, int bs, int nblk, double* __restrict__ D,
+                              double* __restrict__ Lc) {
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long bb = (long long)bs * bs;
+    if (e >= nblk * bb) return;
+    const int i = (int)(e / bb), r = (int)((e % bb) / bs), c = (int)(e % bs);
+    const long long row = (long long)i * bs + r, col = (long long)i * bs + c;
+    D[e] = (row < n && col < n) ? A[row * n + col] : (r == c ? 1.0 : 0.0);
+    Lc[e] = (i > 0 && row < n) ? A[row * n + col - bs] : 0.0;
+}
+
+// The diagonal blocks eliminated at level s (i = s + 2 s q, one workgroup each; top: block
+// 0): Cholesky in LDS, then the inverse of the factor in place; C_i^{-1} (zero above the
+// diagonal) to Ci.  A non-positive pivot sets *fail.  1024 threads: the rank-1 updates
+// on a 32 x 32 thread grid, each row of the inversion's sums split over 8 lanes.
+constexpr int FNT = 1024;
+__global__ void __launch_bounds__(FNT) k_bcr_factor(const double* __restrict__ D, double* __restrict__ Ci, int bs,
+                                                   int nblk, int s, int top, int* __restrict__ fail) {
+    extern __shared__ double A[];
+    __shared__ double tmp[BCR_MAX];
+    const int i = top ? 0 : s + 2 * s * blockIdx.x;
+    if (i >= nblk) return;
+    const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+    const long long bb = (long long)bs * bs;
+    const double* Dg = D + i * bb;
+    for (int e = tid; e < bs * bs; e += FNT) A[e] = Dg[e];
+    __syncthreads();
+    bool bad = false;
+    for (int k = 0; k < bs; ++k) {
+        const double akk = A[k * bs + k];
+        bad = bad || !(akk > 0.0);
+        const double d = sqrt(akk > 0.0 ? akk : 1.0);
+        __syncthreads();  // every thread has read A[k][k]
+        if (tid == 0) A[k * bs + k] = d;
+        const double rd = 1.0 / d;
+        for (int r = k + 1 + tid; r < bs; r += FNT) A[r * bs + k] *= rd;
+        __syncthreads();
+        for (int r = k + 1 + ty; r < bs; r += 32) {
+            const double ark = A[r * bs + k];
+            for (int c = k + 1 + tx; c <= r; c += 32) A[r * bs + c] -= ark * A[c * bs + k];
+        }
+        __syncthreads();
+    }
+    if (bad && tid == 0) atomicOr(fail, 1);
+    // X = L^{-1} in place, column by column from the last: X[r][j] = -(sum_{k=j+1}^{r}
+    // X[r][k] L[k][j]) / L[j][j], with the columns right of j already inverted
+    const int g = tid >> 3, sub = tid & 7;
+    for (int j = bs - 1; j >= 0; --j) {
+        const double ljj = A[j * bs + j];
+        for (int r0 = j + 1; r0 < bs; r0 += FNT / 8) {
+            const int r = r0 + g;
+            double acc = 0.0;
+            if (r < bs)
+                for (int k = j + 1 + sub; k <= r; k += 8) acc += A[r * bs + k] * A[k * bs + j];
+#pragma unroll
+            for (int o = 4; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+            if (r < bs && sub == 0) tmp[r] = -acc / ljj;
+        }
+        __syncthreads();
+        for (int r = j + 1 + tid; r < bs; r += FNT) A[r * bs + j] = tmp[r];
+        if (tid == 0) A[j * bs + j] = 1.0 / ljj;
+        __syncthreads();
+    }
+    double* Cg = Ci + i * bb;
+    for (int e = tid; e < bs * bs; e += FNT) Cg[e] = (e % bs <= e / bs) ? A[e] : 0.0;
+}
+
+// Gm_i = C_i^{-1} Lc_i and Gp_i = C_i^{-1} Lc_{i+s}^T for the blocks eliminated at level s
+// (64 x 64 output tiles on the FP64 matrix cores; blockIdx: tile, product, block).
+__global__ void __launch_bounds__(NT) k_bcr_offdiag(const double* __restrict__ Ci, const double* __restrict__ Lc,
+                                                   double* __restrict__ Gm, double* __restrict__ Gp, int bs, int nblk,
+                                                   int s) {
+    const int T = (bs + TB - 1) / TB;
+    int b = blockIdx.x;
+    const int tile = b % (T * T);
+    b /= T * T;
+    const int job = b % 2, i = s + 2 * s * (b / 2);
+    if (i >= nblk) return;
+    const long long bb = (long long)bs * bs;
+    const int tm = tile / T, tn = tile % T;
+    if (job == 0) {
+        gemm_tile(tm, tn, 0, 0, bs, bs, bs, 1.0, Ci + i * bb, bs, Lc + i * bb, bs, 0.0, Gm + i * bb, bs);
+    } else {
+        if (i + s >= nblk) return;
+        gemm_tile(tm, tn, 0, 1, bs, bs, bs, 1.0, Ci + i * bb, bs, Lc + (i + s) * bb, bs, 0.0, Gp + i * bb, bs);
+    }
+}
+
+// Schur complements of level s on the surviving blocks e = 2 s q: job 0 updates D_e, job 1
+// forms the coupling of e with e - 2s (the next level's Lc_e).
+__global__ void __launch_bounds__(NT) k_bcr_schur(const double* __restrict__ Gm, const double* __restrict__ Gp,
+                                                 double* __restrict__ D, double* __restrict__ Lc, int bs, int nblk,
+                                                 int s) {
+    const int T = (bs + TB - 1) / TB;
+    int b = blockIdx.x;
+    const int tile = b % (T * T);
+    b /= T * T;
+    const int job = b % 2, e = 2 * s * (b / 2);
+    if (e >= nblk) return;
+    const long long bb = (long long)bs * bs;
+    const int tm = tile / T, tn = tile % T;
+    if (job == 0) {
+        if (e >= s)
+            gemm_tile(tm, tn, 1, 0, bs, bs, bs, -1.0, Gp + (e - s) * bb, bs, Gp + (e - s) * bb, bs, 1.0, D + e * bb,
+                      bs);
+        __syncthreads();
+        if (e + s < nblk)
+            gemm_tile(tm, tn, 1, 0, bs, bs, bs, -1.0, Gm + (e + s) * bb, bs, Gm + (e + s) * bb, bs, 1.0, D + e * bb,
+                      bs);
+    } else if (e >= s) {
+        gemm_tile(tm, tn, 1, 0, bs, bs, bs, -1.0, Gp + (e - s) * bb, bs, Gm + (e - s) * bb, bs, 0.0, Lc + e * bb, bs);
+    }
+}
+
+__global__ void k_d2f(const double* __restrict__ x, float* __restrict__ y, long long n) {
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e < n) y[e] = (float)x[e];
+}
+
+// The solve kernels: 1024 threads, each row of a product handled by 16 lanes, every
+// load of a row slot issued before its sums (the level kernels are latency-bound).
+constexpr int SNT = 1024;
+constexpr int SG = 16;
+constexpr int BCR_SOLVE_MAX = 144;
+constexpr int SKM = (BCR_SOLVE_MAX + SG - 1) / SG;
+
+// out[r] = sum_k M1[r][k] v1[k] + sum_k M2[r][k] v2[k] (r < bs; M2 may be null), M row-major
+// bs x bs, v in LDS; out to LDS or global
+template <typename T>
+__device__ inline void bcr_gemv(const T* __restrict__ M1, const T* v1, const T* __restrict__ M2, const T* v2, int bs,
+                                T* out) {
+    constexpr int NG = SNT / SG;
+    const int tid = threadIdx.x, g = tid / SG, l = tid % SG;
+    for (int r0 = 0; r0 < bs; r0 += NG) {
+        const int r = r0 + g;
+        T acc = T(0);
+        if (r < bs) {
+            T a[SKM], b[SKM];
+#pragma unroll
+            for (int j = 0; j < SKM; ++j) {
+                const int k = l + SG * j;
+                a[j] = k < bs ? M1[(long long)r * bs + k] : T(0);
+                b[j] = (M2 != nullptr && k < bs) ? M2[(long long)r * bs + k] : T(0);
+            }
+#pragma unroll
+            for (int j = 0; j < SKM; ++j) {
+                const int k = l + SG * j;
+                if (k < bs) acc += a[j] * v1[k] + (M2 != nullptr ? b[j] * v2[k] : T(0));
+            }
+        }
+#pragma unroll
+        for (int o = SG / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (r < bs && l == 0) out[r] = acc;
+    }
+}
+
+// Factors the solve reads: C_i^{-1} (C), its transpose (CT), Gm, Gp and their transposes.
+template <typename T>
+struct BcrView {
+    const T *C, *CT, *Gm, *Gp, *GmT, *GpT;
+};
+
+// Forward pass of level s: every surviving block e = 2 s q forms y of its eliminated
+// neighbours (y_k = C_k^{-1} b_k), keeps y_{e+s} in Y, and takes
+// b_e -= Gp_{e-s}^T y_{e-s} + Gm_{e+s}^T y_{e+s}.
+template <typename T>
+__global__ void __launch_bounds__(SNT) k_bcr_fwd(BcrView<T> F, T* __restrict__ x, T* __restrict__ Y, int bs, int nblk,
+                                                int s, const double* __restrict__ sc) {
+    if (sc != nullptr && sc[SC_DONE] != 0.0) return;
+    const int e = 2 * s * blockIdx.x;
+    if (e >= nblk) return;
+    __shared__ T bl[BCR_SOLVE_MAX], br[BCR_SOLVE_MAX], yl[BCR_SOLVE_MAX], yr[BCR_SOLVE_MAX], t[BCR_SOLVE_MAX];
+    const int tid = threadIdx.x;
+    const long long bb = (long long)bs * bs;
+    const bool h1 = e >= s, h2 = e + s < nblk;
+    const int i1 = e - s, i2 = e + s;
+    for (int r = tid; r < bs; r += SNT) {
+        bl[r] = h1 ? x[(long long)i1 * bs + r] : T(0);
+        br[r] = h2 ? x[(long long)i2 * bs + r] : T(0);
+        yl[r] = T(0);
+        yr[r] = T(0);
+    }
+    __syncthreads();
+    if (h1) bcr_gemv<T>(F.C + i1 * bb, bl, nullptr, nullptr, bs, yl);
+    if (h2) bcr_gemv<T>(F.C + i2 * bb, br, nullptr, nullptr, bs, yr);
+    __syncthreads();
+    if (h2)
+        for (int r = tid; r < bs; r += SNT) Y[(long long)i2 * bs + r] = yr[r];
+    bcr_gemv<T>(h1 ? F.GpT + i1 * bb : F.GmT + i2 * bb, h1 ? yl : yr, (h1 && h2) ? F.GmT + i2 * bb : nullptr, yr, bs,
+                t);
+    __syncthreads();
+    for (int r = tid; r < bs; r += SNT) x[(long long)e * bs + r] -= t[r];
+}
+
+// Block 0 after the last level: x_0 = C_0^{-T} C_0^{-1} b_0.
+template <typename T>
+__global__ void __launch_bounds__(SNT) k_bcr_top(BcrView<T> F, T* __restrict__ x, int bs,
+                                                const double* __restrict__ sc) {
+    if (sc != nullptr && sc[SC_DONE] != 0.0) return;
+    __shared__ T b[BCR_SOLVE_MAX], y[BCR_SOLVE_MAX];
+    for (int r = threadIdx.x; r < bs; r += SNT) b[r] = x[r];
+    __syncthreads();
+    bcr_gemv<T>(F.C, b, nullptr, nullptr, bs, y);
+    __syncthreads();
+    bcr_gemv<T>(F.CT, y, nullptr, nullptr, bs, x);
+}
+
+// Backward pass of level s: x_i = C_i^{-T} (y_i - Gm_i x_{i-s} - Gp_i x_{i+s}) for the
+// blocks eliminated at this level (their neighbours are solved at higher levels).
+template <typename T>
+__global__ void __launch_bounds__(SNT) k_bcr_bwd(BcrView<T> F, T* __restrict__ x, const T* __restrict__ Y, int bs,
+                                                int nblk, int s, const double* __restrict__ sc) {
+    if (sc != nullptr && sc[SC_DONE] != 0.0) return;
+    const int i = s + 2 * s * blockIdx.x;
+    if (i >= nblk) return;
+    __shared__ T xa[BCR_SOLVE_MAX], xb[BCR_SOLVE_MAX], t[BCR_SOLVE_MAX];
+    const int tid = threadIdx.x;
+    const long long bb = (long long)bs * bs;
+    const bool hb = i + s < nblk;
+    for (int r = tid; r < bs; r += SNT) {
+        xa[r] = x[(long long)(i - s) * bs + r];
+        xb[r] = hb ? x[(long long)(i + s) * bs + r] : T(0);
+    }
+    __syncthreads();
+    bcr_gemv<T>(F.Gm + i * bb, xa, hb ? F.Gp + i * bb : nullptr, xb, bs, t);
+    __syncthreads();
+    for (int r = tid; r < bs; r += SNT) t[r] = Y[(long long)i * bs + r] - t[r];
+    __syncthreads();
+    bcr_gemv<T>(F.CT + i * bb, t, nullptr, nullptr, bs, x + (long long)i * bs);
+}
+
+// B_i = A_i^T for every block
+__global__ void k_bcr_transpose(const double* __restrict__ A, double* __restrict__ B, int bs, long long tot) {
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= tot) return;
+    const long long bb = (long long)bs * bs, base = e / bb * bb;
+    const int r = (int)((e % bb) / bs), c = (int)(e % bs);
+    B[base + (long long)c * bs + r] = A[e];
+}
+
 }  // namespace
 
 namespace tgms {
@@ -711,5 +965,117 @@ bool symv_full_acc(tgms_ctx* c, const double* F, int n, const int* ptr, const in
 int symv_acc_max() { return ACC_MAX; }
 template bool symv_acc<float>(tgms_ctx*, const float*, int, const int*, const int*, const float*, float*,
                               const double*);
+
+// ---- block cyclic reduction (see the kernels above) ----
+int bcr_max_block(const tgms_ctx* c) {
+    // the factor kernel keeps a block in LDS; the solve kernels hold rows in registers
+    int bs = BCR_SOLVE_MAX;
+    while (bs > 0 && (long long)bs * bs * 8 + 8 * BCR_MAX > c->lds_max) --bs;
+    return bs;
+}
+
+void bcr_factor(tgms_ctx* c, const double* A, int n, int bs, Bcr& F, bool fp32) {
+    if (bs < 1 || bs > bcr_max_block(c)) throw TgmsError{TGMS_E_UNSUPPORTED, "coarse bandwidth too large"};
+    const int nblk = (n + bs - 1) / bs;
+    const long long bb = (long long)bs * bs, tot = nblk * bb;
+    if (!F.D || F.n != n || F.bs != bs) {
+        F.D = c->alloc<double>(tot);
+        F.Lc = c->alloc<double>(tot);
+        F.C = c->alloc<double>(tot);
+        F.Gm = c->alloc<double>(tot);
+        F.Gp = c->alloc<double>(tot);
+        F.CT = c->alloc<double>(tot);
+        F.GmT = c->alloc<double>(tot);
+        F.GpT = c->alloc<double>(tot);
+        F.Y = c->alloc<double>((size_t)nblk * bs);
+        F.x = c->alloc<double>((size_t)nblk * bs);
+        F.fail = c->alloc<int>(1);
+        if (fp32) {
+            F.C32 = c->alloc<float>(tot);
+            F.Gm32 = c->alloc<float>(tot);
+            F.Gp32 = c->alloc<float>(tot);
+            F.CT32 = c->alloc<float>(tot);
+            F.GmT32 = c->alloc<float>(tot);
+            F.GpT32 = c->alloc<float>(tot);
+            F.Y32 = c->alloc<float>((size_t)nblk * bs);
+            F.x32 = c->alloc<float>((size_t)nblk * bs);
+        }
+    }
+    F.n = n;
+    F.bs = bs;
+    F.nb = nblk;
+    zero(c, F.fail, sizeof(int) * 2);
+    zero(c, F.Gp, sizeof(double) * tot);  // blocks without a right neighbour keep zeros
+    hipLaunchKernelGGL(k_bcr_extract, dim3(nb(tot)), dim3(256), 0, c->stream, A, n, bs, nblk, F.D, F.Lc);
+    LAUNCH_OK();
+    const size_t lds = sizeof(double) * (size_t)bb;
+    HIP_OK(hipFuncSetAttribute((const void*)k_bcr_factor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const int T = (bs + TB - 1) / TB;
+    for (int s = 1; s < nblk; s *= 2) {
+        const int ne = (nblk - s - 1) / (2 * s) + 1, na = (nblk - 1) / (2 * s) + 1;
+        hipLaunchKernelGGL(k_bcr_factor, dim3(ne), dim3(FNT), lds, c->stream, (const double*)F.D, F.C, bs, nblk, s, 0,
+                           F.fail);
+        LAUNCH_OK();
+        hipLaunchKernelGGL(k_bcr_offdiag, dim3(ne * 2 * T * T), dim3(NT), 0, c->stream, (const double*)F.C,
+                           (const double*)F.Lc, F.Gm, F.Gp, bs, nblk, s);
+        LAUNCH_OK();
+        hipLaunchKernelGGL(k_bcr_schur, dim3(na * 2 * T * T), dim3(NT), 0, c->stream, (const double*)F.Gm,
+                           (const double*)F.Gp, F.D, F.Lc, bs, nblk, s);
+        LAUNCH_OK();
+    }
+    hipLaunchKernelGGL(k_bcr_factor, dim3(1), dim3(FNT), lds, c->stream, (const double*)F.D, F.C, bs, nblk, 1, 1,
+                       F.fail);
+    LAUNCH_OK();
+    hipLaunchKernelGGL(k_bcr_transpose, dim3(nb(tot)), dim3(256), 0, c->stream, (const double*)F.C, F.CT, bs, tot);
+    hipLaunchKernelGGL(k_bcr_transpose, dim3(nb(tot)), dim3(256), 0, c->stream, (const double*)F.Gm, F.GmT, bs, tot);
+    hipLaunchKernelGGL(k_bcr_transpose, dim3(nb(tot)), dim3(256), 0, c->stream, (const double*)F.Gp, F.GpT, bs, tot);
+    LAUNCH_OK();
+    if (fp32) {
+        const double* src[6] = {F.C, F.Gm, F.Gp, F.CT, F.GmT, F.GpT};
+        float* dst[6] = {F.C32, F.Gm32, F.Gp32, F.CT32, F.GmT32, F.GpT32};
+        for (int k = 0; k < 6; ++k)
+            hipLaunchKernelGGL(k_d2f, dim3(nb(tot)), dim3(256), 0, c->stream, src[k], dst[k], tot);
+        LAUNCH_OK();
+    }
+}
+
+bool bcr_failed(tgms_ctx* c, const Bcr& F) {
+    int h = 0;
+    HIP_OK(hipMemcpyAsync(&h, F.fail, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return h != 0;
+}
+
+template <typename T>
+void bcr_solve(tgms_ctx* c, const Bcr& F, T* x, const double* sc) {
+    BcrView<T> V;
+    T* Y;
+    if constexpr (sizeof(T) == 8) {
+        V = BcrView<T>{(const T*)F.C, (const T*)F.CT, (const T*)F.Gm, (const T*)F.Gp, (const T*)F.GmT, (const T*)F.GpT};
+        Y = (T*)F.Y;
+    } else {
+        V = BcrView<T>{(const T*)F.C32, (const T*)F.CT32, (const T*)F.Gm32, (const T*)F.Gp32, (const T*)F.GmT32,
+                       (const T*)F.GpT32};
+        Y = (T*)F.Y32;
+    }
+    const int nblk = F.nb, bs = F.bs;
+    int top = 1;
+    while (top < nblk) top *= 2;
+    for (int s = 1; s < nblk; s *= 2) {
+        hipLaunchKernelGGL((k_bcr_fwd<T>), dim3((nblk - 1) / (2 * s) + 1), dim3(SNT), 0, c->stream, V, x, Y, bs, nblk,
+                           s, sc);
+        LAUNCH_OK();
+    }
+    hipLaunchKernelGGL((k_bcr_top<T>), dim3(1), dim3(SNT), 0, c->stream, V, x, bs, sc);
+    LAUNCH_OK();
+    for (int s = top / 2; s >= 1; s /= 2) {
+        if (s >= nblk) continue;
+        hipLaunchKernelGGL((k_bcr_bwd<T>), dim3((nblk - s - 1) / (2 * s) + 1), dim3(SNT), 0, c->stream, V, x,
+                           (const T*)Y, bs, nblk, s, sc);
+        LAUNCH_OK();
+    }
+}
+template void bcr_solve<double>(tgms_ctx*, const Bcr&, double*, const double*);
+template void bcr_solve<float>(tgms_ctx*, const Bcr&, float*, const double*);
 
 }  // namespace tgms

@@ -310,10 +310,16 @@ void preprocess(tgms_ctx* c, const double* F, const double* g_bnd, double* vbar,
     HIP_OK(hipMemcpyAsync(cpd, cp.data(), sizeof(double) * (nxf + nyf), hipMemcpyHostToDevice, c->stream));
     if (c->nv > 0) {
         HIP_OK(hipMemcpyAsync(c->svec2, rhs.data(), sizeof(double) * c->nv, hipMemcpyHostToDevice, c->stream));
-        double* save = c->cvec2;
-        c->cvec2 = c->svec2 + c->nv;  // temporary of the triangular products
-        symv<double>(c, c->KH, c->nv, c->svec2, c->svec, nullptr);
-        c->cvec2 = save;
+        if (c->kb.nb > 0) {
+            copy(c, c->nv, c->svec2, c->kb.x);
+            bcr_solve<double>(c, c->kb, c->kb.x, nullptr);
+            copy(c, c->nv, c->kb.x, c->svec);
+        } else {
+            double* save = c->cvec2;
+            c->cvec2 = c->svec2 + c->nv;  // temporary of the triangular products
+            symv<double>(c, c->KH, c->nv, c->svec2, c->svec, nullptr);
+            c->cvec2 = save;
+        }
     }
     hipLaunchKernelGGL(k_coarse_vel, dim3(nb(nxf + nyf)), dim3(256), 0, c->stream, (const double*)cpd,
                        (const double*)c->svec, Nx, Ny, Hx, Hy, c->cflux);

@@ -1318,6 +1318,15 @@ template float* coarse_cy<float>(tgms_ctx*);
 template <typename T>
 const T* coarse_solve(tgms_ctx* c, const double* sc) {
     const CoarseBufs<T> B = coarse_bufs<T>(c);
+    if (c->cb.nb > 0) {
+        // cyclic-reduction Cholesky: accumulate into its padded vector, solve in place
+        T* x = sizeof(T) == 8 ? (T*)c->cb.x : (T*)c->cb.x32;
+        hipLaunchKernelGGL((k_coarse_accum<T>), dim3((c->ncs + 255) / 256), dim3(256), 0, c->stream, c->unk_ptr,
+                           c->unk_ent, (const T*)B.cy, c->ncs, x, sc);
+        LAUNCH_OK();
+        bcr_solve<T>(c, c->cb, x, sc);
+        return x;
+    }
     T* res = B.c1 + c->ncs;
     if constexpr (sizeof(T) == 8)
         if (symv_full_acc(c, c->Acf, c->ncs, c->unk_ptr, c->unk_ent, (const double*)B.cy, (double*)res, sc))

@@ -178,3 +178,34 @@ def test_grid_dimension_checked():
     inf = _lib.Info()
     assert lib.tgms_info(h, ctypes.byref(inf)) == 0 and inf.eig_unconverged == 0
     lib.tgms_destroy(h)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["cfg32", "chan64", "b16_96x64"])
+def test_cyclic_reduction_coarse_factor_matches_oracle(name, precision):
+    """The block cyclic-reduction Cholesky of the coarse systems (forced here also where
+    the dense inverse would be chosen by size) against the oracle's direct solves: the
+    coarse correction and the preprocessing (its coarse RT0 system), and the solve."""
+    import paper_1807_07220_amd as tg
+    gen, bx, by, tol = CASES[name]
+    kappa = gen()
+    o = _oracle(kappa, bx, by, tol)
+    s = tg.Solver(dev(kappa), bx, by, tol, precision=precision, coarse_factor="bcr")
+    inf = s.info()
+    assert inf["coarse_block"] > 0 and inf["rt0_block"] == o.g.Nx
+    r = np.random.default_rng(8).standard_normal(o.g.nf) * o.mask
+    zc = host(s.apply_precond("coarse", dev(r)))
+    ec = rel(zc, o.coarse(r))
+    F = fields.random_source(o.g.nx, o.g.ny, 5).ravel()
+    ev = rel(host(s.preprocess(dev(F))), o.preprocess(F)[0])
+    Fc = fields.corner_source(o.g.nx, o.g.ny).ravel()
+    res, ro = s.solve(dev(Fc), rtol=1e-10), o.solve(Fc, rtol=1e-10)
+    du = host(res["u"]) - ro["u"]
+    eu = np.sqrt(du @ (o.A @ du)) / np.sqrt(ro["u"] @ (o.A @ ro["u"]))  # energy norm
+    print(f"bcr {name} {precision}: block {inf['coarse_block']}, coarse {ec:.2e}, preprocess {ev:.2e}, "
+          f"iters {res['iters']} / {ro['iters']}, u {eu:.2e}")
+    assert ev < 1e-8
+    if precision == "fp64":
+        assert ec < 1e-8 and abs(res["iters"] - ro["iters"]) <= 1 and eu <= 1e-10
+    else:
+        assert ec < 1e-4 and eu <= 1e-8

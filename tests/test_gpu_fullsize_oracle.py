@@ -8,10 +8,13 @@ rtol 1e-12.  The library runs in the launch configuration the benchmark times
 (autotuned, HIP graphs) and is compared with those values:
   * counts identical except where an oracle eigenvalue lies within 1e-8 of the tolerance;
   * iterations to rtol 1e-8 within one of the oracle's;
-  * at rtol 1e-12 (both sides), the sampled velocity and pressure within 1e-10 relative
-    (FP64 preconditioner) or 1e-8 (FP32 preconditioner in the flexible FP64 PCG), or
-    within twice the oracle iterate's distance to the direct solve of the full saddle
-    system where that (recorded up to 256^2) is larger: the attainable FP64 accuracy.
+  * at rtol 1e-12 (both sides), the sampled velocity in the energy norm (weights: the
+    mass matrix's diagonal) and the sampled pressure within 1e-10 relative (FP64
+    preconditioner) or 1e-8 (FP32 preconditioner in the flexible FP64 PCG);
+  * the sampled velocity in the 2-norm within the same bar or within twice the oracle
+    iterate's own distance to the direct solve of the full saddle system, where that
+    attainable FP64 accuracy is coarser (at contrast 1e6 the 2-norm is dominated by the
+    channel faces, whose velocities the energy norm weights by 1e-6).
 """
 import os
 
@@ -28,6 +31,25 @@ from gpu_util import dev, eig_bound, host  # noqa: E402
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 RUNS = [("darcy2d_256_b16", "fp64"), ("darcy2d_1024_b16", "fp64"), ("darcy2d_1024_b16", "mixed"),
         ("darcy2d_1024_b8", "fp64")]
+
+
+def mass_diagonal(kappa, idx):
+    """Diagonal of the RT0 mass matrix A at the full-numbered faces idx: each adjacent cell
+    c contributes |c| kappa_c^{-1} / 3 (A is spectrally equivalent to its diagonal, within
+    a factor 3 for these elements, so the weighted sum below estimates the energy norm)."""
+    ny, nx = kappa.shape
+    area = 1.0 / (nx * ny)
+    kinv = 1.0 / kappa
+    nfx = (nx + 1) * ny
+    d = np.zeros(idx.size)
+    isx = idx < nfx
+    fx, fy = idx[isx], idx[~isx] - nfx
+    j, i = fx // (nx + 1), fx % (nx + 1)
+    dx = np.where(i > 0, kinv[j, np.maximum(i - 1, 0)], 0.0) + np.where(i < nx, kinv[j, np.minimum(i, nx - 1)], 0.0)
+    j, i = fy // nx, fy % nx
+    dy = np.where(j > 0, kinv[np.maximum(j - 1, 0), i], 0.0) + np.where(j < ny, kinv[np.minimum(j, ny - 1), i], 0.0)
+    d[isx], d[~isx] = dx, dy
+    return d * area / 3.0
 
 
 def _golden(name):
@@ -67,16 +89,19 @@ def test_fullsize_matches_oracle(name, precision):
         p = host(r12["p"])[gold["cell_idx"]]
         eu = np.linalg.norm(u - gold["u_1e12"]) / np.linalg.norm(gold["u_1e12"])
         ep = np.linalg.norm(p - gold["p_1e12"]) / np.linalg.norm(gold["p_1e12"])
+        dm = mass_diagonal(kappa, gold["face_idx"])
+        ea = np.sqrt(np.sum(dm * (u - gold["u_1e12"]) ** 2) / np.sum(dm * gold["u_1e12"] ** 2))
         print(f"{name} {precision}: iters gpu {r8['iters']} oracle {int(gold['iters_1e8'])} "
               f"(Cond {float(gold['cond_1e8']):.3g}); at rtol 1e-12 gpu {r12['iters']} oracle "
-              f"{int(gold['iters_1e12'])}; sampled u err {eu:.2e}, p err {ep:.2e}")
+              f"{int(gold['iters_1e12'])}; sampled u err {eu:.2e} (energy norm {ea:.2e}), p err {ep:.2e}")
         # 1e-10 (FP64) or 1e-8 (FP32 preconditioner), or twice the oracle iterate's own
         # distance to the direct solve where that attainable accuracy is coarser
         bar = 1e-10 if precision == "fp64" else 1e-8
         fu, fp = float(gold.get("floor_u", np.nan)), float(gold.get("floor_p", np.nan))
         bu = max(bar, 2 * fu) if np.isfinite(fu) else bar
         bp = max(bar, 2 * fp) if np.isfinite(fp) else bar
-        assert eu <= bu and ep <= bp, (eu, bu, ep, bp)
+        assert ea <= bar and ep <= bp, (ea, bar, ep, bp)
+        assert eu <= bu, (eu, bu)
         assert abs(r8["iters"] - int(gold["iters_1e8"])) <= 1
     finally:
         s.close()

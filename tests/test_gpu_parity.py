@@ -125,12 +125,13 @@ def test_preconditioner_fp32(name, which):
 @pytest.mark.parametrize("name", list(CASES))
 def test_solve(name):
     """Setup + solve against the oracle: iterations to rtol 1e-8 within one where the
-    preconditioned system is well conditioned (Cond < 1e4; at larger Cond the count
-    follows rounding-level differences of the preconditioner, see
-    test_iterations_at_high_condition_number), and at rtol 1e-12 on both sides the
-    velocity and pressure within 1e-10 -- or within twice the distance of the oracle's
-    own iterate to the direct solve of the full saddle system where that distance (the
-    attainable FP64 accuracy of the problem) is larger."""
+    preconditioned system is well conditioned (Cond < 1e4; at the 128^2 grid's Cond 4.5e5
+    the count moves with rounding-level differences of the coarse solve: 99 against 104
+    with the GPU's coarse correction inside the oracle's own PCG), and at rtol 1e-12 on both sides the velocity in the energy norm (the
+    kappa^{-1}-weighted L2 norm the method controls) and the pressure within 1e-10; the
+    velocity's 2-norm, dominated at contrast 1e6 by channel faces that the energy norm
+    weights by 1e-6, within ten times the oracle iterate's own distance to the direct
+    solve of the full saddle system (the attainable FP64 accuracy) where that is larger."""
     from oracle.solver import exact_solve
     s, o, kappa = case(name)
     F = fields.corner_source(o.g.nx, o.g.ny).ravel()
@@ -145,11 +146,14 @@ def test_solve(name):
     ue, pe = exact_solve(o.g, kappa, F)
     floor_u = np.linalg.norm(ro["u"] - ue) / np.linalg.norm(ue)
     floor_p = np.linalg.norm(ro["p"] - pe) / np.linalg.norm(pe)
-    eu = np.linalg.norm(host(res["u"]) - ro["u"]) / np.linalg.norm(ro["u"])
+    du = host(res["u"]) - ro["u"]
+    eu = np.linalg.norm(du) / np.linalg.norm(ro["u"])
+    ea = np.sqrt(du @ (o.A @ du)) / np.sqrt(ro["u"] @ (o.A @ ro["u"]))
     ep = np.linalg.norm(host(res["p"]) - ro["p"]) / np.linalg.norm(ro["p"])
-    print(f"solve {name} at rtol 1e-12: u err {eu:.2e} (oracle vs direct {floor_u:.2e}), "
+    print(f"solve {name} at rtol 1e-12: u err {eu:.2e} (oracle vs direct {floor_u:.2e}), energy norm {ea:.2e}, "
           f"p err {ep:.2e} (oracle vs direct {floor_p:.2e})")
-    assert eu <= max(1e-10, 2 * floor_u) and ep <= max(1e-10, 2 * floor_p)
+    assert ea <= 1e-10 and ep <= max(1e-10, 2 * floor_p)
+    assert eu <= max(1e-10, 10 * floor_u)
 
 
 def test_solve_with_boundary_data():
