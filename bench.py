@@ -158,6 +158,90 @@ def cpu_baseline(w, kappa, F, gpu_iters, window=256, budget_iters=20):
             "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
+def mobility_sequence(w, precision, steps):
+    """Section 6.2's reuse: the coarse space of the initial permeability kept over a
+    sequence of mobility fields (update_mobility + solve) against a new coarse space for
+    each (setup on lambda kappa + solve).  Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    import paper_1807_07220_amd as tg
+    from workloads import fields
+    kappa, F = w.make_inputs()
+    dev = torch.device("cuda:0")
+    kd, Fd = torch.tensor(kappa, device=dev), torch.tensor(F, device=dev)
+    s = tg.Solver(kd, w.bx, w.by, w.eig_tol, precision=precision)
+    rows = []
+    for k in range(steps):
+        t = 1.4 * (k + 1) / (steps + 1)
+        lam = torch.tensor(fields.mobility_front(w.nx, w.ny, t), device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.update_mobility(lam)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = s.solve(Fd, rtol=w.rtol, maxit=2000)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        f = tg.Solver(kd * lam, w.bx, w.by, w.eig_tol, precision=precision)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        rf = f.solve(Fd, rtol=w.rtol, maxit=2000)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        rows.append({"front": t, "kept_iters": r["iters"], "new_iters": rf["iters"], "update_s": t1 - t0,
+                     "kept_solve_s": t2 - t1, "new_setup_s": t3 - t2, "new_solve_s": t4 - t3,
+                     "new_dim": f.info()["dim"]})
+        f.close()
+    out = {"mode": "mobility_sequence", "workload": w.name, "precision": precision, "dim_kept": s.info()["dim"],
+           "steps": rows,
+           "extra_iterations_max": max(r["kept_iters"] - r["new_iters"] for r in rows),
+           "kept_s_per_step": float(np.mean([r["update_s"] + r["kept_solve_s"] for r in rows])),
+           "new_s_per_step": float(np.mean([r["new_setup_s"] + r["new_solve_s"] for r in rows]))}
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
+def variant_sweep(w, precision):
+    """Setup + solve of one workload under the cycle's controls (one setup + solve warm-up,
+    then the median of three per form).  Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    import paper_1807_07220_amd as tg
+    kappa, F = w.make_inputs()
+    dev = torch.device("cuda:0")
+    kd, Fd = torch.tensor(kappa, device=dev), torch.tensor(F, device=dev)
+    forms = [("paper", {}), ("tol x0.5", {"tol": w.eig_tol * 0.5}), ("tol x10", {"tol": w.eig_tol * 10}),
+             ("tol x50", {"tol": w.eig_tol * 50}), ("eta 0.1", {"eta": 0.1}), ("eta 0.24", {"eta": 0.24}),
+             ("overlap 1", {"overlap": 1}), ("overlap 3", {"overlap": 3}), ("m1 = m2 = 2", {"smooth_steps": 2}),
+             ("additive Schwarz", {"additive": True}), ("MsFEM coarse space", {"coarse_space": "msfem"}),
+             ("RT0 coarse space", {"coarse_space": "rt0"})]
+    rows = []
+    for name, kw in forms:
+        kw = dict(kw)
+        tol = kw.pop("tol", w.eig_tol)
+        ts = []
+        for rep in range(4):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s = tg.Solver(kd, w.bx, w.by, tol, precision=precision, **kw)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r = s.solve(Fd, rtol=w.rtol, maxit=5000)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if rep:
+                ts.append((t1 - t0, t2 - t1))
+            inf, cond = s.info(), s.cond()
+            s.close()
+        rows.append({"form": name, "eig_tol": tol, "dim": inf["dim"], "iters": r["iters"], "converged": r["converged"],
+                     "cond": cond, "setup_s": float(np.median([a for a, _ in ts])),
+                     "solve_s": float(np.median([b for _, b in ts]))})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    print(json.dumps({"mode": "variants", "workload": w.name, "precision": precision, "rows": rows}), flush=True)
+
+
 def copy_calibration(nbytes, reps=5):
     import torch
     n = nbytes // 8
@@ -184,6 +268,14 @@ def main():
                     help="autotuner cache file (read, and written when a shape is tuned): runs that share it "
                          "use the same launch configuration")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES")
+    ap.add_argument("--variants", action="store_true",
+                    help="instead of the benchmark line: setup + solve of the workload under section 5's controls "
+                         "(eigenvalue tolerance, smoother weight, oversampling, smoothing steps, additive "
+                         "two-level form, coarse space)")
+    ap.add_argument("--mobility-steps", type=int, default=0, metavar="K",
+                    help="instead of the benchmark line: one setup, then K mobility updates (a water front "
+                         "advancing from the source corner) each followed by a solve with the coarse space kept, "
+                         "against a new setup + solve for lambda * kappa at each step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a design "
@@ -201,6 +293,12 @@ def main():
 
     w = configs.get(args.workload)
     precision = args.precision or w.precision
+    if args.mobility_steps:
+        mobility_sequence(w, precision, args.mobility_steps)
+        return
+    if args.variants:
+        variant_sweep(w, precision)
+        return
     tol = args.eig_tol if args.eig_tol is not None else w.eig_tol
     kappa, F = w.make_inputs()
     dev = torch.device("cuda:0")

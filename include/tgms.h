@@ -117,6 +117,11 @@ typedef struct {
                            Cholesky inverse for small FP64 systems, else the cyclic-reduction
                            Cholesky of the band where it fits); 1 always the dense inverse;
                            2 cyclic reduction wherever the band fits */
+    int smooth_steps;  /* m1 = m2: smoothing steps before and after the coarse correction (section 5,
+                          with the residual recomputed after each; the paper uses 1), 1..16 */
+    int additive;      /* 1: the two-level additive Schwarz form z = S r + P r instead of the
+                          multiplicative two-grid cycle (section 5 contrasts the two: the
+                          residual is not recomputed between the parts); 0 (default): the cycle */
 } tgms_options;
 
 typedef struct {

@@ -99,13 +99,18 @@ class OracleSolver:
     """Setup (Steps 1-2 pieces that do not depend on the source) and solve."""
 
     def __init__(self, g: Grid2D, kappa: np.ndarray, eig_tol: float, eta: float = 0.2,
-                 overlap: int = 2, s_scale: float | None = 1.0, basis: str = "gmsfem", force_counts=None):
+                 overlap: int = 2, s_scale: float | None = 1.0, basis: str = "gmsfem", force_counts=None,
+                 m_pre: int = 1, m_post: int = 1, additive: bool = False):
         """basis: "gmsfem" (section 4, the adaptive space), "msfem" (one function per
         coarse face, the sum of its snapshots, eq. msfem) or "rt0" (the coarse RT0
         space); the last two are the comparators of section 6.  force_counts: the
         number of eigenfunctions kept per coarse face (in the order of
         ``g.coarse_faces()``) instead of #{lambda < tol}, for comparisons where an
-        eigenvalue lies at the tolerance."""
+        eigenvalue lies at the tolerance.  m_pre, m_post: smoothing steps before and
+        after the coarse correction (section 5; 1 and 1 in the paper); additive: the
+        two-level additive Schwarz form S r + P r instead of the cycle (section 5 sets the
+        two apart by whether the residual is recomputed)."""
+        self.m_pre, self.m_post, self.additive = int(m_pre), int(m_post), bool(additive)
         self.g = g
         self.kappa = np.asarray(kappa, dtype=np.float64).reshape(g.ny, g.nx)
         if not np.all(np.isfinite(self.kappa)) or np.any(self.kappa <= 0):
@@ -227,10 +232,16 @@ class OracleSolver:
         return self.Phi @ sol[: self.nH]
 
     def twogrid(self, r):
-        """One pre-smoothing, one coarse correction, one post-smoothing (section 5)."""
+        """Pre-smoothing, coarse correction, post-smoothing, the residual recomputed after
+        each step (section 5; one step each in the paper), or the additive form."""
+        if self.additive:
+            return self.smooth(r) + self.coarse(r)
         z = self.smooth(r)
+        for _ in range(self.m_pre - 1):
+            z = z + self.smooth(r - self.apply_A(z))
         z = z + self.coarse(r - self.apply_A(z))
-        z = z + self.smooth(r - self.apply_A(z))
+        for _ in range(self.m_post):
+            z = z + self.smooth(r - self.apply_A(z))
         return z
 
     # ---- Step 1: preprocessing (section 3) -----------------------------

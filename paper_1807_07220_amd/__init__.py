@@ -45,7 +45,8 @@ class Solver:
                  graphs: bool = True, autotune: bool = True, tune_cache: str | None = None,
                  warm_start: str = "exact", cnn_weights: torch.Tensor | None = None, rq_tol: float = 1e-6,
                  smoother_staging: int = -1, rows_per_thread: int = 0, force_counts=None,
-                 coarse_space: str = "gmsfem", coarse_factor: str = "auto", _restore: str | None = None):
+                 coarse_space: str = "gmsfem", coarse_factor: str = "auto", smooth_steps: int = 1,
+                 additive: bool = False, _restore: str | None = None):
         lib = load()
         if kappa is not None and kappa.dim() != 2:
             raise ValueError("kappa must be (ny, nx)")
@@ -64,6 +65,8 @@ class Solver:
         opt.rows_per_thread = int(rows_per_thread)
         opt.coarse_space = COARSE_SPACES[coarse_space]
         opt.coarse_factor = {"auto": 0, "dense": 1, "bcr": 2}[coarse_factor]
+        opt.smooth_steps = int(smooth_steps)
+        opt.additive = 1 if additive else 0
         if _restore is not None:
             handle = ctypes.c_void_p()
             check(lib.tgms_load(str(_restore).encode(), ctypes.byref(opt), ctypes.byref(handle)))

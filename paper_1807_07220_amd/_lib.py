@@ -35,7 +35,7 @@ class Options(ctypes.Structure):
                 ("stream", c_void_p), ("graphs", c_int), ("autotune", c_int), ("tune_cache", c_char_p),
                 ("warm_start", c_int), ("cnn_weights", c_void_p), ("rq_tol", c_double),
                 ("smoother_staging", c_int), ("rows_per_thread", c_int), ("force_counts", c_void_p),
-                ("coarse_space", c_int), ("coarse_factor", c_int)]
+                ("coarse_space", c_int), ("coarse_factor", c_int), ("smooth_steps", c_int), ("additive", c_int)]
 
 
 class Info(ctypes.Structure):

@@ -220,9 +220,85 @@ double lanczos_cond(const std::vector<double>& al, const std::vector<double>& be
 // preconditioner's precision (T), gd: the same right-hand side in FP64 (the
 // residuals are formed in FP64 from it); z: FP64 output.  With dots, the final
 // gather also forms the PCG scalars from gd (and gold for the flexible variant).
+// The variants of section 5's cycle, unfused: m = c->msteps pre- and post-smoothing steps
+// with the residual recomputed after each (z += S(g - K z)), and the two-level additive
+// Schwarz form z = S g + P g (c->additive).  The iterate of the cycle is kept in FP64
+// (vt2), the residual formed in FP64 (vt) and rounded to the preconditioner's precision;
+// the first smoothing carries the PCG update like the fused cycle, the last gather forms
+// the PCG's partial sums.
+template <typename T>
+void twogrid_variant(tgms_ctx* c, const T* g, const double* gd, double* z, const double* gold, bool dots, bool first,
+                     const FusedUpdate* fu) {
+    const double* sc = dots ? c->sc : nullptr;
+    const long long nv = (long long)c->nx * c->ny;
+    const T* w = sizeof(T) == 8 ? (const T*)c->patW : (const T*)c->patW32;
+    double* z1 = c->vt2;
+    double* tmp = c->vt3;
+    double* td = c->vt;
+    T* tT = sizeof(T) == 8 ? (T*)c->vt : (T*)c->ft;
+    auto to_T = [&](const double* x) -> const T* {  // x in the preconditioner's precision
+        if constexpr (sizeof(T) == 8) return (const T*)x;
+        tgms::cast_d2f(c, nv, x, c->ft);
+        return (const T*)c->ft;
+    };
+    auto smooth_add = [&](const T* rhs, bool with_update, bool last) {
+        // z1 += S rhs (the last post-smoothing gathers into z with the PCG sums instead)
+        tgms::smooth_patches<T>(c, rhs, sc, with_update ? fu : nullptr);
+        if (last) {
+            const T* zin;
+            if constexpr (sizeof(T) == 8) {
+                zin = (const T*)z1;
+            } else {
+                tgms::cast_d2f(c, nv, z1, c->ft2);
+                zin = (const T*)c->ft2;
+            }
+            tgms::gather_final<T>(c, w, zin, z, dots ? gd : nullptr, gold, dots, first);
+        } else {
+            tgms::gather_final<T>(c, w, nullptr, tmp, nullptr, nullptr, false, false);
+            tgms::axpy(c, nv, 1.0, tmp, z1);
+        }
+    };
+    if (c->additive) {
+        // z = S g + P g: the smoothing first (it carries the PCG update, which forms g)
+        tgms::smooth_patches<T>(c, g, sc, fu);
+        T* zc = sizeof(T) == 8 ? (T*)c->vt2 : (T*)c->ft2;
+        tgms::coarse_apply<T>(c, to_T(gd), zc, false, sc);
+        tgms::gather_final<T>(c, w, (const T*)zc, z, dots ? gd : nullptr, gold, dots, first);
+        return;
+    }
+    const int m = c->msteps;
+    tgms::zero(c, z1, sizeof(double) * nv);
+    for (int k = 0; k < m; ++k) {  // pre-smoothing
+        if (k == 0) {
+            smooth_add(g, true, false);
+        } else {
+            tgms::vertex_residual(c, gd, z1, td);
+            smooth_add(to_T(td), false, false);
+        }
+    }
+    // coarse correction of the residual
+    tgms::vertex_residual(c, gd, z1, td);
+    if constexpr (sizeof(T) == 8) {
+        tgms::coarse_apply<double>(c, td, z1, true, sc);
+    } else {
+        tgms::coarse_apply<float>(c, to_T(td), c->ft2, false, sc);
+        tgms::cast_f2d(c, nv, c->ft2, tmp);
+        tgms::axpy(c, nv, 1.0, tmp, z1);
+    }
+    for (int k = 0; k < m; ++k) {  // post-smoothing
+        tgms::vertex_residual(c, gd, z1, td);
+        smooth_add(to_T(td), false, k == m - 1);
+    }
+    (void)tT;
+}
+
 template <typename T>
 void twogrid(tgms_ctx* c, const T* g, const double* gd, double* z, const double* gold, bool dots, bool first,
              const FusedUpdate* fu = nullptr) {
+    if (c->msteps != 1 || c->additive) {
+        twogrid_variant<T>(c, g, gd, z, gold, dots, first, fu);
+        return;
+    }
     const double* sc = dots ? c->sc : nullptr;
     T *w, *z1, *z2, *t;
     if constexpr (sizeof(T) == 8) {
@@ -524,6 +600,8 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         throw TgmsError{TGMS_E_INVAL, "rows_per_thread must be 0, 1 or 4"};
     if (o.coarse_space < 0 || o.coarse_space > 2) throw TgmsError{TGMS_E_INVAL, "coarse_space must be 0, 1 or 2"};
     if (o.coarse_factor < 0 || o.coarse_factor > 2) throw TgmsError{TGMS_E_INVAL, "coarse_factor must be 0, 1 or 2"};
+    if (o.smooth_steps < 1 || o.smooth_steps > 16) throw TgmsError{TGMS_E_INVAL, "smooth_steps must lie in [1, 16]"};
+    if (o.additive != 0 && o.additive != 1) throw TgmsError{TGMS_E_INVAL, "additive must be 0 or 1"};
     if (o.force_counts && (o.warm_start != 0 || o.coarse_space != 0))
         throw TgmsError{TGMS_E_INVAL, "force_counts needs the dense eigensolve of the adaptive space"};
     if (o.coarse_space != 0 && o.warm_start != 0)
@@ -574,6 +652,8 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         c->H = o.s_scale > 0 ? o.s_scale : std::sqrt(bx * c->hx * by * c->hy);
         c->coarse_space = o.coarse_space;
         c->coarse_factor = o.coarse_factor;
+        c->msteps = o.smooth_steps;
+        c->additive = o.additive ? 1 : 0;
         c->eig_bad = c->alloc<int>(1);
         c->eta = o.eta; c->tol = eig_tol; c->overlap = o.overlap; c->precision = o.precision ? 1 : 0;
         c->graph_failed = o.graphs == 0;  // never capture: launch every kernel directly
@@ -1252,6 +1332,8 @@ void tgms_default_options(tgms_options* opt) {
     opt->force_counts = nullptr;
     opt->coarse_space = 0;
     opt->coarse_factor = 0;
+    opt->smooth_steps = 1;
+    opt->additive = 0;
 }
 
 tgms_status tgms_setup(const tgms_grid* grid, const double* kappa, double eig_tol, const tgms_options* opt,

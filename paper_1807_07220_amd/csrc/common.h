@@ -219,6 +219,8 @@ struct tgms_ctx {
     double* AH0c = nullptr;   // nblk * 6 coarse RT0 Grams for the RT0 coarse space (main stream)
     int cband = 0;            // half-bandwidth of the coarse SPD matrix in its numbering
     int coarse_factor = 0;    // tgms_options.coarse_factor
+    int msteps = 1;           // pre- and post-smoothing steps of the two-grid cycle
+    int additive = 0;         // 1: two-level additive Schwarz (no residual recomputed)
     Bcr cb;                   // its cyclic-reduction Cholesky (cb.nb == 0: the dense inverse is used)
     Bcr kb;                   // the same for the coarse RT0 stiffness of the preprocessing
     // coarse RT0 (preprocessing)
@@ -404,6 +406,7 @@ int nred_max();
 void autotune(tgms_ctx* c, const char* cache_path);  // picks nred, smoother staging (k_tune.hip)
 void twogrid_probe(tgms_ctx* c);  // one two-grid application on the context's zeroed vectors (timing)
 void dir_apply(tgms_ctx* c, const double* z, const double* pin, double* pout, double* q);
+void vertex_residual(tgms_ctx* c, const double* g, const double* z, double* t);  // t = g - K z (FP64)
 void finalize(tgms_ctx* c, bool first);  // scalars from pending gather partials (first: rho_0, |z_0|^2)
 void allow_fused_lds(tgms_ctx* c);      // LDS limit of the per-block fused kernels (large blocks)
 template <typename T>

@@ -389,9 +389,36 @@ inline const T* slots(tgms_ctx* c) {
     return sizeof(T) == 8 ? (const T*)c->patW4 : (const T*)c->patW4_32;
 }
 
+// t = g - K z on the interior vertices (zero elsewhere), FP64: the residual between the
+// steps of the unfused two-grid variants (several smoothings, additive coarse correction)
+__global__ void k_vertex_residual(const double* __restrict__ g, const double* __restrict__ z,
+                                  const double* __restrict__ a, int nx, int ny, double sx2, double sy2,
+                                  double* __restrict__ t) {
+    const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (v >= (long long)nx * ny) return;
+    const int i = (int)(v % nx), j = (int)(v / nx);
+    if (i == 0 || j == 0) {
+        t[v] = 0.0;
+        return;
+    }
+    auto Z = [&](int ii, int jj) { return (ii >= 1 && ii < nx && jj >= 1 && jj < ny) ? z[(long long)jj * nx + ii] : 0.0; };
+    const Stencil9 k = stencil9(a[v - nx - 1], a[v - nx], a[v - 1], a[v], sx2, sy2);
+    const double kz = k.c * Z(i, j) + k.e * Z(i + 1, j) + k.w * Z(i - 1, j) + k.n * Z(i, j + 1) + k.s * Z(i, j - 1) +
+                      k.ne * Z(i + 1, j + 1) + k.nw * Z(i - 1, j + 1) + k.se * Z(i + 1, j - 1) + k.sw * Z(i - 1, j - 1);
+    t[v] = g[v] - kz;
+}
+
 }  // namespace
 
 namespace tgms {
+
+void vertex_residual(tgms_ctx* c, const double* g, const double* z, double* t) {
+    const long long n = (long long)c->nx * c->ny;
+    hipLaunchKernelGGL(k_vertex_residual, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, g, z,
+                       (const double*)c->a, c->nx, c->ny, c->sx * c->sx, c->sy * c->sy, t);
+    LAUNCH_OK();
+}
+
 
 unsigned pcg_tiles(tgms_ctx*) { return NRED; }
 int nred_max() { return NRED; }

@@ -226,3 +226,50 @@ def test_forced_counts_follow_the_eigenvalue_order():
     more = np.minimum(o.counts + 1, [e.size for e in o.eigs])
     om = OracleSolver(g, kappa, 0.5, force_counts=more)
     assert np.array_equal(om.counts, more) and om.dim == o.dim + int((more - o.counts).sum())
+
+
+def test_fixed_coarse_space_under_mobility_costs_at_most_two_iterations():
+    """Section 6.2 keeps the coarse space of the initial permeability while the total
+    mobility changes, at a cost of one or two extra iterations.  Here, for four positions
+    of a water front (quadratic relative permeabilities, viscosity ratio 5), the PCG with
+    the kept basis (operator, coarse matrix and smoother rebuilt for lambda kappa) against
+    one whose coarse space is built anew for lambda kappa."""
+    n, b = 32, 8
+    g = Grid2D(n, n, b, b)
+    kappa = fields.field_straight(n, n, 1, contrast=1e4)
+    F = fields.corner_source(n, n).ravel()
+    o = OracleSolver(g, kappa, 0.5)
+    for t in (0.3, 0.6, 0.9, 1.2):
+        lam = fields.mobility_front(n, n, t)
+        o.update_mobility(lam)
+        kept = o.solve(F, rtol=1e-8)
+        fresh = OracleSolver(g, kappa * lam.reshape(n, n), 0.5).solve(F, rtol=1e-8)
+        assert kept["iters"] <= fresh["iters"] + 2, (t, kept["iters"], fresh["iters"])
+        # both reach the same discrete solution of the updated operator
+        assert np.linalg.norm(kept["u"] - fresh["u"]) <= 1e-6 * np.linalg.norm(fresh["u"])
+
+
+def test_cycle_variants_symmetric_and_ordered():
+    """Section 5's controls: more smoothing steps (m1 = m2 = 2) keep the preconditioner
+    symmetric and positive on ker B and cut the iterations; the two-level additive Schwarz
+    form S + P (no residual recomputed) is symmetric too but needs more iterations than
+    the multiplicative cycle; its spectrum of (S + P) A on ker B lies in (0, 4 eta + 1]."""
+    g, kappa, o1 = _small(n=16, b=4, tol=0.5)
+    o2 = OracleSolver(g, kappa, 0.5, m_pre=2, m_post=2)
+    oa = OracleSolver(g, kappa, 0.5, additive=True)
+    rng = np.random.default_rng(4)
+    x, y = o1.mask * rng.standard_normal(g.nf), o1.mask * rng.standard_normal(g.nf)
+    for o in (o2, oa):
+        assert abs(x @ o.twogrid(y) - y @ o.twogrid(x)) < 1e-12 * abs(x @ o.twogrid(y))
+    Z, MA = _dense_on_kerB(o2, lambda v: o2.twogrid(o2.apply_A(v)))
+    ev2 = np.linalg.eigvals(Z.T @ MA).real
+    assert ev2.min() > 0 and ev2.max() <= 1 + 1e-10
+    Z, MA = _dense_on_kerB(oa, lambda v: oa.twogrid(oa.apply_A(v)))
+    eva = np.linalg.eigvals(Z.T @ MA).real
+    assert eva.min() > 0 and eva.max() <= 4 * oa.eta + 1 + 1e-10
+    F = fields.random_source(g.nx, g.ny, 3).ravel()
+    i1, i2, ia = (o.solve(F, rtol=1e-10)["iters"] for o in (o1, o2, oa))
+    assert i2 < i1 < ia, (i1, i2, ia)
+    # m = 1 is the paper's cycle exactly
+    o11 = OracleSolver(g, kappa, 0.5, m_pre=1, m_post=1)
+    assert np.array_equal(o11.twogrid(x), o1.twogrid(x))
