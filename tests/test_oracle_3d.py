@@ -1,0 +1,164 @@
+"""Pins of the three-dimensional oracle (CPU): assembly against quadrature, the paper's
+unknown counts, a manufactured solution, the local spectral problem at constant
+permeability, the projection, and the two-grid PCG against the direct solve."""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle.grid3d import Grid3D, div_matrix, mass_matrix
+from oracle.local import BorderedSaddle
+from oracle.solver3d import CellLaplacian, OracleSolver3D, exact_solve, face_geometry, pencil, snapshots
+
+pytestmark = pytest.mark.filterwarnings("ignore::scipy.sparse.SparseEfficiencyWarning")
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_mass_and_divergence_against_quadrature():
+    """A by 2-point Gauss quadrature (exact for products of the linear RT0 shape functions)
+    of kappa^{-1} phi_i . phi_j cell by cell, and B by the divergence theorem."""
+    g = Grid3D(2, 3, 2)
+    kinv = np.exp(np.random.default_rng(1).standard_normal(g.nc))
+    A = mass_matrix(g, kinv).toarray()
+    Aq = np.zeros_like(A)
+    gp = np.array([0.5 - 0.5 / np.sqrt(3), 0.5 + 0.5 / np.sqrt(3)])
+    for k, j, i in itertools.product(range(g.nz), range(g.ny), range(g.nx)):
+        c = g.cell(i, j, k)
+        # the six faces of the cell and their shape functions at a reference point t in [0,1]^3
+        faces = [(g.face(0, i, j, k), 0, 0), (g.face(0, i + 1, j, k), 0, 1), (g.face(1, i, j, k), 1, 0),
+                 (g.face(1, i, j + 1, k), 1, 1), (g.face(2, i, j, k), 2, 0), (g.face(2, i, j, k + 1), 2, 1)]
+        for t in itertools.product(gp, gp, gp):
+            vals = []
+            for f, a, hi in faces:
+                v = np.zeros(3)
+                v[a] = t[a] if hi else 1.0 - t[a]
+                vals.append((f, v))
+            for fi, vi in vals:
+                for fj, vj in vals:
+                    Aq[fi, fj] += kinv[c] * (vi @ vj) * g.cell_vol / 8.0
+    assert np.abs(A - Aq).max() < 1e-14 * np.abs(A).max()
+    B = div_matrix(g)
+    ones = np.zeros(g.nf)
+    ones[: g.n_xf] = 1.0  # uniform unit x-velocity: div 0 inside, net flux +-|e| at the walls only
+    d = B @ ones
+    assert np.abs(d).max() < 1e-15
+    assert np.allclose(np.asarray(B.sum(axis=1)).ravel(), 0.0)
+
+
+def test_unknown_counts_of_the_paper():
+    """Section 6.1 quotes the unknowns of the model 2 and model 3 fine systems; interior
+    faces + cells + 1 (the mean-zero multiplier) reproduces both, and interior coarse
+    faces + blocks + 1 the RT0 coarse dimensions of the model-2 and model-3 tables."""
+    with open(os.path.join(GOLDEN, "paper_counts.json")) as f:
+        gold = json.load(f)
+    for ent in gold["fine_dof"]:
+        g = Grid3D(*ent["cells"])
+        assert g.interior_idx.size + g.nc + 1 == ent["dof"]
+    for ent in gold["rt0_coarse_dim"]:
+        Nb = ent["blocks"]
+        g = Grid3D(*Nb)
+        assert g.interior_idx.size + g.nc + 1 == ent["dim"]
+
+
+def test_manufactured_solution_converges():
+    """kappa = 2, p = cos(pi x) cos(pi y) cos(pi z), v = -kappa grad p, f = 3 kappa pi^2 p:
+    the cell pressures and face fluxes of the direct solve approach the exact ones at
+    first order (observed second order at cell centres and face midpoints)."""
+    k0 = 2.0
+    errs = []
+    for n in (4, 8, 16):
+        g = Grid3D(n, n, n)
+        x = np.linspace(0, 1, n + 1)
+        s = (np.sin(np.pi * x[1:]) - np.sin(np.pi * x[:-1])) / np.pi
+        F = 3 * k0 * np.pi ** 2 * np.einsum("k,j,i->kji", s, s, s).ravel()
+        u, p = exact_solve(g, np.full(g.nc, k0), F)
+        xc = (np.arange(n) + 0.5) / n
+        pe = np.einsum("k,j,i->kji", np.cos(np.pi * xc), np.cos(np.pi * xc), np.cos(np.pi * xc)).ravel()
+        # x-face (i, j, k): v_x = k0 pi sin(pi x_i) cos(pi y_j) cos(pi z_k) at the face midpoint
+        I, J, K = g._mesh(n + 1, n, n)
+        ux = k0 * np.pi * np.sin(np.pi * x[I]) * np.cos(np.pi * xc[J]) * np.cos(np.pi * xc[K])
+        eu = np.abs(u[g.face(0, I, J, K).ravel()] - ux.ravel()).max() / np.abs(ux).max()
+        errs.append((np.abs(p - pe).max() / np.abs(pe).max(), eu))
+    errs = np.array(errs)
+    rates = np.log2(errs[:-1] / errs[1:])
+    assert np.all(rates >= 0.9), errs
+
+
+@pytest.mark.parametrize("s_scale", [None, 1.0])
+def test_lambda0_closed_form_and_tensor_dct_modes(s_scale):
+    """kappa = c on a uniform grid with cubic blocks of side H: the sum of the snapshots is
+    the coarse RT0 function, lambda_0 = sigma H / (2 H^2 / 3 + 2 c) for the s-form
+    prefactor 1/sigma (the same closed form as in 2D), and the pencil separates along the
+    two tangential axes of E, so every tensor product of DCT-II vectors is an eigenvector."""
+    n, b, c = 12, 4, 3.0
+    g = Grid3D(n, n, n, b, b, b)
+    kinv = np.full(g.nc, 1.0 / c)
+    A, B = mass_matrix(g, kinv).tocsr(), div_matrix(g).tocsr()
+    H = b / n
+    sigma = H if s_scale is None else s_scale
+    cache = {}
+
+    def block(I):
+        if I not in cache:
+            lo, hi = g.block_box(I)
+            cache[I] = BorderedSaddle(A, B, g.faces_in(lo, hi), g.cells_in(lo, hi))
+        return cache[I]
+    for face in (g.coarse_faces()[0], g.coarse_faces()[-1]):
+        fa, Psi = snapshots(g, A, B, block, face)
+        Dg, S = pencil(g, A, B, kinv, face, fa, Psi, s_scale)
+        import scipy.linalg as sla
+        lam = sla.eigh(np.diag(Dg), S, eigvals_only=True)
+        assert abs(lam[0] - sigma * H / (2 * H * H / 3 + 2 * c)) < 1e-12 * lam[0]
+        l = np.arange(b)
+        for m1, m2 in itertools.product(range(b), range(b)):
+            d = np.outer(np.cos(m2 * np.pi * (l + 0.5) / b), np.cos(m1 * np.pi * (l + 0.5) / b)).ravel()
+            mu = (d @ (Dg * d)) / (d @ S @ d)
+            assert np.linalg.norm(Dg * d - mu * (S @ d)) < 1e-10 * np.linalg.norm(Dg * d)
+
+
+def test_one_mode_per_face_at_unit_kappa_and_rt0_dim():
+    """kappa = 1 with a tolerance between lambda_0 and lambda_1 keeps one mode per face:
+    the GMsFEM space has the RT0 dimension (the model-2 tables at k2 = 1), and its coarse
+    correction equals the RT0 and MsFEM ones."""
+    g = Grid3D(12, 12, 12, 4, 4, 4)
+    os_ = [OracleSolver3D(g, np.ones(g.nc), 2.0, overlap=1, basis=bb) for bb in ("gmsfem", "msfem", "rt0")]
+    assert np.all(os_[0].counts == 1)
+    assert os_[0].dim == len(g.coarse_faces()) + 27 + 1 == os_[2].dim
+    r = os_[0].mask * np.random.default_rng(2).standard_normal(g.nf)
+    z = [o.coarse(r) for o in os_]
+    assert np.abs(z[1] - z[0]).max() < 1e-12 * np.abs(z[0]).max()
+    assert np.abs(z[2] - z[0]).max() < 1e-12 * np.abs(z[0]).max()
+
+
+def test_projection_by_dct_equals_sparse_solve():
+    g = Grid3D(5, 4, 6)
+    B = div_matrix(g).tocsr()
+    BI = B[:, g.interior_idx]
+    L = (BI @ BI.T).toarray()
+    b = np.random.default_rng(3).standard_normal(g.nc)
+    b -= b.mean()
+    q = CellLaplacian(g)(b)
+    assert np.abs(L @ q - b).max() < 1e-12 * np.abs(b).max() and abs(q.mean()) < 1e-14
+
+
+def test_twogrid_pcg_reaches_direct_solution():
+    """On 12^3 cells with 4^3 blocks and a log-normal permeability: B_TG symmetric, PCG at
+    rtol 1e-13 equals the direct solve, and B vbar = F after the preprocessing."""
+    g = Grid3D(12, 12, 12, 4, 4, 4)
+    kappa = np.exp(1.5 * np.random.default_rng(4).standard_normal(g.nc))
+    o = OracleSolver3D(g, kappa, 2.0, overlap=1)
+    rng = np.random.default_rng(5)
+    x, y = o.mask * rng.standard_normal(g.nf), o.mask * rng.standard_normal(g.nf)
+    assert abs(x @ o.twogrid(y) - y @ o.twogrid(x)) < 1e-11 * abs(x @ o.twogrid(y))
+    F = rng.standard_normal(g.nc)
+    F -= F.mean()
+    vbar, _, _ = o.preprocess(F)
+    assert np.abs(o.B @ vbar - F).max() < 1e-12 * np.abs(F).max()
+    res = o.solve(F, rtol=1e-13, maxit=300)
+    ue, pe = exact_solve(g, kappa, F)
+    assert res["iters"] < 40
+    assert np.linalg.norm(res["u"] - ue) <= 1e-10 * np.linalg.norm(ue)
+    assert np.linalg.norm(res["p"] - pe) <= 1e-10 * np.linalg.norm(pe)
