@@ -340,6 +340,64 @@ tgms_status tgms_cnn_train_step(float* params, float* adam_m, float* adam_v, int
  * tgms_update_mobility (TGMS_E_INVAL). */
 tgms_status tgms_cnn_samples(tgms_ctx* ctx, float* X, float* V);
 
+/* ---- two-phase flow by IMPES (section 6.2) ----------------------------------
+ * Quadratic relative permeabilities (k_rw = s^2, k_ro = (1 - s)^2, eqs. fraction,
+ * mobility): total mobility lambda(s) = s^2 / mu_w + (1 - s)^2 / mu_o, fractional
+ * flow f_w(s) = (s^2 / mu_w) / lambda(s).  The saturation s is the water
+ * saturation per cell (cell numbering above). */
+typedef struct {
+    double phi;         /* porosity, > 0 (0.2); the step divides by phi |cell| */
+    double mu_w, mu_o;  /* viscosities, > 0 (1, 5) */
+    double tol;         /* the step ends when max_i |R_i| <= tol (1e-12; R_i below) */
+    int max_outer;      /* tile launches per step (0: 8 (nx + ny)) */
+} tgms_transport_params;
+
+void tgms_default_transport(tgms_transport_params* prm);
+
+/* lambda = total mobility of s (n cells; device arrays; stream a hipStream_t or
+ * NULL).  TGMS_E_INVAL for n < 0 or a null pointer with n > 0. */
+tgms_status tgms_total_mobility(const double* s, long long n, const tgms_transport_params* prm, double* lambda,
+                                void* stream);
+
+/*
+ * One backward-Euler upwind finite-volume step of the saturation equation (eqs.
+ * satEq, DisSatEq_Implicit, integralFlux) on the nx x ny grid: s^{n+1} solves, for
+ * every cell i,
+ *   R_i = s_i - s_i^n - dt / (phi |c_i|) (q_i^+ - sum_sides f_w(s_up) out_i,side
+ *                                         + f_w(s_i) q_i^-) = 0,
+ * out_i,side = u_f |f| the total flux out of cell i through that side, s_up the
+ * saturation of the cell the flux leaves, q^+ = max(q, 0) injected water, q^- =
+ * min(q, 0) produced at the cell's fractional flow.  The system is triangular in
+ * flow order for a potential flow; it is solved by nonlinear Gauss-Seidel over 16 x
+ * 16 cell tiles (every cell's scalar equation by bracketed Newton on [0, 1]) until
+ * max_i |R_i| <= tol.  The solution stays in [0, 1].
+ *   u  device, nfaces doubles: total velocity (normal, full numbering; boundary
+ *      entries not read, the boundary is no-flow);
+ *   q  device, nx*ny doubles: cell-integrated sources (tgms_solve's F);
+ *   s  device, nx*ny doubles: s^n on entry, s^{n+1} on return;
+ *   outer, residual  host or NULL: tile launches used, max_i |R_i| at return.
+ * TGMS_E_INVAL for bad sizes or parameters; TGMS_E_NOTCONV when max_outer launches
+ * do not reach tol (s then holds the last iterate; tol below the rounding of the
+ * largest a_i = dt / (phi |c_i|) outflow_i cannot be reached).  Synchronises the
+ * stream (the convergence test reads the device).
+ */
+tgms_status tgms_transport_step(int nx, int ny, const double* u, const double* q, double* s, double dt,
+                                const tgms_transport_params* prm, void* stream, long long* outer, double* residual);
+
+/*
+ * The IMPES loop of section 6.2 with the context's coarse space kept: for k = 0 ..
+ * steps-1, when k % pressure_every == 0 the mobility of the current s is set
+ * (tgms_update_mobility) and the pressure equation solved (tgms_solve with F, no-flow
+ * boundary, rtol, maxit); then s takes one transport step of length dt with q = F.
+ *   F  device, nx*ny doubles (cell-integrated sources, sum 0);
+ *   s  device, nx*ny doubles: initial saturation on entry, final on return;
+ *   u  device, nfaces doubles, or NULL: the last pressure solve's velocity;
+ *   pcg_iters  host, ceil(steps / pressure_every) ints, or NULL.
+ * Runs on the context's stream; errors as in the calls it makes.
+ */
+tgms_status tgms_impes(tgms_ctx* ctx, const double* F, double* s, int steps, double dt, int pressure_every,
+                       const tgms_transport_params* prm, double rtol, int maxit, double* u, int* pcg_iters);
+
 void tgms_destroy(tgms_ctx* ctx);
 const char* tgms_last_error(void);
 

@@ -12,9 +12,9 @@ import ctypes
 
 import torch
 
-from ._lib import Grid, Info, Options, TgmsError, check, load  # noqa: F401
+from ._lib import Grid, Info, Options, TgmsError, TransportParams, check, load  # noqa: F401
 
-__all__ = ["Solver", "TgmsError", "nfaces", "trim_device_cache"]
+__all__ = ["Solver", "TgmsError", "nfaces", "total_mobility", "transport_step", "trim_device_cache"]
 
 COARSE_SPACES = {"gmsfem": 0, "msfem": 1, "rt0": 2}
 
@@ -35,6 +35,42 @@ def _ptr(t):
     if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
         raise ValueError("expected a contiguous float64 CUDA tensor")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _transport_params(**kw) -> TransportParams:
+    """tgms_transport_params with the library's defaults, overridden by kw."""
+    prm = TransportParams()
+    load().tgms_default_transport(ctypes.byref(prm))
+    for k, v in kw.items():
+        if not hasattr(prm, k):
+            raise TypeError(f"unknown transport parameter {k}")
+        setattr(prm, k, v)
+    return prm
+
+
+def total_mobility(s: torch.Tensor, **params) -> torch.Tensor:
+    """lambda(s) = s^2 / mu_w + (1 - s)^2 / mu_o per cell (tgms_total_mobility)."""
+    s = s.contiguous()
+    lam = torch.empty_like(s)
+    prm = _transport_params(**params)
+    check(load().tgms_total_mobility(_ptr(s), s.numel(), ctypes.byref(prm), _ptr(lam),
+                                     ctypes.c_void_p(torch.cuda.current_stream(s.device).cuda_stream)))
+    return lam
+
+
+def transport_step(u: torch.Tensor, q: torch.Tensor, s: torch.Tensor, dt: float, **params):
+    """One implicit upwind saturation step (tgms_transport_step) on the (ny, nx) grid of s.
+
+    Returns (s_new, tile launches, final max |R_i|); s is not modified."""
+    ny, nx = s.shape
+    s_new = s.contiguous().clone()
+    prm = _transport_params(**params)
+    outer, res = ctypes.c_longlong(0), ctypes.c_double(0.0)
+    check(load().tgms_transport_step(nx, ny, _ptr(u.contiguous()), _ptr(q.contiguous().reshape(-1)), _ptr(s_new),
+                                     float(dt), ctypes.byref(prm),
+                                     ctypes.c_void_p(torch.cuda.current_stream(s.device).cuda_stream),
+                                     ctypes.byref(outer), ctypes.byref(res)))
+    return s_new, outer.value, res.value
 
 
 class Solver:
@@ -132,6 +168,21 @@ class Solver:
         if code not in (0, -3):
             check(code)
         return {"u": u, "p": p, "iters": it.value, "relres": rel.value, "converged": converged}
+
+    def impes(self, F: torch.Tensor, s0: torch.Tensor, steps: int, dt: float, pressure_every: int = 1,
+              rtol: float = 1e-8, maxit: int = 1000, **params):
+        """Section 6.2's IMPES loop with this context's coarse space kept (tgms_impes).
+
+        Returns {"s": final saturation (ny, nx), "u": last velocity, "pcg_iters": per pressure solve}."""
+        F = F.contiguous().reshape(-1)
+        s = s0.contiguous().clone()
+        u = torch.empty(nfaces(self.nx, self.ny), dtype=torch.float64, device=self.device)
+        npres = (steps + pressure_every - 1) // pressure_every
+        its = (ctypes.c_int * max(npres, 1))()
+        prm = _transport_params(**params)
+        check(load().tgms_impes(self._h, _ptr(F), _ptr(s), int(steps), float(dt), int(pressure_every),
+                                ctypes.byref(prm), float(rtol), int(maxit), _ptr(u), ctypes.cast(its, ctypes.c_void_p)))
+        return {"s": s, "u": u, "pcg_iters": list(its)[:npres]}
 
     def update_mobility(self, lam: torch.Tensor):
         """Rebuild the operator for the total mobility lam (cells), keeping the coarse basis."""

@@ -48,6 +48,11 @@ class Info(ctypes.Structure):
                 ("by", c_int), ("precision", c_int), ("coarse_block", c_int), ("rt0_block", c_int)]
 
 
+class TransportParams(ctypes.Structure):
+    _fields_ = [("phi", c_double), ("mu_w", c_double), ("mu_o", c_double), ("tol", c_double),
+                ("max_outer", c_int)]
+
+
 _lib = None
 
 # name -> (restype, argtypes); the exported C ABI of include/tgms.h
@@ -84,6 +89,14 @@ SIGNATURES = {
     "tgms_load": (c_int, [c_char_p, ctypes.POINTER(Options), ctypes.POINTER(c_void_p)]),
     "tgms_probe_pencil": (c_int, [c_void_p, c_void_p, c_void_p]),
     "tgms_trim_device_cache": (None, []),
+    "tgms_default_transport": (None, [ctypes.POINTER(TransportParams)]),
+    "tgms_total_mobility": (c_int, [c_void_p, ctypes.c_longlong, ctypes.POINTER(TransportParams), c_void_p,
+                                    c_void_p]),
+    "tgms_transport_step": (c_int, [c_int, c_int, c_void_p, c_void_p, c_void_p, c_double,
+                                    ctypes.POINTER(TransportParams), c_void_p, ctypes.POINTER(ctypes.c_longlong),
+                                    ctypes.POINTER(c_double)]),
+    "tgms_impes": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_double, c_int, ctypes.POINTER(TransportParams),
+                           c_double, c_int, c_void_p, c_void_p]),
 }
 
 

@@ -1309,6 +1309,68 @@ void load_impl(const char* path, const tgms_options* opt, tgms_ctx** out) {
     setup_impl(&g, nullptr, h.tol, &o, out, &a);
 }
 
+
+tgms_transport_params transport_params(const tgms_transport_params* prm, int nx, int ny) {
+    tgms_transport_params t;
+    tgms_default_transport(&t);
+    if (prm) t = *prm;
+    if (!(t.phi > 0) || !(t.mu_w > 0) || !(t.mu_o > 0) || !(t.tol > 0) || t.max_outer < 0 || !std::isfinite(t.phi) ||
+        !std::isfinite(t.mu_w) || !std::isfinite(t.mu_o))
+        throw TgmsError{TGMS_E_INVAL, "transport parameters: phi, mu_w, mu_o and tol must be positive and finite"};
+    if (t.max_outer == 0) t.max_outer = 8 * (nx + ny);
+    return t;
+}
+
+tgms::TransportResult transport_checked(hipStream_t st, int nx, int ny, const double* u, const double* q, double* s,
+                                        double dt, const tgms_transport_params& t) {
+    if (nx < 1 || ny < 1 || !u || !q || !s) throw TgmsError{TGMS_E_INVAL, "transport: bad sizes or null argument"};
+    if (!(dt > 0) || !std::isfinite(dt)) throw TgmsError{TGMS_E_INVAL, "transport: dt must be positive"};
+    return tgms::transport_step(st, nx, ny, u, q, s, t.phi, dt, t.mu_w, t.mu_o, t.tol, t.max_outer);
+}
+
+void impes_impl(tgms_ctx* c, const double* F, double* s, int steps, double dt, int pressure_every,
+                const tgms_transport_params* prm, double rtol, int maxit, double* u, int* pcg_iters,
+                tgms_status* st) {
+    if (!c || !F || !s) throw TgmsError{TGMS_E_INVAL, "null argument"};
+    if (steps < 0 || pressure_every < 1) throw TgmsError{TGMS_E_INVAL, "steps >= 0 and pressure_every >= 1"};
+    const tgms_transport_params t = transport_params(prm, c->nx, c->ny);
+    tgms::enter(c);
+    const long long nc = (long long)c->nx * c->ny;
+    size_t got = 0;
+    const size_t bytes = sizeof(double) * ((size_t)c->nf + 2 * (size_t)nc);
+    double* w = (double*)tgms::dev_alloc(bytes, &got);
+    struct Free {
+        double* p;
+        size_t b;
+        hipStream_t st;
+        ~Free() {
+            (void)hipStreamSynchronize(st);
+            tgms::dev_free(p, b);
+        }
+    } fr{w, got, c->stream};
+    double* uu = u ? u : w;
+    double* lam = w + c->nf;
+    double* pp = lam + nc;
+    int np = 0;
+    for (int k = 0; k < steps; ++k) {
+        if (k % pressure_every == 0) {
+            tgms::total_mobility(c->stream, s, nc, t.mu_w, t.mu_o, lam);
+            update_mobility_impl(c, lam);
+            int it = 0;
+            double rr = 0.0;
+            tgms_status sst = TGMS_OK;
+            solve_impl(c, F, nullptr, rtol, maxit, uu, pp, &it, &rr, &sst);
+            if (pcg_iters) pcg_iters[np] = it;
+            ++np;
+            if (sst != TGMS_OK) {
+                *st = sst;
+                return;
+            }
+        }
+        const tgms::TransportResult r = transport_checked(c->stream, c->nx, c->ny, uu, F, s, dt, t);
+        if (!r.converged) throw TgmsError{TGMS_E_NOTCONV, "transport: the step did not converge within max_outer"};
+    }
+}
 }  // namespace
 
 // ---------------------------------------------------------------- C ABI
@@ -1679,6 +1741,48 @@ tgms_status tgms_profile_get(tgms_ctx* c, int kernel, int* launches, double* tot
         *launches = n;
         *total_ms = t;
     });
+}
+
+void tgms_default_transport(tgms_transport_params* prm) {
+    if (!prm) return;
+    prm->phi = 0.2;
+    prm->mu_w = 1.0;
+    prm->mu_o = 5.0;
+    prm->tol = 1e-12;
+    prm->max_outer = 0;
+}
+
+tgms_status tgms_total_mobility(const double* s, long long n, const tgms_transport_params* prm, double* lambda,
+                                void* stream) {
+    return guarded([&] {
+        if (n < 0 || (n > 0 && (!s || !lambda))) throw TgmsError{TGMS_E_INVAL, "bad size or null argument"};
+        const tgms_transport_params t = transport_params(prm, 1, 1);
+        if (n > 0) tgms::total_mobility((hipStream_t)stream, s, n, t.mu_w, t.mu_o, lambda);
+    });
+}
+
+tgms_status tgms_transport_step(int nx, int ny, const double* u, const double* q, double* s, double dt,
+                                const tgms_transport_params* prm, void* stream, long long* outer, double* residual) {
+    tgms_status st = TGMS_OK;
+    tgms_status r = guarded([&] {
+        const tgms_transport_params t = transport_params(prm, nx, ny);
+        const tgms::TransportResult res = transport_checked((hipStream_t)stream, nx, ny, u, q, s, dt, t);
+        if (outer) *outer = res.sweeps;
+        if (residual) *residual = res.residual;
+        if (!res.converged) {
+            g_last_error = "transport: the step did not converge within max_outer";
+            st = TGMS_E_NOTCONV;
+        }
+    });
+    return r != TGMS_OK ? r : st;
+}
+
+tgms_status tgms_impes(tgms_ctx* ctx, const double* F, double* s, int steps, double dt, int pressure_every,
+                       const tgms_transport_params* prm, double rtol, int maxit, double* u, int* pcg_iters) {
+    tgms_status st = TGMS_OK;
+    tgms_status r =
+        guarded([&] { impes_impl(ctx, F, s, steps, dt, pressure_every, prm, rtol, maxit, u, pcg_iters, &st); });
+    return r != TGMS_OK ? r : st;
 }
 
 void tgms_destroy(tgms_ctx* c) {

@@ -485,4 +485,13 @@ void gemm(tgms_ctx* c, int transA, int transB, int M, int N, int K, double alpha
 void preprocess(tgms_ctx* c, const double* F, const double* g_bnd, double* vbar, double* Fp);
 void pressure(tgms_ctx* c, const double* u, double* p);
 void dct_matrix(tgms_ctx* c, int n, double* Q, double* lam);  // orthonormal DCT-II and Neumann eigenvalues
+// two-phase transport (k_transport.hip)
+struct TransportResult {
+    long long sweeps = 0;   // outer (tile) launches
+    double residual = 0.0;  // max_i |R_i| at return
+    bool converged = false;
+};
+void total_mobility(hipStream_t st, const double* s, long long n, double mu_w, double mu_o, double* lam);
+TransportResult transport_step(hipStream_t st, int nx, int ny, const double* u, const double* q, double* s, double phi,
+                               double dt, double mu_w, double mu_o, double tol, int max_outer);
 }  // namespace tgms

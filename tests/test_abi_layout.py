@@ -1,7 +1,7 @@
 """The ctypes structures of the Python binding match the C layout of include/tgms.h (CPU only).
 
 A small C program (gcc) prints sizeof and offsetof of every field of tgms_grid,
-tgms_options and tgms_info_t; the binding's ctypes structures must agree.
+tgms_options, tgms_info_t and tgms_transport_params; the binding's ctypes structures must agree.
 """
 import os
 import shutil
@@ -16,7 +16,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 @pytest.mark.skipif(shutil.which("gcc") is None, reason="no C compiler")
 def test_struct_layouts_match_header():
     from paper_1807_07220_amd import _lib
-    structs = {"tgms_grid": _lib.Grid, "tgms_options": _lib.Options, "tgms_info_t": _lib.Info}
+    structs = {"tgms_grid": _lib.Grid, "tgms_options": _lib.Options, "tgms_info_t": _lib.Info,
+               "tgms_transport_params": _lib.TransportParams}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tgms.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
