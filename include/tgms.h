@@ -54,9 +54,10 @@ typedef enum {
 } tgms_status;
 
 typedef struct {
-    int dim;          /* 2 (the unit square); 3 returns TGMS_E_UNSUPPORTED (not implemented) */
+    int dim;          /* 2 (the unit square) or 3 (the unit cube, see below) */
     int nx, ny, nz;   /* fine cells per axis (nz: 0 or 1 when dim = 2) */
-    int bx, by, bz;   /* coarse block size in fine cells; nx % bx == 0, ny % by == 0 (bz: 0 or 1) */
+    int bx, by, bz;   /* coarse block size in fine cells; nx % bx == 0, ny % by == 0 (bz: 0 or 1
+                         when dim = 2, nz % bz == 0 when dim = 3) */
 } tgms_grid;
 
 typedef struct {
@@ -169,6 +170,22 @@ void tgms_default_options(tgms_options* opt);
  * blocks, an overlap not smaller than the block, blocks wider than 64 cells or
  * smoother patches (block + 2 overlap, clipped to D) wider than 33 cells.
  * On success *out owns all device workspaces until tgms_destroy.
+ *
+ * The unit cube (dim = 3; the paper's models 2 and 3): cells (i, j, k) index
+ * (k ny + j) nx + i; faces x ((k ny + j)(nx + 1) + i), then y ((k (ny + 1) + j) nx
+ * + i), then z ((k ny + j) nx + i); kappa and F have nx ny nz entries.  Local
+ * problems are solved through their pressure Schur complement (line-tridiagonal
+ * A^{-1}, a dense inverse per block and per patch), the coarse problem through a
+ * dense solution operator; PCG runs on the face vectors.  Supported: FP64
+ * (precision 0), no warm start, one pre- and one post-smoothing (smooth_steps 1,
+ * additive 0), no-flow boundary (g_bnd NULL), at least 2 blocks per axis, an
+ * overlap of at most the block size, patches of at most 32 cells per axis, at most
+ * 64 fine faces per coarse face; coarse_space 0, 1 and 2.  tgms_solve,
+ * tgms_update_mobility, tgms_impes, tgms_info, tgms_get_counts, tgms_get_eigs,
+ * tgms_last_cond, tgms_apply_A, tgms_preprocess and tgms_apply_precond accept such
+ * a context; the other calls that take a context return TGMS_E_UNSUPPORTED for it.
+ * Coarse faces are ordered x, y, z, each by (K, J, I) of the block on the face's
+ * high side; the fine faces of a coarse face with the lower tangential axis fastest.
  */
 tgms_status tgms_setup(const tgms_grid* grid, const double* kappa, double eig_tol,
                        const tgms_options* opt, tgms_ctx** out);
@@ -256,7 +273,8 @@ void tgms_trim_device_cache(void);
 
 /* Basis counts l_i (host, n_coarse_faces ints) and all eigenvalues lambda of
  * each local spectral problem, ascending (host, n_coarse_faces * jmax doubles,
- * jmax = max(bx, by); rows of faces with fewer fine faces are padded with 0).
+ * jmax = max(bx, by), on the cube the most fine faces of a coarse face; rows of faces
+ * with fewer fine faces are padded with 0).
  * Coarse faces are ordered: x-faces (block row J, I = 1..Nx-1), then y-faces
  * (J = 1..Ny-1, block column I). */
 tgms_status tgms_get_counts(const tgms_ctx* ctx, int* counts);
@@ -349,7 +367,7 @@ typedef struct {
     double phi;         /* porosity, > 0 (0.2); the step divides by phi |cell| */
     double mu_w, mu_o;  /* viscosities, > 0 (1, 5) */
     double tol;         /* the step ends when max_i |R_i| <= tol (1e-12; R_i below) */
-    int max_outer;      /* tile launches per step (0: 8 (nx + ny)) */
+    int max_outer;      /* tile launches per step (0: 8 (nx + ny + nz)) */
 } tgms_transport_params;
 
 void tgms_default_transport(tgms_transport_params* prm);
@@ -361,16 +379,17 @@ tgms_status tgms_total_mobility(const double* s, long long n, const tgms_transpo
 
 /*
  * One backward-Euler upwind finite-volume step of the saturation equation (eqs.
- * satEq, DisSatEq_Implicit, integralFlux) on the nx x ny grid: s^{n+1} solves, for
- * every cell i,
+ * satEq, DisSatEq_Implicit, integralFlux) on the nx x ny grid of the square (nz 0 or
+ * 1) or the nx x ny x nz grid of the cube (cell and face numbering of tgms_setup for
+ * that dimension): s^{n+1} solves, for every cell i,
  *   R_i = s_i - s_i^n - dt / (phi |c_i|) (q_i^+ - sum_sides f_w(s_up) out_i,side
  *                                         + f_w(s_i) q_i^-) = 0,
  * out_i,side = u_f |f| the total flux out of cell i through that side, s_up the
  * saturation of the cell the flux leaves, q^+ = max(q, 0) injected water, q^- =
  * min(q, 0) produced at the cell's fractional flow.  The system is triangular in
  * flow order for a potential flow; it is solved by nonlinear Gauss-Seidel over 16 x
- * 16 cell tiles (every cell's scalar equation by bracketed Newton on [0, 1]) until
- * max_i |R_i| <= tol.  The solution stays in [0, 1].
+ * 16 (cube: 8 x 8 x 4) cell tiles (every cell's scalar equation by bracketed Newton on
+ * [0, 1]) until max_i |R_i| <= tol.  The solution stays in [0, 1].
  *   u  device, nfaces doubles: total velocity (normal, full numbering; boundary
  *      entries not read, the boundary is no-flow);
  *   q  device, nx*ny doubles: cell-integrated sources (tgms_solve's F);
@@ -381,7 +400,7 @@ tgms_status tgms_total_mobility(const double* s, long long n, const tgms_transpo
  * largest a_i = dt / (phi |c_i|) outflow_i cannot be reached).  Synchronises the
  * stream (the convergence test reads the device).
  */
-tgms_status tgms_transport_step(int nx, int ny, const double* u, const double* q, double* s, double dt,
+tgms_status tgms_transport_step(int nx, int ny, int nz, const double* u, const double* q, double* s, double dt,
                                 const tgms_transport_params* prm, void* stream, long long* outer, double* residual);
 
 /*

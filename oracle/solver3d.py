@@ -185,6 +185,22 @@ class OracleSolver3D(OracleSolver):
         self.patches = [BorderedSaddle(self.A, self.B, g.faces_in(*g.block_box(I, self.overlap)),
                                        g.cells_in(*g.block_box(I, self.overlap))) for I in g.blocks()]
 
+    def update_mobility(self, lam):
+        """The mobility update of section 6.2 with the basis kept, on the cube: A from
+        kappa^{-1} / lam, the coarse operator over the same Phi, the blocks and the smoother
+        patches factorised again (OracleSolver.update_mobility in three dimensions)."""
+        g = self.g
+        lam = np.asarray(lam, dtype=np.float64).ravel()
+        if lam.size != g.nc or not np.all(np.isfinite(lam)) or np.any(lam <= 0):
+            raise ValueError("mobility must be finite and positive on every cell")
+        self.A = mass_matrix(g, self.kinv / lam).tocsr()
+        AH = (self.Phi.T @ self.A @ self.Phi).toarray()
+        BH = (self.RQ @ self.B @ self.Phi).toarray()
+        self.coarse_lu, self.nH, self.mH = bordered_dense_or_sparse(AH, BH)
+        self._blocks = {}
+        self.patches = [BorderedSaddle(self.A, self.B, g.faces_in(*g.block_box(I, self.overlap)),
+                                       g.cells_in(*g.block_box(I, self.overlap))) for I in g.blocks()]
+
     def block(self, I) -> BorderedSaddle:
         """L_K = R_K L R_K^T on coarse block K (faces strictly inside K, cells of K)."""
         I = tuple(I)

@@ -43,14 +43,29 @@ def fractional_flow(s, mu_w=1.0, mu_o=5.0):
 
 
 def face_fluxes(g, u_full):
-    """Per cell and side (W, E, S, N) the total flux out of the cell and the neighbour
-    across that side (-1 at the boundary of D, where the no-flow flux is 0)."""
+    """Per cell and side (W, E, S, N; on the cube also bottom, top) the total flux out of
+    the cell and the neighbour across that side (-1 at the boundary of D, where the
+    no-flow flux is 0)."""
+    u = np.asarray(u_full)
+    if hasattr(g, "nz"):
+        nx, ny, nz = g.n
+        I, J, K = (a.ravel() for a in g._mesh(nx, ny, nz))
+        out = np.zeros((g.nc, 6))
+        nb = -np.ones((g.nc, 6), dtype=np.int64)
+        area = [g.cell_vol / h for h in g.h]
+        for a, (di, dj, dk) in enumerate(((1, 0, 0), (0, 1, 0), (0, 0, 1))):
+            out[:, 2 * a] = -u[g.face(a, I, J, K)] * area[a]
+            out[:, 2 * a + 1] = u[g.face(a, I + di, J + dj, K + dk)] * area[a]
+            pos = (I, J, K)[a]
+            nb[:, 2 * a] = np.where(pos > 0, g.cell(I - di, J - dj, K - dk), -1)
+            nb[:, 2 * a + 1] = np.where(pos < g.n[a] - 1, g.cell(I + di, J + dj, K + dk), -1)
+        out[nb < 0] = 0.0
+        return out, nb
     nx, ny = g.nx, g.ny
     J, I = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
     I, J = I.ravel(), J.ravel()
     out = np.zeros((g.nc, 4))
     nb = -np.ones((g.nc, 4), dtype=np.int64)
-    u = np.asarray(u_full)
     out[:, 0] = -u[g.xf(I, J)] * g.hy
     out[:, 1] = u[g.xf(I + 1, J)] * g.hy
     out[:, 2] = -u[g.yf(I, J)] * g.hx
@@ -76,7 +91,7 @@ def transport_jacobian(s, out, nb, q, coef, mu_w, mu_o) -> sp.csr_matrix:
     n = s.size
     diag = 1.0 + coef * (np.sum(np.where(out > 0.0, out, 0.0), axis=1) - np.minimum(q, 0.0)) * df
     rows, cols, vals = [np.arange(n)], [np.arange(n)], [diag]
-    for k in range(4):
+    for k in range(out.shape[1]):
         m = (out[:, k] < 0.0) & (nb[:, k] >= 0)
         i = np.flatnonzero(m)
         j = nb[i, k]
@@ -93,7 +108,7 @@ def transport_step(g, u_full, q, s, dt, phi=0.2, mu_w=1.0, mu_o=5.0, newton_tol=
     clip to [0, 1]."""
     out, nb = face_fluxes(g, u_full)
     q = np.asarray(q, dtype=np.float64).ravel()
-    coef = dt / (phi * g.cell_area)
+    coef = dt / (phi * (g.cell_vol if hasattr(g, "nz") else g.cell_area))
     s_old = np.asarray(s, dtype=np.float64).ravel().copy()
     s = s_old.copy()
     for it in range(max_newton + 1):

@@ -24,9 +24,12 @@ def trim_device_cache():
     load().tgms_trim_device_cache()
 
 
-def nfaces(nx: int, ny: int) -> int:
-    """Length of a full face array: (nx+1)*ny x-faces then nx*(ny+1) y-faces."""
-    return (nx + 1) * ny + nx * (ny + 1)
+def nfaces(nx: int, ny: int, nz: int | None = None) -> int:
+    """Length of a full face array: (nx+1)*ny x-faces then nx*(ny+1) y-faces (the square),
+    or x-, y- and z-faces of the nx x ny x nz cube."""
+    if nz is None:
+        return (nx + 1) * ny + nx * (ny + 1)
+    return (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1)
 
 
 def _ptr(t):
@@ -59,14 +62,15 @@ def total_mobility(s: torch.Tensor, **params) -> torch.Tensor:
 
 
 def transport_step(u: torch.Tensor, q: torch.Tensor, s: torch.Tensor, dt: float, **params):
-    """One implicit upwind saturation step (tgms_transport_step) on the (ny, nx) grid of s.
+    """One implicit upwind saturation step (tgms_transport_step) on the (ny, nx) grid of s
+    (or the (nz, ny, nx) grid of the cube).
 
     Returns (s_new, tile launches, final max |R_i|); s is not modified."""
-    ny, nx = s.shape
+    nz, ny, nx = s.shape if s.dim() == 3 else (1, *s.shape)
     s_new = s.contiguous().clone()
     prm = _transport_params(**params)
     outer, res = ctypes.c_longlong(0), ctypes.c_double(0.0)
-    check(load().tgms_transport_step(nx, ny, _ptr(u.contiguous()), _ptr(q.contiguous().reshape(-1)), _ptr(s_new),
+    check(load().tgms_transport_step(nx, ny, nz if s.dim() == 3 else 1, _ptr(u.contiguous()), _ptr(q.contiguous().reshape(-1)), _ptr(s_new),
                                      float(dt), ctypes.byref(prm),
                                      ctypes.c_void_p(torch.cuda.current_stream(s.device).cuda_stream),
                                      ctypes.byref(outer), ctypes.byref(res)))
@@ -82,10 +86,12 @@ class Solver:
                  warm_start: str = "exact", cnn_weights: torch.Tensor | None = None, rq_tol: float = 1e-6,
                  smoother_staging: int = -1, rows_per_thread: int = 0, force_counts=None,
                  coarse_space: str = "gmsfem", coarse_factor: str = "auto", smooth_steps: int = 1,
-                 additive: bool = False, _restore: str | None = None):
+                 additive: bool = False, bz: int | None = None, _restore: str | None = None):
         lib = load()
-        if kappa is not None and kappa.dim() != 2:
-            raise ValueError("kappa must be (ny, nx)")
+        if kappa is not None and kappa.dim() not in (2, 3):
+            raise ValueError("kappa must be (ny, nx) or (nz, ny, nx)")
+        self.dim = 3 if kappa is not None and kappa.dim() == 3 else 2
+        self.nz, self.bz = 1, 1
         self.device = kappa.device if kappa is not None else torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         opt = Options()
@@ -109,7 +115,13 @@ class Solver:
             self._h = handle
             self._from_info()
             return
-        self.ny, self.nx = kappa.shape
+        if self.dim == 3:
+            self.nz, self.ny, self.nx = kappa.shape
+            if bz is None:
+                raise ValueError("a cube needs bz")
+            self.bz = int(bz)
+        else:
+            self.ny, self.nx = kappa.shape
         self.bx, self.by = int(bx), int(by)
         if force_counts is not None:
             import numpy as np
@@ -121,7 +133,7 @@ class Solver:
                 raise ValueError("cnn_weights must be a contiguous float32 CUDA tensor")
             opt.cnn_weights = ctypes.c_void_p(cnn_weights.data_ptr())
         opt.rq_tol = float(rq_tol)
-        grid = Grid(2, self.nx, self.ny, 1, self.bx, self.by, 1)
+        grid = Grid(self.dim, self.nx, self.ny, self.nz, self.bx, self.by, self.bz)
         handle = ctypes.c_void_p()
         kappa = kappa.contiguous()
         check(lib.tgms_setup(ctypes.byref(grid), _ptr(kappa), float(eig_tol), ctypes.byref(opt),
@@ -135,6 +147,14 @@ class Solver:
         """Restore a context written by save() (tgms_load): the coarse space is read, not solved for."""
         return cls(None, 0, 0, 0.0, stream=stream, graphs=graphs, autotune=autotune, tune_cache=tune_cache,
                    smoother_staging=smoother_staging, rows_per_thread=rows_per_thread, _restore=path)
+
+    @property
+    def ncells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def nfaces(self) -> int:
+        return nfaces(self.nx, self.ny, self.nz if self.dim == 3 else None)
 
     def _from_info(self):
         inf = self.info()
@@ -159,8 +179,8 @@ class Solver:
               pressure: bool = True):
         lib = load()
         F = F.contiguous().reshape(-1)
-        u = torch.empty(nfaces(self.nx, self.ny), dtype=torch.float64, device=self.device)
-        p = torch.empty(self.nx * self.ny, dtype=torch.float64, device=self.device) if pressure else None
+        u = torch.empty(self.nfaces, dtype=torch.float64, device=self.device)
+        p = torch.empty(self.ncells, dtype=torch.float64, device=self.device) if pressure else None
         it, rel = ctypes.c_int(0), ctypes.c_double(0.0)
         code = lib.tgms_solve(self._h, _ptr(F), _ptr(g), float(rtol), int(maxit), _ptr(u), _ptr(p),
                               ctypes.byref(it), ctypes.byref(rel))
@@ -176,7 +196,7 @@ class Solver:
         Returns {"s": final saturation (ny, nx), "u": last velocity, "pcg_iters": per pressure solve}."""
         F = F.contiguous().reshape(-1)
         s = s0.contiguous().clone()
-        u = torch.empty(nfaces(self.nx, self.ny), dtype=torch.float64, device=self.device)
+        u = torch.empty(self.nfaces, dtype=torch.float64, device=self.device)
         npres = (steps + pressure_every - 1) // pressure_every
         its = (ctypes.c_int * max(npres, 1))()
         prm = _transport_params(**params)
@@ -187,8 +207,8 @@ class Solver:
     def update_mobility(self, lam: torch.Tensor):
         """Rebuild the operator for the total mobility lam (cells), keeping the coarse basis."""
         lam = lam.contiguous().reshape(-1)
-        if lam.numel() != self.nx * self.ny or lam.dtype != torch.float64:
-            raise ValueError("mobility must be an (ny, nx) float64 field")
+        if lam.numel() != self.ncells or lam.dtype != torch.float64:
+            raise ValueError("mobility must be a float64 field of one value per cell")
         check(load().tgms_update_mobility(self._h, _ptr(lam)))
 
     def info(self) -> dict:
@@ -222,7 +242,8 @@ class Solver:
     def eigs(self):
         import numpy as np
         n = self.info()["n_coarse_faces"]
-        out = np.zeros((n, max(self.bx, self.by)), dtype=np.float64)
+        jm = max(self.bx, self.by) if self.dim == 2 else max(self.by * self.bz, self.bx * self.bz, self.bx * self.by)
+        out = np.zeros((n, jm), dtype=np.float64)
         check(load().tgms_get_eigs(self._h, out.ctypes.data_as(ctypes.c_void_p)))
         return out
 
@@ -263,7 +284,7 @@ class Solver:
         return y
 
     def preprocess(self, F: torch.Tensor, g: torch.Tensor | None = None) -> torch.Tensor:
-        v = torch.empty(nfaces(self.nx, self.ny), dtype=torch.float64, device=self.device)
+        v = torch.empty(self.nfaces, dtype=torch.float64, device=self.device)
         check(load().tgms_preprocess(self._h, _ptr(F.contiguous().reshape(-1)), _ptr(g), _ptr(v)))
         return v
 

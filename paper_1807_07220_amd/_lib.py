@@ -92,7 +92,7 @@ SIGNATURES = {
     "tgms_default_transport": (None, [ctypes.POINTER(TransportParams)]),
     "tgms_total_mobility": (c_int, [c_void_p, ctypes.c_longlong, ctypes.POINTER(TransportParams), c_void_p,
                                     c_void_p]),
-    "tgms_transport_step": (c_int, [c_int, c_int, c_void_p, c_void_p, c_void_p, c_double,
+    "tgms_transport_step": (c_int, [c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_double,
                                     ctypes.POINTER(TransportParams), c_void_p, ctypes.POINTER(ctypes.c_longlong),
                                     ctypes.POINTER(c_double)]),
     "tgms_impes": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_double, c_int, ctypes.POINTER(TransportParams),

@@ -17,6 +17,7 @@
 #include <string>
 
 #include "common.h"
+#include "d3.h"
 #include "band.h"
 #include "patch.h"
 
@@ -575,7 +576,22 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
     tgms_options o;
     tgms_default_options(&o);
     if (opt) o = *opt;
-    if (grid->dim == 3) throw TgmsError{TGMS_E_UNSUPPORTED, "three-dimensional grids are not implemented"};
+    if (grid->dim == 3) {
+        if (art) throw TgmsError{TGMS_E_UNSUPPORTED, "saved contexts are two-dimensional"};
+        auto* c = new tgms_ctx();
+        try {
+            c->user_stream = (hipStream_t)o.stream;
+            HIP_OK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+            HIP_OK(hipEventCreateWithFlags(&c->ev_enter, hipEventDisableTiming));
+            tgms::enter(c);
+            tgms3::setup3(c, grid, kappa, eig_tol, &o);
+        } catch (...) {
+            tgms_destroy(c);
+            throw;
+        }
+        *out = c;
+        return;
+    }
     if (grid->dim != 2 || grid->nz > 1 || grid->bz > 1)
         throw TgmsError{TGMS_E_INVAL, "dim must be 2 (with nz and bz 0 or 1)"};
     const int nx = grid->nx, ny = grid->ny, bx = grid->bx, by = grid->by;
@@ -979,6 +995,10 @@ void rebuild_operator(tgms_ctx* c) {
 void update_mobility_impl(tgms_ctx* c, const double* lambda) {
     if (!c || !lambda) throw TgmsError{TGMS_E_INVAL, "null argument"};
     tgms::enter(c);
+    if (c->dim == 3) {
+        tgms3::update_mobility3(c, lambda);
+        return;
+    }
     // the new weights go to a scratch array first: an invalid field leaves the context as it was
     int* bad = c->alloc_scratch_int();
     tgms::mobility_weights(c, lambda, bad, c->cellw2);
@@ -997,6 +1017,13 @@ void solve_impl(tgms_ctx* c, const double* F, const double* g_bnd, double rtol, 
     if (!c || !F || !u) throw TgmsError{TGMS_E_INVAL, "null argument"};
     if (!(rtol >= 0) || maxit < 0) throw TgmsError{TGMS_E_INVAL, "bad rtol or maxit"};
     tgms::enter(c);
+    if (c->dim == 3) {
+        if (g_bnd) throw TgmsError{TGMS_E_UNSUPPORTED, "on the cube only the no-flow boundary (g_bnd NULL)"};
+        tgms3::solve3(c, F, rtol, maxit, u, p, iters, relres, st);
+        if (*st == TGMS_E_NOTCONV) g_last_error = "PCG did not converge within maxit";
+        if (*st == TGMS_E_BREAKDOWN) g_last_error = "PCG breakdown";
+        return;
+    }
     const long long nv = (long long)c->nx * c->ny;
     // Step 1: preprocessing
     tgms::preprocess(c, F, g_bnd, c->fbar, c->cellw2);
@@ -1310,22 +1337,22 @@ void load_impl(const char* path, const tgms_options* opt, tgms_ctx** out) {
 }
 
 
-tgms_transport_params transport_params(const tgms_transport_params* prm, int nx, int ny) {
+tgms_transport_params transport_params(const tgms_transport_params* prm, int nx, int ny, int nz) {
     tgms_transport_params t;
     tgms_default_transport(&t);
     if (prm) t = *prm;
     if (!(t.phi > 0) || !(t.mu_w > 0) || !(t.mu_o > 0) || !(t.tol > 0) || t.max_outer < 0 || !std::isfinite(t.phi) ||
         !std::isfinite(t.mu_w) || !std::isfinite(t.mu_o))
         throw TgmsError{TGMS_E_INVAL, "transport parameters: phi, mu_w, mu_o and tol must be positive and finite"};
-    if (t.max_outer == 0) t.max_outer = 8 * (nx + ny);
+    if (t.max_outer == 0) t.max_outer = 8 * (nx + ny + std::max(nz, 1));
     return t;
 }
 
-tgms::TransportResult transport_checked(hipStream_t st, int nx, int ny, const double* u, const double* q, double* s,
-                                        double dt, const tgms_transport_params& t) {
-    if (nx < 1 || ny < 1 || !u || !q || !s) throw TgmsError{TGMS_E_INVAL, "transport: bad sizes or null argument"};
+tgms::TransportResult transport_checked(hipStream_t st, int nx, int ny, int nz, const double* u, const double* q,
+                                        double* s, double dt, const tgms_transport_params& t) {
+    if (nx < 1 || ny < 1 || nz < 0 || !u || !q || !s) throw TgmsError{TGMS_E_INVAL, "transport: bad sizes or null argument"};
     if (!(dt > 0) || !std::isfinite(dt)) throw TgmsError{TGMS_E_INVAL, "transport: dt must be positive"};
-    return tgms::transport_step(st, nx, ny, u, q, s, t.phi, dt, t.mu_w, t.mu_o, t.tol, t.max_outer);
+    return tgms::transport_step(st, nx, ny, nz, u, q, s, t.phi, dt, t.mu_w, t.mu_o, t.tol, t.max_outer);
 }
 
 void impes_impl(tgms_ctx* c, const double* F, double* s, int steps, double dt, int pressure_every,
@@ -1333,11 +1360,13 @@ void impes_impl(tgms_ctx* c, const double* F, double* s, int steps, double dt, i
                 tgms_status* st) {
     if (!c || !F || !s) throw TgmsError{TGMS_E_INVAL, "null argument"};
     if (steps < 0 || pressure_every < 1) throw TgmsError{TGMS_E_INVAL, "steps >= 0 and pressure_every >= 1"};
-    const tgms_transport_params t = transport_params(prm, c->nx, c->ny);
+    const int nz = c->dim == 3 ? c->d3->g.n[2] : 1;
+    const tgms_transport_params t = transport_params(prm, c->nx, c->ny, nz);
     tgms::enter(c);
-    const long long nc = (long long)c->nx * c->ny;
+    const long long nc = (long long)c->nx * c->ny * nz;
+    const long long nfaces = c->dim == 3 ? c->d3->g.nf : (long long)c->nf;
     size_t got = 0;
-    const size_t bytes = sizeof(double) * ((size_t)c->nf + 2 * (size_t)nc);
+    const size_t bytes = sizeof(double) * ((size_t)nfaces + 2 * (size_t)nc);
     double* w = (double*)tgms::dev_alloc(bytes, &got);
     struct Free {
         double* p;
@@ -1349,7 +1378,7 @@ void impes_impl(tgms_ctx* c, const double* F, double* s, int steps, double dt, i
         }
     } fr{w, got, c->stream};
     double* uu = u ? u : w;
-    double* lam = w + c->nf;
+    double* lam = w + nfaces;
     double* pp = lam + nc;
     int np = 0;
     for (int k = 0; k < steps; ++k) {
@@ -1367,7 +1396,7 @@ void impes_impl(tgms_ctx* c, const double* F, double* s, int steps, double dt, i
                 return;
             }
         }
-        const tgms::TransportResult r = transport_checked(c->stream, c->nx, c->ny, uu, F, s, dt, t);
+        const tgms::TransportResult r = transport_checked(c->stream, c->nx, c->ny, nz, uu, F, s, dt, t);
         if (!r.converged) throw TgmsError{TGMS_E_NOTCONV, "transport: the step did not converge within max_outer"};
     }
 }
@@ -1413,6 +1442,10 @@ tgms_status tgms_solve(tgms_ctx* ctx, const double* F, const double* g_bnd, doub
 
 tgms_status tgms_solve_noalloc(tgms_ctx* ctx, const double* F, const double* g_bnd, double rtol, int maxit,
                                double* u, double* p, int* iters, double* relres) {
+    if (ctx && ctx->dim == 3) {
+        g_last_error = "solve_noalloc: not available on the cube";
+        return TGMS_E_UNSUPPORTED;
+    }
     tgms_status st = TGMS_OK;
     tgms_status r = guarded([&] { solve_noalloc_impl(ctx, F, g_bnd, rtol, maxit, u, p, iters, relres, &st); });
     return r != TGMS_OK ? r : st;
@@ -1460,6 +1493,10 @@ tgms_status tgms_info(const tgms_ctx* c, tgms_info_t* info) {
 }
 
 tgms_status tgms_probe_pencil(tgms_ctx* c, double* D, double* S) {
+    if (c && c->dim == 3) {
+        g_last_error = "probe_pencil: not available on the cube";
+        return TGMS_E_UNSUPPORTED;
+    }
     if (!c || !D || !S) {
         g_last_error = "null argument";
         return TGMS_E_INVAL;
@@ -1486,6 +1523,10 @@ void tgms_trim_device_cache(void) {
 }
 
 tgms_status tgms_save(const tgms_ctx* c, const char* path) {
+    if (c && c->dim == 3) {
+        g_last_error = "save: not available on the cube";
+        return TGMS_E_UNSUPPORTED;
+    }
     if (!c || !path) {
         g_last_error = "null argument";
         return TGMS_E_INVAL;
@@ -1559,6 +1600,10 @@ tgms_status tgms_cnn_train_step(float* params, float* adam_m, float* adam_v, int
 }
 
 tgms_status tgms_cnn_samples(tgms_ctx* c, float* X, float* V) {
+    if (c && c->dim == 3) {
+        g_last_error = "cnn_samples: not available on the cube";
+        return TGMS_E_UNSUPPORTED;
+    }
     if (!c || !X || !V) {
         g_last_error = "null argument";
         return TGMS_E_INVAL;
@@ -1626,6 +1671,10 @@ tgms_status tgms_get_eigs(const tgms_ctx* c, double* eigs) {
         g_last_error = "null argument";
         return TGMS_E_INVAL;
     }
+    if (c->dim == 3) {
+        std::copy(c->d3->eigs_h.begin(), c->d3->eigs_h.end(), eigs);
+        return TGMS_OK;
+    }
     return guarded([&] {
         HIP_OK(hipMemcpyAsync(eigs, c->eigs, sizeof(double) * c->ne * c->jmax, hipMemcpyDeviceToHost, c->stream));
         HIP_OK(hipStreamSynchronize(c->stream));
@@ -1642,6 +1691,10 @@ tgms_status tgms_last_cond(const tgms_ctx* c, double* cond) {
 }
 
 tgms_status tgms_profile(tgms_ctx* c, int enable) {
+    if (c && c->dim == 3) {
+        g_last_error = "profile: not available on the cube";
+        return TGMS_E_UNSUPPORTED;
+    }
     if (!c) {
         g_last_error = "null argument";
         return TGMS_E_INVAL;
@@ -1659,6 +1712,10 @@ tgms_status tgms_profile(tgms_ctx* c, int enable) {
 }
 
 tgms_status tgms_time_smoother(tgms_ctx* c, int reps, double* avg_ms) {
+    if (c && c->dim == 3) {
+        g_last_error = "time_smoother: not available on the cube";
+        return TGMS_E_UNSUPPORTED;
+    }
     if (!c || !avg_ms || reps < 1 || reps > 100000) {
         g_last_error = "bad argument";
         return TGMS_E_INVAL;
@@ -1691,6 +1748,10 @@ tgms_status tgms_time_smoother(tgms_ctx* c, int reps, double* avg_ms) {
 }
 
 tgms_status tgms_time_dir_apply(tgms_ctx* c, int reps, double* avg_ms) {
+    if (c && c->dim == 3) {
+        g_last_error = "time_dir_apply: not available on the cube";
+        return TGMS_E_UNSUPPORTED;
+    }
     if (!c || !avg_ms || reps < 1 || reps > 100000) {
         g_last_error = "bad argument";
         return TGMS_E_INVAL;
@@ -1723,6 +1784,10 @@ tgms_status tgms_time_dir_apply(tgms_ctx* c, int reps, double* avg_ms) {
 }
 
 tgms_status tgms_profile_get(tgms_ctx* c, int kernel, int* launches, double* total_ms) {
+    if (c && c->dim == 3) {
+        g_last_error = "profile_get: not available on the cube";
+        return TGMS_E_UNSUPPORTED;
+    }
     if (!c || !launches || !total_ms || kernel < 0 || kernel >= tgms::PK_COUNT) {
         g_last_error = "bad argument";
         return TGMS_E_INVAL;
@@ -1756,17 +1821,17 @@ tgms_status tgms_total_mobility(const double* s, long long n, const tgms_transpo
                                 void* stream) {
     return guarded([&] {
         if (n < 0 || (n > 0 && (!s || !lambda))) throw TgmsError{TGMS_E_INVAL, "bad size or null argument"};
-        const tgms_transport_params t = transport_params(prm, 1, 1);
+        const tgms_transport_params t = transport_params(prm, 1, 1, 1);
         if (n > 0) tgms::total_mobility((hipStream_t)stream, s, n, t.mu_w, t.mu_o, lambda);
     });
 }
 
-tgms_status tgms_transport_step(int nx, int ny, const double* u, const double* q, double* s, double dt,
+tgms_status tgms_transport_step(int nx, int ny, int nz, const double* u, const double* q, double* s, double dt,
                                 const tgms_transport_params* prm, void* stream, long long* outer, double* residual) {
     tgms_status st = TGMS_OK;
     tgms_status r = guarded([&] {
-        const tgms_transport_params t = transport_params(prm, nx, ny);
-        const tgms::TransportResult res = transport_checked((hipStream_t)stream, nx, ny, u, q, s, dt, t);
+        const tgms_transport_params t = transport_params(prm, nx, ny, nz);
+        const tgms::TransportResult res = transport_checked((hipStream_t)stream, nx, ny, nz, u, q, s, dt, t);
         if (outer) *outer = res.sweeps;
         if (residual) *residual = res.residual;
         if (!res.converged) {
@@ -1789,6 +1854,7 @@ void tgms_destroy(tgms_ctx* c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
+    if (c->d3) tgms3::destroy3(c);
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->iter_graph) (void)hipGraphExecDestroy(c->iter_graph);
     for (auto& b : c->owned) tgms::dev_free(b.p, b.bytes);
@@ -1807,7 +1873,10 @@ tgms_status tgms_apply_A(tgms_ctx* c, const double* x, double* y) {
     }
     return guarded([&] {
         tgms::enter(c);
-        tgms::faces_A_probe(c, x, y);
+        if (c->dim == 3)
+            tgms3::apply_A3(c, x, y);
+        else
+            tgms::faces_A_probe(c, x, y);
         HIP_OK(hipStreamSynchronize(c->stream));
     });
 }
@@ -1819,7 +1888,12 @@ tgms_status tgms_preprocess(tgms_ctx* c, const double* F, const double* g_bnd, d
     }
     return guarded([&] {
         tgms::enter(c);
-        tgms::preprocess(c, F, g_bnd, vbar, c->cellw2);
+        if (c->dim == 3) {
+            if (g_bnd) throw TgmsError{TGMS_E_UNSUPPORTED, "on the cube only the no-flow boundary (g_bnd NULL)"};
+            tgms3::preprocess3(c, F, vbar);
+        } else {
+            tgms::preprocess(c, F, g_bnd, vbar, c->cellw2);
+        }
         HIP_OK(hipStreamSynchronize(c->stream));
     });
 }
@@ -1831,6 +1905,10 @@ tgms_status tgms_apply_precond(tgms_ctx* c, int which, const double* r, double* 
     }
     return guarded([&] {
         tgms::enter(c);
+        if (c->dim == 3) {
+            tgms3::apply_precond3(c, which, r, z);
+            return;
+        }
         tgms::curlT(c, r, c->vgold);
         precond(c, which, c->vgold, c->vq);
         tgms::curl_add(c, c->vq, nullptr, z);

@@ -148,7 +148,13 @@ void* dev_alloc(size_t bytes, size_t* got);
 void dev_free(void* p, size_t bytes);
 }  // namespace tgms
 
+namespace tgms3 {
+struct Ctx3;
+}
+
 struct tgms_ctx {
+    int dim = 2;
+    tgms3::Ctx3* d3 = nullptr;  // the cube's solver (dim 3)
     // grid
     int nx, ny, bx, by, Nx, Ny, nblk, ne, nex, jmax;
     double hx, hy, sx, sy, H, eta, tol;
@@ -481,6 +487,16 @@ bool symv_full_acc(tgms_ctx* c, const double* F, int n, const int* ptr, const in
 int symv_acc_max();
 void gemm(tgms_ctx* c, int transA, int transB, int M, int N, int K, double alpha, const double* A, int lda,
           const double* B, int ldb, double beta, double* C, int ldc);
+// batched GEMM: matrix z of A (and B, C) at A + (z / nin) * outer + (z % nin) * inner
+struct Strided {
+    long long outer = 0, inner = 0;
+    int nin = 1;
+};
+void gemm_batched(tgms_ctx* c, int transA, int transB, int M, int N, int K, double alpha, const double* A, int lda,
+                  Strided sa, const double* B, int ldb, Strided sb, double beta, double* C, int ldc, Strided sc,
+                  long long batch, bool lower_only = false);
+// each of batch consecutive n x n SPD matrices -> its explicit inverse, in place
+void dense_spd_inverse_batched(tgms_ctx* c, double* A, int n, long long batch);
 // preprocessing and pressure (k_pre.hip)
 void preprocess(tgms_ctx* c, const double* F, const double* g_bnd, double* vbar, double* Fp);
 void pressure(tgms_ctx* c, const double* u, double* p);
@@ -492,6 +508,7 @@ struct TransportResult {
     bool converged = false;
 };
 void total_mobility(hipStream_t st, const double* s, long long n, double mu_w, double mu_o, double* lam);
-TransportResult transport_step(hipStream_t st, int nx, int ny, const double* u, const double* q, double* s, double phi,
-                               double dt, double mu_w, double mu_o, double tol, int max_outer);
+// nz <= 1: the square (16 x 16 tiles); nz > 1: the cube (8 x 8 x 4 tiles)
+TransportResult transport_step(hipStream_t st, int nx, int ny, int nz, const double* u, const double* q, double* s,
+                               double phi, double dt, double mu_w, double mu_o, double tol, int max_outer);
 }  // namespace tgms

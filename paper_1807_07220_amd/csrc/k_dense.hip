@@ -185,8 +185,8 @@ __global__ void k_copy_diag_blocks(const double* __restrict__ Dinv, double* __re
 // at or above the panel and the w of columns at or left of it are zero, so those
 // entries are unchanged exactly; entries above the diagonal of S are never read.
 // Rows and columns past kb are the identity (unit pivots, no coupling).
-__global__ void __launch_bounds__(NT) k_potrf_diag(double* __restrict__ A, int lda, int k0, int kb,
-                                                   double* __restrict__ Dinv, int* __restrict__ fail) {
+__device__ inline void potrf_diag(double* __restrict__ A, int lda, int k0, int kb, double* __restrict__ Dinv,
+                                  int* __restrict__ fail) {
     __shared__ __align__(16) double colp[2][TB][4];
     __shared__ __align__(16) double rowp[2][4][TB];
     __shared__ __align__(16) double dg[TB];
@@ -362,6 +362,76 @@ __global__ void __launch_bounds__(NT) k_potrf_diag(double* __restrict__ A, int l
             if (in) A[(long long)(k0 + i) * lda + k0 + k] = (k == i) ? si[r] : S[r][q] * rsk[q];
             Dinv[i * TB + k] = in ? U[r][q] * rsi[r] : 0.0;
         }
+}
+
+__global__ void __launch_bounds__(NT) k_potrf_diag(double* __restrict__ A, int lda, int k0, int kb,
+                                                   double* __restrict__ Dinv, int* __restrict__ fail) {
+    potrf_diag(A, lda, k0, kb, Dinv, fail);
+}
+
+// ---- batched forms: matrix z of a batch at base + z * stride (blockIdx.z) -------------
+__global__ void __launch_bounds__(NT) k_potrf_diag_b(double* __restrict__ A, long long sA, int lda, int k0, int kb,
+                                                     double* __restrict__ Dinv, long long sD, int* __restrict__ fail) {
+    const long long z = blockIdx.z;
+    potrf_diag(A + z * sA, lda, k0, kb, Dinv + z * sD, fail);
+}
+
+// batch index z -> offset (z / nin) * outer + (z % nin) * inner
+struct BStride {
+    long long outer, inner;
+    int nin;
+    __device__ long long off(long long z) const { return (z / nin) * outer + (z % nin) * inner; }
+};
+
+__global__ void __launch_bounds__(NT) k_gemm_b(int transA, int transB, int M, int N, int K, double alpha,
+                                               const double* __restrict__ A, int lda, BStride sa,
+                                               const double* __restrict__ B, int ldb, BStride sb, double beta,
+                                               double* C, int ldc, BStride sc, int lower_only, long long z0) {
+    const int tm = blockIdx.y, tn = blockIdx.x;
+    if (lower_only && tm < tn) return;
+    const long long z = z0 + blockIdx.z;
+    gemm_tile(tm, tn, transA, transB, M, N, K, alpha, A + sa.off(z), lda, B + sb.off(z), ldb, beta, C + sc.off(z),
+              ldc);
+}
+
+__global__ void k_copy_diag_blocks_b(const double* __restrict__ Dinv, long long sD, double* __restrict__ X,
+                                     long long sX, int n) {
+    const long long z = blockIdx.z;
+    const int b = blockIdx.x, o = b * TB, len = min(TB, n - o);
+    for (int e = threadIdx.x; e < len * len; e += blockDim.x) {
+        const int i = e / len, j = e % len;
+        X[z * sX + (long long)(o + i) * n + o + j] = Dinv[z * sD + (long long)b * TB * TB + i * TB + j];
+    }
+}
+
+// k_inv_level over a batch: blockIdx.z = node + count * matrix
+__global__ void __launch_bounds__(NT) k_inv_level_b(InvLevel lv, int step, const double* __restrict__ L,
+                                                    double* __restrict__ X, double* __restrict__ Tm, int n,
+                                                    long long sT) {
+    const int node = blockIdx.z % lv.count;
+    const long long z = blockIdx.z / lv.count;
+    const int o = lv.o[node], n1 = lv.n1[node], n2 = lv.n2[node];
+    const int tm = blockIdx.y, tn = blockIdx.x;
+    if (tm * TB >= n2 || tn * TB >= n1) return;
+    const long long sM = (long long)n * n;
+    const double* Lz = L + z * sM;
+    double* Xz = X + z * sM;
+    double* T = Tm + z * sT + lv.toff[node];
+    if (step == 0)
+        gemm_tile(tm, tn, 0, 0, n2, n1, n1, 1.0, Lz + (long long)(o + n1) * n + o, n, Xz + (long long)o * n + o, n, 0.0,
+                  T, n1, tn * TB);
+    else
+        gemm_tile(tm, tn, 0, 0, n2, n1, min(n2, (tm + 1) * TB), -1.0, Xz + (long long)(o + n1) * n + o + n1, n, T, n1,
+                  0.0, Xz + (long long)(o + n1) * n + o, n);
+}
+
+__global__ void k_mirror_lower_b(double* __restrict__ F, int n, long long count) {
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long sM = (long long)n * n;
+    if (e >= sM * count) return;
+    const long long z = e / sM, r = e % sM;
+    const int i = (int)(r / n), j = (int)(r % n);
+    if (j > i) F[e] = F[z * sM + (long long)j * n + i];
 }
 
 // B[i][j] = X[i][j] (j <= i), B[i][j] = X[j][i] (j > i)
@@ -851,6 +921,127 @@ static void dense_inverse_sizes(int n, size_t& dinv, size_t& x, size_t& tm) {
     x = (size_t)n * n;
     tm = (size_t)n * (n / 2 + TB);
 }
+
+void gemm_batched(tgms_ctx* c, int transA, int transB, int M, int N, int K, double alpha, const double* A, int lda,
+                  Strided sa, const double* B, int ldb, Strided sb, double beta, double* C, int ldc, Strided sc,
+                  long long batch, bool lower_only) {
+    if (M <= 0 || N <= 0 || batch <= 0) return;
+    const BStride a{sa.outer, sa.inner, sa.nin}, b{sb.outer, sb.inner, sb.nin}, cc{sc.outer, sc.inner, sc.nin};
+    for (long long z0 = 0; z0 < batch; z0 += 65535) {
+        const unsigned nz = (unsigned)std::min<long long>(65535, batch - z0);
+        dim3 grid((N + TB - 1) / TB, (M + TB - 1) / TB, nz);
+        hipLaunchKernelGGL(k_gemm_b, grid, dim3(NT), 0, c->stream, transA, transB, M, N, K, alpha, A, lda, a, B, ldb,
+                           b, beta, C, ldc, cc, lower_only ? 1 : 0, z0);
+        LAUNCH_OK();
+    }
+}
+
+// In place: each of the batch matrices A_z (n x n, row-major, consecutive, symmetric
+// positive definite) -> its explicit inverse.  Per chunk of matrices: blocked Cholesky
+// (64-wide panels, the diagonal blocks and their inverses by potrf_diag), X = L^{-1} by
+// the recursive halving of the single-matrix inverse, then A = X^T X (lower tiles,
+// mirrored).  The workspace of a chunk comes from the device cache.
+void dense_spd_inverse_batched(tgms_ctx* c, double* A, int n, long long batch) {
+    if (n <= 0 || batch <= 0) return;
+    size_t nd, nx, nt;
+    dense_inverse_sizes(n, nd, nx, nt);
+    const size_t per = sizeof(double) * (nd + nx + nt);
+    const long long chunk =
+        std::max<long long>(1, std::min<long long>(std::min<long long>(batch, 65535), (4ll << 30) / (long long)per));
+    size_t got[3] = {0, 0, 0}, gotf = 0;
+    double* Dinv = (double*)dev_alloc(sizeof(double) * nd * chunk, &got[0]);
+    double* X = (double*)dev_alloc(sizeof(double) * nx * chunk, &got[1]);
+    double* Tm = (double*)dev_alloc(sizeof(double) * nt * chunk, &got[2]);
+    int* fail = (int*)dev_alloc(sizeof(int) * 64, &gotf);
+    struct Free {
+        void* p[4];
+        size_t b[4];
+        hipStream_t st;
+        ~Free() {
+            (void)hipStreamSynchronize(st);
+            for (int k = 0; k < 4; ++k) dev_free(p[k], b[k]);
+        }
+    } fr{{Dinv, X, Tm, fail}, {got[0], got[1], got[2], gotf}, c->stream};
+    zero(c, fail, sizeof(int) * 64);
+    const long long sM = (long long)n * n;
+    const int nblk = (n + TB - 1) / TB;
+    // the halving tree of the inverse (the same for every matrix)
+    struct Node {
+        int o, n1, n2, height;
+    };
+    std::vector<Node> nodes;
+    std::function<int(int, int)> build = [&](int o, int len) -> int {
+        if (len <= TB) return 0;
+        const int n1 = ((len / TB + 1) / 2) * TB, n2 = len - n1;
+        const int h = 1 + std::max(build(o, n1), build(o + n1, n2));
+        nodes.push_back(Node{o, n1, n2, h});
+        return h;
+    };
+    const int hmax = build(0, n);
+    for (long long b0 = 0; b0 < batch; b0 += chunk) {
+        const long long nbch = std::min(chunk, batch - b0);
+        double* Ab = A + b0 * sM;
+        const Strided one{sM, 0, 1};
+        zero(c, X, sizeof(double) * nx * nbch);
+        // Cholesky, 64 columns at a time
+        for (int k0 = 0; k0 < n; k0 += TB) {
+            const int kb0 = k0 / TB, kb = std::min(TB, n - k0), k1 = k0 + kb;
+            hipLaunchKernelGGL(k_potrf_diag_b, dim3(1, 1, (unsigned)nbch), dim3(NT), 0, c->stream, Ab, sM, n, k0, kb,
+                               Dinv + (size_t)kb0 * TB * TB, (long long)nd, fail);
+            LAUNCH_OK();
+            const int m = n - k1;
+            if (m <= 0) break;
+            // panel A[k1:, k0:k1] *= Dinv^T, then the trailing lower part -= P P^T
+            gemm_batched(c, 0, 1, m, kb, kb, 1.0, Ab + (size_t)k1 * n + k0, n, one,
+                         Dinv + (size_t)kb0 * TB * TB, TB, Strided{(long long)nd, 0, 1}, 0.0,
+                         Ab + (size_t)k1 * n + k0, n, one, nbch);
+            gemm_batched(c, 0, 1, m, m, kb, -1.0, Ab + (size_t)k1 * n + k0, n, one, Ab + (size_t)k1 * n + k0, n, one,
+                         1.0, Ab + (size_t)k1 * n + k1, n, one, nbch, true);
+        }
+        hipLaunchKernelGGL(k_copy_diag_blocks_b, dim3(nblk, 1, (unsigned)nbch), dim3(256), 0, c->stream,
+                           (const double*)Dinv, (long long)nd, X, sM, n);
+        LAUNCH_OK();
+        for (int h = 1; h <= hmax; ++h) {
+            InvLevel lv{};
+            long long toff = 0;
+            int mx1 = 0, mx2 = 0;
+            for (const Node& nd_ : nodes) {
+                if (nd_.height != h) continue;
+                if (lv.count == LEVEL_MAX) throw TgmsError{TGMS_E_UNSUPPORTED, "batched inverse: matrix too large"};
+                lv.o[lv.count] = nd_.o;
+                lv.n1[lv.count] = nd_.n1;
+                lv.n2[lv.count] = nd_.n2;
+                lv.toff[lv.count] = toff;
+                toff += (long long)nd_.n1 * nd_.n2;
+                mx1 = std::max(mx1, nd_.n1);
+                mx2 = std::max(mx2, nd_.n2);
+                ++lv.count;
+            }
+            if (lv.count == 0) continue;
+            // matrices per launch so that count * matrices fits the grid's z range
+            const long long per_launch = std::max<long long>(1, 65535 / lv.count);
+            for (long long z0 = 0; z0 < nbch; z0 += per_launch) {
+                const long long nz = std::min(per_launch, nbch - z0);
+                const dim3 grid((mx1 + TB - 1) / TB, (mx2 + TB - 1) / TB, (unsigned)(nz * lv.count));
+                for (int step = 0; step < 2; ++step) {
+                    hipLaunchKernelGGL(k_inv_level_b, grid, dim3(NT), 0, c->stream, lv, step,
+                                       (const double*)(Ab + z0 * sM), X + z0 * sM, Tm + z0 * (long long)nt, n,
+                                       (long long)nt);
+                    LAUNCH_OK();
+                }
+            }
+        }
+        // A = X^T X (lower tiles), mirrored
+        gemm_batched(c, 1, 0, n, n, n, 1.0, X, n, one, X, n, one, 0.0, Ab, n, one, nbch, true);
+        hipLaunchKernelGGL(k_mirror_lower_b, dim3(nb(sM * nbch)), dim3(256), 0, c->stream, Ab, n, nbch);
+        LAUNCH_OK();
+    }
+    int h = 0;
+    HIP_OK(hipMemcpyAsync(&h, fail, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (h) throw TgmsError{TGMS_E_INVAL, "a local Schur complement is not positive definite"};
+}
+
 
 // In place: A (n x n, row-major, symmetric positive definite) -> B = tril(L^{-1}) + triu(L^{-T}, 1);
 // full (optional, n x n): the explicit inverse L^{-T} L^{-1}, exactly symmetric.

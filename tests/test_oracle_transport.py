@@ -103,3 +103,28 @@ def test_impes_loop_with_kept_coarse_space():
     s, its = impes(o, F, np.zeros(g.nc), steps=6, dt=0.02, pressure_every=2)
     assert len(its) == 3 and max(its) < 40
     assert s[0] > 0.5 and s[-1] < s[0]
+
+
+def test_cube_step_along_each_axis_matches_the_strip():
+    """The cube's six-sided fluxes: a column of n cells along x, y or z with a unit flux
+    through its interior faces gives the saturation of the same strip on the square."""
+    from oracle.grid3d import Grid3D
+    n, dt = 12, 0.05
+    g2 = Grid2D(n, 1, n, 1)
+    u2 = np.zeros(g2.nf)
+    u2[g2.xf(np.arange(1, n), 0)] = 1.0 / g2.hy
+    F = np.zeros(n)
+    F[0], F[-1] = 1.0, -1.0
+    s2, _ = transport_step(g2, u2, F, np.zeros(n), dt, 1.0)
+    for a in range(3):
+        dims = [1, 1, 1]
+        dims[a] = n
+        g3 = Grid3D(*dims)
+        u3 = np.zeros(g3.nf)
+        area = g3.cell_vol / g3.h[a]
+        for t in range(1, n):
+            q = [0, 0, 0]
+            q[a] = t
+            u3[g3.face(a, *q)] = 1.0 / area
+        s3, _ = transport_step(g3, u3, F, np.zeros(n), dt, 1.0)
+        np.testing.assert_allclose(s3, s2, rtol=0, atol=1e-13)
