@@ -121,7 +121,7 @@ struct Ctx3 {
     int* cf = nullptr;        // [ne][4]: axis, I0, I1, I2 (I: the block on the high side)
     int* slot = nullptr;      // [nblk][6]: coarse face of side 2a + (0 low, 1 high), or -1
     int* fnoff = nullptr;     // [ne + 1]: first coarse unknown of each face
-    double* Sblk = nullptr;   // [nblk][n][n]: (B A^{-1} B^T + 1 1^T)^{-1} of the blocks
+    double* Sblk = nullptr;   // [nblk][n][n]: (B A^{-1} B^T + sigma 1 1^T)^{-1} of the blocks
     double* Spat = nullptr;   // the same for the patches
     double* eigs = nullptr;   // [ne][Jmax]
     int* counts = nullptr;    // [ne]

@@ -4,7 +4,7 @@
 // the cell sum of the pressure fixed by one multiplier) are solved through the pressure:
 // the mass matrix of a box couples only the faces of one grid line (no coupling across
 // axes on a box grid with scalar kappa), so A^{-1} is a tridiagonal solve per line, and
-//   p = (B A^{-1} B^T + 1 1^T)^{-1} (B A^{-1} f - g + mu 1),  mu = sum(g) / #cells,
+//   p = (B A^{-1} B^T + sigma 1 1^T)^{-1} (B A^{-1} f - g + mu 1),  mu = sum(g) / #cells,
 //   v = A^{-1} (f - B^T p)
 // solves [A B^T 0; B 0 1; 0 1^T 0] [v; p; mu] = [f; g; 0]; the Schur matrix B A^{-1} B^T
 // is a sum of dense line blocks, and its inverse (with the rank-one term that fixes the
@@ -155,8 +155,11 @@ __device__ inline void box_lines_solve(double* y, const G3& g, const int* E, con
     }
 }
 
-// S = B A^{-1} B^T + 1 1^T on the active cells of each box (identity on inactive ones):
-// one workgroup per box; the line blocks T = B_l A_l^{-1} B_l^T are added axis by axis.
+// S = B A^{-1} B^T + sigma 1 1^T on the active cells of each box (identity on inactive
+// ones), sigma the mean diagonal of B A^{-1} B^T: any sigma > 0 gives the same mean-zero
+// pressure, and this one keeps the constant mode at the scale of the others (with sigma = 1
+// the condition number grows like 1 / (kappa |f|^2 / |c|), 1e11 on thin cells of low kappa).
+// One workgroup per box; the line blocks T = B_l A_l^{-1} B_l^T are added axis by axis.
 __global__ void __launch_bounds__(NT3) k3_schur(Boxes B, G3 g, const double* __restrict__ w, double* __restrict__ S) {
     const int id = blockIdx.x;
     int lo[3], e[3];
@@ -168,7 +171,7 @@ __global__ void __launch_bounds__(NT3) k3_schur(Boxes B, G3 g, const double* __r
         const int ri = r % B.E[0], rj = (r / B.E[0]) % B.E[1], rk = r / (B.E[0] * B.E[1]);
         const int ci = cc % B.E[0], cj = (cc / B.E[0]) % B.E[1], ck = cc / (B.E[0] * B.E[1]);
         const bool ra = ri < e[0] && rj < e[1] && rk < e[2], ca = ci < e[0] && cj < e[1] && ck < e[2];
-        Sb[idx] = (ra && ca) ? 1.0 : (r == cc ? 1.0 : 0.0);
+        Sb[idx] = (!ra || !ca) && r == cc ? 1.0 : 0.0;
     }
     __syncthreads();
     for (int a = 0; a < 3; ++a) {
@@ -205,6 +208,23 @@ __global__ void __launch_bounds__(NT3) k3_schur(Boxes B, G3 g, const double* __r
             }
         }
         __syncthreads();
+    }
+    // sigma = mean of the active diagonal, added to every active pair
+    __shared__ double red[NT3 / 64];
+    double ds = 0.0;
+    for (int c = threadIdx.x; c < n; c += NT3) {
+        const int ci = c % B.E[0], cj = (c / B.E[0]) % B.E[1], ck = c / (B.E[0] * B.E[1]);
+        if (ci < e[0] && cj < e[1] && ck < e[2]) ds += Sb[(long long)c * n + c];
+    }
+    ds = wave_sum(ds);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ds;
+    __syncthreads();
+    const double sigma = (red[0] + red[1] + red[2] + red[3]) / (double)(e[0] * e[1] * e[2]);
+    for (long long idx = threadIdx.x; idx < (long long)n * n; idx += NT3) {
+        const int r = (int)(idx / n), cc = (int)(idx % n);
+        const int ri = r % B.E[0], rj = (r / B.E[0]) % B.E[1], rk = r / (B.E[0] * B.E[1]);
+        const int ci = cc % B.E[0], cj = (cc / B.E[0]) % B.E[1], ck = cc / (B.E[0] * B.E[1]);
+        if (ri < e[0] && rj < e[1] && rk < e[2] && ci < e[0] && cj < e[1] && ck < e[2]) Sb[idx] += sigma;
     }
 }
 
@@ -754,6 +774,17 @@ __global__ void k3_BH(G3 g, const int* __restrict__ slot, const int* __restrict_
     BH[(long long)K * nu + fnoff[E] + k] = ((s & 1) ? 1.0 : -1.0) * (g.vol / g.h[a]) * sum;
 }
 
+// out = mean of the diagonal of the n x n matrix A (one workgroup)
+__global__ void __launch_bounds__(NT3) k3_diag_mean(const double* __restrict__ A, int n, double* __restrict__ out) {
+    __shared__ double red[NT3 / 64];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += NT3) s += A[(long long)i * n + i];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = (red[0] + red[1] + red[2] + red[3]) / n;
+}
+
 __global__ void k3_add_const(double* __restrict__ A, long long n, double v) {
     const long long idx = blockIdx.x * (long long)NT3 + threadIdx.x;
     if (idx < n) A[idx] += v;
@@ -1170,8 +1201,22 @@ void twogrid(tgms_ctx* c, Ctx3* d, const double* r, double* z) {
     tgms::axpy(c, nf, 1.0, d->vt2, z);
 }
 
+// S += sigma 1 1^T, sigma the mean diagonal of S (the scale of the constant mode, as in the
+// boxes' Schur matrices)
+void add_scaled_ones(tgms_ctx* c, Ctx3* d, double* S, int n) {
+    hipLaunchKernelGGL(k3_diag_mean, dim3(1), dim3(NT3), 0, c->stream, (const double*)S, n, d->part);
+    LAUNCH_OK();
+    double sigma = 0.0;
+    HIP_OK(hipMemcpyAsync(&sigma, d->part, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (!(sigma > 0.0) || !std::isfinite(sigma)) sigma = 1.0;
+    hipLaunchKernelGGL(k3_add_const, dim3(nblocks((long long)n * n)), dim3(NT3), 0, c->stream, S, (long long)n * n,
+                       sigma);
+    LAUNCH_OK();
+}
+
 // the coarse operator over the kept basis: A_H = sum_K W_K^T A^(K) W_K, B_H, and
-// P_H = A_H^{-1} - A_H^{-1} B_H^T (B_H A_H^{-1} B_H^T + 1 1^T)^{-1} B_H A_H^{-1}
+// P_H = A_H^{-1} - A_H^{-1} B_H^T (B_H A_H^{-1} B_H^T + sigma 1 1^T)^{-1} B_H A_H^{-1}
 void build_coarse(tgms_ctx* c, Ctx3* d) {
     const Boxes& B = d->blk;
     const int m = 6 * d->cmax, nu = d->nu, nb = d->nblk;
@@ -1203,16 +1248,14 @@ void build_coarse(tgms_ctx* c, Ctx3* d) {
         SHi(sizeof(double) * (size_t)nb * nb, c->stream), T2(sizeof(double) * (size_t)nb * nu, c->stream);
     tgms::gemm(c, 0, 0, nb, nu, nu, 1.0, d->BH, nu, d->PH, nu, 0.0, T1.as<double>(), nu);
     tgms::gemm(c, 0, 1, nb, nb, nu, 1.0, T1.as<double>(), nu, d->BH, nu, 0.0, SH.as<double>(), nb);
-    hipLaunchKernelGGL(k3_add_const, dim3(nblocks((long long)nb * nb)), dim3(NT3), 0, c->stream, SH.as<double>(),
-                       (long long)nb * nb, 1.0);
-    LAUNCH_OK();
+    add_scaled_ones(c, d, SH.as<double>(), nb);
     tgms::dense_spd_inverse(c, SH.as<double>(), nb, SHi.as<double>());
     tgms::gemm(c, 0, 0, nb, nu, nb, 1.0, SHi.as<double>(), nb, T1.as<double>(), nu, 0.0, T2.as<double>(), nu);
     tgms::gemm(c, 1, 0, nu, nu, nb, -1.0, T1.as<double>(), nu, T2.as<double>(), nu, 1.0, d->PH, nu);
     HIP_OK(hipStreamSynchronize(c->stream));
 }
 
-// the preprocessing's coarse RT0 operator: vH = Q0T^T (gK - mu), Q0T = (S + 1 1^T)^{-1} B_H0 A_H0^{-1}
+// the preprocessing's coarse RT0 operator: vH = Q0T^T (gK - mu), Q0T = (S + sigma 1 1^T)^{-1} B_H0 A_H0^{-1}
 void build_rt0(tgms_ctx* c, Ctx3* d) {
     const int ne = d->ne, nb = d->nblk;
     Tmp AH0(sizeof(double) * (size_t)ne * ne, c->stream), AH0i(sizeof(double) * (size_t)ne * ne, c->stream),
@@ -1231,9 +1274,7 @@ void build_rt0(tgms_ctx* c, Ctx3* d) {
     tgms::dense_spd_inverse(c, AH0.as<double>(), ne, AH0i.as<double>());
     tgms::gemm(c, 0, 0, nb, ne, ne, 1.0, BH0.as<double>(), ne, AH0i.as<double>(), ne, 0.0, T1.as<double>(), ne);
     tgms::gemm(c, 0, 1, nb, nb, ne, 1.0, T1.as<double>(), ne, BH0.as<double>(), ne, 0.0, SH.as<double>(), nb);
-    hipLaunchKernelGGL(k3_add_const, dim3(nblocks((long long)nb * nb)), dim3(NT3), 0, c->stream, SH.as<double>(),
-                       (long long)nb * nb, 1.0);
-    LAUNCH_OK();
+    add_scaled_ones(c, d, SH.as<double>(), nb);
     tgms::dense_spd_inverse(c, SH.as<double>(), nb, SHi.as<double>());
     if (!d->Q0T) d->Q0T = c->alloc<double>((size_t)nb * ne);
     tgms::gemm(c, 0, 0, nb, ne, nb, 1.0, SHi.as<double>(), nb, T1.as<double>(), ne, 0.0, d->Q0T, ne);
@@ -1307,10 +1348,12 @@ void pressure(tgms_ctx* c, Ctx3* d, const double* u, double* p) {
     LAUNCH_OK();
 }
 
-// vbar with B vbar = F (section 3): the coarse RT0 solve, then one local solve per block
-void preprocess(tgms_ctx* c, Ctx3* d, const double* F, double* vbar) {
+// w with B w = G (section 3's construction): the coarse RT0 solve for the block sums of G,
+// interpolated to the fine faces, then one local saddle solve per block for the rest
+// (f = -A w_H, g = G - B w_H); uses vt, cell1, gK, vH
+void particular(tgms_ctx* c, Ctx3* d, const double* G, double* w) {
     const G3& g = d->g;
-    hipLaunchKernelGGL(k3_block_sums, dim3(d->nblk), dim3(64), 0, c->stream, d->blk, g, F, d->gK);
+    hipLaunchKernelGGL(k3_block_sums, dim3(d->nblk), dim3(64), 0, c->stream, d->blk, g, G, d->gK);
     LAUNCH_OK();
     std::vector<double> gk(d->nblk);
     HIP_OK(hipMemcpyAsync(gk.data(), d->gK, sizeof(double) * d->nblk, hipMemcpyDeviceToHost, c->stream));
@@ -1322,15 +1365,46 @@ void preprocess(tgms_ctx* c, Ctx3* d, const double* F, double* vbar) {
                        (const double*)d->gK, mu, d->nblk, d->ne, d->vH);
     LAUNCH_OK();
     hipLaunchKernelGGL(k3_rt0_interp, dim3(nblocks(g.nf)), dim3(NT3), 0, c->stream, g, d->blk, (const double*)d->vH,
-                       vbar);
+                       w);
     LAUNCH_OK();
-    applyA(c, d, vbar, d->vt);
-    hipLaunchKernelGGL(k3_div, dim3(nblocks(g.nc)), dim3(NT3), 0, c->stream, g, (const double*)vbar, d->cell1, F);
+    applyA(c, d, w, d->vt);
+    hipLaunchKernelGGL(k3_div, dim3(nblocks(g.nc)), dim3(NT3), 0, c->stream, g, (const double*)w, d->cell1, G);
     LAUNCH_OK();
     hipLaunchKernelGGL(k3_box_solve, dim3(d->blk.count), dim3(NT3), box_lds(d->blk), c->stream, d->blk, g,
                        (const double*)d->w, (const double*)d->Sblk, (const double*)d->vt, -1.0,
-                       (const double*)d->cell1, (double*)nullptr, vbar);
+                       (const double*)d->cell1, (double*)nullptr, w);
     LAUNCH_OK();
+}
+
+// vbar with B vbar = F (section 3)
+void preprocess(tgms_ctx* c, Ctx3* d, const double* F, double* vbar) {
+    const G3& g = d->g;
+    particular(c, d, F, vbar);
+    // The block solves meet B vbar = F only to about eps cond(S_K) of the right-hand side
+    // (explicit Schur inverses), and the PCG, kept in ker B, cannot repair it: the minimal
+    // correction vbar += B^T (B B^T)^+ (F - B vbar) restores the constraint to round-off.
+    // Any vbar with B vbar = F gives the same solution.
+    hipLaunchKernelGGL(k3_div, dim3(nblocks(g.nc)), dim3(NT3), 0, c->stream, g, (const double*)vbar, d->cell1, F);
+    LAUNCH_OK();
+    cell_laplace_solve(c, d);
+    hipLaunchKernelGGL(k3_add_grad, dim3(nblocks(g.nf)), dim3(NT3), 0, c->stream, g, (const double*)d->cell1, 1.0,
+                       vbar);
+    LAUNCH_OK();
+}
+
+// z -= w with B w = B z: every part of the two-grid cycle returns a divergence-free field in
+// exact arithmetic, but the local solves leave a divergence of about eps cond(S) |z|, and
+// the PCG iterate, a sum of such directions, would drift off ker B (an energy error of 1e-6
+// at contrasts of 1e8).  The correction is section 3's particular solution of that tiny
+// divergence: block-local and energy-weighted, so it does not disturb the low-permeability
+// faces the way a Euclidean projection does.  A no-op in exact arithmetic.
+void repair_divergence(tgms_ctx* c, Ctx3* d, double* z) {
+    const G3& g = d->g;
+    hipLaunchKernelGGL(k3_div, dim3(nblocks(g.nc)), dim3(NT3), 0, c->stream, g, (const double*)z, d->cell2,
+                       (const double*)nullptr);
+    LAUNCH_OK();
+    particular(c, d, d->cell2, d->vt2);
+    tgms::axpy(c, g.nf, -1.0, d->vt2, z);
 }
 
 }  // namespace
@@ -1434,6 +1508,7 @@ void setup3(tgms_ctx* c, const tgms_grid* grid, const double* kappa, double eig_
     d->slot = c->alloc<int>(slot.size());
     HIP_OK(hipMemcpyAsync(d->cf, cf.data(), sizeof(int) * cf.size(), hipMemcpyHostToDevice, c->stream));
     HIP_OK(hipMemcpyAsync(d->slot, slot.data(), sizeof(int) * slot.size(), hipMemcpyHostToDevice, c->stream));
+    d->part = c->alloc<double>(NPART);
     // cell weights
     d->w = c->alloc<double>(g.nc);
     d->kinv = c->alloc<double>(g.nc);
@@ -1573,7 +1648,6 @@ void setup3(tgms_ctx* c, const tgms_grid* grid, const double* kappa, double eig_
     d->cz = c->alloc<double>(d->nu);
     d->cell1 = c->alloc<double>(g.nc);
     d->cell2 = c->alloc<double>(g.nc);
-    d->part = c->alloc<double>(NPART);
     d->gK = c->alloc<double>(d->nblk);
     d->vH = c->alloc<double>(d->ne);
     HIP_OK(hipStreamSynchronize(c->stream));
@@ -1620,6 +1694,7 @@ void solve3(tgms_ctx* c, const double* F, double rtol, int maxit, double* u, dou
     project(c, d, d->vr);
     tgms::zero(c, d->vx, sizeof(double) * nf);
     twogrid(c, d, d->vr, d->vz);
+    repair_divergence(c, d, d->vz);
     const double z0 = std::sqrt(dot3(c, d, d->vz, d->vz, nf));
     c->alphas.clear();
     c->betas.clear();
@@ -1641,6 +1716,7 @@ void solve3(tgms_ctx* c, const double* F, double rtol, int maxit, double* u, dou
             tgms::axpy(c, nf, -alpha, d->vq, d->vr);
             project(c, d, d->vr);
             twogrid(c, d, d->vr, d->vz);
+            repair_divergence(c, d, d->vz);
             ++it;
             c->alphas.push_back(alpha);
             rel = std::sqrt(dot3(c, d, d->vz, d->vz, nf)) / z0;

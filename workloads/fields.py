@@ -189,3 +189,48 @@ def gradient_flow(nx, ny, seed, corr_len=0.1):
     q = (ux[:, 1:] - ux[:, :-1]) / ny + (uy[1:, :] - uy[:-1, :]) / nx
     scale = 1.0 / np.sum(np.maximum(q, 0.0))
     return np.concatenate([ux.ravel(), uy.ravel()]) * scale, q * scale
+
+
+def field_layered_3d(nx, ny, nz, seed, n_smooth=None, log_var=3.0, corr_len=0.1, n_channels=6, contrast=1e7):
+    """Layered permeability of the cube, indexed [k, j, i] (layer k along z, x fastest).
+
+    The top ``n_smooth`` layers (largest k; by default 35 of every 85) are a smooth
+    log-normal medium: per layer a
+    Gaussian field in the (x, y) plane, correlated between neighbouring layers by an
+    AR(1) blend, scaled to log-variance ``log_var``.  The layers below are fluvial: a
+    low-permeability log-normal background (log-variance 1) cut by sinuous channels whose
+    geometry drifts slowly from layer to layer (a new set every 5 layers), channel and
+    background values set ``contrast`` apart.  A stand-in, built from the same
+    ingredients, for the layered reservoir models of the paper's experiments.
+    """
+    rng = _rng(seed)
+    if n_smooth is None:
+        n_smooth = int(round(nz * 35 / 85))
+    kappa = np.empty((nz, ny, nx))
+    prev = gaussian_field_2d(nx, ny, corr_len, rng)
+    rho = 0.8
+    n_fluvial = max(nz - n_smooth, 0)
+    for k in range(nz - 1, nz - 1 - min(n_smooth, nz), -1):
+        prev = rho * prev + np.sqrt(1.0 - rho * rho) * gaussian_field_2d(nx, ny, corr_len, rng)
+        kappa[k] = np.exp(np.sqrt(log_var) * prev)
+    mask = None
+    bg = gaussian_field_2d(nx, ny, corr_len, rng)
+    low = 1.0 / np.sqrt(contrast)
+    for k in range(n_fluvial):
+        if k % 5 == 0:
+            mask = curved_channels(nx, ny, n_channels, rng, width=(0.04, 0.08))
+        bg = rho * bg + np.sqrt(1.0 - rho * rho) * gaussian_field_2d(nx, ny, corr_len, rng)
+        layer = low * np.exp(bg)
+        layer[mask] = low * contrast
+        kappa[k] = layer
+    return kappa
+
+
+def well_pattern_3d(nx, ny, nz):
+    """Cell-integrated sources of a five-spot through the whole thickness: injectors in the
+    four vertical corner columns (total +1), the producer in the central column (-1)."""
+    f = np.zeros((nz, ny, nx))
+    for (i, j) in ((0, 0), (nx - 1, 0), (0, ny - 1), (nx - 1, ny - 1)):
+        f[:, j, i] += 0.25 / nz
+    f[:, ny // 2, nx // 2] -= 1.0 / nz
+    return f
