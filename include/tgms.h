@@ -182,8 +182,9 @@ void tgms_default_options(tgms_options* opt);
  * overlap of at most the block size, patches of at most 32 cells per axis, at most
  * 64 fine faces per coarse face; coarse_space 0, 1 and 2.  tgms_solve,
  * tgms_update_mobility, tgms_impes, tgms_info, tgms_get_counts, tgms_get_eigs,
- * tgms_last_cond, tgms_apply_A, tgms_preprocess and tgms_apply_precond accept such
- * a context; the other calls that take a context return TGMS_E_UNSUPPORTED for it.
+ * tgms_last_cond, tgms_apply_A, tgms_preprocess, tgms_apply_precond and
+ * tgms_time_smoother (the patch solves) accept such a context; the other calls
+ * that take a context return TGMS_E_UNSUPPORTED for it.
  * Coarse faces are ordered x, y, z, each by (K, J, I) of the block on the face's
  * high side; the fine faces of a coarse face with the lower tangential axis fastest.
  */

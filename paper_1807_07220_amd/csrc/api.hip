@@ -1712,10 +1712,6 @@ tgms_status tgms_profile(tgms_ctx* c, int enable) {
 }
 
 tgms_status tgms_time_smoother(tgms_ctx* c, int reps, double* avg_ms) {
-    if (c && c->dim == 3) {
-        g_last_error = "time_smoother: not available on the cube";
-        return TGMS_E_UNSUPPORTED;
-    }
     if (!c || !avg_ms || reps < 1 || reps > 100000) {
         g_last_error = "bad argument";
         return TGMS_E_INVAL;
@@ -1725,7 +1721,9 @@ tgms_status tgms_time_smoother(tgms_ctx* c, int reps, double* avg_ms) {
         const bool prof = c->prof;
         c->prof = false;
         auto body = [&] {
-            if (c->precision != 0)
+            if (c->dim == 3)
+                tgms3::smooth_patches3(c);
+            else if (c->precision != 0)
                 tgms::smooth_patches<float>(c, c->fz, nullptr);
             else
                 tgms::smooth_patches<double>(c, c->vz, nullptr);

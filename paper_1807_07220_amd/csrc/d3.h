@@ -151,5 +151,6 @@ void apply_A3(tgms_ctx* c, const double* x, double* y);
 void preprocess3(tgms_ctx* c, const double* F, double* vbar);
 void apply_precond3(tgms_ctx* c, int which, const double* r, double* z);
 void destroy3(tgms_ctx* c);
+void smooth_patches3(tgms_ctx* c);  // one launch of the patch solves on the solve workspace (timing)
 
 }  // namespace tgms3

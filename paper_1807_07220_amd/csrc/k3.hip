@@ -1762,6 +1762,14 @@ void apply_precond3(tgms_ctx* c, int which, const double* r, double* z) {
     HIP_OK(hipStreamSynchronize(c->stream));
 }
 
+void smooth_patches3(tgms_ctx* c) {
+    Ctx3* d = c->d3;
+    hipLaunchKernelGGL(k3_box_solve, dim3(d->pat.count), dim3(NT3), box_lds(d->pat), c->stream, d->pat, d->g,
+                       (const double*)d->w, (const double*)d->Spat, (const double*)d->vr, 1.0, (const double*)nullptr,
+                       d->patch_out, (double*)nullptr);
+    LAUNCH_OK();
+}
+
 void destroy3(tgms_ctx* c) {
     delete c->d3;
     c->d3 = nullptr;
