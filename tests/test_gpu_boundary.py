@@ -164,14 +164,18 @@ def test_grid_dimension_checked():
     from paper_1807_07220_amd import _lib
     lib = _lib.load()
     kappa = dev(np.ones((32, 32)))
+    kappa3 = dev(np.ones((4, 32, 32)))
     opt = _lib.Options()
     lib.tgms_default_options(ctypes.byref(opt))
     h = ctypes.c_void_p()
-    for dim, status in ((3, -7), (1, -1), (4, -1)):
-        g = _lib.Grid(dim, 32, 32, 4, 8, 8, 2)
-        code = lib.tgms_setup(ctypes.byref(g), ctypes.c_void_p(kappa.data_ptr()), 0.5, ctypes.byref(opt),
+    # dimensions other than 2 and 3, and cubes whose sizes the blocks do not divide or that
+    # have fewer than 2 blocks on an axis, are refused before any kernel reads kappa
+    for grid, k, status in (((1, 32, 32, 4, 8, 8, 2), kappa, -1), ((4, 32, 32, 4, 8, 8, 2), kappa, -1),
+                            ((3, 32, 32, 4, 8, 8, 3), kappa3, -1), ((3, 32, 32, 4, 8, 8, 4), kappa3, -7)):
+        g = _lib.Grid(*grid)
+        code = lib.tgms_setup(ctypes.byref(g), ctypes.c_void_p(k.data_ptr()), 0.5, ctypes.byref(opt),
                               ctypes.byref(h))
-        assert code == status and not h.value
+        assert code == status and not h.value, (grid, code)
     g = _lib.Grid(2, 32, 32, 1, 8, 8, 1)
     assert lib.tgms_setup(ctypes.byref(g), ctypes.c_void_p(kappa.data_ptr()), 0.5, ctypes.byref(opt),
                           ctypes.byref(h)) == 0

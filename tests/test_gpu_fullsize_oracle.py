@@ -94,11 +94,17 @@ def test_fullsize_matches_oracle(name, precision):
         print(f"{name} {precision}: iters gpu {r8['iters']} oracle {int(gold['iters_1e8'])} "
               f"(Cond {float(gold['cond_1e8']):.3g}); at rtol 1e-12 gpu {r12['iters']} oracle "
               f"{int(gold['iters_1e12'])}; sampled u err {eu:.2e} (energy norm {ea:.2e}), p err {ep:.2e}")
-        # 1e-10 (FP64) or 1e-8 (FP32 preconditioner), or twice the oracle iterate's own
-        # distance to the direct solve where that attainable accuracy is coarser
+        # 1e-10 (FP64) or 1e-8 (FP32 preconditioner) in the energy norm of the velocity (the
+        # norm the PCG minimises) and for the pressure, or twice the oracle iterate's own
+        # distance to the direct solve where that attainable accuracy is coarser.  In the
+        # 2-norm the velocity follows from the energy norm through the ratio of the mass
+        # matrix's diagonal entries, the permeability contrast: |e|_2 / |u|_2 <=
+        # sqrt(contrast) |e|_A / |u|_A.  The channels (kappa 1e6) weigh a millionth in the
+        # energy norm and hold most of the 2-norm.
         bar = 1e-10 if precision == "fp64" else 1e-8
         fu, fp = float(gold.get("floor_u", np.nan)), float(gold.get("floor_p", np.nan))
-        bu = max(bar, 2 * fu) if np.isfinite(fu) else bar
+        contrast = float(kappa.max() / kappa.min())
+        bu = max(bar * np.sqrt(contrast), 2 * fu) if np.isfinite(fu) else bar * np.sqrt(contrast)
         bp = max(bar, 2 * fp) if np.isfinite(fp) else bar
         assert ea <= bar and ep <= bp, (ea, bar, ep, bp)
         assert eu <= bu, (eu, bu)
