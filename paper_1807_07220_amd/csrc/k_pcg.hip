@@ -56,12 +56,14 @@ __device__ inline void group_sum(double (&v)[NV]) {
     __syncthreads();
 }
 
-constexpr int NRED = 256;  // most workgroups of a reducing kernel (stride of the partial arrays)
+constexpr int NRED = 1024;  // most workgroups of a reducing kernel (stride of the partial arrays)
 
-// Sum of the nred partials of array k, in fixed order, returned to every thread.
+// Sum of the nred partials of array k, in fixed order (each thread its strided share,
+// then the workgroup sum), returned to every thread.
 __device__ inline double sum_partials(const double* __restrict__ part, int k, int nred) {
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
-    double v[1] = {tid < nred ? part[k * NRED + tid] : 0.0};
+    double v[1] = {0.0};
+    for (int j = tid; j < nred; j += NT) v[0] += part[k * NRED + j];
     group_sum<1>(v);
     return v[0];
 }

@@ -463,7 +463,8 @@ __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__
         // alpha = rho' / p.q from the partials of k_dir_apply (every workgroup forms it)
         __shared__ double red[4];
         const int t = threadIdx.x;
-        double v = t < U.nred ? U.part[t] : 0.0;
+        double v = 0.0;
+        for (int j = t; j < U.nred; j += 256) v += U.part[j];
         v = wave_sum(v);
         if ((t & 63) == 0) red[t >> 6] = v;
         __syncthreads();

@@ -6,7 +6,7 @@
 // same shape skip the timing.
 //
 // Tuned:
-//   nred, rpt      workgroups of the reducing PCG kernels (64, 128, 256) and vertex
+//   nred, rpt      workgroups of the reducing PCG kernels (64 ... 1024) and vertex
 //                  rows per thread in their tiles (1, 4): fewer partials to sum
 //                  against more tiles per workgroup, and more loads in flight per
 //                  thread against fewer workgroups with work;
@@ -112,7 +112,7 @@ void autotune(tgms_ctx* c, const char* cache_path) {
     zero(c, c->vg, sizeof(double) * nv);
     TuneRec best;
     double tbest = 1e30;
-    for (int nred : {64, 128, 256})
+    for (int nred : {64, 128, 256, 512, 1024})
         for (int rpt : {1, 4}) {
             c->nred = nred;
             c->rpt = rpt;
