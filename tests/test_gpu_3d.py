@@ -19,6 +19,10 @@ CASES = {
     "cube12_b4_ov2": ((12, 12, 12), (4, 4, 4), 2, 2.0, 2.0),
     "box15x12x9_b5x4x3_ov1": ((15, 12, 9), (5, 4, 3), 1, 2.0, 2.0),
     "box20x20x10_b5_ov2": ((20, 20, 10), (5, 5, 5), 2, 2.0, 3.0),
+    # blocks one cell thick along z (no interior z-faces inside a block, one-cell lines)
+    "thin12x12x4_b4x4x1_ov1": ((12, 12, 4), (4, 4, 1), 1, 2.0, 2.0),
+    # two blocks per axis with overlap 3: every patch clipped on one side of each axis
+    "two8x6x10_b4x3x5_ov3": ((8, 6, 10), (4, 3, 5), 3, 2.0, 2.0),
 }
 
 
