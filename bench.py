@@ -55,14 +55,14 @@ def smoother_bytes(nx, ny, bx, by, overlap, word):
 
     Per patch K_i^+ with m x mh interior vertices (n = m*mh) the local solver is
     stored in the two-sided block-elimination form: mh symmetric pivot inverses
-    (m(m+1)/2 words each, packed), mh-1 dense m x m coupling blocks and the n
-    equilibration scales.  The launch reads that once, reads the residual on the
-    patch (n words) and writes the local solution (n words).
+    (m(m+1)/2 words each, packed), mh-1 tridiagonal coupling blocks (3m words each)
+    and the n equilibration scales.  The launch reads that once, reads the residual
+    on the patch (n words) and writes the local solution (n words).
     """
     total = 0
     for m, mh in patch_rects(nx, ny, bx, by, overlap):
         n = m * mh
-        factor = mh * m * (m + 1) // 2 + (mh - 1) * m * m + n
+        factor = mh * m * (m + 1) // 2 + (mh - 1) * 3 * m + n
         total += factor + 2 * n
     return total * word
 

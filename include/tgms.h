@@ -93,11 +93,10 @@ typedef struct {
     const float* cnn_weights;  /* device, tgms_cnn_nparams() floats (warm_start 2; read during
                                   setup only) */
     double rq_tol;     /* relative Ritz residual |T u - theta u| / theta for acceptance (1e-6) */
-    int smoother_staging;  /* -1: chosen by the autotuner (without it: staged where the factor
-                              fits in LDS); 0: the patch solves read their factor from global
-                              memory; 1: the factor is first staged in LDS; 2: staged in LDS by
-                              two waves while the other two run the forward sweeps from global
-                              memory (1 and 2 fall back to 0 where the factor does not fit) */
+    int smoother_staging;  /* -1: chosen by the autotuner (without it: 0); 0: each chain step's
+                              factor blocks are staged in LDS by the forward chains and again by
+                              the backward chains; 1: the forward chains' blocks are kept in LDS
+                              for the backward chains (falls back to 0 where they do not fit) */
     int rows_per_thread;   /* vertex rows per thread in the tiled PCG kernels: 0 chosen by the
                               autotuner (without it: 1); 1 or 4 */
     const int* force_counts;  /* host, n_coarse_faces ints (face order of tgms_get_counts), or NULL:
@@ -137,7 +136,7 @@ typedef struct {
                              HIP graph */
     int tuned;            /* launch configuration: 0 defaults, 1 timed at this setup, 2 from the cache */
     int nred;             /* workgroups of the reducing PCG kernels */
-    int smooth_staged;    /* smoother factor: 1 staged in LDS, 0 read from global, -1 by LDS fit */
+    int smooth_staged;    /* smoother: 1 forward blocks kept in LDS, 0 staged twice */
     int warm_accepted;    /* warm start: faces whose modes were certified without the dense solve */
     int warm_iters;       /* warm start: subspace iterations summed over the accepted faces */
     double t_cnn_ms;      /* warm start 2: network inputs and forward pass (inside t_eig_ms) */

@@ -610,8 +610,8 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
     if (ex > 33) throw TgmsError{TGMS_E_UNSUPPORTED, "smoother patches wider than 33 cells"};
     (void)ey;
     if (o.warm_start < 0 || o.warm_start > 2) throw TgmsError{TGMS_E_INVAL, "warm_start must be 0, 1 or 2"};
-    if (o.smoother_staging < -1 || o.smoother_staging > 2)
-        throw TgmsError{TGMS_E_INVAL, "smoother_staging must be -1, 0, 1 or 2"};
+    if (o.smoother_staging < -1 || o.smoother_staging > 1)
+        throw TgmsError{TGMS_E_INVAL, "smoother_staging must be -1, 0 or 1"};
     if (o.rows_per_thread != 0 && o.rows_per_thread != 1 && o.rows_per_thread != 4)
         throw TgmsError{TGMS_E_INVAL, "rows_per_thread must be 0, 1 or 4"};
     if (o.coarse_space < 0 || o.coarse_space > 2) throw TgmsError{TGMS_E_INVAL, "coarse_space must be 0, 1 or 2"};
@@ -855,6 +855,7 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                     c->pat_zmax = std::max(c->pat_zmax, (long long)(r.i1 - r.i0 + 1) * (r.j1 - r.j0 + 1));
                     voff += n;
                     c->pat_nmax = std::max(c->pat_nmax, n);
+                    c->pat_hmax = std::max(c->pat_hmax, r.j1 - r.j0 - 1);
                     c->pat_bmax = std::max(c->pat_bmax, m + 1);
                     widths.insert(m);
                 }

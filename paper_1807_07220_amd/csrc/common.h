@@ -176,6 +176,7 @@ struct tgms_ctx {
     int pat_bmax = 0, pat_nmax = 0;
     int pat_m1 = 0, pat_m2 = 0;  // the row widths present among the patches (m1 >= m2)
     long long pat_fmax = 0;   // largest patch factor (elements)
+    int pat_hmax = 0;         // most vertex rows of a patch
     long long pat_zmax = 0;   // largest patch with its one-vertex halo (vertices)
     int lds_max = 65536;      // device limit on LDS per workgroup (bytes)
     long long pat_pool = 0, pat_vpool = 0;
@@ -257,7 +258,7 @@ struct tgms_ctx {
     double* vg2 = nullptr;    // second residual buffer (residual updates fused into the smoother)
     int nred = 256;           // workgroups of the reducing PCG kernels (autotuned)
     int rpt = 1;              // vertex rows per thread in the tiled PCG kernels (1 or 4; autotuned)
-    int smooth_staged = -1;   // smoother: 1 factor staged in LDS, 0 read from global, -1 by LDS fit
+    int smooth_staged = -1;   // smoother: 1 forward blocks kept in LDS for the backward chains, 0 staged twice
     int snap_cols = 1;        // snapshots: 1 one lane per column where supported, 0 one wave per block
     int tuned = 0;            // 0 defaults, 1 timed at setup, 2 taken from the tuning cache
     double* vp1 = nullptr;    // second search-direction buffer (p alternates between vp and vp1)

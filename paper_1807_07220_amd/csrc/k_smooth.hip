@@ -13,10 +13,6 @@
 #include "common.h"
 #include "patch.h"
 
-#ifndef TGMS_PF_DIRECT
-#define TGMS_PF_DIRECT 1  // link lines in flight per chain when the factor is read from global memory
-#endif
-
 namespace {
 
 // ------------------------------------------------------------------ factorisation
@@ -95,8 +91,9 @@ __global__ void __launch_bounds__(64) k_patch_factor(const Rect* __restrict__ re
         double* Mid = G + mm;
         double* F = Fpool + R.off;
         double* Pout = F;
-        double* Lout = F + tw_links(m, mh);
+        double* Bout = F + tw_links(m, mh);
         double* Sout = F + tw_scale(m, mh);
+        const int trip = tw_trip(m), b3 = tw_b3(m);
         // stencil couplings of each interior vertex with its east, north, north-east
         // and north-west neighbours (zero where the neighbour is not a patch vertex)
         for (int r = lane; r < n; r += 64) {
@@ -126,13 +123,20 @@ __global__ void __launch_bounds__(64) k_patch_factor(const Rect* __restrict__ re
             Sout[r] = s;
         }
         __syncthreads();
+        // the coupling blocks (three rows of m words per link, zero-padded to b3)
+        for (int e = lane; e < (mh - 1) * b3; e += 64) {
+            const int l = e / b3, q = e - l * b3, which = q / m, sidx = q - which * m;
+            const double* src = which == 0 ? kn : which == 1 ? kne : knw;
+            Bout[e] = which < 3 ? src[l * m + sidx] : 0.0;
+        }
         const PatchStencil P{kc, ke, kn, kne, knw, m};
         for (int e = lane; e < mm; e += 64) Mid[e] = P.A(k, e / m, e % m);
         auto store_pivot = [&](int j) {
             for (int e = lane; e < mm; e += 64) {
                 const int r = e / m, s = e - r * m;
-                if (r >= s) Pout[(long long)j * tw_tri(m) + tw_offP(s, m) + (r - s)] = W[e];
+                if (r >= s) Pout[(long long)j * trip + tw_offP(s, m) + (r - s)] = W[e];
             }
+            for (int e = tw_tri(m) + lane; e < trip; e += 64) Pout[(long long)j * trip + e] = 0.0;
         };
         // top sweep: rows 0..k-1
         if (k >= 1)
@@ -149,7 +153,6 @@ __global__ void __launch_bounds__(64) k_patch_factor(const Rect* __restrict__ re
                 if (r >= 1) g += kne[o + r - 1] * W[(r - 1) * m + s];
                 if (r + 1 < m) g += knw[o + r + 1] * W[(r + 1) * m + s];
                 G[e] = g;
-                Lout[(long long)j * mm + e] = g;
             }
             __syncthreads();
             // G B_j^T, subtracted from the next diagonal block (or from the middle one)
@@ -180,7 +183,6 @@ __global__ void __launch_bounds__(64) k_patch_factor(const Rect* __restrict__ re
                 if (r + 1 < m) h += kne[o + r] * W[(r + 1) * m + s];
                 if (r >= 1) h += knw[o + r] * W[(r - 1) * m + s];
                 G[e] = h;
-                Lout[(long long)(j - 1) * mm + e] = h;
             }
             __syncthreads();
             // H B_{j-1}
@@ -205,28 +207,34 @@ __global__ void __launch_bounds__(64) k_patch_factor(const Rect* __restrict__ re
 }
 
 // ------------------------------------------------------------------ application
-// Per patch: psi = S K~^{-1} S g on the patch's interior vertices.  Waves 0 and 1
-// run the top and bottom chains; lane a < m holds entry a of the current block
-// vector, and the entries a matrix-vector product needs are broadcast from their
-// lanes with readlane.  The line of the link used by step t+1 (and the entry of
-// b or u) is loaded while step t computes.  Between the forward and backward
-// chains all four waves form the independent products u_j = P_j w_j.
-//
-// M: the compile-time row width (registers, unrolled loops, fixed offsets).
-template <typename T, int M>
-struct Lines {
-    int a;
-    // row a of a dense M x M row-major matrix
-    __device__ void row(T (&v)[M], const T* p) const {
-#pragma unroll
-        for (int c = 0; c < M; ++c) v[c] = p[a * M + c];
-    }
-    // column a of a dense M x M row-major matrix
-    __device__ void column(T (&v)[M], const T* p) const {
-#pragma unroll
-        for (int c = 0; c < M; ++c) v[c] = p[c * M + a];
-    }
-};
+// Per patch: psi = S K~^{-1} S g on the patch's interior vertices, by the chains of
+// patch.h.  Wave 0 runs the top chains and wave 1 the bottom ones; lane a holds entry
+// a of the current block vector.  A dense symmetric product P v broadcasts the
+// entries of v with readlane; a tridiagonal product with B_l takes the neighbouring
+// lanes' entries by wave shifts (DPP).  Every step's pivot and coupling blocks are
+// staged in LDS by the wave that uses them, with 16-byte loads over all 64 lanes (the
+// loads of the next two steps in flight while a step computes), and each lane reads
+// its row there: few, full-width memory instructions instead of one narrow load per
+// row entry.
+
+// v of lane a-1 (0 on lane 0) and of lane a+1 (0 on lane 63)
+__device__ inline int dpp_shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true); }
+__device__ inline int dpp_shl1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true); }
+__device__ inline float shr1(float v) { return __int_as_float(dpp_shr1(__float_as_int(v))); }
+__device__ inline float shl1(float v) { return __int_as_float(dpp_shl1(__float_as_int(v))); }
+__device__ inline double shr1(double v) {
+    return __hiloint2double(dpp_shr1(__double2hiint(v)), dpp_shr1(__double2loint(v)));
+}
+__device__ inline double shl1(double v) {
+    return __hiloint2double(dpp_shl1(__double2hiint(v)), dpp_shl1(__double2loint(v)));
+}
+
+// (B v)_a and (B^T v)_a from the coupling rows n, e, w of lane a (v zero beyond the
+// patch row, so that the shifts bring zeros in)
+template <typename T>
+__device__ inline T b_apply(T n, T e, T w, T v) { return n * v + shr1(e * v) + shl1(w * v); }
+template <typename T>
+__device__ inline T bt_apply(T n, T e, T w, T v) { return n * v + e * shl1(v) + w * shr1(v); }
 
 template <typename T, int M>
 __device__ inline T dot_lanes(const T (&v)[M], T x) {
@@ -259,214 +267,308 @@ struct PatchOut {
     }
 };
 
-// One chain of steps t = 0..steps-1 on link lk(t): line(t) . x with line = row
-// (ROW) or column of the link; then x = base[r(t)] - product, handed to put(r(t), .)
-// (scaled by scale[r(t)] when given), except that with TO_MID the last product
-// goes to mid instead.  The lines of the next PF steps are in flight while a step
-// computes (PF + 1 register buffers, rotated by unrolling).
-template <typename T, int M, bool ROW, bool TO_MID, int PF, typename RowOf, typename LinkOf, typename Put>
-__device__ inline void chain(const Lines<T, M>& ln, int steps, const T* Lk, const T* base, Put put, const T* scale,
-                             T* mid, T x, bool act, RowOf rr, LinkOf lk) {
+// 16 bytes as a native vector (kept in registers where a HIP vector struct array
+// is not)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// The blocks of one chain step of a patch with rows of M vertices: the pivot block
+// P_j (packed, padded to TRIP words) and the coupling block B_l (B3 words), staged
+// together in one LDS slot of SW words.
+template <typename T, int M>
+struct Blocks {
+    static constexpr int TRIP = (M * (M + 1) / 2 + 3) & ~3, B3 = (3 * M + 3) & ~3, SW = TRIP + B3;
+    static constexpr int VW = 16 / (int)sizeof(T);  // words per 16-byte vector
+    static constexpr int NVP = TRIP / VW, NV = SW / VW, PER = (NV + 63) / 64;
+    using V = u32x4;
+    const T* P;   // the patch's pivot blocks (global memory)
+    const T* Bq;  // its coupling blocks
+    int lane;
+    // every lane loads (lanes past the blocks re-read the last vector): no branch, so
+    // the loaded registers are only waited for where they are stored
+    __device__ void load(V (&r)[PER], int prow, int link) const {
+        const V* gp = reinterpret_cast<const V*>(P + (long long)prow * TRIP);
+        const V* gb = reinterpret_cast<const V*>(Bq + (long long)link * B3);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int v = lane + 64 * q, vb = v - NVP;
+            r[q] = v < NVP ? gp[v] : gb[vb < NV - NVP ? vb : NV - NVP - 1];
+        }
+    }
+    __device__ void store(const V (&r)[PER], T* slot) const {
+        V* d = reinterpret_cast<V*>(slot);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int v = lane + 64 * q;
+            if (v < NV) d[v] = r[q];
+        }
+    }
+};
+
+// Row a of a staged step: the pivot row and the three coupling entries
+template <typename T, int M>
+struct StepRow {
+    T pr[M];
+    T n, e, w;
+};
+
+// P[a][c] of a packed symmetric block: (c, a) below the diagonal for c <= a, (a, c)
+// otherwise; offa = offP(a) - a (formed once per lane)
+template <int M>
+__device__ inline int packed_at(int a, int offa, int c) {
+    return c <= a ? tw_offP(c, M) - c + a : offa + c;
+}
+
+template <typename T, int M>
+__device__ inline void read_row(StepRow<T, M>& R, const T* slot, int offa, int a, bool act) {
+#pragma unroll
+    for (int c = 0; c < M; ++c) R.pr[c] = slot[packed_at<M>(a, offa, c)];
+    const T* b = slot + Blocks<T, M>::TRIP;
+    R.n = act ? b[a] : T(0);
+    R.e = act ? b[M + a] : T(0);
+    R.w = act ? b[2 * M + a] : T(0);
+}
+
+// `steps` chain steps of one wave; step t uses the pivot block of row prow(t) and the
+// coupling block of link lnk(t), in LDS slot slot(t).  FILL: the wave stages them
+// there itself (the loads of steps t+1 and t+2 in flight in registers while step t
+// computes); otherwise they are in their slots already.  body(t, row) forms the step.
+template <typename T, int M, bool FILL, typename ProwOf, typename LinkOf, typename SlotOf, typename Body>
+__device__ inline void staged_steps(const Blocks<T, M>& bk, int steps, ProwOf prow, LinkOf lnk, SlotOf slot,
+                                    int offa, int a, bool act, Body body) {
     if (steps <= 0) return;
-    constexpr long long mm = (long long)M * M;
-    constexpr int NB = PF + 1;
-    const int a = ln.a;
-    T L[NB][M];
-    T bv[NB], sv[NB];
-    auto load = [&](T(&Ld)[M], T& b, T& sc, int t) {
-        if (ROW)
-            ln.row(Ld, Lk + lk(t) * mm);
-        else
-            ln.column(Ld, Lk + lk(t) * mm);
-        b = (!TO_MID || t + 1 < steps) ? base[rr(t) * M + a] : T(0);
-        sc = scale ? scale[rr(t) * M + a] : T(1);
+    using V = u32x4;
+    constexpr int PER = Blocks<T, M>::PER;
+    // two register buffers named apart (constant indices only, so that they stay in
+    // registers): at step t, `next` holds step t+1 and the other one step t+2
+    V ra[PER], rb[PER];
+    if constexpr (FILL) {
+        bk.load(ra, prow(0), lnk(0));
+        if (steps > 1) bk.load(rb, prow(1), lnk(1));
+        bk.store(ra, slot(0));
+        if (steps > 2) bk.load(ra, prow(2), lnk(2));
+    }
+    auto step = [&](int t, V (&next)[PER]) __attribute__((always_inline)) {
+        StepRow<T, M> row;
+        read_row<T, M>(row, slot(t), offa, a, act);
+        if constexpr (FILL) {
+            // step t+1 into its slot (the slot of step t-1, whose rows are read), then
+            // the registers take step t+3
+            if (t + 1 < steps) bk.store(next, slot(t + 1));
+            if (t + 3 < steps) bk.load(next, prow(t + 3), lnk(t + 3));
+        }
+        body(t, row);
     };
-#pragma unroll
-    for (int d = 0; d < PF; ++d)
-        if (d < steps) load(L[d], bv[d], sv[d], d);
-    for (int t0 = 0; t0 < steps; t0 += NB) {
-#pragma unroll
-        for (int d = 0; d < NB; ++d) {
-            const int t = t0 + d;
-            if (t < steps) {
-                const T s = dot_lanes<T, M>(L[d], x);
-                __builtin_amdgcn_sched_barrier(0);  // keep the next loads behind this step's products
-                const int dn = (d + PF) % NB;  // a constant once the loop is unrolled
-                if (t + PF < steps) load(L[dn], bv[dn], sv[dn], t + PF);
-                if (TO_MID && t + 1 == steps) {
-                    if (act) mid[a] = s;
-                } else {
-                    x = bv[d] - s;
-                    if (act) put(rr(t), scale ? sv[d] * x : x);
-                }
-            }
-        }
+    for (int t0 = 0; t0 < steps; t0 += 2) {
+        step(t0, rb);
+        if (t0 + 1 < steps) step(t0 + 1, ra);
     }
 }
 
-// Fg: the factor in global memory, read by the forward sweeps; F: the factor the rest
-// reads (Fg, or its LDS copy).  With stage (F in LDS, not yet filled): waves 2 and 3
-// copy the factor from Fg to F while waves 0 and 1 run the forward sweeps.
-template <typename T, int M, int PF>
-__device__ inline void solve_patch(int mh, const T* F, const T* Fg, T* vec, T* u, T* mid, const PatchOut<T>& out,
-                                   long long stage) {
-    constexpr int m = M, tri = M * (M + 1) / 2;
-    const int k = mh / 2;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const bool act = lane < m;
-    const Lines<T, M> ln{act ? lane : m - 1};
-    const int a = ln.a;
-    const T* P = F;
-    const T* Lk = F + tw_links(m, mh);
-    const T* Lf = Fg + tw_links(m, mh);  // the forward sweeps' links
-    const T* S = F + tw_scale(m, mh);
-    if (stage > 0 && wave >= 2) {
-        // 16-byte copies, eight in flight per thread (128 threads)
-        using V = float4;
-        constexpr int PER = 16 / sizeof(T), U = 8;
-        const V* src = reinterpret_cast<const V*>(Fg);
-        V* dst = reinterpret_cast<V*>(const_cast<T*>(F));
-        const int nvec = (int)((stage + PER - 1) / PER), t2 = tid - 128;
-        int e = t2;
-        for (; e + (U - 1) * 128 < nvec; e += U * 128) {
-            V v[U];
-#pragma unroll
-            for (int q = 0; q < U; ++q) v[q] = src[e + q * 128];
-#pragma unroll
-            for (int q = 0; q < U; ++q) dst[e + q * 128] = v[q];
-        }
-        for (; e < nvec; e += 128) dst[e] = src[e];
-    }
+// One patch (fixed row width M).  LDS: vec (b, then the forward chains' w), u, mid
+// (the two chains' last products), the middle row's pivot block and the chain slots:
+// KEEP: one slot per forward step and wave (the backward chains read them again
+// without touching global memory); otherwise two per wave, refilled by the backward
+// chains.
+template <typename T, int M, bool KEEP>
+__device__ inline void solve_patch(int mh, const T* Fg, T* vec, T* u, T* mid, const T* midP, T* slots,
+                                   const PatchOut<T>& out) {
+    using Bk = Blocks<T, M>;
+    constexpr int SW = Bk::SW;
+    const int k = mh / 2, top = k, bot = mh - 1 - k;
+    // the wave index in a scalar register: the branches on it are taken by whole waves
+    const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const bool act = lane < M;
+    const int a = act ? lane : M - 1;
+    const T* S = Fg + tw_scale(M, mh);
+    const Bk bk{Fg, Fg + tw_links(M, mh), lane};
+    const int offa = tw_offP(a, M) - a;
+    T* my = slots + (KEEP ? wave * k : wave * 2) * SW;  // this wave's slots
+    auto sl = [=](int t) { return my + (KEEP ? t : (t & 1)) * SW; };
     if (wave == 0) {
-        // w_{t+1} = b_{t+1} - G_t w_t for t < k-1, stored over b; G_{k-1} w_{k-1} -> mid
-        auto to_vec = [&](int row, T v) { vec[row * M + a] = v; };
-        chain<T, M, true, true, PF>(ln, k, Lf, vec, to_vec, (const T*)nullptr, mid, vec[a], act,
-                                [](int t) { return t + 1; }, [](int t) { return (long long)t; });
-        if (k == 0 && act) mid[a] = T(0);
-    } else if (wave == 1) {
-        // w_{r-1} = b_{r-1} - H_{r-1} w_r from r = mh-1 down; H_k w_{k+1} -> mid + M
-        auto to_vec = [&](int row, T v) { vec[row * M + a] = v; };
-        chain<T, M, true, true, PF>(ln, mh - 1 - k, Lf, vec, to_vec, (const T*)nullptr, mid + M, vec[(mh - 1) * M + a],
-                                act, [=](int t) { return mh - 2 - t; }, [=](int t) { return (long long)(mh - 2 - t); });
-        if (mh - 1 == k && act) mid[M + a] = T(0);
+        // u_t = P_t w_t; w_{t+1} = b_{t+1} - B_t u_t, the last product into mid
+        T v = vec[a];
+        staged_steps<T, M, true>(bk, top, [](int t) { return t; }, [](int t) { return t; }, sl, offa, a, act,
+                                 [&](int t, const StepRow<T, M>& r) {
+                                     const T ut = dot_lanes<T, M>(r.pr, v);
+                                     if (act) u[t * M + a] = ut;
+                                     const T z = b_apply(r.n, r.e, r.w, act ? ut : T(0));
+                                     if (t + 1 < top)
+                                         v = vec[(t + 1) * M + a] - z;
+                                     else if (act)
+                                         mid[a] = z;
+                                 });
+        if (top == 0 && act) mid[a] = T(0);
+    } else {
+        // u_r = P_r w_r; w_{r-1} = b_{r-1} - B_{r-1}^T u_r from r = mh-1 down, the last into mid + 64
+        T v = vec[(mh - 1) * M + a];
+        staged_steps<T, M, true>(
+            bk, bot, [=](int i) { return mh - 1 - i; }, [=](int i) { return mh - 2 - i; }, sl, offa, a, act,
+            [&](int i, const StepRow<T, M>& r) {
+                const int row = mh - 1 - i;
+                const T ur = dot_lanes<T, M>(r.pr, v);
+                if (act) u[row * M + a] = ur;
+                const T z = bt_apply(r.n, r.e, r.w, act ? ur : T(0));
+                if (row - 1 > k)
+                    v = vec[(row - 1) * M + a] - z;
+                else if (act)
+                    mid[64 + a] = z;
+            });
+        if (bot == 0 && act) mid[64 + a] = T(0);
     }
     __syncthreads();
-    // u_j = P_j w_j for every row j (w_k = b_k - G_{k-1} w_{k-1} - H_k w_{k+1})
-    {
-        int idx[M];  // position of P_j[a][c] in the packed lower triangle
+    if (wave == 0) {
+        // the middle row: x_k = P_k (b_k - B_{k-1} u_{k-1} - B_k^T u_{k+1})
+        T pr[M];
 #pragma unroll
-        for (int c = 0; c < M; ++c) idx[c] = (c <= a) ? tw_offP(c, M) - c + a : tw_offP(a, M) - a + c;
-        for (int j = wave; j < mh; j += 4) {
-            const T* Pj = P + (long long)j * tri;
-            T pr[M];
-#pragma unroll
-            for (int c = 0; c < M; ++c) pr[c] = Pj[idx[c]];
-            T wj = vec[j * M + a];
-            if (j == k) wj -= mid[a] + mid[M + a];
-            const T uj = dot_lanes<T, M>(pr, wj);
-            if (act) u[j * M + a] = uj;
+        for (int c = 0; c < M; ++c) pr[c] = midP[packed_at<M>(a, offa, c)];
+        const T xk = dot_lanes<T, M>(pr, vec[k * M + a] - mid[a] - mid[64 + a]);
+        if (act) {
+            u[k * M + a] = xk;
+            out.put(k, a, S[k * M + a] * xk);
         }
     }
     __syncthreads();
-    const T xk = u[k * M + a];
-    auto to_out = [&](int row, T v) { out.put(row, a, v); };
+    T x = u[k * M + a];
     if (wave == 0) {
-        if (act) out.put(k, a, S[k * M + a] * xk);
-        // x_l = u_l - G_l^T x_{l+1}, l = k-1 .. 0
-        chain<T, M, false, false, PF>(ln, k, Lk, u, to_out, S, mid, xk, act, [=](int t) { return k - 1 - t; },
-                                  [=](int t) { return (long long)(k - 1 - t); });
-    } else if (wave == 1) {
-        // x_{l+1} = u_{l+1} - H_l^T x_l, l = k .. mh-2
-        chain<T, M, false, false, PF>(ln, mh - 1 - k, Lk, u, to_out, S, mid, xk, act, [=](int t) { return k + 1 + t; },
-                                  [=](int t) { return (long long)(k + t); });
+        // x_l = u_l - P_l B_l^T x_{l+1}, l = k-1 .. 0
+        staged_steps<T, M, !KEEP>(bk, top, [=](int t) { return k - 1 - t; }, [=](int t) { return k - 1 - t; },
+                                  [=](int t) { return KEEP ? my + (k - 1 - t) * SW : my + (t & 1) * SW; }, offa, a,
+                                  act, [&](int t, const StepRow<T, M>& r) {
+                                      const int l = k - 1 - t;
+                                      const T y = bt_apply(r.n, r.e, r.w, act ? x : T(0));
+                                      x = u[l * M + a] - dot_lanes<T, M>(r.pr, y);
+                                      if (act) out.put(l, a, S[l * M + a] * x);
+                                  });
+    } else {
+        // x_{l+1} = u_{l+1} - P_{l+1} B_l x_l, l = k .. mh-2 (forward slot mh-2-l)
+        staged_steps<T, M, !KEEP>(bk, bot, [=](int t) { return k + 1 + t; }, [=](int t) { return k + t; },
+                                  [=](int t) { return KEEP ? my + (bot - 1 - t) * SW : my + (t & 1) * SW; }, offa,
+                                  a, act, [&](int t, const StepRow<T, M>& r) {
+                                      const int l = k + t;
+                                      const T y = b_apply(r.n, r.e, r.w, act ? x : T(0));
+                                      x = u[(l + 1) * M + a] - dot_lanes<T, M>(r.pr, y);
+                                      if (act) out.put(l + 1, a, S[(l + 1) * M + a] * x);
+                                  });
     }
 }
 
-// Any row width m <= 64: the same two-sided sweeps with runtime loops over the
-// columns (no register lines, no prefetch).  Used for widths without a
-// fixed-width instantiation.
+// Any row width m <= 64: the same chains with runtime loops over the columns, the
+// blocks read from global memory directly.  Used for widths without a fixed-width
+// instantiation.
 template <typename T>
-__device__ inline void solve_patch_any(int m, int mh, const T* F, T* vec, T* u, T* mid, const PatchOut<T>& out) {
-    const int k = mh / 2, tri = tw_tri(m);
-    const long long mm = (long long)m * m;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+__device__ inline void solve_patch_any(int m, int mh, const T* Fg, T* vec, T* u, T* mid, const PatchOut<T>& out) {
+    const int k = mh / 2, top = k, bot = mh - 1 - k, trip = tw_trip(m), b3 = tw_b3(m);
+    const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const bool act = lane < m;
     const int a = act ? lane : 0;
-    const T* P = F;
-    const T* Lk = F + tw_links(m, mh);
-    const T* S = F + tw_scale(m, mh);
-    auto psym = [&](const T* Pj, int c) { return c <= a ? Pj[tw_offP(c, m) + a - c] : Pj[tw_offP(a, m) + c - a]; };
-    if (wave < 2) {
-        const bool top = wave == 0;
-        const int steps = top ? k : mh - 1 - k;
-        T* md = mid + (top ? 0 : 64);
-        if (steps == 0 && act) md[a] = T(0);
-        int r = top ? 0 : mh - 1;
-        T w = act ? vec[r * m + a] : T(0);
-        for (int t = 0; t < steps; ++t) {
-            const long long l = top ? t : mh - 2 - t;
-            const T* Lr = Lk + l * mm + (long long)a * m;
-            const T* Pj = P + (long long)r * tri;
-            T s = T(0), p = T(0);
-            for (int c = 0; c < m; ++c) {
-                const T xc = readlane(w, c);
-                s += Lr[c] * xc;
-                p += psym(Pj, c) * xc;
-            }
-            if (act) u[r * m + a] = p;
-            r += top ? 1 : -1;
-            if (t + 1 < steps)
-                w = act ? vec[r * m + a] - s : T(0);
+    const T* P = Fg;
+    const T* Bq = Fg + tw_links(m, mh);
+    const T* S = Fg + tw_scale(m, mh);
+    auto pdot = [&](int j, T v) {  // (P_j v)_a
+        const T* Pj = P + (long long)j * trip;
+        T s = T(0);
+        for (int c = 0; c < m; ++c) {
+            const T pac = c <= a ? Pj[tw_offP(c, m) + a - c] : Pj[tw_offP(a, m) + c - a];
+            s += pac * readlane(v, c);
+        }
+        return s;
+    };
+    auto cpl = [&](int l, T& n, T& e, T& w) {
+        const T* b = Bq + (long long)l * b3;
+        n = act ? b[a] : T(0);
+        e = act ? b[m + a] : T(0);
+        w = act ? b[2 * m + a] : T(0);
+    };
+    if (wave == 0) {
+        T v = vec[a];
+        for (int t = 0; t < top; ++t) {
+            T n, e, w;
+            cpl(t, n, e, w);
+            const T ut = pdot(t, v);
+            if (act) u[t * m + a] = ut;
+            const T z = b_apply(n, e, w, act ? ut : T(0));
+            if (t + 1 < top)
+                v = vec[(t + 1) * m + a] - z;
             else if (act)
-                md[a] = s;
+                mid[a] = z;
+        }
+        if (top == 0 && act) mid[a] = T(0);
+    } else if (wave == 1) {
+        T v = vec[(mh - 1) * m + a];
+        for (int row = mh - 1; row > k; --row) {
+            T n, e, w;
+            cpl(row - 1, n, e, w);
+            const T ur = pdot(row, v);
+            if (act) u[row * m + a] = ur;
+            const T z = bt_apply(n, e, w, act ? ur : T(0));
+            if (row - 1 > k)
+                v = vec[(row - 1) * m + a] - z;
+            else if (act)
+                mid[64 + a] = z;
+        }
+        if (bot == 0 && act) mid[64 + a] = T(0);
+    }
+    __syncthreads();
+    if (wave == 0) {
+        const T xk = pdot(k, vec[k * m + a] - mid[a] - mid[64 + a]);
+        if (act) {
+            u[k * m + a] = xk;
+            out.put(k, a, S[k * m + a] * xk);
         }
     }
     __syncthreads();
-    if (wave < 2) {
-        const bool top = wave == 0;
-        T wk = act ? vec[k * m + a] - mid[a] - mid[64 + a] : T(0);
-        const T* Pk = P + (long long)k * tri;
-        T x = T(0);
-        for (int c = 0; c < m; ++c) x += psym(Pk, c) * readlane(wk, c);
-        if (!act) x = T(0);
-        if (top && act) out.put(k, a, S[k * m + a] * x);
-        const int steps = top ? k : mh - 1 - k;
-        for (int t = 0; t < steps; ++t) {
-            const long long l = top ? k - 1 - t : k + t;
-            const int r = top ? k - 1 - t : k + 1 + t;
-            const T* Lc = Lk + l * mm + a;
-            T s = T(0);
-            for (int c = 0; c < m; ++c) s += Lc[(long long)c * m] * readlane(x, c);
-            x = act ? u[r * m + a] - s : T(0);
-            if (act) out.put(r, a, S[r * m + a] * x);
+    T x = u[k * m + a];
+    if (wave == 0) {
+        for (int l = k - 1; l >= 0; --l) {
+            T n, e, w;
+            cpl(l, n, e, w);
+            const T y = bt_apply(n, e, w, act ? x : T(0));
+            x = u[l * m + a] - pdot(l, y);
+            if (act) out.put(l, a, S[l * m + a] * x);
+        }
+    } else if (wave == 1) {
+        for (int l = k; l <= mh - 2; ++l) {
+            T n, e, w;
+            cpl(l, n, e, w);
+            const T y = b_apply(n, e, w, act ? x : T(0));
+            x = u[(l + 1) * m + a] - pdot(l + 1, y);
+            if (act) out.put(l + 1, a, S[(l + 1) * m + a] * x);
         }
     }
 }
 
-// One workgroup (4 waves) per patch.  MODE 1: the factor is first copied to LDS
-// with 16-byte loads (eight in flight per thread); MODE 0: the chains read it from
-// global memory with the lines of the next steps in flight; MODE 2: the forward
-// chains read global memory while waves 2 and 3 copy the factor to LDS, which the
-// pivot products and the backward chains then read (the staging is hidden behind
-// the forward sweeps and the links are read from HBM once).  GENERIC: every patch
-// takes the clamped path of width M1 (m <= M1; MODE 2 runs as MODE 0); otherwise
-// every patch has width M1 or M2 and takes the fixed-width path of its width.
-template <typename T, int M1, int M2, bool GENERIC, int MODE>
-__global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__ rects, const T* __restrict__ Fpool,
+// LDS words of one workgroup beyond the input vectors: mid, the middle pivot block and
+// the chain slots of a patch with rows of M vertices and at most mh rows
+template <typename T, int M>
+__host__ __device__ constexpr long long patch_lds_words(bool keep, int mh) {
+    return 128 + Blocks<T, M>::TRIP + (keep ? 2LL * (mh / 2) : 4LL) * Blocks<T, M>::SW;
+}
+
+// One workgroup (two waves) per patch.  GENERIC: every patch takes the runtime-width
+// path (m <= M1 unused); otherwise every patch has width M1 or M2.  KEEP: the chain
+// slots hold every forward step (see solve_patch).
+template <typename T, int M1, int M2, bool GENERIC, bool KEEP>
+__global__ void __launch_bounds__(128) k_smooth_twisted(const Rect* __restrict__ rects, const T* __restrict__ Fpool,
                                                         const T* __restrict__ g, int nx, int ny, T* __restrict__ wout,
                                                         T* __restrict__ w4, int bx, int by, int Nx,
                                                         const double* __restrict__ sc, FusedUpdate U,
                                                         PreResidual<T> Pr) {
+    constexpr int NW = 2, NT = NW * 64;
     if (sc != nullptr && sc[SC_DONE] != 0.0) return;  // PCG already converged
     double al = 0.0;
     if (U.gin) {
-        // alpha = rho' / p.q from the partials of k_dir_apply (every workgroup forms it)
+        // alpha = rho' / p.q from the partials of k_dir_apply (every workgroup forms it,
+        // summed in the order of a 256-thread workgroup)
         __shared__ double red[4];
         const int t = threadIdx.x;
-        double v = 0.0;
-        for (int j = t; j < U.nred; j += 256) v += U.part[j];
-        v = wave_sum(v);
-        if ((t & 63) == 0) red[t >> 6] = v;
+#pragma unroll
+        for (int h = 0; h < 4 / NW; ++h) {
+            const int tv = t + h * NT;
+            double v = 0.0;
+            for (int j = tv; j < U.nred; j += 256) v += U.part[j];
+            v = wave_sum(v);
+            if ((t & 63) == 0) red[tv >> 6] = v;
+        }
         __syncthreads();
         const double pq = red[0] + red[1] + red[2] + red[3];
         const double rho = U.sc[SC_RHO_NEW];
@@ -490,63 +592,46 @@ __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__
     const Rect R = rects[blockIdx.x];
     const int m = R.i1 - R.i0 - 1, mh = R.j1 - R.j0 - 1;
     const int n = m * mh;
-    const long long fs = tw_size(m, mh);
     const T* Fg = Fpool + R.off;
     const int tid = threadIdx.x;
-    const T* F;
-    T* vec;
-    constexpr bool STAGED = MODE == 1;          // staged before the sweeps
-    constexpr bool OVERLAP = MODE == 2 && !GENERIC;  // staged during the forward sweeps
-    if constexpr (STAGED) {
-        using V = float4;
-        constexpr int PER = 16 / sizeof(T);
-        constexpr int U = 8;
-        const V* src = reinterpret_cast<const V*>(Fg);
-        V* dst = reinterpret_cast<V*>(sm);
-        const int nvec = (int)((fs + PER - 1) / PER);
-        int e = tid;
-        for (; e + (U - 1) * 256 < nvec; e += U * 256) {
-            V v[U];
-#pragma unroll
-            for (int q = 0; q < U; ++q) v[q] = src[e + q * 256];
-#pragma unroll
-            for (int q = 0; q < U; ++q) dst[e + q * 256] = v[q];
-        }
-        for (; e < nvec; e += 256) dst[e] = src[e];
-        F = sm;
-        vec = sm + ((fs + 3) & ~3LL);
-    } else if constexpr (OVERLAP) {
-        F = sm;  // filled by waves 2 and 3 during the forward sweeps
-        vec = sm + ((fs + 3) & ~3LL);
-    } else {
-        F = Fg;
-        vec = sm;
-    }
+    T* vec = sm;
     T* u = vec + ((n + 3) & ~3);
     T* mid = u + ((n + 3) & ~3);  // 2 * 64
-    // the scale from the staged copy (read once from global memory)
-    if constexpr (STAGED) __syncthreads();
-    const T* Sg = (OVERLAP ? Fg : F) + tw_scale(m, mh);
+    T* midP = mid + 128;           // the middle row's pivot block (fixed widths)
+    const int MW = GENERIC ? 0 : (m == M1 ? M1 : M2);
+    const int trip = tw_trip(m), sw = trip + tw_b3(m);
+    T* slots = midP + (GENERIC ? 0 : trip);
+    const long long lds_fixed = GENERIC ? 128 : 128 + trip + (KEEP ? 2LL * (mh / 2) : 4LL) * sw;
+    (void)MW;
+    if (!GENERIC) {
+        // stage P_k (16-byte copies)
+        using V = float4;
+        constexpr int VW = 16 / (int)sizeof(T);
+        const V* src = reinterpret_cast<const V*>(Fg + (long long)(mh / 2) * trip);
+        V* dst = reinterpret_cast<V*>(midP);
+        for (int e = tid; e < trip / VW; e += NT) dst[e] = src[e];
+    }
+    const T* Sg = Fg + tw_scale(m, mh);
     const int I = blockIdx.x % Nx, J = blockIdx.x / Nx;
     if (Pr.z1) {
         // z1' = z1 + W c on the patch and its one-vertex halo (LDS, FP64 of the stored
         // value), the own block's z1' written out, then t = g - K z1' in FP64, rounded once
         const int pw = m + 2, ph = mh + 2, mu = Pr.mu, nown = bx * by;
-        const size_t zoff = ((reinterpret_cast<size_t>(mid + 2 * 64) + 15) & ~(size_t)15);
+        const size_t zoff = ((reinterpret_cast<size_t>(mid + lds_fixed) + 15) & ~(size_t)15);
         double* Zt = reinterpret_cast<double*>(zoff);
         T* cb = reinterpret_cast<T*>(Zt + pw * ph);  // [9][mu]: the 3 x 3 blocks around K_i
         const int Ny = ny / by;
-        for (int e = tid; e < 9 * mu; e += 256) {
-            const int nb = e / mu, u = e % mu, Ib = I + nb % 3 - 1, Jb = J + nb / 3 - 1;
+        for (int e = tid; e < 9 * mu; e += NT) {
+            const int nb = e / mu, uu = e % mu, Ib = I + nb % 3 - 1, Jb = J + nb / 3 - 1;
             T val = T(0);
             if (Ib >= 0 && Ib < Nx && Jb >= 0 && Jb < Ny) {
                 const int b = Jb * Nx + Ib;
-                if (u < Pr.nunk[b]) val = Pr.c[Pr.unk[(long long)b * mu + u]];
+                if (uu < Pr.nunk[b]) val = Pr.c[Pr.unk[(long long)b * mu + uu]];
             }
             cb[e] = val;
         }
         __syncthreads();
-        for (int e = tid; e < pw * ph; e += 256) {
+        for (int e = tid; e < pw * ph; e += NT) {
             const int ii = R.i0 + e % pw, jj = R.j0 + e / pw;
             const bool own = ii >= I * bx && ii < (I + 1) * bx && jj >= J * by && jj < (J + 1) * by;
             const long long v = (long long)jj * nx + ii;
@@ -559,7 +644,7 @@ __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__
                 const T* cv = cb + nb * mu;
                 const int nu = Pr.nunk[b];
                 T s = T(0);
-                for (int u = 0; u < nu; ++u) s += Wv[u] * cv[u];
+                for (int q = 0; q < nu; ++q) s += Wv[q] * cv[q];
                 const T zz = Pr.z1[v] + s;
                 val = double(zz);
                 if (own) Pr.z1p[v] = zz;
@@ -569,14 +654,14 @@ __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__
             Zt[e] = val;
         }
         __syncthreads();
-        for (int r = tid; r < n; r += 256) {
+        for (int r = tid; r < n; r += NT) {
             const int aa = r % m, bb = r / m;
             const long long v = (long long)(R.j0 + 1 + bb) * nx + R.i0 + 1 + aa;
             const VertexData d = vertex_data(Pr.g, Pr.a, v, nx, true);
             vec[r] = Sg[r] * T(d.g - stencil_at4(Zt, pw, aa + 1, bb + 1, d.A, Pr.sx2, Pr.sy2));
         }
     } else
-    for (int r = tid; r < n; r += 256) {
+    for (int r = tid; r < n; r += NT) {
         const int aa = r % m, bb = r / m, i = R.i0 + 1 + aa, j = R.j0 + 1 + bb;
         const long long v = (long long)j * nx + i;
         T gv;
@@ -596,19 +681,19 @@ __global__ void __launch_bounds__(256) k_smooth_twisted(const Rect* __restrict__
     const long long plane = (long long)nx * ny;
     const PatchOut<T> out{wout + R.voff, w4, plane, m, nx, R.i0, R.j0, I * bx, (I + 1) * bx, J * by, (J + 1) * by};
     if constexpr (GENERIC)
-        solve_patch_any<T>(m, mh, F, vec, u, mid, out);
+        solve_patch_any<T>(m, mh, Fg, vec, u, mid, out);
     else if (m == M1)
-        solve_patch<T, M1, STAGED ? 1 : TGMS_PF_DIRECT>(mh, F, STAGED ? F : Fg, vec, u, mid, out, OVERLAP ? fs : 0);
+        solve_patch<T, M1, KEEP>(mh, Fg, vec, u, mid, midP, slots, out);
     else
-        solve_patch<T, M2, STAGED ? 1 : TGMS_PF_DIRECT>(mh, F, STAGED ? F : Fg, vec, u, mid, out, OVERLAP ? fs : 0);
+        solve_patch<T, M2, KEEP>(mh, Fg, vec, u, mid, midP, slots, out);
 }
 
 // Fixed-width pairs (interior width, boundary-clipped width) with an overlap of
 // two cells for blocks of 4, 6, 8, 12, 16, 20, 24 and 28 cells; other widths take
-// the clamped path.
+// the runtime-width path.
 #define TGMS_TW_PAIRS(X) X(7, 5) X(9, 7) X(11, 9) X(15, 13) X(19, 17) X(23, 21) X(27, 25) X(31, 29)
 
-template <typename T, int M1, int M2, bool GENERIC, int MODE>
+template <typename T, int M1, int M2, bool GENERIC, bool KEEP>
 void launch_tw(tgms_ctx* c, const T* L, const T* g, T* w, size_t lds, const double* sc, const FusedUpdate& U,
                const PreResidual<T>& Pr) {
     T* w4 = nullptr;
@@ -616,50 +701,54 @@ void launch_tw(tgms_ctx* c, const T* L, const T* g, T* w, size_t lds, const doub
     if (c->prof) {
         // events recorded by the dispatch itself (kernel execution only)
         hipEvent_t e1 = tgms::take_event(c), e2 = tgms::take_event(c);
-        hipExtLaunchKernelGGL((k_smooth_twisted<T, M1, M2, GENERIC, MODE>), dim3(c->nblk), dim3(256), lds,
+        hipExtLaunchKernelGGL((k_smooth_twisted<T, M1, M2, GENERIC, KEEP>), dim3(c->nblk), dim3(128), lds,
                               c->stream, e1, e2, 0, c->patch, L, g, c->nx, c->ny, w, w4, c->bx, c->by, c->Nx, sc, U, Pr);
         c->prof_rec.push_back({tgms::PK_SMOOTH, c->prof_iter, e1, e2});
     } else {
-        hipLaunchKernelGGL((k_smooth_twisted<T, M1, M2, GENERIC, MODE>), dim3(c->nblk), dim3(256), lds, c->stream,
+        hipLaunchKernelGGL((k_smooth_twisted<T, M1, M2, GENERIC, KEEP>), dim3(c->nblk), dim3(128), lds, c->stream,
                            c->patch, L, g, c->nx, c->ny, w, w4, c->bx, c->by, c->Nx, sc, U, Pr);
     }
 }
 
+// LDS bytes of the smoother launch: the input vectors, mid, the middle pivot block,
+// the chain slots (the widest patch and the tallest) and, for the second smoothing,
+// the z1' tile and the coarse coefficients
+template <typename T>
+size_t smooth_lds(const tgms_ctx* c, bool keep, int mw, const PreResidual<T>* pr) {
+    const long long trip = tw_trip(mw), sw = trip + tw_b3(mw);
+    long long words = 2 * ((c->pat_nmax + 3) & ~3LL) + 128 + trip + (keep ? 2LL * (c->pat_hmax / 2) : 4LL) * sw;
+    size_t bytes = (size_t)words * sizeof(T);
+    if (pr && pr->z1) bytes += 16 + (size_t)c->pat_zmax * sizeof(double) + 9 * (size_t)pr->mu * sizeof(T);
+    return bytes;
+}
+
 // m1 >= m2: the two row widths present among the patches (equal when all
 // patches have one width, -1 when there are more than two)
-template <typename T, int MODE>
-void dispatch_mode(tgms_ctx* c, int m1, int m2, const T* L, const T* g, T* w, size_t lds, const double* sc,
+template <typename T, bool KEEP>
+bool dispatch_keep(tgms_ctx* c, int m1, int m2, const T* L, const T* g, T* w, const double* sc,
                    const FusedUpdate& U, const PreResidual<T>& Pr) {
-#define TGMS_TW_CASE(A, B)                                        \
-    if (m1 == A && (m2 == B || m2 == A)) {                        \
-        launch_tw<T, A, B, false, MODE>(c, L, g, w, lds, sc, U, Pr); \
-        return;                                                   \
+#define TGMS_TW_CASE(A, B)                                                     \
+    if (m1 == A && (m2 == B || m2 == A)) {                                     \
+        const size_t lds = smooth_lds<T>(c, KEEP, A, &Pr);                     \
+        if (lds + 64 > (size_t)c->lds_max) return false;                       \
+        launch_tw<T, A, B, false, KEEP>(c, L, g, w, lds, sc, U, Pr);           \
+        return true;                                                           \
     }
     TGMS_TW_PAIRS(TGMS_TW_CASE)
 #undef TGMS_TW_CASE
-    launch_tw<T, 0, 0, true, MODE == 1 ? 1 : 0>(c, L, g, w, lds, sc, U, Pr);
-}
-
-template <typename T>
-void dispatch_twisted(tgms_ctx* c, int m1, int m2, int mode, const T* L, const T* g, T* w, size_t lds,
-                      const double* sc, const FusedUpdate& U, const PreResidual<T>& Pr) {
-    if (mode == 1)
-        dispatch_mode<T, 1>(c, m1, m2, L, g, w, lds, sc, U, Pr);
-    else if (mode == 2)
-        dispatch_mode<T, 2>(c, m1, m2, L, g, w, lds, sc, U, Pr);
-    else
-        dispatch_mode<T, 0>(c, m1, m2, L, g, w, lds, sc, U, Pr);
+    launch_tw<T, 0, 0, true, false>(c, L, g, w, smooth_lds<T>(c, false, 0, &Pr), sc, U, Pr);
+    return true;
 }
 
 template <typename T>
 void allow_lds(int lds_max) {
     auto set = [&](const void* f) { (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max); };
 #define TGMS_TW_ATTR(A, B)                                 \
-    set((const void*)k_smooth_twisted<T, A, B, false, 1>); \
-    set((const void*)k_smooth_twisted<T, A, B, false, 2>);
+    set((const void*)k_smooth_twisted<T, A, B, false, false>); \
+    set((const void*)k_smooth_twisted<T, A, B, false, true>);
     TGMS_TW_PAIRS(TGMS_TW_ATTR)
 #undef TGMS_TW_ATTR
-    set((const void*)k_smooth_twisted<T, 0, 0, true, 1>);
+    set((const void*)k_smooth_twisted<T, 0, 0, true, false>);
 }
 
 }  // namespace
@@ -705,18 +794,18 @@ void smooth_patches(tgms_ctx* c, const T* g, const double* sc, const FusedUpdate
         L = (const T*)c->patL32;
         w = (T*)c->patW32;
     }
-    size_t work = (size_t)(2 * ((c->pat_nmax + 3) & ~3) + 2 * 64) * sizeof(T);
-    if (pr && pr->z1)  // the patch tile of z1' (16-byte aligned) and the coarse coefficients
-        work += 16 + (size_t)c->pat_zmax * sizeof(double) + 9 * (size_t)pr->mu * sizeof(T);
-    const size_t staged = (size_t)((c->pat_fmax + 3) & ~3LL) * sizeof(T) + work;
-    // 1 / 2 (staged before / during the forward sweeps) where the factor fits in LDS (+ the
-    // static scalars), else 0 (direct reads); -1: staged before where it fits
-    int mode = c->smooth_staged < 0 ? 1 : c->smooth_staged;
-    if (mode != 0 && staged + 64 > (size_t)c->lds_max) mode = 0;
+    // 1: the forward chains' blocks kept in LDS for the backward chains (where they
+    // fit); 0 (and -1): staged twice, two slots per wave
     const FusedUpdate none{};
     const PreResidual<T> plain{};
-    dispatch_twisted<T>(c, c->pat_m1, c->pat_m2, mode, L, g, w, mode ? staged : work, sc, fu ? *fu : none,
-                        pr ? *pr : plain);
+    const FusedUpdate& U = fu ? *fu : none;
+    const PreResidual<T>& P = pr ? *pr : plain;
+    if (c->smooth_staged == 1 && dispatch_keep<T, true>(c, c->pat_m1, c->pat_m2, L, g, w, sc, U, P)) {
+        LAUNCH_OK();
+        return;
+    }
+    if (!dispatch_keep<T, false>(c, c->pat_m1, c->pat_m2, L, g, w, sc, U, P))
+        throw TgmsError{TGMS_E_UNSUPPORTED, "smoother patch too large for LDS"};
     LAUNCH_OK();
 }
 template void smooth_patches<double>(tgms_ctx*, const double*, const double*, const FusedUpdate*,

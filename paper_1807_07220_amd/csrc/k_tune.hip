@@ -10,9 +10,9 @@
 //                  rows per thread in their tiles (1, 4): fewer partials to sum
 //                  against more tiles per workgroup, and more loads in flight per
 //                  thread against fewer workgroups with work;
-//   smooth_staged  smoother patch factor read by the chains from global memory (0),
-//                  staged in LDS with 16-byte copies before the sweeps (1), or staged by
-//                  two waves while the other two run the forward sweeps (2).
+//   smooth_staged  smoother: each chain step's blocks staged in LDS by the forward and
+//                  again by the backward chains (0), or kept in LDS from the forward
+//                  chains for the backward ones (1).
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -125,20 +125,18 @@ void autotune(tgms_ctx* c, const char* cache_path) {
         }
     c->nred = best.nred;
     c->rpt = best.rpt;
-    // smoother: direct reads, staged before or during the forward sweeps (a staged mode
-    // whose factor does not fit in LDS runs as direct reads)
+    // smoother: every step's blocks staged twice (forward and backward chains) or kept
+    // in LDS from the forward chains (fewer bytes, fewer workgroups per CU)
     const bool prec32 = c->precision != 0;
-    double ts[3] = {1e30, 1e30, 1e30};
+    double ts[2] = {1e30, 1e30};
     // timed as whole two-grid applications: the solve's smoothings also form their
     // right-hand sides, which changes the balance between the modes
     (void)prec32;
-    for (int st = 0; st < 3; ++st) {
+    for (int st = 0; st < 2; ++st) {
         c->smooth_staged = st;
         ts[st] = time_ms(c, 3, [&] { twogrid_probe(c); });
     }
-    best.staged = 0;
-    for (int st = 1; st < 3; ++st)
-        if (ts[st] < ts[best.staged]) best.staged = st;
+    best.staged = ts[1] < ts[0] ? 1 : 0;
     c->smooth_staged = best.staged;
     HIP_OK(hipStreamSynchronize(c->stream));
     c->tuned = 1;

@@ -343,7 +343,7 @@ def test_autotune_cache(tmp_path):
     cache = tmp_path / "tune.txt"
     s1 = tg.Solver(dev(kappa), bx, by, 0.5, tune_cache=str(cache))
     i1 = s1.info()
-    assert i1["tuned"] in (1, 2) and i1["nred"] in (64, 128, 256) and i1["smooth_staged"] in (0, 1, 2)
+    assert i1["tuned"] in (1, 2) and i1["nred"] in (64, 128, 256, 512, 1024) and i1["smooth_staged"] in (0, 1)
     assert i1["rows_per_thread"] in (1, 4)
     text = cache.read_text()
     assert "40x24/b8x8" in text
@@ -362,12 +362,12 @@ def test_autotune_cache(tmp_path):
         assert np.linalg.norm(host(r["u"]) - ro["u"]) <= 1e-10 * np.linalg.norm(ro["u"])
 
 
-@pytest.mark.parametrize("staging,rpt", [(0, 1), (1, 1), (2, 1), (0, 4), (1, 4), (2, 4)])
+@pytest.mark.parametrize("staging,rpt", [(0, 1), (1, 1), (0, 4), (1, 4)])
 def test_launch_variants_match_oracle(staging, rpt):
-    """Every launch variant the autotuner can pick (smoother factor read from global
-    memory, staged in LDS before the sweeps, or staged during the forward sweeps; one
-    or four vertex rows per thread in the tiled PCG kernels) gives the oracle's
-    preconditioner and solution."""
+    """Every launch variant the autotuner can pick (smoother blocks staged in LDS by the
+    forward and again by the backward chains, or kept there between them; one or four
+    vertex rows per thread in the tiled PCG kernels) gives the oracle's preconditioner
+    and solution."""
     import paper_1807_07220_amd as tg
     nx, ny, bx, by, gen, tol = CASES["chan64"]
     kappa = gen()
@@ -418,10 +418,10 @@ def test_overlap_zero_rejected():
         tg.Solver(dev(np.ones((32, 32))), 8, 8, 0.5, overlap=0)
 
 
-@pytest.mark.parametrize("staging", [0, 1, 2])
+@pytest.mark.parametrize("staging", [0, 1])
 def test_mixed_smoother_modes_match_oracle(staging):
-    """The FP32 smoother with its factor read from global memory or staged in LDS
-    keeps the mixed-precision solution within 1e-8 of the FP64 oracle's."""
+    """The FP32 smoother in either staging mode keeps the mixed-precision solution
+    within 1e-8 of the FP64 oracle's."""
     import paper_1807_07220_amd as tg
     nx, ny, bx, by, gen, tol = CASES["chan64"]
     kappa = gen()
