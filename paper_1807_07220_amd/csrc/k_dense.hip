@@ -787,6 +787,129 @@ __global__ void __launch_bounds__(SNT) k_bcr_bwd(BcrView<T> F, T* __restrict__ x
     bcr_gemv<T>(F.CT + i * bb, t, nullptr, nullptr, bs, x + (long long)i * bs);
 }
 
+// The same three kernels with every matrix entry a thread uses loaded into registers
+// at entry: row r = tid / SGX of each bs x bs block, columns l + SGX j (l = tid % SGX,
+// j < KM; bs <= SNT / SGX and bs <= SGX KM), so one memory latency per launch instead
+// of one per product.  Waves whose rows all lie beyond bs skip the loads and sums
+// (a wave-uniform test); the others read clamped addresses unconditionally (an entry
+// beyond bs, or a missing neighbour block, re-reads a valid one) and the sums mask
+// what is not needed, so nothing waits on a load before all are in flight.
+template <typename T, int SGX, int KM>
+struct BcrRows {
+    T a[KM];
+    __device__ __attribute__((always_inline)) void load(const T* __restrict__ M, int bs) {
+        const int r = min((int)threadIdx.x / SGX, bs - 1), l = threadIdx.x % SGX;
+#pragma unroll
+        for (int j = 0; j < KM; ++j) a[j] = M[(long long)r * bs + min(l + SGX * j, bs - 1)];
+    }
+};
+
+// this wave holds at least one row of a bs x bs block
+template <int SGX>
+__device__ inline bool bcr_wave_live(int bs) {
+    return (int)(threadIdx.x & ~63u) / SGX < bs;
+}
+
+// out[r] = sum_k A[r][k] v1[k] (+ B[r][k] v2[k] when `two`), from the preloaded rows
+template <typename T, int SGX, int KM>
+__device__ __attribute__((always_inline)) inline void bcr_gemv_rows(const BcrRows<T, SGX, KM>& A, const T* v1,
+                                                                    const BcrRows<T, SGX, KM>& B, bool two,
+                                                                    const T* v2, int bs, T* out) {
+    const int r = threadIdx.x / SGX, l = threadIdx.x % SGX;
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+        const int k = l + SGX * j;
+        if (r < bs && k < bs) acc += A.a[j] * v1[k] + (two ? B.a[j] * v2[k] : T(0));
+    }
+#pragma unroll
+    for (int o = SGX / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (r < bs && l == 0) out[r] = acc;
+}
+
+template <typename T, int SGX, int KM>
+__global__ void __launch_bounds__(SNT) k_bcr_fwd_r(BcrView<T> F, T* __restrict__ x, T* __restrict__ Y, int bs,
+                                                  int nblk, int s, const double* __restrict__ sc) {
+    if (sc != nullptr && sc[SC_DONE] != 0.0) return;
+    const int e = 2 * s * blockIdx.x;
+    if (e >= nblk) return;
+    __shared__ T bl[BCR_SOLVE_MAX], br[BCR_SOLVE_MAX], yl[BCR_SOLVE_MAX], yr[BCR_SOLVE_MAX], t[BCR_SOLVE_MAX];
+    const int tid = threadIdx.x;
+    const long long bb = (long long)bs * bs;
+    const bool h1 = e >= s, h2 = e + s < nblk;
+    const int i1 = h1 ? e - s : e, i2 = h2 ? e + s : e;  // clamped: a missing neighbour reads block e
+    const bool live = bcr_wave_live<SGX>(bs);
+    BcrRows<T, SGX, KM> c1, c2, g1, g2;
+    if (live) {
+        c1.load(F.C + i1 * bb, bs);
+        c2.load(F.C + i2 * bb, bs);
+        g1.load(h1 ? F.GpT + i1 * bb : F.GmT + i2 * bb, bs);
+        g2.load(F.GmT + i2 * bb, bs);
+    }
+    for (int r = tid; r < bs; r += SNT) {
+        bl[r] = h1 ? x[(long long)i1 * bs + r] : T(0);
+        br[r] = h2 ? x[(long long)i2 * bs + r] : T(0);
+    }
+    __syncthreads();
+    if (live) {
+        bcr_gemv_rows<T, SGX, KM>(c1, bl, c1, false, bl, bs, yl);
+        bcr_gemv_rows<T, SGX, KM>(c2, br, c2, false, br, bs, yr);
+    }
+    __syncthreads();
+    if (h2)
+        for (int r = tid; r < bs; r += SNT) Y[(long long)i2 * bs + r] = yr[r];
+    if (live) bcr_gemv_rows<T, SGX, KM>(g1, h1 ? yl : yr, g2, h1 && h2, yr, bs, t);
+    __syncthreads();
+    for (int r = tid; r < bs; r += SNT) x[(long long)e * bs + r] -= t[r];
+}
+
+template <typename T, int SGX, int KM>
+__global__ void __launch_bounds__(SNT) k_bcr_top_r(BcrView<T> F, T* __restrict__ x, int bs,
+                                                  const double* __restrict__ sc) {
+    if (sc != nullptr && sc[SC_DONE] != 0.0) return;
+    __shared__ T b[BCR_SOLVE_MAX], y[BCR_SOLVE_MAX];
+    const bool live = bcr_wave_live<SGX>(bs);
+    BcrRows<T, SGX, KM> c, ct;
+    if (live) {
+        c.load(F.C, bs);
+        ct.load(F.CT, bs);
+    }
+    for (int r = threadIdx.x; r < bs; r += SNT) b[r] = x[r];
+    __syncthreads();
+    if (live) bcr_gemv_rows<T, SGX, KM>(c, b, c, false, b, bs, y);
+    __syncthreads();
+    if (live) bcr_gemv_rows<T, SGX, KM>(ct, y, ct, false, y, bs, x);
+}
+
+template <typename T, int SGX, int KM>
+__global__ void __launch_bounds__(SNT) k_bcr_bwd_r(BcrView<T> F, T* __restrict__ x, const T* __restrict__ Y,
+                                                  int bs, int nblk, int s, const double* __restrict__ sc) {
+    if (sc != nullptr && sc[SC_DONE] != 0.0) return;
+    const int i = s + 2 * s * blockIdx.x;
+    if (i >= nblk) return;
+    __shared__ T xa[BCR_SOLVE_MAX], xb[BCR_SOLVE_MAX], t[BCR_SOLVE_MAX];
+    const int tid = threadIdx.x;
+    const long long bb = (long long)bs * bs;
+    const bool hb = i + s < nblk;
+    const bool live = bcr_wave_live<SGX>(bs);
+    BcrRows<T, SGX, KM> gm, gp, ct;
+    if (live) {
+        gm.load(F.Gm + i * bb, bs);
+        gp.load(F.Gp + i * bb, bs);  // unused without the upper neighbour
+        ct.load(F.CT + i * bb, bs);
+    }
+    for (int r = tid; r < bs; r += SNT) {
+        xa[r] = x[(long long)(i - s) * bs + r];
+        xb[r] = hb ? x[(long long)(i + s) * bs + r] : T(0);
+    }
+    __syncthreads();
+    if (live) bcr_gemv_rows<T, SGX, KM>(gm, xa, gp, hb, xb, bs, t);
+    __syncthreads();
+    for (int r = tid; r < bs; r += SNT) t[r] = Y[(long long)i * bs + r] - t[r];
+    __syncthreads();
+    if (live) bcr_gemv_rows<T, SGX, KM>(ct, t, ct, false, t, bs, x + (long long)i * bs);
+}
+
 // B_i = A_i^T for every block
 __global__ void k_bcr_transpose(const double* __restrict__ A, double* __restrict__ B, int bs, long long tot) {
     const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -1237,6 +1360,23 @@ bool bcr_failed(tgms_ctx* c, const Bcr& F) {
     return h != 0;
 }
 
+template <typename T, int SGX, int KM>
+void bcr_solve_r(tgms_ctx* c, const BcrView<T>& V, T* x, T* Y, int bs, int nblk, int top, const double* sc) {
+    for (int s = 1; s < nblk; s *= 2) {
+        hipLaunchKernelGGL((k_bcr_fwd_r<T, SGX, KM>), dim3((nblk - 1) / (2 * s) + 1), dim3(SNT), 0, c->stream, V, x,
+                           Y, bs, nblk, s, sc);
+        LAUNCH_OK();
+    }
+    hipLaunchKernelGGL((k_bcr_top_r<T, SGX, KM>), dim3(1), dim3(SNT), 0, c->stream, V, x, bs, sc);
+    LAUNCH_OK();
+    for (int s = top / 2; s >= 1; s /= 2) {
+        if (s >= nblk) continue;
+        hipLaunchKernelGGL((k_bcr_bwd_r<T, SGX, KM>), dim3((nblk - s - 1) / (2 * s) + 1), dim3(SNT), 0, c->stream,
+                           V, x, (const T*)Y, bs, nblk, s, sc);
+        LAUNCH_OK();
+    }
+}
+
 template <typename T>
 void bcr_solve(tgms_ctx* c, const Bcr& F, T* x, const double* sc) {
     BcrView<T> V;
@@ -1252,6 +1392,22 @@ void bcr_solve(tgms_ctx* c, const Bcr& F, T* x, const double* sc) {
     const int nblk = F.nb, bs = F.bs;
     int top = 1;
     while (top < nblk) top *= 2;
+    // blocks of up to 64 rows (16 lanes a row), 72 rows (8 lanes a row) and, in FP32,
+    // 128 rows: the register-prefetched kernels
+    if (bs <= 64) {
+        bcr_solve_r<T, 16, 4>(c, V, x, Y, bs, nblk, top, sc);
+        return;
+    }
+    if (bs <= 72) {
+        bcr_solve_r<T, 8, 9>(c, V, x, Y, bs, nblk, top, sc);
+        return;
+    }
+    if constexpr (sizeof(T) == 4) {
+        if (bs <= 128) {
+            bcr_solve_r<T, 8, 16>(c, V, x, Y, bs, nblk, top, sc);
+            return;
+        }
+    }
     for (int s = 1; s < nblk; s *= 2) {
         hipLaunchKernelGGL((k_bcr_fwd<T>), dim3((nblk - 1) / (2 * s) + 1), dim3(SNT), 0, c->stream, V, x, Y, bs, nblk,
                            s, sc);
