@@ -758,8 +758,64 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                     tgms::bcr_factor(c, c->KH, c->nv, std::max(c->Nx, 1), c->kb, false);  // checked at the join
                 else
                     tgms::dense_spd_inverse_begin(c, c->KH, c->nv, kh_inv);
+                HIP_OK(hipEventRecord(side.e1, side.s));
+                // smoother patches (section 5): factorised on this second stream after the
+                // coarse RT0 operator, concurrently with the spectral setup on the main one
+                // (the patch matrices depend on the cell weights only)
+                c->patch_h.resize(c->nblk);
+                long long off = 0, voff = 0;
+                std::set<int> widths;
+                for (int J = 0; J < c->Ny; ++J)
+                    for (int I = 0; I < c->Nx; ++I) {
+                        Rect& r = c->patch_h[J * c->Nx + I];
+                        r.i0 = std::max(I * bx - o.overlap, 0);
+                        r.i1 = std::min((I + 1) * bx + o.overlap, nx);
+                        r.j0 = std::max(J * by - o.overlap, 0);
+                        r.j1 = std::min((J + 1) * by + o.overlap, ny);
+                        const int m = r.i1 - r.i0 - 1, n = m * (r.j1 - r.j0 - 1);
+                        r.off = off;
+                        r.voff = voff;
+                        off += (tw_size(m, r.j1 - r.j0 - 1) + 3) & ~3LL;  // 16-byte aligned factors
+                        c->pat_fmax = std::max(c->pat_fmax, tw_size(m, r.j1 - r.j0 - 1));
+                        c->pat_zmax = std::max(c->pat_zmax, (long long)(r.i1 - r.i0 + 1) * (r.j1 - r.j0 + 1));
+                        voff += n;
+                        c->pat_nmax = std::max(c->pat_nmax, n);
+                        c->pat_hmax = std::max(c->pat_hmax, r.j1 - r.j0 - 1);
+                        c->pat_bmax = std::max(c->pat_bmax, m + 1);
+                        widths.insert(m);
+                    }
+                // the kernels take fixed-width paths for up to two distinct row widths
+                c->pat_m1 = *widths.rbegin();
+                c->pat_m2 = widths.size() == 1 ? c->pat_m1 : widths.size() == 2 ? *widths.begin() : -1;
+                c->pat_pool = off;
+                c->pat_vpool = voff;
+                c->patch = c->alloc<Rect>(c->nblk);
+                HIP_OK(hipMemcpyAsync(c->patch, c->patch_h.data(), sizeof(Rect) * c->nblk, hipMemcpyHostToDevice,
+                                      c->stream));
+                c->patL = c->alloc<double>(off);
+                c->patW = c->alloc<double>(voff);
+                if (c->precision) {
+                    c->patL32 = c->alloc<float>(off);
+                    c->patW32 = c->alloc<float>(voff);
+                }
+                // a vertex is covered by its own block's patch and, when blocks are at least
+                // twice the overlap, by at most one neighbour per direction: four slots
+                c->slots = bx >= 2 * o.overlap && by >= 2 * o.overlap;
+                if (c->slots) {
+                    c->patW4 = c->alloc<double>(4 * (size_t)ncell);  // zero: slots no patch covers stay zero
+                    if (c->precision) c->patW4_32 = c->alloc<float>(4 * (size_t)ncell);
+                }
+                pat_fail = c->alloc<int>(1);
+                pat_timer.start(side.s);
+                // two workgroups per CU: the spectral setup on the main stream keeps CUs to
+                // run on
+                int cus = 0, dev = 0;
+                HIP_OK(hipGetDevice(&dev));
+                if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+                tgms::factor_patches_launch(c, pat_fail, 2 * cus);
+                pat_timer.stop(side.s);
+                HIP_OK(hipEventRecord(side.e2, side.s));
             }
-            HIP_OK(hipEventRecord(side.e1, side.s));
             c->t_snap_ms = t.ms();
             // the block factorisation, checked once the GPU has reached this point (before
             // the spectral problems use the snapshots)
@@ -835,71 +891,6 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                 tgms::fill_td(c, metad, YQd, c->Td);
                 tgms::coarse_local_run(c, c->Td, c->zcd);
             }
-            // smoother patches (section 5): factorised on the second stream while the
-            // dense coarse factorisation, a chain of small kernels, runs on this one
-            c->patch_h.resize(c->nblk);
-            long long off = 0, voff = 0;
-            std::set<int> widths;
-            for (int J = 0; J < c->Ny; ++J)
-                for (int I = 0; I < c->Nx; ++I) {
-                    Rect& r = c->patch_h[J * c->Nx + I];
-                    r.i0 = std::max(I * bx - o.overlap, 0);
-                    r.i1 = std::min((I + 1) * bx + o.overlap, nx);
-                    r.j0 = std::max(J * by - o.overlap, 0);
-                    r.j1 = std::min((J + 1) * by + o.overlap, ny);
-                    const int m = r.i1 - r.i0 - 1, n = m * (r.j1 - r.j0 - 1);
-                    r.off = off;
-                    r.voff = voff;
-                    off += (tw_size(m, r.j1 - r.j0 - 1) + 3) & ~3LL;  // 16-byte aligned factors
-                    c->pat_fmax = std::max(c->pat_fmax, tw_size(m, r.j1 - r.j0 - 1));
-                    c->pat_zmax = std::max(c->pat_zmax, (long long)(r.i1 - r.i0 + 1) * (r.j1 - r.j0 + 1));
-                    voff += n;
-                    c->pat_nmax = std::max(c->pat_nmax, n);
-                    c->pat_hmax = std::max(c->pat_hmax, r.j1 - r.j0 - 1);
-                    c->pat_bmax = std::max(c->pat_bmax, m + 1);
-                    widths.insert(m);
-                }
-            // the kernels take fixed-width paths for up to two distinct row widths
-            c->pat_m1 = *widths.rbegin();
-            c->pat_m2 = widths.size() == 1 ? c->pat_m1 : widths.size() == 2 ? *widths.begin() : -1;
-            c->pat_pool = off;
-            c->pat_vpool = voff;
-            c->patch = c->alloc<Rect>(c->nblk);
-            HIP_OK(hipMemcpyAsync(c->patch, c->patch_h.data(), sizeof(Rect) * c->nblk, hipMemcpyHostToDevice, c->stream));
-            c->patL = c->alloc<double>(off);
-            c->patW = c->alloc<double>(voff);
-            if (c->precision) {
-                c->patL32 = c->alloc<float>(off);
-                c->patW32 = c->alloc<float>(voff);
-            }
-            // a vertex is covered by its own block's patch and, when blocks are at least
-            // twice the overlap, by at most one neighbour per direction: four slots
-            c->slots = bx >= 2 * o.overlap && by >= 2 * o.overlap;
-            if (c->slots) {
-                c->patW4 = c->alloc<double>(4 * (size_t)ncell);  // zero: slots no patch covers stay zero
-                if (c->precision) c->patW4_32 = c->alloc<float>(4 * (size_t)ncell);
-            }
-            pat_fail = c->alloc<int>(1);
-            HIP_OK(hipEventRecord(side.e0, c->stream));
-            HIP_OK(hipStreamWaitEvent(side.s, side.e0, 0));
-            {
-                const hipStream_t main_stream = c->stream;
-                struct Restore {
-                    tgms_ctx* c;
-                    hipStream_t s;
-                    ~Restore() { c->stream = s; }
-                } restore{c, main_stream};
-                c->stream = side.s;
-                pat_timer.start(side.s);
-                // two workgroups per CU: the serial chain of the coarse Cholesky on the
-                // main stream keeps CUs to run on
-                int cus = 0, dev = 0;
-                HIP_OK(hipGetDevice(&dev));
-                if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
-                tgms::factor_patches_launch(c, pat_fail, 2 * cus);
-                pat_timer.stop(side.s);
-            }
-            HIP_OK(hipEventRecord(side.e2, side.s));
             factor_coarse(c);
             c->cy = c->alloc<double>((size_t)c->nblk * c->mu);
             c->cvec = c->alloc<double>(2 * (size_t)c->ncs + 1);
