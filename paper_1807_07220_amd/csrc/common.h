@@ -131,9 +131,13 @@ struct DeviceBuf {
 struct Bcr {
     int n = 0, bs = 0, nb = 0;
     double *D = nullptr, *Lc = nullptr, *C = nullptr, *Gm = nullptr, *Gp = nullptr, *Y = nullptr, *x = nullptr;
-    double *CT = nullptr, *GmT = nullptr, *GpT = nullptr;  // transposes (the solve reads rows only)
-    float *C32 = nullptr, *Gm32 = nullptr, *Gp32 = nullptr, *Y32 = nullptr, *x32 = nullptr;
-    float *CT32 = nullptr, *GmT32 = nullptr, *GpT32 = nullptr;
+    // the products the FP64 solve applies (row-major blocks): Gp^T C, Gm^T C (forward),
+    // C^T Gm, C^T Gp (backward) and C^T C = D^{-1}
+    double *PGP = nullptr, *PGM = nullptr, *QGM = nullptr, *QGP = nullptr, *R = nullptr;
+    // the FP32 solve's factors (two-step form): C, its transpose, Gm, Gp and theirs
+    double *CT = nullptr, *GmT = nullptr, *GpT = nullptr;
+    float *C32 = nullptr, *Gm32 = nullptr, *Gp32 = nullptr, *CT32 = nullptr, *GmT32 = nullptr, *GpT32 = nullptr;
+    float *Y32 = nullptr, *x32 = nullptr;
     int* fail = nullptr;
 };
 

@@ -675,20 +675,147 @@ __global__ void k_d2f(const double* __restrict__ x, float* __restrict__ y, long 
     if (e < n) y[e] = (float)x[e];
 }
 
-// The solve kernels: 1024 threads, each row of a product handled by 16 lanes, every
-// load of a row slot issued before its sums (the level kernels are latency-bound).
-constexpr int SNT = 1024;
+// The solve.  With R_i = C_i^T C_i = D_i^{-1} and the products Gp_i^T C_i, Gm_i^T C_i,
+// C_i^T Gm_i, C_i^T Gp_i formed once per factorisation, every level is one set of
+// independent block products:
+//   forward, e = 0, 2s, 4s, ...:  x_e -= (Gp^T C)_{e-s} x_{e-s} + (Gm^T C)_{e+s} x_{e+s},
+//                                 Y_{e+s} = R_{e+s} x_{e+s};
+//   block 0:                      x_0 = R_0 x_0;
+//   backward, i = s, 3s, ...:     x_i = Y_i - (C^T Gm)_i x_{i-s} - (C^T Gp)_i x_{i+s},
+// where each level reads only blocks it does not write.  The rows of every level are
+// split over workgroups of 256 threads (16 rows, 16 lanes a row): a launch is one
+// memory latency with every product's loads in flight, spread over many CUs.  Loads
+// read clamped addresses unconditionally (an entry beyond bs, or a missing neighbour
+// block, re-reads a valid one) and the sums mask what is not needed.
+constexpr int SNT = 256;
 constexpr int SG = 16;
+constexpr int SROWS = SNT / SG;
 constexpr int BCR_SOLVE_MAX = 144;
-constexpr int SKM = (BCR_SOLVE_MAX + SG - 1) / SG;
+
+template <typename T>
+struct BcrView {
+    const T *PGP, *PGM, *QGM, *QGP, *R;
+};
+
+template <typename T, int KM>
+__global__ void __launch_bounds__(SNT) k_bcr_fwd(BcrView<T> F, T* __restrict__ x, T* __restrict__ Y, int bs,
+                                                int nblk, int s, int chunks, const double* __restrict__ sc) {
+    if (sc != nullptr && sc[SC_DONE] != 0.0) return;
+    const int pos = blockIdx.x / chunks, ch = blockIdx.x - pos * chunks;
+    const int e = 2 * s * pos;
+    const int r = ch * SROWS + (int)threadIdx.x / SG, l = threadIdx.x % SG, rc = min(r, bs - 1);
+    const bool h1 = e >= s, h2 = e + s < nblk;
+    const int i1 = h1 ? e - s : e, i2 = h2 ? e + s : e;
+    const long long bb = (long long)bs * bs;
+    const T* a1 = F.PGP + i1 * bb + (long long)rc * bs;
+    const T* a2 = F.PGM + i2 * bb + (long long)rc * bs;
+    const T* a3 = F.R + i2 * bb + (long long)rc * bs;
+    const T* v1 = x + (long long)i1 * bs;
+    const T* v2 = x + (long long)i2 * bs;
+    T p1[KM], p2[KM], p3[KM], w1[KM], w2[KM];
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+        const int k = min(l + SG * j, bs - 1);
+        p1[j] = a1[k];
+        p2[j] = a2[k];
+        p3[j] = a3[k];
+        w1[j] = v1[k];
+        w2[j] = v2[k];
+    }
+    T t = T(0), y = T(0);
+#pragma unroll
+    for (int j = 0; j < KM; ++j)
+        if (l + SG * j < bs) {
+            t += (h1 ? p1[j] * w1[j] : T(0)) + (h2 ? p2[j] * w2[j] : T(0));
+            y += p3[j] * w2[j];
+        }
+#pragma unroll
+    for (int o = SG / 2; o > 0; o >>= 1) {
+        t += __shfl_xor(t, o, 64);
+        y += __shfl_xor(y, o, 64);
+    }
+    if (r < bs && l == 0) {
+        x[(long long)e * bs + r] -= t;
+        if (h2) Y[(long long)i2 * bs + r] = y;
+    }
+}
+
+// x_0 = R_0 x_0: one workgroup of 1024 threads (64 rows a pass), x_0 staged in LDS
+// first (the rows overwrite it)
+constexpr int TNT = 1024;
+template <typename T, int KM>
+__global__ void __launch_bounds__(TNT) k_bcr_top(BcrView<T> F, T* __restrict__ x, int bs,
+                                                const double* __restrict__ sc) {
+    if (sc != nullptr && sc[SC_DONE] != 0.0) return;
+    __shared__ T b[BCR_SOLVE_MAX];
+    for (int r = threadIdx.x; r < bs; r += TNT) b[r] = x[r];
+    __syncthreads();
+    const int l = threadIdx.x % SG;
+    for (int r0 = 0; r0 < bs; r0 += TNT / SG) {
+        const int r = r0 + (int)threadIdx.x / SG, rc = min(r, bs - 1);
+        const T* a = F.R + (long long)rc * bs;
+        T p[KM];
+#pragma unroll
+        for (int j = 0; j < KM; ++j) p[j] = a[min(l + SG * j, bs - 1)];
+        T y = T(0);
+#pragma unroll
+        for (int j = 0; j < KM; ++j)
+            if (l + SG * j < bs) y += p[j] * b[l + SG * j];
+#pragma unroll
+        for (int o = SG / 2; o > 0; o >>= 1) y += __shfl_xor(y, o, 64);
+        if (r < bs && l == 0) x[r] = y;
+    }
+}
+
+template <typename T, int KM>
+__global__ void __launch_bounds__(SNT) k_bcr_bwd(BcrView<T> F, T* __restrict__ x, const T* __restrict__ Y, int bs,
+                                                int nblk, int s, int chunks, const double* __restrict__ sc) {
+    if (sc != nullptr && sc[SC_DONE] != 0.0) return;
+    const int pos = blockIdx.x / chunks, ch = blockIdx.x - pos * chunks;
+    const int i = s + 2 * s * pos;
+    const int r = ch * SROWS + (int)threadIdx.x / SG, l = threadIdx.x % SG, rc = min(r, bs - 1);
+    const bool hb = i + s < nblk;
+    const int ib = hb ? i + s : i;
+    const long long bb = (long long)bs * bs;
+    const T* a1 = F.QGM + i * bb + (long long)rc * bs;
+    const T* a2 = F.QGP + i * bb + (long long)rc * bs;
+    const T* v1 = x + (long long)(i - s) * bs;
+    const T* v2 = x + (long long)ib * bs;
+    T p1[KM], p2[KM], w1[KM], w2[KM];
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+        const int k = min(l + SG * j, bs - 1);
+        p1[j] = a1[k];
+        p2[j] = a2[k];
+        w1[j] = v1[k];
+        w2[j] = v2[k];
+    }
+    const T yi = Y[(long long)i * bs + rc];
+    T t = T(0);
+#pragma unroll
+    for (int j = 0; j < KM; ++j)
+        if (l + SG * j < bs) t += p1[j] * w1[j] + (hb ? p2[j] * w2[j] : T(0));
+#pragma unroll
+    for (int o = SG / 2; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if (r < bs && l == 0) x[(long long)i * bs + r] = yi - t;
+}
+
+// The FP32 solve: the two-step form (C_i b, then the couplings), each level one
+// workgroup of 1024 threads per block; each row of a product handled by 16 lanes, every
+// load of a row slot issued before its sums (the level kernels are latency-bound).  The
+// product form of the FP64 solve would apply D_i^{-1} as one rounded product and lose
+// eps * kappa instead of eps * sqrt(kappa) per block in FP32.
+constexpr int SNT2 = 1024;
+constexpr int SG2 = 16;
+constexpr int SKM = (BCR_SOLVE_MAX + SG2 - 1) / SG2;
 
 // out[r] = sum_k M1[r][k] v1[k] + sum_k M2[r][k] v2[k] (r < bs; M2 may be null), M row-major
 // bs x bs, v in LDS; out to LDS or global
 template <typename T>
 __device__ inline void bcr_gemv(const T* __restrict__ M1, const T* v1, const T* __restrict__ M2, const T* v2, int bs,
                                 T* out) {
-    constexpr int NG = SNT / SG;
-    const int tid = threadIdx.x, g = tid / SG, l = tid % SG;
+    constexpr int NG = SNT2 / SG2;
+    const int tid = threadIdx.x, g = tid / SG2, l = tid % SG2;
     for (int r0 = 0; r0 < bs; r0 += NG) {
         const int r = r0 + g;
         T acc = T(0);
@@ -696,25 +823,25 @@ __device__ inline void bcr_gemv(const T* __restrict__ M1, const T* v1, const T* 
             T a[SKM], b[SKM];
 #pragma unroll
             for (int j = 0; j < SKM; ++j) {
-                const int k = l + SG * j;
+                const int k = l + SG2 * j;
                 a[j] = k < bs ? M1[(long long)r * bs + k] : T(0);
                 b[j] = (M2 != nullptr && k < bs) ? M2[(long long)r * bs + k] : T(0);
             }
 #pragma unroll
             for (int j = 0; j < SKM; ++j) {
-                const int k = l + SG * j;
+                const int k = l + SG2 * j;
                 if (k < bs) acc += a[j] * v1[k] + (M2 != nullptr ? b[j] * v2[k] : T(0));
             }
         }
 #pragma unroll
-        for (int o = SG / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        for (int o = SG2 / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
         if (r < bs && l == 0) out[r] = acc;
     }
 }
 
 // Factors the solve reads: C_i^{-1} (C), its transpose (CT), Gm, Gp and their transposes.
 template <typename T>
-struct BcrView {
+struct BcrView2 {
     const T *C, *CT, *Gm, *Gp, *GmT, *GpT;
 };
 
@@ -722,7 +849,7 @@ struct BcrView {
 // neighbours (y_k = C_k^{-1} b_k), keeps y_{e+s} in Y, and takes
 // b_e -= Gp_{e-s}^T y_{e-s} + Gm_{e+s}^T y_{e+s}.
 template <typename T>
-__global__ void __launch_bounds__(SNT) k_bcr_fwd(BcrView<T> F, T* __restrict__ x, T* __restrict__ Y, int bs, int nblk,
+__global__ void __launch_bounds__(SNT2) k_bcr2_fwd(BcrView2<T> F, T* __restrict__ x, T* __restrict__ Y, int bs, int nblk,
                                                 int s, const double* __restrict__ sc) {
     if (sc != nullptr && sc[SC_DONE] != 0.0) return;
     const int e = 2 * s * blockIdx.x;
@@ -732,7 +859,7 @@ __global__ void __launch_bounds__(SNT) k_bcr_fwd(BcrView<T> F, T* __restrict__ x
     const long long bb = (long long)bs * bs;
     const bool h1 = e >= s, h2 = e + s < nblk;
     const int i1 = e - s, i2 = e + s;
-    for (int r = tid; r < bs; r += SNT) {
+    for (int r = tid; r < bs; r += SNT2) {
         bl[r] = h1 ? x[(long long)i1 * bs + r] : T(0);
         br[r] = h2 ? x[(long long)i2 * bs + r] : T(0);
         yl[r] = T(0);
@@ -743,20 +870,20 @@ __global__ void __launch_bounds__(SNT) k_bcr_fwd(BcrView<T> F, T* __restrict__ x
     if (h2) bcr_gemv<T>(F.C + i2 * bb, br, nullptr, nullptr, bs, yr);
     __syncthreads();
     if (h2)
-        for (int r = tid; r < bs; r += SNT) Y[(long long)i2 * bs + r] = yr[r];
+        for (int r = tid; r < bs; r += SNT2) Y[(long long)i2 * bs + r] = yr[r];
     bcr_gemv<T>(h1 ? F.GpT + i1 * bb : F.GmT + i2 * bb, h1 ? yl : yr, (h1 && h2) ? F.GmT + i2 * bb : nullptr, yr, bs,
                 t);
     __syncthreads();
-    for (int r = tid; r < bs; r += SNT) x[(long long)e * bs + r] -= t[r];
+    for (int r = tid; r < bs; r += SNT2) x[(long long)e * bs + r] -= t[r];
 }
 
 // Block 0 after the last level: x_0 = C_0^{-T} C_0^{-1} b_0.
 template <typename T>
-__global__ void __launch_bounds__(SNT) k_bcr_top(BcrView<T> F, T* __restrict__ x, int bs,
+__global__ void __launch_bounds__(SNT2) k_bcr2_top(BcrView2<T> F, T* __restrict__ x, int bs,
                                                 const double* __restrict__ sc) {
     if (sc != nullptr && sc[SC_DONE] != 0.0) return;
     __shared__ T b[BCR_SOLVE_MAX], y[BCR_SOLVE_MAX];
-    for (int r = threadIdx.x; r < bs; r += SNT) b[r] = x[r];
+    for (int r = threadIdx.x; r < bs; r += SNT2) b[r] = x[r];
     __syncthreads();
     bcr_gemv<T>(F.C, b, nullptr, nullptr, bs, y);
     __syncthreads();
@@ -766,7 +893,7 @@ __global__ void __launch_bounds__(SNT) k_bcr_top(BcrView<T> F, T* __restrict__ x
 // Backward pass of level s: x_i = C_i^{-T} (y_i - Gm_i x_{i-s} - Gp_i x_{i+s}) for the
 // blocks eliminated at this level (their neighbours are solved at higher levels).
 template <typename T>
-__global__ void __launch_bounds__(SNT) k_bcr_bwd(BcrView<T> F, T* __restrict__ x, const T* __restrict__ Y, int bs,
+__global__ void __launch_bounds__(SNT2) k_bcr2_bwd(BcrView2<T> F, T* __restrict__ x, const T* __restrict__ Y, int bs,
                                                 int nblk, int s, const double* __restrict__ sc) {
     if (sc != nullptr && sc[SC_DONE] != 0.0) return;
     const int i = s + 2 * s * blockIdx.x;
@@ -775,21 +902,21 @@ __global__ void __launch_bounds__(SNT) k_bcr_bwd(BcrView<T> F, T* __restrict__ x
     const int tid = threadIdx.x;
     const long long bb = (long long)bs * bs;
     const bool hb = i + s < nblk;
-    for (int r = tid; r < bs; r += SNT) {
+    for (int r = tid; r < bs; r += SNT2) {
         xa[r] = x[(long long)(i - s) * bs + r];
         xb[r] = hb ? x[(long long)(i + s) * bs + r] : T(0);
     }
     __syncthreads();
     bcr_gemv<T>(F.Gm + i * bb, xa, hb ? F.Gp + i * bb : nullptr, xb, bs, t);
     __syncthreads();
-    for (int r = tid; r < bs; r += SNT) t[r] = Y[(long long)i * bs + r] - t[r];
+    for (int r = tid; r < bs; r += SNT2) t[r] = Y[(long long)i * bs + r] - t[r];
     __syncthreads();
     bcr_gemv<T>(F.CT + i * bb, t, nullptr, nullptr, bs, x + (long long)i * bs);
 }
 
 // The same three kernels with every matrix entry a thread uses loaded into registers
 // at entry: row r = tid / SGX of each bs x bs block, columns l + SGX j (l = tid % SGX,
-// j < KM; bs <= SNT / SGX and bs <= SGX KM), so one memory latency per launch instead
+// j < KM; bs <= SNT2 / SGX and bs <= SGX KM), so one memory latency per launch instead
 // of one per product.  Waves whose rows all lie beyond bs skip the loads and sums
 // (a wave-uniform test); the others read clamped addresses unconditionally (an entry
 // beyond bs, or a missing neighbour block, re-reads a valid one) and the sums mask
@@ -828,7 +955,7 @@ __device__ __attribute__((always_inline)) inline void bcr_gemv_rows(const BcrRow
 }
 
 template <typename T, int SGX, int KM>
-__global__ void __launch_bounds__(SNT) k_bcr_fwd_r(BcrView<T> F, T* __restrict__ x, T* __restrict__ Y, int bs,
+__global__ void __launch_bounds__(SNT2) k_bcr2_fwd_r(BcrView2<T> F, T* __restrict__ x, T* __restrict__ Y, int bs,
                                                   int nblk, int s, const double* __restrict__ sc) {
     if (sc != nullptr && sc[SC_DONE] != 0.0) return;
     const int e = 2 * s * blockIdx.x;
@@ -846,7 +973,7 @@ __global__ void __launch_bounds__(SNT) k_bcr_fwd_r(BcrView<T> F, T* __restrict__
         g1.load(h1 ? F.GpT + i1 * bb : F.GmT + i2 * bb, bs);
         g2.load(F.GmT + i2 * bb, bs);
     }
-    for (int r = tid; r < bs; r += SNT) {
+    for (int r = tid; r < bs; r += SNT2) {
         bl[r] = h1 ? x[(long long)i1 * bs + r] : T(0);
         br[r] = h2 ? x[(long long)i2 * bs + r] : T(0);
     }
@@ -857,14 +984,14 @@ __global__ void __launch_bounds__(SNT) k_bcr_fwd_r(BcrView<T> F, T* __restrict__
     }
     __syncthreads();
     if (h2)
-        for (int r = tid; r < bs; r += SNT) Y[(long long)i2 * bs + r] = yr[r];
+        for (int r = tid; r < bs; r += SNT2) Y[(long long)i2 * bs + r] = yr[r];
     if (live) bcr_gemv_rows<T, SGX, KM>(g1, h1 ? yl : yr, g2, h1 && h2, yr, bs, t);
     __syncthreads();
-    for (int r = tid; r < bs; r += SNT) x[(long long)e * bs + r] -= t[r];
+    for (int r = tid; r < bs; r += SNT2) x[(long long)e * bs + r] -= t[r];
 }
 
 template <typename T, int SGX, int KM>
-__global__ void __launch_bounds__(SNT) k_bcr_top_r(BcrView<T> F, T* __restrict__ x, int bs,
+__global__ void __launch_bounds__(SNT2) k_bcr2_top_r(BcrView2<T> F, T* __restrict__ x, int bs,
                                                   const double* __restrict__ sc) {
     if (sc != nullptr && sc[SC_DONE] != 0.0) return;
     __shared__ T b[BCR_SOLVE_MAX], y[BCR_SOLVE_MAX];
@@ -874,7 +1001,7 @@ __global__ void __launch_bounds__(SNT) k_bcr_top_r(BcrView<T> F, T* __restrict__
         c.load(F.C, bs);
         ct.load(F.CT, bs);
     }
-    for (int r = threadIdx.x; r < bs; r += SNT) b[r] = x[r];
+    for (int r = threadIdx.x; r < bs; r += SNT2) b[r] = x[r];
     __syncthreads();
     if (live) bcr_gemv_rows<T, SGX, KM>(c, b, c, false, b, bs, y);
     __syncthreads();
@@ -882,7 +1009,7 @@ __global__ void __launch_bounds__(SNT) k_bcr_top_r(BcrView<T> F, T* __restrict__
 }
 
 template <typename T, int SGX, int KM>
-__global__ void __launch_bounds__(SNT) k_bcr_bwd_r(BcrView<T> F, T* __restrict__ x, const T* __restrict__ Y,
+__global__ void __launch_bounds__(SNT2) k_bcr2_bwd_r(BcrView2<T> F, T* __restrict__ x, const T* __restrict__ Y,
                                                   int bs, int nblk, int s, const double* __restrict__ sc) {
     if (sc != nullptr && sc[SC_DONE] != 0.0) return;
     const int i = s + 2 * s * blockIdx.x;
@@ -898,14 +1025,14 @@ __global__ void __launch_bounds__(SNT) k_bcr_bwd_r(BcrView<T> F, T* __restrict__
         gp.load(F.Gp + i * bb, bs);  // unused without the upper neighbour
         ct.load(F.CT + i * bb, bs);
     }
-    for (int r = tid; r < bs; r += SNT) {
+    for (int r = tid; r < bs; r += SNT2) {
         xa[r] = x[(long long)(i - s) * bs + r];
         xb[r] = hb ? x[(long long)(i + s) * bs + r] : T(0);
     }
     __syncthreads();
     if (live) bcr_gemv_rows<T, SGX, KM>(gm, xa, gp, hb, xb, bs, t);
     __syncthreads();
-    for (int r = tid; r < bs; r += SNT) t[r] = Y[(long long)i * bs + r] - t[r];
+    for (int r = tid; r < bs; r += SNT2) t[r] = Y[(long long)i * bs + r] - t[r];
     __syncthreads();
     if (live) bcr_gemv_rows<T, SGX, KM>(ct, t, ct, false, t, bs, x + (long long)i * bs);
 }
@@ -1298,13 +1425,18 @@ void bcr_factor(tgms_ctx* c, const double* A, int n, int bs, Bcr& F, bool fp32) 
         F.C = c->alloc<double>(tot);
         F.Gm = c->alloc<double>(tot);
         F.Gp = c->alloc<double>(tot);
-        F.CT = c->alloc<double>(tot);
-        F.GmT = c->alloc<double>(tot);
-        F.GpT = c->alloc<double>(tot);
+        F.PGP = c->alloc<double>(tot);
+        F.PGM = c->alloc<double>(tot);
+        F.QGM = c->alloc<double>(tot);
+        F.QGP = c->alloc<double>(tot);
+        F.R = c->alloc<double>(tot);
         F.Y = c->alloc<double>((size_t)nblk * bs);
         F.x = c->alloc<double>((size_t)nblk * bs);
         F.fail = c->alloc<int>(1);
         if (fp32) {
+            F.CT = c->alloc<double>(tot);
+            F.GmT = c->alloc<double>(tot);
+            F.GpT = c->alloc<double>(tot);
             F.C32 = c->alloc<float>(tot);
             F.Gm32 = c->alloc<float>(tot);
             F.Gp32 = c->alloc<float>(tot);
@@ -1340,11 +1472,21 @@ void bcr_factor(tgms_ctx* c, const double* A, int n, int bs, Bcr& F, bool fp32) 
     hipLaunchKernelGGL(k_bcr_factor, dim3(1), dim3(FNT), lds, c->stream, (const double*)F.D, F.C, bs, nblk, 1, 1,
                        F.fail);
     LAUNCH_OK();
-    hipLaunchKernelGGL(k_bcr_transpose, dim3(nb(tot)), dim3(256), 0, c->stream, (const double*)F.C, F.CT, bs, tot);
-    hipLaunchKernelGGL(k_bcr_transpose, dim3(nb(tot)), dim3(256), 0, c->stream, (const double*)F.Gm, F.GmT, bs, tot);
-    hipLaunchKernelGGL(k_bcr_transpose, dim3(nb(tot)), dim3(256), 0, c->stream, (const double*)F.Gp, F.GpT, bs, tot);
-    LAUNCH_OK();
+    // the products the solve applies (MFMA, batched over the blocks; rows of Gp and
+    // columns of Gm without a neighbour are zero)
+    const Strided one{bb, 0, 1};
+    gemm_batched(c, 1, 0, bs, bs, bs, 1.0, F.Gp, bs, one, F.C, bs, one, 0.0, F.PGP, bs, one, nblk);
+    gemm_batched(c, 1, 0, bs, bs, bs, 1.0, F.Gm, bs, one, F.C, bs, one, 0.0, F.PGM, bs, one, nblk);
+    gemm_batched(c, 1, 0, bs, bs, bs, 1.0, F.C, bs, one, F.Gm, bs, one, 0.0, F.QGM, bs, one, nblk);
+    gemm_batched(c, 1, 0, bs, bs, bs, 1.0, F.C, bs, one, F.Gp, bs, one, 0.0, F.QGP, bs, one, nblk);
+    gemm_batched(c, 1, 0, bs, bs, bs, 1.0, F.C, bs, one, F.C, bs, one, 0.0, F.R, bs, one, nblk);
     if (fp32) {
+        hipLaunchKernelGGL(k_bcr_transpose, dim3(nb(tot)), dim3(256), 0, c->stream, (const double*)F.C, F.CT, bs, tot);
+        hipLaunchKernelGGL(k_bcr_transpose, dim3(nb(tot)), dim3(256), 0, c->stream, (const double*)F.Gm, F.GmT, bs,
+                           tot);
+        hipLaunchKernelGGL(k_bcr_transpose, dim3(nb(tot)), dim3(256), 0, c->stream, (const double*)F.Gp, F.GpT, bs,
+                           tot);
+        LAUNCH_OK();
         const double* src[6] = {F.C, F.Gm, F.Gp, F.CT, F.GmT, F.GpT};
         float* dst[6] = {F.C32, F.Gm32, F.Gp32, F.CT32, F.GmT32, F.GpT32};
         for (int k = 0; k < 6; ++k)
@@ -1360,66 +1502,100 @@ bool bcr_failed(tgms_ctx* c, const Bcr& F) {
     return h != 0;
 }
 
-template <typename T, int SGX, int KM>
-void bcr_solve_r(tgms_ctx* c, const BcrView<T>& V, T* x, T* Y, int bs, int nblk, int top, const double* sc) {
+template <typename T, int KM>
+void bcr_solve_k(tgms_ctx* c, const BcrView<T>& V, T* x, T* Y, int bs, int nblk, const double* sc) {
+    const int chunks = (bs + SROWS - 1) / SROWS;
+    int top = 1;
+    while (top < nblk) top *= 2;
     for (int s = 1; s < nblk; s *= 2) {
-        hipLaunchKernelGGL((k_bcr_fwd_r<T, SGX, KM>), dim3((nblk - 1) / (2 * s) + 1), dim3(SNT), 0, c->stream, V, x,
-                           Y, bs, nblk, s, sc);
+        const int na = (nblk - 1) / (2 * s) + 1;
+        hipLaunchKernelGGL((k_bcr_fwd<T, KM>), dim3(na * chunks), dim3(SNT), 0, c->stream, V, x, Y, bs, nblk, s,
+                           chunks, sc);
         LAUNCH_OK();
     }
-    hipLaunchKernelGGL((k_bcr_top_r<T, SGX, KM>), dim3(1), dim3(SNT), 0, c->stream, V, x, bs, sc);
+    hipLaunchKernelGGL((k_bcr_top<T, KM>), dim3(1), dim3(TNT), 0, c->stream, V, x, bs, sc);
     LAUNCH_OK();
     for (int s = top / 2; s >= 1; s /= 2) {
         if (s >= nblk) continue;
-        hipLaunchKernelGGL((k_bcr_bwd_r<T, SGX, KM>), dim3((nblk - s - 1) / (2 * s) + 1), dim3(SNT), 0, c->stream,
-                           V, x, (const T*)Y, bs, nblk, s, sc);
+        const int ne = (nblk - s - 1) / (2 * s) + 1;
+        hipLaunchKernelGGL((k_bcr_bwd<T, KM>), dim3(ne * chunks), dim3(SNT), 0, c->stream, V, x, (const T*)Y, bs,
+                           nblk, s, chunks, sc);
+        LAUNCH_OK();
+    }
+}
+
+template <int SGX, int KM>
+void bcr_solve2_r(tgms_ctx* c, const BcrView2<float>& V, float* x, float* Y, int bs, int nblk, int top,
+                  const double* sc) {
+    for (int s = 1; s < nblk; s *= 2) {
+        hipLaunchKernelGGL((k_bcr2_fwd_r<float, SGX, KM>), dim3((nblk - 1) / (2 * s) + 1), dim3(SNT2), 0, c->stream,
+                           V, x, Y, bs, nblk, s, sc);
+        LAUNCH_OK();
+    }
+    hipLaunchKernelGGL((k_bcr2_top_r<float, SGX, KM>), dim3(1), dim3(SNT2), 0, c->stream, V, x, bs, sc);
+    LAUNCH_OK();
+    for (int s = top / 2; s >= 1; s /= 2) {
+        if (s >= nblk) continue;
+        hipLaunchKernelGGL((k_bcr2_bwd_r<float, SGX, KM>), dim3((nblk - s - 1) / (2 * s) + 1), dim3(SNT2), 0,
+                           c->stream, V, x, (const float*)Y, bs, nblk, s, sc);
+        LAUNCH_OK();
+    }
+}
+
+// FP32: the two-step form (see k_bcr2_fwd)
+void bcr_solve2(tgms_ctx* c, const Bcr& F, float* x, const double* sc) {
+    const BcrView2<float> V{F.C32, F.CT32, F.Gm32, F.Gp32, F.GmT32, F.GpT32};
+    float* Y = F.Y32;
+    const int nblk = F.nb, bs = F.bs;
+    int top = 1;
+    while (top < nblk) top *= 2;
+    // blocks of up to 64 rows (16 lanes a row) or 72 and 128 rows (8 lanes a row): the
+    // register-prefetched kernels
+    if (bs <= 64) {
+        bcr_solve2_r<16, 4>(c, V, x, Y, bs, nblk, top, sc);
+        return;
+    }
+    if (bs <= 72) {
+        bcr_solve2_r<8, 9>(c, V, x, Y, bs, nblk, top, sc);
+        return;
+    }
+    if (bs <= 128) {
+        bcr_solve2_r<8, 16>(c, V, x, Y, bs, nblk, top, sc);
+        return;
+    }
+    for (int s = 1; s < nblk; s *= 2) {
+        hipLaunchKernelGGL((k_bcr2_fwd<float>), dim3((nblk - 1) / (2 * s) + 1), dim3(SNT2), 0, c->stream, V, x, Y, bs,
+                           nblk, s, sc);
+        LAUNCH_OK();
+    }
+    hipLaunchKernelGGL((k_bcr2_top<float>), dim3(1), dim3(SNT2), 0, c->stream, V, x, bs, sc);
+    LAUNCH_OK();
+    for (int s = top / 2; s >= 1; s /= 2) {
+        if (s >= nblk) continue;
+        hipLaunchKernelGGL((k_bcr2_bwd<float>), dim3((nblk - s - 1) / (2 * s) + 1), dim3(SNT2), 0, c->stream, V, x,
+                           (const float*)Y, bs, nblk, s, sc);
         LAUNCH_OK();
     }
 }
 
 template <typename T>
 void bcr_solve(tgms_ctx* c, const Bcr& F, T* x, const double* sc) {
-    BcrView<T> V;
-    T* Y;
-    if constexpr (sizeof(T) == 8) {
-        V = BcrView<T>{(const T*)F.C, (const T*)F.CT, (const T*)F.Gm, (const T*)F.Gp, (const T*)F.GmT, (const T*)F.GpT};
-        Y = (T*)F.Y;
-    } else {
-        V = BcrView<T>{(const T*)F.C32, (const T*)F.CT32, (const T*)F.Gm32, (const T*)F.Gp32, (const T*)F.GmT32,
-                       (const T*)F.GpT32};
-        Y = (T*)F.Y32;
-    }
     const int nblk = F.nb, bs = F.bs;
-    int top = 1;
-    while (top < nblk) top *= 2;
-    // blocks of up to 64 rows (16 lanes a row), 72 rows (8 lanes a row) and, in FP32,
-    // 128 rows: the register-prefetched kernels
-    if (bs <= 64) {
-        bcr_solve_r<T, 16, 4>(c, V, x, Y, bs, nblk, top, sc);
-        return;
-    }
-    if (bs <= 72) {
-        bcr_solve_r<T, 8, 9>(c, V, x, Y, bs, nblk, top, sc);
-        return;
-    }
+    if (bs > BCR_SOLVE_MAX) throw TgmsError{TGMS_E_UNSUPPORTED, "coarse block too wide for the solve"};
     if constexpr (sizeof(T) == 4) {
-        if (bs <= 128) {
-            bcr_solve_r<T, 8, 16>(c, V, x, Y, bs, nblk, top, sc);
-            return;
-        }
-    }
-    for (int s = 1; s < nblk; s *= 2) {
-        hipLaunchKernelGGL((k_bcr_fwd<T>), dim3((nblk - 1) / (2 * s) + 1), dim3(SNT), 0, c->stream, V, x, Y, bs, nblk,
-                           s, sc);
-        LAUNCH_OK();
-    }
-    hipLaunchKernelGGL((k_bcr_top<T>), dim3(1), dim3(SNT), 0, c->stream, V, x, bs, sc);
-    LAUNCH_OK();
-    for (int s = top / 2; s >= 1; s /= 2) {
-        if (s >= nblk) continue;
-        hipLaunchKernelGGL((k_bcr_bwd<T>), dim3((nblk - s - 1) / (2 * s) + 1), dim3(SNT), 0, c->stream, V, x,
-                           (const T*)Y, bs, nblk, s, sc);
-        LAUNCH_OK();
+        bcr_solve2(c, F, x, sc);
+    } else {
+        const BcrView<T> V{F.PGP, F.PGM, F.QGM, F.QGP, F.R};
+        T* Y = F.Y;
+        // column slots per lane: 16 lanes a row
+        if (bs <= 4 * SG)
+            bcr_solve_k<T, 4>(c, V, x, Y, bs, nblk, sc);
+        else if (bs <= 5 * SG)
+            bcr_solve_k<T, 5>(c, V, x, Y, bs, nblk, sc);
+        else if (bs <= 8 * SG)
+            bcr_solve_k<T, 8>(c, V, x, Y, bs, nblk, sc);
+        else
+            bcr_solve_k<T, 9>(c, V, x, Y, bs, nblk, sc);
     }
 }
 template void bcr_solve<double>(tgms_ctx*, const Bcr&, double*, const double*);
