@@ -824,75 +824,187 @@ __global__ void k_fill_td(BlockGeom G, int mu, const int* __restrict__ meta, con
 // path integral of every snapshot column to vertex values (for the stream functions).
 // Launched once per colour (I%2, J%2): blocks of one colour share no coarse unknown, so
 // their contributions are added without atomics and the assembly is deterministic.
-__global__ void k_coarse_local(BlockGeom G, const double* __restrict__ Gm, const double* __restrict__ Tm, int mu,
-                               const int* __restrict__ unk, const int* __restrict__ nunk, double* __restrict__ Ac,
-                               int ncs, const double* __restrict__ Psi, double* __restrict__ PPsi, int colour) {
-    extern __shared__ double sm[];
-    const int bxc = (G.Nx + 1 - (colour & 1)) / 2;
-    const int bI = 2 * (blockIdx.x % bxc) + (colour & 1), bJ = 2 * (blockIdx.x / bxc) + (colour >> 1);
-    if (bI >= G.Nx || bJ >= G.Ny) return;
-    const int blk = bJ * G.Nx + bI, tid = threadIdx.x, nth = blockDim.x;
-    const int ncol = G.ncol, nu = nunk[blk];
-    const double* Gb = Gm + (long long)blk * ncol * ncol;
-    const double* Tb = Tm + (long long)blk * ncol * mu;
-    double* GT = sm;  // ncol x mu
-    for (int e = tid; e < ncol * nu; e += nth) {
-        const int r = e / nu, u = e % nu;
-        double s = 0.0;
-        for (int k = 0; k < ncol; ++k) s += Gb[r * ncol + k] * Tb[k * mu + u];
-        GT[r * mu + u] = s;
-    }
-    __syncthreads();
-    const int* ub = unk + (long long)blk * mu;
-    for (int e = tid; e < nu * nu; e += nth) {
-        const int u = e / nu, w = e % nu;
-        double s = 0.0;
-        for (int k = 0; k < ncol; ++k) s += Tb[k * mu + u] * GT[k * mu + w];
-        Ac[(long long)ub[u] * ncs + ub[w]] += s;
-    }
-    // path integral: psi(0,0) = 0, along the bottom edge by the y-fluxes, then up each column by the x-fluxes
+// Path integrals of every snapshot: the stream function psi with psi(0,0) = 0, along the
+// bottom edge by the y-fluxes, then up each vertex column by the x-fluxes.  One thread
+// per (snapshot column, vertex column); PPsi is [vertex][column] per block.
+__global__ void k_path_psi(BlockGeom G, const double* __restrict__ Psi, double* __restrict__ PPsi) {
+    const int blk = blockIdx.x, ncol = G.ncol;
     const int bxl = G.bx, byl = G.by, nfx = byl * (bxl + 1);
     const int nvtx = (bxl + 1) * (byl + 1);
-    for (int col = tid; col < ncol; col += nth) {
+    double* o = PPsi + (long long)blk * nvtx * ncol;
+    for (int task = threadIdx.x; task < ncol * (bxl + 1); task += blockDim.x) {
+        const int col = task % ncol, a = task / ncol;
         const double* v = Psi + ((long long)blk * ncol + col) * G.nfk;
-        double* o = PPsi + (long long)blk * nvtx * ncol;
-        double acc = 0.0;
-        o[col] = 0.0;
-        for (int a = 0; a < bxl; ++a) {
-            acc -= G.hx * v[nfx + a];  // y-face (a, 0)
-            o[(long long)(a + 1) * ncol + col] = acc;
-        }
-        for (int a = 0; a <= bxl; ++a) {
-            double p = o[(long long)a * ncol + col];
-            for (int b = 0; b < byl; ++b) {
-                p += G.hy * v[b * (bxl + 1) + a];
-                o[(long long)((b + 1) * (bxl + 1) + a) * ncol + col] = p;
-            }
+        double p = 0.0;
+        for (int q = 0; q < a; ++q) p -= G.hx * v[nfx + q];  // y-faces (q, 0)
+        o[(long long)a * ncol + col] = p;
+#pragma unroll 4
+        for (int b = 0; b < byl; ++b) {
+            p += G.hy * v[b * (bxl + 1) + a];
+            o[(long long)((b + 1) * (bxl + 1) + a) * ncol + col] = p;
         }
     }
 }
 
-// W_K[v][u] = sum_col PPsi[v][col] T[col][u] - (same at the unknown's zero corner), owned vertices.
-__global__ void k_coarse_W(BlockGeom G, const double* __restrict__ PPsi, const double* __restrict__ Tm, int mu,
-                           const int* __restrict__ nunk, const int* __restrict__ zc, double* __restrict__ W,
-                           float* __restrict__ W32) {
+// A_c[unk(u)][unk(w)] += H_K[u][w] for one colour of blocks (blocks of a colour share no
+// unknown, so no atomics): H_K = T_K^T G_K T_K, formed by batched products
+__global__ void k_coarse_scatter(int Nx, int Ny, const double* __restrict__ H, int mu, const int* __restrict__ unk,
+                                 const int* __restrict__ nunk, double* __restrict__ Ac, int ncs, int colour) {
+    const int bxc = (Nx + 1 - (colour & 1)) / 2;
+    const int bI = 2 * (blockIdx.x % bxc) + (colour & 1), bJ = 2 * (blockIdx.x / bxc) + (colour >> 1);
+    if (bI >= Nx || bJ >= Ny) return;
+    const int blk = bJ * Nx + bI, nu = nunk[blk];
+    const int* ub = unk + (long long)blk * mu;
+    const double* Hb = H + (long long)blk * mu * mu;
+    for (int e = threadIdx.x; e < nu * nu; e += blockDim.x) {
+        const int u = e / nu, w = e % nu;
+        Ac[(long long)ub[u] * ncs + ub[w]] += Hb[u * mu + w];
+    }
+}
+
+// W_K[v][u] = PT[v][u] - PT[zero corner of u][u] on the owned vertices, PT = PPsi T (the
+// stream function of the unknown's flux field, pinned to zero at its corner)
+__global__ void k_coarse_W(BlockGeom G, const double* __restrict__ PT, int mu, const int* __restrict__ nunk,
+                           const int* __restrict__ zc, double* __restrict__ W, float* __restrict__ W32) {
     const int blk = blockIdx.x, tid = threadIdx.x;
     const int I = blk % G.Nx, J = blk / G.Nx;
-    const int bxl = G.bx, byl = G.by, ncol = G.ncol, nu = nunk[blk];
+    const int bxl = G.bx, byl = G.by, nu = nunk[blk];
     const int nvtx = (bxl + 1) * (byl + 1), nown = bxl * byl;
-    const double* Pb = PPsi + (long long)blk * nvtx * ncol;
-    const double* Tb = Tm + (long long)blk * ncol * mu;
+    const double* Pb = PT + (long long)blk * nvtx * mu;
     for (int e = tid; e < nown * mu; e += blockDim.x) {
         const int v = e / mu, u = e % mu;
         const int a = v % bxl, b = v / bxl;
         double val = 0.0;
         if (u < nu && !((I == 0 && a == 0) || (J == 0 && b == 0))) {
             const int corner = zc[(long long)blk * mu + u];
-            const int vv = b * (bxl + 1) + a;
-            for (int k = 0; k < ncol; ++k) val += (Pb[(long long)vv * ncol + k] - Pb[(long long)corner * ncol + k]) * Tb[k * mu + u];
+            val = Pb[(long long)(b * (bxl + 1) + a) * mu + u] - Pb[(long long)corner * mu + u];
         }
         W[(long long)blk * nown * mu + e] = val;
         if (W32) W32[(long long)blk * nown * mu + e] = (float)val;
+    }
+}
+
+// H_K = T_K^T G_K T_K per block (G_K symmetric: column r of G is read as row r, so
+// consecutive threads read consecutive words); T and G T in LDS.
+__global__ void __launch_bounds__(256) k_coarse_H(BlockGeom G, const double* __restrict__ Gm,
+                                                  const double* __restrict__ Tm, int mu,
+                                                  const int* __restrict__ nunk, double* __restrict__ H) {
+    extern __shared__ double sm[];
+    const int blk = blockIdx.x, tid = threadIdx.x, nth = blockDim.x;
+    const int ncol = G.ncol, nu = nunk[blk];
+    double* Ts = sm;            // ncol x mu
+    double* GT = Ts + ncol * mu;  // ncol x mu
+    const double* Gb = Gm + (long long)blk * ncol * ncol;
+    const double* Tb = Tm + (long long)blk * ncol * mu;
+    for (int e = tid; e < ncol * mu; e += nth) Ts[e] = Tb[e];
+    __syncthreads();
+    for (int e = tid; e < ncol * nu; e += nth) {
+        const int r = e % ncol, u = e / ncol;
+        double s = 0.0;
+#pragma unroll 8
+        for (int k = 0; k < ncol; ++k) s += Gb[(long long)k * ncol + r] * Ts[k * mu + u];
+        GT[r * mu + u] = s;
+    }
+    __syncthreads();
+    double* Hb = H + (long long)blk * mu * mu;
+    for (int e = tid; e < nu * nu; e += nth) {
+        const int u = e / nu, w = e % nu;
+        double s = 0.0;
+        for (int k = 0; k < ncol; ++k) s += Ts[k * mu + u] * GT[k * mu + w];
+        Hb[u * mu + w] = s;
+    }
+}
+
+// The stream functions of a block's coarse unknowns.  By linearity the stream function
+// of an unknown is the path integral (psi(0,0) = 0, along the bottom edge by the
+// y-fluxes, then up each vertex column by the x-fluxes) of its flux field
+// Psi_K T_K[:, u], so the snapshots are combined first and only the unknowns' fields are
+// integrated; W_K[v][u] = psi_u(v) - psi_u(zero corner of u) on the owned vertices.
+// 512 threads: two per fine face for the flux fields (each half of the snapshot
+// columns, eight loads in flight, summed across the lane pair), chunks of CL_UC
+// unknowns; LDS: T (padded with zero columns to whole chunks), a chunk of the flux
+// fields and of their stream functions.
+constexpr int CL_UC = 8;
+constexpr int CL_NT = 512;
+__global__ void __launch_bounds__(CL_NT) k_coarse_W2(BlockGeom G, const double* __restrict__ Psi,
+                                                     const double* __restrict__ Tm, int mu,
+                                                     const int* __restrict__ nunk, const int* __restrict__ zc,
+                                                     double* __restrict__ W, float* __restrict__ W32) {
+    extern __shared__ double sm[];
+    const int blk = blockIdx.x, tid = threadIdx.x;
+    const int I = blk % G.Nx, J = blk / G.Nx;
+    const int ncol = G.ncol, nfk = G.nfk, nu = nunk[blk];
+    const int bxl = G.bx, byl = G.by, nfx = byl * (bxl + 1);
+    const int nown = bxl * byl;
+    const int mup = (mu + CL_UC - 1) / CL_UC * CL_UC;
+    double* Ts = sm;                           // ncol x mup
+    double* Fs = Ts + ncol * mup;              // nfk x CL_UC
+    double* Ps = Fs + (long long)nfk * CL_UC;  // nvtx x CL_UC
+    const double* Tb = Tm + (long long)blk * ncol * mu;
+    for (int e = tid; e < ncol * mup; e += CL_NT) {
+        const int r = e / mup, u = e % mup;
+        Ts[e] = u < mu ? Tb[r * mu + u] : 0.0;
+    }
+    __syncthreads();
+    const double* Pb = Psi + (long long)blk * ncol * nfk;
+    double* Wb = W + (long long)blk * nown * mu;
+    float* Wb32 = W32 ? W32 + (long long)blk * nown * mu : nullptr;
+    const int half = tid & 1, hc = ncol / 2, c0 = half * hc;
+    for (int u0 = 0; u0 < mu; u0 += CL_UC) {
+        const int uc = min(CL_UC, mu - u0);
+        // flux fields F[f][j] = sum_col Psi[col][f] T[col][u0 + j]; the whole wave runs
+        // every pass (lanes past nfk read face nfk - 1 and discard it), so the pair sum is
+        // taken by both lanes
+        for (int f0 = tid >> 1; f0 < ((nfk + CL_NT / 2 - 1) / (CL_NT / 2)) * (CL_NT / 2); f0 += CL_NT / 2) {
+            const int f = min(f0, nfk - 1);
+            double acc[CL_UC];
+#pragma unroll
+            for (int j = 0; j < CL_UC; ++j) acc[j] = 0.0;
+            // eight snapshot columns a step: every load issued (clamped rows past hc)
+            // before any product uses one
+            for (int q0 = 0; q0 < hc; q0 += 8) {
+                double pv[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) pv[t] = Pb[(long long)(c0 + min(q0 + t, hc - 1)) * nfk + f];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const double w = q0 + t < hc ? pv[t] : 0.0;
+                    const double* tr = Ts + (c0 + min(q0 + t, hc - 1)) * mup + u0;
+#pragma unroll
+                    for (int j = 0; j < CL_UC; ++j) acc[j] += w * tr[j];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < CL_UC; ++j) acc[j] += __shfl_xor(acc[j], 1, 64);
+            if (half == 0 && f0 < nfk)
+#pragma unroll
+                for (int j = 0; j < CL_UC; ++j) Fs[f * CL_UC + j] = acc[j];
+        }
+        __syncthreads();
+        // path integrals: one task per (unknown of the chunk, vertex column)
+        for (int task = tid; task < uc * (bxl + 1); task += CL_NT) {
+            const int j = task % uc, a = task / uc;
+            double p = 0.0;
+            for (int q = 0; q < a; ++q) p -= G.hx * Fs[(nfx + q) * CL_UC + j];
+            Ps[a * CL_UC + j] = p;
+            for (int b = 0; b < byl; ++b) {
+                p += G.hy * Fs[(b * (bxl + 1) + a) * CL_UC + j];
+                Ps[((b + 1) * (bxl + 1) + a) * CL_UC + j] = p;
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < nown * uc; e += CL_NT) {
+            const int v = e / uc, j = e % uc, u = u0 + j;
+            const int a = v % bxl, b = v / bxl;
+            double val = 0.0;
+            if (u < nu && !((I == 0 && a == 0) || (J == 0 && b == 0))) {
+                const int corner = zc[(long long)blk * mu + u];
+                val = Ps[(b * (bxl + 1) + a) * CL_UC + j] - Ps[corner * CL_UC + j];
+            }
+            Wb[(long long)v * mu + u] = val;
+            if (Wb32) Wb32[(long long)v * mu + u] = (float)val;
+        }
+        __syncthreads();
     }
 }
 
@@ -1192,16 +1304,57 @@ void fill_td(tgms_ctx* c, const int* meta, const double* YQ, double* Td) {
 
 void coarse_local_run(tgms_ctx* c, const double* Tm, const int* zc) {
     BlockGeom G = geom(c);
-    size_t lds = sizeof(double) * c->ncol * c->mu;
+    const int ncol = c->ncol, mu = c->mu, nblk = c->nblk;
+    const int nvtx = (c->bx + 1) * (c->by + 1);
+    const size_t lds_h = sizeof(double) * 2 * (size_t)ncol * mu;
+    const size_t lds_w = sizeof(double) * ((size_t)ncol * ((mu + CL_UC - 1) / CL_UC * CL_UC) +
+                                           (size_t)(c->nfk + nvtx) * CL_UC);
+    if (lds_h <= (size_t)c->lds_max && lds_w <= (size_t)c->lds_max && ncol % 2 == 0) {
+        if (!c->clH) c->clH = c->alloc<double>((size_t)nblk * mu * mu);
+        (void)hipFuncSetAttribute((const void*)k_coarse_H, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_h);
+        (void)hipFuncSetAttribute((const void*)k_coarse_W2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_w);
+        hipLaunchKernelGGL(k_coarse_H, dim3(nblk), dim3(256), lds_h, c->stream, G, (const double*)c->G, Tm, mu,
+                           c->blk_nu, c->clH);
+        LAUNCH_OK();
+        for (int colour = 0; colour < 4; ++colour) {
+            const int bxc = (c->Nx + 1 - (colour & 1)) / 2, byc = (c->Ny + 1 - (colour >> 1)) / 2;
+            if (bxc <= 0 || byc <= 0) continue;
+            hipLaunchKernelGGL(k_coarse_scatter, dim3(bxc * byc), dim3(64), 0, c->stream, c->Nx, c->Ny,
+                               (const double*)c->clH, mu, c->blk_unk, c->blk_nu, c->Ac, c->ncs, colour);
+            LAUNCH_OK();
+        }
+        hipLaunchKernelGGL(k_coarse_W2, dim3(nblk), dim3(CL_NT), lds_w, c->stream, G, (const double*)c->Psi, Tm, mu,
+                           c->blk_nu, zc, c->W, c->precision ? c->W32 : nullptr);
+        LAUNCH_OK();
+        return;
+    }
+    // blocks whose assembly does not fit in LDS: path integrals of every snapshot and
+    // batched products
+    if (!c->clGT) {
+        c->clGT = c->alloc<double>((size_t)nblk * ncol * mu);
+        if (!c->clH) c->clH = c->alloc<double>((size_t)nblk * mu * mu);
+        c->clPT = c->alloc<double>((size_t)nblk * nvtx * mu);
+    }
+    // the snapshots' stream functions (into the A Psi array, free at this point)
+    hipLaunchKernelGGL(k_path_psi, dim3(nblk), dim3(256), 0, c->stream, G, c->Psi, c->APsi);
+    LAUNCH_OK();
+    // per block (batched FP64 MFMA products): GT = G_K T_K, H = T_K^T GT, PT = PPsi_K T_K
+    const long long sg = (long long)ncol * ncol, st = (long long)ncol * mu;
+    gemm_batched(c, 0, 0, ncol, mu, ncol, 1.0, c->G, ncol, Strided{sg, 0, 1}, Tm, mu, Strided{st, 0, 1}, 0.0,
+                 c->clGT, mu, Strided{st, 0, 1}, nblk);
+    gemm_batched(c, 1, 0, mu, mu, ncol, 1.0, Tm, mu, Strided{st, 0, 1}, c->clGT, mu, Strided{st, 0, 1}, 0.0,
+                 c->clH, mu, Strided{(long long)mu * mu, 0, 1}, nblk);
+    gemm_batched(c, 0, 0, nvtx, mu, ncol, 1.0, c->APsi, ncol, Strided{(long long)nvtx * ncol, 0, 1}, Tm, mu,
+                 Strided{st, 0, 1}, 0.0, c->clPT, mu, Strided{(long long)nvtx * mu, 0, 1}, nblk);
     for (int colour = 0; colour < 4; ++colour) {
         const int bxc = (c->Nx + 1 - (colour & 1)) / 2, byc = (c->Ny + 1 - (colour >> 1)) / 2;
         if (bxc <= 0 || byc <= 0) continue;
-        hipLaunchKernelGGL(k_coarse_local, dim3(bxc * byc), dim3(256), lds, c->stream, G, c->G, Tm, c->mu, c->blk_unk,
-                           c->blk_nu, c->Ac, c->ncs, c->Psi, c->APsi, colour);
+        hipLaunchKernelGGL(k_coarse_scatter, dim3(bxc * byc), dim3(64), 0, c->stream, c->Nx, c->Ny,
+                           (const double*)c->clH, mu, c->blk_unk, c->blk_nu, c->Ac, c->ncs, colour);
         LAUNCH_OK();
     }
-    hipLaunchKernelGGL(k_coarse_W, dim3(c->nblk), dim3(256), 0, c->stream, G, c->APsi, Tm, c->mu, c->blk_nu, zc, c->W,
-                       c->precision ? c->W32 : nullptr);
+    hipLaunchKernelGGL(k_coarse_W, dim3(nblk), dim3(256), 0, c->stream, G, (const double*)c->clPT, mu, c->blk_nu, zc,
+                       c->W, c->precision ? c->W32 : nullptr);
     LAUNCH_OK();
 }
 
