@@ -288,7 +288,7 @@ struct tgms_ctx {
     std::vector<DeviceBuf> owned;
     Rect* blk_rects = nullptr;
     double* Td = nullptr;      // coarse basis combination matrices (kept for mobility updates)
-    double *clGT = nullptr, *clH = nullptr, *clPT = nullptr;  // coarse assembly products (per block)
+    double* clH = nullptr;     // H_K = T_K^T G_K T_K per block (coarse assembly)
     int* zcd = nullptr;
     // warm-started local eigensolves (tgms_options.warm_start)
     int warm = 0;               // 0 dense Jacobi, 1 DCT-II start, 2 network start

@@ -824,28 +824,6 @@ __global__ void k_fill_td(BlockGeom G, int mu, const int* __restrict__ meta, con
 // path integral of every snapshot column to vertex values (for the stream functions).
 // Launched once per colour (I%2, J%2): blocks of one colour share no coarse unknown, so
 // their contributions are added without atomics and the assembly is deterministic.
-// Path integrals of every snapshot: the stream function psi with psi(0,0) = 0, along the
-// bottom edge by the y-fluxes, then up each vertex column by the x-fluxes.  One thread
-// per (snapshot column, vertex column); PPsi is [vertex][column] per block.
-__global__ void k_path_psi(BlockGeom G, const double* __restrict__ Psi, double* __restrict__ PPsi) {
-    const int blk = blockIdx.x, ncol = G.ncol;
-    const int bxl = G.bx, byl = G.by, nfx = byl * (bxl + 1);
-    const int nvtx = (bxl + 1) * (byl + 1);
-    double* o = PPsi + (long long)blk * nvtx * ncol;
-    for (int task = threadIdx.x; task < ncol * (bxl + 1); task += blockDim.x) {
-        const int col = task % ncol, a = task / ncol;
-        const double* v = Psi + ((long long)blk * ncol + col) * G.nfk;
-        double p = 0.0;
-        for (int q = 0; q < a; ++q) p -= G.hx * v[nfx + q];  // y-faces (q, 0)
-        o[(long long)a * ncol + col] = p;
-#pragma unroll 4
-        for (int b = 0; b < byl; ++b) {
-            p += G.hy * v[b * (bxl + 1) + a];
-            o[(long long)((b + 1) * (bxl + 1) + a) * ncol + col] = p;
-        }
-    }
-}
-
 // A_c[unk(u)][unk(w)] += H_K[u][w] for one colour of blocks (blocks of a colour share no
 // unknown, so no atomics): H_K = T_K^T G_K T_K, formed by batched products
 __global__ void k_coarse_scatter(int Nx, int Ny, const double* __restrict__ H, int mu, const int* __restrict__ unk,
@@ -859,28 +837,6 @@ __global__ void k_coarse_scatter(int Nx, int Ny, const double* __restrict__ H, i
     for (int e = threadIdx.x; e < nu * nu; e += blockDim.x) {
         const int u = e / nu, w = e % nu;
         Ac[(long long)ub[u] * ncs + ub[w]] += Hb[u * mu + w];
-    }
-}
-
-// W_K[v][u] = PT[v][u] - PT[zero corner of u][u] on the owned vertices, PT = PPsi T (the
-// stream function of the unknown's flux field, pinned to zero at its corner)
-__global__ void k_coarse_W(BlockGeom G, const double* __restrict__ PT, int mu, const int* __restrict__ nunk,
-                           const int* __restrict__ zc, double* __restrict__ W, float* __restrict__ W32) {
-    const int blk = blockIdx.x, tid = threadIdx.x;
-    const int I = blk % G.Nx, J = blk / G.Nx;
-    const int bxl = G.bx, byl = G.by, nu = nunk[blk];
-    const int nvtx = (bxl + 1) * (byl + 1), nown = bxl * byl;
-    const double* Pb = PT + (long long)blk * nvtx * mu;
-    for (int e = tid; e < nown * mu; e += blockDim.x) {
-        const int v = e / mu, u = e % mu;
-        const int a = v % bxl, b = v / bxl;
-        double val = 0.0;
-        if (u < nu && !((I == 0 && a == 0) || (J == 0 && b == 0))) {
-            const int corner = zc[(long long)blk * mu + u];
-            val = Pb[(long long)(b * (bxl + 1) + a) * mu + u] - Pb[(long long)corner * mu + u];
-        }
-        W[(long long)blk * nown * mu + e] = val;
-        if (W32) W32[(long long)blk * nown * mu + e] = (float)val;
     }
 }
 
@@ -1328,34 +1284,8 @@ void coarse_local_run(tgms_ctx* c, const double* Tm, const int* zc) {
         LAUNCH_OK();
         return;
     }
-    // blocks whose assembly does not fit in LDS: path integrals of every snapshot and
-    // batched products
-    if (!c->clGT) {
-        c->clGT = c->alloc<double>((size_t)nblk * ncol * mu);
-        if (!c->clH) c->clH = c->alloc<double>((size_t)nblk * mu * mu);
-        c->clPT = c->alloc<double>((size_t)nblk * nvtx * mu);
-    }
-    // the snapshots' stream functions (into the A Psi array, free at this point)
-    hipLaunchKernelGGL(k_path_psi, dim3(nblk), dim3(256), 0, c->stream, G, c->Psi, c->APsi);
-    LAUNCH_OK();
-    // per block (batched FP64 MFMA products): GT = G_K T_K, H = T_K^T GT, PT = PPsi_K T_K
-    const long long sg = (long long)ncol * ncol, st = (long long)ncol * mu;
-    gemm_batched(c, 0, 0, ncol, mu, ncol, 1.0, c->G, ncol, Strided{sg, 0, 1}, Tm, mu, Strided{st, 0, 1}, 0.0,
-                 c->clGT, mu, Strided{st, 0, 1}, nblk);
-    gemm_batched(c, 1, 0, mu, mu, ncol, 1.0, Tm, mu, Strided{st, 0, 1}, c->clGT, mu, Strided{st, 0, 1}, 0.0,
-                 c->clH, mu, Strided{(long long)mu * mu, 0, 1}, nblk);
-    gemm_batched(c, 0, 0, nvtx, mu, ncol, 1.0, c->APsi, ncol, Strided{(long long)nvtx * ncol, 0, 1}, Tm, mu,
-                 Strided{st, 0, 1}, 0.0, c->clPT, mu, Strided{(long long)nvtx * mu, 0, 1}, nblk);
-    for (int colour = 0; colour < 4; ++colour) {
-        const int bxc = (c->Nx + 1 - (colour & 1)) / 2, byc = (c->Ny + 1 - (colour >> 1)) / 2;
-        if (bxc <= 0 || byc <= 0) continue;
-        hipLaunchKernelGGL(k_coarse_scatter, dim3(bxc * byc), dim3(64), 0, c->stream, c->Nx, c->Ny,
-                           (const double*)c->clH, mu, c->blk_unk, c->blk_nu, c->Ac, c->ncs, colour);
-        LAUNCH_OK();
-    }
-    hipLaunchKernelGGL(k_coarse_W, dim3(nblk), dim3(256), 0, c->stream, G, (const double*)c->clPT, mu, c->blk_nu, zc,
-                       c->W, c->precision ? c->W32 : nullptr);
-    LAUNCH_OK();
+    // (blocks up to the band factor's limit, 20 x 20 cells, need at most about 133 KB)
+    throw TgmsError{TGMS_E_UNSUPPORTED, "coarse assembly of a block exceeds the LDS"};
 }
 
 void rt0_stiffness(tgms_ctx* c, const double* AH0, double* K) {

@@ -388,6 +388,29 @@ def test_launch_variants_match_oracle(staging, rpt):
     s.close()
 
 
+def test_largest_blocks_many_modes():
+    """The largest blocks the local band factors take (20 x 20 cells) with many modes per
+    face (tol 50): the per-block coarse assembly at its largest LDS footprint (the
+    centre block holds up to 80 coarse unknowns); counts, the two-grid operator and the
+    solution match the oracle's."""
+    import paper_1807_07220_amd as tg
+    from oracle import Grid2D, OracleSolver
+    nx = ny = 60
+    bx = by = 20
+    kappa = fields.field_channelized(nx, ny, 23, contrast=1e4)
+    o = OracleSolver(Grid2D(nx, ny, bx, by), kappa, 50.0)
+    s = tg.Solver(dev(kappa), bx, by, 50.0)
+    assert np.array_equal(s.counts(), np.asarray(o.counts))
+    r = np.random.default_rng(5).standard_normal(o.g.nf) * o.mask
+    z = host(s.apply_precond("twogrid", dev(r)))
+    assert rel(z * o.mask, o.twogrid(r)) <= 1e-9
+    F = fields.random_source(nx, ny, 9).ravel()
+    res, ro = s.solve(dev(F), rtol=1e-10), o.solve(F, rtol=1e-10)
+    assert abs(res["iters"] - ro["iters"]) <= 1
+    assert np.linalg.norm(host(res["u"]) - ro["u"]) <= 1e-10 * np.linalg.norm(ro["u"])
+    s.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_overlap_one_matches_oracle(precision):
     """Overlap 1 (patch widths without a fixed-width smoother kernel) against the
