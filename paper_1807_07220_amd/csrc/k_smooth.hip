@@ -16,12 +16,15 @@
 namespace {
 
 // ------------------------------------------------------------------ factorisation
-// One wavefront per patch.  LDS: the scaled stencil (c, e, n, ne, nw per vertex),
-// the scale S, and three m x m work matrices.
-constexpr int FAC_MAXE = 16;  // m*m <= 1024 entries, 16 per lane
+// One workgroup of four waves per patch (the elimination is a chain of pivot steps per
+// block row, so the patch's latency falls with the threads sharing each step).  LDS:
+// the scaled stencil (c, e, n, ne, nw per vertex), the scale S, and three m x m work
+// matrices.
+constexpr int FAC_NT = 256;
+constexpr int FAC_MAXE = 1024 / FAC_NT;  // m*m <= 1024 entries
 
 // In-place Gauss-Jordan inversion of the SPD matrix W (m x m, row-major) by one
-// wavefront; the pivots are Schur-complement diagonals, positive for SPD input.
+// workgroup; the pivots are Schur-complement diagonals, positive for SPD input.
 __device__ void gj_invert(double* W, int m, int* fail) {
     const int lane = threadIdx.x;
     const int mm = m * m;
@@ -32,7 +35,7 @@ __device__ void gj_invert(double* W, int m, int* fail) {
         double nv[FAC_MAXE];
 #pragma unroll
         for (int t = 0; t < FAC_MAXE; ++t) {
-            const int e = lane + 64 * t;
+            const int e = lane + FAC_NT * t;
             nv[t] = 0.0;
             if (e < mm) {
                 const int i = e / m, j = e - i * m;
@@ -50,7 +53,7 @@ __device__ void gj_invert(double* W, int m, int* fail) {
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < FAC_MAXE; ++t) {
-            const int e = lane + 64 * t;
+            const int e = lane + FAC_NT * t;
             if (e < mm) W[e] = nv[t];
         }
         __syncthreads();
@@ -69,7 +72,7 @@ struct PatchStencil {
     }
 };
 
-__global__ void __launch_bounds__(64) k_patch_factor(const Rect* __restrict__ rects, const double* __restrict__ a,
+__global__ void __launch_bounds__(FAC_NT) k_patch_factor(const Rect* __restrict__ rects, const double* __restrict__ a,
                                                      int nx, double sx2, double sy2, double* __restrict__ Fpool,
                                                      int* __restrict__ fail, int npatch) {
     extern __shared__ double sm[];
@@ -96,7 +99,7 @@ __global__ void __launch_bounds__(64) k_patch_factor(const Rect* __restrict__ re
         const int trip = tw_trip(m), b3 = tw_b3(m);
         // stencil couplings of each interior vertex with its east, north, north-east
         // and north-west neighbours (zero where the neighbour is not a patch vertex)
-        for (int r = lane; r < n; r += 64) {
+        for (int r = lane; r < n; r += FAC_NT) {
             const int aa = r % m, bb = r / m;
             const int i = R.i0 + 1 + aa, j = R.j0 + 1 + bb;
             const long long v = (long long)j * nx + i;
@@ -110,7 +113,7 @@ __global__ void __launch_bounds__(64) k_patch_factor(const Rect* __restrict__ re
             S[r] = 1.0 / sqrt(st.c);
         }
         __syncthreads();
-        for (int r = lane; r < n; r += 64) {
+        for (int r = lane; r < n; r += FAC_NT) {
             const int aa = r % m, bb = r / m;
             const double s = S[r];
             kc[r] *= s * s;
@@ -124,30 +127,30 @@ __global__ void __launch_bounds__(64) k_patch_factor(const Rect* __restrict__ re
         }
         __syncthreads();
         // the coupling blocks (three rows of m words per link, zero-padded to b3)
-        for (int e = lane; e < (mh - 1) * b3; e += 64) {
+        for (int e = lane; e < (mh - 1) * b3; e += FAC_NT) {
             const int l = e / b3, q = e - l * b3, which = q / m, sidx = q - which * m;
             const double* src = which == 0 ? kn : which == 1 ? kne : knw;
             Bout[e] = which < 3 ? src[l * m + sidx] : 0.0;
         }
         const PatchStencil P{kc, ke, kn, kne, knw, m};
-        for (int e = lane; e < mm; e += 64) Mid[e] = P.A(k, e / m, e % m);
+        for (int e = lane; e < mm; e += FAC_NT) Mid[e] = P.A(k, e / m, e % m);
         auto store_pivot = [&](int j) {
-            for (int e = lane; e < mm; e += 64) {
+            for (int e = lane; e < mm; e += FAC_NT) {
                 const int r = e / m, s = e - r * m;
                 if (r >= s) Pout[(long long)j * trip + tw_offP(s, m) + (r - s)] = W[e];
             }
-            for (int e = tw_tri(m) + lane; e < trip; e += 64) Pout[(long long)j * trip + e] = 0.0;
+            for (int e = tw_tri(m) + lane; e < trip; e += FAC_NT) Pout[(long long)j * trip + e] = 0.0;
         };
         // top sweep: rows 0..k-1
         if (k >= 1)
-            for (int e = lane; e < mm; e += 64) W[e] = P.A(0, e / m, e % m);
+            for (int e = lane; e < mm; e += FAC_NT) W[e] = P.A(0, e / m, e % m);
         __syncthreads();
         for (int j = 0; j < k; ++j) {
             gj_invert(W, m, fail);
             store_pivot(j);
             // G = B_j T_j^{-1}; B_j[r][s] = kn(s) (r = s), kne(s) (r = s+1), knw(s) (r = s-1) at row j
             const int o = j * m;
-            for (int e = lane; e < mm; e += 64) {
+            for (int e = lane; e < mm; e += FAC_NT) {
                 const int r = e / m, s = e - r * m;
                 double g = kn[o + r] * W[r * m + s];
                 if (r >= 1) g += kne[o + r - 1] * W[(r - 1) * m + s];
@@ -156,7 +159,7 @@ __global__ void __launch_bounds__(64) k_patch_factor(const Rect* __restrict__ re
             }
             __syncthreads();
             // G B_j^T, subtracted from the next diagonal block (or from the middle one)
-            for (int e = lane; e < mm; e += 64) {
+            for (int e = lane; e < mm; e += FAC_NT) {
                 const int r = e / m, s = e - r * m;
                 double cb = G[r * m + s] * kn[o + s];
                 if (s >= 1) cb += G[r * m + s - 1] * kne[o + s - 1];
@@ -170,14 +173,14 @@ __global__ void __launch_bounds__(64) k_patch_factor(const Rect* __restrict__ re
         }
         // bottom sweep: rows mh-1..k+1
         if (mh - 1 > k)
-            for (int e = lane; e < mm; e += 64) W[e] = P.A(mh - 1, e / m, e % m);
+            for (int e = lane; e < mm; e += FAC_NT) W[e] = P.A(mh - 1, e / m, e % m);
         __syncthreads();
         for (int j = mh - 1; j > k; --j) {
             gj_invert(W, m, fail);
             store_pivot(j);
             // H = B_{j-1}^T U_j^{-1}
             const int o = (j - 1) * m;
-            for (int e = lane; e < mm; e += 64) {
+            for (int e = lane; e < mm; e += FAC_NT) {
                 const int r = e / m, s = e - r * m;
                 double h = kn[o + r] * W[r * m + s];
                 if (r + 1 < m) h += kne[o + r] * W[(r + 1) * m + s];
@@ -186,7 +189,7 @@ __global__ void __launch_bounds__(64) k_patch_factor(const Rect* __restrict__ re
             }
             __syncthreads();
             // H B_{j-1}
-            for (int e = lane; e < mm; e += 64) {
+            for (int e = lane; e < mm; e += FAC_NT) {
                 const int r = e / m, s = e - r * m;
                 double cb = G[r * m + s] * kn[o + s];
                 if (s + 1 < m) cb += G[r * m + s + 1] * kne[o + s];
@@ -198,7 +201,7 @@ __global__ void __launch_bounds__(64) k_patch_factor(const Rect* __restrict__ re
             }
             __syncthreads();
         }
-        for (int e = lane; e < mm; e += 64) W[e] = Mid[e];
+        for (int e = lane; e < mm; e += FAC_NT) W[e] = Mid[e];
         __syncthreads();
         gj_invert(W, m, fail);
         store_pivot(k);
@@ -767,7 +770,7 @@ void factor_patches_launch(tgms_ctx* c, int* fail, int max_groups) {
     allow_lds<float>(c->lds_max);
     (void)hipGetLastError();
     const int groups = max_groups > 0 ? std::min(c->nblk, max_groups) : c->nblk;
-    hipLaunchKernelGGL(k_patch_factor, dim3(groups), dim3(64), lds, c->stream, c->patch, c->a, c->nx,
+    hipLaunchKernelGGL(k_patch_factor, dim3(groups), dim3(FAC_NT), lds, c->stream, c->patch, c->a, c->nx,
                        c->sx * c->sx, c->sy * c->sy, c->patL, fail, c->nblk);
     LAUNCH_OK();
     if (c->patL32) cast_d2f(c, c->pat_pool, c->patL, c->patL32);
