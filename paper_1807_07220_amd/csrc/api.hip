@@ -371,10 +371,12 @@ namespace {
 // Coarse unknowns (the zero-flux modes of every face, then one stream function per
 // interior coarse vertex), the unknowns touching each block (slots, ordered by id) and
 // their CSR inverse, and the description of each slot's combination of the face
-// modes (uploaded as meta for k_fill_td, which forms Td on the device from YQ).
-void build_coarse_numbering(tgms_ctx* c, std::vector<int>& meta) {
-    const int Nx = c->Nx, Ny = c->Ny;
-    const std::vector<int>& cnt = c->counts_h;
+// modes (meta, read by k_fill_td, which forms Td on the device from YQ).  All of it is
+// written into `pack` and uploaded with one copy; `pack` must outlive that copy.  Returns
+// the device address of meta.
+int* build_coarse_numbering(tgms_ctx* c, std::vector<int>& pack) {
+    const int Nx = c->Nx, Ny = c->Ny, nex = c->nex, nblk = c->nblk;
+    const int* cnt = c->counts_h.data();
     // Numbering in the row-major order of the unknowns' positions on the coarse grid, in
     // doubled coordinates: vertex (I, J) at (2I, 2J), the zero-flux modes of x-face (I, J)
     // at (2I, 2J + 1), of y-face (I, J) at (2I + 1, 2J).  Unknowns couple only through a
@@ -383,120 +385,136 @@ void build_coarse_numbering(tgms_ctx* c, std::vector<int>& meta) {
     // vertices come in row-major order.
     std::vector<int> zstart(c->ne, -1), vtx((size_t)(Nx + 1) * (Ny + 1), -1);
     int next = 0;
-    for (int py = 0; py <= 2 * Ny; ++py)
-        for (int px = 0; px <= 2 * Nx; ++px) {
-            if (py % 2 == 0 && px % 2 == 0) {
-                const int I = px / 2, J = py / 2;
-                if (I >= 1 && I <= Nx - 1 && J >= 1 && J <= Ny - 1) vtx[(size_t)J * (Nx + 1) + I] = next++;
-            } else if (px % 2 == 0) {  // x-face (I, J): X = I, block row J
-                const int I = px / 2, J = (py - 1) / 2;
-                if (I >= 1 && I <= Nx - 1) {
-                    const int f = J * (Nx - 1) + I - 1;
-                    zstart[f] = next;
-                    next += cnt[f] - 1;
-                }
-            } else if (py % 2 == 0) {  // y-face (I, J): Y = J, block column I
-                const int I = (px - 1) / 2, J = py / 2;
-                if (J >= 1 && J <= Ny - 1) {
-                    const int f = c->nex + (J - 1) * Nx + I;
-                    zstart[f] = next;
-                    next += cnt[f] - 1;
-                }
+    for (int J = 0; J <= Ny; ++J) {
+        // doubled row 2J: vertices (I, J) and the y-faces (I, J) between them
+        for (int I = 0; I <= Nx; ++I) {
+            if (I >= 1 && I <= Nx - 1 && J >= 1 && J <= Ny - 1) vtx[(size_t)J * (Nx + 1) + I] = next++;
+            if (I < Nx && J >= 1 && J <= Ny - 1) {
+                const int f = nex + (J - 1) * Nx + I;
+                zstart[f] = next;
+                next += cnt[f] - 1;
             }
         }
+        if (J == Ny) break;
+        // doubled row 2J + 1: the interior x-faces (I, J) of block row J
+        for (int I = 1; I <= Nx - 1; ++I) {
+            const int f = J * (Nx - 1) + I - 1;
+            zstart[f] = next;
+            next += cnt[f] - 1;
+        }
+    }
     c->nv = (Nx - 1) * (Ny - 1);
     c->ncs = next;
+    const int ncs = next;
     auto vid = [&](int I, int J) { return (I <= 0 || I >= Nx || J <= 0 || J >= Ny) ? -1 : vtx[(size_t)J * (Nx + 1) + I]; };
-    struct Slot {
-        int id, corner, n;
-        int f[2], side[2], k[2], sign[2];
+    // faces of block (I, J): 0 left (x-face I), 1 right (x-face I + 1), 2 bottom
+    // (y-face J), 3 top (y-face J + 1); -1 on the domain boundary
+    auto faces = [&](int I, int J, int face[4]) {
+        face[0] = I > 0 ? J * (Nx - 1) + I - 1 : -1;
+        face[1] = I + 1 < Nx ? J * (Nx - 1) + I : -1;
+        face[2] = J > 0 ? nex + (J - 1) * Nx + I : -1;
+        face[3] = J + 1 < Ny ? nex + J * Nx + I : -1;
     };
-    std::vector<std::vector<Slot>> slots(c->nblk);
     int mu = 1;
     for (int J = 0; J < Ny; ++J)
         for (int I = 0; I < Nx; ++I) {
-            const int blk = J * Nx + I;
-            std::vector<Slot>& m = slots[blk];
-            int face[4] = {-1, -1, -1, -1};
-            if (I > 0) face[0] = J * (Nx - 1) + I - 1;
-            if (I + 1 < Nx) face[1] = J * (Nx - 1) + I;
-            if (J > 0) face[2] = c->nex + (J - 1) * Nx + I;
-            if (J + 1 < Ny) face[3] = c->nex + J * Nx + I;
-            for (int s = 0; s < 4; ++s) {
-                const int f = face[s];
-                if (f < 0) continue;
-                for (int k = 1; k < cnt[f]; ++k) m.push_back(Slot{zstart[f] + k - 1, 0, 1, {f, 0}, {s, 0}, {k, 0}, {1, 0}});
-                // carrier of this face enters the coarse-curl combination of its two end vertices
-                int v0I, v0J, v1I, v1J;
-                if (s == 0) { v0I = I; v0J = J + 1; v1I = I; v1J = J; }
-                else if (s == 1) { v0I = I + 1; v0J = J + 1; v1I = I + 1; v1J = J; }
-                else if (s == 2) { v0I = I; v0J = J; v1I = I + 1; v1J = J; }
-                else { v0I = I; v0J = J + 1; v1I = I + 1; v1J = J + 1; }
-                const int vv[2] = {vid(v0I, v0J), vid(v1I, v1J)};
-                const int ss[2] = {1, -1};
-                const int VI[2] = {v0I, v1I}, VJ[2] = {v0J, v1J};
-                for (int e = 0; e < 2; ++e) {
-                    if (vv[e] < 0) continue;
-                    Slot* sl = nullptr;
-                    for (auto& x : m)
-                        if (x.id == vv[e]) sl = &x;
-                    if (!sl) {
-                        const int ci = (VI[e] == I + 1) ? 0 : c->bx, cj = (VJ[e] == J + 1) ? 0 : c->by;
-                        m.push_back(Slot{vv[e], cj * (c->bx + 1) + ci, 0, {0, 0}, {0, 0}, {0, 0}, {0, 0}});
-                        sl = &m.back();
-                    }
-                    if (sl->n >= 2) throw TgmsError{TGMS_E_DEVICE, "coarse numbering: more than two carriers at a corner"};
-                    sl->f[sl->n] = f;
-                    sl->side[sl->n] = s;
-                    sl->k[sl->n] = 0;
-                    sl->sign[sl->n] = ss[e];
-                    ++sl->n;
-                }
-            }
-            std::sort(m.begin(), m.end(), [](const Slot& a, const Slot& b) { return a.id < b.id; });
-            mu = std::max(mu, (int)m.size());
+            int face[4], n = 0;
+            faces(I, J, face);
+            for (int s = 0; s < 4; ++s)
+                if (face[s] >= 0) n += cnt[face[s]] - 1;
+            n += (vid(I, J) >= 0) + (vid(I + 1, J) >= 0) + (vid(I, J + 1) >= 0) + (vid(I + 1, J + 1) >= 0);
+            mu = std::max(mu, n);
         }
     c->mu = mu;
-    // half-bandwidth of the coarse matrix: unknowns couple only within a block
-    c->cband = 0;
-    for (int b = 0; b < c->nblk; ++b)
-        if (!slots[b].empty()) c->cband = std::max(c->cband, slots[b].back().id - slots[b].front().id);
-    meta.assign((size_t)c->nblk * mu * 11, 0);
-    std::vector<int> zc((size_t)c->nblk * mu, 0), unk((size_t)c->nblk * mu, 0), nu(c->nblk), ptr(c->ncs + 1, 0);
-    for (int b = 0; b < c->nblk; ++b)
-        for (const Slot& sl : slots[b]) ++ptr[sl.id + 1];
-    for (int u = 0; u < c->ncs; ++u) ptr[u + 1] += ptr[u];
-    std::vector<int> flat(std::max(ptr[c->ncs], 1)), fill(ptr.begin(), ptr.end() - 1);
-    for (int b = 0; b < c->nblk; ++b) {
-        nu[b] = (int)slots[b].size();
-        for (int u = 0; u < nu[b]; ++u) {
-            const Slot& sl = slots[b][u];
-            unk[(size_t)b * mu + u] = sl.id;
-            zc[(size_t)b * mu + u] = sl.corner;
-            flat[fill[sl.id]++] = b * mu + u;  // blocks in increasing order: the accumulation order
-            int* mm = &meta[((size_t)b * mu + u) * 11];
-            mm[0] = sl.id;
-            mm[1] = sl.corner;
-            mm[2] = sl.n;
-            for (int q = 0; q < sl.n; ++q) {
-                mm[3 + 4 * q] = sl.f[q];
-                mm[4 + 4 * q] = sl.side[q];
-                mm[5 + 4 * q] = sl.k[q];
-                mm[6 + 4 * q] = sl.sign[q];
-            }
+    // pack: meta (11 words per slot), slot ids, slot counts, CSR pointers and entries,
+    // slot corners; each part starts on a 256-byte boundary
+    const size_t nslot = (size_t)nblk * mu;
+    auto up = [](size_t n) { return (n + 63) & ~(size_t)63; };
+    const size_t o_meta = 0, o_unk = up(nslot * 11), o_nu = o_unk + up(nslot), o_ptr = o_nu + up(nblk),
+                 o_flat = o_ptr + up((size_t)ncs + 1), o_zc = o_flat + up(std::max(nslot, (size_t)1));
+    pack.assign(o_zc + up(nslot), 0);
+    int* meta = pack.data() + o_meta;
+    int* unk = pack.data() + o_unk;
+    int* nu = pack.data() + o_nu;
+    int* ptr = pack.data() + o_ptr;
+    int* flat = pack.data() + o_flat;
+    int* zc = pack.data() + o_zc;
+    // Slots of a block in increasing id, i.e. in the doubled-coordinate raster: vertex
+    // (I, J), bottom face modes, vertex (I + 1, J), left face modes, right face modes,
+    // vertex (I, J + 1), top face modes, vertex (I + 1, J + 1).  A face mode k >= 1 is its
+    // own slot; a corner vertex's slot combines the carriers (k = 0) of the block's two
+    // faces meeting there, in face order, with sign +1 where the vertex is the face's
+    // first end (left/right faces: the upper vertex; bottom/top: the left one) and -1
+    // where it is the second.  `corner` is the vertex's local index in the (bx+1) x (by+1)
+    // grid of the block, counted from the diagonally opposite corner.
+    const int bx = c->bx, by = c->by;
+    int cband = 0;
+    for (int J = 0; J < Ny; ++J)
+        for (int I = 0; I < Nx; ++I) {
+            const int b = J * Nx + I;
+            int face[4];
+            faces(I, J, face);
+            int u = 0;
+            auto slot = [&](int id, int corner, int n) -> int* {
+                unk[(size_t)b * mu + u] = id;
+                zc[(size_t)b * mu + u] = corner;
+                int* mm = meta + ((size_t)b * mu + u) * 11;
+                mm[0] = id;
+                mm[1] = corner;
+                mm[2] = n;
+                ++u;
+                return mm;
+            };
+            auto modes = [&](int s) {
+                const int f = face[s];
+                if (f < 0) return;
+                for (int k = 1; k < cnt[f]; ++k) {
+                    int* mm = slot(zstart[f] + k - 1, 0, 1);
+                    mm[3] = f;
+                    mm[4] = s;
+                    mm[5] = k;
+                    mm[6] = 1;
+                }
+            };
+            // vertex slot: carriers of faces s0 and s1 with signs g0, g1
+            auto vertex = [&](int v, int corner, int s0, int g0, int s1, int g1) {
+                if (v < 0) return;
+                int* mm = slot(v, corner, 2);
+                mm[3] = face[s0];
+                mm[4] = s0;
+                mm[5] = 0;
+                mm[6] = g0;
+                mm[7] = face[s1];
+                mm[8] = s1;
+                mm[9] = 0;
+                mm[10] = g1;
+            };
+            vertex(vid(I, J), by * (bx + 1) + bx, 0, -1, 2, 1);
+            modes(2);
+            vertex(vid(I + 1, J), by * (bx + 1), 1, -1, 2, -1);
+            modes(0);
+            modes(1);
+            vertex(vid(I, J + 1), bx, 0, 1, 3, 1);
+            modes(3);
+            vertex(vid(I + 1, J + 1), 0, 1, 1, 3, -1);
+            nu[b] = u;
+            if (u > 0) cband = std::max(cband, unk[(size_t)b * mu + u - 1] - unk[(size_t)b * mu]);
+            for (int q = 0; q < u; ++q) ++ptr[unk[(size_t)b * mu + q] + 1];
         }
-    }
-    c->blk_unk = c->alloc<int>((size_t)c->nblk * mu);
-    c->blk_nu = c->alloc<int>(c->nblk);
-    c->unk_ptr = c->alloc<int>(c->ncs + 1);
-    c->unk_ent = c->alloc<int>(flat.size());
-    c->zcd = c->alloc<int>(zc.size());
-    HIP_OK(hipMemcpyAsync(c->blk_unk, unk.data(), sizeof(int) * unk.size(), hipMemcpyHostToDevice, c->stream));
-    HIP_OK(hipMemcpyAsync(c->blk_nu, nu.data(), sizeof(int) * nu.size(), hipMemcpyHostToDevice, c->stream));
-    HIP_OK(hipMemcpyAsync(c->unk_ptr, ptr.data(), sizeof(int) * ptr.size(), hipMemcpyHostToDevice, c->stream));
-    HIP_OK(hipMemcpyAsync(c->unk_ent, flat.data(), sizeof(int) * flat.size(), hipMemcpyHostToDevice, c->stream));
-    HIP_OK(hipMemcpyAsync(c->zcd, zc.data(), sizeof(int) * zc.size(), hipMemcpyHostToDevice, c->stream));
-    HIP_OK(hipStreamSynchronize(c->stream));
+    // half-bandwidth of the coarse matrix: unknowns couple only within a block
+    c->cband = cband;
+    for (int q = 0; q < ncs; ++q) ptr[q + 1] += ptr[q];
+    std::vector<int> fill(ptr, ptr + ncs);
+    for (int b = 0; b < nblk; ++b)  // blocks in increasing order: the accumulation order
+        for (int q = 0; q < nu[b]; ++q) flat[fill[unk[(size_t)b * mu + q]]++] = b * mu + q;
+    int* d = c->alloc<int>(pack.size());
+    HIP_OK(hipMemcpyAsync(d, pack.data(), sizeof(int) * pack.size(), hipMemcpyHostToDevice, c->stream));
+    c->blk_unk = d + o_unk;
+    c->blk_nu = d + o_nu;
+    c->unk_ptr = d + o_ptr;
+    c->unk_ent = d + o_flat;
+    c->zcd = d + o_zc;
+    return d + o_meta;
 }
 
 // Coarse RT0 vertex stiffness K_H = C_H^T A_H0 C_H (dense, host-assembled from the per-block Grams).
@@ -876,10 +894,8 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                     ++c->warm_accepted;
                     c->warm_iters += w;
                 }
-            std::vector<int> meta;
-            build_coarse_numbering(c, meta);
-            int* metad = c->alloc<int>(meta.size());
-            HIP_OK(hipMemcpyAsync(metad, meta.data(), sizeof(int) * meta.size(), hipMemcpyHostToDevice, c->stream));
+            std::vector<int> pack;  // host side of the numbering upload, kept until the timer's synchronisation
+            int* metad = build_coarse_numbering(c, pack);
             c->W = c->alloc<double>((size_t)c->nblk * bx * by * c->mu);
             if (c->precision) c->W32 = c->alloc<float>((size_t)c->nblk * bx * by * c->mu);
             c->Ac = c->alloc<double>((size_t)c->ncs * c->ncs);
