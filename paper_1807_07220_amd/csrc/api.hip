@@ -225,11 +225,10 @@ double lanczos_cond(const std::vector<double>& al, const std::vector<double>& be
 // with the residual recomputed after each (z += S(g - K z)), and the two-level additive
 // Schwarz form z = S g + P g (c->additive).  The iterate of the cycle is kept in FP64
 // (vt2), the residual formed in FP64 (vt) and rounded to the preconditioner's precision;
-// the first smoothing carries the PCG update like the fused cycle, the last gather forms
-// the PCG's partial sums.
+// the last gather forms the PCG's partial sums.
 template <typename T>
-void twogrid_variant(tgms_ctx* c, const T* g, const double* gd, double* z, const double* gold, bool dots, bool first,
-                     const FusedUpdate* fu) {
+void twogrid_variant(tgms_ctx* c, const T* g, const double* gd, double* z, const double* gold, bool dots,
+                     bool first) {
     const double* sc = dots ? c->sc : nullptr;
     const long long nv = (long long)c->nx * c->ny;
     const T* w = sizeof(T) == 8 ? (const T*)c->patW : (const T*)c->patW32;
@@ -242,9 +241,9 @@ void twogrid_variant(tgms_ctx* c, const T* g, const double* gd, double* z, const
         tgms::cast_d2f(c, nv, x, c->ft);
         return (const T*)c->ft;
     };
-    auto smooth_add = [&](const T* rhs, bool with_update, bool last) {
+    auto smooth_add = [&](const T* rhs, bool last) {
         // z1 += S rhs (the last post-smoothing gathers into z with the PCG sums instead)
-        tgms::smooth_patches<T>(c, rhs, sc, with_update ? fu : nullptr);
+        tgms::smooth_patches<T>(c, rhs, sc);
         if (last) {
             const T* zin;
             if constexpr (sizeof(T) == 8) {
@@ -260,8 +259,8 @@ void twogrid_variant(tgms_ctx* c, const T* g, const double* gd, double* z, const
         }
     };
     if (c->additive) {
-        // z = S g + P g: the smoothing first (it carries the PCG update, which forms g)
-        tgms::smooth_patches<T>(c, g, sc, fu);
+        // z = S g + P g
+        tgms::smooth_patches<T>(c, g, sc);
         T* zc = sizeof(T) == 8 ? (T*)c->vt2 : (T*)c->ft2;
         tgms::coarse_apply<T>(c, to_T(gd), zc, false, sc);
         tgms::gather_final<T>(c, w, (const T*)zc, z, dots ? gd : nullptr, gold, dots, first);
@@ -271,10 +270,10 @@ void twogrid_variant(tgms_ctx* c, const T* g, const double* gd, double* z, const
     tgms::zero(c, z1, sizeof(double) * nv);
     for (int k = 0; k < m; ++k) {  // pre-smoothing
         if (k == 0) {
-            smooth_add(g, true, false);
+            smooth_add(g, false);
         } else {
             tgms::vertex_residual(c, gd, z1, td);
-            smooth_add(to_T(td), false, false);
+            smooth_add(to_T(td), false);
         }
     }
     // coarse correction of the residual
@@ -288,16 +287,23 @@ void twogrid_variant(tgms_ctx* c, const T* g, const double* gd, double* z, const
     }
     for (int k = 0; k < m; ++k) {  // post-smoothing
         tgms::vertex_residual(c, gd, z1, td);
-        smooth_add(to_T(td), false, k == m - 1);
+        smooth_add(to_T(td), k == m - 1);
     }
     (void)tT;
 }
 
+// With fu, the PCG update runs first and forms the right-hand side g (gd = fu->gout in
+// FP64; for an FP32 preconditioner its rounding, in fg).
 template <typename T>
 void twogrid(tgms_ctx* c, const T* g, const double* gd, double* z, const double* gold, bool dots, bool first,
              const FusedUpdate* fu = nullptr) {
+    if (fu) {
+        T* gT = sizeof(T) == 8 ? nullptr : (T*)c->fg;
+        tgms::pcg_update<T>(c, *fu, gT);
+        g = sizeof(T) == 8 ? (const T*)fu->gout : gT;
+    }
     if (c->msteps != 1 || c->additive) {
-        twogrid_variant<T>(c, g, gd, z, gold, dots, first, fu);
+        twogrid_variant<T>(c, g, gd, z, gold, dots, first);
         return;
     }
     const double* sc = dots ? c->sc : nullptr;
@@ -313,10 +319,10 @@ void twogrid(tgms_ctx* c, const T* g, const double* gd, double* z, const double*
         z2 = (T*)c->ft2;
         t = (T*)c->ft;
     }
-    tgms::smooth_patches<T>(c, g, sc, fu);
+    tgms::smooth_patches<T>(c, g, sc);
     tgms::gather_res_restrict<T>(c, w, gd, z1, t, tgms::coarse_cy<T>(c), sc);
-    // the second smoothing prolongs the coarse solution and forms its right-hand side
-    // g - K (z1 + W c) on each patch itself; it also writes z1 + W c (z2)
+    // the coarse solution prolonged, z2 = z1 + W c, and the second smoothing's right-hand
+    // side g - K z2 (into t, whose restriction the coarse solve has consumed)
     PreResidual<T> pr;
     pr.z1 = z1;
     pr.z1p = z2;
@@ -332,7 +338,8 @@ void twogrid(tgms_ctx* c, const T* g, const double* gd, double* z, const double*
     pr.a = c->a;
     pr.sx2 = c->sx * c->sx;
     pr.sy2 = c->sy * c->sy;
-    tgms::smooth_patches<T>(c, nullptr, sc, nullptr, &pr);
+    tgms::prolong_residual<T>(c, pr, t, sc);
+    tgms::smooth_patches<T>(c, t, sc);
     tgms::gather_final<T>(c, w, z2, z, dots ? gd : nullptr, gold, dots, first);
 }
 
@@ -795,7 +802,6 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                         r.voff = voff;
                         off += (tw_size(m, r.j1 - r.j0 - 1) + 3) & ~3LL;  // 16-byte aligned factors
                         c->pat_fmax = std::max(c->pat_fmax, tw_size(m, r.j1 - r.j0 - 1));
-                        c->pat_zmax = std::max(c->pat_zmax, (long long)(r.i1 - r.i0 + 1) * (r.j1 - r.j0 + 1));
                         voff += n;
                         c->pat_nmax = std::max(c->pat_nmax, n);
                         c->pat_hmax = std::max(c->pat_hmax, r.j1 - r.j0 - 1);
@@ -1072,9 +1078,8 @@ void solve_impl(tgms_ctx* c, const double* F, const double* g_bnd, double rtol, 
     } else {
         twogrid<double>(c, c->vg, c->vg, c->vz, nullptr, true, true);
     }
-    // Every vertex of a block lies inside its own (oversampled) patch, so the update
-    // x += alpha p, g -= alpha q runs inside the first smoothing, which reads g from
-    // one buffer and writes the new g to the other (gin / gout alternate with the
+    // The update x += alpha p, g -= alpha q runs ahead of the preconditioning; it reads
+    // g from one buffer and writes the new g to the other (gin / gout alternate with the
     // search direction; gin is also the old residual the flexible beta needs).
     auto iteration = [&](const double* pin, double* pout, double* gin, double* gout) {
         tgms::dir_apply(c, c->vz, pin, pout, c->vq);

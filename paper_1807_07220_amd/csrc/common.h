@@ -181,7 +181,6 @@ struct tgms_ctx {
     int pat_m1 = 0, pat_m2 = 0;  // the row widths present among the patches (m1 >= m2)
     long long pat_fmax = 0;   // largest patch factor (elements)
     int pat_hmax = 0;         // most vertex rows of a patch
-    long long pat_zmax = 0;   // largest patch with its one-vertex halo (vertices)
     int lds_max = 65536;      // device limit on LDS per workgroup (bytes)
     long long pat_pool = 0, pat_vpool = 0;
     double* patL = nullptr;
@@ -351,6 +350,7 @@ __device__ inline T gather_sum(const int* __restrict__ ent, const T* __restrict_
     return v;
 }
 
+// inputs of k_prolong_residual: z1p = z1 + W c and the residual g - K z1p
 template <typename T>
 struct PreResidual {
     const T* z1 = nullptr;
@@ -365,6 +365,7 @@ struct PreResidual {
     double sx2 = 0, sy2 = 0;
 };
 
+// inputs of k_pcg_update: the p.q partials, the PCG scalars and the vectors
 struct FusedUpdate {
     const double* part;
     int nred;
@@ -410,8 +411,7 @@ void factor_patches(tgms_ctx* c);
 // max_groups > 0 bounds the workgroups (each then factors several patches in turn)
 void factor_patches_launch(tgms_ctx* c, int* fail, int max_groups);
 template <typename T>
-void smooth_patches(tgms_ctx* c, const T* g, const double* sc, const struct FusedUpdate* fu = nullptr,
-                    const PreResidual<T>* pr = nullptr);  // local solves of S g into the patch pool
+void smooth_patches(tgms_ctx* c, const T* g, const double* sc);  // local solves of S g into the patch pool
 // fused PCG / two-grid kernels (k_pcg.hip); sc: skip when the done flag is set (may be null)
 unsigned pcg_tiles(tgms_ctx* c);
 int nred_max();
@@ -419,6 +419,10 @@ void autotune(tgms_ctx* c, const char* cache_path);  // picks nred, smoother sta
 void twogrid_probe(tgms_ctx* c);  // one two-grid application on the context's zeroed vectors (timing)
 void dir_apply(tgms_ctx* c, const double* z, const double* pin, double* pout, double* q);
 void vertex_residual(tgms_ctx* c, const double* g, const double* z, double* t);  // t = g - K z (FP64)
+template <typename T>
+void pcg_update(tgms_ctx* c, const FusedUpdate& fu, T* gT);  // alpha, g = gin - alpha q (and T(g) in gT), x += alpha p
+template <typename T>
+void prolong_residual(tgms_ctx* c, const PreResidual<T>& pr, T* t, const double* sc);  // z1p = z1 + W c, t = g - K z1p
 void finalize(tgms_ctx* c, bool first);  // scalars from pending gather partials (first: rho_0, |z_0|^2)
 void allow_fused_lds(tgms_ctx* c);      // LDS limit of the per-block fused kernels (large blocks)
 template <typename T>

@@ -1,24 +1,24 @@
 // Fused kernels of the PCG iteration (paper section 5, Step 3) and of the
 // two-grid preconditioner around the smoother and coarse solves.
 //
-// One PCG iteration in stream-function coordinates is 7 kernels (6 in FP64 with
-// at most 1024 coarse unknowns, 8 with more than 1024):
+// One PCG iteration in stream-function coordinates is these kernels (the coarse
+// solve one product with an explicit inverse, or the levels of the cyclic reduction):
 //   [finalise the last iteration: rho' = g.z, beta, |C z|^2 test]
 //   p = z + beta p;  q = K p;  partial p.q                        (k_dir_apply)
-//   z = B_TG g: alpha = rho / p.q, x += alpha p and g -= alpha q inside the
-//   first smoothing; z1 = eta sum ext(w), t = g - K z1 and the
+//   alpha = rho / p.q, x += alpha p and g -= alpha q             (k_pcg_update)
+//   z = B_TG g: the first smoothing; z1 = eta sum ext(w), t = g - K z1 and the
 //   block restriction W_b^T t (k_gather_res_restrict); coarse accumulation and
 //   the two triangular products, or one product with the explicit inverse
-//   (k_dense.hip); the second smoothing, which forms
-//   z1' = z1 + W c and its right-hand side g - K z1' on each patch itself
-//   (k_smooth.hip); z = z1' + eta sum ext(w) with the partials of g.z, gold.z and
-//   |C z|^2 (k_gather_final).
+//   (k_dense.hip); z1' = z1 + W c and the second smoothing's right-hand side
+//   g - K z1' (k_prolong_residual); the second smoothing (k_smooth.hip);
+//   z = z1' + eta sum ext(w) with the partials of g.z, gold.z and |C z|^2
+//   (k_gather_final).
 // The partials of k_gather_final are finalised by the next iteration's
 // k_dir_apply (every workgroup forms the same sums; workgroup 0 records them),
 // or by k_finalize where the host needs the scalars (after the first
 // preconditioning and at the end of each group of queued iterations).  A
 // "pending" flag in sc tells which: set by k_gather_final, cleared by k_finalize
-// or by the first smoothing (the kernel after the one that finalised), so that no
+// or by k_pcg_update (the kernel after the one that finalised), so that no
 // workgroup reads a scalar another workgroup of the same kernel writes.
 // The reducing kernels run on a fixed grid of nred <= NRED workgroups (chosen by
 // the autotuner) that loop over the tiles and write one partial each; the
@@ -393,6 +393,107 @@ inline const T* slots(tgms_ctx* c) {
 
 // t = g - K z on the interior vertices (zero elsewhere), FP64: the residual between the
 // steps of the unfused two-grid variants (several smoothings, additive coarse correction)
+// The PCG update ahead of a preconditioning: alpha = rho' / p.q from the partials of
+// k_dir_apply (every workgroup forms the sum, in the order of a 256-thread workgroup;
+// workgroup 0 records the scalars), then on the interior vertices g = gin - alpha q
+// (FP64, and rounded once to T for the smoother where gT is given) and x += alpha p.
+// A p.q that is not positive and finite stops the iteration (breakdown flag).
+template <typename T>
+__global__ void __launch_bounds__(NT) k_pcg_update(FusedUpdate U, T* __restrict__ gT, int nx, int ny) {
+    if (finished(U.sc)) return;
+    __shared__ double red[NT / 64];
+    const int t = threadIdx.y * TX + threadIdx.x;
+    double v = 0.0;
+    for (int j = t; j < U.nred; j += NT) v += U.part[j];
+    v = wave_sum(v);
+    if ((t & 63) == 0) red[t >> 6] = v;
+    __syncthreads();
+    const double pq = red[0] + red[1] + red[2] + red[3];
+    const double rho = U.sc[SC_RHO_NEW];
+    const double al = rho / pq;
+    const bool bad = !(pq > 0.0) || !(pq < INFINITY);
+    if (blockIdx.x == 0 && t == 0) {
+        U.sc[SC_RHO] = rho;
+        U.sc[SC_PENDING] = 0.0;
+        U.sc[SC_PQ] = pq;
+        U.sc[SC_ALPHA] = al;
+        U.hist[2 * (int)U.sc[SC_IT]] = al;
+        if (bad) {
+            U.sc[SC_FLAG] = 1.0;
+            U.sc[SC_DONE] = 1.0;
+        }
+    }
+    if (bad) return;
+    const long long nv = (long long)nx * ny;
+    for (long long v = blockIdx.x * (long long)NT + t; v < nv; v += (long long)gridDim.x * NT) {
+        const int i = (int)(v % nx), j = (int)(v / nx);
+        if (i == 0 || j == 0) continue;
+        const double gn = U.gin[v] - al * U.q[v];
+        U.gout[v] = gn;
+        U.x[v] += al * U.p[v];
+        if (gT != nullptr) gT[v] = T(gn);
+    }
+}
+
+// The second smoothing's right-hand side: z1' = z1 + W c on the coarse block's vertices
+// (written to Pr.z1p) and t = g - K z1' there, formed in FP64 and rounded once to T.
+// One workgroup per coarse block; the one-vertex halo of z1' is recomputed from the
+// neighbouring blocks' W and c (the same arithmetic as the block's own vertices), so
+// that every vertex of t is a function of that vertex alone.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_prolong_residual(PreResidual<T> Pr, T* __restrict__ t, int nx, int ny,
+                                                         int bx, int by, int Nx, const double* __restrict__ sc) {
+    if (finished(sc)) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int I = blockIdx.x % Nx, J = blockIdx.x / Nx, Ny = ny / by;
+    const int pw = bx + 2, ph = by + 2, mu = Pr.mu, nown = bx * by;
+    const int tid = threadIdx.y * TX + threadIdx.x;
+    double* Zt = reinterpret_cast<double*>(smem_raw);
+    T* cb = reinterpret_cast<T*>(Zt + pw * ph);  // [9][mu]: the coefficients of the 3 x 3 blocks around
+    for (int e = tid; e < 9 * mu; e += NT) {
+        const int nb = e / mu, uu = e % mu, Ib = I + nb % 3 - 1, Jb = J + nb / 3 - 1;
+        T val = T(0);
+        if (Ib >= 0 && Ib < Nx && Jb >= 0 && Jb < Ny) {
+            const int b = Jb * Nx + Ib;
+            if (uu < Pr.nunk[b]) val = Pr.c[Pr.unk[(long long)b * mu + uu]];
+        }
+        cb[e] = val;
+    }
+    __syncthreads();
+    for (int e = tid; e < pw * ph; e += NT) {
+        const int ex = e % pw, ey = e / pw, ii = I * bx - 1 + ex, jj = J * by - 1 + ey;
+        const bool own = ex >= 1 && ex <= bx && ey >= 1 && ey <= by;
+        const long long v = (long long)jj * nx + ii;
+        double val = 0.0;
+        if (ii >= 1 && ii < nx && jj >= 1 && jj < ny) {
+            const int Ib = ii / bx, Jb = jj / by, b = Jb * Nx + Ib;
+            const int nb = (Jb - J + 1) * 3 + (Ib - I + 1);
+            const T* Wv = Pr.W + ((long long)b * nown + (jj % by) * bx + ii % bx) * mu;
+            const T* cv = cb + nb * mu;
+            const int nu = Pr.nunk[b];
+            T s = T(0);
+            for (int q = 0; q < nu; ++q) s += Wv[q] * cv[q];
+            const T zz = Pr.z1[v] + s;
+            val = double(zz);
+            if (own) Pr.z1p[v] = zz;
+        } else if (own) {
+            Pr.z1p[v] = T(0);
+        }
+        Zt[e] = val;
+    }
+    __syncthreads();
+    for (int r = tid; r < nown; r += NT) {
+        const int aa = r % bx, bb = r / bx, i = I * bx + aa, j = J * by + bb;
+        const long long v = (long long)j * nx + i;
+        if (i == 0 || j == 0) {
+            t[v] = T(0);
+            continue;
+        }
+        const VertexData d = vertex_data(Pr.g, Pr.a, v, nx, true);
+        t[v] = T(d.g - stencil_at4(Zt, pw, aa + 1, bb + 1, d.A, Pr.sx2, Pr.sy2));
+    }
+}
+
 __global__ void k_vertex_residual(const double* __restrict__ g, const double* __restrict__ z,
                                   const double* __restrict__ a, int nx, int ny, double sx2, double sy2,
                                   double* __restrict__ t) {
@@ -437,6 +538,26 @@ void dir_apply(tgms_ctx* c, const double* z, const double* pin, double* pout, do
                            (const double*)c->part, c->nred, c->part2);
     LAUNCH_OK();
 }
+
+template <typename T>
+void pcg_update(tgms_ctx* c, const FusedUpdate& fu, T* gT) {
+    const long long nv = (long long)c->nx * c->ny;
+    const unsigned grid = (unsigned)std::min<long long>((nv + 4 * NT - 1) / (4 * NT), 2048);
+    hipLaunchKernelGGL((k_pcg_update<T>), dim3(std::max(grid, 1u)), dim3(TX, TY), 0, c->stream, fu, gT, c->nx, c->ny);
+    LAUNCH_OK();
+}
+template void pcg_update<double>(tgms_ctx*, const FusedUpdate&, double*);
+template void pcg_update<float>(tgms_ctx*, const FusedUpdate&, float*);
+
+template <typename T>
+void prolong_residual(tgms_ctx* c, const PreResidual<T>& pr, T* t, const double* sc) {
+    const size_t lds = sizeof(double) * (size_t)(c->bx + 2) * (c->by + 2) + sizeof(T) * 9 * (size_t)pr.mu;
+    hipLaunchKernelGGL((k_prolong_residual<T>), dim3(c->nblk), dim3(TX, TY), lds, c->stream, pr, t, c->nx, c->ny,
+                       c->bx, c->by, c->Nx, sc);
+    LAUNCH_OK();
+}
+template void prolong_residual<double>(tgms_ctx*, const PreResidual<double>&, double*, const double*);
+template void prolong_residual<float>(tgms_ctx*, const PreResidual<float>&, float*, const double*);
 
 void finalize(tgms_ctx* c, bool first) {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(TX, TY), 0, c->stream, c->sc, c->hist, (const double*)c->part,

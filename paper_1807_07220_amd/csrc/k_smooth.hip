@@ -554,42 +554,9 @@ template <typename T, int M1, int M2, bool GENERIC, bool KEEP>
 __global__ void __launch_bounds__(128) k_smooth_twisted(const Rect* __restrict__ rects, const T* __restrict__ Fpool,
                                                         const T* __restrict__ g, int nx, int ny, T* __restrict__ wout,
                                                         T* __restrict__ w4, int bx, int by, int Nx,
-                                                        const double* __restrict__ sc, FusedUpdate U,
-                                                        PreResidual<T> Pr) {
+                                                        const double* __restrict__ sc) {
     constexpr int NW = 2, NT = NW * 64;
     if (sc != nullptr && sc[SC_DONE] != 0.0) return;  // PCG already converged
-    double al = 0.0;
-    if (U.gin) {
-        // alpha = rho' / p.q from the partials of k_dir_apply (every workgroup forms it,
-        // summed in the order of a 256-thread workgroup)
-        __shared__ double red[4];
-        const int t = threadIdx.x;
-#pragma unroll
-        for (int h = 0; h < 4 / NW; ++h) {
-            const int tv = t + h * NT;
-            double v = 0.0;
-            for (int j = tv; j < U.nred; j += 256) v += U.part[j];
-            v = wave_sum(v);
-            if ((t & 63) == 0) red[tv >> 6] = v;
-        }
-        __syncthreads();
-        const double pq = red[0] + red[1] + red[2] + red[3];
-        const double rho = U.sc[SC_RHO_NEW];
-        al = rho / pq;
-        const bool bad = !(pq > 0.0) || !(pq < INFINITY);
-        if (blockIdx.x == 0 && t == 0) {
-            U.sc[SC_RHO] = rho;
-            U.sc[SC_PENDING] = 0.0;
-            U.sc[SC_PQ] = pq;
-            U.sc[SC_ALPHA] = al;
-            U.hist[2 * (int)U.sc[SC_IT]] = al;
-            if (bad) {
-                U.sc[SC_FLAG] = 1.0;
-                U.sc[SC_DONE] = 1.0;
-            }
-        }
-        if (bad) return;
-    }
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sm = reinterpret_cast<T*>(smem_raw);
     const Rect R = rects[blockIdx.x];
@@ -604,8 +571,8 @@ __global__ void __launch_bounds__(128) k_smooth_twisted(const Rect* __restrict__
     const int MW = GENERIC ? 0 : (m == M1 ? M1 : M2);
     const int trip = tw_trip(m), sw = trip + tw_b3(m);
     T* slots = midP + (GENERIC ? 0 : trip);
-    const long long lds_fixed = GENERIC ? 128 : 128 + trip + (KEEP ? 2LL * (mh / 2) : 4LL) * sw;
     (void)MW;
+    (void)sw;
     if (!GENERIC) {
         // stage P_k (16-byte copies)
         using V = float4;
@@ -616,69 +583,9 @@ __global__ void __launch_bounds__(128) k_smooth_twisted(const Rect* __restrict__
     }
     const T* Sg = Fg + tw_scale(m, mh);
     const int I = blockIdx.x % Nx, J = blockIdx.x / Nx;
-    if (Pr.z1) {
-        // z1' = z1 + W c on the patch and its one-vertex halo (LDS, FP64 of the stored
-        // value), the own block's z1' written out, then t = g - K z1' in FP64, rounded once
-        const int pw = m + 2, ph = mh + 2, mu = Pr.mu, nown = bx * by;
-        const size_t zoff = ((reinterpret_cast<size_t>(mid + lds_fixed) + 15) & ~(size_t)15);
-        double* Zt = reinterpret_cast<double*>(zoff);
-        T* cb = reinterpret_cast<T*>(Zt + pw * ph);  // [9][mu]: the 3 x 3 blocks around K_i
-        const int Ny = ny / by;
-        for (int e = tid; e < 9 * mu; e += NT) {
-            const int nb = e / mu, uu = e % mu, Ib = I + nb % 3 - 1, Jb = J + nb / 3 - 1;
-            T val = T(0);
-            if (Ib >= 0 && Ib < Nx && Jb >= 0 && Jb < Ny) {
-                const int b = Jb * Nx + Ib;
-                if (uu < Pr.nunk[b]) val = Pr.c[Pr.unk[(long long)b * mu + uu]];
-            }
-            cb[e] = val;
-        }
-        __syncthreads();
-        for (int e = tid; e < pw * ph; e += NT) {
-            const int ii = R.i0 + e % pw, jj = R.j0 + e / pw;
-            const bool own = ii >= I * bx && ii < (I + 1) * bx && jj >= J * by && jj < (J + 1) * by;
-            const long long v = (long long)jj * nx + ii;
-            double val = 0.0;
-            if (ii >= 1 && ii < nx && jj >= 1 && jj < ny) {
-                // vertex (ii, jj) lies in block (ii / bx, jj / by): neighbour nb of K_i
-                const int Ib = ii / bx, Jb = jj / by, b = Jb * Nx + Ib;
-                const int nb = (Jb - J + 1) * 3 + (Ib - I + 1);
-                const T* Wv = Pr.W + ((long long)b * nown + (jj % by) * bx + ii % bx) * mu;
-                const T* cv = cb + nb * mu;
-                const int nu = Pr.nunk[b];
-                T s = T(0);
-                for (int q = 0; q < nu; ++q) s += Wv[q] * cv[q];
-                const T zz = Pr.z1[v] + s;
-                val = double(zz);
-                if (own) Pr.z1p[v] = zz;
-            } else if (own && ii < nx && jj < ny) {
-                Pr.z1p[v] = T(0);
-            }
-            Zt[e] = val;
-        }
-        __syncthreads();
-        for (int r = tid; r < n; r += NT) {
-            const int aa = r % m, bb = r / m;
-            const long long v = (long long)(R.j0 + 1 + bb) * nx + R.i0 + 1 + aa;
-            const VertexData d = vertex_data(Pr.g, Pr.a, v, nx, true);
-            vec[r] = Sg[r] * T(d.g - stencil_at4(Zt, pw, aa + 1, bb + 1, d.A, Pr.sx2, Pr.sy2));
-        }
-    } else
     for (int r = tid; r < n; r += NT) {
-        const int aa = r % m, bb = r / m, i = R.i0 + 1 + aa, j = R.j0 + 1 + bb;
-        const long long v = (long long)j * nx + i;
-        T gv;
-        if (U.gin) {
-            const double gn = U.gin[v] - al * U.q[v];
-            if (i >= I * bx && i < (I + 1) * bx && j >= J * by && j < (J + 1) * by) {
-                U.gout[v] = gn;
-                U.x[v] += al * U.p[v];
-            }
-            gv = T(gn);
-        } else {
-            gv = g[v];
-        }
-        vec[r] = Sg[r] * gv;
+        const int aa = r % m, bb = r / m;
+        vec[r] = Sg[r] * g[(long long)(R.j0 + 1 + bb) * nx + R.i0 + 1 + aa];
     }
     __syncthreads();
     const long long plane = (long long)nx * ny;
@@ -697,49 +604,44 @@ __global__ void __launch_bounds__(128) k_smooth_twisted(const Rect* __restrict__
 #define TGMS_TW_PAIRS(X) X(7, 5) X(9, 7) X(11, 9) X(15, 13) X(19, 17) X(23, 21) X(27, 25) X(31, 29)
 
 template <typename T, int M1, int M2, bool GENERIC, bool KEEP>
-void launch_tw(tgms_ctx* c, const T* L, const T* g, T* w, size_t lds, const double* sc, const FusedUpdate& U,
-               const PreResidual<T>& Pr) {
+void launch_tw(tgms_ctx* c, const T* L, const T* g, T* w, size_t lds, const double* sc) {
     T* w4 = nullptr;
     if (c->slots) w4 = sizeof(T) == 8 ? (T*)c->patW4 : (T*)c->patW4_32;
     if (c->prof) {
         // events recorded by the dispatch itself (kernel execution only)
         hipEvent_t e1 = tgms::take_event(c), e2 = tgms::take_event(c);
         hipExtLaunchKernelGGL((k_smooth_twisted<T, M1, M2, GENERIC, KEEP>), dim3(c->nblk), dim3(128), lds,
-                              c->stream, e1, e2, 0, c->patch, L, g, c->nx, c->ny, w, w4, c->bx, c->by, c->Nx, sc, U, Pr);
+                              c->stream, e1, e2, 0, c->patch, L, g, c->nx, c->ny, w, w4, c->bx, c->by, c->Nx, sc);
         c->prof_rec.push_back({tgms::PK_SMOOTH, c->prof_iter, e1, e2});
     } else {
         hipLaunchKernelGGL((k_smooth_twisted<T, M1, M2, GENERIC, KEEP>), dim3(c->nblk), dim3(128), lds, c->stream,
-                           c->patch, L, g, c->nx, c->ny, w, w4, c->bx, c->by, c->Nx, sc, U, Pr);
+                           c->patch, L, g, c->nx, c->ny, w, w4, c->bx, c->by, c->Nx, sc);
     }
 }
 
-// LDS bytes of the smoother launch: the input vectors, mid, the middle pivot block,
-// the chain slots (the widest patch and the tallest) and, for the second smoothing,
-// the z1' tile and the coarse coefficients
+// LDS bytes of the smoother launch: the input vectors, mid, the middle pivot block and
+// the chain slots (the widest patch and the tallest)
 template <typename T>
-size_t smooth_lds(const tgms_ctx* c, bool keep, int mw, const PreResidual<T>* pr) {
+size_t smooth_lds(const tgms_ctx* c, bool keep, int mw) {
     const long long trip = tw_trip(mw), sw = trip + tw_b3(mw);
-    long long words = 2 * ((c->pat_nmax + 3) & ~3LL) + 128 + trip + (keep ? 2LL * (c->pat_hmax / 2) : 4LL) * sw;
-    size_t bytes = (size_t)words * sizeof(T);
-    if (pr && pr->z1) bytes += 16 + (size_t)c->pat_zmax * sizeof(double) + 9 * (size_t)pr->mu * sizeof(T);
-    return bytes;
+    const long long words = 2 * ((c->pat_nmax + 3) & ~3LL) + 128 + trip + (keep ? 2LL * (c->pat_hmax / 2) : 4LL) * sw;
+    return (size_t)words * sizeof(T);
 }
 
 // m1 >= m2: the two row widths present among the patches (equal when all
 // patches have one width, -1 when there are more than two)
 template <typename T, bool KEEP>
-bool dispatch_keep(tgms_ctx* c, int m1, int m2, const T* L, const T* g, T* w, const double* sc,
-                   const FusedUpdate& U, const PreResidual<T>& Pr) {
-#define TGMS_TW_CASE(A, B)                                                     \
-    if (m1 == A && (m2 == B || m2 == A)) {                                     \
-        const size_t lds = smooth_lds<T>(c, KEEP, A, &Pr);                     \
-        if (lds + 64 > (size_t)c->lds_max) return false;                       \
-        launch_tw<T, A, B, false, KEEP>(c, L, g, w, lds, sc, U, Pr);           \
-        return true;                                                           \
+bool dispatch_keep(tgms_ctx* c, int m1, int m2, const T* L, const T* g, T* w, const double* sc) {
+#define TGMS_TW_CASE(A, B)                                 \
+    if (m1 == A && (m2 == B || m2 == A)) {                 \
+        const size_t lds = smooth_lds<T>(c, KEEP, A);      \
+        if (lds + 64 > (size_t)c->lds_max) return false;   \
+        launch_tw<T, A, B, false, KEEP>(c, L, g, w, lds, sc); \
+        return true;                                       \
     }
     TGMS_TW_PAIRS(TGMS_TW_CASE)
 #undef TGMS_TW_CASE
-    launch_tw<T, 0, 0, true, false>(c, L, g, w, smooth_lds<T>(c, false, 0, &Pr), sc, U, Pr);
+    launch_tw<T, 0, 0, true, false>(c, L, g, w, smooth_lds<T>(c, false, 0), sc);
     return true;
 }
 
@@ -787,7 +689,7 @@ void factor_patches(tgms_ctx* c) {
 
 // local solves of every patch on g into the patch solution pool (patW / patW32)
 template <typename T>
-void smooth_patches(tgms_ctx* c, const T* g, const double* sc, const FusedUpdate* fu, const PreResidual<T>* pr) {
+void smooth_patches(tgms_ctx* c, const T* g, const double* sc) {
     const T* L;
     T* w;
     if constexpr (sizeof(T) == 8) {
@@ -799,21 +701,15 @@ void smooth_patches(tgms_ctx* c, const T* g, const double* sc, const FusedUpdate
     }
     // 1: the forward chains' blocks kept in LDS for the backward chains (where they
     // fit); 0 (and -1): staged twice, two slots per wave
-    const FusedUpdate none{};
-    const PreResidual<T> plain{};
-    const FusedUpdate& U = fu ? *fu : none;
-    const PreResidual<T>& P = pr ? *pr : plain;
-    if (c->smooth_staged == 1 && dispatch_keep<T, true>(c, c->pat_m1, c->pat_m2, L, g, w, sc, U, P)) {
+    if (c->smooth_staged == 1 && dispatch_keep<T, true>(c, c->pat_m1, c->pat_m2, L, g, w, sc)) {
         LAUNCH_OK();
         return;
     }
-    if (!dispatch_keep<T, false>(c, c->pat_m1, c->pat_m2, L, g, w, sc, U, P))
+    if (!dispatch_keep<T, false>(c, c->pat_m1, c->pat_m2, L, g, w, sc))
         throw TgmsError{TGMS_E_UNSUPPORTED, "smoother patch too large for LDS"};
     LAUNCH_OK();
 }
-template void smooth_patches<double>(tgms_ctx*, const double*, const double*, const FusedUpdate*,
-                                     const PreResidual<double>*);
-template void smooth_patches<float>(tgms_ctx*, const float*, const double*, const FusedUpdate*,
-                                    const PreResidual<float>*);
+template void smooth_patches<double>(tgms_ctx*, const double*, const double*);
+template void smooth_patches<float>(tgms_ctx*, const float*, const double*);
 
 }  // namespace tgms
