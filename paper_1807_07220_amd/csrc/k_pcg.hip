@@ -397,12 +397,27 @@ inline const T* slots(tgms_ctx* c) {
 // k_dir_apply (every workgroup forms the sum, in the order of a 256-thread workgroup;
 // workgroup 0 records the scalars), then on the interior vertices g = gin - alpha q
 // (FP64, and rounded once to T for the smoother where gT is given) and x += alpha p.
-// A p.q that is not positive and finite stops the iteration (breakdown flag).
+// A p.q that is not positive and finite stops the iteration (breakdown flag).  Each
+// thread takes UP vertices, whose vectors are loaded before the partials are summed
+// so that both are in flight together.
 template <typename T>
 __global__ void __launch_bounds__(NT) k_pcg_update(FusedUpdate U, T* __restrict__ gT, int nx, int ny) {
     if (finished(U.sc)) return;
-    __shared__ double red[NT / 64];
+    constexpr int UP = 4;
     const int t = threadIdx.y * TX + threadIdx.x;
+    const long long nv = (long long)nx * ny;
+    double G[UP], Q[UP], P[UP], X[UP];
+    long long vv[UP];
+#pragma unroll
+    for (int h = 0; h < UP; ++h) {
+        vv[h] = (long long)blockIdx.x * (UP * NT) + h * NT + t;
+        const long long k = vv[h] < nv ? vv[h] : nv - 1;
+        G[h] = U.gin[k];
+        Q[h] = U.q[k];
+        P[h] = U.p[k];
+        X[h] = U.x[k];
+    }
+    __shared__ double red[NT / 64];
     double v = 0.0;
     for (int j = t; j < U.nred; j += NT) v += U.part[j];
     v = wave_sum(v);
@@ -424,14 +439,14 @@ __global__ void __launch_bounds__(NT) k_pcg_update(FusedUpdate U, T* __restrict_
         }
     }
     if (bad) return;
-    const long long nv = (long long)nx * ny;
-    for (long long v = blockIdx.x * (long long)NT + t; v < nv; v += (long long)gridDim.x * NT) {
-        const int i = (int)(v % nx), j = (int)(v / nx);
-        if (i == 0 || j == 0) continue;
-        const double gn = U.gin[v] - al * U.q[v];
-        U.gout[v] = gn;
-        U.x[v] += al * U.p[v];
-        if (gT != nullptr) gT[v] = T(gn);
+#pragma unroll
+    for (int h = 0; h < UP; ++h) {
+        const long long k = vv[h];
+        if (k >= nv || k % nx == 0 || k < nx) continue;  // past the end, or a boundary vertex
+        const double gn = G[h] - al * Q[h];
+        U.gout[k] = gn;
+        U.x[k] = X[h] + al * P[h];
+        if (gT != nullptr) gT[k] = T(gn);
     }
 }
 
@@ -439,17 +454,51 @@ __global__ void __launch_bounds__(NT) k_pcg_update(FusedUpdate U, T* __restrict_
 // (written to Pr.z1p) and t = g - K z1' there, formed in FP64 and rounded once to T.
 // One workgroup per coarse block; the one-vertex halo of z1' is recomputed from the
 // neighbouring blocks' W and c (the same arithmetic as the block's own vertices), so
-// that every vertex of t is a function of that vertex alone.
+// that every vertex of t is a function of that vertex alone.  The loads that do not
+// depend on c (z1, the first QB entries of each W row, the own vertices' g and cell
+// weights) are issued before the coefficients are staged; W rows are read QB entries
+// at a time, the indices past the row clamped to its last entry and multiplied by
+// zero coefficients, so that each batch is in flight at once and the sum is that of
+// the row's nu entries.
 template <typename T>
 __global__ void __launch_bounds__(NT) k_prolong_residual(PreResidual<T> Pr, T* __restrict__ t, int nx, int ny,
                                                          int bx, int by, int Nx, const double* __restrict__ sc) {
     if (finished(sc)) return;
+    constexpr int QB = 8;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int I = blockIdx.x % Nx, J = blockIdx.x / Nx, Ny = ny / by;
-    const int pw = bx + 2, ph = by + 2, mu = Pr.mu, nown = bx * by;
+    const int pw = bx + 2, ph = by + 2, mu = Pr.mu, nown = bx * by, ntile = pw * ph;
     const int tid = threadIdx.y * TX + threadIdx.x;
     double* Zt = reinterpret_cast<double*>(smem_raw);
-    T* cb = reinterpret_cast<T*>(Zt + pw * ph);  // [9][mu]: the coefficients of the 3 x 3 blocks around
+    T* cb = reinterpret_cast<T*>(Zt + ntile);  // [9][mu]: the coefficients of the 3 x 3 blocks around
+    // tile element e: vertex (ii, jj), its block's W row and neighbour index (-1 outside the domain)
+    struct Elem {
+        long long v;
+        const T* Wv;
+        int nb;
+    };
+    auto elem = [&](int e) {
+        const int ii = I * bx - 1 + e % pw, jj = J * by - 1 + e / pw;
+        Elem x{(long long)jj * nx + ii, Pr.W, -1};
+        if (ii >= 1 && ii < nx && jj >= 1 && jj < ny) {
+            const int Ib = ii / bx, Jb = jj / by;
+            x.Wv = Pr.W + ((long long)(Jb * Nx + Ib) * nown + (jj % by) * bx + ii % bx) * mu;
+            x.nb = (Jb - J + 1) * 3 + (Ib - I + 1);
+        }
+        return x;
+    };
+    auto load_w = [&](const Elem& x, int q0, T (&w)[QB]) {
+#pragma unroll
+        for (int q = 0; q < QB; ++q) w[q] = x.Wv[min(q0 + q, mu - 1)];
+    };
+    // prefetch: the first tile element's z1 and W entries, the first own vertex's data
+    const Elem x0 = elem(tid < ntile ? tid : 0);
+    T w0[QB];
+    load_w(x0, 0, w0);
+    const T z0 = x0.nb >= 0 ? Pr.z1[x0.v] : T(0);
+    const int r0 = tid < nown ? tid : 0;
+    const long long v0 = (long long)(J * by + r0 / bx) * nx + I * bx + r0 % bx;
+    const VertexData d0 = vertex_data(Pr.g, Pr.a, v0, nx, J * by + r0 / bx > 0 && I * bx + r0 % bx > 0);
     for (int e = tid; e < 9 * mu; e += NT) {
         const int nb = e / mu, uu = e % mu, Ib = I + nb % 3 - 1, Jb = J + nb / 3 - 1;
         T val = T(0);
@@ -460,24 +509,31 @@ __global__ void __launch_bounds__(NT) k_prolong_residual(PreResidual<T> Pr, T* _
         cb[e] = val;
     }
     __syncthreads();
-    for (int e = tid; e < pw * ph; e += NT) {
-        const int ex = e % pw, ey = e / pw, ii = I * bx - 1 + ex, jj = J * by - 1 + ey;
+    for (int e = tid; e < ntile; e += NT) {
+        const bool first = e == tid;
+        const Elem x = first ? x0 : elem(e);
+        const int ex = e % pw, ey = e / pw;
         const bool own = ex >= 1 && ex <= bx && ey >= 1 && ey <= by;
-        const long long v = (long long)jj * nx + ii;
         double val = 0.0;
-        if (ii >= 1 && ii < nx && jj >= 1 && jj < ny) {
-            const int Ib = ii / bx, Jb = jj / by, b = Jb * Nx + Ib;
-            const int nb = (Jb - J + 1) * 3 + (Ib - I + 1);
-            const T* Wv = Pr.W + ((long long)b * nown + (jj % by) * bx + ii % bx) * mu;
-            const T* cv = cb + nb * mu;
-            const int nu = Pr.nunk[b];
+        if (x.nb >= 0) {
+            const T* cv = cb + x.nb * mu;
             T s = T(0);
-            for (int q = 0; q < nu; ++q) s += Wv[q] * cv[q];
-            const T zz = Pr.z1[v] + s;
+            T w[QB];
+            for (int q0 = 0; q0 < mu; q0 += QB) {
+                if (first && q0 == 0) {
+#pragma unroll
+                    for (int q = 0; q < QB; ++q) w[q] = w0[q];
+                } else {
+                    load_w(x, q0, w);
+                }
+#pragma unroll
+                for (int q = 0; q < QB; ++q) s += w[q] * (q0 + q < mu ? cv[q0 + q] : T(0));
+            }
+            const T zz = (first ? z0 : Pr.z1[x.v]) + s;
             val = double(zz);
-            if (own) Pr.z1p[v] = zz;
+            if (own) Pr.z1p[x.v] = zz;
         } else if (own) {
-            Pr.z1p[v] = T(0);
+            Pr.z1p[x.v] = T(0);
         }
         Zt[e] = val;
     }
@@ -489,7 +545,7 @@ __global__ void __launch_bounds__(NT) k_prolong_residual(PreResidual<T> Pr, T* _
             t[v] = T(0);
             continue;
         }
-        const VertexData d = vertex_data(Pr.g, Pr.a, v, nx, true);
+        const VertexData d = r == tid ? d0 : vertex_data(Pr.g, Pr.a, v, nx, true);
         t[v] = T(d.g - stencil_at4(Zt, pw, aa + 1, bb + 1, d.A, Pr.sx2, Pr.sy2));
     }
 }
@@ -542,7 +598,7 @@ void dir_apply(tgms_ctx* c, const double* z, const double* pin, double* pout, do
 template <typename T>
 void pcg_update(tgms_ctx* c, const FusedUpdate& fu, T* gT) {
     const long long nv = (long long)c->nx * c->ny;
-    const unsigned grid = (unsigned)std::min<long long>((nv + 4 * NT - 1) / (4 * NT), 2048);
+    const unsigned grid = (unsigned)((nv + 4 * NT - 1) / (4 * NT));
     hipLaunchKernelGGL((k_pcg_update<T>), dim3(std::max(grid, 1u)), dim3(TX, TY), 0, c->stream, fu, gT, c->nx, c->ny);
     LAUNCH_OK();
 }
