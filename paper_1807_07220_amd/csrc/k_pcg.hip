@@ -118,7 +118,12 @@ __device__ inline bool finalise(double* __restrict__ sc, double* __restrict__ hi
 
 // p_out = z + beta p_in, q = K p_out, and the workgroup's partial sum of p_out . q
 // (part).  beta comes from finalising the pending partials gpart, else from sc.  The
-// workgroups loop over tiles of 64 x 4 RPT vertices, RPT rows per thread.
+// workgroups loop over tiles of 64 x 4 RPT vertices, RPT rows per thread; the loads
+// of a tile (cell weights, z and p_in on the tile and its halo) are issued before
+// the previous tile's stencil (and the first tile's before the partials are
+// finalised), at indices clamped into the grid and zeroed outside it, so that they
+// are in flight while the workgroup computes.  Past the last tile the prefetch
+// repeats the grid's last tile (an L2 hit: every workgroup ends there).
 template <int RPT>
 __global__ void __launch_bounds__(NT) k_dir_apply(const double* __restrict__ z, const double* __restrict__ pin,
                                                   double* __restrict__ pout, double* __restrict__ q,
@@ -127,10 +132,39 @@ __global__ void __launch_bounds__(NT) k_dir_apply(const double* __restrict__ z, 
                                                   const double* __restrict__ gpart, int nred,
                                                   double* __restrict__ part) {
     if (finished(sc)) return;
-    constexpr int H = TY * RPT;
+    constexpr int H = TY * RPT, NE = (TX + 2) * (H + 2), HE = (NE + NT - 1) / NT;
     __shared__ double P[H + 2][TX + 2];
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
     const int ntx = (nx + TX - 1) / TX, ntiles = ntx * ((ny + H - 1) / H);
+    struct Tile {
+        double A[RPT][4];  // cell weights of the thread's vertices
+        double Z[HE], Q[HE];  // z and p_in of its halo-tile elements
+    };
+    auto load = [&](int tile, Tile& T) {
+        const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * H, i = i0 + tx;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int j = j0 + ty + TY * r;
+            const bool in = i > 0 && j > 0 && i < nx && j < ny;
+            const long long vv = in ? (long long)j * nx + i : nx + 1;
+            const double w0 = a[vv - nx - 1], w1 = a[vv - nx], w2 = a[vv - 1], w3 = a[vv];
+            T.A[r][0] = in ? w0 : 0.0;
+            T.A[r][1] = in ? w1 : 0.0;
+            T.A[r][2] = in ? w2 : 0.0;
+            T.A[r][3] = in ? w3 : 0.0;
+        }
+#pragma unroll
+        for (int h = 0; h < HE; ++h) {
+            const int e = tid + h * NT, ii = i0 - 1 + e % (TX + 2), jj = j0 - 1 + e / (TX + 2);
+            const bool in = e < NE && ii >= 1 && ii < nx && jj >= 1 && jj < ny;
+            const long long ve = in ? (long long)jj * nx + ii : 0;
+            const double zv = z[ve], pv = pin[ve];
+            T.Z[h] = in ? zv : 0.0;
+            T.Q[h] = in ? pv : 0.0;
+        }
+    };
+    Tile cur;
+    load(min((int)blockIdx.x, ntiles - 1), cur);
     double beta = sc[SC_BETA];
     if (sc[SC_PENDING] != 0.0) {
         const bool rec = blockIdx.x == 0 && tid == 0;
@@ -140,28 +174,18 @@ __global__ void __launch_bounds__(NT) k_dir_apply(const double* __restrict__ z, 
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * H;
         const int i = i0 + tx;
-        double A[RPT][4];  // weights load with the tile
 #pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            const int j = j0 + ty + TY * r;
-            const long long vv = (long long)j * nx + i;
-            const bool in = i > 0 && j > 0 && i < nx && j < ny;
-            A[r][0] = in ? a[vv - nx - 1] : 0.0;
-            A[r][1] = in ? a[vv - nx] : 0.0;
-            A[r][2] = in ? a[vv - 1] : 0.0;
-            A[r][3] = in ? a[vv] : 0.0;
+        for (int h = 0; h < HE; ++h) {
+            const int e = tid + h * NT;
+            if (e < NE) P[e / (TX + 2)][e % (TX + 2)] = cur.Z[h] + beta * cur.Q[h];
         }
+        double A[RPT][4];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) A[r][k] = cur.A[r][k];
         __syncthreads();
-        for (int e = tid; e < (TX + 2) * (H + 2); e += NT) {
-            const int ii = i0 - 1 + e % (TX + 2), jj = j0 - 1 + e / (TX + 2);
-            double val = 0.0;
-            if (ii >= 1 && ii < nx && jj >= 1 && jj < ny) {
-                const long long ve = (long long)jj * nx + ii;
-                val = z[ve] + beta * pin[ve];
-            }
-            P[e / (TX + 2)][e % (TX + 2)] = val;
-        }
-        __syncthreads();
+        load(min(tile + (int)gridDim.x, ntiles - 1), cur);
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             const int y = ty + TY * r, j = j0 + y;
@@ -174,6 +198,7 @@ __global__ void __launch_bounds__(NT) k_dir_apply(const double* __restrict__ z, 
                 v[0] += pc * qv;
             }
         }
+        __syncthreads();
     }
     group_sum<1>(v);
     if (tid == 0) part[blockIdx.x] = v[0];
