@@ -670,6 +670,26 @@ __global__ void __launch_bounds__(NT) k_bcr_schur(const double* __restrict__ Gm,
     }
 }
 
+// The system left after the levels s < step: blocks p = 0 .. nr-1 standing for e = p step,
+// diagonal D_e, couplings A_{e, e-step} = Lc_e (and their transposes above the
+// diagonal); M is (nr bs) x (nr bs), row-major.
+__global__ void k_bcr_reduced(const double* __restrict__ D, const double* __restrict__ Lc, int bs, int step, int nr,
+                              double* __restrict__ M) {
+    const long long nn = (long long)nr * bs, e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= nn * nn) return;
+    const int R = (int)(e / nn), Cc = (int)(e % nn);
+    const int p = R / bs, r = R % bs, q = Cc / bs, cc = Cc % bs;
+    const long long bb = (long long)bs * bs;
+    double v = 0.0;
+    if (p == q)
+        v = D[(long long)p * step * bb + (long long)r * bs + cc];
+    else if (q == p - 1)
+        v = Lc[(long long)p * step * bb + (long long)r * bs + cc];
+    else if (q == p + 1)
+        v = Lc[(long long)q * step * bb + (long long)cc * bs + r];
+    M[e] = v;
+}
+
 __global__ void k_d2f(const double* __restrict__ x, float* __restrict__ y, long long n) {
     const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (e < n) y[e] = (float)x[e];
@@ -699,7 +719,8 @@ struct BcrView {
 
 template <typename T, int KM>
 __global__ void __launch_bounds__(SNT) k_bcr_fwd(BcrView<T> F, T* __restrict__ x, T* __restrict__ Y, int bs,
-                                                int nblk, int s, int chunks, const double* __restrict__ sc) {
+                                                int nblk, int s, int chunks, int stage,
+                                                const double* __restrict__ sc) {
     if (sc != nullptr && sc[SC_DONE] != 0.0) return;
     const int pos = blockIdx.x / chunks, ch = blockIdx.x - pos * chunks;
     const int e = 2 * s * pos;
@@ -735,9 +756,38 @@ __global__ void __launch_bounds__(SNT) k_bcr_fwd(BcrView<T> F, T* __restrict__ x
         y += __shfl_xor(y, o, 64);
     }
     if (r < bs && l == 0) {
-        x[(long long)e * bs + r] -= t;
+        const T xe = x[(long long)e * bs + r] - t;
+        x[(long long)e * bs + r] = xe;
         if (h2) Y[(long long)i2 * bs + r] = y;
+        if (stage) Y[(long long)e * bs + r] = xe;  // the reduced system's right-hand side
     }
+}
+
+// The truncated reduction's top: x_e = (Minv b)_e on the remaining blocks e = p step,
+// b read from Y there (staged by the last forward level, so that no workgroup reads
+// what another writes).  Four rows a workgroup, one wavefront a row, each lane KD
+// columns with their loads in flight together; b staged in LDS.
+constexpr int DNT = 256;
+template <int KD>
+__global__ void __launch_bounds__(DNT) k_bcr_dense(const double* __restrict__ Minv, double* __restrict__ x,
+                                                  const double* __restrict__ Y, int bs, int step, int nr,
+                                                  const double* __restrict__ sc) {
+    if (sc != nullptr && sc[SC_DONE] != 0.0) return;
+    __shared__ double b[64 * KD];
+    const int nn = nr * bs, tid = threadIdx.x, lane = tid & 63;
+    const int row = blockIdx.x * (DNT / 64) + (tid >> 6), rc = min(row, nn - 1);
+    const double* a = Minv + (long long)rc * nn;
+    double m[KD];
+#pragma unroll
+    for (int j = 0; j < KD; ++j) m[j] = a[min(lane + 64 * j, nn - 1)];
+    for (int k = tid; k < nn; k += DNT) b[k] = Y[((long long)(k / bs) * step) * bs + k % bs];
+    __syncthreads();
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < KD; ++j)
+        if (lane + 64 * j < nn) acc += m[j] * b[lane + 64 * j];
+    acc = wave_sum(acc);
+    if (row < nn && lane == 0) x[((long long)(row / bs) * step) * bs + row % bs] = acc;
 }
 
 // x_0 = R_0 x_0: one workgroup of 1024 threads (64 rows a pass), x_0 staged in LDS
@@ -1415,7 +1465,7 @@ int bcr_max_block(const tgms_ctx* c) {
     return bs;
 }
 
-void bcr_factor(tgms_ctx* c, const double* A, int n, int bs, Bcr& F, bool fp32) {
+void bcr_factor(tgms_ctx* c, const double* A, int n, int bs, Bcr& F, bool fp32, bool truncate) {
     if (bs < 1 || bs > bcr_max_block(c)) throw TgmsError{TGMS_E_UNSUPPORTED, "coarse bandwidth too large"};
     const int nblk = (n + bs - 1) / bs;
     const long long bb = (long long)bs * bs, tot = nblk * bb;
@@ -1433,6 +1483,7 @@ void bcr_factor(tgms_ctx* c, const double* A, int n, int bs, Bcr& F, bool fp32) 
         F.Y = c->alloc<double>((size_t)nblk * bs);
         F.x = c->alloc<double>((size_t)nblk * bs);
         F.fail = c->alloc<int>(1);
+        F.Minv = nullptr;
         if (fp32) {
             F.CT = c->alloc<double>(tot);
             F.GmT = c->alloc<double>(tot);
@@ -1457,7 +1508,21 @@ void bcr_factor(tgms_ctx* c, const double* A, int n, int bs, Bcr& F, bool fp32) 
     const size_t lds = sizeof(double) * (size_t)bb;
     HIP_OK(hipFuncSetAttribute((const void*)k_bcr_factor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const int T = (bs + TB - 1) / TB;
-    for (int s = 1; s < nblk; s *= 2) {
+    // truncation: the smallest step (a power of two, at least 2) whose remaining system
+    // fits the explicit-inverse apply, if that skips at least one level
+    int step = 0;
+    if (truncate && !fp32) {
+        int full = 1;
+        while (full < nblk) full *= 2;
+        for (int st = 2; st < full; st *= 2)
+            if ((long long)((nblk + st - 1) / st) * bs <= symv_acc_max()) {
+                step = st;
+                break;
+            }
+    }
+    F.step = step;
+    F.nr = step ? (nblk + step - 1) / step : 0;
+    for (int s = 1; s < nblk && (step == 0 || s < step); s *= 2) {
         const int ne = (nblk - s - 1) / (2 * s) + 1, na = (nblk - 1) / (2 * s) + 1;
         hipLaunchKernelGGL(k_bcr_factor, dim3(ne), dim3(FNT), lds, c->stream, (const double*)F.D, F.C, bs, nblk, s, 0,
                            F.fail);
@@ -1469,9 +1534,22 @@ void bcr_factor(tgms_ctx* c, const double* A, int n, int bs, Bcr& F, bool fp32) 
                            (const double*)F.Gp, F.D, F.Lc, bs, nblk, s);
         LAUNCH_OK();
     }
-    hipLaunchKernelGGL(k_bcr_factor, dim3(1), dim3(FNT), lds, c->stream, (const double*)F.D, F.C, bs, nblk, 1, 1,
-                       F.fail);
-    LAUNCH_OK();
+    if (step) {
+        // the remaining blocks 0, step, 2 step, ...: their system, inverted explicitly
+        const long long nn = (long long)F.nr * bs;
+        if (!F.Minv) F.Minv = c->alloc<double>(nn * nn);
+        double* M = c->alloc<double>(nn * nn);
+        hipLaunchKernelGGL(k_bcr_reduced, dim3(nb(nn * nn)), dim3(256), 0, c->stream, (const double*)F.D,
+                           (const double*)F.Lc, bs, step, F.nr, M);
+        LAUNCH_OK();
+        dense_spd_inverse(c, M, (int)nn, F.Minv);  // synchronises: M is free again
+        dev_free(c->owned.back().p, c->owned.back().bytes);
+        c->owned.pop_back();
+    } else {
+        hipLaunchKernelGGL(k_bcr_factor, dim3(1), dim3(FNT), lds, c->stream, (const double*)F.D, F.C, bs, nblk, 1, 1,
+                           F.fail);
+        LAUNCH_OK();
+    }
     // the products the solve applies (MFMA, batched over the blocks; rows of Gp and
     // columns of Gm without a neighbour are zero)
     const Strided one{bb, 0, 1};
@@ -1502,19 +1580,40 @@ bool bcr_failed(tgms_ctx* c, const Bcr& F) {
     return h != 0;
 }
 
+// the truncated top: x on the remaining blocks = Minv (their staged right-hand side)
+void bcr_dense_top(tgms_ctx* c, const Bcr& F, double* x, const double* sc) {
+    const int nn = F.nr * F.bs;
+    const dim3 grid((unsigned)((nn + DNT / 64 - 1) / (DNT / 64)));
+    if (nn <= 64 * 4)
+        hipLaunchKernelGGL((k_bcr_dense<4>), grid, dim3(DNT), 0, c->stream, F.Minv, x, F.Y, F.bs, F.step, F.nr, sc);
+    else if (nn <= 64 * 8)
+        hipLaunchKernelGGL((k_bcr_dense<8>), grid, dim3(DNT), 0, c->stream, F.Minv, x, F.Y, F.bs, F.step, F.nr, sc);
+    else if (nn <= 64 * 16)
+        hipLaunchKernelGGL((k_bcr_dense<16>), grid, dim3(DNT), 0, c->stream, F.Minv, x, F.Y, F.bs, F.step, F.nr, sc);
+    else
+        throw TgmsError{TGMS_E_UNSUPPORTED, "reduced coarse system too large"};
+    LAUNCH_OK();
+}
+
 template <typename T, int KM>
-void bcr_solve_k(tgms_ctx* c, const BcrView<T>& V, T* x, T* Y, int bs, int nblk, const double* sc) {
+void bcr_solve_k(tgms_ctx* c, const Bcr& F, const BcrView<T>& V, T* x, T* Y, int bs, int nblk, const double* sc) {
     const int chunks = (bs + SROWS - 1) / SROWS;
     int top = 1;
     while (top < nblk) top *= 2;
-    for (int s = 1; s < nblk; s *= 2) {
+    const int step = F.step;
+    for (int s = 1; s < nblk && (step == 0 || s < step); s *= 2) {
         const int na = (nblk - 1) / (2 * s) + 1;
         hipLaunchKernelGGL((k_bcr_fwd<T, KM>), dim3(na * chunks), dim3(SNT), 0, c->stream, V, x, Y, bs, nblk, s,
-                           chunks, sc);
+                           chunks, step != 0 && 2 * s == step ? 1 : 0, sc);
         LAUNCH_OK();
     }
-    hipLaunchKernelGGL((k_bcr_top<T, KM>), dim3(1), dim3(TNT), 0, c->stream, V, x, bs, sc);
-    LAUNCH_OK();
+    if (step) {
+        bcr_dense_top(c, F, x, sc);
+        top = step;
+    } else {
+        hipLaunchKernelGGL((k_bcr_top<T, KM>), dim3(1), dim3(TNT), 0, c->stream, V, x, bs, sc);
+        LAUNCH_OK();
+    }
     for (int s = top / 2; s >= 1; s /= 2) {
         if (s >= nblk) continue;
         const int ne = (nblk - s - 1) / (2 * s) + 1;
@@ -1589,13 +1688,13 @@ void bcr_solve(tgms_ctx* c, const Bcr& F, T* x, const double* sc) {
         T* Y = F.Y;
         // column slots per lane: 16 lanes a row
         if (bs <= 4 * SG)
-            bcr_solve_k<T, 4>(c, V, x, Y, bs, nblk, sc);
+            bcr_solve_k<T, 4>(c, F, V, x, Y, bs, nblk, sc);
         else if (bs <= 5 * SG)
-            bcr_solve_k<T, 5>(c, V, x, Y, bs, nblk, sc);
+            bcr_solve_k<T, 5>(c, F, V, x, Y, bs, nblk, sc);
         else if (bs <= 8 * SG)
-            bcr_solve_k<T, 8>(c, V, x, Y, bs, nblk, sc);
+            bcr_solve_k<T, 8>(c, F, V, x, Y, bs, nblk, sc);
         else
-            bcr_solve_k<T, 9>(c, V, x, Y, bs, nblk, sc);
+            bcr_solve_k<T, 9>(c, F, V, x, Y, bs, nblk, sc);
     }
 }
 template void bcr_solve<double>(tgms_ctx*, const Bcr&, double*, const double*);
