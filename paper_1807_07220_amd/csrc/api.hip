@@ -662,9 +662,10 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
     // that the inverse's clean-up still finds it
     struct Side {
         hipStream_t s = nullptr;
-        hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, ez = nullptr;
         ~Side() {
             if (s) (void)hipStreamSynchronize(s);
+            if (ez) (void)hipEventDestroy(ez);
             if (e0) (void)hipEventDestroy(e0);
             if (e1) (void)hipEventDestroy(e1);
             if (e2) (void)hipEventDestroy(e2);
@@ -748,8 +749,30 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         HIP_OK(hipEventCreateWithFlags(&side.e0, hipEventDisableTiming));
         HIP_OK(hipEventCreateWithFlags(&side.e1, hipEventDisableTiming));
         HIP_OK(hipEventCreateWithFlags(&side.e2, hipEventDisableTiming));
+        HIP_OK(hipEventCreateWithFlags(&side.ez, hipEventDisableTiming));
         HIP_OK(hipEventRecord(side.e0, c->stream));
         HIP_OK(hipStreamWaitEvent(side.s, side.e0, 0));
+        // The large spectral buffers are allocated with their clearing queued on the
+        // second stream, where it runs during the block factorisation; the snapshots wait
+        // for it (event ez).
+        const bool gram_mfma = tgms::gram_uses_mfma(c);
+        const size_t nvk = (size_t)(bx + 1) * (by + 1);
+        {
+            const hipStream_t main_stream = c->stream;
+            struct Restore {
+                tgms_ctx* c;
+                hipStream_t s;
+                ~Restore() { c->stream = s; }
+            } restore{c, main_stream};
+            c->stream = side.s;
+            // snapshots (A Psi is the snapshot solves' scratch until the Gram products),
+            // A_K Psi for the Gram kernel without matrix cores (the path integrals of the
+            // coarse assembly reuse it: nblk * (bx+1)(by+1) * ncol) and the Grams
+            c->Psi = c->alloc<double>((size_t)c->nblk * c->ncol * c->nfk);
+            c->APsi = c->alloc<double>((size_t)c->nblk * c->ncol * (gram_mfma ? nvk : (size_t)c->nfk));
+            c->G = c->alloc<double>((size_t)c->nblk * c->ncol * c->ncol);
+            HIP_OK(hipEventRecord(side.ez, side.s));
+        }
         {
             Timer t(c->stream);
             blk_fail = c->alloc<int>(1);
@@ -757,14 +780,7 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
             // snapshots + Gram (queued before the coarse RT0 inverse on the second stream:
             // queueing that inverse's few hundred launches takes the host milliseconds,
             // which these kernels then cover)
-            c->Psi = c->alloc<double>((size_t)c->nblk * c->ncol * c->nfk);
-            // A_K Psi for the Gram kernel without matrix cores; the path integrals of the
-            // coarse assembly reuse it (nblk * (bx+1)(by+1) * ncol)
-            const bool gram_mfma = tgms::gram_uses_mfma(c);
-            const size_t nvk = (size_t)(bx + 1) * (by + 1);
-            c->APsi = c->alloc<double>((size_t)c->nblk * c->ncol * (gram_mfma ? nvk : (size_t)c->nfk));
-            c->G = c->alloc<double>((size_t)c->nblk * c->ncol * c->ncol);
-            // the A Psi array is free until the Gram products: the snapshot solves' scratch
+            HIP_OK(hipStreamWaitEvent(c->stream, side.ez, 0));
             if (c->coarse_space != 2) {  // the RT0 coarse space needs no snapshots
                 tgms::snapshots(c, c->APsi, (long long)c->ncol * (gram_mfma ? (long long)nvk : (long long)c->nfk));
                 tgms::gram(c);
@@ -838,6 +854,32 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                 if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
                 tgms::factor_patches_launch(c, pat_fail, 2 * cus);
                 pat_timer.stop(side.s);
+                // the pressure's DCT matrices and the solve workspaces, cleared on this
+                // stream too (the host queues them while the spectral kernels run)
+                // pressure: orthonormal DCT-II matrices and the 1D Neumann eigenvalues
+                c->Qx = c->alloc<double>((size_t)nx * nx);
+                c->lamx = c->alloc<double>(nx);
+                c->Qy = c->alloc<double>((size_t)ny * ny);
+                c->lamy = c->alloc<double>(ny);
+                tgms::dct_matrix(c, nx, c->Qx, c->lamx);
+                tgms::dct_matrix(c, ny, c->Qy, c->lamy);
+                // solve workspaces
+                const long long nvtx = ncell;
+                c->vx = c->alloc<double>(nvtx); c->vg = c->alloc<double>(nvtx); c->vz = c->alloc<double>(nvtx);
+                c->vp = c->alloc<double>(nvtx); c->vq = c->alloc<double>(nvtx); c->vt = c->alloc<double>(nvtx);
+                c->vt2 = c->alloc<double>(nvtx); c->vt3 = c->alloc<double>(nvtx); c->vgold = c->alloc<double>(nvtx);
+                c->vg2 = c->alloc<double>(nvtx);
+                c->fg = c->alloc<float>(nvtx); c->fz = c->alloc<float>(nvtx); c->ft = c->alloc<float>(nvtx);
+                c->ft2 = c->alloc<float>(nvtx);
+                c->fbar = c->alloc<double>(c->nf); c->fu = c->alloc<double>(c->nf); c->fF = c->alloc<double>(c->nf);
+                c->cellw = c->alloc<double>(ncell); c->cellw2 = c->alloc<double>(std::max<long long>(ncell, 2 * c->nblk));
+                c->blkbuf = c->alloc<double>(2 * (size_t)c->nblk);
+                c->sc = c->alloc<double>(SC_COUNT);
+                c->part = c->alloc<double>(3 * (size_t)tgms::pcg_tiles(c));
+                c->part2 = c->alloc<double>((size_t)tgms::pcg_tiles(c));
+                tgms::allow_fused_lds(c);
+                c->vp1 = c->alloc<double>(nvtx);
+                HIP_OK(hipHostMalloc((void**)&c->red_h, SC_COUNT * sizeof(double), hipHostMallocDefault));
                 HIP_OK(hipEventRecord(side.e2, side.s));
             }
             c->t_snap_ms = t.ms();
@@ -939,30 +981,6 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
             c->t_smoother_ms = pat_timer.ms();
             if (h) throw TgmsError{TGMS_E_INVAL, "smoother patch matrix is not positive definite"};
         }
-        // pressure: orthonormal DCT-II matrices and the 1D Neumann eigenvalues
-        c->Qx = c->alloc<double>((size_t)nx * nx);
-        c->lamx = c->alloc<double>(nx);
-        c->Qy = c->alloc<double>((size_t)ny * ny);
-        c->lamy = c->alloc<double>(ny);
-        tgms::dct_matrix(c, nx, c->Qx, c->lamx);
-        tgms::dct_matrix(c, ny, c->Qy, c->lamy);
-        // solve workspaces
-        const long long nvtx = ncell;
-        c->vx = c->alloc<double>(nvtx); c->vg = c->alloc<double>(nvtx); c->vz = c->alloc<double>(nvtx);
-        c->vp = c->alloc<double>(nvtx); c->vq = c->alloc<double>(nvtx); c->vt = c->alloc<double>(nvtx);
-        c->vt2 = c->alloc<double>(nvtx); c->vt3 = c->alloc<double>(nvtx); c->vgold = c->alloc<double>(nvtx);
-        c->vg2 = c->alloc<double>(nvtx);
-        c->fg = c->alloc<float>(nvtx); c->fz = c->alloc<float>(nvtx); c->ft = c->alloc<float>(nvtx);
-        c->ft2 = c->alloc<float>(nvtx);
-        c->fbar = c->alloc<double>(c->nf); c->fu = c->alloc<double>(c->nf); c->fF = c->alloc<double>(c->nf);
-        c->cellw = c->alloc<double>(ncell); c->cellw2 = c->alloc<double>(std::max<long long>(ncell, 2 * c->nblk));
-        c->blkbuf = c->alloc<double>(2 * (size_t)c->nblk);
-        c->sc = c->alloc<double>(SC_COUNT);
-        c->part = c->alloc<double>(3 * (size_t)tgms::pcg_tiles(c));
-        c->part2 = c->alloc<double>((size_t)tgms::pcg_tiles(c));
-        tgms::allow_fused_lds(c);
-        c->vp1 = c->alloc<double>(nvtx);
-        HIP_OK(hipHostMalloc((void**)&c->red_h, SC_COUNT * sizeof(double), hipHostMallocDefault));
         if (art && art->mobility) {
             // the saved context had its mobility updated: its weights, and every factor
             // built from them
