@@ -13,8 +13,9 @@
 
 namespace {
 
-// One wavefront per rectangle; band matrix in LDS (n * (b+1) doubles).  NQ: pairs of
-// the trailing update per lane (ceil(b (b+1) / 2 / 64)).
+// One wavefront per rectangle; band matrix in LDS (n * (b+1) doubles, then m * m for the
+// diagonal blocks' inverses).  NQ: pairs of the trailing update per lane
+// (ceil(b (b+1) / 2 / 64)).
 template <bool WRITE32, int NQ>
 __global__ void k_band_factor(const Rect* __restrict__ rects, const double* __restrict__ a, int nx, double sx2,
                               double sy2, double* __restrict__ Lpool, double* __restrict__ Spool,
@@ -88,19 +89,23 @@ __global__ void k_band_factor(const Rect* __restrict__ rects, const double* __re
         if (lane == 0) col[0] = inv;
         __syncthreads();
     }
-    // repack by vertex rows: D_j = L_jj^{-1} (lower, by columns), E_j = L_{j+1,j} (Hessenberg, by columns)
+    // repack by vertex rows: D_j = L_jj^{-1} (lower, by columns), E_j = L_{j+1,j} (Hessenberg, by columns);
+    // each column of L_jj^{-1} is formed in LDS (X, m words a lane) and written out as it goes
     const int tri = btri_tri(m), bs = tri + btri_hes(m);
     double* out = Lpool + R.off;
+    double* X = M + (long long)n * ld;
     for (int j = 0; j < mh; ++j) {
         double* D = out + (long long)j * bs;
         if (lane < m) {
             const int cc = lane;  // column of L_jj^{-1}: solve L_jj x = e_cc, rows cc..m-1
+            double* xc = X + (long long)cc * m;
             for (int r = cc; r < m; ++r) {
                 double acc = (r == cc) ? 1.0 : 0.0;
-                for (int k = cc; k < r; ++k)
-                    acc -= M[(long long)(j * m + k) * ld + (r - k)] * D[btri_offD(cc, m) + (k - cc)];
+                for (int k = cc; k < r; ++k) acc -= M[(long long)(j * m + k) * ld + (r - k)] * xc[k];
                 // diagonal of L stored as its reciprocal
-                D[btri_offD(cc, m) + (r - cc)] = acc * M[(long long)(j * m + r) * ld];
+                const double xr = acc * M[(long long)(j * m + r) * ld];
+                xc[r] = xr;
+                D[btri_offD(cc, m) + (r - cc)] = xr;
             }
         }
         if (j + 1 < mh) {
@@ -130,7 +135,8 @@ namespace tgms {
 // caller later (null: checked here, after waiting)
 static void factor_rects(tgms_ctx* c, Rect* rects, int count, int max_n, int max_b, double* L, double* S,
                          int* fail_out) {
-    size_t lds = (size_t)max_n * (max_b + 1) * sizeof(double);
+    // the band and the columns of one diagonal block's inverse
+    size_t lds = ((size_t)max_n * (max_b + 1) + (size_t)(max_b - 1) * (max_b - 1)) * sizeof(double);
     if (lds > 65536) throw TgmsError{TGMS_E_UNSUPPORTED, "local band factor exceeds 64 KiB of LDS"};
     int* fail = fail_out ? fail_out : c->alloc_scratch_int();
     if (max_b - 1 > TGMS_MMAX) throw TgmsError{TGMS_E_UNSUPPORTED, "local rectangle wider than 33 cells"};
