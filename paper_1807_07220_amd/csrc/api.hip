@@ -674,6 +674,8 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
     } side;
     tgms::DenseInvAsync kh_inv;
     SpanTimer pat_timer;     // the smoother factorisation on the second stream
+    // the main stream's phases, read after the final synchronisation (no waits between)
+    SpanTimer snap_timer, eig_timer, coarse_timer;
     int* pat_fail = nullptr;
     int* blk_fail = nullptr;  // the block factorisation (checked at the end)
     try {
@@ -773,8 +775,9 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
             c->G = c->alloc<double>((size_t)c->nblk * c->ncol * c->ncol);
             HIP_OK(hipEventRecord(side.ez, side.s));
         }
+        double* YQd = nullptr;
         {
-            Timer t(c->stream);
+            snap_timer.start(c->stream);
             blk_fail = c->alloc<int>(1);
             tgms::factor_blocks(c, blk_fail);
             // snapshots + Gram (queued before the coarse RT0 inverse on the second stream:
@@ -879,10 +882,20 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                 c->part2 = c->alloc<double>((size_t)tgms::pcg_tiles(c));
                 tgms::allow_fused_lds(c);
                 c->vp1 = c->alloc<double>(nvtx);
+                c->cflux = c->alloc<double>(2 * ((size_t)c->Ny * (c->Nx + 1) + (size_t)(c->Ny + 1) * c->Nx));
+                c->svec = c->alloc<double>((size_t)c->nv + 1);
+                c->svec2 = c->alloc<double>(2 * (size_t)c->nv + 1);
                 HIP_OK(hipHostMalloc((void**)&c->red_h, SC_COUNT * sizeof(double), hipHostMallocDefault));
                 HIP_OK(hipEventRecord(side.e2, side.s));
             }
-            c->t_snap_ms = t.ms();
+            snap_timer.stop(c->stream);
+            // the eigenproblems' buffers, queued while the spectral kernels run
+            c->eigs = c->alloc<double>((size_t)c->ne * c->jmax);
+            c->counts = c->alloc<int>(c->ne);
+            c->Y = c->alloc<double>((size_t)c->ne * c->jmax * c->jmax);
+            YQd = c->alloc<double>((size_t)c->ne * c->jmax * c->jmax);
+            c->YQ = YQd;
+            if (!art && c->coarse_space != 2 && c->warm) c->wstat = c->alloc<int>(c->ne);
             // the block factorisation, checked once the GPU has reached this point (before
             // the spectral problems use the snapshots)
             int hb = 0;
@@ -891,11 +904,6 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
             if (hb) throw TgmsError{TGMS_E_INVAL, "local stream-function matrix is not positive definite"};
         }
         // pencils and eigenproblems
-        c->eigs = c->alloc<double>((size_t)c->ne * c->jmax);
-        c->counts = c->alloc<int>(c->ne);
-        c->Y = c->alloc<double>((size_t)c->ne * c->jmax * c->jmax);
-        double* YQd = c->alloc<double>((size_t)c->ne * c->jmax * c->jmax);
-        c->YQ = YQd;
         if (art) {
             // the coarse space of the saved context
             Timer t(c->stream);
@@ -910,9 +918,8 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
             std::vector<int> ones(c->ne, 1);
             HIP_OK(hipMemcpyAsync(c->counts, ones.data(), sizeof(int) * c->ne, hipMemcpyHostToDevice, c->stream));
         } else {
-            Timer t(c->stream);
+            eig_timer.start(c->stream);
             const float* Y0 = nullptr;
-            if (c->warm) c->wstat = c->alloc<int>(c->ne);
             if (c->warm == 2) {
                 // network inputs of every face and the initial blocks [ne][8][b]
                 Timer tc(c->stream);
@@ -924,11 +931,11 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                 c->t_cnn_ms = tc.ms();
             }
             tgms::pencil_eig_q(c, YQd, Y0, nullptr);
-            c->t_eig_ms = t.ms();
+            eig_timer.stop(c->stream);
             HIP_OK(hipMemcpyAsync(&c->eig_unconverged, c->eig_bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
         }
         {
-            Timer t(c->stream);
+            coarse_timer.start(c->stream);
             c->counts_h.resize(c->ne);
             HIP_OK(hipMemcpyAsync(c->counts_h.data(), c->counts, sizeof(int) * c->ne, hipMemcpyDeviceToHost, c->stream));
             if (c->warm) {
@@ -944,6 +951,11 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                 }
             std::vector<int> pack;  // host side of the numbering upload, kept until the timer's synchronisation
             int* metad = build_coarse_numbering(c, pack);
+            if (c->coarse_space != 2) {
+                // the first coarse kernel as soon as the numbering is up (the GPU waits for the host here)
+                c->Td = c->alloc<double>((size_t)c->nblk * c->ncol * c->mu);
+                tgms::fill_td(c, metad, YQd, c->Td);
+            }
             c->W = c->alloc<double>((size_t)c->nblk * bx * by * c->mu);
             if (c->precision) c->W32 = c->alloc<float>((size_t)c->nblk * bx * by * c->mu);
             c->Ac = c->alloc<double>((size_t)c->ncs * c->ncs);
@@ -951,26 +963,21 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                 tgms::rt0_coarse_W(c);
                 rt0_coarse_matrix(c);
             } else {
-                c->Td = c->alloc<double>((size_t)c->nblk * c->ncol * c->mu);
-                tgms::fill_td(c, metad, YQd, c->Td);
                 tgms::coarse_local_run(c, c->Td, c->zcd);
             }
-            factor_coarse(c);
             c->cy = c->alloc<double>((size_t)c->nblk * c->mu);
             c->cvec = c->alloc<double>(2 * (size_t)c->ncs + 1);
             c->cvec2 = c->alloc<double>((size_t)c->ncs + 1);
             c->cy32 = c->alloc<float>((size_t)c->nblk * c->mu);
             c->cvec32 = c->alloc<float>(2 * (size_t)c->ncs + 1);
             c->cvec2_32 = c->alloc<float>((size_t)c->ncs + 1);
+            factor_coarse(c);
             // coarse RT0 for the preprocessing: join the second stream
             HIP_OK(hipStreamWaitEvent(c->stream, side.e1, 0));
             tgms::dense_spd_inverse_end(kh_inv);
             if (c->kb.nb > 0 && tgms::bcr_failed(c, c->kb))
                 throw TgmsError{TGMS_E_INVAL, "coarse RT0 operator is not positive definite"};
-            c->cflux = c->alloc<double>(2 * ((size_t)c->Ny * (c->Nx + 1) + (size_t)(c->Ny + 1) * c->Nx));
-            c->svec = c->alloc<double>((size_t)c->nv + 1);
-            c->svec2 = c->alloc<double>(2 * (size_t)c->nv + 1);
-            c->t_coarse_ms = t.ms();
+            coarse_timer.stop(c->stream);
         }
         // smoother patches: join the second stream and check the factorisation
         {
@@ -993,6 +1000,9 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         if (o.rows_per_thread == 1 || o.rows_per_thread == 4) c->rpt = o.rows_per_thread;
         HIP_OK(hipStreamSynchronize(c->stream));
         c->t_setup_ms = total.ms();
+        c->t_snap_ms = snap_timer.ms();
+        if (eig_timer.a) c->t_eig_ms = eig_timer.ms();
+        c->t_coarse_ms = coarse_timer.ms();
         *out = c;
     } catch (...) {
         if (side.s) (void)hipStreamSynchronize(side.s);  // its work writes into the context's buffers
