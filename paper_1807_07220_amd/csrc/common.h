@@ -263,7 +263,7 @@ struct tgms_ctx {
     double* part = nullptr;   // per-workgroup partial sums of the final gather (3 x NRED)
     double* part2 = nullptr;  // per-workgroup partial sums of p.q (NRED)
     double* vt3 = nullptr;    // z1 after the coarse correction (FP64 preconditioner)
-    double* vg2 = nullptr;    // second residual buffer (residual updates fused into the smoother)
+    double* vg2 = nullptr;    // second residual buffer (the PCG update reads one and writes the other)
     int nred = 256;           // workgroups of the reducing PCG kernels (autotuned)
     int rpt = 1;              // vertex rows per thread in the tiled PCG kernels (1 or 4; autotuned)
     int smooth_staged = -1;   // smoother: 1 forward blocks kept in LDS for the backward chains, 0 staged twice
@@ -328,14 +328,6 @@ struct tgms_ctx {
 enum { SC_RHO = 0, SC_PQ, SC_ALPHA, SC_BETA, SC_ZN2, SC_REL2, SC_Z02, SC_FLAG, SC_IT, SC_DONE, SC_RTOL2, SC_MAXIT,
        SC_FLEX, SC_RHO_NEW, SC_PENDING, SC_COUNT };
 
-// The PCG update fused into an iteration's first smoothing: with this, the smoother's
-// right-hand side is g = gin - alpha q with alpha = rho' / (sum of the p.q partials),
-// and each patch writes g to gout and x += alpha p on its own block's vertices
-// (workgroup 0 records the scalars, as the separate update kernel would).
-// Inputs of the second smoothing of the two-grid cycle when it also forms its own
-// right-hand side: t = g - K z1' with z1' = z1 + W c (the coarse correction
-// prolonged), on each patch and its one-vertex halo; the patch's own block writes z1'.
-// z1 null: the smoother reads its right-hand side as given.
 // sum of cy[ent[k]] for k in [k0, k1), added in order; the index and value loads of
 // four terms are issued together (two memory round trips per four terms, not eight)
 template <typename T>

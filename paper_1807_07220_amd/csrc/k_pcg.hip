@@ -239,7 +239,7 @@ __device__ inline T patch_sum(const Rect* __restrict__ rects, const T* __restric
     return gather_w<T>(rects, w, i, j, G.bx, G.by, G.Nx, G.Ny);
 }
 
-// Coarse-space data of the fused two-grid kernels: stream functions W
+// Coarse-space data of the two-grid kernels: stream functions W
 // [block][owned vertex][slot], per-block unknown ids and counts.
 template <typename T>
 struct CoarseW {
