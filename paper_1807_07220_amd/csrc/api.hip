@@ -752,11 +752,10 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
         HIP_OK(hipEventCreateWithFlags(&side.e1, hipEventDisableTiming));
         HIP_OK(hipEventCreateWithFlags(&side.e2, hipEventDisableTiming));
         HIP_OK(hipEventCreateWithFlags(&side.ez, hipEventDisableTiming));
-        HIP_OK(hipEventRecord(side.e0, c->stream));
-        HIP_OK(hipStreamWaitEvent(side.s, side.e0, 0));
-        // The large spectral buffers are allocated with their clearing queued on the
-        // second stream, where it runs during the block factorisation; the snapshots wait
-        // for it (event ez).
+        // The smoother's patch table and the large spectral buffers are allocated with
+        // their upload and clearing queued on the second stream ahead of its other work
+        // (they depend on nothing queued before), where they run during the block
+        // factorisation; the snapshots wait for the clearing (event ez).
         const bool gram_mfma = tgms::gram_uses_mfma(c);
         const size_t nvk = (size_t)(bx + 1) * (by + 1);
         {
@@ -767,6 +766,37 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                 ~Restore() { c->stream = s; }
             } restore{c, main_stream};
             c->stream = side.s;
+            // the smoother's patch table, uploaded first on this stream (a copy from pageable
+            // memory holds the host until the stream reaches it)
+            c->patch_h.resize(c->nblk);
+            long long off = 0, voff = 0;
+            std::set<int> widths;
+            for (int J = 0; J < c->Ny; ++J)
+                for (int I = 0; I < c->Nx; ++I) {
+                    Rect& r = c->patch_h[J * c->Nx + I];
+                    r.i0 = std::max(I * bx - o.overlap, 0);
+                    r.i1 = std::min((I + 1) * bx + o.overlap, nx);
+                    r.j0 = std::max(J * by - o.overlap, 0);
+                    r.j1 = std::min((J + 1) * by + o.overlap, ny);
+                    const int m = r.i1 - r.i0 - 1, n = m * (r.j1 - r.j0 - 1);
+                    r.off = off;
+                    r.voff = voff;
+                    off += (tw_size(m, r.j1 - r.j0 - 1) + 3) & ~3LL;  // 16-byte aligned factors
+                    c->pat_fmax = std::max(c->pat_fmax, tw_size(m, r.j1 - r.j0 - 1));
+                    voff += n;
+                    c->pat_nmax = std::max(c->pat_nmax, n);
+                    c->pat_hmax = std::max(c->pat_hmax, r.j1 - r.j0 - 1);
+                    c->pat_bmax = std::max(c->pat_bmax, m + 1);
+                    widths.insert(m);
+                }
+            // the kernels take fixed-width paths for up to two distinct row widths
+            c->pat_m1 = *widths.rbegin();
+            c->pat_m2 = widths.size() == 1 ? c->pat_m1 : widths.size() == 2 ? *widths.begin() : -1;
+            c->pat_pool = off;
+            c->pat_vpool = voff;
+            c->patch = c->alloc<Rect>(c->nblk);
+            HIP_OK(hipMemcpyAsync(c->patch, c->patch_h.data(), sizeof(Rect) * c->nblk, hipMemcpyHostToDevice,
+                                  c->stream));
             // snapshots (A Psi is the snapshot solves' scratch until the Gram products),
             // A_K Psi for the Gram kernel without matrix cores (the path integrals of the
             // coarse assembly reuse it: nblk * (bx+1)(by+1) * ncol) and the Grams
@@ -774,6 +804,9 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
             c->APsi = c->alloc<double>((size_t)c->nblk * c->ncol * (gram_mfma ? nvk : (size_t)c->nfk));
             c->G = c->alloc<double>((size_t)c->nblk * c->ncol * c->ncol);
             HIP_OK(hipEventRecord(side.ez, side.s));
+            // the rest of this stream's work reads what the main stream has queued so far
+            HIP_OK(hipEventRecord(side.e0, main_stream));
+            HIP_OK(hipStreamWaitEvent(side.s, side.e0, 0));
         }
         double* YQd = nullptr;
         {
@@ -805,36 +838,9 @@ void setup_impl(const tgms_grid* grid, const double* kappa, double eig_tol, cons
                 HIP_OK(hipEventRecord(side.e1, side.s));
                 // smoother patches (section 5): factorised on this second stream after the
                 // coarse RT0 operator, concurrently with the spectral setup on the main one
-                // (the patch matrices depend on the cell weights only)
-                c->patch_h.resize(c->nblk);
-                long long off = 0, voff = 0;
-                std::set<int> widths;
-                for (int J = 0; J < c->Ny; ++J)
-                    for (int I = 0; I < c->Nx; ++I) {
-                        Rect& r = c->patch_h[J * c->Nx + I];
-                        r.i0 = std::max(I * bx - o.overlap, 0);
-                        r.i1 = std::min((I + 1) * bx + o.overlap, nx);
-                        r.j0 = std::max(J * by - o.overlap, 0);
-                        r.j1 = std::min((J + 1) * by + o.overlap, ny);
-                        const int m = r.i1 - r.i0 - 1, n = m * (r.j1 - r.j0 - 1);
-                        r.off = off;
-                        r.voff = voff;
-                        off += (tw_size(m, r.j1 - r.j0 - 1) + 3) & ~3LL;  // 16-byte aligned factors
-                        c->pat_fmax = std::max(c->pat_fmax, tw_size(m, r.j1 - r.j0 - 1));
-                        voff += n;
-                        c->pat_nmax = std::max(c->pat_nmax, n);
-                        c->pat_hmax = std::max(c->pat_hmax, r.j1 - r.j0 - 1);
-                        c->pat_bmax = std::max(c->pat_bmax, m + 1);
-                        widths.insert(m);
-                    }
-                // the kernels take fixed-width paths for up to two distinct row widths
-                c->pat_m1 = *widths.rbegin();
-                c->pat_m2 = widths.size() == 1 ? c->pat_m1 : widths.size() == 2 ? *widths.begin() : -1;
-                c->pat_pool = off;
-                c->pat_vpool = voff;
-                c->patch = c->alloc<Rect>(c->nblk);
-                HIP_OK(hipMemcpyAsync(c->patch, c->patch_h.data(), sizeof(Rect) * c->nblk, hipMemcpyHostToDevice,
-                                      c->stream));
+                // (the patch matrices depend on the cell weights only); the patch table is up
+                // already
+                const long long off = c->pat_pool, voff = c->pat_vpool;
                 c->patL = c->alloc<double>(off);
                 c->patW = c->alloc<double>(voff);
                 if (c->precision) {
