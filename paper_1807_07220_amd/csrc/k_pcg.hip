@@ -475,40 +475,44 @@ __global__ void __launch_bounds__(NT) k_pcg_update(FusedUpdate U, T* __restrict_
     }
 }
 
-// The second smoothing's right-hand side: z1' = z1 + W c on the coarse block's vertices
+// The second smoothing's right-hand side: z1' = z1 + W c on the coarse blocks' vertices
 // (written to Pr.z1p) and t = g - K z1' there, formed in FP64 and rounded once to T.
-// One workgroup per coarse block; the one-vertex halo of z1' is recomputed from the
-// neighbouring blocks' W and c (the same arithmetic as the block's own vertices), so
-// that every vertex of t is a function of that vertex alone.  The loads that do not
-// depend on c (z1, the first QB entries of each W row, the own vertices' g and cell
-// weights) are issued before the coefficients are staged; W rows are read QB entries
-// at a time, the indices past the row clamped to its last entry and multiplied by
-// zero coefficients, so that each batch is in flight at once and the sum is that of
-// the row's nu entries.
+// One workgroup per group of gx x gy coarse blocks (several small blocks share one
+// tile); the one-vertex halo of z1' is recomputed from the neighbouring blocks' W and c
+// (the same arithmetic as the group's own vertices), so that every vertex of t is a
+// function of that vertex alone.  The loads that do not depend on c (z1, the first QB
+// entries of each W row, the own vertices' g and cell weights) are issued before the
+// coefficients are staged; W rows are read QB entries at a time, the indices past the
+// row clamped to its last entry and multiplied by zero coefficients, so that each batch
+// is in flight at once and the sum is that of the row's nu entries.
 template <typename T>
 __global__ void __launch_bounds__(NT) k_prolong_residual(PreResidual<T> Pr, T* __restrict__ t, int nx, int ny,
-                                                         int bx, int by, int Nx, const double* __restrict__ sc) {
+                                                         int bx, int by, int Nx, int gx, int gy,
+                                                         const double* __restrict__ sc) {
     if (finished(sc)) return;
     constexpr int QB = 8;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int I = blockIdx.x % Nx, J = blockIdx.x / Nx, Ny = ny / by;
-    const int pw = bx + 2, ph = by + 2, mu = Pr.mu, nown = bx * by, ntile = pw * ph;
+    const int Ny = ny / by, ngx = (Nx + gx - 1) / gx;
+    const int I0 = (int)(blockIdx.x % ngx) * gx, J0 = (int)(blockIdx.x / ngx) * gy;  // the group's first block
+    const int ow = gx * bx, oh = gy * by;            // the group's vertex rectangle
+    const int pw = ow + 2, ph = oh + 2, sbx = gx + 2;  // tile with halo; staged blocks per row
+    const int mu = Pr.mu, nown = bx * by, ntile = pw * ph, nco = ow * oh;
     const int tid = threadIdx.y * TX + threadIdx.x;
     double* Zt = reinterpret_cast<double*>(smem_raw);
-    T* cb = reinterpret_cast<T*>(Zt + ntile);  // [9][mu]: the coefficients of the 3 x 3 blocks around
-    // tile element e: vertex (ii, jj), its block's W row and neighbour index (-1 outside the domain)
+    T* cb = reinterpret_cast<T*>(Zt + ntile);  // [(gx+2)(gy+2)][mu]: the coefficients of the blocks around
+    // tile element e: vertex (ii, jj), its block's W row and staged-block index (-1 outside the domain)
     struct Elem {
         long long v;
         const T* Wv;
         int nb;
     };
     auto elem = [&](int e) {
-        const int ii = I * bx - 1 + e % pw, jj = J * by - 1 + e / pw;
+        const int ii = I0 * bx - 1 + e % pw, jj = J0 * by - 1 + e / pw;
         Elem x{(long long)jj * nx + ii, Pr.W, -1};
         if (ii >= 1 && ii < nx && jj >= 1 && jj < ny) {
             const int Ib = ii / bx, Jb = jj / by;
             x.Wv = Pr.W + ((long long)(Jb * Nx + Ib) * nown + (jj % by) * bx + ii % bx) * mu;
-            x.nb = (Jb - J + 1) * 3 + (Ib - I + 1);
+            x.nb = (Jb - J0 + 1) * sbx + (Ib - I0 + 1);
         }
         return x;
     };
@@ -521,11 +525,11 @@ __global__ void __launch_bounds__(NT) k_prolong_residual(PreResidual<T> Pr, T* _
     T w0[QB];
     load_w(x0, 0, w0);
     const T z0 = x0.nb >= 0 ? Pr.z1[x0.v] : T(0);
-    const int r0 = tid < nown ? tid : 0;
-    const long long v0 = (long long)(J * by + r0 / bx) * nx + I * bx + r0 % bx;
-    const VertexData d0 = vertex_data(Pr.g, Pr.a, v0, nx, J * by + r0 / bx > 0 && I * bx + r0 % bx > 0);
-    for (int e = tid; e < 9 * mu; e += NT) {
-        const int nb = e / mu, uu = e % mu, Ib = I + nb % 3 - 1, Jb = J + nb / 3 - 1;
+    const int r0 = tid < nco ? tid : 0, i0v = I0 * bx + r0 % ow, j0v = J0 * by + r0 / ow;
+    const bool in0 = i0v > 0 && j0v > 0 && i0v < nx && j0v < ny;
+    const VertexData d0 = vertex_data(Pr.g, Pr.a, in0 ? (long long)j0v * nx + i0v : 0, nx, in0);
+    for (int e = tid; e < sbx * (gy + 2) * mu; e += NT) {
+        const int nb = e / mu, uu = e % mu, Ib = I0 + nb % sbx - 1, Jb = J0 + nb / sbx - 1;
         T val = T(0);
         if (Ib >= 0 && Ib < Nx && Jb >= 0 && Jb < Ny) {
             const int b = Jb * Nx + Ib;
@@ -538,7 +542,7 @@ __global__ void __launch_bounds__(NT) k_prolong_residual(PreResidual<T> Pr, T* _
         const bool first = e == tid;
         const Elem x = first ? x0 : elem(e);
         const int ex = e % pw, ey = e / pw;
-        const bool own = ex >= 1 && ex <= bx && ey >= 1 && ey <= by;
+        const bool own = ex >= 1 && ex <= ow && ey >= 1 && ey <= oh && I0 * bx - 1 + ex < nx && J0 * by - 1 + ey < ny;
         double val = 0.0;
         if (x.nb >= 0) {
             const T* cv = cb + x.nb * mu;
@@ -563,8 +567,9 @@ __global__ void __launch_bounds__(NT) k_prolong_residual(PreResidual<T> Pr, T* _
         Zt[e] = val;
     }
     __syncthreads();
-    for (int r = tid; r < nown; r += NT) {
-        const int aa = r % bx, bb = r / bx, i = I * bx + aa, j = J * by + bb;
+    for (int r = tid; r < nco; r += NT) {
+        const int aa = r % ow, bb = r / ow, i = I0 * bx + aa, j = J0 * by + bb;
+        if (i >= nx || j >= ny) continue;  // past the last block of an edge group
         const long long v = (long long)j * nx + i;
         if (i == 0 || j == 0) {
             t[v] = T(0);
@@ -632,9 +637,13 @@ template void pcg_update<float>(tgms_ctx*, const FusedUpdate&, float*);
 
 template <typename T>
 void prolong_residual(tgms_ctx* c, const PreResidual<T>& pr, T* t, const double* sc) {
-    const size_t lds = sizeof(double) * (size_t)(c->bx + 2) * (c->by + 2) + sizeof(T) * 9 * (size_t)pr.mu;
-    hipLaunchKernelGGL((k_prolong_residual<T>), dim3(c->nblk), dim3(TX, TY), lds, c->stream, pr, t, c->nx, c->ny,
-                       c->bx, c->by, c->Nx, sc);
+    // blocks of at most 64 vertices go in 2 x 2 groups (one tile of about a workgroup's size)
+    const int g = c->bx * c->by <= 64 ? 2 : 1;
+    const int ngx = (c->Nx + g - 1) / g, ngy = (c->Ny + g - 1) / g;
+    const size_t lds = sizeof(double) * (size_t)(g * c->bx + 2) * (g * c->by + 2) +
+                       sizeof(T) * (size_t)(g + 2) * (g + 2) * pr.mu;
+    hipLaunchKernelGGL((k_prolong_residual<T>), dim3(ngx * ngy), dim3(TX, TY), lds, c->stream, pr, t, c->nx, c->ny,
+                       c->bx, c->by, c->Nx, g, g, sc);
     LAUNCH_OK();
 }
 template void prolong_residual<double>(tgms_ctx*, const PreResidual<double>&, double*, const double*);
