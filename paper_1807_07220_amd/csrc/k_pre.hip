@@ -248,8 +248,10 @@ void preprocess(tgms_ctx* c, const double* F, const double* g_bnd, double* vbar,
     hipLaunchKernelGGL(k_block_sums, dim3(c->nblk), dim3(64), 0, c->stream, (const double*)Fp, c->nx, c->bx, c->by,
                        c->Nx, FH, FabsH);
     LAUNCH_OK();
-    std::vector<double> fh(2 * c->nblk);
+    // the block sums and the coarse RT0 block masses, read back with one wait
+    std::vector<double> fh(2 * c->nblk), ah(6 * c->nblk);
     HIP_OK(hipMemcpyAsync(fh.data(), FH, sizeof(double) * 2 * c->nblk, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipMemcpyAsync(ah.data(), c->AH0, sizeof(double) * 6 * c->nblk, hipMemcpyDeviceToHost, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
     const int Nx = c->Nx, Ny = c->Ny;
     double tot = 0.0, tabs = 0.0;
@@ -281,9 +283,6 @@ void preprocess(tgms_ctx* c, const double* F, const double* g_bnd, double* vbar,
     // rhs_s = -C_H^T A_H0 c_p  (per block: 2x2 mass for the x pair and the y pair)
     std::vector<double> rhs(c->nv > 0 ? c->nv : 1, 0.0);
     auto vid = [&](int I, int J) { return (I <= 0 || I >= Nx || J <= 0 || J >= Ny) ? -1 : (J - 1) * (Nx - 1) + I - 1; };
-    std::vector<double> ah(6 * c->nblk);
-    HIP_OK(hipMemcpyAsync(ah.data(), c->AH0, sizeof(double) * 6 * c->nblk, hipMemcpyDeviceToHost, c->stream));
-    HIP_OK(hipStreamSynchronize(c->stream));
     for (int J = 0; J < Ny; ++J)
         for (int I = 0; I < Nx; ++I) {
             const double* m = &ah[6 * (J * Nx + I)];
