@@ -558,7 +558,7 @@ void build_rt0_stiffness(tgms_ctx* c) {
 void factor_coarse(tgms_ctx* c) {
     const long long n2 = (long long)c->ncs * c->ncs;
     if (use_bcr(c, c->ncs, c->cband, c->precision != 0)) {
-        tgms::bcr_factor(c, c->Ac, c->ncs, std::max(c->cband, 1), c->cb, c->precision != 0, c->precision == 0);
+        tgms::bcr_factor(c, c->Ac, c->ncs, std::max(c->cband, 1), c->cb, c->precision != 0, true);
         if (tgms::bcr_failed(c, c->cb)) throw TgmsError{TGMS_E_INVAL, "coarse operator is not positive definite"};
         return;
     }

@@ -139,7 +139,7 @@ struct Bcr {
     float *C32 = nullptr, *Gm32 = nullptr, *Gp32 = nullptr, *CT32 = nullptr, *GmT32 = nullptr, *GpT32 = nullptr;
     float *Y32 = nullptr, *x32 = nullptr;
     int* fail = nullptr;
-    // truncated reduction (FP64 solve): levels s < step only, then the explicit inverse
+    // truncated reduction: levels s < step only, then the explicit FP64 inverse
     // Minv of the remaining block tridiagonal system (blocks 0, step, 2 step, ...; nr of
     // them); step 0: reduced to block 0
     int step = 0, nr = 0;
@@ -481,7 +481,8 @@ void dense_spd_inverse_end(DenseInvAsync& h);
 int bcr_max_block(const tgms_ctx* c);  // largest block the factor kernel holds in LDS
 // factorise the banded SPD A (dense n x n, row-major; zero beyond half-bandwidth bs)
 // truncate: stop the reduction where the remaining system has at most symv_acc_max()
-// unknowns and invert that explicitly (FP64 solve only; synchronises)
+// unknowns and invert that explicitly in FP64 (applied in FP64 by both solves;
+// synchronises)
 void bcr_factor(tgms_ctx* c, const double* A, int n, int bs, Bcr& F, bool fp32, bool truncate = false);
 bool bcr_failed(tgms_ctx* c, const Bcr& F);  // a non-positive pivot (synchronises)
 template <typename T>

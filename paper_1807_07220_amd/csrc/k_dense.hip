@@ -766,11 +766,12 @@ __global__ void __launch_bounds__(SNT) k_bcr_fwd(BcrView<T> F, T* __restrict__ x
 // The truncated reduction's top: x_e = (Minv b)_e on the remaining blocks e = p step,
 // b read from Y there (staged by the last forward level, so that no workgroup reads
 // what another writes).  Four rows a workgroup, one wavefront a row, each lane KD
-// columns with their loads in flight together; b staged in LDS.
+// columns with their loads in flight together; b staged in LDS.  The product is FP64
+// (Minv is), also for an FP32 solve (T float: b widened, the result rounded once).
 constexpr int DNT = 256;
-template <int KD>
-__global__ void __launch_bounds__(DNT) k_bcr_dense(const double* __restrict__ Minv, double* __restrict__ x,
-                                                  const double* __restrict__ Y, int bs, int step, int nr,
+template <typename T, int KD>
+__global__ void __launch_bounds__(DNT) k_bcr_dense(const double* __restrict__ Minv, T* __restrict__ x,
+                                                  const T* __restrict__ Y, int bs, int step, int nr,
                                                   const double* __restrict__ sc) {
     if (sc != nullptr && sc[SC_DONE] != 0.0) return;
     __shared__ double b[64 * KD];
@@ -780,14 +781,14 @@ __global__ void __launch_bounds__(DNT) k_bcr_dense(const double* __restrict__ Mi
     double m[KD];
 #pragma unroll
     for (int j = 0; j < KD; ++j) m[j] = a[min(lane + 64 * j, nn - 1)];
-    for (int k = tid; k < nn; k += DNT) b[k] = Y[((long long)(k / bs) * step) * bs + k % bs];
+    for (int k = tid; k < nn; k += DNT) b[k] = double(Y[((long long)(k / bs) * step) * bs + k % bs]);
     __syncthreads();
     double acc = 0.0;
 #pragma unroll
     for (int j = 0; j < KD; ++j)
         if (lane + 64 * j < nn) acc += m[j] * b[lane + 64 * j];
     acc = wave_sum(acc);
-    if (row < nn && lane == 0) x[((long long)(row / bs) * step) * bs + row % bs] = acc;
+    if (row < nn && lane == 0) x[((long long)(row / bs) * step) * bs + row % bs] = T(acc);
 }
 
 // x_0 = R_0 x_0: one workgroup of 1024 threads (64 rows a pass), x_0 staged in LDS
@@ -900,7 +901,7 @@ struct BcrView2 {
 // b_e -= Gp_{e-s}^T y_{e-s} + Gm_{e+s}^T y_{e+s}.
 template <typename T>
 __global__ void __launch_bounds__(SNT2) k_bcr2_fwd(BcrView2<T> F, T* __restrict__ x, T* __restrict__ Y, int bs, int nblk,
-                                                int s, const double* __restrict__ sc) {
+                                                int s, int stage, const double* __restrict__ sc) {
     if (sc != nullptr && sc[SC_DONE] != 0.0) return;
     const int e = 2 * s * blockIdx.x;
     if (e >= nblk) return;
@@ -924,7 +925,11 @@ __global__ void __launch_bounds__(SNT2) k_bcr2_fwd(BcrView2<T> F, T* __restrict_
     bcr_gemv<T>(h1 ? F.GpT + i1 * bb : F.GmT + i2 * bb, h1 ? yl : yr, (h1 && h2) ? F.GmT + i2 * bb : nullptr, yr, bs,
                 t);
     __syncthreads();
-    for (int r = tid; r < bs; r += SNT2) x[(long long)e * bs + r] -= t[r];
+    for (int r = tid; r < bs; r += SNT2) {
+        const T xe = x[(long long)e * bs + r] - t[r];
+        x[(long long)e * bs + r] = xe;
+        if (stage) Y[(long long)e * bs + r] = xe;  // the truncated top's right-hand side
+    }
 }
 
 // Block 0 after the last level: x_0 = C_0^{-T} C_0^{-1} b_0.
@@ -1006,7 +1011,7 @@ __device__ __attribute__((always_inline)) inline void bcr_gemv_rows(const BcrRow
 
 template <typename T, int SGX, int KM>
 __global__ void __launch_bounds__(SNT2) k_bcr2_fwd_r(BcrView2<T> F, T* __restrict__ x, T* __restrict__ Y, int bs,
-                                                  int nblk, int s, const double* __restrict__ sc) {
+                                                  int nblk, int s, int stage, const double* __restrict__ sc) {
     if (sc != nullptr && sc[SC_DONE] != 0.0) return;
     const int e = 2 * s * blockIdx.x;
     if (e >= nblk) return;
@@ -1037,7 +1042,11 @@ __global__ void __launch_bounds__(SNT2) k_bcr2_fwd_r(BcrView2<T> F, T* __restric
         for (int r = tid; r < bs; r += SNT2) Y[(long long)i2 * bs + r] = yr[r];
     if (live) bcr_gemv_rows<T, SGX, KM>(g1, h1 ? yl : yr, g2, h1 && h2, yr, bs, t);
     __syncthreads();
-    for (int r = tid; r < bs; r += SNT2) x[(long long)e * bs + r] -= t[r];
+    for (int r = tid; r < bs; r += SNT2) {
+        const T xe = x[(long long)e * bs + r] - t[r];
+        x[(long long)e * bs + r] = xe;
+        if (stage) Y[(long long)e * bs + r] = xe;  // the truncated top's right-hand side
+    }
 }
 
 template <typename T, int SGX, int KM>
@@ -1511,7 +1520,7 @@ void bcr_factor(tgms_ctx* c, const double* A, int n, int bs, Bcr& F, bool fp32, 
     // truncation: the smallest step (a power of two, at least 2) whose remaining system
     // fits the explicit-inverse apply, if that skips at least one level
     int step = 0;
-    if (truncate && !fp32) {
+    if (truncate) {
         int full = 1;
         while (full < nblk) full *= 2;
         for (int st = 2; st < full; st *= 2)
@@ -1581,15 +1590,16 @@ bool bcr_failed(tgms_ctx* c, const Bcr& F) {
 }
 
 // the truncated top: x on the remaining blocks = Minv (their staged right-hand side)
-void bcr_dense_top(tgms_ctx* c, const Bcr& F, double* x, const double* sc) {
+template <typename T>
+void bcr_dense_top(tgms_ctx* c, const Bcr& F, T* x, const T* Y, const double* sc) {
     const int nn = F.nr * F.bs;
     const dim3 grid((unsigned)((nn + DNT / 64 - 1) / (DNT / 64)));
     if (nn <= 64 * 4)
-        hipLaunchKernelGGL((k_bcr_dense<4>), grid, dim3(DNT), 0, c->stream, F.Minv, x, F.Y, F.bs, F.step, F.nr, sc);
+        hipLaunchKernelGGL((k_bcr_dense<T, 4>), grid, dim3(DNT), 0, c->stream, F.Minv, x, Y, F.bs, F.step, F.nr, sc);
     else if (nn <= 64 * 8)
-        hipLaunchKernelGGL((k_bcr_dense<8>), grid, dim3(DNT), 0, c->stream, F.Minv, x, F.Y, F.bs, F.step, F.nr, sc);
+        hipLaunchKernelGGL((k_bcr_dense<T, 8>), grid, dim3(DNT), 0, c->stream, F.Minv, x, Y, F.bs, F.step, F.nr, sc);
     else if (nn <= 64 * 16)
-        hipLaunchKernelGGL((k_bcr_dense<16>), grid, dim3(DNT), 0, c->stream, F.Minv, x, F.Y, F.bs, F.step, F.nr, sc);
+        hipLaunchKernelGGL((k_bcr_dense<T, 16>), grid, dim3(DNT), 0, c->stream, F.Minv, x, Y, F.bs, F.step, F.nr, sc);
     else
         throw TgmsError{TGMS_E_UNSUPPORTED, "reduced coarse system too large"};
     LAUNCH_OK();
@@ -1608,7 +1618,7 @@ void bcr_solve_k(tgms_ctx* c, const Bcr& F, const BcrView<T>& V, T* x, T* Y, int
         LAUNCH_OK();
     }
     if (step) {
-        bcr_dense_top(c, F, x, sc);
+        bcr_dense_top<T>(c, F, x, Y, sc);
         top = step;
     } else {
         hipLaunchKernelGGL((k_bcr_top<T, KM>), dim3(1), dim3(TNT), 0, c->stream, V, x, bs, sc);
@@ -1624,15 +1634,21 @@ void bcr_solve_k(tgms_ctx* c, const Bcr& F, const BcrView<T>& V, T* x, T* Y, int
 }
 
 template <int SGX, int KM>
-void bcr_solve2_r(tgms_ctx* c, const BcrView2<float>& V, float* x, float* Y, int bs, int nblk, int top,
+void bcr_solve2_r(tgms_ctx* c, const Bcr& F, const BcrView2<float>& V, float* x, float* Y, int bs, int nblk, int top,
                   const double* sc) {
-    for (int s = 1; s < nblk; s *= 2) {
+    const int step = F.step;
+    for (int s = 1; s < nblk && (step == 0 || s < step); s *= 2) {
         hipLaunchKernelGGL((k_bcr2_fwd_r<float, SGX, KM>), dim3((nblk - 1) / (2 * s) + 1), dim3(SNT2), 0, c->stream,
-                           V, x, Y, bs, nblk, s, sc);
+                           V, x, Y, bs, nblk, s, step != 0 && 2 * s == step ? 1 : 0, sc);
         LAUNCH_OK();
     }
-    hipLaunchKernelGGL((k_bcr2_top_r<float, SGX, KM>), dim3(1), dim3(SNT2), 0, c->stream, V, x, bs, sc);
-    LAUNCH_OK();
+    if (step) {
+        bcr_dense_top<float>(c, F, x, Y, sc);
+        top = step;
+    } else {
+        hipLaunchKernelGGL((k_bcr2_top_r<float, SGX, KM>), dim3(1), dim3(SNT2), 0, c->stream, V, x, bs, sc);
+        LAUNCH_OK();
+    }
     for (int s = top / 2; s >= 1; s /= 2) {
         if (s >= nblk) continue;
         hipLaunchKernelGGL((k_bcr2_bwd_r<float, SGX, KM>), dim3((nblk - s - 1) / (2 * s) + 1), dim3(SNT2), 0,
@@ -1651,24 +1667,30 @@ void bcr_solve2(tgms_ctx* c, const Bcr& F, float* x, const double* sc) {
     // blocks of up to 64 rows (16 lanes a row) or 72 and 128 rows (8 lanes a row): the
     // register-prefetched kernels
     if (bs <= 64) {
-        bcr_solve2_r<16, 4>(c, V, x, Y, bs, nblk, top, sc);
+        bcr_solve2_r<16, 4>(c, F, V, x, Y, bs, nblk, top, sc);
         return;
     }
     if (bs <= 72) {
-        bcr_solve2_r<8, 9>(c, V, x, Y, bs, nblk, top, sc);
+        bcr_solve2_r<8, 9>(c, F, V, x, Y, bs, nblk, top, sc);
         return;
     }
     if (bs <= 128) {
-        bcr_solve2_r<8, 16>(c, V, x, Y, bs, nblk, top, sc);
+        bcr_solve2_r<8, 16>(c, F, V, x, Y, bs, nblk, top, sc);
         return;
     }
-    for (int s = 1; s < nblk; s *= 2) {
+    const int step = F.step;
+    for (int s = 1; s < nblk && (step == 0 || s < step); s *= 2) {
         hipLaunchKernelGGL((k_bcr2_fwd<float>), dim3((nblk - 1) / (2 * s) + 1), dim3(SNT2), 0, c->stream, V, x, Y, bs,
-                           nblk, s, sc);
+                           nblk, s, step != 0 && 2 * s == step ? 1 : 0, sc);
         LAUNCH_OK();
     }
-    hipLaunchKernelGGL((k_bcr2_top<float>), dim3(1), dim3(SNT2), 0, c->stream, V, x, bs, sc);
-    LAUNCH_OK();
+    if (step) {
+        bcr_dense_top<float>(c, F, x, Y, sc);
+        top = step;
+    } else {
+        hipLaunchKernelGGL((k_bcr2_top<float>), dim3(1), dim3(SNT2), 0, c->stream, V, x, bs, sc);
+        LAUNCH_OK();
+    }
     for (int s = top / 2; s >= 1; s /= 2) {
         if (s >= nblk) continue;
         hipLaunchKernelGGL((k_bcr2_bwd<float>), dim3((nblk - s - 1) / (2 * s) + 1), dim3(SNT2), 0, c->stream, V, x,
