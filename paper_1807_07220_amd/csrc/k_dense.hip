@@ -552,7 +552,11 @@ inline unsigned nb(long long n, int t = 256) { return (unsigned)((n + t - 1) / t
 // A_{e, e-2s} = -Gp_{e-s}^T Gm_{e-s}; block 0 is left last.  This is the Cholesky
 // factorisation of the matrix in the odd-even order of its blocks (block factor
 // diagonal C_i, off-diagonal Gm_i^T, Gp_i^T); it is stored as C_i^{-1} (lower), Gm_i,
-// Gp_i.  A solve is one forward and one backward pass over the levels.
+// Gp_i.  A solve is one forward and one backward pass over the levels.  Truncated
+// (bcr_factor's truncate): the levels stop at the first step whose surviving blocks
+// 0, step, 2 step, ... hold at most symv_acc_max() unknowns; their block tridiagonal
+// system (the Schur complements and couplings of that level) is inverted explicitly in
+// FP64, and the solve applies that inverse in place of the remaining levels and block 0.
 constexpr int BCR_MAX = 256;  // largest block (LDS vectors of the solve kernels)
 
 // D_i and Lc_i from the dense matrix A (n x n, row-major); rows beyond n: identity.
